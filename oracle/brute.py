@@ -1,0 +1,124 @@
+"""Brute-force checks on tiny inputs -- TEST INFRASTRUCTURE ONLY.
+
+Pure Python, deliberately independent of ``oracle.c``: these routines work on
+the letters themselves (no codes, no base-|Sigma| integers, no logarithms of
+odds) so that a mistake in the C oracle cannot hide behind the same mistake
+here.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from collections import Counter
+from typing import Dict, List, Sequence, Tuple
+
+
+def projected_string(lmer: str, mask: int) -> str:
+    """h_k of an l-mer (Sec. 5): the kept letters, in order."""
+    return "".join(ch for p, ch in enumerate(lmer) if mask >> p & 1)
+
+
+def bucket_sizes(seqs: Sequence[str], l: int, mask: int) -> Counter:
+    """PROJECTION1-style dictionary of projected strings -> multiplicity."""
+    c = Counter()
+    for S in seqs:
+        for a in range(len(S) - l + 1):
+            c[projected_string(S[a:a + l], mask)] += 1
+    return c
+
+
+def pairwise_sizes(seqs: Sequence[str], l: int, mask: int) -> List[int]:
+    """PROJECTION2 (Sec. 5.2 / Sec. 6): every projected k-mer compared with all
+    others; the bucket size of l-mer w is 1 + the number of other l-mers with
+    an equal projection.  Returned in window order."""
+    ks = [projected_string(S[a:a + l], mask) for S in seqs for a in range(len(S) - l + 1)]
+    return [1 + sum(1 for v, u in enumerate(ks) if v != w and u == ks[w]) for w in range(len(ks))]
+
+
+def windows(seqs: Sequence[str], l: int) -> List[Tuple[int, int]]:
+    return [(i, a) for i, S in enumerate(seqs) for a in range(len(S) - l + 1)]
+
+
+def profile_of(lmers: Sequence[str], letters: str) -> Dict[str, List[int]]:
+    """Profile matrix P(s) (Sec. 2): per letter, count in each column."""
+    l = len(lmers[0])
+    return {c: [sum(1 for x in lmers if x[p] == c) for p in range(l)] for c in letters}
+
+
+def score(lmers: Sequence[str], letters: str) -> int:
+    """Score(s) = sum over columns of the largest letter count (Sec. 2)."""
+    P = profile_of(lmers, letters)
+    return sum(max(P[c][p] for c in letters) for p in range(len(lmers[0])))
+
+
+def naive_mfp(seqs: Sequence[str], l: int, letters: str) -> Tuple[int, Tuple[int, ...]]:
+    """Alg. 1: exhaust every start vector, keep the best Score.  Exponential;
+    only for t <= 4 and short sequences."""
+    best, arg = -1, None
+    ranges = [range(len(S) - l + 1) for S in seqs]
+    for st in itertools.product(*ranges):
+        v = score([S[a:a + l] for S, a in zip(seqs, st)], letters)
+        if v > best:
+            best, arg = v, st
+    return best, arg
+
+
+def hamming(u: str, v: str) -> int:
+    return sum(1 for a, b in zip(u, v) if a != b)
+
+
+def ld_candidates(seqs: Sequence[str], l: int, d: int, letters: str) -> List[str]:
+    """Every M in Sigma^l that has an l-mer at Hamming distance exactly d in
+    every sequence (the (l,d) planted-motif definition, Sec. 2)."""
+    out = []
+    lm = [[S[a:a + l] for a in range(len(S) - l + 1)] for S in seqs]
+    for tup in itertools.product(letters, repeat=l):
+        M = "".join(tup)
+        if all(any(hamming(M, x) == d for x in xs) for xs in lm):
+            out.append(M)
+    return out
+
+
+def oops_loglik_ratio(seqs: Sequence[str], l: int, theta: Dict[str, List[float]],
+                      bg: Dict[str, float]) -> float:
+    """ln of the OOPS likelihood of the sequences under theta divided by the
+    all-background likelihood, computed by explicit products over every start
+    position with a uniform start prior (no log-odds, no log-sum-exp)."""
+    total = 0.0
+    for S in seqs:
+        L = len(S) - l + 1
+        back = math.prod(bg[ch] for ch in S)
+        acc = 0.0
+        for a in range(L):
+            pr = 1.0
+            for j, ch in enumerate(S):
+                pr *= theta[ch][j - a] if a <= j < a + l else bg[ch]
+            acc += pr / L
+        total += math.log(acc / back)
+    return total
+
+
+def oops_posterior(S: str, l: int, theta: Dict[str, List[float]], bg: Dict[str, float]) -> List[float]:
+    """P(start = a | S, theta) by Bayes' rule over explicit products."""
+    L = len(S) - l + 1
+    w = []
+    for a in range(L):
+        pr = 1.0
+        for j, ch in enumerate(S):
+            pr *= theta[ch][j - a] if a <= j < a + l else bg[ch]
+        w.append(pr)
+    z = sum(w)
+    return [v / z for v in w]
+
+
+def expected_complete_loglik(seqs: Sequence[str], l: int, post: Sequence[Sequence[float]],
+                             theta: Dict[str, List[float]]) -> float:
+    """Q(theta) = sum_i sum_a P(a | S_i) * sum_p ln theta[S_i[a+p]][p]: the part of
+    the expected complete-data log likelihood that depends on the motif model."""
+    q = 0.0
+    for S, ps in zip(seqs, post):
+        for a, w in enumerate(ps):
+            if w == 0.0:
+                continue
+            q += w * sum(math.log(theta[S[a + p]][p]) for p in range(l))
+    return q

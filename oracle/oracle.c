@@ -1,0 +1,394 @@
+/*
+ * oracle.c -- plain, slow, FP64 CPU reference of the PROJECTION hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or constant generator
+ * with the GPU path.
+ *
+ * Paper: "PROJECTION Algorithm for Motif Finding on GPUs" (Clemente, Cabarle,
+ * Adorna).  Each function cites the passage it follows.  Readings of passages
+ * that are silent or garbled are listed beside the function that takes them.
+ *
+ * Layout conventions (plain, no packing):
+ *   codes[]    one byte per symbol, all t sequences concatenated;
+ *   off[t+1]   symbol offsets, sequence i is codes[off[i] .. off[i+1]);
+ *   window     the l-mer of sequence i starting at a (0-based), a in
+ *              [0, n_i - l]; windows are numbered w = 0..x-1 in (i, a) order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------------- */
+/* Sec. 2 (notation) and Sec. 6 (integer equivalent of a k-mer): the DNA
+ * letters map to A:0, C:1, T:2, G:3.  The paper only lists the first protein
+ * letters (garbled); the reading taken is the conventional 20-letter order
+ * A R N D C Q E G H I L K M F P S T W Y V.                                  */
+static int code_of(int A, char ch)
+{
+    if (ch >= 'a' && ch <= 'z') ch = (char)(ch - 'a' + 'A');
+    if (A == 4) {
+        switch (ch) {
+        case 'A': return 0;
+        case 'C': return 1;
+        case 'T': return 2;
+        case 'G': return 3;
+        default: return -1;
+        }
+    }
+    if (A == 20) {
+        const char *order = "ARNDCQEGHILKMFPSTWYV";
+        for (int i = 0; i < 20; ++i)
+            if (order[i] == ch) return i;
+        return -1;
+    }
+    return -1;
+}
+
+char or_letter(int A, int code)
+{
+    if (A == 4) return "ACTG"[code];
+    return "ARNDCQEGHILKMFPSTWYV"[code];
+}
+
+/* Returns -1 on success, else the index of the first symbol outside Sigma. */
+int64_t or_encode(int A, const char *ascii, int64_t n, uint8_t *codes)
+{
+    for (int64_t g = 0; g < n; ++g) {
+        int c = code_of(A, ascii[g]);
+        if (c < 0) return g;
+        codes[g] = (uint8_t)c;
+    }
+    return -1;
+}
+
+static int64_t windows_total(int t, const int64_t *off, int l)
+{
+    int64_t x = 0;
+    for (int i = 0; i < t; ++i) x += (off[i + 1] - off[i]) - l + 1;
+    return x;
+}
+
+int64_t or_num_windows(int t, const int64_t *off, int l) { return windows_total(t, off, l); }
+
+/* ---------------------------------------------------------------------- */
+/* Sec. 5, random projection h_k and Alg. 2 steps 2(b)-(c); Sec. 6, base-|Sigma|
+ * integer of the projected k-mer, most significant symbol first (the example
+ * "AAAAAAACG" -> 7 fixes the digit order).
+ *
+ * masks[j]: bit p set <=> window position p is projected in trial j.  The
+ * projected positions are taken in ascending order (order preserved).
+ * keys:   [m][x] or NULL;  counts: [m][A^k] or NULL.                       */
+int or_hash(int A, int t, const int64_t *off, const uint8_t *codes, int l, int k,
+            const uint32_t *masks, int m, uint32_t *keys, uint32_t *counts)
+{
+    /* a mask must keep exactly k of the l positions */
+    for (int j = 0; j < m; ++j) {
+        int pc = 0;
+        for (int p = 0; p < 32; ++p)
+            if (masks[j] >> p & 1u) pc += (p < l) ? 1 : 100;
+        if (pc != k) return -1;
+    }
+    int64_t x = windows_total(t, off, l);
+    uint64_t nb = 1;
+    for (int q = 0; q < k; ++q) nb *= (uint64_t)A;
+#pragma omp parallel for schedule(dynamic)
+    for (int j = 0; j < m; ++j) {
+        int pos[32];
+        int kk = 0;
+        for (int p = 0; p < l; ++p)
+            if (masks[j] & (1u << p)) pos[kk++] = p;
+        uint32_t *cnt = counts ? counts + (int64_t)j * (int64_t)nb : NULL;
+        if (cnt) memset(cnt, 0, nb * sizeof(uint32_t));
+        int64_t w = 0;
+        for (int i = 0; i < t; ++i) {
+            int64_t n_i = off[i + 1] - off[i];
+            for (int64_t a = 0; a + l <= n_i; ++a, ++w) {
+                uint64_t key = 0;
+                for (int q = 0; q < kk; ++q)
+                    key = key * (uint64_t)A + codes[off[i] + a + pos[q]];
+                if (keys) keys[(int64_t)j * x + w] = (uint32_t)key;
+                if (cnt) cnt[key] += 1;
+            }
+        }
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Alg. 2 step 3, "identify enriched buckets": a bucket of trial j is enriched
+ * when it holds at least s l-mers.  Readings: the l-mer itself counts (size
+ * >= s); several l-mers of one sequence all count; one bucket per
+ * (trial, key), listed in ascending (trial, key) order; members are window
+ * numbers in ascending order.
+ *
+ * Output (truncated to the capacities, required totals in n_out[0..1]):
+ *   bk[4*b + 0..3] = trial, key, size, first member slot.
+ * Returns 0, or -3 when a capacity was too small.                          */
+int or_select(int t, const int64_t *off, int l, int A, int k,
+              const uint32_t *keys, const uint32_t *counts, int m, uint32_t s,
+              uint32_t *bk, int64_t cap_b, uint32_t *members, int64_t cap_m,
+              int64_t *n_out)
+{
+    int64_t x = windows_total(t, off, l);
+    uint64_t nb = 1;
+    for (int q = 0; q < k; ++q) nb *= (uint64_t)A;
+    int64_t nbk = 0, nmem = 0;
+    int64_t *slot = (int64_t *)malloc(nb * sizeof(int64_t));
+    for (int j = 0; j < m; ++j) {
+        const uint32_t *cnt = counts + (int64_t)j * (int64_t)nb;
+        const uint32_t *kj = keys + (int64_t)j * x;
+        for (uint64_t key = 0; key < nb; ++key) slot[key] = -1;
+        for (uint64_t key = 0; key < nb; ++key) {
+            if (cnt[key] >= s && cnt[key] > 0) {
+                if (nbk < cap_b) {
+                    bk[4 * nbk + 0] = (uint32_t)j;
+                    bk[4 * nbk + 1] = (uint32_t)key;
+                    bk[4 * nbk + 2] = cnt[key];
+                    bk[4 * nbk + 3] = (uint32_t)nmem;
+                }
+                slot[key] = nmem;
+                nbk += 1;
+                nmem += cnt[key];
+            }
+        }
+        /* stable placement: windows visited in ascending order */
+        for (int64_t w = 0; w < x; ++w) {
+            int64_t sl = slot[kj[w]];
+            if (sl >= 0) {
+                if (sl < cap_m) members[sl] = (uint32_t)w;
+                slot[kj[w]] = sl + 1;
+            }
+        }
+    }
+    free(slot);
+    n_out[0] = nbk;
+    n_out[1] = nmem;
+    return (nbk > cap_b || nmem > cap_m) ? -3 : 0;
+}
+
+/* window number -> (sequence, start) */
+static void window_site(int t, const int64_t *off, int l, int64_t w, int *i_out, int64_t *a_out)
+{
+    for (int i = 0; i < t; ++i) {
+        int64_t L = (off[i + 1] - off[i]) - l + 1;
+        if (w < L) { *i_out = i; *a_out = w; return; }
+        w -= L;
+    }
+    *i_out = -1; *a_out = -1;
+}
+
+/* Sec. 2, profile matrix P(s): count of each letter in each column of the
+ * alignment of the bucket's l-mers.  prof: [nb_use][A][l].                 */
+void or_profile(int t, const int64_t *off, const uint8_t *codes, int l, int A,
+                const uint32_t *bk, int64_t nbk, const uint32_t *members, uint32_t *prof)
+{
+    for (int64_t b = 0; b < nbk; ++b) {
+        uint32_t *P = prof + b * A * l;
+        memset(P, 0, sizeof(uint32_t) * A * l);
+        for (uint32_t r = 0; r < bk[4 * b + 2]; ++r) {
+            int i; int64_t a;
+            window_site(t, off, l, members[bk[4 * b + 3] + r], &i, &a);
+            for (int p = 0; p < l; ++p) P[codes[off[i] + a + p] * l + p] += 1;
+        }
+    }
+}
+
+/* Sec. 5.1 and Fig. 4: the initial model theta^0 is the column-letter
+ * frequency of the bucket's alignment.  Reading (the paper prints zeros and
+ * gives no pseudocounts): theta0 = (f + beta*bg) / (size + beta); beta = 0
+ * gives the paper's raw frequencies.                                       */
+void or_theta0(int A, int l, const uint32_t *prof, int64_t nbk, const double *bg,
+               double beta, double *theta0)
+{
+    for (int64_t b = 0; b < nbk; ++b) {
+        const uint32_t *P = prof + b * A * l;
+        double size = 0;
+        for (int c = 0; c < A; ++c) size += P[c * l + 0];
+        for (int c = 0; c < A; ++c)
+            for (int p = 0; p < l; ++p)
+                theta0[b * A * l + c * l + p] = (P[c * l + p] + beta * bg[c]) / (size + beta);
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Sec. 5.1, EM refinement under the OOPS model (Sec. 2: one occurrence per
+ * sequence).  The paper states neither step; the reading taken is the
+ * standard OOPS EM of the works it cites (Lawrence & Reilly; Bailey), with a
+ * uniform prior 1/L_i over the L_i = n_i - l + 1 starts and the background
+ * fixed at bg:
+ *
+ *   W[c][p]  = ln theta[c][p] - ln bg[c]
+ *   s_ia     = sum_p W[S_i[a+p]][p]                   (log-odds of start a)
+ *   LSE_i    = ln sum_a exp(s_ia)
+ *   Z_ia     = exp(s_ia - LSE_i)                      (E-step posterior)
+ *   LLR      = sum_i (LSE_i - ln L_i)
+ *   J        = LLR + beta * sum_{c,p} bg[c] ln theta[c][p]
+ *   counts   c[c][p] = sum_{i,a} Z_ia [S_i[a+p] = c]   (M-step)
+ *   theta'   = (counts + beta*bg) / (t + beta)
+ *
+ * J is the penalised likelihood that this EM never decreases (Dempster et
+ * al.).  This function does one E-step for one model and exposes every
+ * intermediate; s, Z: [x]; lse: [t].  Returns LLR.                          */
+double or_estep(int t, const int64_t *off, const uint8_t *codes, int l, int A,
+                const double *theta, const double *bg, double *s, double *Z, double *lse)
+{
+    double W[20 * 32];
+    for (int c = 0; c < A; ++c)
+        for (int p = 0; p < l; ++p) W[c * l + p] = log(theta[c * l + p]) - log(bg[c]);
+    double llr = 0;
+    int64_t w0 = 0;
+    for (int i = 0; i < t; ++i) {
+        int64_t L = (off[i + 1] - off[i]) - l + 1;
+        double mx = -INFINITY;
+        for (int64_t a = 0; a < L; ++a) {
+            double v = 0;
+            for (int p = 0; p < l; ++p) v += W[codes[off[i] + a + p] * l + p];
+            s[w0 + a] = v;
+            if (v > mx) mx = v;
+        }
+        double sum = 0;
+        for (int64_t a = 0; a < L; ++a) sum += exp(s[w0 + a] - mx);
+        double ls = mx + log(sum);
+        if (lse) lse[i] = ls;
+        for (int64_t a = 0; a < L; ++a) Z[w0 + a] = exp(s[w0 + a] - ls);
+        llr += ls - log((double)L);
+        w0 += L;
+    }
+    return llr;
+}
+
+/* The M-step above for one model given the posteriors Z: [x]. */
+void or_mstep(int t, const int64_t *off, const uint8_t *codes, int l, int A,
+              const double *Z, const double *bg, double beta, double *theta_new)
+{
+    double cnt[20 * 32];
+    memset(cnt, 0, sizeof(cnt));
+    int64_t w0 = 0;
+    for (int i = 0; i < t; ++i) {
+        int64_t L = (off[i + 1] - off[i]) - l + 1;
+        for (int64_t a = 0; a < L; ++a)
+            for (int p = 0; p < l; ++p) cnt[codes[off[i] + a + p] * l + p] += Z[w0 + a];
+        w0 += L;
+    }
+    for (int c = 0; c < A; ++c)
+        for (int p = 0; p < l; ++p)
+            theta_new[c * l + p] = (cnt[c * l + p] + beta * bg[c]) / ((double)t + beta);
+}
+
+static double prior_term(int A, int l, const double *theta, const double *bg, double beta)
+{
+    if (beta == 0) return 0;
+    double v = 0;
+    for (int c = 0; c < A; ++c)
+        for (int p = 0; p < l; ++p) v += bg[c] * log(theta[c * l + p]);
+    return beta * v;
+}
+
+/* EM for B independent models, iters iterations, then a final E-step.
+ *   theta0, theta_out: [B][A][l];  J, llr: [B][iters+1] (for theta^0..theta^iters);
+ *   sites: [B][t], the start a maximising s_ia under theta^iters (first on ties). */
+void or_em(int t, const int64_t *off, const uint8_t *codes, int l, int A,
+           const double *theta0, const double *bg, int64_t B, int iters, double beta,
+           double *theta_out, double *J, double *llr, int32_t *sites)
+{
+    int64_t x = windows_total(t, off, l);
+#pragma omp parallel
+    {
+        double *s = (double *)malloc(sizeof(double) * (x > 0 ? x : 1));
+        double *Z = (double *)malloc(sizeof(double) * (x > 0 ? x : 1));
+        double th[20 * 32], th2[20 * 32];
+#pragma omp for schedule(dynamic)
+        for (int64_t b = 0; b < B; ++b) {
+            memcpy(th, theta0 + b * A * l, sizeof(double) * A * l);
+            for (int it = 0; it <= iters; ++it) {
+                double v = or_estep(t, off, codes, l, A, th, bg, s, Z, NULL);
+                llr[b * (iters + 1) + it] = v;
+                J[b * (iters + 1) + it] = v + prior_term(A, l, th, bg, beta);
+                if (it < iters) {
+                    or_mstep(t, off, codes, l, A, Z, bg, beta, th2);
+                    memcpy(th, th2, sizeof(double) * A * l);
+                }
+            }
+            memcpy(theta_out + b * A * l, th, sizeof(double) * A * l);
+            int64_t w0 = 0;
+            for (int i = 0; i < t; ++i) {
+                int64_t L = (off[i + 1] - off[i]) - l + 1;
+                int64_t best = 0;
+                for (int64_t a = 1; a < L; ++a)
+                    if (s[w0 + a] > s[w0 + best]) best = a;
+                sites[b * t + i] = (int32_t)best;
+                w0 += L;
+            }
+        }
+        free(s);
+        free(Z);
+    }
+}
+
+/* Sec. 5.1: the model with the highest objective is the answer.  Readings:
+ * the objective is J(theta^iters); ties go to the lowest bucket index (the
+ * lowest (trial, key)); the consensus takes in each column the letter of
+ * largest probability, the lowest code on ties (Sec. 2 lets ties be broken
+ * arbitrarily).  NaN objectives never win.  Returns the bucket index or -1. */
+int64_t or_best(const double *J, int64_t B, int iters, const double *theta, int A, int l,
+                char *consensus)
+{
+    int64_t best = -1;
+    for (int64_t b = 0; b < B; ++b) {
+        double v = J[b * (iters + 1) + iters];
+        if (v != v) continue;
+        if (best < 0 || v > J[best * (iters + 1) + iters]) best = b;
+    }
+    if (best >= 0 && consensus) {
+        const double *th = theta + best * A * l;
+        for (int p = 0; p < l; ++p) {
+            int bc = 0;
+            for (int c = 1; c < A; ++c)
+                if (th[c * l + p] > th[bc * l + p]) bc = c;
+            consensus[p] = or_letter(A, bc);
+        }
+        consensus[l] = 0;
+    }
+    return best;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Projection tables from a seed (Sec. 6: l-k positions *not* to project are
+ * drawn on the host).  Generator: the minimal standard generator of Park and
+ * Miller (the paper's cited RNG), x <- 16807 x mod (2^31 - 1).  Reading of
+ * "l-k random numbers in range [0,l]": l-k distinct positions from
+ * {0..l-1}, drawn by a partial Fisher-Yates shuffle of the identity
+ * permutation with index i + (r mod (l - i)).  The state for trial j starts
+ * at 1 + (seed + j) mod (2^31 - 2), so every trial has its own stream.     */
+static uint32_t pm_next(uint64_t *state)
+{
+    *state = (*state * 16807u) % 2147483647u;
+    return (uint32_t)*state;
+}
+
+uint32_t or_parkmiller(uint64_t seed, int n)
+{
+    uint64_t st = seed;
+    uint32_t v = 0;
+    for (int i = 0; i < n; ++i) v = pm_next(&st);
+    return v;
+}
+
+void or_masks(uint64_t seed, int l, int k, int m, uint32_t *masks)
+{
+    for (int j = 0; j < m; ++j) {
+        uint64_t st = 1 + (seed + (uint64_t)j) % 2147483646u;
+        int perm[32];
+        for (int p = 0; p < l; ++p) perm[p] = p;
+        uint32_t mask = (l == 32) ? 0xffffffffu : ((1u << l) - 1u);
+        for (int i = 0; i < l - k; ++i) {
+            int r = i + (int)(pm_next(&st) % (uint32_t)(l - i));
+            int tmp = perm[i]; perm[i] = perm[r]; perm[r] = tmp;
+            mask &= ~(1u << perm[i]);
+        }
+        masks[j] = mask;
+    }
+}
