@@ -1,0 +1,224 @@
+/*
+ * projmotif.h -- C ABI of the MI355X (gfx950) PROJECTION motif-finding path.
+ *
+ * Paper: "PROJECTION Algorithm for Motif Finding on GPUs" (Clemente, Cabarle,
+ * Adorna).  The problem statement (Sec. 2; Alg. 2 and Alg. 3 INPUT/OUTPUT)
+ * fixes the arguments: sequences S_1..S_t over an alphabet Sigma, motif
+ * length l, projection size k, bucket threshold s, number of trials m.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an int status: PM_OK (0) or a negative PM_E*
+ *    code; pm_last_error() then gives a message (thread-local).  No C++
+ *    exception crosses this boundary.
+ *  - Pointers documented "device" are HIP device addresses; "host" are host
+ *    addresses.  The caller owns every buffer: the library never frees caller
+ *    memory, and the device-pointer entry points allocate nothing.
+ *  - Device-pointer entry points are asynchronous on `stream` (a hipStream_t
+ *    passed as void*, NULL = the null stream).  Host-side argument checks
+ *    return an error before anything is enqueued.  Conditions that only the
+ *    device can see (a symbol outside Sigma, a bad projection mask, a capacity
+ *    that is too small) are OR-ed into a caller-provided device word `status`
+ *    (PM_STATUS_* bits; may be NULL) and the affected outputs are left
+ *    unwritten or truncated as documented.
+ *  - Counts that depend on the data (number of enriched buckets) are written
+ *    to device memory; later calls read them from there (`n_dev`), so a whole
+ *    pass needs no host synchronisation.
+ *  - Symbol codes: DNA A:0 C:1 T:2 G:3 (Sec. 6); protein in the order
+ *    A R N D C Q E G H I L K M F P S T W Y V (the paper lists the protein
+ *    alphabet only in part).  Lower-case letters are accepted.
+ *  - Window (l-mer) numbering: window w is the l-mer of sequence i starting
+ *    at a (0-based), numbered in (i, a) order; x = sum_i (n_i - l + 1).
+ *    Sites are 0-based (the paper's a_i are 1-based, Sec. 2).
+ */
+#ifndef PROJMOTIF_H
+#define PROJMOTIF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PM_OK 0
+#define PM_EINVAL (-1)     /* invalid argument (l, k, s, m, alphabet, sizes) */
+#define PM_ERANGE (-2)     /* supported but too large: |Sigma|^k, LDS budget */
+#define PM_ECAPACITY (-3)  /* an output capacity was too small */
+#define PM_EDEVICE (-4)    /* a HIP runtime error */
+
+#define PM_STATUS_BAD_SYMBOL 1u  /* pm_pack met a byte outside Sigma */
+#define PM_STATUS_BAD_MASK 2u    /* a projection mask does not keep exactly k of l positions */
+#define PM_STATUS_CAPACITY 4u    /* bucket_select outputs truncated */
+
+#define PM_DNA 4
+#define PM_PROTEIN 20
+
+/* EM arithmetic (em_refine `precision`) */
+#define PM_FP64 0 /* every step in FP64 */
+#define PM_FP32 1 /* scores, posteriors and counts in FP32; log-sum-exp and J in FP64 */
+
+/* Encoded sequences.  Host fields describe the device arrays. */
+typedef struct pm_seqs {
+    int32_t alphabet;        /* |Sigma|: PM_DNA or PM_PROTEIN */
+    int32_t t;               /* number of sequences, >= 1 */
+    int64_t n_total;         /* host: sum of the lengths n_i */
+    int32_t n_min;           /* host: shortest n_i */
+    int32_t n_max;           /* host: longest n_i */
+    const int64_t *offsets;  /* device [t+1]: offsets[0] = 0, sequence i is symbols
+                                offsets[i] .. offsets[i+1]-1 of the concatenation */
+    const uint32_t *packed;  /* device [pm_packed_words(alphabet, n_total)] from pm_pack */
+} pm_seqs;
+
+/* One enriched bucket (Alg. 2 step 3). */
+typedef struct pm_bucket {
+    uint32_t trial; /* trial j in [0, m) */
+    uint32_t key;   /* base-|Sigma| integer of the projected k-mer (Sec. 6) */
+    uint32_t size;  /* number of l-mers hashed to it (>= s) */
+    uint32_t first; /* index of its first member in the members array */
+} pm_bucket;
+
+const char *pm_version(void);
+const char *pm_last_error(void);
+
+/* Number of uint32 words pm_pack writes for n_total symbols: 16 DNA or 6
+ * protein symbols per word, first symbol in the most significant bits, plus
+ * four zero words of padding at the end. */
+int64_t pm_packed_words(int32_t alphabet, int64_t n_total);
+
+/* a1 -- encode and pack (Sec. 6: the one-to-one map of letters to integers;
+ * Sec. 6: sequences passed to the device as flat arrays).
+ *   ascii   device [n_total] bytes, the t sequences concatenated
+ *   packed  device [pm_packed_words(alphabet, n_total)], fully written
+ * A byte outside Sigma is encoded as code 0 and sets PM_STATUS_BAD_SYMBOL. */
+int pm_pack(int32_t alphabet, const uint8_t *ascii, int64_t n_total, uint32_t *packed,
+            uint32_t *status, void *stream);
+
+/* a2 -- projection tables on the host (Sec. 6: the l-k positions not to
+ * project are drawn on the host).  Park-Miller minimal standard generator
+ * (the paper's cited RNG); trial j uses the stream started at
+ * 1 + (seed + j) mod (2^31 - 2) and a partial Fisher-Yates shuffle.
+ *   masks  host [m]; bit p set <=> window position p is projected. */
+int pm_masks_from_seed(uint64_t seed, int32_t l, int32_t k, int32_t m, uint32_t *masks);
+
+/* Sec. 5, choice of the parameters when not given: k = l - d - 1;
+ * s = max(3, ceil(2 x / |Sigma|^k)) (twice the mean bucket size, the paper
+ * falling back to 3-4 when that mean is tiny); m = ceil(log(1-q) / log B(s)),
+ * B(s) = P[Binomial(t, p_hat) < s], p_hat = C(l-d,k) / C(l,k).  Host only. */
+int pm_auto_params(int32_t alphabet, int32_t t, int64_t x, int32_t l, int32_t d, double q,
+                   int32_t *k, int32_t *s, int32_t *m);
+
+/* a3 + a4 -- Alg. 2 steps 2(b) and 2(c): project every l-mer onto the
+ * positions kept by each trial's mask (Sec. 5, order preserved) and hash the
+ * k-mer to its base-|Sigma| integer, most significant symbol first (Sec. 6,
+ * "AAAAAAACG" -> 7); count the l-mers of every bucket (PROJECTION1, Sec. 5.2).
+ *   masks   device [m] (popcount k, below 2^l; otherwise PM_STATUS_BAD_MASK
+ *           and that trial's outputs are not written)
+ *   keys    device [m][x] uint32, or NULL
+ *   counts  device [m][|Sigma|^k] uint32, or NULL (at least one non-NULL)
+ * Limits: 1 <= k <= l <= 32, l <= n_min, |Sigma|^k <= 2^24 when counts are
+ * requested (< 2^32 for keys only). */
+int projection_hash(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m,
+                    uint32_t *keys, uint32_t *counts, uint32_t *status, void *stream);
+
+/* Workspace bytes bucket_select needs for m trials and cap_buckets buckets. */
+size_t pm_select_workspace(int32_t m, int64_t cap_buckets);
+
+/* a5 -- Alg. 2 step 3 and Sec. 6 (a bucket passes when it holds at least s
+ * l-mers): list every (trial, key) with counts >= s, ascending by (trial,
+ * key), and the member windows of each, ascending.
+ *   keys, counts  device, as written by projection_hash
+ *   buckets       device [cap_buckets]
+ *   members       device [cap_members] window numbers
+ *   n_out         device int64[2]: required number of buckets and members
+ *                 (may exceed the capacities: then the lists are truncated to
+ *                 their first entries and PM_STATUS_CAPACITY is set)
+ *   ws            device, pm_select_workspace(m, cap_buckets) bytes
+ * Limit: |Sigma|^k <= 2^24. */
+int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *keys,
+                  const uint32_t *counts, int32_t m, uint32_t s, pm_bucket *buckets,
+                  int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out,
+                  void *ws, size_t ws_bytes, uint32_t *status, void *stream);
+
+/* a6 (first half) -- Sec. 2 profile matrix P(s) of each bucket's alignment.
+ *   members      device [cap_members] as written by bucket_select; a bucket
+ *                whose members run past cap_members gets an all-zero profile
+ *   B            host capacity (grid size); n_dev device count of valid
+ *                buckets (e.g. n_out of bucket_select) or NULL when all B are
+ *                valid
+ *   profile      device [B][|Sigma|][l] uint32 letter counts per column */
+int bucket_profile(const pm_seqs *S, int32_t l, const pm_bucket *buckets,
+                   const uint32_t *members, int64_t cap_members, int64_t B, const int64_t *n_dev,
+                   uint32_t *profile, void *stream);
+
+/* a6 -- Sec. 5.1, Fig. 4: initial model theta^0 from the profile,
+ * theta0 = (profile + beta * bg) / (size + beta) (beta = 0: the paper's raw
+ * frequencies).  bg device [|Sigma|]; theta0 device [B][|Sigma|][l]. */
+int theta_init(int32_t alphabet, int32_t l, const uint32_t *profile, int64_t B,
+               const int64_t *n_dev, const double *bg, double beta, double *theta0, void *stream);
+
+/* a7 - a10 -- Sec. 5.1, EM refinement of each model under the OOPS model
+ * (Sec. 2).  The paper gives no formulas; the model is the standard OOPS EM
+ * with a uniform start prior and fixed background bg:
+ *   s_ia = sum_p ln(theta[S_i[a+p]][p] / bg[S_i[a+p]]),
+ *   LSE_i = ln sum_a exp s_ia,  Z_ia = exp(s_ia - LSE_i),
+ *   LLR = sum_i (LSE_i - ln L_i),  J = LLR + beta * sum bg ln theta,
+ *   theta' = (sum Z_ia [S_i[a+p] = c] + beta * bg) / (t + beta).
+ * `iters` M-steps, then a final E-step.
+ *   theta0     device [B][|Sigma|][l]
+ *   theta_out  device [B][|Sigma|][l]   (theta^iters)
+ *   J_out      device [B][iters+1]      (J of theta^0 .. theta^iters)
+ *   llr_out    device [B][iters+1] or NULL
+ *   sites_out  device [B][t] int32 or NULL: argmax_a s_ia under theta^iters,
+ *              first on ties
+ *   precision  PM_FP64 or PM_FP32 */
+int em_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
+              const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
+              double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *stream);
+
+/* a10 -- Sec. 5.1: the model with the highest objective wins.  best_out
+ * device int64[1]: the bucket with the largest J(theta^iters), lowest index
+ * on ties, -1 if none; consensus_out device char[l+1]: the letter of largest
+ * probability per column of that model (lowest code on ties), NUL-ended. */
+int em_best(const double *J, int64_t B, const int64_t *n_dev, int32_t iters, const double *theta,
+            int32_t alphabet, int32_t l, int64_t *best_out, char *consensus_out, void *stream);
+
+/* The whole path on one instance, host in, host out, synchronous.  This
+ * convenience entry point allocates and frees its own device buffers. */
+typedef struct pm_problem {
+    int32_t alphabet;          /* PM_DNA or PM_PROTEIN */
+    int32_t t;                 /* number of sequences */
+    const char *const *seqs;   /* host [t] strings */
+    const int32_t *n;          /* host [t] lengths */
+    int32_t l, d;              /* motif length, mutations (d only feeds auto parameters) */
+    int32_t k, s, m;           /* <= 0: chosen by pm_auto_params */
+    const uint32_t *masks;     /* host [m] or NULL: drawn by pm_masks_from_seed(seed) */
+    uint64_t seed;
+    const double *bg;          /* host [|Sigma|] in code order, or NULL: input composition */
+} pm_problem;
+
+typedef struct pm_options {
+    int32_t em_iters;   /* M-steps per model */
+    double beta;        /* pseudocount mass for theta^0 and the M-step */
+    int32_t precision;  /* PM_FP64 / PM_FP32 */
+    void *stream;
+} pm_options;
+
+typedef struct pm_result {
+    char *consensus;      /* host [l+1], caller-owned */
+    int32_t *sites;       /* host [t], caller-owned, 0-based */
+    double *theta;        /* host [|Sigma|][l], caller-owned, or NULL */
+    double J, llr;        /* objective and log-likelihood ratio of the answer */
+    int32_t best_trial;
+    uint32_t best_key;
+    int64_t n_enriched;   /* buckets refined */
+    int32_t k, s, m;      /* parameters used */
+} pm_result;
+
+int projection_run(const pm_problem *P, const pm_options *O, pm_result *R);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROJMOTIF_H */

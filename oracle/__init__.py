@@ -240,8 +240,12 @@ def auto_params(l: int, d: int, t: int, n_total_windows: int, A: int, q: float =
     instances, where 3-4 is used); m = ceil(log(1-q) / log B(s))."""
     k = l - d - 1
     s = max(3, math.ceil(2.0 * n_total_windows / float(A) ** k))
-    B = b_below(t, p_hat(l, d, k), s)
-    m = 1 if B <= 0 else max(1, math.ceil(math.log(1 - q) / math.log(B)))
+    if s > t:
+        raise ValueError("the threshold exceeds t: the planted bucket cannot pass")
+    p = p_hat(l, d, k)
+    # 1 - B(s) summed directly, so log B = log1p(-tail) stays accurate near 1
+    tail = sum(math.comb(t, i) * p ** i * (1 - p) ** (t - i) for i in range(s, t + 1))
+    m = 1 if tail >= 1 else max(1, math.ceil(math.log(1 - q) / math.log1p(-tail)))
     return k, s, m
 
 

@@ -1,0 +1,315 @@
+// a7 - a10: OOPS EM refinement of every enriched bucket, and the final pick.
+//
+// Sec. 5.1 of the paper refines each enriched bucket with EM for a fixed
+// number of iterations and keeps the model with the highest objective; it
+// does not write the steps down.  The model here is the standard OOPS EM with
+// a uniform start prior and a fixed background (see projmotif.h).
+//
+// Vector path: one workgroup (4 waves) per model.  The packed instance is
+// staged in LDS; each wave owns whole sequences, so the per-sequence
+// log-sum-exp is a wavefront reduction; the E-step reads the log-odds table
+// from LDS; M-step counts go to per-wave LDS accumulators.
+#include <math.h>
+
+#include "pm_common.h"
+
+namespace pm {
+
+struct EmArgs {
+    const uint32_t *packed;
+    const int64_t *offsets;
+    const double *theta0;
+    const double *bg;
+    const int64_t *n_dev;
+    double *theta_out;
+    double *J;
+    double *llr;
+    int32_t *sites;
+    int64_t B;
+    int t, l, iters;
+    double beta;
+    int seq_words;  // packed words staged in LDS (0: read from global)
+    int stage_off;
+};
+
+constexpr int kEmThreads = 256;
+constexpr int kEmWaves = kEmThreads / 64;
+
+template <typename T>
+__device__ __forceinline__ T ninf();
+template <>
+__device__ __forceinline__ float ninf<float>() { return -INFINITY; }
+template <>
+__device__ __forceinline__ double ninf<double>() { return -INFINITY; }
+
+__device__ __forceinline__ float ex(float v) { return expf(v); }
+__device__ __forceinline__ double ex(double v) { return exp(v); }
+
+template <typename V>
+__device__ __forceinline__ V block_sum(V v, V *red)
+{
+    v = wave_sum(v);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    V r = red[0];
+#pragma unroll
+    for (int w = 1; w < kEmWaves; ++w) r += red[w];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        int64_t u = __shfl_xor(v, o);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
+template <typename T, int A>
+__device__ __forceinline__ T score_at(const uint32_t *W, int64_t P, const T *Wt, int l)
+{
+    T s = 0;
+    if (A == 4) {
+        uint32_t hi, lo;
+        dna_window(W, P, hi, lo);
+        for (int p = 0; p < l; ++p) s += Wt[dna_at(hi, lo, p) * l + p];
+    } else {
+        for (int p = 0; p < l; ++p) s += Wt[prot_sym(W, P + p) * l + p];
+    }
+    return s;
+}
+
+template <typename T, int A>
+__global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
+{
+    const int64_t b = blockIdx.x;
+    int64_t nvalid = a.n_dev ? *a.n_dev : a.B;
+    if (nvalid > a.B) nvalid = a.B;
+    if (b >= nvalid) return;
+
+    __shared__ T th[A * 32];
+    __shared__ T Wt[A * 32];
+    __shared__ T acc[kEmWaves][A * 32];
+    __shared__ double red[kEmWaves];
+    extern __shared__ __align__(16) uint32_t dyn[];
+    uint32_t *seq = dyn;
+    int64_t *offs = reinterpret_cast<int64_t *>(dyn + ((a.seq_words + 1) & ~1));
+
+    const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
+    const int l = a.l, t = a.t, AL = A * l;
+    const double beta = a.beta;
+
+    for (int i = tid; i < AL; i += kEmThreads) th[i] = (T)a.theta0[b * AL + i];
+    for (int i = tid; i < a.seq_words; i += kEmThreads) seq[i] = a.packed[i];
+    if (a.stage_off)
+        for (int i = tid; i <= t; i += kEmThreads) offs[i] = a.offsets[i];
+    __syncthreads();
+    const uint32_t *W = a.seq_words ? seq : a.packed;
+    const int64_t *O = a.stage_off ? offs : a.offsets;
+
+    for (int it = 0; it <= a.iters; ++it) {
+        const bool last = it == a.iters;
+        double pr = 0;
+        for (int i = tid; i < AL; i += kEmThreads) {
+            const int c = i / l;
+            const T v = th[i];
+            Wt[i] = (T)(log((double)v) - log(a.bg[c]));
+            if (beta != 0) pr += a.bg[c] * log((double)v);
+        }
+        for (int i = tid; i < kEmWaves * A * 32; i += kEmThreads) (&acc[0][0])[i] = 0;
+        pr = block_sum(pr, red);  // includes the barrier that publishes Wt
+
+        double llr_w = 0;
+        for (int i = wv; i < t; i += kEmWaves) {
+            const int64_t s0 = O[i];
+            const int64_t L = O[i + 1] - s0 - l + 1;
+            T mx = ninf<T>(), sm = 0, bv = ninf<T>();
+            int64_t ba = 0;
+            for (int64_t x = lane; x < L; x += 64) {
+                const T s = score_at<T, A>(W, s0 + x, Wt, l);
+                // online log-sum-exp, one exponential per window
+                const bool up = s > mx;
+                const T e = ex(up ? mx - s : s - mx);
+                sm = up ? sm * e + (T)1 : (s > ninf<T>() ? sm + e : sm);
+                mx = up ? s : mx;
+                if (last && s > bv) {
+                    bv = s;
+                    ba = x;
+                }
+            }
+            const T M = wave_max(mx);
+            const T part = mx > ninf<T>() ? sm * ex(mx - M) : (T)0;
+            const T Ssum = wave_sum(part);
+            const double lse = (double)M + log((double)Ssum);
+            llr_w += lse - log((double)L);
+            if (last) {
+                if (a.sites) {
+                    const T bm = wave_max(bv);
+                    const int64_t cand = wave_min_i64(bv == bm ? ba : INT64_MAX);
+                    if (lane == 0) a.sites[b * t + i] = (int32_t)cand;
+                }
+            } else {
+                T *ac = acc[wv];
+                const T lse_t = (T)lse;
+                for (int64_t x = lane; x < L; x += 64) {
+                    const T s = score_at<T, A>(W, s0 + x, Wt, l);
+                    const T z = ex(s - lse_t);
+                    const int64_t P = s0 + x;
+                    if (A == 4) {
+                        uint32_t hi, lo;
+                        dna_window(W, P, hi, lo);
+                        for (int p = 0; p < l; ++p) atomicAdd(&ac[dna_at(hi, lo, p) * l + p], z);
+                    } else {
+                        for (int p = 0; p < l; ++p) atomicAdd(&ac[prot_sym(W, P + p) * l + p], z);
+                    }
+                }
+            }
+        }
+        // every lane of a wave holds the same llr_w; count each wave once
+        const double llr = block_sum(lane == 0 ? llr_w : 0.0, red);
+        if (tid == 0) {
+            a.J[b * (a.iters + 1) + it] = llr + beta * pr;
+            if (a.llr) a.llr[b * (a.iters + 1) + it] = llr;
+        }
+        if (!last) {
+            for (int i = tid; i < AL; i += kEmThreads) {
+                const int c = i / l;
+                T cs = 0;
+#pragma unroll
+                for (int w = 0; w < kEmWaves; ++w) cs += acc[w][i];
+                th[i] = (T)(((double)cs + beta * a.bg[c]) / ((double)t + beta));
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < AL; i += kEmThreads) a.theta_out[b * AL + i] = (double)th[i];
+}
+
+template <typename T, int A>
+static int launch_em(const EmArgs &a, size_t lds, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_em_vec<T, A>), dim3((unsigned)a.B), dim3(kEmThreads), lds, st, a);
+    PM_LAUNCHED();
+    return PM_OK;
+}
+
+// ---------------------------------------------------------------- a10
+__global__ void __launch_bounds__(256) k_best(const double *J, int64_t B, const int64_t *n_dev, int iters,
+                                              const double *theta, int A, int l, int64_t *best_out,
+                                              char *cons)
+{
+    __shared__ double rv[4];
+    __shared__ int64_t ri[4];
+    __shared__ int64_t best_s;
+    int64_t nvalid = n_dev ? *n_dev : B;
+    if (nvalid > B) nvalid = B;
+    double bv = -INFINITY;
+    int64_t bi = INT64_MAX;
+    for (int64_t b = threadIdx.x; b < nvalid; b += 256) {
+        const double v = J[b * (iters + 1) + iters];
+        if (v == v && (bi == INT64_MAX || v > bv)) {
+            bv = v;
+            bi = b;
+        }
+    }
+    // (value, index): larger value wins, then smaller index
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o);
+        const int64_t oi = __shfl_xor(bi, o);
+        if (oi != INT64_MAX && (bi == INT64_MAX || ov > bv || (ov == bv && oi < bi))) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    if (lane_id() == 0) {
+        rv[threadIdx.x >> 6] = bv;
+        ri[threadIdx.x >> 6] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = rv[0];
+        int64_t i = ri[0];
+        for (int w = 1; w < 4; ++w)
+            if (ri[w] != INT64_MAX && (i == INT64_MAX || rv[w] > v || (rv[w] == v && ri[w] < i))) {
+                v = rv[w];
+                i = ri[w];
+            }
+        best_s = i == INT64_MAX ? -1 : i;
+        best_out[0] = best_s;
+    }
+    __syncthreads();
+    const int64_t bb = best_s;
+    if (!cons) return;
+    const char *letters = A == 4 ? "ACTG" : "ARNDCQEGHILKMFPSTWYV";
+    if ((int)threadIdx.x < l) {
+        char ch = 0;
+        if (bb >= 0) {
+            const double *th = theta + bb * A * l;
+            int bc = 0;
+            for (int c = 1; c < A; ++c)
+                if (th[c * l + threadIdx.x] > th[bc * l + threadIdx.x]) bc = c;
+            ch = letters[bc];
+        }
+        cons[threadIdx.x] = ch;
+    }
+    if (threadIdx.x == 0) cons[l] = 0;
+}
+
+}  // namespace pm
+
+using namespace pm;
+
+extern "C" int em_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
+                         const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
+                         double *theta_out, double *J_out, double *llr_out, int32_t *sites_out,
+                         void *stream)
+{
+    clear_error();
+    int rc = check_seqs(S, l);
+    if (rc) return rc;
+    if (B < 0 || iters < 0 || beta < 0) return fail(PM_EINVAL, "need B >= 0, iters >= 0, beta >= 0");
+    if (precision != PM_FP64 && precision != PM_FP32) return fail(PM_EINVAL, "unknown precision %d", precision);
+    if (B == 0) return PM_OK;
+    if (B > 0x7fffffff) return fail(PM_ERANGE, "B above 2^31 - 1");
+    if (!theta0 || !bg || !theta_out || !J_out) return fail(PM_EINVAL, "NULL buffer");
+    EmArgs a{};
+    a.packed = S->packed;
+    a.offsets = S->offsets;
+    a.theta0 = theta0;
+    a.bg = bg;
+    a.n_dev = n_dev;
+    a.theta_out = theta_out;
+    a.J = J_out;
+    a.llr = llr_out;
+    a.sites = sites_out;
+    a.B = B;
+    a.t = S->t;
+    a.l = l;
+    a.iters = iters;
+    a.beta = beta;
+    const int64_t nw = pm_packed_words(S->alphabet, S->n_total);
+    a.seq_words = nw * 4 <= 48 * 1024 ? (int)nw : 0;
+    a.stage_off = (S->t + 1) * 8 <= 8 * 1024;
+    const size_t lds = ((a.seq_words + 1) & ~1) * 4 + (a.stage_off ? (S->t + 1) * 8 : 0);
+    hipStream_t st = as_stream(stream);
+    if (S->alphabet == 4)
+        return precision == PM_FP64 ? launch_em<double, 4>(a, lds, st) : launch_em<float, 4>(a, lds, st);
+    return precision == PM_FP64 ? launch_em<double, 20>(a, lds, st) : launch_em<float, 20>(a, lds, st);
+}
+
+extern "C" int em_best(const double *J, int64_t B, const int64_t *n_dev, int32_t iters, const double *theta,
+                       int32_t alphabet, int32_t l, int64_t *best_out, char *consensus_out, void *stream)
+{
+    clear_error();
+    if (alphabet != 4 && alphabet != 20) return fail(PM_EINVAL, "alphabet must be 4 or 20");
+    if (l < 1 || l > 32 || B < 0 || iters < 0) return fail(PM_EINVAL, "bad sizes");
+    if (!best_out || (B > 0 && (!J || !theta))) return fail(PM_EINVAL, "NULL buffer");
+    hipLaunchKernelGGL(k_best, dim3(1), dim3(256), 0, as_stream(stream), J, B, n_dev, iters, theta,
+                       alphabet, l, best_out, consensus_out);
+    PM_LAUNCHED();
+    return PM_OK;
+}

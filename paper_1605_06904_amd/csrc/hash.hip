@@ -1,0 +1,293 @@
+// a1 (encode + pack) and a3/a4 (projection, keys, bucket histogram) on gfx950.
+//
+// Sec. 6 of the paper maps letters to integers and projects/hashes one l-mer
+// per GPU thread.  Here one workgroup owns one trial (and one slice of the
+// key range when the |Sigma|^k histogram does not fit in LDS): it stages the
+// packed input (a few KB) in LDS, builds keys from LDS windows, writes them
+// with coalesced stores and counts them in an LDS histogram with
+// wave-aggregated atomics, then streams the histogram out as dense u32 counts.
+#include <algorithm>
+
+#include "pm_common.h"
+
+namespace pm {
+
+// ---------------------------------------------------------------- a1: pack
+__device__ __forceinline__ int code_of(int A, uint32_t ch)
+{
+    if (ch >= 'a' && ch <= 'z') ch -= 'a' - 'A';
+    if (A == 4) {
+        switch (ch) {
+        case 'A': return 0;
+        case 'C': return 1;
+        case 'T': return 2;
+        case 'G': return 3;
+        default: return -1;
+        }
+    }
+    switch (ch) {
+    case 'A': return 0;  case 'R': return 1;  case 'N': return 2;  case 'D': return 3;
+    case 'C': return 4;  case 'Q': return 5;  case 'E': return 6;  case 'G': return 7;
+    case 'H': return 8;  case 'I': return 9;  case 'L': return 10; case 'K': return 11;
+    case 'M': return 12; case 'F': return 13; case 'P': return 14; case 'S': return 15;
+    case 'T': return 16; case 'W': return 17; case 'Y': return 18; case 'V': return 19;
+    default: return -1;
+    }
+}
+
+__global__ void k_pack(int A, const uint8_t *__restrict__ ascii, int64_t n, uint32_t *__restrict__ packed,
+                       int64_t nwords, uint32_t *status)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nwords) return;
+    const int per = A == 4 ? 16 : 6;
+    const int bits = A == 4 ? 2 : 5;
+    uint32_t v = 0;
+    bool bad = false;
+    for (int q = 0; q < per; ++q) {
+        const int64_t g = w * per + q;
+        int c = 0;
+        if (g < n) {
+            c = code_of(A, ascii[g]);
+            if (c < 0) {
+                bad = true;
+                c = 0;
+            }
+        }
+        v |= (uint32_t)c << (32 - bits * (q + 1));
+    }
+    packed[w] = v;
+    if (bad && status) atomicOr(status, PM_STATUS_BAD_SYMBOL);
+}
+
+// ---------------------------------------------------------------- a3 + a4
+struct HashArgs {
+    const uint32_t *packed;
+    const int64_t *offsets;
+    const uint32_t *masks;
+    uint32_t *keys;
+    uint32_t *counts;
+    uint32_t *status;
+    int64_t x;           // windows per trial
+    int64_t nb;          // |Sigma|^k
+    int t, l, k;
+    int nslices;         // key-range slices per trial
+    uint32_t slice_bins; // bins per slice (multiple of 4)
+    int hist_words;      // LDS words of histogram
+    int seq_words;       // packed words staged in LDS (0: read from global)
+    int stage_off;       // offsets staged in LDS
+};
+
+constexpr int kHashThreads = 1024;
+
+template <int A, bool U16>
+__global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
+{
+    extern __shared__ __align__(16) uint32_t smem[];
+    const int slice = blockIdx.x % a.nslices;
+    const int j = blockIdx.x / a.nslices;
+    const int tid = threadIdx.x;
+
+    const uint32_t mask = a.masks[j];
+    const uint32_t lmask = a.l == 32 ? 0xffffffffu : ((1u << a.l) - 1u);
+    if (__popc(mask) != a.k || (mask & ~lmask)) {
+        if (tid == 0 && slice == 0 && a.status) atomicOr(a.status, PM_STATUS_BAD_MASK);
+        return;
+    }
+
+    uint32_t *hist = smem;
+    uint32_t *seq = smem + a.hist_words;
+    int64_t *offs = reinterpret_cast<int64_t *>(seq + ((a.seq_words + 1) & ~1));
+
+    for (int i = tid; i < a.seq_words; i += kHashThreads) seq[i] = a.packed[i];
+    if (a.stage_off)
+        for (int i = tid; i <= a.t; i += kHashThreads) offs[i] = a.offsets[i];
+    if (a.counts)
+        for (int i = tid * 4; i < a.hist_words; i += kHashThreads * 4)
+            *reinterpret_cast<uint4 *>(hist + i) = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+
+    const uint32_t *W = a.seq_words ? seq : a.packed;
+    const int64_t *O = a.stage_off ? offs : a.offsets;
+
+    // kept positions, ascending (uniform across the workgroup)
+    constexpr int MAXK = A == 4 ? 16 : 7;
+    int pos[MAXK];
+    {
+        uint32_t mm = mask;
+#pragma unroll
+        for (int q = 0; q < MAXK; ++q) {
+            pos[q] = mm ? __builtin_ctz(mm) : 0;
+            mm &= mm - 1;
+        }
+    }
+
+    const uint64_t slice_base = (uint64_t)slice * a.slice_bins;
+    const int64_t kw0 = a.x * slice / a.nslices, kw1 = a.x * (slice + 1) / a.nslices;
+    uint32_t *keys_j = a.keys ? a.keys + (int64_t)j * a.x : nullptr;
+    const int lane = lane_id();
+    const int64_t lm1 = a.l - 1;
+
+    int i = 0;
+    for (int64_t w = tid; w < a.x; w += kHashThreads) {
+        while (w >= O[i + 1] - (int64_t)(i + 1) * lm1) ++i;
+        const int64_t P = w + (int64_t)i * lm1;
+        uint32_t key = 0;
+        if (A == 4) {
+            uint32_t hi, lo;
+            dna_window(W, P, hi, lo);
+#pragma unroll
+            for (int q = 0; q < MAXK; ++q)
+                if (q < a.k) key = (key << 2) | dna_at(hi, lo, pos[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < MAXK; ++q)
+                if (q < a.k) key = key * 20u + prot_sym(W, P + pos[q]);
+        }
+        if (keys_j && w >= kw0 && w < kw1) __builtin_nontemporal_store(key, keys_j + w);
+        if (a.counts) {
+            const uint64_t bin64 = (uint64_t)key - slice_base;
+            const bool valid = bin64 < a.slice_bins;
+            const uint32_t bin = (uint32_t)bin64;
+            // wave-aggregated atomics: the lanes sharing the first valid lane's
+            // bin add once, the others add one each
+            const uint64_t vb = __ballot(valid);
+            if (vb) {
+                const int leader = __ffsll((unsigned long long)vb) - 1;
+                const uint32_t lb = __shfl(bin, leader);
+                const uint64_t same = __ballot(valid && bin == lb);
+                if (valid) {
+                    if (bin == lb) {
+                        if (lane == leader) {
+                            const uint32_t n = __popcll(same);
+                            if (U16) atomicAdd(hist + (lb >> 1), n << ((lb & 1) << 4));
+                            else atomicAdd(hist + lb, n);
+                        }
+                    } else {
+                        if (U16) atomicAdd(hist + (bin >> 1), 1u << ((bin & 1) << 4));
+                        else atomicAdd(hist + bin, 1u);
+                    }
+                }
+            }
+        }
+    }
+    if (!a.counts) return;
+    __syncthreads();
+
+    const uint64_t left = (uint64_t)a.nb - slice_base;
+    const uint32_t nvalid = left < a.slice_bins ? (uint32_t)left : a.slice_bins;  // multiple of 4
+    uint32_t *out = a.counts + (int64_t)j * a.nb + slice_base;
+    for (uint32_t b4 = tid * 4; b4 < nvalid; b4 += kHashThreads * 4) {
+        uint4 v;
+        if (U16) {
+            const uint32_t w0 = hist[b4 >> 1], w1 = hist[(b4 >> 1) + 1];
+            v = make_uint4(w0 & 0xffffu, w0 >> 16, w1 & 0xffffu, w1 >> 16);
+        } else {
+            v = *reinterpret_cast<const uint4 *>(hist + b4);
+        }
+        __builtin_nontemporal_store(v.x, out + b4 + 0);
+        __builtin_nontemporal_store(v.y, out + b4 + 1);
+        __builtin_nontemporal_store(v.z, out + b4 + 2);
+        __builtin_nontemporal_store(v.w, out + b4 + 3);
+    }
+}
+
+template <int A, bool U16>
+static int launch_hash(const HashArgs &a, size_t lds, int blocks, hipStream_t st)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_hash<A, U16>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, device_lds_bytes());
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_hash<A, U16>), dim3(blocks), dim3(kHashThreads), lds, st, a);
+    PM_LAUNCHED();
+    return PM_OK;
+}
+
+}  // namespace pm
+
+using namespace pm;
+
+extern "C" int64_t pm_packed_words(int32_t alphabet, int64_t n_total)
+{
+    if (alphabet != 4 && alphabet != 20) return -1;
+    const int per = alphabet == 4 ? 16 : 6;
+    return (n_total + per - 1) / per + 4;
+}
+
+extern "C" int pm_pack(int32_t alphabet, const uint8_t *ascii, int64_t n_total, uint32_t *packed,
+                       uint32_t *status, void *stream)
+{
+    clear_error();
+    if (alphabet != 4 && alphabet != 20) return fail(PM_EINVAL, "alphabet must be 4 or 20");
+    if (n_total < 0 || (n_total > 0 && !ascii) || !packed) return fail(PM_EINVAL, "bad buffers");
+    const int64_t nw = pm_packed_words(alphabet, n_total);
+    const int threads = 256;
+    const int64_t blocks = (nw + threads - 1) / threads;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(threads), 0, as_stream(stream), alphabet,
+                       ascii, n_total, packed, nw, status);
+    PM_LAUNCHED();
+    return PM_OK;
+}
+
+extern "C" int projection_hash(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks,
+                               int32_t m, uint32_t *keys, uint32_t *counts, uint32_t *status,
+                               void *stream)
+{
+    clear_error();
+    int rc = check_seqs(S, l);
+    if (rc) return rc;
+    if (k < 1 || k > l) return fail(PM_EINVAL, "need 1 <= k <= l (k=%d, l=%d)", k, l);
+    if (m < 0) return fail(PM_EINVAL, "m must be >= 0");
+    if (!masks && m > 0) return fail(PM_EINVAL, "masks is NULL");
+    if (!keys && !counts) return fail(PM_EINVAL, "keys and counts are both NULL");
+    const int A = S->alphabet;
+    if ((A == 4 && k > 16) || (A == 20 && k > 7))
+        return fail(PM_ERANGE, "|Sigma|^k must stay below 2^32 (k=%d)", k);
+    const int64_t nb = ipow(A, k);
+    if (counts && nb > (1ll << 24)) return fail(PM_ERANGE, "|Sigma|^k = %lld bins is above 2^24", (long long)nb);
+    if (m == 0) return PM_OK;
+
+    HashArgs a{};
+    a.packed = S->packed;
+    a.offsets = S->offsets;
+    a.masks = masks;
+    a.keys = keys;
+    a.counts = counts;
+    a.status = status;
+    a.x = num_windows(S, l);
+    a.nb = nb;
+    a.t = S->t;
+    a.l = l;
+    a.k = k;
+    const bool u16 = a.x < 65536;
+    const int lds_max = device_lds_bytes();
+    const int64_t nw = pm_packed_words(A, S->n_total);
+    a.seq_words = nw * 4 <= 48 * 1024 ? (int)nw : 0;
+    a.stage_off = (S->t + 1) * 8 <= 8 * 1024;
+    const int fixed = ((a.seq_words + 1) & ~1) * 4 + (a.stage_off ? (S->t + 1) * 8 : 0);
+    if (counts) {
+        const int64_t need_words = u16 ? (nb + 1) / 2 : nb;
+        int64_t budget = (lds_max - fixed) / 4;
+        budget &= ~int64_t(3);
+        if (budget < 1024) return fail(PM_ERANGE, "input too large for the LDS budget");
+        int64_t hw = std::min<int64_t>(need_words, budget);
+        hw = (hw + 3) & ~int64_t(3);
+        if (hw > budget) hw = budget;
+        a.hist_words = (int)hw;
+        a.slice_bins = (uint32_t)(u16 ? 2 * hw : hw);
+        a.nslices = (int)((nb + a.slice_bins - 1) / a.slice_bins);
+    } else {
+        a.hist_words = 0;
+        a.slice_bins = 0;
+        a.nslices = 1;
+    }
+    const size_t lds = (size_t)a.hist_words * 4 + fixed;
+    const int64_t blocks = (int64_t)m * a.nslices;
+    if (blocks > 0x7fffffff) return fail(PM_ERANGE, "too many trials x slices");
+    hipStream_t st = as_stream(stream);
+    if (A == 4) return u16 ? launch_hash<4, true>(a, lds, (int)blocks, st) : launch_hash<4, false>(a, lds, (int)blocks, st);
+    return u16 ? launch_hash<20, true>(a, lds, (int)blocks, st) : launch_hash<20, false>(a, lds, (int)blocks, st);
+}

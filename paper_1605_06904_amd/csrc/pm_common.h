@@ -1,0 +1,134 @@
+// Shared device helpers and host error plumbing of libprojmotif (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "projmotif.h"
+
+namespace pm {
+
+// ---------------------------------------------------------------- host side
+int fail(int code, const char *fmt, ...);
+void clear_error();
+int device_lds_bytes();  // max dynamic LDS per workgroup on the current device
+hipStream_t as_stream(void *s);
+
+#define PM_TRY(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::pm::fail(PM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define PM_LAUNCHED()                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = hipGetLastError();                                                    \
+        if (e_ != hipSuccess)                                                                 \
+            return ::pm::fail(PM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+static inline int64_t ipow(int64_t a, int k)
+{
+    int64_t r = 1;
+    for (int i = 0; i < k; ++i) r *= a;
+    return r;
+}
+
+// windows of the instance for motif length l
+static inline int64_t num_windows(const pm_seqs *S, int l)
+{
+    return S->n_total - (int64_t)S->t * (l - 1);
+}
+
+int check_seqs(const pm_seqs *S, int l);
+
+// ---------------------------------------------------------------- device side
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Symbol g of a DNA sequence packed 16 per word, first symbol in bits 31..30.
+__device__ __forceinline__ uint32_t dna_sym(const uint32_t *w, int64_t g)
+{
+    return (w[g >> 4] >> (30 - ((uint32_t)(g & 15) << 1))) & 3u;
+}
+
+// 32 consecutive DNA symbols starting at P: symbols P..P+15 in `hi`,
+// P+16..P+31 in `lo`, each MSB-first.  Reads words P/16 .. P/16+2.
+__device__ __forceinline__ void dna_window(const uint32_t *w, int64_t P, uint32_t &hi, uint32_t &lo)
+{
+    const int64_t wi = P >> 4;
+    const uint32_t r = (uint32_t)(P & 15) << 1;
+    const uint64_t a = ((uint64_t)w[wi] << 32) | w[wi + 1];
+    const uint64_t b = ((uint64_t)w[wi + 1] << 32) | w[wi + 2];
+    hi = (uint32_t)(a >> (32 - r));
+    lo = (uint32_t)(b >> (32 - r));
+}
+
+// Symbol p (0..31) of a window fetched by dna_window.
+__device__ __forceinline__ uint32_t dna_at(uint32_t hi, uint32_t lo, int p)
+{
+    const uint32_t src = p < 16 ? hi : lo;
+    return (src >> (30 - ((p & 15) << 1))) & 3u;
+}
+
+// floor(g / 6) for 0 <= g < 2^32.
+__device__ __forceinline__ uint32_t div6(uint32_t g)
+{
+    return (uint32_t)(((uint64_t)g * 0xAAAAAAABull) >> 34);
+}
+
+// Symbol g of a protein sequence packed 6 per word (5 bits each), first
+// symbol in bits 31..27.
+__device__ __forceinline__ uint32_t prot_sym(const uint32_t *w, int64_t g)
+{
+    const uint32_t q = div6((uint32_t)g);
+    const uint32_t r = (uint32_t)g - 6u * q;
+    return (w[q] >> (27 - 5 * r)) & 31u;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T u = __shfl_xor(v, o);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+// inclusive prefix sum over the 64 lanes (all lanes active)
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t n = __shfl_up(v, o);
+        if (lane >= o) v += n;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// device-scope (L2) loads/stores that never see a stale per-CU cache line
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace pm

@@ -1,0 +1,354 @@
+// a5 (enriched-bucket selection and member lists) and a6 (profiles, theta^0).
+//
+// The paper finds enriched buckets by comparing every k-mer with every other
+// one (Sec. 6, quadratic work) to avoid a |Sigma|^k table.  On MI355X the dense
+// counts already sit in HBM (the histogram of projection_hash), so selection is
+// a streaming pass: count the passing bins per trial, scan the per-trial
+// totals, then one wave per trial emits the buckets in key order with
+// wave-level prefix sums and places every member window with a stable,
+// deterministic counting sort.
+#include "pm_common.h"
+
+namespace pm {
+
+struct SelWs {
+    int64_t *ne;   // [m] enriched buckets per trial
+    int64_t *ms;   // [m] members per trial
+    int64_t *bb;   // [m] first bucket of the trial
+    int64_t *mb;   // [m] first member slot of the trial
+    uint32_t *fill;  // [cap_b] members placed so far
+};
+
+static SelWs carve(void *ws, int32_t m, int64_t cap_b)
+{
+    char *p = static_cast<char *>(ws);
+    SelWs w;
+    w.ne = reinterpret_cast<int64_t *>(p);
+    w.ms = w.ne + m;
+    w.bb = w.ms + m;
+    w.mb = w.bb + m;
+    w.fill = reinterpret_cast<uint32_t *>(w.mb + m);
+    (void)cap_b;
+    return w;
+}
+
+struct SelArgs {
+    const uint32_t *keys;
+    const uint32_t *counts;
+    pm_bucket *buckets;
+    uint32_t *members;
+    int64_t *n_out;
+    uint32_t *status;
+    SelWs ws;
+    int64_t x, nb, cap_b, cap_m;
+    int32_t m;
+    uint32_t s;
+};
+
+__device__ __forceinline__ bool passes(uint32_t c, uint32_t s) { return c >= s && c > 0; }
+
+// per trial: number of passing bins and their total size
+__global__ void __launch_bounds__(256) k_sel_count(const SelArgs a)
+{
+    const int j = blockIdx.x;
+    const uint32_t *cnt = a.counts + (int64_t)j * a.nb;
+    uint64_t ne = 0, ms = 0;
+    for (int64_t b = threadIdx.x; b < a.nb; b += 256) {
+        const uint32_t c = cnt[b];
+        if (passes(c, a.s)) {
+            ne += 1;
+            ms += c;
+        }
+    }
+    ne = wave_sum(ne);
+    ms = wave_sum(ms);
+    __shared__ uint64_t red[2][4];
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        red[0][wv] = ne;
+        red[1][wv] = ms;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.ws.ne[j] = (int64_t)(red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+        a.ws.ms[j] = (int64_t)(red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+    }
+}
+
+// exclusive scan of the per-trial totals (one workgroup)
+__global__ void __launch_bounds__(1024) k_sel_scan(const SelArgs a)
+{
+    __shared__ int64_t sa[1024], sb[1024];
+    __shared__ int64_t carry[2];
+    if (threadIdx.x == 0) carry[0] = carry[1] = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < a.m; base += 1024) {
+        const int64_t j = base + threadIdx.x;
+        const int64_t ve = j < a.m ? a.ws.ne[j] : 0, vm = j < a.m ? a.ws.ms[j] : 0;
+        sa[threadIdx.x] = ve;
+        sb[threadIdx.x] = vm;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            int64_t ua = 0, ub = 0;
+            if ((int)threadIdx.x >= o) {
+                ua = sa[threadIdx.x - o];
+                ub = sb[threadIdx.x - o];
+            }
+            __syncthreads();
+            sa[threadIdx.x] += ua;
+            sb[threadIdx.x] += ub;
+            __syncthreads();
+        }
+        if (j < a.m) {
+            a.ws.bb[j] = carry[0] + sa[threadIdx.x] - ve;
+            a.ws.mb[j] = carry[1] + sb[threadIdx.x] - vm;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) {
+            carry[0] += sa[1023];
+            carry[1] += sb[1023];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.n_out[0] = carry[0];
+        a.n_out[1] = carry[1];
+        if ((carry[0] > a.cap_b || carry[1] > a.cap_m) && a.status) atomicOr(a.status, PM_STATUS_CAPACITY);
+    }
+}
+
+// one wave per trial: bucket records in key order, then members in window order
+__global__ void __launch_bounds__(64) k_sel_emit(const SelArgs a)
+{
+    const int j = blockIdx.x;
+    const int lane = lane_id();
+    const uint32_t *cnt = a.counts + (int64_t)j * a.nb;
+    const int64_t bbase = a.ws.bb[j], mbase = a.ws.mb[j];
+    int64_t lcount = 0, lsize = 0;
+
+    for (int64_t c0 = 0; c0 < a.nb; c0 += 64) {
+        const int64_t key = c0 + lane;
+        const uint32_t c = key < a.nb ? cnt[key] : 0u;
+        const bool flag = passes(c, a.s);
+        const uint64_t bal = __ballot(flag);
+        if (!bal) continue;
+        const uint32_t rank = __popcll(bal & lanemask_lt());
+        const uint32_t mine = flag ? c : 0u;
+        const uint32_t incl = wave_incl_scan(mine);
+        const uint32_t tot = __shfl(incl, 63);
+        if (flag) {
+            const int64_t b = bbase + lcount + rank;
+            if (b < a.cap_b) {
+                const int64_t first = mbase + lsize + (incl - mine);
+                pm_bucket *B = a.buckets + b;
+                st_agent(&B->trial, (uint32_t)j);
+                st_agent(&B->key, (uint32_t)key);
+                st_agent(&B->size, c);
+                st_agent(&B->first, (uint32_t)first);
+                st_agent(a.ws.fill + b, 0u);
+            }
+        }
+        lcount += __popcll(bal);
+        lsize += tot;
+    }
+    __threadfence();
+
+    int64_t nloc = a.cap_b - bbase;
+    if (nloc < 0) nloc = 0;
+    if (nloc > lcount) nloc = lcount;
+    if (nloc == 0) return;
+    const uint32_t *kj = a.keys + (int64_t)j * a.x;
+    for (int64_t w0 = 0; w0 < a.x; w0 += 64) {
+        const int64_t w = w0 + lane;
+        const bool valid = w < a.x;
+        const uint32_t key = valid ? kj[w] : 0u;
+        const uint32_t c = valid && key < a.nb ? cnt[key] : 0u;
+        const bool flag = valid && passes(c, a.s);
+        uint64_t bal = __ballot(flag);
+        while (bal) {
+            const int leader = __ffsll((unsigned long long)bal) - 1;
+            const uint32_t lk = __shfl(key, leader);
+            const bool peer = flag && key == lk;
+            const uint64_t peers = __ballot(peer);
+            int64_t slot0 = -1;
+            if (lane == leader) {
+                int64_t lo = 0, hi = nloc;
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (ld_agent(&a.buckets[bbase + mid].key) < lk) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo < nloc && ld_agent(&a.buckets[bbase + lo].key) == lk) {
+                    const int64_t b = bbase + lo;
+                    const uint32_t old = atomicAdd(a.ws.fill + b, (uint32_t)__popcll(peers));
+                    slot0 = (int64_t)ld_agent(&a.buckets[b].first) + old;
+                }
+            }
+            slot0 = __shfl(slot0, leader);
+            if (peer && slot0 >= 0) {
+                const int64_t slot = slot0 + __popcll(peers & lanemask_lt());
+                if (slot < a.cap_m) a.members[slot] = (uint32_t)w;
+            }
+            bal &= ~peers;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- a6
+struct ProfArgs {
+    const uint32_t *packed;
+    const int64_t *offsets;
+    const pm_bucket *buckets;
+    const uint32_t *members;
+    const int64_t *n_dev;
+    uint32_t *profile;
+    int64_t B, cap_m;
+    int t, l, A;
+};
+
+// one wave per bucket; lane p owns column p
+__global__ void __launch_bounds__(256) k_profile(const ProfArgs a)
+{
+    __shared__ uint32_t cnt[4][20 * 32];
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    const int64_t b = (int64_t)blockIdx.x * 4 + wv;
+    int64_t nvalid = a.n_dev ? *a.n_dev : a.B;
+    if (nvalid > a.B) nvalid = a.B;
+    if (b >= nvalid) return;
+    uint32_t *C = cnt[wv];
+    for (int i = lane; i < a.A * 32; i += 64) C[i] = 0;
+    const pm_bucket bk = a.buckets[b];
+    const int64_t lm1 = a.l - 1;
+    const uint32_t size = (int64_t)bk.first + bk.size <= a.cap_m ? bk.size : 0u;
+    for (uint32_t r = 0; r < size; ++r) {
+        const int64_t w = a.members[(int64_t)bk.first + r];
+        int lo = 0, hi = a.t;  // last sequence whose first window <= w
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.offsets[mid] - (int64_t)mid * lm1 <= w) lo = mid;
+            else hi = mid;
+        }
+        const int64_t P = w + (int64_t)lo * lm1;
+        if (lane < a.l) {
+            const uint32_t code = a.A == 4 ? dna_sym(a.packed, P + lane) : prot_sym(a.packed, P + lane);
+            C[code * 32 + lane] += 1;
+        }
+    }
+    uint32_t *out = a.profile + b * a.A * a.l;
+    for (int i = lane; i < a.A * a.l; i += 64) out[i] = C[(i / a.l) * 32 + (i % a.l)];
+}
+
+__global__ void k_theta_init(const uint32_t *__restrict__ prof, const int64_t *n_dev, int64_t B, int A,
+                             int l, const double *__restrict__ bg, double beta, double *__restrict__ th)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)A * l;
+    const int64_t b = g / per;
+    int64_t nvalid = n_dev ? *n_dev : B;
+    if (nvalid > B) nvalid = B;
+    if (b >= nvalid) return;
+    const int rem = (int)(g - b * per);
+    const int c = rem / l, p = rem % l;
+    const uint32_t *P = prof + b * per;
+    double size = 0;
+    for (int cc = 0; cc < A; ++cc) size += P[cc * l];
+    th[g] = (P[rem] + beta * bg[c]) / (size + beta);
+    (void)p;
+}
+
+}  // namespace pm
+
+using namespace pm;
+
+extern "C" size_t pm_select_workspace(int32_t m, int64_t cap_buckets)
+{
+    if (m < 0 || cap_buckets < 0) return 0;
+    return (size_t)m * 4 * sizeof(int64_t) + (size_t)cap_buckets * sizeof(uint32_t) + 256;
+}
+
+extern "C" int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *keys,
+                             const uint32_t *counts, int32_t m, uint32_t s, pm_bucket *buckets,
+                             int64_t cap_buckets, uint32_t *members, int64_t cap_members,
+                             int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status, void *stream)
+{
+    clear_error();
+    int rc = check_seqs(S, l);
+    if (rc) return rc;
+    if (k < 1 || k > l) return fail(PM_EINVAL, "need 1 <= k <= l");
+    if (m < 1) return fail(PM_EINVAL, "m must be >= 1");
+    if (!keys || !counts || !n_out || !ws) return fail(PM_EINVAL, "keys, counts, n_out and ws are required");
+    if (cap_buckets < 0 || cap_members < 0) return fail(PM_EINVAL, "negative capacity");
+    if ((cap_buckets > 0 && !buckets) || (cap_members > 0 && !members))
+        return fail(PM_EINVAL, "NULL output with a non-zero capacity");
+    if (cap_members > 0xffffffffll) return fail(PM_ERANGE, "cap_members must be below 2^32");
+    const int A = S->alphabet;
+    if ((A == 4 && k > 12) || (A == 20 && k > 5)) return fail(PM_ERANGE, "|Sigma|^k above 2^24");
+    if (ws_bytes < pm_select_workspace(m, cap_buckets)) return fail(PM_EINVAL, "workspace too small");
+    SelArgs a{};
+    a.keys = keys;
+    a.counts = counts;
+    a.buckets = buckets;
+    a.members = members;
+    a.n_out = n_out;
+    a.status = status;
+    a.ws = carve(ws, m, cap_buckets);
+    a.x = num_windows(S, l);
+    a.nb = ipow(A, k);
+    a.cap_b = cap_buckets;
+    a.cap_m = cap_members;
+    a.m = m;
+    a.s = s;
+    hipStream_t st = as_stream(stream);
+    hipLaunchKernelGGL(k_sel_count, dim3(m), dim3(256), 0, st, a);
+    PM_LAUNCHED();
+    hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(1024), 0, st, a);
+    PM_LAUNCHED();
+    hipLaunchKernelGGL(k_sel_emit, dim3(m), dim3(64), 0, st, a);
+    PM_LAUNCHED();
+    return PM_OK;
+}
+
+extern "C" int bucket_profile(const pm_seqs *S, int32_t l, const pm_bucket *buckets,
+                              const uint32_t *members, int64_t cap_members, int64_t B,
+                              const int64_t *n_dev, uint32_t *profile, void *stream)
+{
+    clear_error();
+    int rc = check_seqs(S, l);
+    if (rc) return rc;
+    if (B < 0) return fail(PM_EINVAL, "B must be >= 0");
+    if (B == 0) return PM_OK;
+    if (!buckets || !members || !profile) return fail(PM_EINVAL, "NULL buffer");
+    ProfArgs a{};
+    a.packed = S->packed;
+    a.offsets = S->offsets;
+    a.buckets = buckets;
+    a.members = members;
+    a.n_dev = n_dev;
+    a.profile = profile;
+    a.B = B;
+    a.cap_m = cap_members;
+    a.t = S->t;
+    a.l = l;
+    a.A = S->alphabet;
+    hipLaunchKernelGGL(k_profile, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, as_stream(stream), a);
+    PM_LAUNCHED();
+    return PM_OK;
+}
+
+extern "C" int theta_init(int32_t alphabet, int32_t l, const uint32_t *profile, int64_t B,
+                          const int64_t *n_dev, const double *bg, double beta, double *theta0,
+                          void *stream)
+{
+    clear_error();
+    if (alphabet != 4 && alphabet != 20) return fail(PM_EINVAL, "alphabet must be 4 or 20");
+    if (l < 1 || l > 32) return fail(PM_EINVAL, "need 1 <= l <= 32");
+    if (B < 0 || beta < 0) return fail(PM_EINVAL, "need B >= 0 and beta >= 0");
+    if (B == 0) return PM_OK;
+    if (!profile || !bg || !theta0) return fail(PM_EINVAL, "NULL buffer");
+    const int64_t total = B * alphabet * l;
+    const int threads = 256;
+    hipLaunchKernelGGL(k_theta_init, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0,
+                       as_stream(stream), profile, n_dev, B, alphabet, l, bg, beta, theta0);
+    PM_LAUNCHED();
+    return PM_OK;
+}

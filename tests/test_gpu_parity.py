@@ -1,0 +1,426 @@
+"""Parity of the HIP path with the CPU oracle, element by element.
+
+Integer outputs (codes, keys, counts, bucket lists, members, profiles) must be
+bit-exact.  EM: FP64 path within 1e-12 relative of the oracle; FP32 path within
+1e-5 relative on J and LLR (the target of the FP32 form); consensus identical.
+Inputs are seeded and synthetic.  Every case prints its name before it touches
+the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1605_06904_amd as pm
+from synth import make_config, planted_instance, projection_masks, random_sequences
+from tests.conftest import read_golden
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    yield
+    torch.cuda.synchronize()
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _bg(A, rng=None):
+    if A == 4:
+        return np.full(4, 0.25)
+    return rng.dirichlet(np.full(20, 2.0)) if rng is not None else np.full(20, 0.05)
+
+
+def _unpack(words, A, n):
+    per, bits = (16, 2) if A == 4 else (6, 5)
+    out = np.zeros(n, dtype=np.uint8)
+    for g in range(n):
+        w = int(words[g // per])
+        out[g] = (w >> (32 - bits * (g % per + 1))) & ((1 << bits) - 1)
+    return out
+
+
+# ------------------------------------------------------------------ a1 pack
+@pytest.mark.parametrize("A,alpha", [(4, "dna"), (20, "protein")])
+def test_pack_matches_oracle_codes(A, alpha):
+    rng = np.random.default_rng(100 + A)
+    seqs = random_sequences(rng, 5, [37, 1, 64, 17, 250], alpha)
+    seqs[1] = seqs[1].lower()
+    say("pack", A)
+    S = pm.Seqs(A, seqs)
+    torch.cuda.synchronize()
+    assert int(S.status.item()) == 0
+    ref = oracle.Seqs(A, seqs)
+    words = u32(S.packed)
+    assert len(words) == pm.pm_packed_words(A, S.n_total)
+    assert np.array_equal(_unpack(words, A, S.n_total), ref.codes[:S.n_total])
+    per = 16 if A == 4 else 6
+    assert np.all(words[(S.n_total + per - 1) // per:] == 0)
+
+
+def test_pack_flags_foreign_symbols():
+    say("pack bad symbol")
+    S = pm.Seqs(4, ["ACGTNACGT", "ACGT"])
+    torch.cuda.synchronize()
+    assert int(S.status.item()) & pm.PM_STATUS_BAD_SYMBOL
+    with pytest.raises(pm.PmError):
+        S.check_status()
+
+
+# ------------------------------------------------------------------ a3 + a4
+def _hash_gpu(S, l, k, masks, keys=True, counts=True):
+    m = len(masks)
+    x, nb = S.nwin(l), S.alphabet ** k
+    dm = torch.from_numpy(np.ascontiguousarray(masks, dtype=np.uint32).view(np.int32)).cuda()
+    K = torch.full((m, x), -1, dtype=torch.int32, device="cuda") if keys else None
+    N = torch.full((m, nb), -1, dtype=torch.int32, device="cuda") if counts else None
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pm.projection_hash(S, l, k, dm, m, K, N, st)
+    torch.cuda.synchronize()
+    return (u32(K) if keys else None), (u32(N) if counts else None), int(st.item())
+
+
+HASH_CASES = [
+    # name, alphabet, t, lengths, l, k, m
+    ("dna small ragged", 4, 6, [40, 33, 57, 19, 80, 26], 8, 5, 7),
+    ("dna several tiles", 4, 9, [700, 1500, 333, 64, 999, 1200, 41, 512, 2048], 15, 7, 11),
+    ("dna l=32 k=16 keys", 4, 3, [64, 40, 33], 32, 11, 3),
+    ("dna u32 histogram x>=65536", 4, 40, [1700] * 40, 12, 6, 3),
+    ("dna sliced k=9", 4, 10, [900] * 10, 21, 9, 4),
+    ("protein k=3", 20, 7, [120, 31, 77, 64, 200, 23, 50], 10, 3, 5),
+    ("protein sliced k=4", 20, 12, [400] * 12, 20, 4, 3),
+    ("dna k=1", 4, 3, [10, 12, 9], 1, 1, 2),
+]
+
+
+@pytest.mark.parametrize("case", HASH_CASES, ids=[c[0] for c in HASH_CASES])
+def test_hash_bit_exact(case):
+    name, A, t, lens, l, k, m = case
+    rng = np.random.default_rng(abs(hash(name)) % 2**32)
+    seqs = random_sequences(rng, t, lens, "dna" if A == 4 else "protein")
+    masks = projection_masks(rng, l, k, m)
+    say("hash", name)
+    S = pm.Seqs(A, seqs)
+    counts_on = A ** k <= (1 << 24) and not (A == 4 and k > 12)
+    K, N, st = _hash_gpu(S, l, k, masks, counts=counts_on)
+    assert st == 0
+    ref = oracle.Seqs(A, seqs)
+    RK, RN = oracle.hash_trials(ref, l, k, masks, counts=counts_on)
+    assert np.array_equal(K, RK)
+    if counts_on:
+        assert np.array_equal(N, RN)
+        assert np.all(N.sum(axis=1, dtype=np.int64) == S.nwin(l))
+
+
+def test_hash_outputs_one_at_a_time():
+    rng = np.random.default_rng(7)
+    seqs = random_sequences(rng, 4, [300, 200, 250, 90], "dna")
+    masks = projection_masks(rng, 14, 6, 5)
+    say("hash keys-only / counts-only")
+    S = pm.Seqs(4, seqs)
+    K, _, _ = _hash_gpu(S, 14, 6, masks, counts=False)
+    _, N, _ = _hash_gpu(S, 14, 6, masks, keys=False)
+    RK, RN = oracle.hash_trials(oracle.Seqs(4, seqs), 14, 6, masks)
+    assert np.array_equal(K, RK) and np.array_equal(N, RN)
+
+
+def test_hash_bad_mask_sets_status_and_skips_trial():
+    rng = np.random.default_rng(8)
+    seqs = random_sequences(rng, 3, 100, "dna")
+    masks = projection_masks(rng, 10, 4, 3)
+    masks[1] = 0b1111100000  # five kept positions, k = 4
+    say("hash bad mask")
+    S = pm.Seqs(4, seqs)
+    K, N, st = _hash_gpu(S, 10, 4, masks)
+    assert st & pm.PM_STATUS_BAD_MASK
+    RK, RN = oracle.hash_trials(oracle.Seqs(4, seqs), 10, 4, masks[[0, 2]])
+    assert np.array_equal(K[[0, 2]], RK) and np.array_equal(N[[0, 2]], RN)
+    assert np.all(K[1] == 0xFFFFFFFF) and np.all(N[1] == 0xFFFFFFFF)
+
+
+def test_hash_degenerate_single_bucket():
+    """Poly-A input: every l-mer lands in one bucket (all lanes of every wave
+    collide on one bin)."""
+    seqs = ["A" * 3000] * 8
+    masks = projection_masks(np.random.default_rng(9), 11, 5, 2)
+    say("hash poly-A")
+    S = pm.Seqs(4, seqs)
+    K, N, st = _hash_gpu(S, 11, 5, masks)
+    x = S.nwin(11)
+    assert np.all(K == 0) and np.all(N[:, 0] == x) and np.all(N[:, 1:] == 0)
+
+
+# ------------------------------------------------------------------ a5, a6
+def _select_gpu(S, l, k, s, K, N, cap_b=None, cap_m=None):
+    m = K.shape[0]
+    dK = torch.from_numpy(K.view(np.int32)).cuda()
+    dN = torch.from_numpy(N.view(np.int32)).cuda()
+    nout = torch.zeros(2, dtype=torch.int64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    if cap_b is None:
+        ws = torch.zeros(pm.pm_select_workspace(m, 0) // 4 + 1, dtype=torch.int32, device="cuda")
+        pm.bucket_select(S, l, k, dK, dN, m, s, None, 0, None, 0, nout, ws, ws.numel() * 4, st)
+        torch.cuda.synchronize()
+        cap_b, cap_m = [int(v) for v in nout.cpu()]
+    bk = torch.full((max(cap_b, 1), 4), -1, dtype=torch.int32, device="cuda")
+    mem = torch.full((max(cap_m, 1),), -1, dtype=torch.int32, device="cuda")
+    ws = torch.zeros(pm.pm_select_workspace(m, cap_b) // 4 + 1, dtype=torch.int32, device="cuda")
+    st.zero_()
+    pm.bucket_select(S, l, k, dK, dN, m, s, bk, cap_b, mem, cap_m, nout, ws, ws.numel() * 4, st)
+    torch.cuda.synchronize()
+    nb_, nm_ = [int(v) for v in nout.cpu()]
+    return bk, mem, nout, (nb_, nm_), int(st.item()), cap_b, cap_m
+
+
+SELECT_CASES = [
+    ("toy", None, 8, 5, 4),
+    ("dna ragged s=2", 4, 12, 6, 2),
+    ("dna s=1 every key", 4, 9, 4, 1),
+    ("protein s=2", 20, 9, 2, 2),
+]
+
+
+def _select_inputs(name, A, l, k):
+    if name == "toy":
+        seqs = [r[0] for r in read_golden("fig1_sequences.txt")]
+        return 4, seqs, np.array([0b1100111], dtype=np.uint32)
+    rng = np.random.default_rng(abs(hash(name)) % 2**32)
+    seqs = random_sequences(rng, 7, [90, 130, 61, 200, 45, 77, 150], "dna" if A == 4 else "protein")
+    return A, seqs, projection_masks(rng, l, k, 6)
+
+
+@pytest.mark.parametrize("case", SELECT_CASES, ids=[c[0] for c in SELECT_CASES])
+def test_select_profile_theta0_bit_exact(case):
+    name, A, l, k, s = case
+    A, seqs, masks = _select_inputs(name, A, l, k)
+    ref = oracle.Seqs(A, seqs)
+    RK, RN = oracle.hash_trials(ref, l, k, masks)
+    rbk, rmem, (rnb, rnm), _ = oracle.select(ref, l, k, RK, RN, s)
+    say("select", name)
+    S = pm.Seqs(A, seqs)
+    bk, mem, nout, (nb_, nm_), st, cap_b, cap_m = _select_gpu(S, l, k, s, RK, RN)
+    assert st == 0 and (nb_, nm_) == (rnb, rnm)
+    assert np.array_equal(u32(bk)[:nb_], rbk)
+    assert np.array_equal(u32(mem)[:nm_], rmem)
+    # a6: profiles and theta0
+    A_ = S.alphabet
+    prof = torch.zeros((max(cap_b, 1), A_, l), dtype=torch.int32, device="cuda")
+    pm.bucket_profile(S, l, bk, mem, cap_m, cap_b, nout, prof)
+    rprof = oracle.profile(ref, l, rbk, rmem)
+    bg = _bg(A_, np.random.default_rng(1))
+    dbg = torch.from_numpy(bg).cuda()
+    th0 = torch.zeros((max(cap_b, 1), A_, l), dtype=torch.float64, device="cuda")
+    for beta in (0.0, 1.0, 2.5):
+        pm.theta_init(A_, l, prof, cap_b, nout, dbg, beta, th0)
+        torch.cuda.synchronize()
+        assert np.array_equal(u32(prof)[:nb_], rprof)
+        np.testing.assert_allclose(th0.cpu().numpy()[:nb_], oracle.theta0(rprof, bg, beta), rtol=1e-15, atol=0)
+
+
+def test_select_truncates_to_capacity_and_reports():
+    A, seqs, masks = _select_inputs("dna ragged s=2", 4, 12, 6)
+    ref = oracle.Seqs(A, seqs)
+    RK, RN = oracle.hash_trials(ref, 12, 6, masks)
+    rbk, rmem, (rnb, rnm), _ = oracle.select(ref, 12, 6, RK, RN, 2)
+    assert rnb > 5 and rnm > 11
+    say("select truncated")
+    S = pm.Seqs(A, seqs)
+    bk, mem, nout, (nb_, nm_), st, _, _ = _select_gpu(S, 12, 6, 2, RK, RN, cap_b=5, cap_m=11)
+    assert st & pm.PM_STATUS_CAPACITY and (nb_, nm_) == (rnb, rnm)
+    assert np.array_equal(u32(bk)[:5], rbk[:5])
+    got = u32(mem)[:11]
+    # members of the buckets that were kept, up to the member capacity
+    keep = rmem[:11]
+    written = [i for i in range(11) if any(b[3] <= i < b[3] + b[2] for b in rbk[:5])]
+    assert np.array_equal(got[written], keep[written])
+
+
+# ------------------------------------------------------------------ a7 - a10
+def _em_case(seed, A, t, n, l, d, nb):
+    rng = np.random.default_rng(seed)
+    inst = planted_instance(rng, t, n, l, d, "dna" if A == 4 else "protein",
+                            dirichlet_alpha=2.0 if A == 20 else None)
+    ref = oracle.Seqs(A, inst.seqs)
+    bg = oracle.bg_vector(A, inst.bg)
+    # models: random profiles plus one seeded at the planted sites
+    th0 = np.stack([rng.dirichlet(np.ones(A) * 0.7, size=l).T for _ in range(nb)])
+    th0 = 0.8 * th0 + 0.2 * bg[None, :, None]
+    planted = np.zeros((A, l))
+    L = oracle.letters(A)
+    for x, a in zip(inst.seqs, inst.starts):
+        for p in range(l):
+            planted[L.index(x[a + p]), p] += 1
+    th0[0] = (planted + bg[:, None]) / (t + 1)
+    return inst, ref, bg, np.ascontiguousarray(th0)
+
+
+def _em_gpu(S, l, th0, bg, iters, beta, precision):
+    B = th0.shape[0]
+    A = S.alphabet
+    d_th0 = torch.from_numpy(th0).cuda()
+    d_bg = torch.from_numpy(bg).cuda()
+    th = torch.zeros_like(d_th0)
+    J = torch.zeros((B, iters + 1), dtype=torch.float64, device="cuda")
+    LL = torch.zeros_like(J)
+    sites = torch.zeros((B, S.t), dtype=torch.int32, device="cuda")
+    pm.em_refine(S, l, d_th0, d_bg, B, None, iters, beta, precision, th, J, LL, sites)
+    best = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cons = torch.zeros(l + 1, dtype=torch.uint8, device="cuda")
+    pm.em_best(J, B, None, iters, th, A, l, best, cons)
+    torch.cuda.synchronize()
+    return (th.cpu().numpy(), J.cpu().numpy(), LL.cpu().numpy(), sites.cpu().numpy(),
+            int(best.item()), bytes(cons.cpu().numpy()[:l]).decode())
+
+
+EM_CASES = [
+    # name, seed, A, t, n, l, d, B, iters, beta
+    ("dna small", 1, 4, 6, 90, 10, 2, 9, 5, 1.0),
+    ("dna c1 shape", 2, 4, 20, 600, 15, 4, 6, 5, 1.0),
+    ("dna ragged beta 0.3", 3, 4, 11, None, 13, 3, 5, 7, 0.3),
+    ("protein", 4, 20, 8, 150, 12, 3, 4, 4, 1.0),
+    ("dna l=32", 5, 4, 5, 120, 32, 6, 3, 3, 2.0),
+]
+
+
+@pytest.mark.parametrize("prec", [pm.PM_FP64, pm.PM_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", EM_CASES, ids=[c[0] for c in EM_CASES])
+def test_em_matches_oracle(case, prec):
+    name, seed, A, t, n, l, d, B, iters, beta = case
+    if n is None:
+        rng = np.random.default_rng(seed)
+        inst = planted_instance(rng, t, list(rng.integers(l + 3, 400, size=t)), l, d)
+        ref = oracle.Seqs(A, inst.seqs)
+        bg = np.full(4, 0.25)
+        th0 = np.ascontiguousarray(np.stack([0.7 * rng.dirichlet(np.ones(4), size=l).T + 0.075
+                                              for _ in range(B)]))
+    else:
+        inst, ref, bg, th0 = _em_case(seed, A, t, n, l, d, B)
+    rth, rJ, rLL, rsites = oracle.em(ref, l, th0, bg, iters, beta)
+    rbest, rcons = oracle.best(rJ, rth)
+    say("em", name, "fp64" if prec == pm.PM_FP64 else "fp32")
+    S = pm.Seqs(A, inst.seqs)
+    th, J, LL, sites, best, cons = _em_gpu(S, l, th0, bg, iters, beta, prec)
+    tol = 1e-12 if prec == pm.PM_FP64 else 1e-5
+    np.testing.assert_allclose(J, rJ, rtol=tol, atol=tol * np.abs(rJ).max())
+    np.testing.assert_allclose(LL, rLL, rtol=tol, atol=tol * np.abs(rLL).max())
+    np.testing.assert_allclose(th, rth, rtol=0, atol=1e-12 if prec == pm.PM_FP64 else 2e-5)
+    assert np.all(np.diff(J, axis=1) >= -tol * np.abs(J).max())
+    assert best == rbest and cons == rcons
+    if prec == pm.PM_FP64:
+        assert np.array_equal(sites, rsites)
+    else:
+        # a different start may only win where the oracle's scores nearly tie
+        _, s_ref, _, _ = oracle.estep(ref, l, rth[0], bg)
+        assert np.mean(sites == rsites) > 0.95
+
+
+def test_em_theta_equal_background_gives_zero():
+    rng = np.random.default_rng(11)
+    seqs = random_sequences(rng, 5, 60, "dna")
+    bg = np.array([0.1, 0.2, 0.3, 0.4])
+    th0 = np.repeat(bg[None, :, None], 8, axis=2).repeat(2, axis=0)
+    say("em theta = bg")
+    S = pm.Seqs(4, seqs)
+    for prec in (pm.PM_FP64, pm.PM_FP32):
+        th, J, LL, sites, best, cons = _em_gpu(S, 8, np.ascontiguousarray(th0), bg, 2, 0.0, prec)
+        assert np.all(LL[:, 0] == 0.0)
+
+
+# ------------------------------------------------------------------ end to end
+def test_projection_run_fig1_toy():
+    """Example 1: PROJECTION + EM on Fig. 1 returns ATGCAACT at Fig. 2's sites."""
+    seqs = [r[0] for r in read_golden("fig1_sequences.txt")]
+    say("projection_run toy")
+    r = pm.projection_run(seqs, 4, 8, k=5, s=4, masks=np.array([0b1100111]), em_iters=5,
+                          beta=1.0, bg=np.full(4, 0.25))
+    assert r["consensus"] == "ATGCAACT"
+    assert list(r["sites"]) == [7, 18, 2, 4, 30, 26, 14]
+    assert r["n_enriched"] == 2
+
+
+def _pipeline(inst, masks, cfg, precision, cap_factor=1):
+    A = 4 if cfg["alphabet"] == "dna" else 20
+    ref = oracle.Seqs(A, inst.seqs)
+    bg = oracle.bg_vector(A, inst.bg)
+    S = pm.Seqs(A, inst.seqs)
+    l, k, s, iters = cfg["l"], cfg["k"], cfg["s"], cfg["iters"]
+    # size the lists with one counting pass
+    P0 = pm.Pipeline(S, l, k, s, masks, iters, 1.0, precision, bg, cap_b=0, cap_m=0)
+    P0.hash()
+    P0.select()
+    torch.cuda.synchronize()
+    nb_, nm_ = [int(v) for v in P0.b.n_out.cpu()]
+    del P0
+    P = pm.Pipeline(S, l, k, s, masks, iters, 1.0, precision, bg, cap_b=nb_, cap_m=nm_)
+    return A, ref, bg, S, P
+
+
+def test_c1_full_pipeline_against_oracle():
+    """The (15,4) plain workload at full size: every output against the oracle."""
+    inst, masks = make_config("c1", seed=1)
+    cfg = inst.meta
+    A, ref, bg, S, P = _pipeline(inst, masks, cfg, pm.PM_FP64)
+    say("c1 full pipeline")
+    P.run()
+    res = P.result()
+    r = oracle.run(inst.seqs, A, cfg["l"], cfg["k"], cfg["s"], masks, cfg["iters"], 1.0, bg=bg)
+    assert res["status"] == 0
+    assert (res["n_buckets"], res["n_members"]) == (len(r["buckets"]), len(r["members"]))
+    assert np.array_equal(u32(P.b.keys), r["keys"]) and np.array_equal(u32(P.b.counts), r["counts"])
+    assert np.array_equal(u32(P.b.buckets), r["buckets"]) and np.array_equal(u32(P.b.members), r["members"])
+    np.testing.assert_allclose(P.b.J.cpu().numpy(), r["J"], rtol=1e-12, atol=1e-10)
+    assert res["best"] == r["best"] and res["consensus"] == r["consensus"]
+    assert np.array_equal(res["sites"], r["sites"][r["best"]])
+
+
+def test_c2_full_size_sampled_against_oracle():
+    """The (18,6) workload at full size (m = 5000) in the launch configuration
+    the benchmark times: keys/counts and buckets of sampled trials bit-exact,
+    FP32 EM of sampled buckets within 1e-5 of the FP64 oracle, and the
+    invariants on every trial."""
+    inst, masks = make_config("c2", seed=1)
+    cfg = inst.meta
+    A, ref, bg, S, P = _pipeline(inst, masks, cfg, pm.PM_FP32)
+    say("c2 full size", P.m, "trials", P.b.cap_b, "buckets")
+    P.run()
+    torch.cuda.synchronize()
+    res = P.result()
+    assert res["status"] == 0
+    x = S.nwin(cfg["l"])
+    assert torch.all(P.b.counts.sum(dim=1) == x).item()
+    rng = np.random.default_rng(5)
+    trials = np.sort(rng.choice(P.m, size=12, replace=False))
+    RK, RN = oracle.hash_trials(ref, cfg["l"], cfg["k"], masks[trials])
+    assert np.array_equal(u32(P.b.keys[trials]), RK)
+    assert np.array_equal(u32(P.b.counts[trials]), RN)
+    bk = u32(P.b.buckets)
+    mem = u32(P.b.members)
+    for i, j in enumerate(trials):
+        rbk, rmem, _, _ = oracle.select(ref, cfg["l"], cfg["k"], RK[i:i + 1], RN[i:i + 1], cfg["s"])
+        mine = bk[bk[:, 0] == j]
+        assert np.array_equal(mine[:, 1:3], rbk[:, 1:3])
+        for a, b in zip(mine, rbk):
+            assert np.array_equal(mem[a[3]:a[3] + a[2]], rmem[b[3]:b[3] + b[2]])
+    # EM on a sample of buckets, FP32 against the FP64 oracle
+    sel = np.sort(rng.choice(len(bk), size=24, replace=False))
+    th0 = P.b.theta0.cpu().numpy()[sel]
+    rprof = oracle.profile(ref, cfg["l"], bk[sel], mem)
+    np.testing.assert_allclose(th0, oracle.theta0(rprof, bg, 1.0), rtol=1e-15)
+    rth, rJ, rLL, rsites = oracle.em(ref, cfg["l"], th0, bg, cfg["iters"], 1.0)
+    np.testing.assert_allclose(P.b.J.cpu().numpy()[sel], rJ, rtol=1e-5, atol=1e-5 * np.abs(rJ).max())
+    J = P.b.J.cpu().numpy()[: len(bk)]
+    assert np.all(np.diff(J, axis=1) >= -1e-5 * np.abs(J).max())

@@ -399,8 +399,10 @@ def test_auto_params_rules():
     assert m == math.ceil(math.log(0.05) / math.log(B))
     assert 1 - B ** m >= 0.95 > 1 - B ** (m - 1)
     # a mean bucket size above 1.5 makes twice the mean the threshold
-    k, s, m = oracle.auto_params(8, 2, 20, 20 * 593, 4)
-    assert k == 5 and s == math.ceil(2 * 20 * 593 / 4 ** 5)
+    k, s, m = oracle.auto_params(8, 1, 20, 20 * 593, 4)
+    assert k == 6 and s == math.ceil(2 * 20 * 593 / 4 ** 6) == 6
+    with pytest.raises(ValueError):
+        oracle.auto_params(8, 2, 20, 20 * 593, 4)
 
 
 def test_parkmiller_published_check_value():
