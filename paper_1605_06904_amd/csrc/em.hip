@@ -90,10 +90,11 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
     if (nvalid > a.B) nvalid = a.B;
     if (b >= nvalid) return;
 
-    __shared__ T th[A * 32];
+    __shared__ double th[A * 32];
     __shared__ T Wt[A * 32];
     __shared__ T acc[kEmWaves][A * 32];
     __shared__ double red[kEmWaves];
+    __shared__ double colsum[32];
     extern __shared__ __align__(16) uint32_t dyn[];
     uint32_t *seq = dyn;
     int64_t *offs = reinterpret_cast<int64_t *>(dyn + ((a.seq_words + 1) & ~1));
@@ -102,7 +103,7 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
     const int l = a.l, t = a.t, AL = A * l;
     const double beta = a.beta;
 
-    for (int i = tid; i < AL; i += kEmThreads) th[i] = (T)a.theta0[b * AL + i];
+    for (int i = tid; i < AL; i += kEmThreads) th[i] = a.theta0[b * AL + i];
     for (int i = tid; i < a.seq_words; i += kEmThreads) seq[i] = a.packed[i];
     if (a.stage_off)
         for (int i = tid; i <= t; i += kEmThreads) offs[i] = a.offsets[i];
@@ -115,9 +116,9 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
         double pr = 0;
         for (int i = tid; i < AL; i += kEmThreads) {
             const int c = i / l;
-            const T v = th[i];
-            Wt[i] = (T)(log((double)v) - log(a.bg[c]));
-            if (beta != 0) pr += a.bg[c] * log((double)v);
+            const double v = th[i];
+            Wt[i] = (T)(log(v) - log(a.bg[c]));
+            if (beta != 0) pr += a.bg[c] * log(v);
         }
         for (int i = tid; i < kEmWaves * A * 32; i += kEmThreads) (&acc[0][0])[i] = 0;
         pr = block_sum(pr, red);  // includes the barrier that publishes Wt
@@ -175,17 +176,28 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
             if (a.llr) a.llr[b * (a.iters + 1) + it] = llr;
         }
         if (!last) {
+            // counts of the four waves, summed in FP64
             for (int i = tid; i < AL; i += kEmThreads) {
-                const int c = i / l;
-                T cs = 0;
+                double cs = 0;
 #pragma unroll
-                for (int w = 0; w < kEmWaves; ++w) cs += acc[w][i];
-                th[i] = (T)(((double)cs + beta * a.bg[c]) / ((double)t + beta));
+                for (int w = 0; w < kEmWaves; ++w) cs += (double)acc[w][i];
+                th[i] = cs;
             }
+            __syncthreads();
+            // theta' = (counts + beta*bg) / (t + beta); every column's counts sum
+            // to t, so dividing by the column's own total is the same update and
+            // keeps each column exactly on the simplex under rounding
+            for (int p = tid; p < l; p += kEmThreads) {
+                double tot = 0;
+                for (int c = 0; c < A; ++c) tot += th[c * l + p];
+                colsum[p] = tot + beta;
+            }
+            __syncthreads();
+            for (int i = tid; i < AL; i += kEmThreads) th[i] = (th[i] + beta * a.bg[i / l]) / colsum[i % l];
             __syncthreads();
         }
     }
-    for (int i = tid; i < AL; i += kEmThreads) a.theta_out[b * AL + i] = (double)th[i];
+    for (int i = tid; i < AL; i += kEmThreads) a.theta_out[b * AL + i] = th[i];
 }
 
 template <typename T, int A>

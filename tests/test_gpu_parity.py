@@ -7,6 +7,7 @@ Inputs are seeded and synthetic.  Every case prints its name before it touches
 the GPU.
 """
 import sys
+import zlib
 
 import numpy as np
 import pytest
@@ -110,7 +111,7 @@ HASH_CASES = [
 @pytest.mark.parametrize("case", HASH_CASES, ids=[c[0] for c in HASH_CASES])
 def test_hash_bit_exact(case):
     name, A, t, lens, l, k, m = case
-    rng = np.random.default_rng(abs(hash(name)) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
     seqs = random_sequences(rng, t, lens, "dna" if A == 4 else "protein")
     masks = projection_masks(rng, l, k, m)
     say("hash", name)
@@ -198,7 +199,7 @@ def _select_inputs(name, A, l, k):
     if name == "toy":
         seqs = [r[0] for r in read_golden("fig1_sequences.txt")]
         return 4, seqs, np.array([0b1100111], dtype=np.uint32)
-    rng = np.random.default_rng(abs(hash(name)) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
     seqs = random_sequences(rng, 7, [90, 130, 61, 200, 45, 77, 150], "dna" if A == 4 else "protein")
     return A, seqs, projection_masks(rng, l, k, 6)
 
@@ -286,6 +287,24 @@ def _em_gpu(S, l, th0, bg, iters, beta, precision):
             int(best.item()), bytes(cons.cpu().numpy()[:l]).decode())
 
 
+def _same_best(got, ref, rJ, tol):
+    """The winning model: the oracle's, or one whose final J ties it within the
+    tolerance (several buckets often converge to the same motif)."""
+    if got != ref:
+        assert abs(rJ[got, -1] - rJ[ref, -1]) <= tol * max(1.0, abs(rJ[ref, -1])), (got, ref)
+
+
+def _same_consensus(got, ref, theta_ref, A, tol):
+    """Identical consensus, except that a column whose two largest oracle
+    probabilities lie within the tolerance of the arithmetic counts as a tie
+    (Sec. 2 lets ties go either way)."""
+    L = oracle.letters(A)
+    assert len(got) == len(ref)
+    for p, (g, r) in enumerate(zip(got, ref)):
+        if g != r:
+            assert abs(theta_ref[L.index(g), p] - theta_ref[L.index(r), p]) <= tol, (p, g, r)
+
+
 EM_CASES = [
     # name, seed, A, t, n, l, d, B, iters, beta
     ("dna small", 1, 4, 6, 90, 10, 2, 9, 5, 1.0),
@@ -319,7 +338,9 @@ def test_em_matches_oracle(case, prec):
     np.testing.assert_allclose(LL, rLL, rtol=tol, atol=tol * np.abs(rLL).max())
     np.testing.assert_allclose(th, rth, rtol=0, atol=1e-12 if prec == pm.PM_FP64 else 2e-5)
     assert np.all(np.diff(J, axis=1) >= -tol * np.abs(J).max())
-    assert best == rbest and cons == rcons
+    _same_best(best, rbest, rJ, tol)
+    _same_consensus(cons, oracle.best(rJ[best:best + 1], rth[best:best + 1])[1], rth[best], A,
+                    1e-12 if prec == pm.PM_FP64 else 2e-5)
     if prec == pm.PM_FP64:
         assert np.array_equal(sites, rsites)
     else:
@@ -383,8 +404,11 @@ def test_c1_full_pipeline_against_oracle():
     assert np.array_equal(u32(P.b.keys), r["keys"]) and np.array_equal(u32(P.b.counts), r["counts"])
     assert np.array_equal(u32(P.b.buckets), r["buckets"]) and np.array_equal(u32(P.b.members), r["members"])
     np.testing.assert_allclose(P.b.J.cpu().numpy(), r["J"], rtol=1e-12, atol=1e-10)
-    assert res["best"] == r["best"] and res["consensus"] == r["consensus"]
-    assert np.array_equal(res["sites"], r["sites"][r["best"]])
+    _same_best(res["best"], r["best"], r["J"], 1e-12)
+    b = res["best"]
+    _same_consensus(res["consensus"], oracle.best(r["J"][b:b + 1], r["theta"][b:b + 1])[1],
+                    r["theta"][b], A, 1e-12)
+    assert np.array_equal(res["sites"], r["sites"][b])
 
 
 def test_c2_full_size_sampled_against_oracle():
