@@ -51,6 +51,7 @@ def main():
     from synth import make_config
 
     torch.cuda.set_device(0)
+    PREC = pm.PM_F16X2
     inst, masks = make_config("c2", seed=args.seed)
     cfg = inst.meta
     A, l, k, s, m, iters = 4, cfg["l"], cfg["k"], cfg["s"], cfg["m"], cfg["iters"]
@@ -60,14 +61,14 @@ def main():
     x = S.nwin(l)
 
     # size the bucket lists once (untimed), then allocate the pass buffers
-    P0 = pm.Pipeline(S, l, k, s, masks, iters, beta, pm.PM_FP32, bg, cap_b=0, cap_m=0)
+    P0 = pm.Pipeline(S, l, k, s, masks, iters, beta, PREC, bg, cap_b=0, cap_m=0)
     P0.hash()
     P0.select()
     torch.cuda.synchronize()
     nbk, nmem = [int(v) for v in P0.b.n_out.cpu()]
     del P0
     torch.cuda.empty_cache()
-    P = pm.Pipeline(S, l, k, s, masks, iters, beta, pm.PM_FP32, bg, cap_b=nbk, cap_m=nmem)
+    P = pm.Pipeline(S, l, k, s, masks, iters, beta, PREC, bg, cap_b=nbk, cap_m=nmem)
 
     for _ in range(args.warmup):
         P.run()

@@ -55,8 +55,11 @@ extern "C" {
 #define PM_PROTEIN 20
 
 /* EM arithmetic (em_refine `precision`) */
-#define PM_FP64 0 /* every step in FP64 */
-#define PM_FP32 1 /* scores, posteriors and counts in FP32; log-sum-exp and J in FP64 */
+#define PM_FP64 0  /* every step in FP64 */
+#define PM_FP32 1  /* scores, posteriors and counts in FP32; log-sum-exp and J in FP64 */
+#define PM_F16X2 2 /* DNA only: E- and M-step on FP16 matrix cores with every non-0/1
+                      operand split into two FP16 halves (about 22 significant bits,
+                      exact products, FP32 sums); log-sum-exp and J in FP64 */
 
 /* Encoded sequences.  Host fields describe the device arrays. */
 typedef struct pm_seqs {
@@ -171,7 +174,7 @@ int theta_init(int32_t alphabet, int32_t l, const uint32_t *profile, int64_t B,
  *   llr_out    device [B][iters+1] or NULL
  *   sites_out  device [B][t] int32 or NULL: argmax_a s_ia under theta^iters,
  *              first on ties
- *   precision  PM_FP64 or PM_FP32 */
+ *   precision  PM_FP64, PM_FP32 or PM_F16X2 (DNA) */
 int em_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
               const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
               double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *stream);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libprojmotif.so")
 PM_OK, PM_EINVAL, PM_ERANGE, PM_ECAPACITY, PM_EDEVICE = 0, -1, -2, -3, -4
 PM_STATUS_BAD_SYMBOL, PM_STATUS_BAD_MASK, PM_STATUS_CAPACITY = 1, 2, 4
 PM_DNA, PM_PROTEIN = 4, 20
-PM_FP64, PM_FP32 = 0, 1
+PM_FP64, PM_FP32, PM_F16X2 = 0, 1, 2
 
 DNA_CODE_ORDER = "ACTG"
 PROTEIN_CODE_ORDER = "ARNDCQEGHILKMFPSTWYV"

@@ -284,7 +284,9 @@ extern "C" int em_refine(const pm_seqs *S, int32_t l, const double *theta0, cons
     int rc = check_seqs(S, l);
     if (rc) return rc;
     if (B < 0 || iters < 0 || beta < 0) return fail(PM_EINVAL, "need B >= 0, iters >= 0, beta >= 0");
-    if (precision != PM_FP64 && precision != PM_FP32) return fail(PM_EINVAL, "unknown precision %d", precision);
+    if (precision != PM_FP64 && precision != PM_FP32 && precision != PM_F16X2)
+        return fail(PM_EINVAL, "unknown precision %d", precision);
+    if (precision == PM_F16X2 && S->alphabet != 4) return fail(PM_EINVAL, "PM_F16X2 is for DNA");
     if (B == 0) return PM_OK;
     if (B > 0x7fffffff) return fail(PM_ERANGE, "B above 2^31 - 1");
     if (!theta0 || !bg || !theta_out || !J_out) return fail(PM_EINVAL, "NULL buffer");
@@ -303,6 +305,9 @@ extern "C" int em_refine(const pm_seqs *S, int32_t l, const double *theta0, cons
     a.l = l;
     a.iters = iters;
     a.beta = beta;
+    if (precision == PM_F16X2)
+        return em_refine_mfma(S, l, theta0, bg, B, n_dev, iters, beta, theta_out, J_out, llr_out, sites_out,
+                              as_stream(stream));
     const int64_t nw = pm_packed_words(S->alphabet, S->n_total);
     a.seq_words = nw * 4 <= 48 * 1024 ? (int)nw : 0;
     a.stage_off = (S->t + 1) * 8 <= 8 * 1024;

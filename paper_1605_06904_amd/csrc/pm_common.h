@@ -43,6 +43,10 @@ static inline int64_t num_windows(const pm_seqs *S, int l)
 
 int check_seqs(const pm_seqs *S, int l);
 
+int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
+                   const int64_t *n_dev, int32_t iters, double beta, double *theta_out, double *J_out,
+                   double *llr_out, int32_t *sites_out, hipStream_t st);
+
 // ---------------------------------------------------------------- device side
 constexpr int kWave = 64;
 

@@ -315,10 +315,32 @@ EM_CASES = [
 ]
 
 
-@pytest.mark.parametrize("prec", [pm.PM_FP64, pm.PM_FP32], ids=["fp64", "fp32"])
+PREC_NAMES = {pm.PM_FP64: "fp64", pm.PM_FP32: "fp32", pm.PM_F16X2: "f16x2"}
+
+
+def _sites_valid(sites, rsites, rth, ref, l, bg, tol):
+    """Sites equal the oracle's, except where the oracle's best score and the
+    score at the chosen start tie within the tolerance."""
+    if np.array_equal(sites, rsites):
+        return
+    L = ref.lens - l + 1
+    cum = np.concatenate([[0], np.cumsum(L)])
+    for b in range(len(sites)):
+        if np.array_equal(sites[b], rsites[b]):
+            continue
+        _, s, _, _ = oracle.estep(ref, l, rth[b], bg)
+        for i in range(len(L)):
+            seg = s[cum[i]:cum[i + 1]]
+            assert 0 <= sites[b, i] < L[i]
+            assert seg.max() - seg[sites[b, i]] <= tol * max(1.0, abs(seg.max())), (b, i)
+
+
+@pytest.mark.parametrize("prec", [pm.PM_FP64, pm.PM_FP32, pm.PM_F16X2], ids=["fp64", "fp32", "f16x2"])
 @pytest.mark.parametrize("case", EM_CASES, ids=[c[0] for c in EM_CASES])
 def test_em_matches_oracle(case, prec):
     name, seed, A, t, n, l, d, B, iters, beta = case
+    if prec == pm.PM_F16X2 and A != 4:
+        pytest.skip("the split-FP16 matrix-core path is for DNA")
     if n is None:
         rng = np.random.default_rng(seed)
         inst = planted_instance(rng, t, list(rng.integers(l + 3, 400, size=t)), l, d)
@@ -330,23 +352,21 @@ def test_em_matches_oracle(case, prec):
         inst, ref, bg, th0 = _em_case(seed, A, t, n, l, d, B)
     rth, rJ, rLL, rsites = oracle.em(ref, l, th0, bg, iters, beta)
     rbest, rcons = oracle.best(rJ, rth)
-    say("em", name, "fp64" if prec == pm.PM_FP64 else "fp32")
+    say("em", name, PREC_NAMES[prec])
     S = pm.Seqs(A, inst.seqs)
     th, J, LL, sites, best, cons = _em_gpu(S, l, th0, bg, iters, beta, prec)
     tol = 1e-12 if prec == pm.PM_FP64 else 1e-5
+    th_tol = 1e-12 if prec == pm.PM_FP64 else 2e-5
     np.testing.assert_allclose(J, rJ, rtol=tol, atol=tol * np.abs(rJ).max())
     np.testing.assert_allclose(LL, rLL, rtol=tol, atol=tol * np.abs(rLL).max())
-    np.testing.assert_allclose(th, rth, rtol=0, atol=1e-12 if prec == pm.PM_FP64 else 2e-5)
+    np.testing.assert_allclose(th, rth, rtol=0, atol=th_tol)
     assert np.all(np.diff(J, axis=1) >= -tol * np.abs(J).max())
     _same_best(best, rbest, rJ, tol)
-    _same_consensus(cons, oracle.best(rJ[best:best + 1], rth[best:best + 1])[1], rth[best], A,
-                    1e-12 if prec == pm.PM_FP64 else 2e-5)
+    _same_consensus(cons, oracle.best(rJ[best:best + 1], rth[best:best + 1])[1], rth[best], A, th_tol)
     if prec == pm.PM_FP64:
         assert np.array_equal(sites, rsites)
     else:
-        # a different start may only win where the oracle's scores nearly tie
-        _, s_ref, _, _ = oracle.estep(ref, l, rth[0], bg)
-        assert np.mean(sites == rsites) > 0.95
+        _sites_valid(sites, rsites, rth, ref, l, bg, 1e-5)
 
 
 def test_em_theta_equal_background_gives_zero():
@@ -356,9 +376,9 @@ def test_em_theta_equal_background_gives_zero():
     th0 = np.repeat(bg[None, :, None], 8, axis=2).repeat(2, axis=0)
     say("em theta = bg")
     S = pm.Seqs(4, seqs)
-    for prec in (pm.PM_FP64, pm.PM_FP32):
+    for prec in (pm.PM_FP64, pm.PM_FP32, pm.PM_F16X2):
         th, J, LL, sites, best, cons = _em_gpu(S, 8, np.ascontiguousarray(th0), bg, 2, 0.0, prec)
-        assert np.all(LL[:, 0] == 0.0)
+        assert np.all(np.abs(LL[:, 0]) <= (0.0 if prec != pm.PM_F16X2 else 1e-9))
 
 
 # ------------------------------------------------------------------ end to end
@@ -418,7 +438,7 @@ def test_c2_full_size_sampled_against_oracle():
     invariants on every trial."""
     inst, masks = make_config("c2", seed=1)
     cfg = inst.meta
-    A, ref, bg, S, P = _pipeline(inst, masks, cfg, pm.PM_FP32)
+    A, ref, bg, S, P = _pipeline(inst, masks, cfg, pm.PM_F16X2)
     say("c2 full size", P.m, "trials", P.b.cap_b, "buckets")
     P.run()
     torch.cuda.synchronize()
