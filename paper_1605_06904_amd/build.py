@@ -25,6 +25,8 @@ FLAGS = [
     "-Wno-unused-function",
     # never let the compiler form packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary VGPRs (no AGPR round trips)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
 ]
 
 

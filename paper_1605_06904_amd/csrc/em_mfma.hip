@@ -5,14 +5,14 @@
 // models' log-odds (4l x 16):  S = OneHot . W.  The M-step counts are the
 // transposed product with the posteriors:  C = OneHot^T . P.  Per sequence
 // the posteriors are a softmax over windows, so one pass over a sequence is
-// an attention-like sweep with a running maximum and rescaled accumulators.
+// an attention-like sweep with a reference maximum and rescaled accumulators.
 //
 // Arithmetic: v_mfma_f32_16x16x32_f16.  The one-hot side is exact in FP16.
 // The other side is split in two FP16 halves, x = hi + lo with
-// hi = fp16(x) and lo = fp16(x - hi), and both halves accumulate into the
-// same FP32 accumulator, so every product is exact and the operand carries
-// about 22 significant bits; sums are FP32.  Scores are kept in log2 units
-// (W scaled by log2 e) so the softmax uses the hardware exp2; the per-sequence
+// hi = fp16(x) and lo = fp16(x - hi), both multiplied by the same one-hot
+// operand, so every product is exact and the operand carries about 22
+// significant bits; sums are FP32.  Scores are kept in log2 units (W scaled
+// by log2 e) so the softmax uses the hardware exp2; the per-sequence
 // log-sum-exp and the objective are formed in FP64.
 //
 // Lane layout of one 16x16x32 MFMA (lane L, r = L % 16, g = L / 16):
@@ -25,13 +25,26 @@
 // models, contraction = 32 windows (two E tiles); lane (r, g) carries windows
 // 4g..4g+3 of the first tile and of the second, exactly the rows its E-step
 // outputs hold, so posteriors feed the M-step without leaving registers.
+//
+// Softmax reference: scores leave the E-step already shifted by the current
+// reference (the accumulator starts at -reference), and the reference moves
+// only when a score passes it by more than kSlack, so the common path needs
+// neither a cross-lane maximum nor a rescale.  Posteriors enter the M-step as
+// 2^(S - ref + kPOff) <= 2^(kPOff + kSlack) = 2^15, inside the FP16 range.
+//
+// Work split: a workgroup of four waves takes 64 models (16 per wave) of one
+// instance; the four waves sweep the same windows in step and build the
+// one-hot tables of each window pair together in LDS (double-buffered, one
+// barrier per pair) from the packed instance staged in LDS.
 #include <math.h>
+#include <stdlib.h>
 
 #include "pm_common.h"
 
 namespace pm {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
 struct EmMfmaArgs {
@@ -47,11 +60,14 @@ struct EmMfmaArgs {
     int64_t B;
     int64_t nwords;  // packed words (reads are clamped below this)
     int t, l, iters;
+    int stage_words; // packed words staged in LDS, 0 = read from global memory
     double beta;
 };
 
+constexpr int kWaves = 4;  // waves (groups of 16 models) per workgroup
 constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kPScale = 11.0f;  // posteriors are scaled by 2^11 before the split
+constexpr float kPOff = 3.0f;
+constexpr float kSlack = 12.0f;
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -60,299 +76,354 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint32_t ld_clamped(const uint32_t *w, int64_t i, int64_t nw)
-{
-    return w[i < nw ? i : nw - 1];
-}
-
-// 16 DNA symbols starting at P (MSB-first), reads clamped to the buffer
-__device__ __forceinline__ uint32_t dna16(const uint32_t *w, int64_t P, int64_t nw)
+// 32 DNA symbols starting at P (MSB-first) as hi (P..P+15) and lo (P+16..P+31).
+// CLAMP: reads clamped below nw (global memory); otherwise the buffer is padded.
+template <bool CLAMP>
+__device__ __forceinline__ void dna32(const uint32_t *w, int64_t P, int64_t nw, uint32_t &hi, uint32_t &lo)
 {
     const int64_t wi = P >> 4;
     const uint32_t r = (uint32_t)(P & 15) << 1;
-    const uint64_t v = ((uint64_t)ld_clamped(w, wi, nw) << 32) | ld_clamped(w, wi + 1, nw);
-    return (uint32_t)(v >> (32 - r));
+    uint32_t w0, w1, w2;
+    if (CLAMP) {
+        w0 = w[wi < nw ? wi : nw - 1];
+        w1 = w[wi + 1 < nw ? wi + 1 : nw - 1];
+        w2 = w[wi + 2 < nw ? wi + 2 : nw - 1];
+    } else {
+        w0 = w[wi];
+        w1 = w[wi + 1];
+        w2 = w[wi + 2];
+    }
+    hi = (uint32_t)((((uint64_t)w0 << 32) | w1) >> (32 - r));
+    lo = (uint32_t)((((uint64_t)w1 << 32) | w2) >> (32 - r));
 }
 
-// two FP16 halves (1.0 where letter == c) for letter codes a (low half) and b
+// words of zero padding after a staged copy of the packed instance: table
+// builds read up to 95 symbols past the last window start
+constexpr int kStagePad = 8;
+
+// two FP16 halves: 1.0 where letter a == c (low half), where b == c (high half)
 __device__ __forceinline__ uint32_t onehot_pair(uint32_t a, uint32_t b, uint32_t c)
 {
     return (a == c ? 0x3C00u : 0u) | (b == c ? 0x3C000000u : 0u);
 }
 
-__device__ __forceinline__ uint32_t pack_h2(_Float16 x, _Float16 y)
+// fp16(p - hi) for two values whose fp16 roundings are packed in hi2
+__device__ __forceinline__ uint32_t split_lo(uint32_t hi2, float p0, float p1)
 {
-    return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
+    uint32_t r;
+    asm volatile(
+        "v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixhi_f16 %0, %1, -1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+        : "=&v"(r)
+        : "v"(hi2), "v"(p0), "v"(p1));
+    return r;
 }
 
-template <int LB, int NG>
-__global__ void __launch_bounds__(64) k_em_mfma(const EmMfmaArgs a)
+__device__ __forceinline__ uint32_t pack_hi(float p0, float p1)
 {
-    constexpr int MTX = 2 * LB;  // M-tiles of 4 positions each, at most
-    constexpr int PX = 8 * LB;   // positions covered by the E-step k-blocks
-    __shared__ __align__(16) uint32_t oh2[64][4];     // one-hot of symbols e, e+1
-    __shared__ __align__(16) uint32_t mt4[64][4][2];  // [e][c]: symbols e..e+3 == c
-    __shared__ __align__(16) float acc[NG][16][PX][4];
+    return __builtin_bit_cast(uint32_t, half2v{(_Float16)p0, (_Float16)p1});
+}
 
-    const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+// E-step k-blocks (8 positions each) for MT M-tiles (4 positions each)
+template <int MT>
+struct Tiles {
+    static constexpr int LB = (MT + 1) / 2;
+    static constexpr int PX = 8 * LB;
+};
+
+// one-hot tables of one window pair: the symbols at s0 + a0 + e
+struct PairTables {
+    uint32_t oh2[64][4];     // letters 0..3 of symbol e, then of symbol e+1
+    uint32_t mt8[64][4][4];  // [e][c]: symbols e..e+3 and e+16..e+19 == c
+};
+
+// lut[y]: four FP16 halves, half q = 1.0 where 2-bit field q of y (from the top)
+// is zero.  With y = (4 symbols) ^ (c * 0x55) that is the one-hot of letter c.
+__device__ __forceinline__ void build_lut(uint2 *lut)
+{
+    const uint32_t y = threadIdx.x;  // the workgroup has 256 threads
+    uint32_t h[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] = ((y >> (6 - 2 * q)) & 3u) ? 0u : 0x3C00u;
+    lut[y] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+}
+
+// Workgroup-cooperative build: thread (e = tid / 4, c = tid % 4) writes
+// mt8[e][c] and word c of oh2[e].
+template <bool CLAMP>
+__device__ __forceinline__ void build_tables(const uint32_t *W, int64_t nw, int64_t base, const uint2 *lut,
+                                             PairTables &T)
+{
+    const int tid = threadIdx.x, e = tid >> 2;
+    const uint32_t c = tid & 3u;
+    uint32_t hi, lo;
+    dna32<CLAMP>(W, base + e, nw, hi, lo);
+    const uint32_t cc = c * 0x55u;
+    const uint2 u0 = lut[(hi >> 24) ^ cc], u1 = lut[(lo >> 24) ^ cc];
+    *reinterpret_cast<uint4 *>(&T.mt8[e][c][0]) = make_uint4(u0.x, u0.y, u1.x, u1.y);
+    // word c of oh2[e]: letters 2(c&1), 2(c&1)+1 of symbol e (c < 2) or e+1
+    const uint32_t sym = c < 2 ? hi >> 30 : (hi >> 28) & 3u;
+    T.oh2[e][c] = (sym >> 1) == (c & 1u) ? 0x3C00u << ((sym & 1u) << 4) : 0u;
+}
+
+struct SeqState {
+    float mref;   // reference (log2 units) of the scores
+    float srun;   // this lane's share of sum 2^(S - mref + kPOff)
+    float bestv;  // final E-step: best score and window of this lane
+    int besti;
+};
+
+// One pair of 16-window tiles (windows a0 .. a0+31 of one sequence) for this
+// wave's 16 models.
+template <int MT, bool LAST, bool TAIL>
+__device__ __forceinline__ void tile_pair(int a0, int L, const PairTables &T, const half8 (&Whi)[Tiles<MT>::LB],
+                                          const half8 (&Wlo)[Tiles<MT>::LB], float4v (&O)[MT], SeqState &st)
+{
+    constexpr int LB = Tiles<MT>::LB;
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    half8 Ae[2][LB];
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+        for (int kb = 0; kb < LB; ++kb)
+            Ae[t2][kb] = *reinterpret_cast<const half8 *>(&T.oh2[16 * t2 + r + 8 * kb + 2 * g][0]);
+    // E-step, already shifted: S' = S - (mref - kPOff); one chain per tile
+    const float sh = st.mref - kPOff;
+    float4v S0 = {-sh, -sh, -sh, -sh}, S1 = S0;
+#pragma unroll
+    for (int kb = 0; kb < LB; ++kb) {
+        S0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[0][kb], Whi[kb], S0, 0, 0, 0);
+        S1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[1][kb], Whi[kb], S1, 0, 0, 0);
+        S0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[0][kb], Wlo[kb], S0, 0, 0, 0);
+        S1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[1][kb], Wlo[kb], S1, 0, 0, 0);
+    }
+    half8 Am[MT];
+    if (!LAST) {
+        // M-step A operand: row (position pm, letter cm); windows 4g..4g+3 of both tiles
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            Am[mt] = *reinterpret_cast<const half8 *>(&T.mt8[4 * g + 4 * mt + (r >> 2)][r & 3][0]);
+    }
+    float S[8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        S[j] = S0[j];
+        S[4 + j] = S1[j];
+    }
+    if (TAIL) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (a0 + 16 * (q >> 2) + 4 * g + (q & 3) >= L) S[q] = -INFINITY;
+    }
+    float tm = fmaxf(fmaxf(fmaxf(S[0], S[1]), fmaxf(S[2], S[3])), fmaxf(fmaxf(S[4], S[5]), fmaxf(S[6], S[7])));
+    if (LAST) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (S[q] + sh > st.bestv) {
+                st.bestv = S[q] + sh;
+                st.besti = a0 + 16 * (q >> 2) + 4 * g + (q & 3);
+            }
+    }
+    if (__builtin_expect(__ballot(tm > kPOff + kSlack) != 0, 0)) {
+        // rare: move the reference up to the model's new maximum
+        tm = fmaxf(tm, __shfl_xor(tm, 16));
+        tm = fmaxf(tm, __shfl_xor(tm, 32));
+        const float d = tm > kPOff + kSlack ? tm - kPOff : 0.f;
+        const float al = __builtin_amdgcn_exp2f(-d);
+        st.srun *= al;
+        if (!LAST)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) O[mt] *= al;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) S[q] -= d;
+        st.mref += d;
+    }
+    float P[8], ps = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        P[q] = __builtin_amdgcn_exp2f(S[q]);
+        ps += P[q];
+    }
+    st.srun += ps;
+    if (!LAST) {
+        uint4 h, lw;
+        h.x = pack_hi(P[0], P[1]);
+        h.y = pack_hi(P[2], P[3]);
+        h.z = pack_hi(P[4], P[5]);
+        h.w = pack_hi(P[6], P[7]);
+        lw.x = split_lo(h.x, P[0], P[1]);
+        lw.y = split_lo(h.y, P[2], P[3]);
+        lw.z = split_lo(h.z, P[4], P[5]);
+        lw.w = split_lo(h.w, P[6], P[7]);
+        const half8 Ph = __builtin_bit_cast(half8, h), Pl = __builtin_bit_cast(half8, lw);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) O[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[mt], Ph, O[mt], 0, 0, 0);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) O[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[mt], Pl, O[mt], 0, 0, 0);
+    }
+}
+
+// One sequence: every window pair (tables built by the whole workgroup), then
+// the per-sequence log-sum-exp and counts, or, in the final E-step, the best
+// start of every model.
+template <int MT, bool STAGED, bool LAST>
+__device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, const uint2 *lut, int i, int64_t bw,
+                                      int64_t nvalid, PairTables *tabs, int &parity, float (*acc)[Tiles<MT>::PX][4],
+                                      const half8 (&Whi)[Tiles<MT>::LB], const half8 (&Wlo)[Tiles<MT>::LB],
+                                      float mlow, double &llr)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    const int64_t s0 = a.offsets[i];
+    const int L = (int)(a.offsets[i + 1] - s0) - a.l + 1;
+    float4v O[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) O[mt] = float4v{0.f, 0.f, 0.f, 0.f};
+    // the reference starts at the lowest score the model can give
+    SeqState st{mlow, 0.f, -INFINITY, 0};
+    for (int a0 = 0; a0 < L; a0 += 32) {
+        PairTables &T = tabs[parity];
+        parity ^= 1;
+        build_tables<!STAGED>(W, a.nwords, s0 + a0, lut, T);
+        __syncthreads();
+        if (a0 + 32 <= L) tile_pair<MT, LAST, false>(a0, L, T, Whi, Wlo, O, st);
+        else tile_pair<MT, LAST, true>(a0, L, T, Whi, Wlo, O, st);
+    }
+    float sr = st.srun;
+    sr += __shfl_xor(sr, 16);
+    sr += __shfl_xor(sr, 32);
+    const double ln2 = 0.6931471805599453;
+    const double lse = ((double)st.mref - (double)kPOff) * ln2 + log((double)sr);
+    llr += lse - log((double)L);
+    if (!LAST) {
+        const float inv = 1.0f / sr;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            float4v *dst = reinterpret_cast<float4v *>(&acc[r][4 * mt + g][0]);
+            *dst += O[mt] * inv;
+        }
+    } else if (a.sites) {
+        float bv = st.bestv;
+        int bi = st.besti;
+#pragma unroll
+        for (int o = 16; o <= 32; o <<= 1) {
+            const float ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
+            if (ov > bv || (ov == bv && oi < bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        const int64_t b = bw + r;
+        if (g == 0 && b < nvalid) a.sites[b * a.t + i] = bi;
+    }
+}
+
+template <int MT, bool STAGED>
+__global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(const EmMfmaArgs a)
+{
+    constexpr int LB = Tiles<MT>::LB, PX = Tiles<MT>::PX;
+    __shared__ __align__(16) PairTables tabs[2];
+    __shared__ __align__(16) uint2 lut[256];
+    __shared__ __align__(16) float accs[kWaves][16][PX][4];
+    extern __shared__ __align__(16) uint32_t staged[];
+
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     int64_t nvalid = a.n_dev ? *a.n_dev : a.B;
     if (nvalid > a.B) nvalid = a.B;
-    const int64_t b0 = (int64_t)blockIdx.x * 16 * NG;
-    if (b0 >= nvalid) return;
+    const int64_t b0 = (int64_t)blockIdx.x * 16 * kWaves;
+    if (b0 >= nvalid) return;  // uniform over the workgroup
+    if (STAGED)
+        for (int k = threadIdx.x; k < a.stage_words + kStagePad; k += 64 * kWaves)
+            staged[k] = k < a.stage_words ? a.packed[k] : 0u;
+    const uint32_t *W = STAGED ? staged : a.packed;
+    build_lut(lut);
+    const int64_t bw = b0 + 16 * wv;
+    float (*acc)[PX][4] = accs[wv];
     const int l = a.l, t = a.t, AL = 4 * l;
-    const int MT = (l + 3) >> 2;
     const double beta = a.beta;
-    const double lbg[4] = {log(a.bg[0]), log(a.bg[1]), log(a.bg[2]), log(a.bg[3])};
+    const int64_t b = bw + r;
+    const bool vb = b < nvalid;
+    int parity = 0;
 
-    half8 Whi[NG][LB], Wlo[NG][LB];
-    float4v O[NG][MTX];
-
+    half8 Whi[LB], Wlo[LB];
     for (int it = 0; it <= a.iters; ++it) {
         const bool last = it == a.iters;
         const double *src = it == 0 ? a.theta0 : a.theta_out;
-        double prior[NG], llr[NG];
-        // ---- log-odds of every model (own entries: positions p = 4mt + g)
-#pragma unroll
-        for (int grp = 0; grp < NG; ++grp) {
-            const int64_t b = b0 + 16 * grp + r;
-            const bool vb = b < nvalid;
-            double pr = 0;
-#pragma unroll
-            for (int mt = 0; mt < MTX; ++mt) {
-                const int p = 4 * mt + g;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    float w = 0.f;
-                    if (p < l && vb) {
-                        const double th = src[b * AL + c * l + p];
-                        if (it == 0) a.theta_out[b * AL + c * l + p] = th;
-                        w = (float)((log(th) - lbg[c]) * (double)kLog2e);
-                        pr += a.bg[c] * log(th);
-                    }
-                    if (p < PX) acc[grp][r][p][c] = w;
+        // ---- log-odds (log2 units) of the wave's models, own entries p = 4mt + g
+        double prior = 0;
+        float wmin = 0.f;
+        #pragma unroll 1
+        for (int mt = 0; mt < 2 * LB; ++mt) {
+            const int p = 4 * mt + g;
+            float mn = 0.f;
+            #pragma unroll 1
+            for (int c = 0; c < 4; ++c) {
+                float w = 0.f;
+                if (p < l && vb) {
+                    const double th = src[b * AL + c * l + p];
+                    if (it == 0) a.theta_out[b * AL + c * l + p] = th;
+                    const double lt = log(th);
+                    w = (float)((lt - log(a.bg[c])) * (double)kLog2e);
+                    prior += a.bg[c] * lt;
                 }
+                acc[r][p][c] = w;
+                mn = c == 0 ? w : fminf(mn, w);
             }
-            pr += __shfl_xor(pr, 16);
-            pr += __shfl_xor(pr, 32);
-            prior[grp] = pr;
-            llr[grp] = 0;
+            wmin += mn;
         }
+        prior += __shfl_xor(prior, 16);
+        prior += __shfl_xor(prior, 32);
+        wmin += __shfl_xor(wmin, 16);
+        wmin += __shfl_xor(wmin, 32);
+        // lowest possible score, a little below to absorb rounding
+        const float mlow = wmin - 1.0f;
         wave_sync();
-        // ---- B operands of the E-step: positions 8kb+2g, 8kb+2g+1, letters 0..3
+        // ---- E-step B operands: positions 8kb+2g and 8kb+2g+1, letters 0..3
 #pragma unroll
-        for (int grp = 0; grp < NG; ++grp)
+        for (int kb = 0; kb < LB; ++kb) {
+            const int p0 = 8 * kb + 2 * g;
+            const float4v u = *reinterpret_cast<const float4v *>(&acc[r][p0][0]);
+            const float4v v = *reinterpret_cast<const float4v *>(&acc[r][p0 + 1][0]);
+            half8 hi, lo;
 #pragma unroll
-            for (int kb = 0; kb < LB; ++kb) {
-                const int p0 = 8 * kb + 2 * g;
-                const float4v u = *reinterpret_cast<const float4v *>(&acc[grp][r][p0][0]);
-                const float4v v = *reinterpret_cast<const float4v *>(&acc[grp][r][p0 + 1][0]);
-                half8 hi, lo;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    hi[q] = (_Float16)u[q];
-                    lo[q] = (_Float16)(u[q] - (float)hi[q]);
-                    hi[q + 4] = (_Float16)v[q];
-                    lo[q + 4] = (_Float16)(v[q] - (float)hi[q + 4]);
-                }
-                Whi[grp][kb] = hi;
-                Wlo[grp][kb] = lo;
+            for (int q = 0; q < 4; ++q) {
+                hi[q] = (_Float16)u[q];
+                lo[q] = (_Float16)(u[q] - (float)hi[q]);
+                hi[q + 4] = (_Float16)v[q];
+                lo[q + 4] = (_Float16)(v[q] - (float)hi[q + 4]);
             }
+            Whi[kb] = hi;
+            Wlo[kb] = lo;
+        }
         wave_sync();
         // ---- clear the count accumulators (own entries)
 #pragma unroll
-        for (int grp = 0; grp < NG; ++grp)
-#pragma unroll
-            for (int mt = 0; mt < MTX; ++mt) {
-                const int p = 4 * mt + g;
-                if (p < PX) *reinterpret_cast<float4v *>(&acc[grp][r][p][0]) = float4v{0.f, 0.f, 0.f, 0.f};
-            }
+        for (int mt = 0; mt < 2 * LB; ++mt)
+            *reinterpret_cast<float4v *>(&acc[r][4 * mt + g][0]) = float4v{0.f, 0.f, 0.f, 0.f};
+        __syncthreads();  // staged sequence visible (first pass), tables free
 
+        double llr = 0;
         for (int i = 0; i < t; ++i) {
-            const int64_t s0 = a.offsets[i];
-            const int L = (int)(a.offsets[i + 1] - s0) - l + 1;
-            float mrun[NG], srun[NG], bestv[NG];
-            int besti[NG];
-#pragma unroll
-            for (int grp = 0; grp < NG; ++grp) {
-                mrun[grp] = -INFINITY;
-                srun[grp] = 0.f;
-                bestv[grp] = -INFINITY;
-                besti[grp] = 0;
-#pragma unroll
-                for (int mt = 0; mt < MTX; ++mt) O[grp][mt] = float4v{0.f, 0.f, 0.f, 0.f};
-            }
-            for (int a0 = 0; a0 < L; a0 += 32) {
-                // ---- tables for the symbols at s0 + a0 + e, e = 0..63 (+3)
-                {
-                    const uint32_t w16 = dna16(a.packed, s0 + a0 + lane, a.nwords);
-                    const uint32_t s_0 = w16 >> 30, s_1 = (w16 >> 28) & 3u, s_2 = (w16 >> 26) & 3u,
-                                   s_3 = (w16 >> 24) & 3u;
-                    uint32_t e0 = onehot_pair(s_0, s_0, 0) & 0xffffu;
-                    e0 |= onehot_pair(s_0, s_0, 1) & 0xffff0000u;
-                    uint32_t e1 = onehot_pair(s_0, s_0, 2) & 0xffffu;
-                    e1 |= onehot_pair(s_0, s_0, 3) & 0xffff0000u;
-                    uint32_t e2 = onehot_pair(s_1, s_1, 0) & 0xffffu;
-                    e2 |= onehot_pair(s_1, s_1, 1) & 0xffff0000u;
-                    uint32_t e3 = onehot_pair(s_1, s_1, 2) & 0xffffu;
-                    e3 |= onehot_pair(s_1, s_1, 3) & 0xffff0000u;
-                    *reinterpret_cast<uint4 *>(&oh2[lane][0]) = make_uint4(e0, e1, e2, e3);
-#pragma unroll
-                    for (uint32_t c = 0; c < 4; ++c)
-                        *reinterpret_cast<uint2 *>(&mt4[lane][c][0]) =
-                            make_uint2(onehot_pair(s_0, s_1, c), onehot_pair(s_2, s_3, c));
-                }
-                wave_sync();
-                half8 Ae[2][LB], Am[MTX];
-#pragma unroll
-                for (int T = 0; T < 2; ++T)
-#pragma unroll
-                    for (int kb = 0; kb < LB; ++kb)
-                        Ae[T][kb] = *reinterpret_cast<const half8 *>(&oh2[16 * T + r + 8 * kb + 2 * g][0]);
-                if (!last) {
-                    // M-step A operand: row (position pm, letter cm), windows 4g..4g+3
-                    // of both tiles
-#pragma unroll
-                    for (int mt = 0; mt < MTX; ++mt) {
-                        const int pm = 4 * mt + (r >> 2), cm = r & 3;
-                        uint4 uu = make_uint4(0, 0, 0, 0);
-                        if (mt < MT) {
-                            const uint2 u0 = *reinterpret_cast<const uint2 *>(&mt4[4 * g + pm][cm][0]);
-                            const uint2 u1 = *reinterpret_cast<const uint2 *>(&mt4[16 + 4 * g + pm][cm][0]);
-                            uu = make_uint4(u0.x, u0.y, u1.x, u1.y);
-                        }
-                        Am[mt] = __builtin_bit_cast(half8, uu);
-                    }
-                }
-                const bool tail = a0 + 32 > L;
-#pragma unroll
-                for (int grp = 0; grp < NG; ++grp) {
-                    float4v S[2];
-#pragma unroll
-                    for (int T = 0; T < 2; ++T) {
-                        S[T] = float4v{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                        for (int kb = 0; kb < LB; ++kb) {
-                            S[T] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[T][kb], Whi[grp][kb], S[T], 0, 0, 0);
-                            S[T] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[T][kb], Wlo[grp][kb], S[T], 0, 0, 0);
-                        }
-                    }
-                    if (tail) {
-#pragma unroll
-                        for (int T = 0; T < 2; ++T)
-#pragma unroll
-                            for (int j = 0; j < 4; ++j)
-                                if (a0 + 16 * T + 4 * g + j >= L) S[T][j] = -INFINITY;
-                    }
-                    if (last) {
-#pragma unroll
-                        for (int T = 0; T < 2; ++T)
-#pragma unroll
-                            for (int j = 0; j < 4; ++j)
-                                if (S[T][j] > bestv[grp]) {
-                                    bestv[grp] = S[T][j];
-                                    besti[grp] = a0 + 16 * T + 4 * g + j;
-                                }
-                    }
-                    // running maximum over the model's windows
-                    float tm = fmaxf(fmaxf(fmaxf(S[0][0], S[0][1]), fmaxf(S[0][2], S[0][3])),
-                                     fmaxf(fmaxf(S[1][0], S[1][1]), fmaxf(S[1][2], S[1][3])));
-                    tm = fmaxf(tm, __shfl_xor(tm, 16));
-                    tm = fmaxf(tm, __shfl_xor(tm, 32));
-                    const float mn = fmaxf(mrun[grp], tm);
-                    if (__ballot(mn > mrun[grp])) {
-                        const float al = __builtin_amdgcn_exp2f(mrun[grp] - mn);
-                        srun[grp] *= al;
-                        if (!last)
-#pragma unroll
-                            for (int mt = 0; mt < MTX; ++mt) O[grp][mt] *= al;
-                    }
-                    mrun[grp] = mn;
-                    const float sh = mn - kPScale;
-                    float P[8];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        P[j] = __builtin_amdgcn_exp2f(S[0][j] - sh);
-                        P[4 + j] = __builtin_amdgcn_exp2f(S[1][j] - sh);
-                    }
-                    float ps = 0.f;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) ps += P[q];
-                    srun[grp] += ps;
-                    if (!last) {
-                        half8 Ph, Pl;
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) {
-                            Ph[q] = (_Float16)P[q];
-                            Pl[q] = (_Float16)(P[q] - (float)Ph[q]);
-                        }
-#pragma unroll
-                        for (int mt = 0; mt < MTX; ++mt) {
-                            if (mt < MT) {
-                                O[grp][mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[mt], Ph, O[grp][mt], 0, 0, 0);
-                                O[grp][mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[mt], Pl, O[grp][mt], 0, 0, 0);
-                            }
-                        }
-                    }
-                }
-                wave_sync();  // the next tile rebuilds the tables
-            }
-            // ---- end of sequence i: log-sum-exp, counts, sites
-#pragma unroll
-            for (int grp = 0; grp < NG; ++grp) {
-                float sr = srun[grp];
-                sr += __shfl_xor(sr, 16);
-                sr += __shfl_xor(sr, 32);
-                const double lse = (double)mrun[grp] * 0.6931471805599453 + log((double)sr) -
-                                   (double)kPScale * 0.6931471805599453;
-                llr[grp] += lse - log((double)L);
-                if (!last) {
-                    const float inv = 1.0f / sr;
-#pragma unroll
-                    for (int mt = 0; mt < MTX; ++mt) {
-                        const int p = 4 * mt + g;
-                        if (mt < MT && p < PX) {
-                            float4v *dst = reinterpret_cast<float4v *>(&acc[grp][r][p][0]);
-                            *dst += O[grp][mt] * inv;
-                        }
-                    }
-                } else if (a.sites) {
-                    float bv = bestv[grp];
-                    int bi = besti[grp];
-#pragma unroll
-                    for (int o = 16; o <= 32; o <<= 1) {
-                        const float ov = __shfl_xor(bv, o);
-                        const int oi = __shfl_xor(bi, o);
-                        if (ov > bv || (ov == bv && oi < bi)) {
-                            bv = ov;
-                            bi = oi;
-                        }
-                    }
-                    const int64_t b = b0 + 16 * grp + r;
-                    if (g == 0 && b < nvalid) a.sites[b * t + i] = bi;
-                }
-            }
+            if (last) sweep<MT, STAGED, true>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
+            else sweep<MT, STAGED, false>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
         }
         // ---- objective of theta^it, then the M-step (own entries)
-#pragma unroll
-        for (int grp = 0; grp < NG; ++grp) {
-            const int64_t b = b0 + 16 * grp + r;
-            if (g == 0 && b < nvalid) {
-                a.J[b * (a.iters + 1) + it] = llr[grp] + beta * prior[grp];
-                if (a.llr) a.llr[b * (a.iters + 1) + it] = llr[grp];
-            }
-            if (!last && b < nvalid) {
-#pragma unroll
-                for (int mt = 0; mt < MTX; ++mt) {
-                    const int p = 4 * mt + g;
-                    if (p < l) {
-                        const float4v cn = *reinterpret_cast<const float4v *>(&acc[grp][r][p][0]);
-                        // every column's counts sum to t: normalising by the column's
-                        // own total is the same update and stays on the simplex
-                        const double tot = (double)cn[0] + (double)cn[1] + (double)cn[2] + (double)cn[3] + beta;
-#pragma unroll
-                        for (int c = 0; c < 4; ++c)
-                            a.theta_out[b * AL + c * l + p] = ((double)cn[c] + beta * a.bg[c]) / tot;
-                    }
+        if (g == 0 && vb) {
+            a.J[b * (a.iters + 1) + it] = llr + beta * prior;
+            if (a.llr) a.llr[b * (a.iters + 1) + it] = llr;
+        }
+        if (!last && vb) {
+            #pragma unroll 1
+            for (int mt = 0; mt < MT; ++mt) {
+                const int p = 4 * mt + g;
+                if (p < l) {
+                    const float4v cn = *reinterpret_cast<const float4v *>(&acc[r][p][0]);
+                    // every column's counts sum to t: normalising by the column's
+                    // own total is the same update and stays on the simplex
+                    const double tot = (double)cn[0] + (double)cn[1] + (double)cn[2] + (double)cn[3] + beta;
+                    #pragma unroll 1
+                    for (int c = 0; c < 4; ++c)
+                        a.theta_out[b * AL + c * l + p] = ((double)cn[c] + beta * a.bg[c]) / tot;
                 }
             }
         }
@@ -360,11 +431,15 @@ __global__ void __launch_bounds__(64) k_em_mfma(const EmMfmaArgs a)
     }
 }
 
-template <int LB, int NG>
+template <int MT>
 static int launch_em_mfma(const EmMfmaArgs &a, hipStream_t st)
 {
-    const int64_t groups = (a.B + 16 * NG - 1) / (16 * NG);
-    hipLaunchKernelGGL((k_em_mfma<LB, NG>), dim3((unsigned)groups), dim3(64), 0, st, a);
+    const int64_t groups = (a.B + 16 * kWaves - 1) / (16 * kWaves);
+    if (a.stage_words)
+        hipLaunchKernelGGL((k_em_mfma<MT, true>), dim3((unsigned)groups), dim3(64 * kWaves),
+                           (size_t)(a.stage_words + kStagePad) * 4, st, a);
+    else
+        hipLaunchKernelGGL((k_em_mfma<MT, false>), dim3((unsigned)groups), dim3(64 * kWaves), 0, st, a);
     PM_LAUNCHED();
     return PM_OK;
 }
@@ -385,16 +460,20 @@ int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const doub
     a.sites = sites_out;
     a.B = B;
     a.nwords = pm_packed_words(S->alphabet, S->n_total);
+    a.stage_words = a.nwords * 4 <= 32 * 1024 ? (int)a.nwords : 0;
     a.t = S->t;
     a.l = l;
     a.iters = iters;
     a.beta = beta;
-    constexpr int NG = 2;
-    switch ((l + 7) / 8) {
-    case 1: return launch_em_mfma<1, NG>(a, st);
-    case 2: return launch_em_mfma<2, NG>(a, st);
-    case 3: return launch_em_mfma<3, NG>(a, st);
-    default: return launch_em_mfma<4, NG>(a, st);
+    switch ((l + 3) / 4) {
+    case 1: return launch_em_mfma<1>(a, st);
+    case 2: return launch_em_mfma<2>(a, st);
+    case 3: return launch_em_mfma<3>(a, st);
+    case 4: return launch_em_mfma<4>(a, st);
+    case 5: return launch_em_mfma<5>(a, st);
+    case 6: return launch_em_mfma<6>(a, st);
+    case 7: return launch_em_mfma<7>(a, st);
+    default: return launch_em_mfma<8>(a, st);
     }
 }
 
