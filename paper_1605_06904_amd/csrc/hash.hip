@@ -199,6 +199,7 @@ static int launch_hash(const HashArgs &a, size_t lds, int blocks, hipStream_t st
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void *)k_hash<A, U16>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, device_lds_bytes());
+        (void)hipGetLastError();  // an unsupported attribute must not poison the launch check
         attr_set = true;
     }
     hipLaunchKernelGGL((k_hash<A, U16>), dim3(blocks), dim3(kHashThreads), lds, st, a);

@@ -4,19 +4,21 @@
 // one (Sec. 6, quadratic work) to avoid a |Sigma|^k table.  On MI355X the dense
 // counts already sit in HBM (the histogram of projection_hash), so selection is
 // a streaming pass: count the passing bins per trial, scan the per-trial
-// totals, then one wave per trial emits the buckets in key order with
-// wave-level prefix sums and places every member window with a stable,
-// deterministic counting sort.
+// totals, then one workgroup per trial turns its counts into an LDS bitmap of
+// passing keys (one ballot per 64 keys), scans it to give every bucket its
+// index and first member slot, and places the member windows with a stable,
+// deterministic two-pass counting sort over four window quarters.
 #include "pm_common.h"
 
 namespace pm {
 
 struct SelWs {
-    int64_t *ne;   // [m] enriched buckets per trial
-    int64_t *ms;   // [m] members per trial
-    int64_t *bb;   // [m] first bucket of the trial
-    int64_t *mb;   // [m] first member slot of the trial
-    uint32_t *fill;  // [cap_b] members placed so far
+    int64_t *ne;      // [m] enriched buckets per trial
+    int64_t *ms;      // [m] members per trial
+    int64_t *bb;      // [m] first bucket of the trial
+    int64_t *mb;      // [m] first member slot of the trial
+    uint32_t *qcnt;   // [cap_b][4] members of the bucket in each window quarter
+    uint32_t *placed; // [cap_b][4] members placed so far by each quarter's wave
 };
 
 static SelWs carve(void *ws, int32_t m, int64_t cap_b)
@@ -27,8 +29,8 @@ static SelWs carve(void *ws, int32_t m, int64_t cap_b)
     w.ms = w.ne + m;
     w.bb = w.ms + m;
     w.mb = w.bb + m;
-    w.fill = reinterpret_cast<uint32_t *>(w.mb + m);
-    (void)cap_b;
+    w.qcnt = reinterpret_cast<uint32_t *>(w.mb + m);
+    w.placed = w.qcnt + 4 * cap_b;
     return w;
 }
 
@@ -43,6 +45,7 @@ struct SelArgs {
     int64_t x, nb, cap_b, cap_m;
     int32_t m;
     uint32_t s;
+    int nwb;  // bitmap words, ceil(nb / 64)
 };
 
 __device__ __forceinline__ bool passes(uint32_t c, uint32_t s) { return c >= s && c > 0; }
@@ -51,14 +54,17 @@ __device__ __forceinline__ bool passes(uint32_t c, uint32_t s) { return c >= s &
 __global__ void __launch_bounds__(256) k_sel_count(const SelArgs a)
 {
     const int j = blockIdx.x;
-    const uint32_t *cnt = a.counts + (int64_t)j * a.nb;
+    const uint4 *cnt = reinterpret_cast<const uint4 *>(a.counts + (int64_t)j * a.nb);  // nb % 4 == 0
     uint64_t ne = 0, ms = 0;
-    for (int64_t b = threadIdx.x; b < a.nb; b += 256) {
-        const uint32_t c = cnt[b];
-        if (passes(c, a.s)) {
-            ne += 1;
-            ms += c;
-        }
+    for (int64_t b = threadIdx.x; b < a.nb / 4; b += 256) {
+        const uint4 v = cnt[b];
+        const uint32_t c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (passes(c[q], a.s)) {
+                ne += 1;
+                ms += c[q];
+            }
     }
     ne = wave_sum(ne);
     ms = wave_sum(ms);
@@ -117,80 +123,151 @@ __global__ void __launch_bounds__(1024) k_sel_scan(const SelArgs a)
     }
 }
 
-// one wave per trial: bucket records in key order, then members in window order
-__global__ void __launch_bounds__(64) k_sel_emit(const SelArgs a)
+// exclusive prefix sums of n u32 values in place (256 threads, n <= 256 * 64)
+__device__ void block_excl_scan(uint32_t *v, int n, uint32_t *tmp)
 {
+    const int tid = threadIdx.x, per = (n + 255) / 256;
+    const int lo = tid * per, hi = lo + per < n ? lo + per : n;
+    uint32_t s = 0;
+    for (int i = lo; i < hi; ++i) s += v[i];
+    tmp[tid] = s;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t u = tid >= o ? tmp[tid - o] : 0u;
+        __syncthreads();
+        tmp[tid] += u;
+        __syncthreads();
+    }
+    uint32_t run = tmp[tid] - s;
+    for (int i = lo; i < hi; ++i) {
+        const uint32_t x = v[i];
+        v[i] = run;
+        run += x;
+    }
+    __syncthreads();
+}
+
+// one workgroup (four waves) per trial
+__global__ void __launch_bounds__(256) k_sel_emit(const SelArgs a)
+{
+    extern __shared__ __align__(16) uint64_t bm[];  // [nwb] passing keys
+    uint32_t *wcnt = reinterpret_cast<uint32_t *>(bm + a.nwb);  // [nwb] -> buckets before the word
+    uint32_t *wsz = wcnt + a.nwb;                               // [nwb] -> members before the word
+    __shared__ uint32_t tmp[256];
     const int j = blockIdx.x;
-    const int lane = lane_id();
+    const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
     const uint32_t *cnt = a.counts + (int64_t)j * a.nb;
     const int64_t bbase = a.ws.bb[j], mbase = a.ws.mb[j];
-    int64_t lcount = 0, lsize = 0;
 
-    for (int64_t c0 = 0; c0 < a.nb; c0 += 64) {
-        const int64_t key = c0 + lane;
-        const uint32_t c = key < a.nb ? cnt[key] : 0u;
-        const bool flag = passes(c, a.s);
-        const uint64_t bal = __ballot(flag);
-        if (!bal) continue;
-        const uint32_t rank = __popcll(bal & lanemask_lt());
-        const uint32_t mine = flag ? c : 0u;
-        const uint32_t incl = wave_incl_scan(mine);
-        const uint32_t tot = __shfl(incl, 63);
-        if (flag) {
-            const int64_t b = bbase + lcount + rank;
+    // ---- bitmap of passing keys, one ballot per word of 64 keys; eight loads
+    // in flight per wave
+    constexpr int U = 8;
+    for (int w0 = wv; w0 < a.nwb; w0 += 4 * U) {
+        uint32_t c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t key = (int64_t)(w0 + 4 * u) * 64 + lane;
+            c[u] = (w0 + 4 * u < a.nwb && key < a.nb) ? cnt[key] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int wi = w0 + 4 * u;
+            const bool flag = passes(c[u], a.s);
+            const uint64_t bal = __ballot(flag);
+            uint32_t sz = 0;
+            if (bal) sz = wave_sum(flag ? c[u] : 0u);
+            if (lane == 0 && wi < a.nwb) {
+                bm[wi] = bal;
+                wcnt[wi] = __popcll(bal);
+                wsz[wi] = sz;
+            }
+        }
+    }
+    __syncthreads();
+    block_excl_scan(wcnt, a.nwb, tmp);
+    block_excl_scan(wsz, a.nwb, tmp);
+
+    // ---- bucket records, in key order
+    for (int wi = tid; wi < a.nwb; wi += 256) {
+        uint64_t bits = bm[wi];
+        int64_t b = bbase + wcnt[wi];
+        int64_t first = mbase + wsz[wi];
+        while (bits) {
+            const int bit = __ffsll((unsigned long long)bits) - 1;
+            bits &= bits - 1;
+            const int64_t key = (int64_t)wi * 64 + bit;
+            const uint32_t c = cnt[key];
             if (b < a.cap_b) {
-                const int64_t first = mbase + lsize + (incl - mine);
                 pm_bucket *B = a.buckets + b;
                 st_agent(&B->trial, (uint32_t)j);
                 st_agent(&B->key, (uint32_t)key);
                 st_agent(&B->size, c);
                 st_agent(&B->first, (uint32_t)first);
-                st_agent(a.ws.fill + b, 0u);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    st_agent(a.ws.qcnt + 4 * b + q, 0u);
+                    st_agent(a.ws.placed + 4 * b + q, 0u);
+                }
             }
+            ++b;
+            first += c;
         }
-        lcount += __popcll(bal);
-        lsize += tot;
     }
-    __threadfence();
+    // the records, counters and first slots above are agent-scope atomics read
+    // back only by this workgroup: a workgroup barrier orders them (an
+    // agent-scope fence would write back and invalidate the whole L2)
+    __syncthreads();
 
-    int64_t nloc = a.cap_b - bbase;
-    if (nloc < 0) nloc = 0;
-    if (nloc > lcount) nloc = lcount;
-    if (nloc == 0) return;
+    // ---- members: wave wv owns windows [lo, hi); pass 0 counts per bucket,
+    // pass 1 places them after the members of earlier quarters
     const uint32_t *kj = a.keys + (int64_t)j * a.x;
-    for (int64_t w0 = 0; w0 < a.x; w0 += 64) {
-        const int64_t w = w0 + lane;
-        const bool valid = w < a.x;
-        const uint32_t key = valid ? kj[w] : 0u;
-        const uint32_t c = valid && key < a.nb ? cnt[key] : 0u;
-        const bool flag = valid && passes(c, a.s);
-        uint64_t bal = __ballot(flag);
-        while (bal) {
-            const int leader = __ffsll((unsigned long long)bal) - 1;
-            const uint32_t lk = __shfl(key, leader);
-            const bool peer = flag && key == lk;
-            const uint64_t peers = __ballot(peer);
-            int64_t slot0 = -1;
-            if (lane == leader) {
-                int64_t lo = 0, hi = nloc;
-                while (lo < hi) {
-                    const int64_t mid = (lo + hi) >> 1;
-                    if (ld_agent(&a.buckets[bbase + mid].key) < lk) lo = mid + 1;
-                    else hi = mid;
+    const int64_t lo = a.x * wv / 4, hi = a.x * (wv + 1) / 4;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int64_t wb = lo; wb < hi; wb += 64 * U) {
+          uint32_t kk[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+              const int64_t w = wb + 64 * u + lane;
+              kk[u] = w < hi ? kj[w] : 0u;
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int64_t w = wb + 64 * u + lane;
+            const bool valid = w < hi;
+            const uint32_t key = kk[u];
+            const bool flag = valid && key < a.nb && ((bm[key >> 6] >> (key & 63)) & 1ull);
+            uint64_t bal = __ballot(flag);
+            while (bal) {
+                const int leader = __ffsll((unsigned long long)bal) - 1;
+                const uint32_t lk = __shfl(key, leader);
+                const bool peer = flag && key == lk;
+                const uint64_t peers = __ballot(peer);
+                int64_t slot0 = -1;
+                if (lane == leader) {
+                    const uint64_t word = bm[lk >> 6];
+                    const int64_t b = bbase + wcnt[lk >> 6] + __popcll(word & ((1ull << (lk & 63)) - 1ull));
+                    if (b < a.cap_b) {
+                        if (pass == 0) {
+                            atomicAdd(a.ws.qcnt + 4 * b + wv, (uint32_t)__popcll(peers));
+                        } else {
+                            int64_t base = ld_agent(&a.buckets[b].first);
+                            for (int q = 0; q < wv; ++q) base += ld_agent(a.ws.qcnt + 4 * b + q);
+                            slot0 = base + atomicAdd(a.ws.placed + 4 * b + wv, (uint32_t)__popcll(peers));
+                        }
+                    }
                 }
-                if (lo < nloc && ld_agent(&a.buckets[bbase + lo].key) == lk) {
-                    const int64_t b = bbase + lo;
-                    const uint32_t old = atomicAdd(a.ws.fill + b, (uint32_t)__popcll(peers));
-                    slot0 = (int64_t)ld_agent(&a.buckets[b].first) + old;
+                if (pass == 1) {
+                    slot0 = __shfl(slot0, leader);
+                    if (peer && slot0 >= 0) {
+                        const int64_t slot = slot0 + __popcll(peers & lanemask_lt());
+                        if (slot < a.cap_m) a.members[slot] = (uint32_t)w;
+                    }
                 }
+                bal &= ~peers;
             }
-            slot0 = __shfl(slot0, leader);
-            if (peer && slot0 >= 0) {
-                const int64_t slot = slot0 + __popcll(peers & lanemask_lt());
-                if (slot < a.cap_m) a.members[slot] = (uint32_t)w;
-            }
-            bal &= ~peers;
+          }
         }
+        __syncthreads();
     }
 }
 
@@ -263,7 +340,7 @@ using namespace pm;
 extern "C" size_t pm_select_workspace(int32_t m, int64_t cap_buckets)
 {
     if (m < 0 || cap_buckets < 0) return 0;
-    return (size_t)m * 4 * sizeof(int64_t) + (size_t)cap_buckets * sizeof(uint32_t) + 256;
+    return (size_t)m * 4 * sizeof(int64_t) + (size_t)cap_buckets * 8 * sizeof(uint32_t) + 256;
 }
 
 extern "C" int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *keys,
@@ -282,7 +359,7 @@ extern "C" int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint3
         return fail(PM_EINVAL, "NULL output with a non-zero capacity");
     if (cap_members > 0xffffffffll) return fail(PM_ERANGE, "cap_members must be below 2^32");
     const int A = S->alphabet;
-    if ((A == 4 && k > 12) || (A == 20 && k > 5)) return fail(PM_ERANGE, "|Sigma|^k above 2^24");
+    if (ipow(A, k) > (1ll << 19)) return fail(PM_ERANGE, "|Sigma|^k above 2^19");
     if (ws_bytes < pm_select_workspace(m, cap_buckets)) return fail(PM_EINVAL, "workspace too small");
     SelArgs a{};
     a.keys = keys;
@@ -303,7 +380,17 @@ extern "C" int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint3
     PM_LAUNCHED();
     hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(1024), 0, st, a);
     PM_LAUNCHED();
-    hipLaunchKernelGGL(k_sel_emit, dim3(m), dim3(64), 0, st, a);
+    a.nwb = (int)((a.nb + 63) / 64);
+    const size_t lds = (size_t)a.nwb * 16;
+    static bool attr = false;
+    if (!attr) {
+        // the kernel also holds 1 KB of static LDS
+        (void)hipFuncSetAttribute((const void *)k_sel_emit, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  device_lds_bytes() - 2048);
+        (void)hipGetLastError();  // an unsupported attribute must not poison the launch check
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_sel_emit, dim3(m), dim3(256), lds, st, a);
     PM_LAUNCHED();
     return PM_OK;
 }
