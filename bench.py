@@ -24,6 +24,23 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 FP16_MFMA_PEAK = 2500.0      # TFLOP/s, MI355X dense FP16 matrix cores
 
+# HBM bytes per launch from the FETCH_SIZE/WRITE_SIZE counter runs recorded in
+# profiles/hbm_traffic_dna_18-6_m5000.md (copy-calibrated), valid only while
+# the kernel source is the one they were taken on (sha256 prefix).
+MEASURED_TRAFFIC = {
+    "hash.hip": ("4e338f9a0a0a036d", 1.779e9),
+    "em_mfma.hip": ("1ba7acbb0d2af902", 0.455e9 + 0.667e9),
+}
+
+
+def traffic(src):
+    import hashlib
+    sha, nbytes = MEASURED_TRAFFIC[src]
+    path = os.path.join(ROOT, "paper_1605_06904_amd", "csrc", src)
+    with open(path, "rb") as f:
+        cur = hashlib.sha256(f.read()).hexdigest()[:16]
+    return nbytes if cur == sha else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -33,6 +50,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also run one plain device copy of this many bytes (counter calibration)")
     return ap.parse_args()
 
 
@@ -126,11 +145,11 @@ def main():
     dominant = max(stage, key=stage.get)
     if dominant == "hash":
         roof = {"kernel": "k_hash<4,true>", "bound": "hbm", "achieved": round(hash_gbs, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4), "traffic": None}
+                "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4), "traffic": traffic("hash.hip")}
     else:
         roof = {"kernel": "k_em_mfma<5,true>", "bound": "mfma", "achieved": round(em_tfs, 3),
                 "peak": FP16_MFMA_PEAK, "unit": "TFLOP/s", "frac": round(em_tfs / FP16_MFMA_PEAK, 5),
-                "traffic": None}
+                "traffic": traffic("em_mfma.hip"), "flops_per_launch": em_flops}
     out = {
         "metric": "projected l-mers/s (whole PROJECTION+EM pass, (18,6) DNA workload)",
         "value": round(value, 1),
@@ -150,14 +169,23 @@ def main():
                    "parallelism": "single GPU"},
         "stage_ms": stage,
         "roofline": roof,
-        "roofline_hash": {"kernel": "k_hash", "bound": "hbm", "achieved": round(hash_gbs, 2),
+        "roofline_hash": {"kernel": "k_hash<4,true>", "bound": "hbm", "achieved": round(hash_gbs, 2),
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4),
-                          "bytes_per_launch": hash_bytes},
+                          "traffic": traffic("hash.hip"), "bytes_per_launch": hash_bytes},
         "hash_lmers_per_s": round(lmers / (stage["hash"] / 1e3), 1),
         "em_column_updates_per_s": round(em_updates / (stage["em"] / 1e3), 1),
         "consensus": res.get("consensus"),
         "planted": inst.motif,
     }
+    if args.copy_probe:
+        # a plain copy of known size, read once and written once, for scaling
+        # the HBM byte counters of the kernels above
+        src = torch.ones(args.copy_probe, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = args.copy_probe
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, masks, cfg, bg, beta, nbk, args.cpu_budget)
     print(json.dumps(out), flush=True)
