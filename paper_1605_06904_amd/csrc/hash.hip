@@ -79,8 +79,9 @@ struct HashArgs {
 };
 
 constexpr int kHashThreads = 1024;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-template <int A, bool U16>
+template <int A, int K, bool U16>
 __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
 {
     extern __shared__ __align__(16) uint32_t smem[];
@@ -111,13 +112,15 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
     const int64_t *O = a.stage_off ? offs : a.offsets;
 
     // kept positions, ascending (uniform across the workgroup)
-    constexpr int MAXK = A == 4 ? 16 : 7;
-    int pos[MAXK];
+    // shift of each kept position's 2-bit field in the 64-bit window (DNA), or
+    // the position itself (protein)
+    int pos[K];
     {
         uint32_t mm = mask;
 #pragma unroll
-        for (int q = 0; q < MAXK; ++q) {
-            pos[q] = mm ? __builtin_ctz(mm) : 0;
+        for (int q = 0; q < K; ++q) {
+            const int p = __builtin_ctz(mm);
+            pos[q] = A == 4 ? 62 - 2 * p : p;
             mm &= mm - 1;
         }
     }
@@ -136,13 +139,12 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
         if (A == 4) {
             uint32_t hi, lo;
             dna_window(W, P, hi, lo);
+            const uint64_t win = ((uint64_t)hi << 32) | lo;
 #pragma unroll
-            for (int q = 0; q < MAXK; ++q)
-                if (q < a.k) key = (key << 2) | dna_at(hi, lo, pos[q]);
+            for (int q = 0; q < K; ++q) key = (key << 2) | ((uint32_t)(win >> pos[q]) & 3u);
         } else {
 #pragma unroll
-            for (int q = 0; q < MAXK; ++q)
-                if (q < a.k) key = key * 20u + prot_sym(W, P + pos[q]);
+            for (int q = 0; q < K; ++q) key = key * 20u + prot_sym(W, P + pos[q]);
         }
         if (keys_j && w >= kw0 && w < kw1) __builtin_nontemporal_store(key, keys_j + w);
         if (a.counts) {
@@ -185,26 +187,42 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
         } else {
             v = *reinterpret_cast<const uint4 *>(hist + b4);
         }
-        __builtin_nontemporal_store(v.x, out + b4 + 0);
-        __builtin_nontemporal_store(v.y, out + b4 + 1);
-        __builtin_nontemporal_store(v.z, out + b4 + 2);
-        __builtin_nontemporal_store(v.w, out + b4 + 3);
+        __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<u32x4 *>(out + b4));
     }
 }
 
-template <int A, bool U16>
+template <int A, int K, bool U16>
 static int launch_hash(const HashArgs &a, size_t lds, int blocks, hipStream_t st)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_hash<A, U16>,
+        (void)hipFuncSetAttribute((const void *)k_hash<A, K, U16>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, device_lds_bytes());
         (void)hipGetLastError();  // an unsupported attribute must not poison the launch check
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_hash<A, U16>), dim3(blocks), dim3(kHashThreads), lds, st, a);
+    hipLaunchKernelGGL((k_hash<A, K, U16>), dim3(blocks), dim3(kHashThreads), lds, st, a);
     PM_LAUNCHED();
     return PM_OK;
+}
+
+// run-time (alphabet, k, histogram width) -> compile-time kernel
+template <int K>
+static int dispatch_hash(int alphabet, int k, bool u16, const HashArgs &a, size_t lds, int blocks, hipStream_t st)
+{
+    constexpr int KMAX = 16;
+    if constexpr (K > KMAX) {
+        return fail(PM_ERANGE, "k=%d not supported", k);
+    } else {
+        if (k != K) {
+            return dispatch_hash<K + 1>(alphabet, k, u16, a, lds, blocks, st);
+        }
+        if (alphabet == 4)
+            return u16 ? launch_hash<4, K, true>(a, lds, blocks, st) : launch_hash<4, K, false>(a, lds, blocks, st);
+        if constexpr (K <= 7)
+            return u16 ? launch_hash<20, K, true>(a, lds, blocks, st) : launch_hash<20, K, false>(a, lds, blocks, st);
+        return fail(PM_ERANGE, "k=%d not supported for protein", k);
+    }
 }
 
 }  // namespace pm
@@ -289,6 +307,5 @@ extern "C" int projection_hash(const pm_seqs *S, int32_t l, int32_t k, const uin
     const int64_t blocks = (int64_t)m * a.nslices;
     if (blocks > 0x7fffffff) return fail(PM_ERANGE, "too many trials x slices");
     hipStream_t st = as_stream(stream);
-    if (A == 4) return u16 ? launch_hash<4, true>(a, lds, (int)blocks, st) : launch_hash<4, false>(a, lds, (int)blocks, st);
-    return u16 ? launch_hash<20, true>(a, lds, (int)blocks, st) : launch_hash<20, false>(a, lds, (int)blocks, st);
+    return dispatch_hash<1>(A, k, u16, a, lds, (int)blocks, st);
 }
