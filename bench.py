@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run one plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--instances", type=int, default=256,
+                    help="(15,4) instances for the instances/s leg (0: skip it)")
     return ap.parse_args()
 
 
@@ -177,6 +179,8 @@ def main():
         "consensus": res.get("consensus"),
         "planted": inst.motif,
     }
+    if args.instances > 0:
+        out["instances"] = instances_leg(torch, pm, args.instances)
     if args.copy_probe:
         # a plain copy of known size, read once and written once, for scaling
         # the HBM byte counters of the kernels above
@@ -189,6 +193,98 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, masks, cfg, bg, beta, nbk, args.cpu_budget)
     print(json.dumps(out), flush=True)
+
+
+def perf_coefficient(starts, sites, l):
+    """|planted residues & predicted residues| / |union|, over the sequences
+    of one instance (windows of length l)."""
+    inter = union = 0
+    for a, b in zip(starts, sites):
+        ov = max(0, min(a, b) + l - max(a, b))
+        inter += ov
+        union += 2 * l - ov
+    return inter / union
+
+
+def instances_leg(torch, pm, count):
+    """(15,4) instances solved per second: every instance through the plain
+    per-instance pipeline (FP64 EM, all enriched buckets), and the same
+    instances as one graph-captured batch (EM on the split-FP16 matrix cores).
+    Solved = consensus equals the planted motif."""
+    from synth import make_config
+    insts = [make_config("c1", seed=i) for i in range(count)]
+    cfg = insts[0][0].meta
+    l, k, s, iters = cfg["l"], cfg["k"], cfg["s"], cfg["iters"]
+    bg = np.full(4, 0.25)
+    beta = 1.0
+
+    def score(cons, sites, inst):
+        return (cons == inst.motif), perf_coefficient(inst.starts, sites, l)
+
+    # ---- plain: one pipeline per instance, run one after another
+    pipes = []
+    for inst, masks in insts:
+        S = pm.Seqs(4, inst.seqs)
+        P0 = pm.Pipeline(S, l, k, s, masks, iters, beta, pm.PM_FP64, bg, cap_b=0, cap_m=0)
+        P0.hash()
+        P0.select()
+        nbk, nmem = [int(v) for v in P0.b.n_out.cpu()]
+        del P0
+        pipes.append(pm.Pipeline(S, l, k, s, masks, iters, beta, pm.PM_FP64, bg, cap_b=nbk, cap_m=nmem))
+    for P in pipes[:2]:
+        P.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for P in pipes:
+        P.run()
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    solved = pcs = 0.0
+    for P, (inst, _) in zip(pipes, insts):
+        r = P.result()
+        ok, pc = score(r.get("consensus"), r.get("sites", [0] * len(inst.starts)), inst)
+        solved += ok
+        pcs += pc
+    plain = {"instances_per_s": round(count / (plain_ms / 1e3), 2), "ms": round(plain_ms, 3),
+             "solved": int(solved), "mean_pc": round(pcs / count, 4), "em": "fp64, all enriched buckets"}
+    del pipes
+    torch.cuda.empty_cache()
+
+    # ---- batched: all instances in one pass of launches, captured in a graph
+    B = pm.Batch(4, l, k, [i.seqs for i, _ in insts], [mk for _, mk in insts])
+    nbk, nmem = pm.size_batch(B, s)
+    BP = pm.BatchPipeline(B, s, iters, beta, pm.PM_F16X2, bg, cap_b=nbk, cap_m=nmem)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        BP.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        BP.run()
+    g.replay()
+    torch.cuda.synchronize()
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1) / reps
+    solved = pcs = 0.0
+    for r, (inst, _) in zip(BP.results(), insts):
+        ok, pc = score(r.get("consensus"), r.get("sites", [0] * len(inst.starts)), inst)
+        solved += ok
+        pcs += pc
+    batched = {"instances_per_s": round(count / (batch_ms / 1e3), 2), "ms": round(batch_ms, 3),
+               "solved": int(solved), "mean_pc": round(pcs / count, 4), "enriched_buckets": nbk,
+               "em": "split-f16 matrix cores, all enriched buckets, one HIP graph"}
+    return {"workload": f"(15,4) DNA: t=20, n=600, k=7, s=4, m=200, 5 EM iterations; {count} instances, seeds 0..{count - 1}",
+            "plain": plain, "batched": batched,
+            "speedup": round(batched["instances_per_s"] / plain["instances_per_s"], 3)}
 
 
 def cpu_baseline(inst, masks, cfg, bg, beta, nbk, budget):

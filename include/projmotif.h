@@ -60,6 +60,10 @@ extern "C" {
 #define PM_F16X2 2 /* DNA only: E- and M-step on FP16 matrix cores with every non-0/1
                       operand split into two FP16 halves (about 22 significant bits,
                       exact products, FP32 sums); log-sum-exp and J in FP64 */
+#define PM_F16 3   /* DNA only, the precision form: the same contractions with one FP16
+                      value per operand (11 significant bits), FP32 accumulation,
+                      log-sum-exp and J in FP64; results carry FP16-level error against
+                      FP64, which the caller measures and states */
 
 /* Encoded sequences.  Host fields describe the device arrays. */
 typedef struct pm_seqs {
@@ -174,7 +178,7 @@ int theta_init(int32_t alphabet, int32_t l, const uint32_t *profile, int64_t B,
  *   llr_out    device [B][iters+1] or NULL
  *   sites_out  device [B][t] int32 or NULL: argmax_a s_ia under theta^iters,
  *              first on ties
- *   precision  PM_FP64, PM_FP32 or PM_F16X2 (DNA) */
+ *   precision  PM_FP64, PM_FP32, PM_F16X2 or PM_F16 (the last two DNA only) */
 int em_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
               const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
               double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *stream);
@@ -185,6 +189,161 @@ int em_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *b
  * probability per column of that model (lowest code on ties), NUL-ended. */
 int em_best(const double *J, int64_t B, const int64_t *n_dev, int32_t iters, const double *theta,
             int32_t alphabet, int32_t l, int64_t *best_out, char *consensus_out, void *stream);
+
+/* ---- Batches: many independent instances in one set of launches ----
+ *
+ * A batch holds P instances that share the alphabet, l and k (one shape
+ * class); each has its own sequences (any t and n_i) and its own trials.  Trial items are numbered over the whole batch:
+ * instance p owns items first_item .. first_item + m - 1, instances in item
+ * order, so a bucket's `trial` field (the item) also names its instance.
+ * Keys of item j of instance p sit at key_base + (j - first_item) * x in the
+ * keys array, counts at j * |Sigma|^k; member numbers are window numbers
+ * within the instance.  Every pass below is the single-instance call of the
+ * same name run over all items, buckets or instances of the batch at once. */
+typedef struct pm_inst {
+    const int64_t *offsets;  /* device [t+1], as pm_seqs.offsets */
+    const uint32_t *packed;  /* device, pm_pack words of this instance */
+    int64_t n_total;         /* sum of the instance's n_i */
+    int64_t x;               /* windows at the batch's l: n_total - t (l - 1) */
+    int64_t key_base;        /* first key slot of the instance's first item */
+    int32_t t;               /* sequences */
+    int32_t n_min;           /* shortest sequence (>= l) */
+    int32_t m;               /* trials (items) of the instance, >= 1 */
+    int32_t first_item;      /* its first item */
+} pm_inst;
+
+typedef struct pm_batch {
+    int32_t alphabet;          /* PM_DNA or PM_PROTEIN */
+    int32_t l, k;              /* motif length and projection size of every instance */
+    int32_t P;                 /* instances, >= 1 */
+    int32_t items;             /* trial items: the sum of m */
+    const pm_inst *inst;       /* device [P] */
+    const pm_inst *inst_host;  /* host [P], the same contents (checks and launch sizes) */
+    const int32_t *item_inst;  /* device [items]: the instance of every item */
+} pm_batch;
+
+/* Checks a batch's host table (item numbering, x, limits); PM_OK or PM_EINVAL. */
+int pm_batch_check(const pm_batch *B);
+
+/* a3 + a4 over every item of a batch.  masks device [items]; keys device
+ * [sum_p m_p x_p] or NULL; counts device [items][|Sigma|^k] or NULL. */
+int projection_hash_batch(const pm_batch *B, const uint32_t *masks, uint32_t *keys, uint32_t *counts,
+                          uint32_t *status, void *stream);
+
+/* a5 over every item of a batch; same outputs as bucket_select with `trial`
+ * holding the item.  ws: pm_select_workspace(items, cap_buckets) bytes. */
+int bucket_select_batch(const pm_batch *B, const uint32_t *keys, const uint32_t *counts, uint32_t s,
+                        pm_bucket *buckets, int64_t cap_buckets, uint32_t *members, int64_t cap_members,
+                        int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status, void *stream);
+
+/* a6 (profiles) for the buckets of a batch. */
+int bucket_profile_batch(const pm_batch *B, const pm_bucket *buckets, const uint32_t *members,
+                         int64_t cap_members, int64_t Bcap, const int64_t *n_dev, uint32_t *profile,
+                         void *stream);
+
+/* Workspace bytes em_refine_batch needs for P instances. */
+size_t pm_em_batch_workspace(int32_t P);
+
+/* a7 - a10 for every bucket of a batch, each against its own instance
+ * (buckets as written by bucket_select_batch, ascending by item).  sites_out
+ * is [Bcap][t_max] with t_max the largest t of the batch (entries past the
+ * instance's t untouched).  The matrix-core form groups the buckets of one
+ * instance into workgroups and issues the instances largest first. */
+int em_refine_batch(const pm_batch *B, const pm_bucket *buckets, const double *theta0, const double *bg,
+                    int64_t Bcap, const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
+                    double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* a10 per instance: best_out device int64[P] (bucket index or -1),
+ * consensus_out device char[P][l+1]. */
+int em_best_batch(const pm_batch *B, const pm_bucket *buckets, const double *J, int64_t Bcap,
+                  const int64_t *n_dev, int32_t iters, const double *theta, int64_t *best_out,
+                  char *consensus_out, void *stream);
+
+/* ---- Learned bucket triage ----
+ *
+ * An addition to the paper's method, which refines every enriched bucket
+ * (Sec. 5.1): a small network scores every bucket from its profile, EM refines
+ * only the best-scored fraction of each instance, and an instance whose best
+ * refined objective per sequence stays below a threshold has all its other
+ * buckets refined too.  DNA only, l <= 21.
+ *
+ * Network: 87 inputs -> 256 -> 256 -> 1, ReLU after both hidden layers.  FP32
+ * parameters in one flat vector of PM_TRIAGE_PARAMS floats:
+ *   W1 [87][256], b1 [256], W2 [256][256], b2 [256], w3 [256][1], b3 [1]
+ * (W[i][o]: input i to output o).  Inputs of a bucket (feature index):
+ *   4p + c (p < 21, c < 4)  frequency of letter c in column p of the bucket's
+ *                           profile (profile / size; 0 for p >= l)
+ *   84  ln(size); 85  background entropy in bits; 86  the largest column
+ *   information content in bits, sum_c f log2(f / bg_c)
+ * each optionally standardised, (v - mu[i]) / sd[i]. */
+#define PM_TRIAGE_PARAMS 88577
+#define PM_TRIAGE_INPUTS 87
+
+/* Features of B buckets from their profiles (bucket_profile layout, DNA).
+ * bg device [4]; mu, sd device [87] or both NULL (raw features);
+ * feat device [B][87] FP32. */
+int triage_features(int32_t l, const uint32_t *profile, int64_t B, const int64_t *n_dev, const double *bg,
+                    const float *mu, const float *sd, float *feat, void *stream);
+
+/* Serving weights: BF16 matrix-core fragments of W1 and W2 plus FP32 biases
+ * and w3, pm_triage_packed_bytes() bytes of device memory, from the FP32
+ * parameter vector (device). */
+size_t pm_triage_packed_bytes(void);
+int triage_pack(const float *params, void *packed, void *stream);
+
+/* Scores of B buckets: BF16 inputs, weights and first hidden layer, FP32
+ * accumulation and second layer.  feat device [B][87]; score device [B]. */
+int triage_forward(const void *packed, const float *feat, int64_t B, const int64_t *n_dev, float *score,
+                   void *stream);
+
+/* One training step on N examples, all in FP32: forward, mean squared error
+ * against target, backward by the chain rule and, when lr > 0, one Adam
+ * update (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step counts from
+ * 1).  params, adam_m, adam_v device [PM_TRIAGE_PARAMS]; X device [N][87];
+ * target device [N]; loss_out device float[1] or NULL; grads_out device
+ * [PM_TRIAGE_PARAMS] or NULL (else kept in ws); ws pm_triage_workspace(N)
+ * bytes. */
+size_t pm_triage_workspace(int32_t N);
+int triage_train_step(float *params, float *adam_m, float *adam_v, int32_t step, const float *X,
+                      const float *target, int32_t N, float lr, float *loss_out, float *grads_out, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* Per instance (Bt: a batch, buckets ascending by item; NULL: the B buckets
+ * of one instance), keep every bucket whose score is at least the c-th
+ * largest score of the instance, c = max(1, ceil(frac n_instance)) (ties all
+ * kept), and compact the kept buckets, in order, with their theta^0 rows.
+ *   taken       device uint8 [B] or NULL: set to 1 for kept buckets (cleared first)
+ *   sel_buckets device [B], sel_theta0 device [B][|Sigma|][l],
+ *   sel_index   device int64 [B] or NULL: original index of each kept bucket
+ *   n_sel       device int64[1]: number kept
+ *   ws          pm_triage_select_workspace(P, B) bytes, kept for the fallback */
+size_t pm_triage_select_workspace(int32_t P, int64_t B);
+int triage_select(const pm_batch *Bt, const pm_bucket *buckets, const float *score, int64_t B,
+                  const int64_t *n_dev, double frac, const double *theta0, int32_t alphabet, int32_t l,
+                  uint8_t *taken, pm_bucket *sel_buckets, double *sel_theta0, int64_t *sel_index,
+                  int64_t *n_sel, void *ws, size_t ws_bytes, void *stream);
+
+/* Fallback after EM of the triaged buckets: an instance whose winner (best,
+ * device int64 [P], from em_best / em_best_batch on the triaged list) has
+ * J(theta^iters) / t below `threshold`, or that has no winner, gets all its
+ * buckets not taken by triage_select compacted as above; fell_back device
+ * int32 [P] or NULL.  Same ws as the preceding triage_select; t_single is t
+ * when Bt is NULL. */
+int triage_fallback_select(const pm_batch *Bt, const pm_bucket *buckets, int64_t B, const int64_t *n_dev,
+                           int32_t t_single, const int64_t *best, const double *J, int32_t iters,
+                           double threshold, const double *theta0, int32_t alphabet, int32_t l, uint8_t *taken,
+                           pm_bucket *sel_buckets, double *sel_theta0, int64_t *sel_index, int64_t *n_sel,
+                           int32_t *fell_back, void *ws, size_t ws_bytes, void *stream);
+
+/* Per instance, the better of the triaged winner (list 1) and the fallback
+ * winner (list 2, or best2 NULL): larger J(theta^iters), lower original bucket
+ * index on ties.  best_out device int64 [P]: original bucket index or -1;
+ * consensus_out device char [P][l+1] or NULL. */
+int triage_merge_best(int32_t P, int32_t alphabet, int32_t l, int32_t iters, const int64_t *best1,
+                      const int64_t *index1, const double *J1, const double *theta1, const int64_t *best2,
+                      const int64_t *index2, const double *J2, const double *theta2, int64_t *best_out,
+                      char *consensus_out, void *stream);
 
 /* The whole path on one instance, host in, host out, synchronous.  This
  * convenience entry point allocates and frees its own device buffers. */

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libprojmotif.so")
 PM_OK, PM_EINVAL, PM_ERANGE, PM_ECAPACITY, PM_EDEVICE = 0, -1, -2, -3, -4
 PM_STATUS_BAD_SYMBOL, PM_STATUS_BAD_MASK, PM_STATUS_CAPACITY = 1, 2, 4
 PM_DNA, PM_PROTEIN = 4, 20
-PM_FP64, PM_FP32, PM_F16X2 = 0, 1, 2
+PM_FP64, PM_FP32, PM_F16X2, PM_F16 = 0, 1, 2, 3
 
 DNA_CODE_ORDER = "ACTG"
 PROTEIN_CODE_ORDER = "ARNDCQEGHILKMFPSTWYV"
@@ -28,7 +28,14 @@ EXPORTS = [
     "pm_version", "pm_last_error", "pm_packed_words", "pm_pack", "pm_masks_from_seed",
     "pm_auto_params", "projection_hash", "pm_select_workspace", "bucket_select",
     "bucket_profile", "theta_init", "em_refine", "em_best", "projection_run",
+    "pm_batch_check", "projection_hash_batch", "bucket_select_batch", "bucket_profile_batch",
+    "pm_em_batch_workspace", "em_refine_batch", "em_best_batch",
+    "triage_features", "pm_triage_packed_bytes", "triage_pack", "triage_forward", "pm_triage_workspace",
+    "triage_train_step", "pm_triage_select_workspace", "triage_select", "triage_fallback_select",
+    "triage_merge_best",
 ]
+
+PM_TRIAGE_PARAMS, PM_TRIAGE_INPUTS = 88577, 87
 
 
 class PmError(RuntimeError):
@@ -46,6 +53,18 @@ class pm_seqs(C.Structure):
 class pm_bucket(C.Structure):
     _fields_ = [("trial", C.c_uint32), ("key", C.c_uint32), ("size", C.c_uint32),
                 ("first", C.c_uint32)]
+
+
+class pm_inst(C.Structure):
+    _fields_ = [("offsets", C.c_void_p), ("packed", C.c_void_p), ("n_total", C.c_int64),
+                ("x", C.c_int64), ("key_base", C.c_int64), ("t", C.c_int32), ("n_min", C.c_int32),
+                ("m", C.c_int32), ("first_item", C.c_int32)]
+
+
+class pm_batch(C.Structure):
+    _fields_ = [("alphabet", C.c_int32), ("l", C.c_int32), ("k", C.c_int32), ("P", C.c_int32),
+                ("items", C.c_int32), ("inst", C.c_void_p), ("inst_host", C.c_void_p),
+                ("item_inst", C.c_void_p)]
 
 
 class pm_problem(C.Structure):
@@ -99,6 +118,26 @@ def lib():
         "em_best": (C.c_int, [P, i64, P, i32, P, i32, i32, P, P, P]),
         "projection_run": (C.c_int, [C.POINTER(pm_problem), C.POINTER(pm_options),
                                      C.POINTER(pm_result)]),
+        "pm_batch_check": (C.c_int, [C.POINTER(pm_batch)]),
+        "projection_hash_batch": (C.c_int, [C.POINTER(pm_batch), P, P, P, P, P]),
+        "bucket_select_batch": (C.c_int, [C.POINTER(pm_batch), P, P, u32, P, i64, P, i64, P, P, sz,
+                                          P, P]),
+        "bucket_profile_batch": (C.c_int, [C.POINTER(pm_batch), P, P, i64, i64, P, P, P]),
+        "pm_em_batch_workspace": (sz, [i32]),
+        "em_refine_batch": (C.c_int, [C.POINTER(pm_batch), P, P, P, i64, P, i32, dbl, i32, P, P, P,
+                                      P, P, sz, P]),
+        "em_best_batch": (C.c_int, [C.POINTER(pm_batch), P, P, i64, P, i32, P, P, P, P]),
+        "triage_features": (C.c_int, [i32, P, i64, P, P, P, P, P, P]),
+        "pm_triage_packed_bytes": (sz, []),
+        "triage_pack": (C.c_int, [P, P, P]),
+        "triage_forward": (C.c_int, [P, P, i64, P, P, P]),
+        "pm_triage_workspace": (sz, [i32]),
+        "triage_train_step": (C.c_int, [P, P, P, i32, P, P, i32, C.c_float, P, P, P, sz, P]),
+        "pm_triage_select_workspace": (sz, [i32, i64]),
+        "triage_select": (C.c_int, [C.c_void_p, P, P, i64, P, dbl, P, i32, i32, P, P, P, P, P, P, sz, P]),
+        "triage_fallback_select": (C.c_int, [C.c_void_p, P, i64, P, i32, P, P, i32, dbl, P, i32, i32, P, P,
+                                             P, P, P, P, P, sz, P]),
+        "triage_merge_best": (C.c_int, [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -195,6 +234,100 @@ def em_refine(S, l, theta0, bg, B, n_dev, iters, beta, precision, theta_out, J_o
 def em_best(J, B, n_dev, iters, theta, alphabet, l, best_out, consensus_out=None, stream=None):
     _check(lib().em_best(_ptr(J), B, _ptr(n_dev), iters, _ptr(theta), alphabet, l, _ptr(best_out),
                          _ptr(consensus_out), _stream(stream)))
+
+
+def pm_batch_check(B: "Batch"):
+    _check(lib().pm_batch_check(C.byref(B.c)))
+
+
+def projection_hash_batch(B: "Batch", masks, keys=None, counts=None, status=None, stream=None):
+    _check(lib().projection_hash_batch(C.byref(B.c), _ptr(masks), _ptr(keys), _ptr(counts), _ptr(status),
+                                       _stream(stream)))
+
+
+def bucket_select_batch(B, keys, counts, s, buckets, cap_buckets, members, cap_members, n_out, ws,
+                        ws_bytes, status=None, stream=None):
+    _check(lib().bucket_select_batch(C.byref(B.c), _ptr(keys), _ptr(counts), s, _ptr(buckets), cap_buckets,
+                                     _ptr(members), cap_members, _ptr(n_out), _ptr(ws), ws_bytes,
+                                     _ptr(status), _stream(stream)))
+
+
+def bucket_profile_batch(B, buckets, members, cap_members, Bcap, n_dev, profile, stream=None):
+    _check(lib().bucket_profile_batch(C.byref(B.c), _ptr(buckets), _ptr(members), cap_members, Bcap,
+                                      _ptr(n_dev), _ptr(profile), _stream(stream)))
+
+
+def pm_em_batch_workspace(P: int) -> int:
+    return int(lib().pm_em_batch_workspace(P))
+
+
+def em_refine_batch(B, buckets, theta0, bg, Bcap, n_dev, iters, beta, precision, theta_out, J_out,
+                    llr_out=None, sites_out=None, ws=None, ws_bytes=0, stream=None):
+    _check(lib().em_refine_batch(C.byref(B.c), _ptr(buckets), _ptr(theta0), _ptr(bg), Bcap, _ptr(n_dev),
+                                 iters, beta, precision, _ptr(theta_out), _ptr(J_out), _ptr(llr_out),
+                                 _ptr(sites_out), _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def em_best_batch(B, buckets, J, Bcap, n_dev, iters, theta, best_out, consensus_out=None, stream=None):
+    _check(lib().em_best_batch(C.byref(B.c), _ptr(buckets), _ptr(J), Bcap, _ptr(n_dev), iters, _ptr(theta),
+                               _ptr(best_out), _ptr(consensus_out), _stream(stream)))
+
+
+def _batch_ptr(B):
+    return None if B is None else C.addressof(B.c)
+
+
+def triage_features(l, profile, B, n_dev, bg, mu, sd, feat, stream=None):
+    _check(lib().triage_features(l, _ptr(profile), B, _ptr(n_dev), _ptr(bg), _ptr(mu), _ptr(sd), _ptr(feat),
+                                 _stream(stream)))
+
+
+def pm_triage_packed_bytes() -> int:
+    return int(lib().pm_triage_packed_bytes())
+
+
+def triage_pack(params, packed, stream=None):
+    _check(lib().triage_pack(_ptr(params), _ptr(packed), _stream(stream)))
+
+
+def triage_forward(packed, feat, B, n_dev, score, stream=None):
+    _check(lib().triage_forward(_ptr(packed), _ptr(feat), B, _ptr(n_dev), _ptr(score), _stream(stream)))
+
+
+def pm_triage_workspace(N: int) -> int:
+    return int(lib().pm_triage_workspace(N))
+
+
+def triage_train_step(params, adam_m, adam_v, step, X, target, N, lr, loss_out=None, grads_out=None, ws=None,
+                      ws_bytes=0, stream=None):
+    _check(lib().triage_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), step, _ptr(X), _ptr(target), N, lr,
+                                   _ptr(loss_out), _ptr(grads_out), _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def pm_triage_select_workspace(P: int, B: int) -> int:
+    return int(lib().pm_triage_select_workspace(P, B))
+
+
+def triage_select(Bt, buckets, score, B, n_dev, frac, theta0, alphabet, l, taken, sel_buckets, sel_theta0,
+                  sel_index, n_sel, ws, ws_bytes, stream=None):
+    _check(lib().triage_select(_batch_ptr(Bt), _ptr(buckets), _ptr(score), B, _ptr(n_dev), frac, _ptr(theta0),
+                               alphabet, l, _ptr(taken), _ptr(sel_buckets), _ptr(sel_theta0), _ptr(sel_index),
+                               _ptr(n_sel), _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def triage_fallback_select(Bt, buckets, B, n_dev, t_single, best, J, iters, threshold, theta0, alphabet, l, taken,
+                           sel_buckets, sel_theta0, sel_index, n_sel, fell_back, ws, ws_bytes, stream=None):
+    _check(lib().triage_fallback_select(_batch_ptr(Bt), _ptr(buckets), B, _ptr(n_dev), t_single, _ptr(best), _ptr(J),
+                                        iters, threshold, _ptr(theta0), alphabet, l, _ptr(taken), _ptr(sel_buckets),
+                                        _ptr(sel_theta0), _ptr(sel_index), _ptr(n_sel), _ptr(fell_back), _ptr(ws),
+                                        ws_bytes, _stream(stream)))
+
+
+def triage_merge_best(P, alphabet, l, iters, best1, index1, J1, theta1, best2, index2, J2, theta2, best_out,
+                      consensus_out=None, stream=None):
+    _check(lib().triage_merge_best(P, alphabet, l, iters, _ptr(best1), _ptr(index1), _ptr(J1), _ptr(theta1),
+                                   _ptr(best2), _ptr(index2), _ptr(J2), _ptr(theta2), _ptr(best_out),
+                                   _ptr(consensus_out), _stream(stream)))
 
 
 def projection_run(seqs: Sequence[str], alphabet: int, l: int, d: int = 0, k: int = 0, s: int = 0,
@@ -357,4 +490,299 @@ class Pipeline:
             out["sites"] = b.sites[best].cpu().numpy()
             out["J"] = float(b.J[best, -1].item())
             out["bucket"] = b.buckets[best].cpu().numpy().view("uint32")
+        return out
+
+
+# ----------------------------------------------------------------- batches
+class Batch:
+    """Many instances of one shape class (alphabet, l, k) on the GPU.
+
+    Every instance's ASCII is padded with code-0 letters to a whole number of
+    packed words plus the four padding words pm_pack appends, so one pm_pack
+    over the concatenation gives each instance its own aligned, zero-padded
+    packed region; offsets are per instance (local symbol numbers)."""
+
+    def __init__(self, alphabet: int, l: int, k: int, instances: Sequence[Sequence[str]], masks,
+                 device="cuda", stream=None):
+        import numpy as np
+        import torch
+        self.alphabet, self.l, self.k = alphabet, l, k
+        self.P = len(instances)
+        per = 16 if alphabet == 4 else 6
+        masks = [np.ascontiguousarray(mk, dtype=np.uint32) for mk in masks]
+        if len(masks) != self.P:
+            raise ValueError("one mask table per instance")
+        chunks, offs, word_base, off_base = [], [], [], []
+        wb = ob = 0
+        self.t, self.x, self.n_total, self.m = [], [], [], []
+        for seqs, mk in zip(instances, masks):
+            lens = [len(q) for q in seqs]
+            n = sum(lens)
+            nw = pm_packed_words(alphabet, n)
+            chunks.append("".join(seqs) + "A" * (nw * per - n))
+            o = np.zeros(len(seqs) + 1, dtype=np.int64)
+            o[1:] = np.cumsum(lens)
+            offs.append(o)
+            word_base.append(wb)
+            off_base.append(ob)
+            wb += nw
+            ob += len(seqs) + 1
+            self.t.append(len(seqs))
+            self.n_total.append(n)
+            self.x.append(n - len(seqs) * (l - 1))
+            self.m.append(len(mk))
+        self.n_min = [min(len(q) for q in seqs) for seqs in instances]
+        raw = np.frombuffer("".join(chunks).encode("ascii"), dtype=np.uint8)
+        self.ascii = torch.from_numpy(raw.copy()).to(device)
+        self.packed = torch.zeros(pm_packed_words(alphabet, len(raw)), dtype=torch.int32, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        pm_pack(alphabet, self.ascii, len(raw), self.packed, self.status, stream)
+        self.offsets = torch.from_numpy(np.concatenate(offs)).to(device)
+        self.items = int(sum(self.m))
+        self.masks = torch.from_numpy(np.concatenate(masks).view(np.int32)).to(device)
+        first, key = 0, 0
+        tab = (pm_inst * self.P)()
+        item_inst = np.zeros(self.items, dtype=np.int32)
+        self.first_item, self.key_base = [], []
+        for p in range(self.P):
+            e = tab[p]
+            e.offsets = self.offsets.data_ptr() + 8 * off_base[p]
+            e.packed = self.packed.data_ptr() + 4 * word_base[p]
+            e.n_total, e.x, e.key_base = self.n_total[p], self.x[p], key
+            e.t, e.n_min, e.m, e.first_item = self.t[p], self.n_min[p], self.m[p], first
+            item_inst[first:first + self.m[p]] = p
+            self.first_item.append(first)
+            self.key_base.append(key)
+            first += self.m[p]
+            key += self.m[p] * self.x[p]
+        self.keys_total = key
+        self.tab_host = tab
+        self.tab = torch.frombuffer(bytearray(bytes(tab)), dtype=torch.uint8).to(device)
+        self.item_inst = torch.from_numpy(item_inst).to(device)
+        self.c = pm_batch(alphabet, l, k, self.P, self.items, self.tab.data_ptr(),
+                          C.cast(tab, C.c_void_p), self.item_inst.data_ptr())
+        pm_batch_check(self)
+
+    @property
+    def t_max(self) -> int:
+        return max(self.t)
+
+
+class BatchPipeline:
+    """All instances of a Batch through the whole path in one set of launches
+    per step (hash, select, profiles, theta^0, EM, per-instance best), with
+    fixed buffers, so the pass can be captured in a HIP graph."""
+
+    def __init__(self, B: Batch, s: int, iters: int, beta: float, precision: int, bg, cap_b: int,
+                 cap_m: int, device="cuda"):
+        import numpy as np
+        import torch
+        self.B, self.s, self.iters, self.beta, self.precision = B, s, iters, beta, precision
+        A, l = B.alphabet, B.l
+        self.nb = A ** B.k
+        dev = device
+        self.bg = torch.as_tensor(np.asarray(bg, dtype=np.float64), device=dev)
+        self.ws_bytes = pm_select_workspace(B.items, cap_b)
+        self.em_ws_bytes = pm_em_batch_workspace(B.P)
+        cb = max(cap_b, 1)
+        z = lambda *shape, dt=torch.int32: torch.zeros(*shape, dtype=dt, device=dev)
+        self.b = PassBuffers(
+            keys=z(B.keys_total), counts=z(B.items, self.nb), status=z(1), n_out=z(2, dt=torch.int64),
+            buckets=z(cb, 4), members=z(max(cap_m, 1)), ws=z((self.ws_bytes + 3) // 4),
+            profile=z(cb, A, l), theta0=z(cb, A, l, dt=torch.float64), theta=z(cb, A, l, dt=torch.float64),
+            J=z(cb, iters + 1, dt=torch.float64), llr=z(cb, iters + 1, dt=torch.float64),
+            sites=z(cb, B.t_max), best=z(B.P, dt=torch.int64),
+            consensus=torch.zeros(B.P, l + 1, dtype=torch.uint8, device=dev), cap_b=cap_b, cap_m=cap_m)
+        self.em_ws = z((self.em_ws_bytes + 3) // 4)
+
+    def hash(self, stream=None):
+        b = self.b
+        projection_hash_batch(self.B, self.B.masks, b.keys, b.counts, b.status, stream)
+
+    def select(self, stream=None):
+        b = self.b
+        bucket_select_batch(self.B, b.keys, b.counts, self.s, b.buckets, b.cap_b, b.members, b.cap_m,
+                            b.n_out, b.ws, self.ws_bytes, b.status, stream)
+
+    def profile(self, stream=None):
+        b = self.b
+        bucket_profile_batch(self.B, b.buckets, b.members, b.cap_m, b.cap_b, b.n_out, b.profile, stream)
+        theta_init(self.B.alphabet, self.B.l, b.profile, b.cap_b, b.n_out, self.bg, self.beta, b.theta0,
+                   stream)
+
+    def refine(self, stream=None):
+        b = self.b
+        em_refine_batch(self.B, b.buckets, b.theta0, self.bg, b.cap_b, b.n_out, self.iters, self.beta,
+                        self.precision, b.theta, b.J, b.llr, b.sites, self.em_ws, self.em_ws_bytes, stream)
+
+    def best(self, stream=None):
+        b = self.b
+        em_best_batch(self.B, b.buckets, b.J, b.cap_b, b.n_out, self.iters, b.theta, b.best, b.consensus,
+                      stream)
+
+    def run(self, stream=None):
+        self.hash(stream)
+        self.select(stream)
+        self.profile(stream)
+        self.refine(stream)
+        self.best(stream)
+
+    def results(self) -> list:
+        """Per-instance answers (synchronises)."""
+        b, l = self.b, self.B.l
+        best = b.best.cpu().numpy()
+        cons = b.consensus.cpu().numpy()
+        J = b.J[:, -1].cpu().numpy()
+        sites = b.sites.cpu().numpy()
+        out = []
+        for p in range(self.B.P):
+            r = dict(best=int(best[p]))
+            if best[p] >= 0:
+                r["consensus"] = bytes(cons[p, :l]).decode()
+                r["J"] = float(J[best[p]])
+                r["sites"] = sites[best[p], : self.B.t[p]].copy()
+            out.append(r)
+        return out
+
+
+def size_batch(B: Batch, s: int, device="cuda"):
+    """Bucket and member counts of a batch (one hash + select pass with zero
+    capacities; synchronises)."""
+    P0 = BatchPipeline(B, s, 0, 1.0, PM_FP64, [1.0 / B.alphabet] * B.alphabet, 0, 0, device)
+    P0.hash()
+    P0.select()
+    nb_, nm_ = [int(v) for v in P0.b.n_out.cpu()]
+    return nb_, nm_
+
+
+# ----------------------------------------------------------------- triage
+class Triage:
+    """A trained triage network on the GPU: FP32 parameters, their packed
+    BF16 serving form, the feature standardisation and the fallback
+    threshold (best J(theta^iters) per sequence)."""
+
+    def __init__(self, params, mu, sd, threshold: float, device="cuda", meta=None):
+        import numpy as np
+        import torch
+        self.params = torch.as_tensor(np.asarray(params, dtype=np.float32), device=device).contiguous()
+        assert self.params.numel() == PM_TRIAGE_PARAMS
+        self.mu = torch.as_tensor(np.asarray(mu, dtype=np.float32), device=device).contiguous()
+        self.sd = torch.as_tensor(np.asarray(sd, dtype=np.float32), device=device).contiguous()
+        self.threshold = float(threshold)
+        self.meta = dict(meta or {})
+        self.packed = torch.zeros(pm_triage_packed_bytes(), dtype=torch.uint8, device=device)
+        self.repack()
+
+    def repack(self, stream=None):
+        triage_pack(self.params, self.packed, stream)
+
+    @classmethod
+    def load(cls, path: str, device="cuda"):
+        import json
+        import numpy as np
+        with np.load(path, allow_pickle=False) as z:
+            meta = json.loads(str(z["meta"]))
+            return cls(z["params"], z["mu"], z["sd"], float(z["threshold"]), device, meta)
+
+    def save(self, path: str):
+        import json
+        import numpy as np
+        np.savez(path, params=self.params.cpu().numpy(), mu=self.mu.cpu().numpy(), sd=self.sd.cpu().numpy(),
+                 threshold=np.float64(self.threshold), meta=json.dumps(self.meta))
+
+    def threshold_for(self, l: int) -> float:
+        """Fallback threshold for motif length l: the per-length value from
+        training when there is one, else the pooled one."""
+        per = self.meta.get("thresholds_by_l", {})
+        return float(per.get(str(l), per.get(l, self.threshold)))
+
+    def score(self, l, profile, B, n_dev, bg, feat, score, stream=None):
+        triage_features(l, profile, B, n_dev, bg, self.mu, self.sd, feat, stream)
+        triage_forward(self.packed, feat, B, n_dev, score, stream)
+
+
+def default_triage_path() -> str:
+    return os.path.join(PKG, "triage_weights.npz")
+
+
+class TriagedBatchPipeline(BatchPipeline):
+    """BatchPipeline with learned triage: after theta^0, the network scores
+    every bucket, EM refines the top `frac` of each instance, instances whose
+    winner is weak fall back to refining all their other buckets, and the
+    better winner is kept.  All on device, no host synchronisation."""
+
+    def __init__(self, B: Batch, s: int, iters: int, beta: float, precision: int, bg, cap_b: int, cap_m: int,
+                 triage: Triage, frac: float = 0.05, device="cuda"):
+        import torch
+        super().__init__(B, s, iters, beta, precision, bg, cap_b, cap_m, device)
+        self.tri, self.frac = triage, frac
+        self.threshold = triage.threshold_for(B.l)
+        A, l = B.alphabet, B.l
+        cb = max(cap_b, 1)
+        z = lambda *shape, dt=torch.int32: torch.zeros(*shape, dtype=dt, device=device)
+        self.feat = z(cb, PM_TRIAGE_INPUTS, dt=torch.float32)
+        self.score_buf = z(cb, dt=torch.float32)
+        self.taken = z(cb, dt=torch.uint8)
+        self.sel_ws_bytes = pm_triage_select_workspace(B.P, cb)
+        self.sel_ws = z((self.sel_ws_bytes + 7) // 8, dt=torch.int64)
+        self.fell_back = z(B.P)
+        self.lists = []
+        for _ in range(2):
+            self.lists.append(dict(
+                buckets=z(cb, 4), theta0=z(cb, A, l, dt=torch.float64), index=z(cb, dt=torch.int64),
+                n=z(1, dt=torch.int64), theta=z(cb, A, l, dt=torch.float64), J=z(cb, iters + 1, dt=torch.float64),
+                llr=z(cb, iters + 1, dt=torch.float64), sites=z(cb, B.t_max), best=z(B.P, dt=torch.int64)))
+
+    def _refine_list(self, L, stream):
+        em_refine_batch(self.B, L["buckets"], L["theta0"], self.bg, self.b.cap_b, L["n"], self.iters, self.beta,
+                        self.precision, L["theta"], L["J"], L["llr"], L["sites"], self.em_ws, self.em_ws_bytes,
+                        stream)
+        em_best_batch(self.B, L["buckets"], L["J"], self.b.cap_b, L["n"], self.iters, L["theta"], L["best"], None,
+                      stream)
+
+    def triage(self, stream=None):
+        b, B = self.b, self.B
+        self.tri.score(B.l, b.profile, b.cap_b, b.n_out, self.bg, self.feat, self.score_buf, stream)
+        L1, L2 = self.lists
+        triage_select(B, b.buckets, self.score_buf, b.cap_b, b.n_out, self.frac, b.theta0, B.alphabet, B.l,
+                      self.taken, L1["buckets"], L1["theta0"], L1["index"], L1["n"], self.sel_ws, self.sel_ws_bytes,
+                      stream)
+        self._refine_list(L1, stream)
+        triage_fallback_select(B, b.buckets, b.cap_b, b.n_out, 0, L1["best"], L1["J"], self.iters,
+                               self.threshold, b.theta0, B.alphabet, B.l, self.taken, L2["buckets"], L2["theta0"],
+                               L2["index"], L2["n"], self.fell_back, self.sel_ws, self.sel_ws_bytes, stream)
+        self._refine_list(L2, stream)
+        triage_merge_best(B.P, B.alphabet, B.l, self.iters, L1["best"], L1["index"], L1["J"], L1["theta"],
+                          L2["best"], L2["index"], L2["J"], L2["theta"], b.best, b.consensus, stream)
+
+    def run(self, stream=None):
+        self.hash(stream)
+        self.select(stream)
+        self.profile(stream)
+        self.triage(stream)
+
+    def results(self) -> list:
+        """Per-instance answers (synchronises); sites from the list that won."""
+        import numpy as np
+        b, l = self.b, self.B.l
+        best = b.best.cpu().numpy()
+        cons = b.consensus.cpu().numpy()
+        L1, L2 = self.lists
+        i1, i2 = L1["index"].cpu().numpy(), L2["index"].cpu().numpy()
+        bb1, bb2 = L1["best"].cpu().numpy(), L2["best"].cpu().numpy()
+        fb = self.fell_back.cpu().numpy()
+        n1, n2 = int(L1["n"].item()), int(L2["n"].item())
+        out = []
+        for p in range(self.B.P):
+            r = dict(best=int(best[p]), fell_back=bool(fb[p]))
+            if best[p] >= 0:
+                r["consensus"] = bytes(cons[p, :l]).decode()
+                if bb1[p] >= 0 and i1[bb1[p]] == best[p]:
+                    L, w = L1, bb1[p]
+                else:
+                    L, w = L2, bb2[p]
+                r["J"] = float(L["J"][w, -1].item())
+                r["sites"] = L["sites"][w, : self.B.t[p]].cpu().numpy()
+            out.append(r)
+        self.refined = n1 + n2
         return out

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -57,9 +58,62 @@ int check_seqs(const pm_seqs *S, int l)
     return PM_OK;
 }
 
+pm_inst inst_of(const pm_seqs *S, int l)
+{
+    pm_inst I{};
+    I.offsets = S->offsets;
+    I.packed = S->packed;
+    I.n_total = S->n_total;
+    I.x = num_windows(S, l);
+    I.key_base = 0;
+    I.t = S->t;
+    I.n_min = S->n_min;
+    I.m = 0;
+    I.first_item = 0;
+    return I;
+}
+
+int check_batch(const pm_batch *B, BatchInfo *info)
+{
+    if (!B) return fail(PM_EINVAL, "batch is NULL");
+    if (B->alphabet != 4 && B->alphabet != 20) return fail(PM_EINVAL, "alphabet must be 4 or 20");
+    if (B->l < 1 || B->l > 32) return fail(PM_EINVAL, "need 1 <= l <= 32 (l=%d)", B->l);
+    if (B->k < 1 || B->k > B->l) return fail(PM_EINVAL, "need 1 <= k <= l (k=%d, l=%d)", B->k, B->l);
+    if (B->P < 1 || B->items < 1) return fail(PM_EINVAL, "need P >= 1 and items >= 1");
+    if (!B->inst || !B->inst_host || !B->item_inst) return fail(PM_EINVAL, "batch tables are NULL");
+    BatchInfo in{};
+    int64_t item = 0, key = 0;
+    for (int p = 0; p < B->P; ++p) {
+        const pm_inst &I = B->inst_host[p];
+        if (I.t < 1 || !I.offsets || !I.packed) return fail(PM_EINVAL, "instance %d: bad sequences", p);
+        if (I.n_min < B->l) return fail(PM_EINVAL, "instance %d: a sequence is shorter than l", p);
+        if (I.n_total < (int64_t)I.n_min * I.t || I.n_total >= (1ll << 31))
+            return fail(PM_EINVAL, "instance %d: bad n_total", p);
+        if (I.x != I.n_total - (int64_t)I.t * (B->l - 1)) return fail(PM_EINVAL, "instance %d: x != n_total - t (l - 1)", p);
+        if (I.m < 1) return fail(PM_EINVAL, "instance %d: m must be >= 1", p);
+        if (I.first_item != item) return fail(PM_EINVAL, "instance %d: first_item must be %lld", p, (long long)item);
+        if (I.key_base != key) return fail(PM_EINVAL, "instance %d: key_base must be %lld", p, (long long)key);
+        item += I.m;
+        key += (int64_t)I.m * I.x;
+        in.t_max = std::max(in.t_max, I.t);
+        in.nw_max = std::max<int64_t>(in.nw_max, pm_packed_words(B->alphabet, I.n_total));
+        in.x_max = std::max(in.x_max, I.x);
+    }
+    if (item != B->items) return fail(PM_EINVAL, "items (%d) is not the sum of m (%lld)", B->items, (long long)item);
+    in.keys_total = key;
+    if (info) *info = in;
+    return PM_OK;
+}
+
 }  // namespace pm
 
 using namespace pm;
+
+extern "C" int pm_batch_check(const pm_batch *B)
+{
+    clear_error();
+    return check_batch(B, nullptr);
+}
 
 extern "C" const char *pm_version(void) { return "projmotif 0.1 (gfx950)"; }
 

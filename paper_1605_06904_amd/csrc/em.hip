@@ -16,8 +16,10 @@
 namespace pm {
 
 struct EmArgs {
-    const uint32_t *packed;
-    const int64_t *offsets;
+    pm_inst one;                // the instance, when inst is NULL
+    const pm_inst *inst;        // batch: instance table, or NULL
+    const int32_t *item_inst;   // batch: instance of every trial item
+    const pm_bucket *buckets;   // batch: the models' buckets (their items)
     const double *theta0;
     const double *bg;
     const int64_t *n_dev;
@@ -26,10 +28,11 @@ struct EmArgs {
     double *llr;
     int32_t *sites;
     int64_t B;
-    int t, l, iters;
+    int l, iters;
+    int site_stride;  // sites row length (t, or the largest t of a batch)
     double beta;
-    int seq_words;  // packed words staged in LDS (0: read from global)
-    int stage_off;
+    int seq_cap;      // LDS words reserved for the packed input (0: read from global)
+    int off_cap;      // LDS offsets reserved (0: read from global)
 };
 
 constexpr int kEmThreads = 256;
@@ -97,19 +100,21 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
     __shared__ double colsum[32];
     extern __shared__ __align__(16) uint32_t dyn[];
     uint32_t *seq = dyn;
-    int64_t *offs = reinterpret_cast<int64_t *>(dyn + ((a.seq_words + 1) & ~1));
+    int64_t *offs = reinterpret_cast<int64_t *>(dyn + ((a.seq_cap + 1) & ~1));
 
+    const pm_inst I = a.inst ? a.inst[a.item_inst[a.buckets[b].trial]] : a.one;
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
-    const int l = a.l, t = a.t, AL = A * l;
+    const int l = a.l, t = I.t, AL = A * l;
     const double beta = a.beta;
+    const int seq_words = a.seq_cap ? (int)(A == 4 ? (I.n_total + 15) / 16 + 4 : (I.n_total + 5) / 6 + 4) : 0;
 
     for (int i = tid; i < AL; i += kEmThreads) th[i] = a.theta0[b * AL + i];
-    for (int i = tid; i < a.seq_words; i += kEmThreads) seq[i] = a.packed[i];
-    if (a.stage_off)
-        for (int i = tid; i <= t; i += kEmThreads) offs[i] = a.offsets[i];
+    for (int i = tid; i < seq_words; i += kEmThreads) seq[i] = I.packed[i];
+    if (a.off_cap)
+        for (int i = tid; i <= t; i += kEmThreads) offs[i] = I.offsets[i];
     __syncthreads();
-    const uint32_t *W = a.seq_words ? seq : a.packed;
-    const int64_t *O = a.stage_off ? offs : a.offsets;
+    const uint32_t *W = a.seq_cap ? seq : I.packed;
+    const int64_t *O = a.off_cap ? offs : I.offsets;
 
     for (int it = 0; it <= a.iters; ++it) {
         const bool last = it == a.iters;
@@ -150,7 +155,7 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
                 if (a.sites) {
                     const T bm = wave_max(bv);
                     const int64_t cand = wave_min_i64(bv == bm ? ba : INT64_MAX);
-                    if (lane == 0) a.sites[b * t + i] = (int32_t)cand;
+                    if (lane == 0) a.sites[b * a.site_stride + i] = (int32_t)cand;
                 }
             } else {
                 T *ac = acc[wv];
@@ -209,18 +214,39 @@ static int launch_em(const EmArgs &a, size_t lds, hipStream_t st)
 }
 
 // ---------------------------------------------------------------- a10
+// one workgroup per instance (inst != NULL: a batch, whose buckets ascend by
+// item) or a single workgroup over all buckets
 __global__ void __launch_bounds__(256) k_best(const double *J, int64_t B, const int64_t *n_dev, int iters,
                                               const double *theta, int A, int l, int64_t *best_out,
-                                              char *cons)
+                                              char *cons, const pm_inst *inst, const pm_bucket *buckets)
 {
     __shared__ double rv[4];
     __shared__ int64_t ri[4];
     __shared__ int64_t best_s;
     int64_t nvalid = n_dev ? *n_dev : B;
     if (nvalid > B) nvalid = B;
+    int64_t lo_b = 0, hi_b = nvalid;
+    if (inst) {
+        const int p = blockIdx.x;
+        int64_t r[2];
+        for (int side = 0; side < 2; ++side) {
+            const int64_t item = (int64_t)inst[p].first_item + (side ? inst[p].m : 0);
+            int64_t lo = 0, hi = nvalid;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if ((int64_t)buckets[mid].trial < item) lo = mid + 1;
+                else hi = mid;
+            }
+            r[side] = lo;
+        }
+        lo_b = r[0];
+        hi_b = r[1];
+        best_out += p;
+        if (cons) cons += (int64_t)p * (l + 1);
+    }
     double bv = -INFINITY;
     int64_t bi = INT64_MAX;
-    for (int64_t b = threadIdx.x; b < nvalid; b += 256) {
+    for (int64_t b = lo_b + threadIdx.x; b < hi_b; b += 256) {
         const double v = J[b * (iters + 1) + iters];
         if (v == v && (bi == INT64_MAX || v > bv)) {
             bv = v;
@@ -275,6 +301,29 @@ __global__ void __launch_bounds__(256) k_best(const double *J, int64_t B, const 
 
 using namespace pm;
 
+static int check_em_args(int A, int64_t B, int32_t iters, double beta, int32_t precision, const double *theta0,
+                         const double *bg, const double *theta_out, const double *J_out)
+{
+    if (B < 0 || iters < 0 || beta < 0) return fail(PM_EINVAL, "need B >= 0, iters >= 0, beta >= 0");
+    if (precision != PM_FP64 && precision != PM_FP32 && precision != PM_F16X2 && precision != PM_F16)
+        return fail(PM_EINVAL, "unknown precision %d", precision);
+    if ((precision == PM_F16X2 || precision == PM_F16) && A != 4)
+        return fail(PM_EINVAL, "the matrix-core forms (PM_F16X2, PM_F16) are for DNA");
+    if (B > 0x7fffffff) return fail(PM_ERANGE, "B above 2^31 - 1");
+    if (B > 0 && (!theta0 || !bg || !theta_out || !J_out)) return fail(PM_EINVAL, "NULL buffer");
+    return PM_OK;
+}
+
+static int vec_launch(EmArgs &a, int A, int32_t precision, int64_t nw_max, int t_max, hipStream_t st)
+{
+    a.seq_cap = nw_max * 4 <= 48 * 1024 ? (int)nw_max : 0;
+    a.off_cap = (t_max + 1) * 8 <= 8 * 1024 ? t_max + 1 : 0;
+    const size_t lds = ((a.seq_cap + 1) & ~1) * 4 + (size_t)a.off_cap * 8;
+    if (A == 4)
+        return precision == PM_FP64 ? launch_em<double, 4>(a, lds, st) : launch_em<float, 4>(a, lds, st);
+    return precision == PM_FP64 ? launch_em<double, 20>(a, lds, st) : launch_em<float, 20>(a, lds, st);
+}
+
 extern "C" int em_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
                          const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
                          double *theta_out, double *J_out, double *llr_out, int32_t *sites_out,
@@ -283,16 +332,14 @@ extern "C" int em_refine(const pm_seqs *S, int32_t l, const double *theta0, cons
     clear_error();
     int rc = check_seqs(S, l);
     if (rc) return rc;
-    if (B < 0 || iters < 0 || beta < 0) return fail(PM_EINVAL, "need B >= 0, iters >= 0, beta >= 0");
-    if (precision != PM_FP64 && precision != PM_FP32 && precision != PM_F16X2)
-        return fail(PM_EINVAL, "unknown precision %d", precision);
-    if (precision == PM_F16X2 && S->alphabet != 4) return fail(PM_EINVAL, "PM_F16X2 is for DNA");
+    if ((rc = check_em_args(S->alphabet, B, iters, beta, precision, theta0, bg, theta_out, J_out))) return rc;
     if (B == 0) return PM_OK;
-    if (B > 0x7fffffff) return fail(PM_ERANGE, "B above 2^31 - 1");
-    if (!theta0 || !bg || !theta_out || !J_out) return fail(PM_EINVAL, "NULL buffer");
+    hipStream_t st = as_stream(stream);
+    if (precision == PM_F16X2 || precision == PM_F16)
+        return em_refine_mfma(S, l, theta0, bg, B, n_dev, iters, beta, theta_out, J_out, llr_out, sites_out,
+                              precision == PM_F16X2, st);
     EmArgs a{};
-    a.packed = S->packed;
-    a.offsets = S->offsets;
+    a.one = inst_of(S, l);
     a.theta0 = theta0;
     a.bg = bg;
     a.n_dev = n_dev;
@@ -301,21 +348,50 @@ extern "C" int em_refine(const pm_seqs *S, int32_t l, const double *theta0, cons
     a.llr = llr_out;
     a.sites = sites_out;
     a.B = B;
-    a.t = S->t;
     a.l = l;
     a.iters = iters;
+    a.site_stride = S->t;
     a.beta = beta;
-    if (precision == PM_F16X2)
-        return em_refine_mfma(S, l, theta0, bg, B, n_dev, iters, beta, theta_out, J_out, llr_out, sites_out,
-                              as_stream(stream));
-    const int64_t nw = pm_packed_words(S->alphabet, S->n_total);
-    a.seq_words = nw * 4 <= 48 * 1024 ? (int)nw : 0;
-    a.stage_off = (S->t + 1) * 8 <= 8 * 1024;
-    const size_t lds = ((a.seq_words + 1) & ~1) * 4 + (a.stage_off ? (S->t + 1) * 8 : 0);
+    return vec_launch(a, S->alphabet, precision, pm_packed_words(S->alphabet, S->n_total), S->t, st);
+}
+
+extern "C" size_t pm_em_batch_workspace(int32_t P) { return em_batch_workspace(P); }
+
+extern "C" int em_refine_batch(const pm_batch *Bt, const pm_bucket *buckets, const double *theta0, const double *bg,
+                               int64_t B, const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
+                               double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *ws,
+                               size_t ws_bytes, void *stream)
+{
+    clear_error();
+    BatchInfo info;
+    int rc = check_batch(Bt, &info);
+    if (rc) return rc;
+    if ((rc = check_em_args(Bt->alphabet, B, iters, beta, precision, theta0, bg, theta_out, J_out))) return rc;
+    if (B == 0) return PM_OK;
+    if (!buckets) return fail(PM_EINVAL, "buckets are NULL");
     hipStream_t st = as_stream(stream);
-    if (S->alphabet == 4)
-        return precision == PM_FP64 ? launch_em<double, 4>(a, lds, st) : launch_em<float, 4>(a, lds, st);
-    return precision == PM_FP64 ? launch_em<double, 20>(a, lds, st) : launch_em<float, 20>(a, lds, st);
+    if (precision == PM_F16X2 || precision == PM_F16) {
+        if (!ws || ws_bytes < em_batch_workspace(Bt->P)) return fail(PM_EINVAL, "workspace too small");
+        return em_refine_mfma_batch(Bt, info.nw_max, info.t_max, buckets, theta0, bg, B, n_dev, iters, beta,
+                                    theta_out, J_out, llr_out, sites_out, ws, precision == PM_F16X2, st);
+    }
+    EmArgs a{};
+    a.inst = Bt->inst;
+    a.item_inst = Bt->item_inst;
+    a.buckets = buckets;
+    a.theta0 = theta0;
+    a.bg = bg;
+    a.n_dev = n_dev;
+    a.theta_out = theta_out;
+    a.J = J_out;
+    a.llr = llr_out;
+    a.sites = sites_out;
+    a.B = B;
+    a.l = Bt->l;
+    a.iters = iters;
+    a.site_stride = info.t_max;
+    a.beta = beta;
+    return vec_launch(a, Bt->alphabet, precision, info.nw_max, info.t_max, st);
 }
 
 extern "C" int em_best(const double *J, int64_t B, const int64_t *n_dev, int32_t iters, const double *theta,
@@ -326,7 +402,22 @@ extern "C" int em_best(const double *J, int64_t B, const int64_t *n_dev, int32_t
     if (l < 1 || l > 32 || B < 0 || iters < 0) return fail(PM_EINVAL, "bad sizes");
     if (!best_out || (B > 0 && (!J || !theta))) return fail(PM_EINVAL, "NULL buffer");
     hipLaunchKernelGGL(k_best, dim3(1), dim3(256), 0, as_stream(stream), J, B, n_dev, iters, theta,
-                       alphabet, l, best_out, consensus_out);
+                       alphabet, l, best_out, consensus_out, nullptr, nullptr);
+    PM_LAUNCHED();
+    return PM_OK;
+}
+
+extern "C" int em_best_batch(const pm_batch *Bt, const pm_bucket *buckets, const double *J, int64_t B,
+                             const int64_t *n_dev, int32_t iters, const double *theta, int64_t *best_out,
+                             char *consensus_out, void *stream)
+{
+    clear_error();
+    int rc = check_batch(Bt, nullptr);
+    if (rc) return rc;
+    if (B < 0 || iters < 0) return fail(PM_EINVAL, "bad sizes");
+    if (!best_out || (B > 0 && (!J || !theta || !buckets))) return fail(PM_EINVAL, "NULL buffer");
+    hipLaunchKernelGGL(k_best, dim3(Bt->P), dim3(256), 0, as_stream(stream), J, B, n_dev, iters, theta,
+                       Bt->alphabet, Bt->l, best_out, consensus_out, Bt->inst, buckets);
     PM_LAUNCHED();
     return PM_OK;
 }

@@ -11,7 +11,8 @@
 // The other side is split in two FP16 halves, x = hi + lo with
 // hi = fp16(x) and lo = fp16(x - hi), both multiplied by the same one-hot
 // operand, so every product is exact and the operand carries about 22
-// significant bits; sums are FP32.  Scores are kept in log2 units (W scaled
+// significant bits; sums are FP32.  The single-FP16 form (SPLIT = false) keeps
+// only hi: half the matrix-core work, 11-bit operands.  Scores are kept in log2 units (W scaled
 // by log2 e) so the softmax uses the hardware exp2; the per-sequence
 // log-sum-exp and the objective are formed in FP64.
 //
@@ -61,8 +62,26 @@ struct EmMfmaArgs {
     int64_t nwords;  // packed words (reads are clamped below this)
     int t, l, iters;
     int stage_words; // packed words staged in LDS, 0 = read from global memory
+    int site_stride; // sites row length (t, or the largest t of a batch)
+    int split;       // 1: two FP16 halves per operand; 0: one FP16 value
     double beta;
+    // batch: the instance table and the workgroup plan (k_em_plan), or NULL
+    const pm_inst *inst;
+    const int64_t *plan;
+    int P;
 };
+
+// Workgroup plan of a batch: the instances in decreasing order of windows
+// (the longest sweeps start first), each cut into groups of 16 * kWaves
+// consecutive buckets.  Layout: wg_start[P + 1] (first workgroup of each rank),
+// b0[P], b1[P] (bucket range of each instance), order[P] (instance of each rank).
+struct PlanView {
+    const int64_t *wg_start, *b0, *b1, *order;
+};
+__host__ __device__ inline PlanView plan_view(const int64_t *plan, int P)
+{
+    return PlanView{plan, plan + P + 1, plan + 2 * P + 1, plan + 3 * P + 1};
+}
 
 constexpr int kWaves = 4;  // waves (groups of 16 models) per workgroup
 constexpr float kLog2e = 1.4426950408889634f;
@@ -175,7 +194,7 @@ struct SeqState {
 
 // One pair of 16-window tiles (windows a0 .. a0+31 of one sequence) for this
 // wave's 16 models.
-template <int MT, bool LAST, bool TAIL>
+template <int MT, bool LAST, bool TAIL, bool SPLIT>
 __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables &T, const half8 (&Whi)[Tiles<MT>::LB],
                                           const half8 (&Wlo)[Tiles<MT>::LB], float4v (&O)[MT], SeqState &st)
 {
@@ -194,8 +213,10 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables &T, co
     for (int kb = 0; kb < LB; ++kb) {
         S0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[0][kb], Whi[kb], S0, 0, 0, 0);
         S1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[1][kb], Whi[kb], S1, 0, 0, 0);
-        S0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[0][kb], Wlo[kb], S0, 0, 0, 0);
-        S1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[1][kb], Wlo[kb], S1, 0, 0, 0);
+        if (SPLIT) {
+            S0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[0][kb], Wlo[kb], S0, 0, 0, 0);
+            S1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[1][kb], Wlo[kb], S1, 0, 0, 0);
+        }
     }
     half8 Am[MT];
     if (!LAST) {
@@ -246,27 +267,31 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables &T, co
     }
     st.srun += ps;
     if (!LAST) {
-        uint4 h, lw;
+        uint4 h;
         h.x = pack_hi(P[0], P[1]);
         h.y = pack_hi(P[2], P[3]);
         h.z = pack_hi(P[4], P[5]);
         h.w = pack_hi(P[6], P[7]);
-        lw.x = split_lo(h.x, P[0], P[1]);
-        lw.y = split_lo(h.y, P[2], P[3]);
-        lw.z = split_lo(h.z, P[4], P[5]);
-        lw.w = split_lo(h.w, P[6], P[7]);
-        const half8 Ph = __builtin_bit_cast(half8, h), Pl = __builtin_bit_cast(half8, lw);
+        const half8 Ph = __builtin_bit_cast(half8, h);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) O[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[mt], Ph, O[mt], 0, 0, 0);
+        if (SPLIT) {
+            uint4 lw;
+            lw.x = split_lo(h.x, P[0], P[1]);
+            lw.y = split_lo(h.y, P[2], P[3]);
+            lw.z = split_lo(h.z, P[4], P[5]);
+            lw.w = split_lo(h.w, P[6], P[7]);
+            const half8 Pl = __builtin_bit_cast(half8, lw);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) O[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[mt], Pl, O[mt], 0, 0, 0);
+            for (int mt = 0; mt < MT; ++mt) O[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[mt], Pl, O[mt], 0, 0, 0);
+        }
     }
 }
 
 // One sequence: every window pair (tables built by the whole workgroup), then
 // the per-sequence log-sum-exp and counts, or, in the final E-step, the best
 // start of every model.
-template <int MT, bool STAGED, bool LAST>
+template <int MT, bool STAGED, bool LAST, bool SPLIT>
 __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, const uint2 *lut, int i, int64_t bw,
                                       int64_t nvalid, PairTables *tabs, int &parity, float (*acc)[Tiles<MT>::PX][4],
                                       const half8 (&Whi)[Tiles<MT>::LB], const half8 (&Wlo)[Tiles<MT>::LB],
@@ -285,8 +310,8 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
         parity ^= 1;
         build_tables<!STAGED>(W, a.nwords, s0 + a0, lut, T);
         __syncthreads();
-        if (a0 + 32 <= L) tile_pair<MT, LAST, false>(a0, L, T, Whi, Wlo, O, st);
-        else tile_pair<MT, LAST, true>(a0, L, T, Whi, Wlo, O, st);
+        if (a0 + 32 <= L) tile_pair<MT, LAST, false, SPLIT>(a0, L, T, Whi, Wlo, O, st);
+        else tile_pair<MT, LAST, true, SPLIT>(a0, L, T, Whi, Wlo, O, st);
     }
     float sr = st.srun;
     sr += __shfl_xor(sr, 16);
@@ -314,12 +339,12 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
             }
         }
         const int64_t b = bw + r;
-        if (g == 0 && b < nvalid) a.sites[b * a.t + i] = bi;
+        if (g == 0 && b < nvalid) a.sites[b * a.site_stride + i] = bi;
     }
 }
 
-template <int MT, bool STAGED>
-__global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(const EmMfmaArgs a)
+template <int MT, bool STAGED, bool SPLIT>
+__global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(const EmMfmaArgs a0)
 {
     constexpr int LB = Tiles<MT>::LB, PX = Tiles<MT>::PX;
     __shared__ __align__(16) PairTables tabs[2];
@@ -328,10 +353,34 @@ __global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(cons
     extern __shared__ __align__(16) uint32_t staged[];
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-    int64_t nvalid = a.n_dev ? *a.n_dev : a.B;
-    if (nvalid > a.B) nvalid = a.B;
-    const int64_t b0 = (int64_t)blockIdx.x * 16 * kWaves;
-    if (b0 >= nvalid) return;  // uniform over the workgroup
+    EmMfmaArgs a = a0;
+    int64_t b0, nvalid;
+    if (a0.inst) {
+        // batch: find this workgroup's instance rank, largest r with wg_start[r] <= wg
+        const PlanView pv = plan_view(a0.plan, a0.P);
+        const int64_t wg = blockIdx.x;
+        if (wg >= pv.wg_start[a0.P]) return;
+        int lo = 0, hi = a0.P;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pv.wg_start[mid] <= wg) lo = mid;
+            else hi = mid;
+        }
+        const int p = (int)pv.order[lo];
+        const pm_inst I = a0.inst[p];
+        a.packed = I.packed;
+        a.offsets = I.offsets;
+        a.t = I.t;
+        a.nwords = (I.n_total + 15) / 16 + 4;
+        a.stage_words = STAGED ? (int)a.nwords : 0;
+        b0 = pv.b0[p] + (wg - pv.wg_start[lo]) * 16 * kWaves;
+        nvalid = pv.b1[p] < b0 + 16 * kWaves ? pv.b1[p] : b0 + 16 * kWaves;
+    } else {
+        nvalid = a.n_dev ? *a.n_dev : a.B;
+        if (nvalid > a.B) nvalid = a.B;
+        b0 = (int64_t)blockIdx.x * 16 * kWaves;
+        if (b0 >= nvalid) return;  // uniform over the workgroup
+    }
     if (STAGED)
         for (int k = threadIdx.x; k < a.stage_words + kStagePad; k += 64 * kWaves)
             staged[k] = k < a.stage_words ? a.packed[k] : 0u;
@@ -404,8 +453,8 @@ __global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(cons
 
         double llr = 0;
         for (int i = 0; i < t; ++i) {
-            if (last) sweep<MT, STAGED, true>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
-            else sweep<MT, STAGED, false>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
+            if (last) sweep<MT, STAGED, true, SPLIT>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
+            else sweep<MT, STAGED, false, SPLIT>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
         }
         // ---- objective of theta^it, then the M-step (own entries)
         if (g == 0 && vb) {
@@ -431,24 +480,41 @@ __global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(cons
     }
 }
 
-template <int MT>
-static int launch_em_mfma(const EmMfmaArgs &a, hipStream_t st)
+template <int MT, bool SPLIT>
+static int launch_em_mfma(const EmMfmaArgs &a, int64_t groups, hipStream_t st)
 {
-    const int64_t groups = (a.B + 16 * kWaves - 1) / (16 * kWaves);
     if (a.stage_words)
-        hipLaunchKernelGGL((k_em_mfma<MT, true>), dim3((unsigned)groups), dim3(64 * kWaves),
+        hipLaunchKernelGGL((k_em_mfma<MT, true, SPLIT>), dim3((unsigned)groups), dim3(64 * kWaves),
                            (size_t)(a.stage_words + kStagePad) * 4, st, a);
     else
-        hipLaunchKernelGGL((k_em_mfma<MT, false>), dim3((unsigned)groups), dim3(64 * kWaves), 0, st, a);
+        hipLaunchKernelGGL((k_em_mfma<MT, false, SPLIT>), dim3((unsigned)groups), dim3(64 * kWaves), 0, st, a);
     PM_LAUNCHED();
     return PM_OK;
 }
 
+static int dispatch_em_mfma(const EmMfmaArgs &a, int64_t groups, hipStream_t st)
+{
+#define PM_EM_CASE(mt) \
+    case mt: return a.split ? launch_em_mfma<mt, true>(a, groups, st) : launch_em_mfma<mt, false>(a, groups, st);
+    switch ((a.l + 3) / 4) {
+    PM_EM_CASE(1)
+    PM_EM_CASE(2)
+    PM_EM_CASE(3)
+    PM_EM_CASE(4)
+    PM_EM_CASE(5)
+    PM_EM_CASE(6)
+    PM_EM_CASE(7)
+    default: return a.split ? launch_em_mfma<8, true>(a, groups, st) : launch_em_mfma<8, false>(a, groups, st);
+    }
+#undef PM_EM_CASE
+}
+
 int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
                    const int64_t *n_dev, int32_t iters, double beta, double *theta_out, double *J_out,
-                   double *llr_out, int32_t *sites_out, hipStream_t st)
+                   double *llr_out, int32_t *sites_out, bool split, hipStream_t st)
 {
     EmMfmaArgs a{};
+    a.split = split;
     a.packed = S->packed;
     a.offsets = S->offsets;
     a.theta0 = theta0;
@@ -462,19 +528,91 @@ int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const doub
     a.nwords = pm_packed_words(S->alphabet, S->n_total);
     a.stage_words = a.nwords * 4 <= 32 * 1024 ? (int)a.nwords : 0;
     a.t = S->t;
+    a.site_stride = S->t;
     a.l = l;
     a.iters = iters;
     a.beta = beta;
-    switch ((l + 3) / 4) {
-    case 1: return launch_em_mfma<1>(a, st);
-    case 2: return launch_em_mfma<2>(a, st);
-    case 3: return launch_em_mfma<3>(a, st);
-    case 4: return launch_em_mfma<4>(a, st);
-    case 5: return launch_em_mfma<5>(a, st);
-    case 6: return launch_em_mfma<6>(a, st);
-    case 7: return launch_em_mfma<7>(a, st);
-    default: return launch_em_mfma<8>(a, st);
+    return dispatch_em_mfma(a, (B + 16 * kWaves - 1) / (16 * kWaves), st);
+}
+
+// One workgroup: each instance's bucket range (buckets ascend by item), its
+// workgroup count, the largest-first order of the instances and the scan of
+// the counts in that order.
+__global__ void __launch_bounds__(1024) k_em_plan(const pm_inst *inst, int P, const pm_bucket *buckets,
+                                                 const int64_t *n_dev, int64_t Bcap, int64_t *plan)
+{
+    const PlanView pv = plan_view(plan, P);
+    int64_t *wg_start = const_cast<int64_t *>(pv.wg_start), *b0 = const_cast<int64_t *>(pv.b0);
+    int64_t *b1 = const_cast<int64_t *>(pv.b1), *order = const_cast<int64_t *>(pv.order);
+    int64_t nvalid = n_dev ? *n_dev : Bcap;
+    if (nvalid > Bcap) nvalid = Bcap;
+    // bucket range of every instance: first bucket whose item is >= first_item
+    for (int p = threadIdx.x; p < P; p += 1024) {
+        for (int side = 0; side < 2; ++side) {
+            const int64_t item = (int64_t)inst[p].first_item + (side ? inst[p].m : 0);
+            int64_t lo = 0, hi = nvalid;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if ((int64_t)buckets[mid].trial < item) lo = mid + 1;
+                else hi = mid;
+            }
+            (side ? b1 : b0)[p] = lo;
+        }
+    }
+    // rank by windows, descending, ties by index
+    for (int p = threadIdx.x; p < P; p += 1024) {
+        const int64_t xp = inst[p].x;
+        int r = 0;
+        for (int q = 0; q < P; ++q) {
+            const int64_t xq = inst[q].x;
+            r += (xq > xp || (xq == xp && q < p)) ? 1 : 0;
+        }
+        order[r] = p;
+    }
+    __syncthreads();
+    // exclusive scan of the workgroup counts in rank order (serial: P is small)
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int r = 0; r < P; ++r) {
+            wg_start[r] = run;
+            const int p = (int)order[r];
+            run += (b1[p] - b0[p] + 16 * kWaves - 1) / (16 * kWaves);
+        }
+        wg_start[P] = run;
     }
 }
+
+int em_refine_mfma_batch(const pm_batch *Bt, int64_t nw_max, int t_max, const pm_bucket *buckets,
+                         const double *theta0, const double *bg, int64_t B, const int64_t *n_dev, int32_t iters,
+                         double beta, double *theta_out, double *J_out, double *llr_out, int32_t *sites_out,
+                         void *ws, bool split, hipStream_t st)
+{
+    int64_t *plan = static_cast<int64_t *>(ws);
+    hipLaunchKernelGGL(k_em_plan, dim3(1), dim3(1024), 0, st, Bt->inst, Bt->P, buckets, n_dev, B, plan);
+    PM_LAUNCHED();
+    EmMfmaArgs a{};
+    a.split = split;
+    a.inst = Bt->inst;
+    a.plan = plan;
+    a.P = Bt->P;
+    a.theta0 = theta0;
+    a.bg = bg;
+    a.n_dev = n_dev;
+    a.theta_out = theta_out;
+    a.J = J_out;
+    a.llr = llr_out;
+    a.sites = sites_out;
+    a.B = B;
+    a.stage_words = nw_max * 4 <= 32 * 1024 ? (int)nw_max : 0;  // LDS reserved; each group stages its own
+    a.site_stride = t_max;
+    a.l = Bt->l;
+    a.iters = iters;
+    a.beta = beta;
+    // every instance wastes at most one partly filled group
+    const int64_t groups = (B + 16 * kWaves - 1) / (16 * kWaves) + Bt->P;
+    return dispatch_em_mfma(a, groups, st);
+}
+
+size_t em_batch_workspace(int32_t P) { return P < 1 ? 0 : (size_t)(4 * (int64_t)P + 1) * sizeof(int64_t) + 256; }
 
 }  // namespace pm

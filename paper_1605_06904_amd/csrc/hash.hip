@@ -62,20 +62,20 @@ __global__ void k_pack(int A, const uint8_t *__restrict__ ascii, int64_t n, uint
 
 // ---------------------------------------------------------------- a3 + a4
 struct HashArgs {
-    const uint32_t *packed;
-    const int64_t *offsets;
+    pm_inst one;               // the instance, when inst is NULL
+    const pm_inst *inst;       // batch: instance table, or NULL
+    const int32_t *item_inst;  // batch: instance of every trial item
     const uint32_t *masks;
     uint32_t *keys;
     uint32_t *counts;
     uint32_t *status;
-    int64_t x;           // windows per trial
     int64_t nb;          // |Sigma|^k
-    int t, l, k;
+    int l, k;
     int nslices;         // key-range slices per trial
     uint32_t slice_bins; // bins per slice (multiple of 4)
     int hist_words;      // LDS words of histogram
-    int seq_words;       // packed words staged in LDS (0: read from global)
-    int stage_off;       // offsets staged in LDS
+    int seq_cap;         // LDS words reserved for the packed input (0: read from global)
+    int off_cap;         // LDS offsets reserved (0: read from global)
 };
 
 constexpr int kHashThreads = 1024;
@@ -88,6 +88,9 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
     const int slice = blockIdx.x % a.nslices;
     const int j = blockIdx.x / a.nslices;
     const int tid = threadIdx.x;
+    const pm_inst I = a.inst ? a.inst[a.item_inst[j]] : a.one;
+    const int64_t x = I.x;
+    const int seq_words = a.seq_cap ? (int)(A == 4 ? (I.n_total + 15) / 16 + 4 : (I.n_total + 5) / 6 + 4) : 0;
 
     const uint32_t mask = a.masks[j];
     const uint32_t lmask = a.l == 32 ? 0xffffffffu : ((1u << a.l) - 1u);
@@ -98,18 +101,18 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
 
     uint32_t *hist = smem;
     uint32_t *seq = smem + a.hist_words;
-    int64_t *offs = reinterpret_cast<int64_t *>(seq + ((a.seq_words + 1) & ~1));
+    int64_t *offs = reinterpret_cast<int64_t *>(seq + ((a.seq_cap + 1) & ~1));
 
-    for (int i = tid; i < a.seq_words; i += kHashThreads) seq[i] = a.packed[i];
-    if (a.stage_off)
-        for (int i = tid; i <= a.t; i += kHashThreads) offs[i] = a.offsets[i];
+    for (int i = tid; i < seq_words; i += kHashThreads) seq[i] = I.packed[i];
+    if (a.off_cap)
+        for (int i = tid; i <= I.t; i += kHashThreads) offs[i] = I.offsets[i];
     if (a.counts)
         for (int i = tid * 4; i < a.hist_words; i += kHashThreads * 4)
             *reinterpret_cast<uint4 *>(hist + i) = make_uint4(0, 0, 0, 0);
     __syncthreads();
 
-    const uint32_t *W = a.seq_words ? seq : a.packed;
-    const int64_t *O = a.stage_off ? offs : a.offsets;
+    const uint32_t *W = a.seq_cap ? seq : I.packed;
+    const int64_t *O = a.off_cap ? offs : I.offsets;
 
     // kept positions, ascending (uniform across the workgroup)
     // shift of each kept position's 2-bit field in the 64-bit window (DNA), or
@@ -126,13 +129,13 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
     }
 
     const uint64_t slice_base = (uint64_t)slice * a.slice_bins;
-    const int64_t kw0 = a.x * slice / a.nslices, kw1 = a.x * (slice + 1) / a.nslices;
-    uint32_t *keys_j = a.keys ? a.keys + (int64_t)j * a.x : nullptr;
+    const int64_t kw0 = x * slice / a.nslices, kw1 = x * (slice + 1) / a.nslices;
+    uint32_t *keys_j = a.keys ? a.keys + I.key_base + (int64_t)(j - I.first_item) * x : nullptr;
     const int lane = lane_id();
     const int64_t lm1 = a.l - 1;
 
     int i = 0;
-    for (int64_t w = tid; w < a.x; w += kHashThreads) {
+    for (int64_t w = tid; w < x; w += kHashThreads) {
         while (w >= O[i + 1] - (int64_t)(i + 1) * lm1) ++i;
         const int64_t P = w + (int64_t)i * lm1;
         uint32_t key = 0;
@@ -251,44 +254,18 @@ extern "C" int pm_pack(int32_t alphabet, const uint8_t *ascii, int64_t n_total, 
     return PM_OK;
 }
 
-extern "C" int projection_hash(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks,
-                               int32_t m, uint32_t *keys, uint32_t *counts, uint32_t *status,
-                               void *stream)
+// sizes the LDS (staged input, histogram slices) for the largest instance
+// and launches one workgroup per (item, slice)
+static int hash_launch(HashArgs &a, int A, int32_t items, int64_t x_max, int64_t nw_max, int t_max,
+                       hipStream_t st)
 {
-    clear_error();
-    int rc = check_seqs(S, l);
-    if (rc) return rc;
-    if (k < 1 || k > l) return fail(PM_EINVAL, "need 1 <= k <= l (k=%d, l=%d)", k, l);
-    if (m < 0) return fail(PM_EINVAL, "m must be >= 0");
-    if (!masks && m > 0) return fail(PM_EINVAL, "masks is NULL");
-    if (!keys && !counts) return fail(PM_EINVAL, "keys and counts are both NULL");
-    const int A = S->alphabet;
-    if ((A == 4 && k > 16) || (A == 20 && k > 7))
-        return fail(PM_ERANGE, "|Sigma|^k must stay below 2^32 (k=%d)", k);
-    const int64_t nb = ipow(A, k);
-    if (counts && nb > (1ll << 24)) return fail(PM_ERANGE, "|Sigma|^k = %lld bins is above 2^24", (long long)nb);
-    if (m == 0) return PM_OK;
-
-    HashArgs a{};
-    a.packed = S->packed;
-    a.offsets = S->offsets;
-    a.masks = masks;
-    a.keys = keys;
-    a.counts = counts;
-    a.status = status;
-    a.x = num_windows(S, l);
-    a.nb = nb;
-    a.t = S->t;
-    a.l = l;
-    a.k = k;
-    const bool u16 = a.x < 65536;
+    const bool u16 = x_max < 65536;
     const int lds_max = device_lds_bytes();
-    const int64_t nw = pm_packed_words(A, S->n_total);
-    a.seq_words = nw * 4 <= 48 * 1024 ? (int)nw : 0;
-    a.stage_off = (S->t + 1) * 8 <= 8 * 1024;
-    const int fixed = ((a.seq_words + 1) & ~1) * 4 + (a.stage_off ? (S->t + 1) * 8 : 0);
-    if (counts) {
-        const int64_t need_words = u16 ? (nb + 1) / 2 : nb;
+    a.seq_cap = nw_max * 4 <= 48 * 1024 ? (int)nw_max : 0;
+    a.off_cap = (t_max + 1) * 8 <= 8 * 1024 ? t_max + 1 : 0;
+    const int fixed = ((a.seq_cap + 1) & ~1) * 4 + a.off_cap * 8;
+    if (a.counts) {
+        const int64_t need_words = u16 ? (a.nb + 1) / 2 : a.nb;
         int64_t budget = (lds_max - fixed) / 4;
         budget &= ~int64_t(3);
         if (budget < 1024) return fail(PM_ERANGE, "input too large for the LDS budget");
@@ -297,15 +274,72 @@ extern "C" int projection_hash(const pm_seqs *S, int32_t l, int32_t k, const uin
         if (hw > budget) hw = budget;
         a.hist_words = (int)hw;
         a.slice_bins = (uint32_t)(u16 ? 2 * hw : hw);
-        a.nslices = (int)((nb + a.slice_bins - 1) / a.slice_bins);
+        a.nslices = (int)((a.nb + a.slice_bins - 1) / a.slice_bins);
     } else {
         a.hist_words = 0;
         a.slice_bins = 0;
         a.nslices = 1;
     }
     const size_t lds = (size_t)a.hist_words * 4 + fixed;
-    const int64_t blocks = (int64_t)m * a.nslices;
+    const int64_t blocks = (int64_t)items * a.nslices;
     if (blocks > 0x7fffffff) return fail(PM_ERANGE, "too many trials x slices");
-    hipStream_t st = as_stream(stream);
-    return dispatch_hash<1>(A, k, u16, a, lds, (int)blocks, st);
+    return dispatch_hash<1>(A, a.k, u16, a, lds, (int)blocks, st);
+}
+
+static int check_hash_args(int A, int l, int k, const uint32_t *masks, int64_t items, const uint32_t *keys,
+                           const uint32_t *counts)
+{
+    if (k < 1 || k > l) return fail(PM_EINVAL, "need 1 <= k <= l (k=%d, l=%d)", k, l);
+    if (items < 0) return fail(PM_EINVAL, "m must be >= 0");
+    if (!masks && items > 0) return fail(PM_EINVAL, "masks is NULL");
+    if (!keys && !counts) return fail(PM_EINVAL, "keys and counts are both NULL");
+    if ((A == 4 && k > 16) || (A == 20 && k > 7))
+        return fail(PM_ERANGE, "|Sigma|^k must stay below 2^32 (k=%d)", k);
+    if (counts && ipow(A, k) > (1ll << 24))
+        return fail(PM_ERANGE, "|Sigma|^k = %lld bins is above 2^24", (long long)ipow(A, k));
+    return PM_OK;
+}
+
+extern "C" int projection_hash(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks,
+                               int32_t m, uint32_t *keys, uint32_t *counts, uint32_t *status,
+                               void *stream)
+{
+    clear_error();
+    int rc = check_seqs(S, l);
+    if (rc) return rc;
+    const int A = S->alphabet;
+    if ((rc = check_hash_args(A, l, k, masks, m, keys, counts))) return rc;
+    if (m == 0) return PM_OK;
+    HashArgs a{};
+    a.one = inst_of(S, l);
+    a.masks = masks;
+    a.keys = keys;
+    a.counts = counts;
+    a.status = status;
+    a.nb = ipow(A, k);
+    a.l = l;
+    a.k = k;
+    return hash_launch(a, A, m, a.one.x, pm_packed_words(A, S->n_total), S->t, as_stream(stream));
+}
+
+extern "C" int projection_hash_batch(const pm_batch *B, const uint32_t *masks, uint32_t *keys,
+                                     uint32_t *counts, uint32_t *status, void *stream)
+{
+    clear_error();
+    BatchInfo info;
+    int rc = check_batch(B, &info);
+    if (rc) return rc;
+    const int A = B->alphabet;
+    if ((rc = check_hash_args(A, B->l, B->k, masks, B->items, keys, counts))) return rc;
+    HashArgs a{};
+    a.inst = B->inst;
+    a.item_inst = B->item_inst;
+    a.masks = masks;
+    a.keys = keys;
+    a.counts = counts;
+    a.status = status;
+    a.nb = ipow(A, B->k);
+    a.l = B->l;
+    a.k = B->k;
+    return hash_launch(a, A, B->items, info.x_max, info.nw_max, info.t_max, as_stream(stream));
 }

@@ -43,9 +43,26 @@ static inline int64_t num_windows(const pm_seqs *S, int l)
 
 int check_seqs(const pm_seqs *S, int l);
 
+// a single instance seen as a one-instance batch entry (key_base 0, item 0)
+pm_inst inst_of(const pm_seqs *S, int l);
+
+// launch sizes of a batch: the largest instance in each respect
+struct BatchInfo {
+    int t_max;
+    int64_t nw_max;      // packed words
+    int64_t x_max;       // windows
+    int64_t keys_total;  // key slots over all items
+};
+int check_batch(const pm_batch *B, BatchInfo *info);
+
 int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
                    const int64_t *n_dev, int32_t iters, double beta, double *theta_out, double *J_out,
-                   double *llr_out, int32_t *sites_out, hipStream_t st);
+                   double *llr_out, int32_t *sites_out, bool split, hipStream_t st);
+int em_refine_mfma_batch(const pm_batch *Bt, int64_t nw_max, int t_max, const pm_bucket *buckets,
+                         const double *theta0, const double *bg, int64_t B, const int64_t *n_dev, int32_t iters,
+                         double beta, double *theta_out, double *J_out, double *llr_out, int32_t *sites_out,
+                         void *ws, bool split, hipStream_t st);
+size_t em_batch_workspace(int32_t P);
 
 // ---------------------------------------------------------------- device side
 constexpr int kWave = 64;

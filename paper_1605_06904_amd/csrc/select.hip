@@ -35,6 +35,9 @@ static SelWs carve(void *ws, int32_t m, int64_t cap_b)
 }
 
 struct SelArgs {
+    pm_inst one;               // the instance, when inst is NULL
+    const pm_inst *inst;       // batch: instance table, or NULL
+    const int32_t *item_inst;  // batch: instance of every trial item
     const uint32_t *keys;
     const uint32_t *counts;
     pm_bucket *buckets;
@@ -42,8 +45,8 @@ struct SelArgs {
     int64_t *n_out;
     uint32_t *status;
     SelWs ws;
-    int64_t x, nb, cap_b, cap_m;
-    int32_t m;
+    int64_t nb, cap_b, cap_m;
+    int32_t m;  // trials (items)
     uint32_t s;
     int nwb;  // bitmap words, ceil(nb / 64)
 };
@@ -158,6 +161,7 @@ __global__ void __launch_bounds__(256) k_sel_emit(const SelArgs a)
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
     const uint32_t *cnt = a.counts + (int64_t)j * a.nb;
     const int64_t bbase = a.ws.bb[j], mbase = a.ws.mb[j];
+    const pm_inst I = a.inst ? a.inst[a.item_inst[j]] : a.one;
 
     // ---- bitmap of passing keys, one ballot per word of 64 keys; eight loads
     // in flight per wave
@@ -220,8 +224,8 @@ __global__ void __launch_bounds__(256) k_sel_emit(const SelArgs a)
 
     // ---- members: wave wv owns windows [lo, hi); pass 0 counts per bucket,
     // pass 1 places them after the members of earlier quarters
-    const uint32_t *kj = a.keys + (int64_t)j * a.x;
-    const int64_t lo = a.x * wv / 4, hi = a.x * (wv + 1) / 4;
+    const uint32_t *kj = a.keys + I.key_base + (int64_t)(j - I.first_item) * I.x;
+    const int64_t lo = I.x * wv / 4, hi = I.x * (wv + 1) / 4;
     for (int pass = 0; pass < 2; ++pass) {
         for (int64_t wb = lo; wb < hi; wb += 64 * U) {
           uint32_t kk[U];
@@ -273,14 +277,15 @@ __global__ void __launch_bounds__(256) k_sel_emit(const SelArgs a)
 
 // ---------------------------------------------------------------- a6
 struct ProfArgs {
-    const uint32_t *packed;
-    const int64_t *offsets;
+    pm_inst one;               // the instance, when inst is NULL
+    const pm_inst *inst;       // batch: instance table, or NULL
+    const int32_t *item_inst;  // batch: instance of every trial item
     const pm_bucket *buckets;
     const uint32_t *members;
     const int64_t *n_dev;
     uint32_t *profile;
     int64_t B, cap_m;
-    int t, l, A;
+    int l, A;
 };
 
 // one wave per bucket; lane p owns column p
@@ -295,19 +300,20 @@ __global__ void __launch_bounds__(256) k_profile(const ProfArgs a)
     uint32_t *C = cnt[wv];
     for (int i = lane; i < a.A * 32; i += 64) C[i] = 0;
     const pm_bucket bk = a.buckets[b];
+    const pm_inst I = a.inst ? a.inst[a.item_inst[bk.trial]] : a.one;
     const int64_t lm1 = a.l - 1;
     const uint32_t size = (int64_t)bk.first + bk.size <= a.cap_m ? bk.size : 0u;
     for (uint32_t r = 0; r < size; ++r) {
         const int64_t w = a.members[(int64_t)bk.first + r];
-        int lo = 0, hi = a.t;  // last sequence whose first window <= w
+        int lo = 0, hi = I.t;  // last sequence whose first window <= w
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (a.offsets[mid] - (int64_t)mid * lm1 <= w) lo = mid;
+            if (I.offsets[mid] - (int64_t)mid * lm1 <= w) lo = mid;
             else hi = mid;
         }
         const int64_t P = w + (int64_t)lo * lm1;
         if (lane < a.l) {
-            const uint32_t code = a.A == 4 ? dna_sym(a.packed, P + lane) : prot_sym(a.packed, P + lane);
+            const uint32_t code = a.A == 4 ? dna_sym(I.packed, P + lane) : prot_sym(I.packed, P + lane);
             C[code * 32 + lane] += 1;
         }
     }
@@ -343,40 +349,11 @@ extern "C" size_t pm_select_workspace(int32_t m, int64_t cap_buckets)
     return (size_t)m * 4 * sizeof(int64_t) + (size_t)cap_buckets * 8 * sizeof(uint32_t) + 256;
 }
 
-extern "C" int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *keys,
-                             const uint32_t *counts, int32_t m, uint32_t s, pm_bucket *buckets,
-                             int64_t cap_buckets, uint32_t *members, int64_t cap_members,
-                             int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status, void *stream)
+static int select_launch(SelArgs &a, int A, int k, hipStream_t st)
 {
-    clear_error();
-    int rc = check_seqs(S, l);
-    if (rc) return rc;
-    if (k < 1 || k > l) return fail(PM_EINVAL, "need 1 <= k <= l");
-    if (m < 1) return fail(PM_EINVAL, "m must be >= 1");
-    if (!keys || !counts || !n_out || !ws) return fail(PM_EINVAL, "keys, counts, n_out and ws are required");
-    if (cap_buckets < 0 || cap_members < 0) return fail(PM_EINVAL, "negative capacity");
-    if ((cap_buckets > 0 && !buckets) || (cap_members > 0 && !members))
-        return fail(PM_EINVAL, "NULL output with a non-zero capacity");
-    if (cap_members > 0xffffffffll) return fail(PM_ERANGE, "cap_members must be below 2^32");
-    const int A = S->alphabet;
     if (ipow(A, k) > (1ll << 19)) return fail(PM_ERANGE, "|Sigma|^k above 2^19");
-    if (ws_bytes < pm_select_workspace(m, cap_buckets)) return fail(PM_EINVAL, "workspace too small");
-    SelArgs a{};
-    a.keys = keys;
-    a.counts = counts;
-    a.buckets = buckets;
-    a.members = members;
-    a.n_out = n_out;
-    a.status = status;
-    a.ws = carve(ws, m, cap_buckets);
-    a.x = num_windows(S, l);
     a.nb = ipow(A, k);
-    a.cap_b = cap_buckets;
-    a.cap_m = cap_members;
-    a.m = m;
-    a.s = s;
-    hipStream_t st = as_stream(stream);
-    hipLaunchKernelGGL(k_sel_count, dim3(m), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_sel_count, dim3(a.m), dim3(256), 0, st, a);
     PM_LAUNCHED();
     hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(1024), 0, st, a);
     PM_LAUNCHED();
@@ -390,7 +367,83 @@ extern "C" int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint3
         (void)hipGetLastError();  // an unsupported attribute must not poison the launch check
         attr = true;
     }
-    hipLaunchKernelGGL(k_sel_emit, dim3(m), dim3(256), lds, st, a);
+    hipLaunchKernelGGL(k_sel_emit, dim3(a.m), dim3(256), lds, st, a);
+    PM_LAUNCHED();
+    return PM_OK;
+}
+
+static int check_select_args(int32_t items, const uint32_t *keys, const uint32_t *counts, const int64_t *n_out,
+                             void *ws, size_t ws_bytes, pm_bucket *buckets, int64_t cap_buckets,
+                             uint32_t *members, int64_t cap_members)
+{
+    if (items < 1) return fail(PM_EINVAL, "m must be >= 1");
+    if (!keys || !counts || !n_out || !ws) return fail(PM_EINVAL, "keys, counts, n_out and ws are required");
+    if (cap_buckets < 0 || cap_members < 0) return fail(PM_EINVAL, "negative capacity");
+    if ((cap_buckets > 0 && !buckets) || (cap_members > 0 && !members))
+        return fail(PM_EINVAL, "NULL output with a non-zero capacity");
+    if (cap_members > 0xffffffffll) return fail(PM_ERANGE, "cap_members must be below 2^32");
+    if (ws_bytes < pm_select_workspace(items, cap_buckets)) return fail(PM_EINVAL, "workspace too small");
+    return PM_OK;
+}
+
+extern "C" int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *keys,
+                             const uint32_t *counts, int32_t m, uint32_t s, pm_bucket *buckets,
+                             int64_t cap_buckets, uint32_t *members, int64_t cap_members,
+                             int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status, void *stream)
+{
+    clear_error();
+    int rc = check_seqs(S, l);
+    if (rc) return rc;
+    if (k < 1 || k > l) return fail(PM_EINVAL, "need 1 <= k <= l");
+    if ((rc = check_select_args(m, keys, counts, n_out, ws, ws_bytes, buckets, cap_buckets, members, cap_members)))
+        return rc;
+    SelArgs a{};
+    a.one = inst_of(S, l);
+    a.keys = keys;
+    a.counts = counts;
+    a.buckets = buckets;
+    a.members = members;
+    a.n_out = n_out;
+    a.status = status;
+    a.ws = carve(ws, m, cap_buckets);
+    a.cap_b = cap_buckets;
+    a.cap_m = cap_members;
+    a.m = m;
+    a.s = s;
+    return select_launch(a, S->alphabet, k, as_stream(stream));
+}
+
+extern "C" int bucket_select_batch(const pm_batch *B, const uint32_t *keys, const uint32_t *counts, uint32_t s,
+                                   pm_bucket *buckets, int64_t cap_buckets, uint32_t *members,
+                                   int64_t cap_members, int64_t *n_out, void *ws, size_t ws_bytes,
+                                   uint32_t *status, void *stream)
+{
+    clear_error();
+    int rc = check_batch(B, nullptr);
+    if (rc) return rc;
+    if ((rc = check_select_args(B->items, keys, counts, n_out, ws, ws_bytes, buckets, cap_buckets, members,
+                                cap_members)))
+        return rc;
+    SelArgs a{};
+    a.inst = B->inst;
+    a.item_inst = B->item_inst;
+    a.keys = keys;
+    a.counts = counts;
+    a.buckets = buckets;
+    a.members = members;
+    a.n_out = n_out;
+    a.status = status;
+    a.ws = carve(ws, B->items, cap_buckets);
+    a.cap_b = cap_buckets;
+    a.cap_m = cap_members;
+    a.m = B->items;
+    a.s = s;
+    return select_launch(a, B->alphabet, B->k, as_stream(stream));
+}
+
+static int profile_launch(const ProfArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_profile, dim3((unsigned)((a.B + 3) / 4)), dim3(256), 0, st, a);
     PM_LAUNCHED();
     return PM_OK;
 }
@@ -406,20 +459,40 @@ extern "C" int bucket_profile(const pm_seqs *S, int32_t l, const pm_bucket *buck
     if (B == 0) return PM_OK;
     if (!buckets || !members || !profile) return fail(PM_EINVAL, "NULL buffer");
     ProfArgs a{};
-    a.packed = S->packed;
-    a.offsets = S->offsets;
+    a.one = inst_of(S, l);
     a.buckets = buckets;
     a.members = members;
     a.n_dev = n_dev;
     a.profile = profile;
     a.B = B;
     a.cap_m = cap_members;
-    a.t = S->t;
     a.l = l;
     a.A = S->alphabet;
-    hipLaunchKernelGGL(k_profile, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, as_stream(stream), a);
-    PM_LAUNCHED();
-    return PM_OK;
+    return profile_launch(a, as_stream(stream));
+}
+
+extern "C" int bucket_profile_batch(const pm_batch *Bt, const pm_bucket *buckets, const uint32_t *members,
+                                    int64_t cap_members, int64_t B, const int64_t *n_dev, uint32_t *profile,
+                                    void *stream)
+{
+    clear_error();
+    int rc = check_batch(Bt, nullptr);
+    if (rc) return rc;
+    if (B < 0) return fail(PM_EINVAL, "B must be >= 0");
+    if (B == 0) return PM_OK;
+    if (!buckets || !members || !profile) return fail(PM_EINVAL, "NULL buffer");
+    ProfArgs a{};
+    a.inst = Bt->inst;
+    a.item_inst = Bt->item_inst;
+    a.buckets = buckets;
+    a.members = members;
+    a.n_dev = n_dev;
+    a.profile = profile;
+    a.B = B;
+    a.cap_m = cap_members;
+    a.l = Bt->l;
+    a.A = Bt->alphabet;
+    return profile_launch(a, as_stream(stream));
 }
 
 extern "C" int theta_init(int32_t alphabet, int32_t l, const uint32_t *profile, int64_t B,
