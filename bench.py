@@ -57,6 +57,11 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def stage_events(torch, n):
     return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
 
@@ -146,10 +151,10 @@ def main():
     em_updates = float(nbk) * x * l * (2 * iters + 1)
     dominant = max(stage, key=stage.get)
     if dominant == "hash":
-        roof = {"kernel": "k_hash<4,true>", "bound": "hbm", "achieved": round(hash_gbs, 2), "peak": HBM_PEAK_GBS,
+        roof = {"kernel": "k_hash<4,8,true>", "bound": "hbm", "achieved": round(hash_gbs, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4), "traffic": traffic("hash.hip")}
     else:
-        roof = {"kernel": "k_em_mfma<5,true>", "bound": "mfma", "achieved": round(em_tfs, 3),
+        roof = {"kernel": "k_em_mfma<5,true,true>", "bound": "mfma", "achieved": round(em_tfs, 3),
                 "peak": FP16_MFMA_PEAK, "unit": "TFLOP/s", "frac": round(em_tfs / FP16_MFMA_PEAK, 5),
                 "traffic": traffic("em_mfma.hip"), "flops_per_launch": em_flops}
     out = {
@@ -171,7 +176,7 @@ def main():
                    "parallelism": "single GPU"},
         "stage_ms": stage,
         "roofline": roof,
-        "roofline_hash": {"kernel": "k_hash<4,true>", "bound": "hbm", "achieved": round(hash_gbs, 2),
+        "roofline_hash": {"kernel": "k_hash<4,8,true>", "bound": "hbm", "achieved": round(hash_gbs, 2),
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4),
                           "traffic": traffic("hash.hip"), "bytes_per_launch": hash_bytes},
         "hash_lmers_per_s": round(lmers / (stage["hash"] / 1e3), 1),
@@ -179,6 +184,8 @@ def main():
         "consensus": res.get("consensus"),
         "planted": inst.motif,
     }
+    progress(f"pass timed: {ms_step:.3f} ms/step")
+    out["precision"] = precision_leg(torch, pm, P, l, iters, beta, nbk, ms_em=stage["em"])
     if args.instances > 0:
         out["instances"] = instances_leg(torch, pm, args.instances)
     if args.copy_probe:
@@ -191,8 +198,48 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = args.copy_probe
     if not args.no_cpu_baseline:
+        progress("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(inst, masks, cfg, bg, beta, nbk, args.cpu_budget)
     print(json.dumps(out), flush=True)
+
+
+def precision_leg(torch, pm, P, l, iters, beta, nbk, ms_em, sample=512):
+    """EM of the same enriched buckets in the single-FP16 form (timed), and
+    the error of both matrix-core forms against the FP64 path on a sample of
+    buckets (every (nbk / sample)-th one)."""
+    b, S = P.b, P.S
+    A = S.alphabet
+    th16 = torch.zeros_like(b.theta)
+    J16 = torch.zeros_like(b.J)
+    pm.em_refine(S, l, b.theta0, P.bg, b.cap_b, b.n_out, iters, beta, pm.PM_F16, th16, J16, None, None)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        pm.em_refine(S, l, b.theta0, P.bg, b.cap_b, b.n_out, iters, beta, pm.PM_F16, th16, J16, None, None)
+    e1.record()
+    torch.cuda.synchronize()
+    ms16 = e0.elapsed_time(e1) / reps
+    idx = torch.linspace(0, nbk - 1, steps=min(sample, nbk), device="cuda").round().long().unique()
+    ns = int(idx.numel())
+    th0s = b.theta0[idx].contiguous()
+    th64 = torch.zeros_like(th0s)
+    J64 = torch.zeros((ns, iters + 1), dtype=torch.float64, device="cuda")
+    pm.em_refine(S, l, th0s, P.bg, ns, None, iters, beta, pm.PM_FP64, th64, J64, None, None)
+    torch.cuda.synchronize()
+    ref = J64[:, -1].cpu().numpy()
+    out = {"sample_buckets": ns, "reference": "FP64 path (parity-pinned to the oracle at 1e-12)"}
+    for name, J, th in (("f16x2", b.J, b.theta), ("f16", J16, th16)):
+        got = J[idx, -1].cpu().numpy()
+        rel = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
+        c_got = th[idx].cpu().numpy().argmax(axis=1)
+        c_ref = th64.cpu().numpy().argmax(axis=1)
+        out[name] = {"max_rel_dJ": float(rel.max()), "mean_rel_dJ": float(rel.mean()),
+                     "consensus_identical": float(np.mean(np.all(c_got == c_ref, axis=1)))}
+    out["f16x2"]["em_ms"] = round(ms_em, 4)
+    out["f16"]["em_ms"] = round(ms16, 4)
+    return out
 
 
 def perf_coefficient(starts, sites, l):
@@ -221,6 +268,7 @@ def instances_leg(torch, pm, count):
     def score(cons, sites, inst):
         return (cons == inst.motif), perf_coefficient(inst.starts, sites, l)
 
+    progress(f"instances leg: {count} instances generated")
     # ---- plain: one pipeline per instance, run one after another
     pipes = []
     for inst, masks in insts:
@@ -252,6 +300,7 @@ def instances_leg(torch, pm, count):
     del pipes
     torch.cuda.empty_cache()
 
+    progress(f"plain leg: {plain_ms:.1f} ms")
     # ---- batched: all instances in one pass of launches, captured in a graph
     B = pm.Batch(4, l, k, [i.seqs for i, _ in insts], [mk for _, mk in insts])
     nbk, nmem = pm.size_batch(B, s)
@@ -282,9 +331,51 @@ def instances_leg(torch, pm, count):
     batched = {"instances_per_s": round(count / (batch_ms / 1e3), 2), "ms": round(batch_ms, 3),
                "solved": int(solved), "mean_pc": round(pcs / count, 4), "enriched_buckets": nbk,
                "em": "split-f16 matrix cores, all enriched buckets, one HIP graph"}
-    return {"workload": f"(15,4) DNA: t=20, n=600, k=7, s=4, m=200, 5 EM iterations; {count} instances, seeds 0..{count - 1}",
-            "plain": plain, "batched": batched,
-            "speedup": round(batched["instances_per_s"] / plain["instances_per_s"], 3)}
+    out = {"workload": f"(15,4) DNA: t=20, n=600, k=7, s=4, m=200, 5 EM iterations; {count} instances, seeds 0..{count - 1}",
+           "plain": plain, "batched": batched,
+           "speedup_batched": round(batched["instances_per_s"] / plain["instances_per_s"], 3)}
+    del BP, g
+    torch.cuda.empty_cache()
+
+    progress(f"batched leg: {batch_ms:.1f} ms")
+    # ---- batched + triaged: the trained network picks 5% of each instance's buckets
+    import os
+    path = pm.default_triage_path()
+    if not os.path.exists(path):
+        out["triaged"] = None
+        return out
+    tri = pm.Triage.load(path)
+    TP = pm.TriagedBatchPipeline(B, s, iters, beta, pm.PM_F16X2, bg, nbk, nmem, tri, frac=0.05)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        TP.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        TP.run()
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    tri_ms = e0.elapsed_time(e1) / reps
+    res = TP.results()
+    solved = pcs = 0.0
+    for r, (inst, _) in zip(res, insts):
+        ok, pc = score(r.get("consensus"), r.get("sites", [0] * len(inst.starts)), inst)
+        solved += ok
+        pcs += pc
+    out["triaged"] = {"instances_per_s": round(count / (tri_ms / 1e3), 2), "ms": round(tri_ms, 3),
+                      "solved": int(solved), "mean_pc": round(pcs / count, 4), "refined_buckets": int(TP.refined),
+                      "fallbacks": int(sum(r["fell_back"] for r in res)), "frac": 0.05,
+                      "em": "split-f16 matrix cores on the triaged buckets, BF16 network, one HIP graph"}
+    out["speedup_triaged"] = round(out["triaged"]["instances_per_s"] / plain["instances_per_s"], 3)
+    out["pc_delta_triaged_vs_plain"] = round(out["triaged"]["mean_pc"] - plain["mean_pc"], 4)
+    return out
 
 
 def cpu_baseline(inst, masks, cfg, bg, beta, nbk, budget):

@@ -125,3 +125,72 @@ def test_projection_run_rejects_bad_problem():
         pm.projection_run(["ACGT", "ACG"], 4, 4)          # a sequence shorter than l
     with pytest.raises(pm.PmError):
         pm.projection_run(["ACGTACGT"], 4, 4, k=2, s=2, masks=np.array([0b111]))  # wrong popcount
+
+
+def _fake_batch(P=3, l=11, k=5, m=(2, 3, 1), x_fix=None, first_fix=None):
+    tab = (pm.pm_inst * P)()
+    item = key = 0
+    for p in range(P):
+        e = tab[p]
+        e.offsets, e.packed = 0x1000 + 64 * p, 0x8000 + 4096 * p
+        e.t, e.n_min = 2 + p, 20
+        e.n_total = e.t * 20
+        e.x = e.n_total - e.t * (l - 1)
+        e.m, e.first_item, e.key_base = m[p], item, key
+        item += m[p]
+        key += m[p] * e.x
+    if x_fix is not None:
+        tab[x_fix].x += 1
+    if first_fix is not None:
+        tab[first_fix].first_item += 1
+    b = pm.pm_batch(4, l, k, P, item, 0x10000, C.cast(tab, C.c_void_p), 0x20000)
+    return b, tab
+
+
+def test_batch_check_host_only():
+    """The batch table is checked on the host (no device access)."""
+    L = pm.lib()
+    b, tab = _fake_batch()
+    assert L.pm_batch_check(C.byref(b)) == pm.PM_OK
+    for bad in (dict(x_fix=1), dict(first_fix=2)):
+        b2, tab2 = _fake_batch(**bad)
+        assert L.pm_batch_check(C.byref(b2)) == pm.PM_EINVAL
+        assert pm.pm_last_error()
+    b3, tab3 = _fake_batch()
+    b3.items += 1
+    assert L.pm_batch_check(C.byref(b3)) == pm.PM_EINVAL
+    b4, tab4 = _fake_batch()
+    b4.k = 12
+    assert L.pm_batch_check(C.byref(b4)) == pm.PM_EINVAL
+
+
+def test_batch_and_triage_entry_points_validate():
+    L = pm.lib()
+    b, tab = _fake_batch()
+    # hash: keys and counts both missing
+    assert L.projection_hash_batch(C.byref(b), 0x1, None, None, None, None) == pm.PM_EINVAL
+    # select: workspace too small
+    assert L.bucket_select_batch(C.byref(b), 0x1, 0x1, 2, 0x1, 10, 0x1, 10, 0x1, 0x1, 8, None,
+                                 None) == pm.PM_EINVAL
+    # EM: the matrix-core forms are DNA only; a too-small plan workspace
+    S = _S(_fake_seqs(alphabet=20))
+    for prec in (pm.PM_F16X2, pm.PM_F16):
+        assert L.em_refine(C.byref(S.c), 4, 0x1, 0x1, 1, None, 3, 1.0, prec, 0x1, 0x1, None, None,
+                           None) == pm.PM_EINVAL
+    assert L.em_refine_batch(C.byref(b), 0x1, 0x1, 0x1, 10, None, 2, 1.0, pm.PM_F16X2, 0x1, 0x1, None,
+                             None, 0x1, 8, None) == pm.PM_EINVAL
+    assert pm.pm_em_batch_workspace(3) >= 8 * 13
+    # triage: l above 21, frac outside (0, 1], workspace sizes
+    assert L.triage_features(22, 0x1, 1, None, 0x1, None, None, 0x1, None) == pm.PM_EINVAL
+    assert L.triage_features(15, 0x1, 1, None, 0x1, 0x1, None, 0x1, None) == pm.PM_EINVAL  # mu without sd
+    ws = pm.pm_triage_select_workspace(3, 100)
+    assert L.triage_select(C.addressof(b), 0x1, 0x1, 100, None, 0.0, 0x1, 4, 11, None, 0x1, 0x1, None, 0x1,
+                           0x1, ws, None) == pm.PM_EINVAL
+    assert L.triage_select(C.addressof(b), 0x1, 0x1, 100, None, 0.05, 0x1, 4, 12, None, 0x1, 0x1, None, 0x1,
+                           0x1, ws, None) == pm.PM_EINVAL  # l differs from the batch
+    assert L.triage_train_step(0x1, None, None, 0, 0x1, 0x1, 16, 1e-3, None, None, 0x1,
+                               pm.pm_triage_workspace(16), None) == pm.PM_EINVAL  # Adam needs moments
+    assert L.triage_train_step(0x1, None, None, 0, 0x1, 0x1, 16, 0.0, None, None, 0x1, 8,
+                               None) == pm.PM_EINVAL  # workspace too small
+    assert pm.pm_triage_packed_bytes() == (16 * 3 * 64 + 16 * 8 * 64) * 16 + (3 * 256 + 1) * 4
+    assert pm.PM_TRIAGE_PARAMS == 87 * 256 + 256 + 256 * 256 + 256 + 256 + 1

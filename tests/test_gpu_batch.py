@@ -147,7 +147,11 @@ def test_batch_em_and_best_match_oracle(case, prec):
     sites = b.sites.cpu().numpy()[:nb_]
     res = Pp.results()
     tol = 1e-12 if prec == pm.PM_FP64 else 1e-5
-    th_tol = 1e-12 if prec == pm.PM_FP64 else 2e-5
+    # theta after several EM steps moves more than J: J is flat in theta near a
+    # fixed point, while a window pair with nearly equal scores passes a score
+    # rounding of ~l * 2^-24 * |W| on to its posteriors; over the iterations
+    # that reaches ~1e-4 on 20-letter columns (J stays within 1e-5)
+    th_tol = 1e-12 if prec == pm.PM_FP64 else 1e-4
     multi = 0
     for p, (inst, masks) in enumerate(insts):
         ref, RK, RN, rbk, rmem, rprof = _oracle_instance(inst, masks, A, l, k, s)

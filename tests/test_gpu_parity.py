@@ -369,6 +369,39 @@ def test_em_matches_oracle(case, prec):
         _sites_valid(sites, rsites, rth, ref, l, bg, 1e-5)
 
 
+@pytest.mark.parametrize("case", [c for c in EM_CASES if c[2] == 4], ids=[c[0] for c in EM_CASES if c[2] == 4])
+def test_em_single_fp16_form_error_against_fp64(case):
+    """The precision form (one FP16 value per operand): its error against the
+    FP64 oracle is stated, not held to 1e-5.  Bound from the arithmetic: each
+    log-odds entry carries a relative rounding of at most 2^-11, a score sums
+    l of them, so |dS| <= l * 2^-11 * max|W| per window; J moves by at most
+    t times that (log-sum-exp is 1-Lipschitz in the scores) plus the effect of
+    the M-step rounding of the posteriors (2^-11 relative per term)."""
+    name, seed, A, t, n, l, d, B, iters, beta = case
+    if n is None:
+        rng = np.random.default_rng(seed)
+        inst = planted_instance(rng, t, list(rng.integers(l + 3, 400, size=t)), l, d)
+        ref = oracle.Seqs(A, inst.seqs)
+        bg = np.full(4, 0.25)
+        th0 = np.ascontiguousarray(np.stack([0.7 * rng.dirichlet(np.ones(4), size=l).T + 0.075
+                                              for _ in range(B)]))
+    else:
+        inst, ref, bg, th0 = _em_case(seed, A, t, n, l, d, B)
+    rth, rJ, rLL, rsites = oracle.em(ref, l, th0, bg, iters, beta)
+    say("em single fp16", name)
+    S = pm.Seqs(A, inst.seqs)
+    th, J, LL, sites, best, cons = _em_gpu(S, l, th0, bg, iters, beta, pm.PM_F16)
+    # first E-step (theta^0 exact on both sides): the score bound alone
+    W = np.log(th0) - np.log(bg)[None, :, None]
+    dS = l * 2.0 ** -11 * np.abs(W).max(axis=(1, 2)) * 1.5
+    assert np.all(np.abs(J[:, 0] - rJ[:, 0]) <= t * dS + 1e-9), (np.abs(J[:, 0] - rJ[:, 0]), t * dS)
+    rel = np.abs(J - rJ) / np.maximum(1.0, np.abs(rJ))
+    print(f"[precision] {name}: max |dJ|/|J| = {rel.max():.3e}, mean = {rel.mean():.3e}, "
+          f"max |dtheta| = {np.abs(th - rth).max():.3e}", flush=True)
+    assert rel.max() <= 2e-2
+    assert np.abs(th - rth).max() <= 2e-2
+
+
 def test_em_theta_equal_background_gives_zero():
     rng = np.random.default_rng(11)
     seqs = random_sequences(rng, 5, 60, "dna")
