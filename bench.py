@@ -28,8 +28,8 @@ FP16_MFMA_PEAK = 2500.0      # TFLOP/s, MI355X dense FP16 matrix cores
 # profiles/hbm_traffic_dna_18-6_m5000.md (copy-calibrated), valid only while
 # the kernel source is the one they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "hash.hip": ("4e338f9a0a0a036d", 1.779e9),
-    "em_mfma.hip": ("1ba7acbb0d2af902", 0.455e9 + 0.667e9),
+    "hash.hip": ("979a700729f9719e", 1.776e9),
+    "em_mfma.hip": ("153203918e1b2405", 0.364e9 + 0.607e9),
 }
 
 

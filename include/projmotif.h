@@ -264,16 +264,20 @@ int em_best_batch(const pm_batch *B, const pm_bucket *buckets, const double *J, 
  *
  * An addition to the paper's method, which refines every enriched bucket
  * (Sec. 5.1): a small network scores every bucket from its profile, EM refines
- * only the best-scored fraction of each instance, and an instance whose best
- * refined objective per sequence stays below a threshold has all its other
- * buckets refined too.  DNA only, l <= 21.
+ * only the best-scored fraction of each instance, and an instance whose refined
+ * winner does not stand out from the other refined buckets (a z-score of its
+ * objective below a threshold) has all its other buckets refined too.  DNA
+ * only, l <= 21.
  *
  * Network: 87 inputs -> 256 -> 256 -> 1, ReLU after both hidden layers.  FP32
  * parameters in one flat vector of PM_TRIAGE_PARAMS floats:
  *   W1 [87][256], b1 [256], W2 [256][256], b2 [256], w3 [256][1], b3 [1]
  * (W[i][o]: input i to output o).  Inputs of a bucket (feature index):
- *   4p + c (p < 21, c < 4)  frequency of letter c in column p of the bucket's
- *                           profile (profile / size; 0 for p >= l)
+ *   4r + j (r < 21, j < 4)  the j-th largest letter frequency (profile / size)
+ *                           of the r-th column, columns in decreasing
+ *                           lexicographic order of their sorted counts; 0 for
+ *                           r >= l (which letters and positions agree says
+ *                           nothing of a motif: the projection is random)
  *   84  ln(size); 85  background entropy in bits; 86  the largest column
  *   information content in bits, sum_c f log2(f / bg_c)
  * each optionally standardised, (v - mu[i]) / sd[i]. */
@@ -324,17 +328,20 @@ int triage_select(const pm_batch *Bt, const pm_bucket *buckets, const float *sco
                   uint8_t *taken, pm_bucket *sel_buckets, double *sel_theta0, int64_t *sel_index,
                   int64_t *n_sel, void *ws, size_t ws_bytes, void *stream);
 
-/* Fallback after EM of the triaged buckets: an instance whose winner (best,
- * device int64 [P], from em_best / em_best_batch on the triaged list) has
- * J(theta^iters) / t below `threshold`, or that has no winner, gets all its
- * buckets not taken by triage_select compacted as above; fell_back device
- * int32 [P] or NULL.  Same ws as the preceding triage_select; t_single is t
- * when Bt is NULL. */
+/* Fallback after EM of the triaged buckets (list 1: sel1 / n_sel1 as written
+ * by triage_select, best device int64 [P] and J device [n_sel1][iters+1] from
+ * em_best / em_best_batch and em_refine on it).  Per instance, z = (J_w - mean)
+ * / sd of the winner's J(theta^iters) among the J of every bucket of the
+ * instance in list 1 (0 when sd = 0, -inf without a winner); an instance with
+ * z below `threshold` gets all its buckets not taken by triage_select
+ * compacted as above.  fell_back device int32 [P] or NULL; z_out device
+ * double [P] or NULL.  Same ws as the preceding triage_select. */
 int triage_fallback_select(const pm_batch *Bt, const pm_bucket *buckets, int64_t B, const int64_t *n_dev,
-                           int32_t t_single, const int64_t *best, const double *J, int32_t iters,
-                           double threshold, const double *theta0, int32_t alphabet, int32_t l, uint8_t *taken,
-                           pm_bucket *sel_buckets, double *sel_theta0, int64_t *sel_index, int64_t *n_sel,
-                           int32_t *fell_back, void *ws, size_t ws_bytes, void *stream);
+                           const pm_bucket *sel1, const int64_t *n_sel1, const int64_t *best, const double *J,
+                           int32_t iters, double threshold, const double *theta0, int32_t alphabet, int32_t l,
+                           uint8_t *taken, pm_bucket *sel_buckets, double *sel_theta0, int64_t *sel_index,
+                           int64_t *n_sel, int32_t *fell_back, double *z_out, void *ws, size_t ws_bytes,
+                           void *stream);
 
 /* Per instance, the better of the triaged winner (list 1) and the fallback
  * winner (list 2, or best2 NULL): larger J(theta^iters), lower original bucket

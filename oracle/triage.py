@@ -8,9 +8,14 @@ profile column in bits relative to the background, the Shannon entropy of the
 background, the chain rule for the gradients, and Adam (Kingma and Ba, 2015).
 Only tests/ may import it.  It shares no code with the GPU path.
 
-Feature vector of a DNA bucket (87 values; the PWM block is padded to l_max =
-21 columns, left-aligned, zeros after column l - 1):
-    [p * 4 + c] for p < 21, c < 4 : profile frequency f_cp = count_cp / size
+Feature vector of a DNA bucket (87 values).  The PWM block is the profile's
+frequencies in a canonical order: within a column the four letter frequencies
+in decreasing order, and the columns in decreasing lexicographic order of
+those sorted counts; padded to l_max = 21 columns with zeros.  Which letters
+and which motif positions carry the agreement says nothing about whether the
+bucket holds motif copies (the projection picks the positions at random), so
+the network sees the agreement pattern only.
+    [r * 4 + j] for r < 21, j < 4 : j-th largest frequency of the r-th column
     [84]  ln(size)
     [85]  background entropy  -sum_c bg_c log2 bg_c        (bits)
     [86]  max over columns of sum_c f_cp log2(f_cp / bg_c) (bits; 0 log 0 = 0)
@@ -36,9 +41,11 @@ def features(profile: np.ndarray, bg: np.ndarray) -> np.ndarray:
     for b in range(B):
         size = profile[b, :, 0].sum()
         f = profile[b] / size
-        for p in range(l):
-            for c in range(4):
-                out[b, 4 * p + c] = f[c, p]
+        cols = sorted((tuple(sorted((int(profile[b, c, p]) for c in range(4)), reverse=True))
+                       for p in range(l)), reverse=True)
+        for r, col in enumerate(cols):
+            for j in range(4):
+                out[b, 4 * r + j] = col[j] / size
         out[b, 84] = math.log(size)
         out[b, 85] = -sum(v * math.log2(v) for v in bg if v > 0)
         ic = []
@@ -147,4 +154,22 @@ def unflat(v: np.ndarray, sizes=(N_IN, HIDDEN, HIDDEN, 1)) -> list:
         o += a * b
         out.append(np.asarray(v[o:o + b], dtype=np.float64).copy())
         o += b
+    return out
+
+
+def winner_z(J: np.ndarray, group: np.ndarray, winner: dict) -> dict:
+    """Fallback statistic per group (instance): the z-score of the winner's
+    objective among the objectives of every refined bucket of the group,
+    (J_w - mean) / sd with the population deviation; 0 when sd = 0; -inf
+    for a group without a winner.  winner maps group -> index into J."""
+    out = {}
+    for gval in np.unique(group):
+        v = J[group == gval]
+        w = winner.get(gval, -1)
+        if w is None or w < 0:
+            out[gval] = -math.inf
+            continue
+        mu = v.mean()
+        sd = math.sqrt(np.mean((v - mu) ** 2))
+        out[gval] = (J[w] - mu) / sd if sd > 0 else 0.0
     return out

@@ -135,8 +135,8 @@ def lib():
         "triage_train_step": (C.c_int, [P, P, P, i32, P, P, i32, C.c_float, P, P, P, sz, P]),
         "pm_triage_select_workspace": (sz, [i32, i64]),
         "triage_select": (C.c_int, [C.c_void_p, P, P, i64, P, dbl, P, i32, i32, P, P, P, P, P, P, sz, P]),
-        "triage_fallback_select": (C.c_int, [C.c_void_p, P, i64, P, i32, P, P, i32, dbl, P, i32, i32, P, P,
-                                             P, P, P, P, P, sz, P]),
+        "triage_fallback_select": (C.c_int, [C.c_void_p, P, i64, P, P, P, P, P, i32, dbl, P, i32, i32, P, P,
+                                             P, P, P, P, P, P, sz, P]),
         "triage_merge_best": (C.c_int, [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -315,12 +315,13 @@ def triage_select(Bt, buckets, score, B, n_dev, frac, theta0, alphabet, l, taken
                                _ptr(n_sel), _ptr(ws), ws_bytes, _stream(stream)))
 
 
-def triage_fallback_select(Bt, buckets, B, n_dev, t_single, best, J, iters, threshold, theta0, alphabet, l, taken,
-                           sel_buckets, sel_theta0, sel_index, n_sel, fell_back, ws, ws_bytes, stream=None):
-    _check(lib().triage_fallback_select(_batch_ptr(Bt), _ptr(buckets), B, _ptr(n_dev), t_single, _ptr(best), _ptr(J),
-                                        iters, threshold, _ptr(theta0), alphabet, l, _ptr(taken), _ptr(sel_buckets),
-                                        _ptr(sel_theta0), _ptr(sel_index), _ptr(n_sel), _ptr(fell_back), _ptr(ws),
-                                        ws_bytes, _stream(stream)))
+def triage_fallback_select(Bt, buckets, B, n_dev, sel1, n_sel1, best, J, iters, threshold, theta0, alphabet, l,
+                           taken, sel_buckets, sel_theta0, sel_index, n_sel, fell_back, z_out, ws, ws_bytes,
+                           stream=None):
+    _check(lib().triage_fallback_select(_batch_ptr(Bt), _ptr(buckets), B, _ptr(n_dev), _ptr(sel1), _ptr(n_sel1),
+                                        _ptr(best), _ptr(J), iters, threshold, _ptr(theta0), alphabet, l, _ptr(taken),
+                                        _ptr(sel_buckets), _ptr(sel_theta0), _ptr(sel_index), _ptr(n_sel),
+                                        _ptr(fell_back), _ptr(z_out), _ptr(ws), ws_bytes, _stream(stream)))
 
 
 def triage_merge_best(P, alphabet, l, iters, best1, index1, J1, theta1, best2, index2, J2, theta2, best_out,
@@ -691,8 +692,9 @@ class Triage:
                  threshold=np.float64(self.threshold), meta=json.dumps(self.meta))
 
     def threshold_for(self, l: int) -> float:
-        """Fallback threshold for motif length l: the per-length value from
-        training when there is one, else the pooled one."""
+        """Fallback threshold (z-score of the triaged winner's objective among
+        the refined buckets of its instance) for motif length l: the
+        per-length value from training when there is one, else the pooled one."""
         per = self.meta.get("thresholds_by_l", {})
         return float(per.get(str(l), per.get(l, self.threshold)))
 
@@ -726,6 +728,7 @@ class TriagedBatchPipeline(BatchPipeline):
         self.sel_ws_bytes = pm_triage_select_workspace(B.P, cb)
         self.sel_ws = z((self.sel_ws_bytes + 7) // 8, dt=torch.int64)
         self.fell_back = z(B.P)
+        self.z = z(B.P, dt=torch.float64)
         self.lists = []
         for _ in range(2):
             self.lists.append(dict(
@@ -748,9 +751,10 @@ class TriagedBatchPipeline(BatchPipeline):
                       self.taken, L1["buckets"], L1["theta0"], L1["index"], L1["n"], self.sel_ws, self.sel_ws_bytes,
                       stream)
         self._refine_list(L1, stream)
-        triage_fallback_select(B, b.buckets, b.cap_b, b.n_out, 0, L1["best"], L1["J"], self.iters,
-                               self.threshold, b.theta0, B.alphabet, B.l, self.taken, L2["buckets"], L2["theta0"],
-                               L2["index"], L2["n"], self.fell_back, self.sel_ws, self.sel_ws_bytes, stream)
+        triage_fallback_select(B, b.buckets, b.cap_b, b.n_out, L1["buckets"], L1["n"], L1["best"], L1["J"],
+                               self.iters, self.threshold, b.theta0, B.alphabet, B.l, self.taken, L2["buckets"],
+                               L2["theta0"], L2["index"], L2["n"], self.fell_back, self.z, self.sel_ws,
+                               self.sel_ws_bytes, stream)
         self._refine_list(L2, stream)
         triage_merge_best(B.P, B.alphabet, B.l, self.iters, L1["best"], L1["index"], L1["J"], L1["theta"],
                           L2["best"], L2["index"], L2["J"], L2["theta"], b.best, b.consensus, stream)
@@ -771,10 +775,11 @@ class TriagedBatchPipeline(BatchPipeline):
         i1, i2 = L1["index"].cpu().numpy(), L2["index"].cpu().numpy()
         bb1, bb2 = L1["best"].cpu().numpy(), L2["best"].cpu().numpy()
         fb = self.fell_back.cpu().numpy()
+        zz = self.z.cpu().numpy()
         n1, n2 = int(L1["n"].item()), int(L2["n"].item())
         out = []
         for p in range(self.B.P):
-            r = dict(best=int(best[p]), fell_back=bool(fb[p]))
+            r = dict(best=int(best[p]), fell_back=bool(fb[p]), z=float(zz[p]))
             if best[p] >= 0:
                 r["consensus"] = bytes(cons[p, :l]).decode()
                 if bb1[p] >= 0 and i1[bb1[p]] == best[p]:

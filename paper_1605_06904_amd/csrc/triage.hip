@@ -34,6 +34,25 @@ __device__ __forceinline__ int64_t valid_count(const int64_t *n_dev, int64_t B)
 }
 
 // ---------------------------------------------------------------- features
+// The PWM block in canonical order: letter counts of a column sorted in
+// decreasing order, columns in decreasing lexicographic order of those sorted
+// counts (equal keys are equal columns, so the order is unique), as
+// frequencies; zeros past column l - 1.
+__device__ __forceinline__ void cswap_desc(uint32_t &x, uint32_t &y)
+{
+    const uint32_t a = x > y ? x : y, b = x > y ? y : x;
+    x = a;
+    y = b;
+}
+
+__device__ __forceinline__ bool lex_greater(const uint32_t (&a)[4], const uint32_t (&b)[4])
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (a[j] != b[j]) return a[j] > b[j];
+    return false;
+}
+
 __global__ void k_tri_features(const uint32_t *__restrict__ prof, int64_t B, const int64_t *n_dev, int l,
                                const double *__restrict__ bg, const float *mu, const float *sd,
                                float *__restrict__ feat)
@@ -47,14 +66,44 @@ __global__ void k_tri_features(const uint32_t *__restrict__ prof, int64_t B, con
     double H = 0, icmax = -INFINITY;
     for (int c = 0; c < 4; ++c)
         if (bg[c] > 0) H -= bg[c] * log2(bg[c]);
+    uint32_t sc[kLmax][4];
+#pragma unroll
     for (int p = 0; p < kLmax; ++p) {
-        double ic = 0;
-        for (int c = 0; c < 4; ++c) {
-            const double f = (p < l && size > 0) ? P[c * l + p] / size : 0.0;
-            put(4 * p + c, f);
-            if (f > 0) ic += f * log2(f / bg[c]);
+        uint32_t a[4] = {0u, 0u, 0u, 0u};
+        if (p < l) {
+            double ic = 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                a[c] = P[c * l + p];
+                const double f = size > 0 ? a[c] / size : 0.0;
+                if (f > 0) ic += f * log2(f / bg[c]);
+            }
+            icmax = ic > icmax ? ic : icmax;
         }
-        if (p < l) icmax = ic > icmax ? ic : icmax;
+        cswap_desc(a[0], a[1]);
+        cswap_desc(a[2], a[3]);
+        cswap_desc(a[0], a[2]);
+        cswap_desc(a[1], a[3]);
+        cswap_desc(a[1], a[2]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sc[p][j] = a[j];
+    }
+    uint32_t used = 0;
+    for (int r = 0; r < kLmax; ++r) {
+        uint32_t best[4] = {0u, 0u, 0u, 0u};
+        int bi = -1;
+        if (r < l) {
+#pragma unroll
+            for (int p = 0; p < kLmax; ++p)
+                if (p < l && !((used >> p) & 1u) && (bi < 0 || lex_greater(sc[p], best))) {
+                    bi = p;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) best[j] = sc[p][j];
+                }
+            used |= 1u << bi;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) put(4 * r + j, (r < l && size > 0) ? best[j] / size : 0.0);
     }
     // an empty profile (a bucket cut off by a capacity) gets all-zero raw features
     put(84, size > 0 ? log(size) : 0.0);
@@ -465,19 +514,59 @@ __global__ void k_tsel_mode(int P, SelView v, int32_t mode)
     if (p < P) v.mode[p] = mode;
 }
 
-// fallback decision: an instance whose best refined J per sequence is below
-// the threshold (or that refined nothing) gets every other bucket refined
-__global__ void k_tsel_fallback(int P, const pm_inst *inst, int t_single, const int64_t *best, const double *J,
-                                int iters, double threshold, SelView v, int32_t *fell_back)
+// fallback decision, one workgroup per instance: the z-score of the triaged
+// winner's J among the J of every bucket the instance refined (list 1); an
+// instance whose winner does not stand out by the threshold (or that refined
+// nothing) gets every other bucket refined
+__device__ __forceinline__ double block_sum_f64(double v, double *red)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    const int t = inst ? inst[p].t : t_single;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256) k_tsel_fallback(int P, const pm_inst *inst, const pm_bucket *sel1,
+                                                       const int64_t *n_sel1, const int64_t *best, const double *J,
+                                                       int iters, double threshold, SelView v, int32_t *fell_back,
+                                                       double *z_out)
+{
+    __shared__ double red[4];
+    const int p = blockIdx.x;
+    const int64_t n1 = *n_sel1;
+    int64_t r[2] = {0, n1};
+    if (inst) {
+        for (int side = 0; side < 2; ++side) {
+            const int64_t item = (int64_t)inst[p].first_item + (side ? inst[p].m : 0);
+            int64_t lo = 0, hi = n1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if ((int64_t)sel1[mid].trial < item) lo = mid + 1;
+                else hi = mid;
+            }
+            r[side] = lo;
+        }
+    }
+    const int64_t n = r[1] - r[0];
+    double s = 0;
+    for (int64_t b = r[0] + threadIdx.x; b < r[1]; b += 256) s += J[b * (iters + 1) + iters];
+    const double mean = n > 0 ? block_sum_f64(s, red) / (double)n : 0.0;
+    double q = 0;
+    for (int64_t b = r[0] + threadIdx.x; b < r[1]; b += 256) {
+        const double d = J[b * (iters + 1) + iters] - mean;
+        q += d * d;
+    }
+    const double sd = n > 0 ? sqrt(block_sum_f64(q, red) / (double)n) : 0.0;
+    if (threadIdx.x != 0) return;
     const int64_t bb = best[p];
-    const bool low = bb < 0 || !(J[bb * (iters + 1) + iters] / t >= threshold);
+    double z = -INFINITY;
+    if (bb >= 0) z = sd > 0 ? (J[bb * (iters + 1) + iters] - mean) / sd : 0.0;
+    const bool low = !(z >= threshold);
     const bool any = v.range[2 * p + 1] > v.range[2 * p];
     v.mode[p] = (low && any) ? 1 : 2;
     if (fell_back) fell_back[p] = (low && any) ? 1 : 0;
+    if (z_out) z_out[p] = z;
 }
 
 // per instance: the better of the triaged winner and the fallback winner, as
@@ -685,27 +774,26 @@ extern "C" int triage_select(const pm_batch *Bt, const pm_bucket *buckets, const
 }
 
 extern "C" int triage_fallback_select(const pm_batch *Bt, const pm_bucket *buckets, int64_t B, const int64_t *n_dev,
-                                      int32_t t_single, const int64_t *best, const double *J, int32_t iters,
-                                      double threshold, const double *theta0, int32_t A, int32_t l, uint8_t *taken,
-                                      pm_bucket *sel_buckets, double *sel_theta0, int64_t *sel_index, int64_t *n_sel,
-                                      int32_t *fell_back, void *ws, size_t ws_bytes, void *stream)
+                                      const pm_bucket *sel1, const int64_t *n_sel1, const int64_t *best,
+                                      const double *J, int32_t iters, double threshold, const double *theta0,
+                                      int32_t A, int32_t l, uint8_t *taken, pm_bucket *sel_buckets,
+                                      double *sel_theta0, int64_t *sel_index, int64_t *n_sel, int32_t *fell_back,
+                                      double *z_out, void *ws, size_t ws_bytes, void *stream)
 {
     clear_error();
     int P = 1;
     const float dummy = 0.f;
     int rc = tsel_args(Bt, B, buckets, &dummy, theta0, A, l, sel_buckets, sel_theta0, n_sel, ws, ws_bytes, &P);
     if (rc) return rc;
-    if (!best || !J || !taken || iters < 0) return fail(PM_EINVAL, "NULL buffer");
-    if (!Bt && t_single < 1) return fail(PM_EINVAL, "t must be >= 1");
+    if (!best || !J || !taken || !sel1 || !n_sel1 || iters < 0) return fail(PM_EINVAL, "NULL buffer");
     if (B == 0) return PM_OK;
     hipStream_t st = as_stream(stream);
     const int64_t nblk = (B + kSelBlock - 1) / kSelBlock;
     const SelView v = sel_view(ws, P, nblk);
     const pm_inst *inst = Bt ? Bt->inst : nullptr;
-    const unsigned pg = (unsigned)((P + 255) / 256);
     // ranges are those of the preceding triage_select on the same workspace
-    hipLaunchKernelGGL(k_tsel_fallback, dim3(pg), dim3(256), 0, st, P, inst, t_single, best, J, iters, threshold, v,
-                       fell_back);
+    hipLaunchKernelGGL(k_tsel_fallback, dim3((unsigned)P), dim3(256), 0, st, P, inst, sel1, n_sel1, best, J, iters,
+                       threshold, v, fell_back, z_out);
     tsel_compact(nullptr, Bt ? Bt->item_inst : nullptr, buckets, n_dev, B, taken, v, nblk, theta0, A * l, sel_buckets,
                  sel_theta0, sel_index, n_sel, st);
     PM_LAUNCHED();

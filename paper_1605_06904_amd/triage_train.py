@@ -7,13 +7,20 @@
    the batching shape (t, n, l drawn per instance, d = floor(l/4) + 1,
    k = clamp(l - d - 4, 6, 9), s = 3), each shape class as one batch.
 2. Each refined bucket gives one pair: its features (the library's
-   triage_features) and its post-EM score LLR(theta^iters) / t.
+   triage_features) and its post-EM outcome: 1 when its refinement ends at the
+   motif of its instance's winner (same consensus), else 0 -- what triage must
+   rank.  Winning buckets are rare and are kept up to a third of the pairs.
+   (--label llr: the post-EM LLR(theta^iters) / t standardised within the
+   instance instead.)
 3. Standardise features and scores with the training statistics, train the
    network with the library's FP32 forward/backward and Adam kernels on
    mini-batches, then fold the score standardisation into the last layer.
-4. Fallback threshold per motif length l: the 1st percentile of the winner's
-   J(theta^iters) / t over training instances whose winner is the planted
-   motif (the pooled value for lengths with no such instance).
+4. Fallback threshold per motif length l: run the triaged pipeline (no
+   fallback) over the training instances with the trained network and take
+   the 1st percentile of the triaged winner's z-score (its J among the J of
+   the instance's refined buckets) over the instances whose triaged winner
+   is the planted motif (the pooled value for lengths with no such instance).
+   A z-score carries no scale of t or n, so it transfers across shapes.
 
 Every step of the arithmetic runs in the library's kernels; this module only
 moves arrays, draws the mini-batches and keeps the bookkeeping.
@@ -33,7 +40,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
 
-def _run_full(pm, torch, insts, l, k, s, iters, bg):
+def _run_full(pm, torch, insts, l, k, s, iters, bg, label="winner"):
     """Full path over one shape class: raw features, scores, per-instance
     winners."""
     B = pm.Batch(4, l, k, [i.seqs for i, _ in insts], [mk for _, mk in insts])
@@ -47,9 +54,25 @@ def _run_full(pm, torch, insts, l, k, s, iters, bg):
     torch.cuda.synchronize()
     bk = P.b.buckets[:nb_].cpu().numpy().view(np.uint32)
     inst_of = B.item_inst.cpu().numpy()[bk[:, 0]]
-    t = np.array(B.t)[inst_of]
-    score = P.b.llr[:nb_, -1].cpu().numpy() / t
     res = P.results()
+    if label == "winner":
+        # 1 where the bucket's refinement ends at the instance winner's motif
+        # (same consensus), else 0: the post-EM outcome triage has to rank
+        cons = P.b.theta[:nb_].argmax(dim=1)            # [nb, l] letter codes (label bookkeeping)
+        best = torch.tensor([max(r["best"], 0) for r in res], device="cuda")
+        inst_d = torch.from_numpy(inst_of.astype(np.int64)).cuda()
+        win_cons = cons[best[inst_d]]
+        has = torch.tensor([r["best"] >= 0 for r in res], device="cuda")[inst_d]
+        score = ((cons == win_cons).all(dim=1) & has).float().cpu().numpy()
+    else:
+        t = np.array(B.t)[inst_of]
+        score = P.b.llr[:nb_, -1].cpu().numpy() / t
+        # the network sees a bucket, not its instance (no t, n): keep only the
+        # within-instance part of the score, standardised per instance
+        for p in np.unique(inst_of):
+            sel = inst_of == p
+            mu, sd = score[sel].mean(), score[sel].std()
+            score[sel] = (score[sel] - mu) / (sd if sd > 0 else 1.0)
     winners = []
     for p, (inst, _) in enumerate(insts):
         r = res[p]
@@ -58,17 +81,30 @@ def _run_full(pm, torch, insts, l, k, s, iters, bg):
     return feat.cpu().numpy(), score, winners
 
 
-def collect(pm, torch, seed: int, batch_count: int, batch_m: int, log=print):
+def collect(pm, torch, seed: int, batch_count: int, batch_m: int, label: str = "winner", extra_c1: int = 0,
+            log=print):
     from synth import batch_config, make_config
     bg = np.full(4, 0.25)
-    X, y, win = [], [], []
+    X, y, win, groups = [], [], [], []
     inst, masks = make_config("c2", seed=seed)
     cfg = inst.meta
-    out = _run_full(pm, torch, [(inst, masks)], cfg["l"], cfg["k"], cfg["s"], cfg["iters"], bg)
+    out = _run_full(pm, torch, [(inst, masks)], cfg["l"], cfg["k"], cfg["s"], cfg["iters"], bg, label)
     X.append(out[0])
     y.append(out[1])
     win += out[2]
+    groups.append(([(inst, masks)], cfg["l"], cfg["k"], cfg["s"], cfg["iters"]))
     log(f"(18,6) instance: {len(out[1])} pairs")
+    if extra_c1:
+        # instances of the (15,4) plain shape the network serves (seeds apart
+        # from every evaluation seed)
+        c1 = [make_config("c1", seed=30000 + seed + i) for i in range(extra_c1)]
+        cfg1 = c1[0][0].meta
+        out = _run_full(pm, torch, c1, cfg1["l"], cfg1["k"], cfg1["s"], cfg1["iters"], bg, label)
+        X.append(out[0])
+        y.append(out[1])
+        win += out[2]
+        groups.append((c1, cfg1["l"], cfg1["k"], cfg1["s"], cfg1["iters"]))
+        log(f"(15,4) instances: {extra_c1}, {len(out[1])} pairs")
     insts = batch_config(seed, count=batch_count, m=batch_m)
     classes = {}
     for inst, masks in insts:
@@ -76,14 +112,37 @@ def collect(pm, torch, seed: int, batch_count: int, batch_m: int, log=print):
     for l in sorted(classes):
         group = classes[l]
         meta = group[0][0].meta
-        out = _run_full(pm, torch, group, l, meta["k"], meta["s"], meta["iters"], bg)
+        out = _run_full(pm, torch, group, l, meta["k"], meta["s"], meta["iters"], bg, label)
         if out is None:
             continue
         X.append(out[0])
         y.append(out[1])
         win += out[2]
+        groups.append((group, l, meta["k"], meta["s"], meta["iters"]))
         log(f"batch class l={l}: {len(group)} instances, {len(out[1])} pairs")
-    return X, y, win
+    return X, y, win, groups
+
+
+def triaged_z(pm, torch, tri, groups, frac: float):
+    """(l, z of the triaged winner, triaged winner is the planted motif) for
+    every training instance, from the library's triaged pipeline without
+    fallback."""
+    bg = np.full(4, 0.25)
+    rows = []
+    for insts, l, k, s, iters in groups:
+        B = pm.Batch(4, l, k, [i.seqs for i, _ in insts], [mk for _, mk in insts])
+        nb_, nm_ = pm.size_batch(B, s)
+        if nb_ == 0:
+            continue
+        TP = pm.TriagedBatchPipeline(B, s, iters, 1.0, pm.PM_F16X2, bg, nb_, nm_, tri, frac=frac)
+        TP.threshold = -math.inf
+        TP.run()
+        for r, (inst, _) in zip(TP.results(), insts):
+            if r["best"] >= 0:
+                rows.append((l, r["z"], r.get("consensus") == inst.motif))
+        del TP, B
+        torch.cuda.empty_cache()
+    return rows
 
 
 def train(pm, torch, X, y, epochs: int, batch: int, lr: float, seed: int, log=print):
@@ -134,21 +193,33 @@ def main(argv=None):
     ap.add_argument("--out", default=os.path.join(HERE, "triage_weights.npz"))
     ap.add_argument("--pairs", type=int, default=200000)
     ap.add_argument("--seed", type=int, default=101)
-    ap.add_argument("--batch-count", type=int, default=48)
-    ap.add_argument("--batch-m", type=int, default=60)
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-m", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--mb", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--frac", type=float, default=0.05)
+    ap.add_argument("--label", choices=["winner", "llr"], default="winner")
+    ap.add_argument("--extra-c1", type=int, default=0, help="(15,4) instances added to the training runs")
     args = ap.parse_args(argv)
     import torch
 
     import paper_1605_06904_amd as pm
     t0 = time.time()
     log = lambda *a: print("[triage-train]", *a, flush=True)
-    Xs, ys, win = collect(pm, torch, args.seed, args.batch_count, args.batch_m, log)
+    Xs, ys, win, groups = collect(pm, torch, args.seed, args.batch_count, args.batch_m, args.label, args.extra_c1,
+                                  log)
     X, y = np.concatenate(Xs), np.concatenate(ys)
     rng = np.random.default_rng(args.seed)
-    if len(y) > args.pairs:
+    if args.label == "winner":
+        # winning buckets are rare: keep them up to a third of the pairs
+        pos, neg = np.nonzero(y > 0.5)[0], np.nonzero(y <= 0.5)[0]
+        npos = min(len(pos), args.pairs // 3)
+        keep = np.concatenate([rng.choice(pos, size=npos, replace=False),
+                               rng.choice(neg, size=min(len(neg), args.pairs - npos), replace=False)])
+        log(f"winning buckets: {len(pos)} of {len(y)}; kept {npos}")
+        X, y = X[keep], y[keep]
+    elif len(y) > args.pairs:
         keep = rng.choice(len(y), size=args.pairs, replace=False)
         X, y = X[keep], y[keep]
     log(f"{len(y)} pairs collected in {time.time() - t0:.1f} s")
@@ -163,9 +234,15 @@ def main(argv=None):
     o_w3 = pm.PM_TRIAGE_PARAMS - 1 - n_w3
     params[o_w3:o_w3 + n_w3] *= ysd
     params[-1] = params[-1] * ysd + ymu
-    pooled, per_l = thresholds(win)
-    meta = dict(pairs=int(len(y)), seed=args.seed, epochs=args.epochs, minibatch=args.mb, lr=args.lr,
-                label="LLR(theta^iters)/t", thresholds_by_l=per_l, threshold_pooled=pooled,
+    zrows = triaged_z(pm, torch, pm.Triage(params, mu, sd, -math.inf), groups, args.frac)
+    pooled, per_l = thresholds(zrows)
+    log(f"triaged winners: {len(zrows)}, planted {sum(ok for _, _, ok in zrows)}; full EM winners planted: "
+        f"{sum(ok for _, _, ok in win)} of {len(win)}")
+    meta = dict(pairs=int(len(y)), seed=args.seed, extra_c1=args.extra_c1, epochs=args.epochs, minibatch=args.mb, lr=args.lr,
+                fallback="z-score of the triaged winner's J among the instance's refined buckets",
+                frac=args.frac, triaged_solved=int(sum(ok for _, _, ok in zrows)),
+                label=("1 if the bucket's refinement ends at the instance winner's consensus" if args.label == "winner"
+                       else "LLR(theta^iters)/t, standardised within the instance"), thresholds_by_l=per_l, threshold_pooled=pooled,
                 winners=len(win), solved_winners=int(sum(ok for _, _, ok in win)),
                 seconds=round(time.time() - t0, 1))
     tri = pm.Triage(params, mu, sd, pooled, meta=meta)

@@ -237,23 +237,42 @@ def test_select_matches_oracle_top_fraction(frac):
     assert torch.equal(sel_t[:n], b.theta0[torch.from_numpy(want).cuda()])
     assert np.array_equal(taken.cpu().numpy().astype(bool), keep)
 
-    # fallback: instance p falls back when its winner's J/t is below the
-    # threshold; feed made-up winners
-    best = torch.tensor([0 if p % 2 == 0 else -1 for p in range(B.P)], dtype=torch.int64, device="cuda")
+    # fallback: the z-score of each instance's winner among its list-1
+    # objectives against a threshold; made-up objectives and winners
+    sel_items = sel_b.cpu().numpy().view(np.uint32)[:n, 0]
+    g1 = item_inst[sel_items]
+    Jv = np.round(rng.normal(size=max(n, 1)) * 3, 2)
+    winners = {}
+    for p in range(B.P):
+        idx = np.nonzero(g1 == p)[0]
+        if len(idx) and p % 3 != 2:
+            winners[p] = int(idx[np.argmax(Jv[idx])]) if p % 2 == 0 else int(idx[0])
+    best = torch.tensor([winners.get(p, -1) for p in range(B.P)], dtype=torch.int64, device="cuda")
     J = torch.zeros((max(n, 1), iters + 1), dtype=torch.float64, device="cuda")
-    J[:, -1] = 5.0
+    J[:, -1] = torch.from_numpy(Jv)
+    zref = T.winner_z(Jv[:n], g1, winners)
+    finite = [v for v in zref.values() if np.isfinite(v)]
+    thr = float(np.median(finite)) if finite else 0.0
     fb = torch.zeros(B.P, dtype=torch.int32, device="cuda")
+    zz = torch.zeros(B.P, dtype=torch.float64, device="cuda")
     sel2_b = torch.full((nb_, 4), -1, dtype=torch.int32, device="cuda")
     sel2_t = torch.zeros_like(sel_t)
     sel2_i = torch.full((nb_,), -1, dtype=torch.int64, device="cuda")
     n2 = torch.zeros(1, dtype=torch.int64, device="cuda")
-    thr = 5.0 / B.t[0] + 1e-9  # instance 0 (t = B.t[0]) falls back, the others by their t
-    pm.triage_fallback_select(B, b.buckets, nb_, b.n_out, 0, best, J, iters, thr, b.theta0, 4, 11, taken, sel2_b,
-                              sel2_t, sel2_i, n2, fb, ws, wsb)
+    pm.triage_fallback_select(B, b.buckets, nb_, b.n_out, sel_b, n_sel, best, J, iters, thr, b.theta0, 4, 11, taken,
+                              sel2_b, sel2_t, sel2_i, n2, fb, zz, ws, wsb)
     torch.cuda.synchronize()
     flags = fb.cpu().numpy()
+    zg = zz.cpu().numpy()
     has = np.array([np.any(group == p) for p in range(B.P)])
-    exp_flags = np.array([(p % 2 == 1 or 5.0 / B.t[p] < thr) and has[p] for p in range(B.P)]).astype(int)
+    exp_flags = np.zeros(B.P, dtype=int)
+    for p in range(B.P):
+        zp = zref.get(p, -np.inf)
+        if np.isfinite(zp):
+            assert abs(zg[p] - zp) <= 1e-9 * max(1.0, abs(zp)), (p, zg[p], zp)
+        else:
+            assert zg[p] == -np.inf
+        exp_flags[p] = int(has[p] and not (zp >= thr))
     assert np.array_equal(flags, exp_flags)
     want2 = np.nonzero(~keep & exp_flags[group].astype(bool))[0]
     assert int(n2.item()) == len(want2)
@@ -306,7 +325,11 @@ def test_triaged_pipeline_refines_the_fraction():
     tr = TP.results()
     bk = full.b.buckets.cpu().numpy().view(np.uint32)[:nb_]
     group = B.item_inst.cpu().numpy()[bk[:, 0]]
-    expect = sum(max(1, math.ceil(0.05 * np.sum(group == p))) for p in range(B.P) if np.any(group == p))
-    assert expect <= TP.refined <= expect + 10 * B.P  # ties may add a few
+    # buckets with equal features score equal and ties are all kept: the count
+    # is the oracle's top fraction of the GPU's own scores
+    scores = TP.score_buf.cpu().numpy()[:nb_].astype(np.float64)
+    expect = int(T.top_fraction(scores, group, 0.05).sum())
+    assert TP.refined == expect
+    assert expect >= sum(max(1, math.ceil(0.05 * np.sum(group == p))) for p in range(B.P) if np.any(group == p))
     for p in range(B.P):
         assert not tr[p]["fell_back"]

@@ -22,6 +22,9 @@ def test_features_closed_forms():
         cols = F[b, :4 * l].reshape(l, 4)
         assert np.allclose(cols.sum(axis=1), 1.0)
         assert math.isclose(F[b, 85], 2.0)
+    assert np.allclose(F[1, :4 * l].reshape(l, 4), [[1, 0, 0, 0]] * l)
+    # bucket 2: two pure columns first, then (2,1,1,0)/4
+    assert np.allclose(F[2, :4 * l].reshape(l, 4), [[1, 0, 0, 0], [1, 0, 0, 0], [0.5, 0.25, 0.25, 0]])
     assert math.isclose(F[0, 84], math.log(8)) and math.isclose(F[1, 84], math.log(5))
     assert math.isclose(F[0, 86], 0.0, abs_tol=1e-15)
     assert math.isclose(F[1, 86], 2.0)
@@ -29,6 +32,29 @@ def test_features_closed_forms():
     prof[2, 0, 1:] = 0
     prof[2, :, 1:] = 1
     assert math.isclose(T.features(prof[2:], bg)[0, 86], 0.5)
+
+
+def test_features_canonical_order():
+    """Sorted letters within a column, columns in decreasing order of their
+    sorted counts; permuting positions or renaming letters changes nothing."""
+    rng = np.random.default_rng(5)
+    bg = np.full(4, 0.25)
+    prof = rng.integers(0, 6, size=(4, 4, 9)).astype(float)
+    prof[:, 0, :] += 1
+    # every column must total the bucket size
+    tot = prof.sum(axis=1, keepdims=True)
+    prof[:, 0:1, :] += tot.max() - tot
+    F = T.features(prof, bg)
+    for b in range(4):
+        cols = F[b, :36].reshape(9, 4)
+        assert np.all(np.diff(cols, axis=1) <= 0)          # letters sorted
+        keys = [tuple(c) for c in cols]
+        assert keys == sorted(keys, reverse=True)          # columns sorted
+    perm = rng.permutation(9)
+    lett = rng.permutation(4)
+    G = T.features(prof[:, lett][:, :, perm], bg)
+    assert np.array_equal(F[:, :84], G[:, :84]) and np.allclose(F[:, 84:86], G[:, 84:86])
+    assert np.allclose(F[:, 86], G[:, 86])
 
 
 def test_features_nonuniform_background_entropy():
@@ -144,3 +170,13 @@ def test_flat_roundtrip_and_count():
     assert v.size == 88577
     back = T.unflat(v)
     assert all(np.array_equal(a, b) for a, b in zip(params, back))
+
+
+def test_winner_z_closed_form():
+    J = np.array([1.0, 2.0, 3.0, 10.0, 10.0, 4.0])
+    group = np.array([0, 0, 0, 1, 1, 2])
+    z = T.winner_z(J, group, {0: 2, 1: 3})
+    # group 0: mean 2, population sd sqrt(2/3) -> z = 1 / sqrt(2/3)
+    assert math.isclose(z[0], 1 / math.sqrt(2 / 3))
+    assert z[1] == 0.0                 # equal objectives: sd = 0
+    assert z[2] == -math.inf           # no winner
