@@ -75,7 +75,7 @@ struct HashArgs {
     uint32_t slice_bins; // bins per slice (multiple of 4)
     int hist_words;      // LDS words of histogram
     int seq_cap;         // LDS words reserved for the packed input (0: read from global)
-    int off_cap;         // LDS offsets reserved (0: read from global)
+    int off_cap;         // LDS window starts reserved, t + 1 (0: read offsets from global)
 };
 
 constexpr int kHashThreads = 1024;
@@ -101,22 +101,19 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
 
     uint32_t *hist = smem;
     uint32_t *seq = smem + a.hist_words;
-    int64_t *offs = reinterpret_cast<int64_t *>(seq + ((a.seq_cap + 1) & ~1));
+    int32_t *wst = reinterpret_cast<int32_t *>(seq + a.seq_cap);  // window number of each sequence start
 
     for (int i = tid; i < seq_words; i += kHashThreads) seq[i] = I.packed[i];
     if (a.off_cap)
-        for (int i = tid; i <= I.t; i += kHashThreads) offs[i] = I.offsets[i];
+        for (int i = tid; i <= I.t; i += kHashThreads) wst[i] = (int32_t)(I.offsets[i] - (int64_t)i * (a.l - 1));
     if (a.counts)
         for (int i = tid * 4; i < a.hist_words; i += kHashThreads * 4)
             *reinterpret_cast<uint4 *>(hist + i) = make_uint4(0, 0, 0, 0);
     __syncthreads();
 
-    const uint32_t *W = a.seq_cap ? seq : I.packed;
-    const int64_t *O = a.off_cap ? offs : I.offsets;
-
-    // kept positions, ascending (uniform across the workgroup)
-    // shift of each kept position's 2-bit field in the 64-bit window (DNA), or
-    // the position itself (protein)
+    // kept positions, ascending (uniform across the workgroup): the shift of
+    // each kept position's 2-bit field in the 64-bit window (DNA), or the
+    // position itself (protein)
     int pos[K];
     {
         uint32_t mm = mask;
@@ -128,52 +125,68 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
         }
     }
 
-    const uint64_t slice_base = (uint64_t)slice * a.slice_bins;
+    const uint32_t slice_base = (uint32_t)slice * a.slice_bins;  // |Sigma|^k <= 2^24
     const int64_t kw0 = x * slice / a.nslices, kw1 = x * (slice + 1) / a.nslices;
     uint32_t *keys_j = a.keys ? a.keys + I.key_base + (int64_t)(j - I.first_item) * x : nullptr;
-    const int lane = lane_id();
-    const int64_t lm1 = a.l - 1;
-
-    int i = 0;
-    for (int64_t w = tid; w < x; w += kHashThreads) {
-        while (w >= O[i + 1] - (int64_t)(i + 1) * lm1) ++i;
-        const int64_t P = w + (int64_t)i * lm1;
-        uint32_t key = 0;
-        if (A == 4) {
-            uint32_t hi, lo;
-            dna_window(W, P, hi, lo);
-            const uint64_t win = ((uint64_t)hi << 32) | lo;
-#pragma unroll
-            for (int q = 0; q < K; ++q) key = (key << 2) | ((uint32_t)(win >> pos[q]) & 3u);
-        } else {
-#pragma unroll
-            for (int q = 0; q < K; ++q) key = key * 20u + prot_sym(W, P + pos[q]);
+    auto count = [&](uint32_t key) {
+        const uint32_t bin = key - slice_base;
+        if (bin < a.slice_bins) {
+            if (U16) atomicAdd(hist + (bin >> 1), 1u << ((bin & 1) << 4));
+            else atomicAdd(hist + bin, 1u);
         }
-        if (keys_j && w >= kw0 && w < kw1) __builtin_nontemporal_store(key, keys_j + w);
-        if (a.counts) {
-            const uint64_t bin64 = (uint64_t)key - slice_base;
-            const bool valid = bin64 < a.slice_bins;
-            const uint32_t bin = (uint32_t)bin64;
-            // wave-aggregated atomics: the lanes sharing the first valid lane's
-            // bin add once, the others add one each
-            const uint64_t vb = __ballot(valid);
-            if (vb) {
-                const int leader = __ffsll((unsigned long long)vb) - 1;
-                const uint32_t lb = __shfl(bin, leader);
-                const uint64_t same = __ballot(valid && bin == lb);
-                if (valid) {
-                    if (bin == lb) {
-                        if (lane == leader) {
-                            const uint32_t n = __popcll(same);
-                            if (U16) atomicAdd(hist + (lb >> 1), n << ((lb & 1) << 4));
-                            else atomicAdd(hist + lb, n);
-                        }
-                    } else {
-                        if (U16) atomicAdd(hist + (bin >> 1), 1u << ((bin & 1) << 4));
-                        else atomicAdd(hist + bin, 1u);
-                    }
+    };
+
+    if (a.seq_cap && a.off_cap) {
+        // staged input: every read below is an LDS read, all indices 32-bit
+        // (n_total < 2^31)
+        const uint32_t x32 = (uint32_t)x, lm1 = (uint32_t)(a.l - 1);
+        const uint32_t k0 = (uint32_t)kw0, k1 = (uint32_t)kw1;
+        int i = 0;
+        for (uint32_t w = tid; w < x32; w += kHashThreads) {
+            while ((int32_t)w >= wst[i + 1]) ++i;
+            const uint32_t P = w + (uint32_t)i * lm1;
+            uint32_t key = 0;
+            if (A == 4) {
+                const uint32_t wi = P >> 4, r = (P & 15u) << 1;
+                const uint32_t w0 = seq[wi], w1 = seq[wi + 1], w2 = seq[wi + 2];
+                const uint32_t hi = (uint32_t)((((uint64_t)w0 << 32) | w1) >> (32 - r));
+                const uint32_t lo = (uint32_t)((((uint64_t)w1 << 32) | w2) >> (32 - r));
+                const uint64_t win = ((uint64_t)hi << 32) | lo;
+#pragma unroll
+                for (int q = 0; q < K; ++q) key = (key << 2) | ((uint32_t)(win >> pos[q]) & 3u);
+            } else {
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    const uint32_t g = P + (uint32_t)pos[q];
+                    const uint32_t qq = div6(g);
+                    key = key * 20u + ((seq[qq] >> (27 - 5 * (g - 6u * qq))) & 31u);
                 }
             }
+            if (keys_j && w >= k0 && w < k1) __builtin_nontemporal_store(key, keys_j + w);
+            if (a.counts) count(key);
+        }
+    } else {
+        // large instances: packed input and offsets read from global memory
+        const uint32_t *W = a.seq_cap ? seq : I.packed;
+        const int64_t *O = I.offsets;
+        const int64_t lm1 = a.l - 1;
+        int i = 0;
+        for (int64_t w = tid; w < x; w += kHashThreads) {
+            while (w >= O[i + 1] - (int64_t)(i + 1) * lm1) ++i;
+            const int64_t P = w + (int64_t)i * lm1;
+            uint32_t key = 0;
+            if (A == 4) {
+                uint32_t hi, lo;
+                dna_window(W, P, hi, lo);
+                const uint64_t win = ((uint64_t)hi << 32) | lo;
+#pragma unroll
+                for (int q = 0; q < K; ++q) key = (key << 2) | ((uint32_t)(win >> pos[q]) & 3u);
+            } else {
+#pragma unroll
+                for (int q = 0; q < K; ++q) key = key * 20u + prot_sym(W, P + pos[q]);
+            }
+            if (keys_j && w >= kw0 && w < kw1) __builtin_nontemporal_store(key, keys_j + w);
+            if (a.counts) count(key);
         }
     }
     if (!a.counts) return;
@@ -262,8 +275,8 @@ static int hash_launch(HashArgs &a, int A, int32_t items, int64_t x_max, int64_t
     const bool u16 = x_max < 65536;
     const int lds_max = device_lds_bytes();
     a.seq_cap = nw_max * 4 <= 48 * 1024 ? (int)nw_max : 0;
-    a.off_cap = (t_max + 1) * 8 <= 8 * 1024 ? t_max + 1 : 0;
-    const int fixed = ((a.seq_cap + 1) & ~1) * 4 + a.off_cap * 8;
+    a.off_cap = (t_max + 1) * 4 <= 8 * 1024 ? t_max + 1 : 0;
+    const int fixed = (a.seq_cap + a.off_cap) * 4;
     if (a.counts) {
         const int64_t need_words = u16 ? (a.nb + 1) / 2 : a.nb;
         int64_t budget = (lds_max - fixed) / 4;
