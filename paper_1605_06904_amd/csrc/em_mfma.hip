@@ -35,8 +35,8 @@
 //
 // Work split: a workgroup of four waves takes 64 models (16 per wave) of one
 // instance; the four waves sweep the same windows in step and build the
-// one-hot tables of each window pair together in LDS (double-buffered, one
-// barrier per pair) from the packed instance staged in LDS.
+// one-hot tables of kPPB window pairs together in LDS (double-buffered, one
+// barrier per kPPB pairs) from the packed instance staged in LDS.
 #include <math.h>
 #include <stdlib.h>
 
@@ -84,6 +84,7 @@ __host__ __device__ inline PlanView plan_view(const int64_t *plan, int P)
 }
 
 constexpr int kWaves = 4;  // waves (groups of 16 models) per workgroup
+constexpr int kPPB = 2;    // window pairs whose tables are built per workgroup barrier
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kPOff = 3.0f;
 constexpr float kSlack = 12.0f;
@@ -305,13 +306,19 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
     for (int mt = 0; mt < MT; ++mt) O[mt] = float4v{0.f, 0.f, 0.f, 0.f};
     // the reference starts at the lowest score the model can give
     SeqState st{mlow, 0.f, -INFINITY, 0};
-    for (int a0 = 0; a0 < L; a0 += 32) {
-        PairTables &T = tabs[parity];
+    for (int a0 = 0; a0 < L; a0 += 32 * kPPB) {
+        PairTables *T = tabs + kPPB * parity;
         parity ^= 1;
-        build_tables<!STAGED>(W, a.nwords, s0 + a0, lut, T);
+#pragma unroll
+        for (int u = 0; u < kPPB; ++u)
+            if (a0 + 32 * u < L) build_tables<!STAGED>(W, a.nwords, s0 + a0 + 32 * u, lut, T[u]);
         __syncthreads();
-        if (a0 + 32 <= L) tile_pair<MT, LAST, false, SPLIT>(a0, L, T, Whi, Wlo, O, st);
-        else tile_pair<MT, LAST, true, SPLIT>(a0, L, T, Whi, Wlo, O, st);
+#pragma unroll
+        for (int u = 0; u < kPPB; ++u) {
+            const int b0 = a0 + 32 * u;
+            if (b0 + 32 <= L) tile_pair<MT, LAST, false, SPLIT>(b0, L, T[u], Whi, Wlo, O, st);
+            else if (b0 < L) tile_pair<MT, LAST, true, SPLIT>(b0, L, T[u], Whi, Wlo, O, st);
+        }
     }
     float sr = st.srun;
     sr += __shfl_xor(sr, 16);
@@ -347,7 +354,7 @@ template <int MT, bool STAGED, bool SPLIT>
 __global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(const EmMfmaArgs a0)
 {
     constexpr int LB = Tiles<MT>::LB, PX = Tiles<MT>::PX;
-    __shared__ __align__(16) PairTables tabs[2];
+    __shared__ __align__(16) PairTables tabs[2 * kPPB];
     __shared__ __align__(16) uint2 lut[256];
     __shared__ __align__(16) float accs[kWaves][16][PX][4];
     extern __shared__ __align__(16) uint32_t staged[];
