@@ -28,8 +28,8 @@ FP16_MFMA_PEAK = 2500.0      # TFLOP/s, MI355X dense FP16 matrix cores
 # profiles/hbm_traffic_dna_18-6_m5000.md (copy-calibrated), valid only while
 # the kernel source is the one they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "hash.hip": ("979a700729f9719e", 1.776e9),
-    "em_mfma.hip": ("153203918e1b2405", 0.364e9 + 0.607e9),
+    "hash.hip": ("9ec1b4adfe82aa62", 1.749e9),
+    "em_mfma.hip": ("f7346fc0d97b8d0e", 0.355e9 + 0.615e9),
 }
 
 
@@ -54,6 +54,10 @@ def parse():
                     help="also run one plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--instances", type=int, default=256,
                     help="(15,4) instances for the instances/s leg (0: skip it)")
+    ap.add_argument("--uneven", type=int, default=0,
+                    help="also run the 512-instance uneven batch with this many trials per instance")
+    ap.add_argument("--c5", action="store_true",
+                    help="also run one (21,7) instance (t=50, n=2000, k=9, s=3, m=10000) with and without triage")
     return ap.parse_args()
 
 
@@ -188,6 +192,10 @@ def main():
     out["precision"] = precision_leg(torch, pm, P, l, iters, beta, nbk, ms_em=stage["em"])
     if args.instances > 0:
         out["instances"] = instances_leg(torch, pm, args.instances)
+    if args.uneven > 0:
+        out["uneven_batch"] = uneven_leg(torch, pm, args.uneven)
+    if args.c5:
+        out["triage_21_7"] = c5_leg(torch, pm)
     if args.copy_probe:
         # a plain copy of known size, read once and written once, for scaling
         # the HBM byte counters of the kernels above
@@ -239,6 +247,105 @@ def precision_leg(torch, pm, P, l, iters, beta, nbk, ms_em, sample=512):
                      "consensus_identical": float(np.mean(np.all(c_got == c_ref, axis=1)))}
     out["f16x2"]["em_ms"] = round(ms_em, 4)
     out["f16"]["em_ms"] = round(ms16, 4)
+    return out
+
+
+def uneven_leg(torch, pm, m, count=512, seed=1):
+    """The uneven batching shape (t~U[10,40], n~U[300,2000], l~U[11,21],
+    d = floor(l/4)+1, k = clamp(l-d-4, 6, 9), s = 3) with m trials per
+    instance: one batch per shape class, all classes captured in one HIP
+    graph and replayed."""
+    from synth import batch_config
+    insts = batch_config(seed, count=count, m=m)
+    classes = {}
+    for inst, masks in insts:
+        classes.setdefault(inst.meta["l"], []).append((inst, masks))
+    bg = np.full(4, 0.25)
+    pipes, nbk_tot, lmers = [], 0, 0
+    for l in sorted(classes):
+        group = classes[l]
+        meta = group[0][0].meta
+        B = pm.Batch(4, l, meta["k"], [i.seqs for i, _ in group], [mk for _, mk in group])
+        nbk, nmem = pm.size_batch(B, meta["s"])
+        nbk_tot += nbk
+        lmers += sum(B.x[p] * B.m[p] for p in range(B.P))
+        pipes.append((B, pm.BatchPipeline(B, meta["s"], meta["iters"], 1.0, pm.PM_F16X2, bg, nbk, nmem)))
+    progress(f"uneven: {len(pipes)} shape classes, {nbk_tot} enriched buckets")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _, P in pipes:
+            P.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _, P in pipes:
+            P.run()
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    solved = 0
+    for (B, P), l in zip(pipes, sorted(classes)):
+        for r, (inst, _) in zip(P.results(), classes[l]):
+            solved += r.get("consensus") == inst.motif
+    return {"workload": f"{count} uneven DNA instances (t~U[10,40], n~U[300,2000], l~U[11,21]), m={m} trials each "
+                        "(of 1000 in the full shape), 5 EM iterations, one graph over all shape classes",
+            "ms": round(ms, 2), "instances_per_s": round(count / (ms / 1e3), 1),
+            "projected_lmers_per_s": round(lmers / (ms / 1e3), 1), "enriched_buckets": nbk_tot,
+            "shape_classes": len(pipes), "solved": int(solved)}
+
+
+def c5_leg(torch, pm, seed=1):
+    """One (21,7) instance, the shape the triage network is meant for: the full
+    path (every enriched bucket refined) against the triaged one (top 5% of
+    the buckets by the network, fallback on a weak winner), same buckets."""
+    import os
+    from synth import make_config
+    inst, masks = make_config("c5", seed=seed)
+    cfg = inst.meta
+    l, k, s, iters = cfg["l"], cfg["k"], cfg["s"], cfg["iters"]
+    bg = np.full(4, 0.25)
+    progress("c5: generated")
+    B = pm.Batch(4, l, k, [inst.seqs], [masks])
+    nbk, nmem = pm.size_batch(B, s)
+    progress(f"c5: {nbk} enriched buckets")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {"workload": "(21,7) DNA: t=50, n=2000, k=9, s=3, m=10000, 5 EM iterations, one instance",
+           "enriched_buckets": nbk, "planted": inst.motif}
+    full = pm.BatchPipeline(B, s, iters, 1.0, pm.PM_F16X2, bg, nbk, nmem)
+    full.run()
+    torch.cuda.synchronize()
+    e0.record()
+    full.run()
+    e1.record()
+    torch.cuda.synchronize()
+    r = full.results()[0]
+    out["full"] = {"ms": round(e0.elapsed_time(e1), 2), "consensus": r.get("consensus"),
+                   "solved": r.get("consensus") == inst.motif}
+    progress(f"c5: full pass {out['full']['ms']} ms")
+    del full
+    torch.cuda.empty_cache()
+    path = pm.default_triage_path()
+    if os.path.exists(path):
+        TP = pm.TriagedBatchPipeline(B, s, iters, 1.0, pm.PM_F16X2, bg, nbk, nmem, pm.Triage.load(path), 0.05)
+        TP.run()
+        torch.cuda.synchronize()
+        e0.record()
+        TP.run()
+        e1.record()
+        torch.cuda.synchronize()
+        r = TP.results()[0]
+        out["triaged"] = {"ms": round(e0.elapsed_time(e1), 2), "consensus": r.get("consensus"),
+                          "solved": r.get("consensus") == inst.motif, "refined_buckets": int(TP.refined),
+                          "fell_back": bool(r["fell_back"]), "z": r["z"]}
+        out["speedup"] = round(out["full"]["ms"] / out["triaged"]["ms"], 3)
+        progress(f"c5: triaged pass {out['triaged']['ms']} ms")
     return out
 
 
