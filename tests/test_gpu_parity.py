@@ -501,3 +501,55 @@ def test_c2_full_size_sampled_against_oracle():
     np.testing.assert_allclose(P.b.J.cpu().numpy()[sel], rJ, rtol=1e-5, atol=1e-5 * np.abs(rJ).max())
     J = P.b.J.cpu().numpy()[: len(bk)]
     assert np.all(np.diff(J, axis=1) >= -1e-5 * np.abs(J).max())
+
+
+def _full_size_sampled(name, precision, n_trials, n_buckets, seed):
+    """Hash and selection of a whole configuration at full size, sampled trials
+    bit-exact against the oracle, Sum counts = x on every trial; EM of sampled
+    buckets (theta^0 rows of the full run) against the FP64 oracle."""
+    inst, masks = make_config(name, seed=seed)
+    cfg = inst.meta
+    A, ref, bg, S, P = _pipeline(inst, masks, cfg, precision)
+    l, k, s, iters = cfg["l"], cfg["k"], cfg["s"], cfg["iters"]
+    say(name, "full size", P.m, "trials", P.b.cap_b, "buckets")
+    P.hash()
+    P.select()
+    pm.bucket_profile(S, l, P.b.buckets, P.b.members, P.b.cap_m, P.b.cap_b, P.b.n_out, P.b.profile)
+    pm.theta_init(A, l, P.b.profile, P.b.cap_b, P.b.n_out, P.bg, 1.0, P.b.theta0)
+    torch.cuda.synchronize()
+    assert int(P.b.status.item()) == 0
+    x = S.nwin(l)
+    assert torch.all(P.b.counts.sum(dim=1) == x).item()
+    rng = np.random.default_rng(seed)
+    trials = np.sort(rng.choice(P.m, size=n_trials, replace=False))
+    RK, RN = oracle.hash_trials(ref, l, k, masks[trials])
+    assert np.array_equal(u32(P.b.keys[trials]), RK)
+    assert np.array_equal(u32(P.b.counts[trials]), RN)
+    bk = u32(P.b.buckets)
+    mem = u32(P.b.members)
+    for i, j in enumerate(trials):
+        rbk, rmem, _, _ = oracle.select(ref, l, k, RK[i:i + 1], RN[i:i + 1], s)
+        mine = bk[bk[:, 0] == j]
+        assert np.array_equal(mine[:, 1:3], rbk[:, 1:3])
+        for a, b in zip(mine, rbk):
+            assert np.array_equal(mem[a[3]:a[3] + a[2]], rmem[b[3]:b[3] + b[2]])
+    sel = np.sort(rng.choice(len(bk), size=n_buckets, replace=False))
+    th0 = P.b.theta0.cpu().numpy()[sel]
+    rprof = oracle.profile(ref, l, bk[sel], mem)
+    np.testing.assert_allclose(th0, oracle.theta0(rprof, bg, 1.0), rtol=1e-15)
+    th, J, LL, sites, best, cons = _em_gpu(S, l, np.ascontiguousarray(th0), bg, iters, 1.0, precision)
+    rth, rJ, rLL, rsites = oracle.em(ref, l, th0, bg, iters, 1.0)
+    np.testing.assert_allclose(J, rJ, rtol=1e-5, atol=1e-5 * np.abs(rJ).max())
+    assert np.all(np.diff(J, axis=1) >= -1e-5 * np.abs(J).max())
+
+
+def test_c4_protein_full_size_sampled_against_oracle():
+    """(20,6) protein, Dirichlet background, t=30, n=1000, k=4 (160 000 bins,
+    key-range slices), m=2000; EM sample on the FP32 path."""
+    _full_size_sampled("c4", pm.PM_FP32, n_trials=6, n_buckets=16, seed=4)
+
+
+def test_c5_full_size_sampled_against_oracle():
+    """(21,7) DNA, t=50, n=2000 (x = 99 000: u32 histogram in key-range slices),
+    k=9, m=10000; EM sample on the split-FP16 matrix cores."""
+    _full_size_sampled("c5", pm.PM_F16X2, n_trials=4, n_buckets=16, seed=5)
