@@ -183,6 +183,20 @@ int em_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *b
               const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
               double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *stream);
 
+/* Tile-shape autotuner of the matrix-core EM (PM_F16X2, PM_F16): runs
+ * em_refine on the caller's B models once per candidate shape (window pairs
+ * whose one-hot tables are built per workgroup barrier: 1 or 2), times each
+ * with HIP events on `stream` (the call synchronises), and records the
+ * fastest for models of length class ceil(l/4) and this precision in a
+ * process-wide table that later em_refine / em_refine_batch calls use.
+ * theta_out, J_out: device scratch of em_refine's shapes (overwritten).
+ * choice_out: host int32[1] or NULL.  em_tuning returns the shape in use
+ * (untuned: 2), or a negative status. */
+int em_autotune(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B, int32_t iters,
+                double beta, int32_t precision, double *theta_out, double *J_out, int32_t *choice_out,
+                void *stream);
+int em_tuning(int32_t l, int32_t precision);
+
 /* a10 -- Sec. 5.1: the model with the highest objective wins.  best_out
  * device int64[1]: the bucket with the largest J(theta^iters), lowest index
  * on ties, -1 if none; consensus_out device char[l+1]: the letter of largest

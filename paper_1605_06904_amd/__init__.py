@@ -32,7 +32,7 @@ EXPORTS = [
     "pm_em_batch_workspace", "em_refine_batch", "em_best_batch",
     "triage_features", "pm_triage_packed_bytes", "triage_pack", "triage_forward", "pm_triage_workspace",
     "triage_train_step", "pm_triage_select_workspace", "triage_select", "triage_fallback_select",
-    "triage_merge_best",
+    "triage_merge_best", "em_autotune", "em_tuning",
 ]
 
 PM_TRIAGE_PARAMS, PM_TRIAGE_INPUTS = 88577, 87
@@ -138,6 +138,8 @@ def lib():
         "triage_fallback_select": (C.c_int, [C.c_void_p, P, i64, P, P, P, P, P, i32, dbl, P, i32, i32, P, P,
                                              P, P, P, P, P, P, sz, P]),
         "triage_merge_best": (C.c_int, [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P]),
+        "em_autotune": (C.c_int, [C.POINTER(pm_seqs), i32, P, P, i64, i32, dbl, i32, P, P, P, P]),
+        "em_tuning": (C.c_int, [i32, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -229,6 +231,20 @@ def em_refine(S, l, theta0, bg, B, n_dev, iters, beta, precision, theta_out, J_o
     _check(lib().em_refine(C.byref(S.c), l, _ptr(theta0), _ptr(bg), B, _ptr(n_dev), iters, beta,
                            precision, _ptr(theta_out), _ptr(J_out), _ptr(llr_out), _ptr(sites_out),
                            _stream(stream)))
+
+
+def em_autotune(S, l, theta0, bg, B, iters, beta, precision, theta_out, J_out, stream=None) -> int:
+    choice = C.c_int32(0)
+    _check(lib().em_autotune(C.byref(S.c), l, _ptr(theta0), _ptr(bg), B, iters, beta, precision, _ptr(theta_out),
+                             _ptr(J_out), C.byref(choice), _stream(stream)))
+    return choice.value
+
+
+def em_tuning(l: int, precision: int) -> int:
+    v = lib().em_tuning(l, precision)
+    if v < 0:
+        _check(v)
+    return v
 
 
 def em_best(J, B, n_dev, iters, theta, alphabet, l, best_out, consensus_out=None, stream=None):

@@ -357,6 +357,27 @@ extern "C" int em_refine(const pm_seqs *S, int32_t l, const double *theta0, cons
 
 extern "C" size_t pm_em_batch_workspace(int32_t P) { return em_batch_workspace(P); }
 
+extern "C" int em_autotune(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
+                           int32_t iters, double beta, int32_t precision, double *theta_out, double *J_out,
+                           int32_t *choice_out, void *stream)
+{
+    clear_error();
+    int rc = check_seqs(S, l);
+    if (rc) return rc;
+    if (precision != PM_F16X2 && precision != PM_F16) return fail(PM_EINVAL, "only the matrix-core forms are tuned");
+    if ((rc = check_em_args(S->alphabet, B, iters, beta, precision, theta0, bg, theta_out, J_out))) return rc;
+    if (B < 1) return fail(PM_EINVAL, "need B >= 1 models to time");
+    return em_autotune_mfma(S, l, theta0, bg, B, iters, beta, precision == PM_F16X2, theta_out, J_out, choice_out,
+                            as_stream(stream));
+}
+
+extern "C" int em_tuning(int32_t l, int32_t precision)
+{
+    clear_error();
+    if (l < 1 || l > 32 || (precision != PM_F16X2 && precision != PM_F16)) return fail(PM_EINVAL, "bad l/precision");
+    return em_tuned_shape(l, precision == PM_F16X2);
+}
+
 extern "C" int em_refine_batch(const pm_batch *Bt, const pm_bucket *buckets, const double *theta0, const double *bg,
                                int64_t B, const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
                                double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *ws,

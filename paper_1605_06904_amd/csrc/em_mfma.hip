@@ -35,8 +35,10 @@
 //
 // Work split: a workgroup of four waves takes 64 models (16 per wave) of one
 // instance; the four waves sweep the same windows in step and build the
-// one-hot tables of kPPB window pairs together in LDS (double-buffered, one
-// barrier per kPPB pairs) from the packed instance staged in LDS.
+// one-hot tables of PPB window pairs together in LDS (double-buffered, one
+// barrier per PPB pairs) from the packed instance staged in LDS.  PPB is the
+// tunable tile shape: em_autotune times the variants on the caller's models
+// and records the fastest per (ceil(l/4), precision) class.
 #include <math.h>
 #include <stdlib.h>
 
@@ -84,7 +86,7 @@ __host__ __device__ inline PlanView plan_view(const int64_t *plan, int P)
 }
 
 constexpr int kWaves = 4;  // waves (groups of 16 models) per workgroup
-constexpr int kPPB = 2;    // window pairs whose tables are built per workgroup barrier
+constexpr int kPPBDefault = 2;  // window pairs built per workgroup barrier, untuned
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kPOff = 3.0f;
 constexpr float kSlack = 12.0f;
@@ -292,7 +294,7 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables &T, co
 // One sequence: every window pair (tables built by the whole workgroup), then
 // the per-sequence log-sum-exp and counts, or, in the final E-step, the best
 // start of every model.
-template <int MT, bool STAGED, bool LAST, bool SPLIT>
+template <int MT, bool STAGED, bool LAST, bool SPLIT, int PPB>
 __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, const uint2 *lut, int i, int64_t bw,
                                       int64_t nvalid, PairTables *tabs, int &parity, float (*acc)[Tiles<MT>::PX][4],
                                       const half8 (&Whi)[Tiles<MT>::LB], const half8 (&Wlo)[Tiles<MT>::LB],
@@ -306,15 +308,15 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
     for (int mt = 0; mt < MT; ++mt) O[mt] = float4v{0.f, 0.f, 0.f, 0.f};
     // the reference starts at the lowest score the model can give
     SeqState st{mlow, 0.f, -INFINITY, 0};
-    for (int a0 = 0; a0 < L; a0 += 32 * kPPB) {
-        PairTables *T = tabs + kPPB * parity;
+    for (int a0 = 0; a0 < L; a0 += 32 * PPB) {
+        PairTables *T = tabs + PPB * parity;
         parity ^= 1;
 #pragma unroll
-        for (int u = 0; u < kPPB; ++u)
+        for (int u = 0; u < PPB; ++u)
             if (a0 + 32 * u < L) build_tables<!STAGED>(W, a.nwords, s0 + a0 + 32 * u, lut, T[u]);
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < kPPB; ++u) {
+        for (int u = 0; u < PPB; ++u) {
             const int b0 = a0 + 32 * u;
             if (b0 + 32 <= L) tile_pair<MT, LAST, false, SPLIT>(b0, L, T[u], Whi, Wlo, O, st);
             else if (b0 < L) tile_pair<MT, LAST, true, SPLIT>(b0, L, T[u], Whi, Wlo, O, st);
@@ -350,11 +352,11 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
     }
 }
 
-template <int MT, bool STAGED, bool SPLIT>
+template <int MT, bool STAGED, bool SPLIT, int PPB>
 __global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(const EmMfmaArgs a0)
 {
     constexpr int LB = Tiles<MT>::LB, PX = Tiles<MT>::PX;
-    __shared__ __align__(16) PairTables tabs[2 * kPPB];
+    __shared__ __align__(16) PairTables tabs[2 * PPB];
     __shared__ __align__(16) uint2 lut[256];
     __shared__ __align__(16) float accs[kWaves][16][PX][4];
     extern __shared__ __align__(16) uint32_t staged[];
@@ -460,8 +462,8 @@ __global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(cons
 
         double llr = 0;
         for (int i = 0; i < t; ++i) {
-            if (last) sweep<MT, STAGED, true, SPLIT>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
-            else sweep<MT, STAGED, false, SPLIT>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
+            if (last) sweep<MT, STAGED, true, SPLIT, PPB>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
+            else sweep<MT, STAGED, false, SPLIT, PPB>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
         }
         // ---- objective of theta^it, then the M-step (own entries)
         if (g == 0 && vb) {
@@ -487,33 +489,47 @@ __global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(cons
     }
 }
 
-template <int MT, bool SPLIT>
+template <int MT, bool SPLIT, int PPB>
 static int launch_em_mfma(const EmMfmaArgs &a, int64_t groups, hipStream_t st)
 {
     if (a.stage_words)
-        hipLaunchKernelGGL((k_em_mfma<MT, true, SPLIT>), dim3((unsigned)groups), dim3(64 * kWaves),
+        hipLaunchKernelGGL((k_em_mfma<MT, true, SPLIT, PPB>), dim3((unsigned)groups), dim3(64 * kWaves),
                            (size_t)(a.stage_words + kStagePad) * 4, st, a);
     else
-        hipLaunchKernelGGL((k_em_mfma<MT, false, SPLIT>), dim3((unsigned)groups), dim3(64 * kWaves), 0, st, a);
+        hipLaunchKernelGGL((k_em_mfma<MT, false, SPLIT, PPB>), dim3((unsigned)groups), dim3(64 * kWaves), 0, st, a);
     PM_LAUNCHED();
     return PM_OK;
 }
 
-static int dispatch_em_mfma(const EmMfmaArgs &a, int64_t groups, hipStream_t st)
+// tile shape in use per (ceil(l/4) - 1, split): 0 = untuned (kPPBDefault)
+static int g_ppb[8][2];
+
+static int tuned_ppb(int l, bool split)
 {
-#define PM_EM_CASE(mt) \
-    case mt: return a.split ? launch_em_mfma<mt, true>(a, groups, st) : launch_em_mfma<mt, false>(a, groups, st);
+    const int v = g_ppb[(l + 3) / 4 - 1][split ? 1 : 0];
+    return v ? v : kPPBDefault;
+}
+
+template <bool SPLIT, int PPB>
+static int dispatch_mt(const EmMfmaArgs &a, int64_t groups, hipStream_t st)
+{
     switch ((a.l + 3) / 4) {
-    PM_EM_CASE(1)
-    PM_EM_CASE(2)
-    PM_EM_CASE(3)
-    PM_EM_CASE(4)
-    PM_EM_CASE(5)
-    PM_EM_CASE(6)
-    PM_EM_CASE(7)
-    default: return a.split ? launch_em_mfma<8, true>(a, groups, st) : launch_em_mfma<8, false>(a, groups, st);
+    case 1: return launch_em_mfma<1, SPLIT, PPB>(a, groups, st);
+    case 2: return launch_em_mfma<2, SPLIT, PPB>(a, groups, st);
+    case 3: return launch_em_mfma<3, SPLIT, PPB>(a, groups, st);
+    case 4: return launch_em_mfma<4, SPLIT, PPB>(a, groups, st);
+    case 5: return launch_em_mfma<5, SPLIT, PPB>(a, groups, st);
+    case 6: return launch_em_mfma<6, SPLIT, PPB>(a, groups, st);
+    case 7: return launch_em_mfma<7, SPLIT, PPB>(a, groups, st);
+    default: return launch_em_mfma<8, SPLIT, PPB>(a, groups, st);
     }
-#undef PM_EM_CASE
+}
+
+static int dispatch_em_mfma(const EmMfmaArgs &a, int64_t groups, hipStream_t st, int ppb = 0)
+{
+    if (!ppb) ppb = tuned_ppb(a.l, a.split != 0);
+    if (a.split) return ppb == 1 ? dispatch_mt<true, 1>(a, groups, st) : dispatch_mt<true, 2>(a, groups, st);
+    return ppb == 1 ? dispatch_mt<false, 1>(a, groups, st) : dispatch_mt<false, 2>(a, groups, st);
 }
 
 int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
@@ -619,6 +635,54 @@ int em_refine_mfma_batch(const pm_batch *Bt, int64_t nw_max, int t_max, const pm
     const int64_t groups = (B + 16 * kWaves - 1) / (16 * kWaves) + Bt->P;
     return dispatch_em_mfma(a, groups, st);
 }
+
+int em_autotune_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B, int32_t iters,
+                     double beta, bool split, double *theta_out, double *J_out, int32_t *choice, hipStream_t st)
+{
+    EmMfmaArgs a{};
+    a.split = split;
+    a.packed = S->packed;
+    a.offsets = S->offsets;
+    a.theta0 = theta0;
+    a.bg = bg;
+    a.theta_out = theta_out;
+    a.J = J_out;
+    a.B = B;
+    a.nwords = pm_packed_words(S->alphabet, S->n_total);
+    a.stage_words = a.nwords * 4 <= 32 * 1024 ? (int)a.nwords : 0;
+    a.t = S->t;
+    a.site_stride = S->t;
+    a.l = l;
+    a.iters = iters;
+    a.beta = beta;
+    const int64_t groups = (B + 16 * kWaves - 1) / (16 * kWaves);
+    hipEvent_t e0, e1;
+    PM_TRY(hipEventCreate(&e0));
+    PM_TRY(hipEventCreate(&e1));
+    float best_ms = 0.f;
+    int best = 0, rc = PM_OK;
+    for (int ppb = 1; ppb <= 2 && rc == PM_OK; ++ppb) {
+        float ms = 0.f;
+        rc = dispatch_em_mfma(a, groups, st, ppb);  // warm-up
+        if (rc == PM_OK && hipEventRecord(e0, st) != hipSuccess) rc = fail(PM_EDEVICE, "hipEventRecord failed");
+        if (rc == PM_OK) rc = dispatch_em_mfma(a, groups, st, ppb);
+        if (rc == PM_OK && hipEventRecord(e1, st) != hipSuccess) rc = fail(PM_EDEVICE, "hipEventRecord failed");
+        if (rc == PM_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(PM_EDEVICE, "hipEventSynchronize failed");
+        if (rc == PM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(PM_EDEVICE, "hipEventElapsedTime failed");
+        if (rc == PM_OK && (best == 0 || ms < best_ms)) {
+            best = ppb;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != PM_OK) return rc;
+    g_ppb[(l + 3) / 4 - 1][split ? 1 : 0] = best;
+    if (choice) *choice = best;
+    return PM_OK;
+}
+
+int em_tuned_shape(int32_t l, bool split) { return tuned_ppb(l, split); }
 
 size_t em_batch_workspace(int32_t P) { return P < 1 ? 0 : (size_t)(4 * (int64_t)P + 1) * sizeof(int64_t) + 256; }
 

@@ -63,6 +63,9 @@ int em_refine_mfma_batch(const pm_batch *Bt, int64_t nw_max, int t_max, const pm
                          double beta, double *theta_out, double *J_out, double *llr_out, int32_t *sites_out,
                          void *ws, bool split, hipStream_t st);
 size_t em_batch_workspace(int32_t P);
+int em_autotune_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B, int32_t iters,
+                     double beta, bool split, double *theta_out, double *J_out, int32_t *choice, hipStream_t st);
+int em_tuned_shape(int32_t l, bool split);
 
 // ---------------------------------------------------------------- device side
 constexpr int kWave = 64;

@@ -553,3 +553,23 @@ def test_c5_full_size_sampled_against_oracle():
     """(21,7) DNA, t=50, n=2000 (x = 99 000: u32 histogram in key-range slices),
     k=9, m=10000; EM sample on the split-FP16 matrix cores."""
     _full_size_sampled("c5", pm.PM_F16X2, n_trials=4, n_buckets=16, seed=5)
+
+
+def test_em_autotune_records_a_shape_and_keeps_results():
+    """The tile-shape autotuner times the candidates on the caller's models,
+    records the fastest, and the recorded shape gives bit-identical results
+    (the shapes change only how many window pairs share a barrier)."""
+    inst, ref, bg, th0 = _em_case(21, 4, 12, 300, 18, 6, 200)
+    say("em autotune")
+    S = pm.Seqs(4, inst.seqs)
+    for prec in (pm.PM_F16X2, pm.PM_F16):
+        before = _em_gpu(S, 18, th0, bg, 3, 1.0, prec)
+        d_th0 = torch.from_numpy(th0).cuda()
+        th = torch.zeros_like(d_th0)
+        J = torch.zeros((th0.shape[0], 4), dtype=torch.float64, device="cuda")
+        choice = pm.em_autotune(S, 18, d_th0, torch.from_numpy(bg).cuda(), th0.shape[0], 3, 1.0, prec, th, J)
+        assert choice in (1, 2) and pm.em_tuning(18, prec) == choice
+        after = _em_gpu(S, 18, th0, bg, 3, 1.0, prec)
+        assert np.array_equal(before[1], after[1]) and np.array_equal(before[0], after[0])
+    with pytest.raises(pm.PmError):
+        pm.em_tuning(18, pm.PM_FP64)
