@@ -29,7 +29,7 @@ FP16_MFMA_PEAK = 2500.0      # TFLOP/s, MI355X dense FP16 matrix cores
 # the kernel source is the one they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
     "hash.hip": ("9ec1b4adfe82aa62", 1.749e9),
-    "em_mfma.hip": ("f7346fc0d97b8d0e", 0.355e9 + 0.615e9),
+    "em_mfma.hip": ("5d988aa6702a5027", 0.352e9 + 0.611e9),
 }
 
 
@@ -412,8 +412,14 @@ def instances_leg(torch, pm, count):
         solved += ok
         pcs += pc
     plain = {"instances_per_s": round(count / (plain_ms / 1e3), 2), "ms": round(plain_ms, 3),
-             "solved": int(solved), "mean_pc": round(pcs / count, 4), "em": "fp64, all enriched buckets"}
-    del pipes
+             "solved": int(solved), "solved_per_s": round(solved / (plain_ms / 1e3), 2),
+             "mean_pc": round(pcs / count, 4), "em": "fp64, all enriched buckets"}
+    # the batched legs use the matrix-core EM: pick its tile shape for this
+    # length class on the first instance's buckets
+    P0 = pipes[0]
+    tune_th, tune_J = torch.zeros_like(P0.b.theta), torch.zeros_like(P0.b.J)
+    tile_shape = pm.em_autotune(P0.S, l, P0.b.theta0, P0.bg, P0.b.cap_b, iters, beta, pm.PM_F16X2, tune_th, tune_J)
+    del pipes, P0, tune_th, tune_J
     torch.cuda.empty_cache()
 
     progress(f"plain leg: {plain_ms:.1f} ms")
@@ -445,7 +451,8 @@ def instances_leg(torch, pm, count):
         solved += ok
         pcs += pc
     batched = {"instances_per_s": round(count / (batch_ms / 1e3), 2), "ms": round(batch_ms, 3),
-               "solved": int(solved), "mean_pc": round(pcs / count, 4), "enriched_buckets": nbk,
+               "solved": int(solved), "solved_per_s": round(solved / (batch_ms / 1e3), 2),
+               "mean_pc": round(pcs / count, 4), "enriched_buckets": nbk, "em_tile_shape": tile_shape,
                "em": "split-f16 matrix cores, all enriched buckets, one HIP graph"}
     out = {"workload": f"(15,4) DNA: t=20, n=600, k=7, s=4, m=200, 5 EM iterations; {count} instances, seeds 0..{count - 1}",
            "plain": plain, "batched": batched,
@@ -486,7 +493,8 @@ def instances_leg(torch, pm, count):
         solved += ok
         pcs += pc
     out["triaged"] = {"instances_per_s": round(count / (tri_ms / 1e3), 2), "ms": round(tri_ms, 3),
-                      "solved": int(solved), "mean_pc": round(pcs / count, 4), "refined_buckets": int(TP.refined),
+                      "solved": int(solved), "solved_per_s": round(solved / (tri_ms / 1e3), 2),
+                      "mean_pc": round(pcs / count, 4), "refined_buckets": int(TP.refined),
                       "fallbacks": int(sum(r["fell_back"] for r in res)), "frac": 0.05,
                       "em": "split-f16 matrix cores on the triaged buckets, BF16 network, one HIP graph"}
     out["speedup_triaged"] = round(out["triaged"]["instances_per_s"] / plain["instances_per_s"], 3)
