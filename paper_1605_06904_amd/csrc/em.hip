@@ -307,8 +307,7 @@ static int check_em_args(int A, int64_t B, int32_t iters, double beta, int32_t p
     if (B < 0 || iters < 0 || beta < 0) return fail(PM_EINVAL, "need B >= 0, iters >= 0, beta >= 0");
     if (precision != PM_FP64 && precision != PM_FP32 && precision != PM_F16X2 && precision != PM_F16)
         return fail(PM_EINVAL, "unknown precision %d", precision);
-    if ((precision == PM_F16X2 || precision == PM_F16) && A != 4)
-        return fail(PM_EINVAL, "the matrix-core forms (PM_F16X2, PM_F16) are for DNA");
+    if (precision == PM_F16X2 && A != 4) return fail(PM_EINVAL, "PM_F16X2 is for DNA");
     if (B > 0x7fffffff) return fail(PM_ERANGE, "B above 2^31 - 1");
     if (B > 0 && (!theta0 || !bg || !theta_out || !J_out)) return fail(PM_EINVAL, "NULL buffer");
     return PM_OK;
@@ -335,6 +334,8 @@ extern "C" int em_refine(const pm_seqs *S, int32_t l, const double *theta0, cons
     if ((rc = check_em_args(S->alphabet, B, iters, beta, precision, theta0, bg, theta_out, J_out))) return rc;
     if (B == 0) return PM_OK;
     hipStream_t st = as_stream(stream);
+    if (precision == PM_F16 && S->alphabet == 20)
+        return em_refine_prot(S, l, theta0, bg, B, n_dev, iters, beta, theta_out, J_out, llr_out, sites_out, st);
     if (precision == PM_F16X2 || precision == PM_F16)
         return em_refine_mfma(S, l, theta0, bg, B, n_dev, iters, beta, theta_out, J_out, llr_out, sites_out,
                               precision == PM_F16X2, st);
@@ -391,6 +392,8 @@ extern "C" int em_refine_batch(const pm_batch *Bt, const pm_bucket *buckets, con
     if (B == 0) return PM_OK;
     if (!buckets) return fail(PM_EINVAL, "buckets are NULL");
     hipStream_t st = as_stream(stream);
+    if (precision == PM_F16 && Bt->alphabet == 20)
+        return fail(PM_EINVAL, "the protein matrix-core form runs on single instances (em_refine)");
     if (precision == PM_F16X2 || precision == PM_F16) {
         if (!ws || ws_bytes < em_batch_workspace(Bt->P)) return fail(PM_EINVAL, "workspace too small");
         return em_refine_mfma_batch(Bt, info.nw_max, info.t_max, buckets, theta0, bg, B, n_dev, iters, beta,

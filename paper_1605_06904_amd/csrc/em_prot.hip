@@ -1,0 +1,351 @@
+// a7 - a9 for protein models on the matrix cores: the precision form with a
+// 20-letter one-hot.
+//
+// E-step scores of a tile of 16 windows for 16 models: S = OneHot . W with
+// contraction index kappa = 20 p + sigma (position p, letter sigma), 20 l of
+// them padded to KS steps of 32.  M-step counts: C = OneHot^T . Z with the
+// contraction over 32 windows (two E tiles), 2 KS row tiles of 16 kappa rows.
+// v_mfma_f32_16x16x32_f16, one FP16 value per non-0/1 operand (the log-odds W
+// and the posteriors Z), FP32 accumulation; per-sequence log-sum-exp combined
+// across lanes in FP32, LLR and J in FP64.
+//
+// A 20-letter model has 20 l count rows, too many to keep one sequence's
+// unnormalised counts beside the running totals, so each sequence is swept
+// twice: first for its log-sum-exp (and, in the final E-step, the best start),
+// then with exactly normalised posteriors feeding the M-step accumulators,
+// which stay in registers across the sequences.
+//
+// Lane layout (lane L, r = L % 16, g = L / 16), as for the DNA kernel:
+//   E-step A: window row r, kappa 32 ks + 8 g .. + 7;  B: model r, same kappa;
+//   D: model r, windows 4g .. 4g+3 of the tile;
+//   M-step A: kappa row 16 rt + r, windows w_j (j < 8) = 4g + j (tile 0) and
+//   16 + 4g + j - 4 (tile 1), exactly the windows of the lane's E-step
+//   outputs, which therefore feed the M-step B operand without moving.
+// A workgroup of four waves takes 64 models of one instance; the tables of a
+// window pair are built by the whole workgroup in LDS from the sequence's
+// symbols unpacked to bytes.
+#include <math.h>
+
+#include "pm_common.h"
+
+namespace pm {
+
+typedef _Float16 half8p __attribute__((ext_vector_type(8)));
+typedef float float4p __attribute__((ext_vector_type(4)));
+
+constexpr int kPW = 4;           // waves per workgroup
+constexpr int kPSymMax = 2048;   // longest sequence (symbols)
+constexpr int kPTMax = 64;       // most sequences
+constexpr float kPLog2e = 1.4426950408889634f;
+
+struct EmProtArgs {
+    const uint32_t *packed;
+    const int64_t *offsets;
+    const double *theta0;
+    const double *bg;
+    const int64_t *n_dev;
+    double *theta_out;
+    double *J;
+    double *llr;
+    int32_t *sites;
+    int64_t B;
+    int t, l, iters;
+    double beta;
+};
+
+template <int KS>
+struct ProtTables {
+    uint4 e[2][KS][64];  // E-step A fragments of the two tiles
+    uint4 m[2 * KS][64]; // M-step A fragments
+};
+
+// eight FP16 halves, 1.0 at the set bits of an 8-bit mask
+__device__ __forceinline__ uint4 mask8_halves(uint32_t mk)
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        w[q] = (((mk >> (2 * q)) & 1u) ? 0x3C00u : 0u) | (((mk >> (2 * q + 1)) & 1u) ? 0x3C000000u : 0u);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// tables of the window pair starting at a0 (sequence-relative), sym = the
+// sequence's symbols as bytes
+template <int KS>
+__device__ __forceinline__ void build_prot_tables(const uint8_t *sym, int a0, int l, bool with_m, ProtTables<KS> &T)
+{
+    const int nk = 20 * l;
+    for (int e = threadIdx.x; e < 2 * KS * 64; e += 64 * kPW) {
+        const int lane = e & 63, ks = (e >> 6) % KS, tile = (e >> 6) / KS;
+        const int r = lane & 15, g = lane >> 4;
+        const int w = a0 + 16 * tile + r;
+        const int k0 = 32 * ks + 8 * g;
+        uint32_t mk = 0;
+        if (k0 < nk) {
+            const int p0 = k0 / 20, p1 = (k0 + 7) / 20;
+            const int i0 = 20 * p0 + sym[w + p0] - k0;
+            if (i0 >= 0 && i0 < 8) mk |= 1u << i0;
+            if (p1 != p0 && p1 < l) {
+                const int i1 = 20 * p1 + sym[w + p1] - k0;
+                if (i1 >= 0 && i1 < 8) mk |= 1u << i1;
+            }
+            // kappa >= 20 l never matches: p1 < l guards the second position
+        }
+        T.e[tile][ks][lane] = mask8_halves(mk);
+    }
+    if (!with_m) return;
+    for (int e = threadIdx.x; e < 2 * KS * 64; e += 64 * kPW) {
+        const int lane = e & 63, rt = e >> 6;
+        const int r = lane & 15, g = lane >> 4;
+        const int kap = 16 * rt + r;
+        uint32_t mk = 0;
+        if (kap < nk) {
+            const int p = kap / 20, sg = kap - 20 * p;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int w = a0 + (j < 4 ? 4 * g + j : 16 + 4 * g + j - 4);
+                if (sym[w + p] == sg) mk |= 1u << j;
+            }
+        }
+        T.m[rt][lane] = mask8_halves(mk);
+    }
+}
+
+template <int KS>
+__global__ void __launch_bounds__(64 * kPW, 2) k_em_prot(const EmProtArgs a)
+{
+    constexpr int RT = 2 * KS;
+    __shared__ __align__(16) ProtTables<KS> T;
+    __shared__ uint8_t sym[kPSymMax + 64];
+    __shared__ double coltot[kPW][16][24];    // M-step: column totals of each model
+
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    int64_t nvalid = a.n_dev ? *a.n_dev : a.B;
+    if (nvalid > a.B) nvalid = a.B;
+    const int64_t b0 = (int64_t)blockIdx.x * 16 * kPW;
+    if (b0 >= nvalid) return;  // uniform over the workgroup
+    const int l = a.l, t = a.t, AL = 20 * l, nk = 20 * l;
+    const int64_t b = b0 + 16 * wv + r;
+    const bool vb = b < nvalid;
+    const double beta = a.beta;
+
+    half8p Wb[KS];
+    float4p C[RT];
+    for (int it = 0; it <= a.iters; ++it) {
+        const bool last = it == a.iters;
+        const double *src = it == 0 ? a.theta0 : a.theta_out;
+        // ---- log-odds of the lane's B-operand entries (log2 units) and the prior
+        double prior = 0;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            half8p h;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int kap = 32 * ks + 8 * g + j;
+                float w = 0.f;
+                if (kap < nk && vb) {
+                    const int p = kap / 20, sg = kap - 20 * p;
+                    const double th = src[b * AL + sg * l + p];
+                    if (it == 0) a.theta_out[b * AL + sg * l + p] = th;
+                    const double lt = log(th);
+                    w = (float)((lt - log(a.bg[sg])) * (double)kPLog2e);
+                    prior += a.bg[sg] * lt;
+                }
+                h[j] = (_Float16)w;
+            }
+            Wb[ks] = h;
+        }
+        prior += __shfl_xor(prior, 16);
+        prior += __shfl_xor(prior, 32);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) C[rt] = float4p{0.f, 0.f, 0.f, 0.f};
+
+        double llr = 0;
+        for (int i = 0; i < t; ++i) {
+            const int64_t s0 = a.offsets[i];
+            const int n = (int)(a.offsets[i + 1] - s0);
+            const int L = n - l + 1;
+            __syncthreads();  // the previous users of sym and T are done
+            for (int q = threadIdx.x; q < n + 64; q += 64 * kPW)
+                sym[q] = q < n ? (uint8_t)prot_sym(a.packed, s0 + q) : (uint8_t)0;
+            // ---- pass 1: log-sum-exp (and the best start in the final E-step)
+            float mx = -INFINITY, sm = 0.f, bestv = -INFINITY;
+            int besti = 0;
+            for (int a0 = 0; a0 < L; a0 += 32) {
+                __syncthreads();
+                build_prot_tables<KS>(sym, a0, l, false, T);
+                __syncthreads();
+                float4p S0 = {0.f, 0.f, 0.f, 0.f}, S1 = S0;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const half8p A0 = __builtin_bit_cast(half8p, T.e[0][ks][lane]);
+                    const half8p A1 = __builtin_bit_cast(half8p, T.e[1][ks][lane]);
+                    S0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, Wb[ks], S0, 0, 0, 0);
+                    S1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, Wb[ks], S1, 0, 0, 0);
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int w = a0 + 16 * (q >> 2) + 4 * g + (q & 3);
+                    const float v = q < 4 ? S0[q & 3] : S1[q & 3];
+                    if (w < L) {
+                        if (v > mx) {
+                            sm = sm * __builtin_amdgcn_exp2f(mx - v) + 1.f;
+                            mx = v;
+                        } else {
+                            sm += __builtin_amdgcn_exp2f(v - mx);
+                        }
+                        if (last && v > bestv) {
+                            bestv = v;
+                            besti = w;
+                        }
+                    }
+                }
+            }
+            // combine the four lanes of each model
+            float M = mx;
+            M = fmaxf(M, __shfl_xor(M, 16));
+            M = fmaxf(M, __shfl_xor(M, 32));
+            float part = mx > -INFINITY ? sm * __builtin_amdgcn_exp2f(mx - M) : 0.f;
+            part += __shfl_xor(part, 16);
+            part += __shfl_xor(part, 32);
+            const float lz = M + __builtin_amdgcn_logf(part);  // log2 of the sum of 2^S
+            const double ln2 = 0.6931471805599453;
+            llr += (double)lz * ln2 - log((double)L);
+            if (last) {
+                if (a.sites) {
+#pragma unroll
+                    for (int o = 16; o <= 32; o <<= 1) {
+                        const float ov = __shfl_xor(bestv, o);
+                        const int oi = __shfl_xor(besti, o);
+                        if (ov > bestv || (ov == bestv && oi < besti)) {
+                            bestv = ov;
+                            besti = oi;
+                        }
+                    }
+                    if (g == 0 && vb) a.sites[b * t + i] = besti;
+                }
+                continue;
+            }
+            // ---- pass 2: normalised posteriors into the M-step accumulators
+            for (int a0 = 0; a0 < L; a0 += 32) {
+                __syncthreads();
+                build_prot_tables<KS>(sym, a0, l, true, T);
+                __syncthreads();
+                float4p S0 = {0.f, 0.f, 0.f, 0.f}, S1 = S0;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const half8p A0 = __builtin_bit_cast(half8p, T.e[0][ks][lane]);
+                    const half8p A1 = __builtin_bit_cast(half8p, T.e[1][ks][lane]);
+                    S0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, Wb[ks], S0, 0, 0, 0);
+                    S1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, Wb[ks], S1, 0, 0, 0);
+                }
+                half8p Ph;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int w = a0 + 16 * (q >> 2) + 4 * g + (q & 3);
+                    const float v = q < 4 ? S0[q & 3] : S1[q & 3];
+                    Ph[q] = (_Float16)(w < L ? __builtin_amdgcn_exp2f(v - lz) : 0.f);
+                }
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const half8p Am = __builtin_bit_cast(half8p, T.m[rt][lane]);
+                    C[rt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am, Ph, C[rt], 0, 0, 0);
+                }
+            }
+        }
+        if (g == 0 && vb) {
+            a.J[b * (a.iters + 1) + it] = llr + beta * prior;
+            if (a.llr) a.llr[b * (a.iters + 1) + it] = llr;
+        }
+        if (last) break;
+        // ---- M-step: counts of the lane's rows (kappa = 16 rt + 4 g + q) go to
+        // theta_out, then every column is normalised by its own total
+        __syncthreads();  // every lane has read its theta^it entries
+        if (vb) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kap = 16 * rt + 4 * g + q;
+                    if (kap < nk) {
+                        const int p = kap / 20, sg = kap - 20 * p;
+                        a.theta_out[b * AL + sg * l + p] = (double)C[rt][q];
+                    }
+                }
+        }
+        __syncthreads();
+        // lane g sums the columns p = g, g + 4, ... of its model
+        if (vb)
+            for (int p = g; p < l; p += 4) {
+                double s = 0;
+                for (int c = 0; c < 20; ++c) s += a.theta_out[b * AL + c * l + p];
+                coltot[wv][r][p] = s + beta;
+            }
+        __syncthreads();
+        if (vb) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kap = 16 * rt + 4 * g + q;
+                    if (kap < nk) {
+                        const int p = kap / 20, sg = kap - 20 * p;
+                        a.theta_out[b * AL + sg * l + p] = ((double)C[rt][q] + beta * a.bg[sg]) / coltot[wv][r][p];
+                    }
+                }
+        }
+        __syncthreads();  // theta^(it+1) visible to every lane before it is read
+    }
+}
+
+template <int KS>
+static int launch_prot(const EmProtArgs &a, hipStream_t st)
+{
+    const int64_t groups = (a.B + 16 * kPW - 1) / (16 * kPW);
+    hipLaunchKernelGGL((k_em_prot<KS>), dim3((unsigned)groups), dim3(64 * kPW), 0, st, a);
+    PM_LAUNCHED();
+    return PM_OK;
+}
+
+int em_refine_prot(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
+                   const int64_t *n_dev, int32_t iters, double beta, double *theta_out, double *J_out,
+                   double *llr_out, int32_t *sites_out, hipStream_t st)
+{
+    if (l > 24) return fail(PM_ERANGE, "the protein matrix-core form takes l <= 24");
+    if (S->t > kPTMax) return fail(PM_ERANGE, "the protein matrix-core form takes t <= %d", kPTMax);
+    if (S->n_max > kPSymMax) return fail(PM_ERANGE, "the protein matrix-core form takes n_i <= %d", kPSymMax);
+    EmProtArgs a{};
+    a.packed = S->packed;
+    a.offsets = S->offsets;
+    a.theta0 = theta0;
+    a.bg = bg;
+    a.n_dev = n_dev;
+    a.theta_out = theta_out;
+    a.J = J_out;
+    a.llr = llr_out;
+    a.sites = sites_out;
+    a.B = B;
+    a.t = S->t;
+    a.l = l;
+    a.iters = iters;
+    a.beta = beta;
+    switch ((20 * l + 31) / 32) {
+    case 1: return launch_prot<1>(a, st);
+    case 2: return launch_prot<2>(a, st);
+    case 3: return launch_prot<3>(a, st);
+    case 4: return launch_prot<4>(a, st);
+    case 5: return launch_prot<5>(a, st);
+    case 6: return launch_prot<6>(a, st);
+    case 7: return launch_prot<7>(a, st);
+    case 8: return launch_prot<8>(a, st);
+    case 9: return launch_prot<9>(a, st);
+    case 10: return launch_prot<10>(a, st);
+    case 11: return launch_prot<11>(a, st);
+    case 12: return launch_prot<12>(a, st);
+    case 13: return launch_prot<13>(a, st);
+    case 14: return launch_prot<14>(a, st);
+    default: return launch_prot<15>(a, st);
+    }
+}
+
+}  // namespace pm
