@@ -174,9 +174,12 @@ def test_batch_and_triage_entry_points_validate():
                                  None) == pm.PM_EINVAL
     # EM: the matrix-core forms are DNA only; a too-small plan workspace
     S = _S(_fake_seqs(alphabet=20))
-    for prec in (pm.PM_F16X2, pm.PM_F16):
-        assert L.em_refine(C.byref(S.c), 4, 0x1, 0x1, 1, None, 3, 1.0, prec, 0x1, 0x1, None, None,
-                           None) == pm.PM_EINVAL
+    assert L.em_refine(C.byref(S.c), 4, 0x1, 0x1, 1, None, 3, 1.0, pm.PM_F16X2, 0x1, 0x1, None, None,
+                       None) == pm.PM_EINVAL
+    # the protein matrix-core form takes l <= 24
+    S25 = _S(_fake_seqs(alphabet=20, n_total=60, n_min=30, n_max=30))
+    assert L.em_refine(C.byref(S25.c), 25, 0x1, 0x1, 1, None, 3, 1.0, pm.PM_F16, 0x1, 0x1, None, None,
+                       None) == pm.PM_ERANGE
     assert L.em_refine_batch(C.byref(b), 0x1, 0x1, 0x1, 10, None, 2, 1.0, pm.PM_F16X2, 0x1, 0x1, None,
                              None, 0x1, 8, None) == pm.PM_EINVAL
     assert pm.pm_em_batch_workspace(3) >= 8 * 13
