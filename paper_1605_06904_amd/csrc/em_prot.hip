@@ -10,10 +10,13 @@
 // across lanes in FP32, LLR and J in FP64.
 //
 // A 20-letter model has 20 l count rows, too many to keep one sequence's
-// unnormalised counts beside the running totals, so each sequence is swept
-// twice: first for its log-sum-exp (and, in the final E-step, the best start),
-// then with exactly normalised posteriors feeding the M-step accumulators,
-// which stay in registers across the sequences.
+// unnormalised counts beside the running totals, so every iteration first
+// sweeps the sequences for their log-sum-exp (kept in LDS; in the final E-step
+// also the best start), then sweeps them again with exactly normalised
+// posteriors feeding M-step accumulators that stay in registers across the
+// sequences.  Beyond 8 contraction steps the count rows are split over two
+// such sweeps, which keeps the accumulators and the log-odds in registers
+// (no spills) at the cost of one more E-step per window pair.
 //
 // Lane layout (lane L, r = L % 16, g = L / 16), as for the DNA kernel:
 //   E-step A: window row r, kappa 32 ks + 8 g .. + 7;  B: model r, same kappa;
@@ -37,6 +40,7 @@ constexpr int kPW = 4;           // waves per workgroup
 constexpr int kPSymMax = 2048;   // longest sequence (symbols)
 constexpr int kPTMax = 64;       // most sequences
 constexpr float kPLog2e = 1.4426950408889634f;
+constexpr int kPOneSweepKS = 14;  // largest KS whose 2 KS count tiles and LDS tables fit two workgroups
 
 struct EmProtArgs {
     const uint32_t *packed;
@@ -53,10 +57,10 @@ struct EmProtArgs {
     double beta;
 };
 
-template <int KS>
+template <int KS, int RH>
 struct ProtTables {
     uint4 e[2][KS][64];  // E-step A fragments of the two tiles
-    uint4 m[2 * KS][64]; // M-step A fragments
+    uint4 m[RH][64];     // M-step A fragments of the sweep's row tiles
 };
 
 // eight FP16 halves, 1.0 at the set bits of an 8-bit mask
@@ -70,9 +74,11 @@ __device__ __forceinline__ uint4 mask8_halves(uint32_t mk)
 }
 
 // tables of the window pair starting at a0 (sequence-relative), sym = the
-// sequence's symbols as bytes
-template <int KS>
-__device__ __forceinline__ void build_prot_tables(const uint8_t *sym, int a0, int l, bool with_m, ProtTables<KS> &T)
+// sequence's symbols as bytes; with h >= 0 also the M-step fragments of the
+// row tiles h RH .. h RH + RH - 1
+template <int KS, int RH>
+__device__ __forceinline__ void build_prot_tables(const uint8_t *sym, int a0, int l, int h, ProtTables<KS, RH> &T,
+                                                  uint32_t *mm)
 {
     const int nk = 20 * l;
     for (int e = threadIdx.x; e < 2 * KS * 64; e += 64 * kPW) {
@@ -93,31 +99,44 @@ __device__ __forceinline__ void build_prot_tables(const uint8_t *sym, int a0, in
         }
         T.e[tile][ks][lane] = mask8_halves(mk);
     }
-    if (!with_m) return;
-    for (int e = threadIdx.x; e < 2 * KS * 64; e += 64 * kPW) {
+    if (h < 0) return;
+    // M-step fragments by scattering each (window, position) symbol to its
+    // kappa row: word mm[kappa - 16 RH h] holds, in byte g, the windows of
+    // lane group g
+    const int kb = 16 * RH * h;
+    for (int q = threadIdx.x; q < 16 * RH; q += 64 * kPW) mm[q] = 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < 32 * l; q += 64 * kPW) {
+        const int p = q >> 5, jj = q & 31, g = jj >> 3, j = jj & 7;
+        const int w = a0 + (j < 4 ? 4 * g + j : 16 + 4 * g + j - 4);
+        const int kr = 20 * p + sym[w + p] - kb;
+        if (kr >= 0 && kr < 16 * RH) atomicOr(mm + kr, 1u << (8 * g + j));
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < RH * 64; e += 64 * kPW) {
         const int lane = e & 63, rt = e >> 6;
         const int r = lane & 15, g = lane >> 4;
-        const int kap = 16 * rt + r;
-        uint32_t mk = 0;
-        if (kap < nk) {
-            const int p = kap / 20, sg = kap - 20 * p;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int w = a0 + (j < 4 ? 4 * g + j : 16 + 4 * g + j - 4);
-                if (sym[w + p] == sg) mk |= 1u << j;
-            }
-        }
-        T.m[rt][lane] = mask8_halves(mk);
+        const int kap = kb + 16 * rt + r;
+        T.m[rt][lane] = mask8_halves(kap < nk ? (mm[16 * rt + r] >> (8 * g)) & 0xffu : 0u);
     }
 }
 
-template <int KS>
+// NH sweeps of the M-step per iteration, each over RH = 2 KS / NH row tiles
+template <int KS, int NH>
 __global__ void __launch_bounds__(64 * kPW, 2) k_em_prot(const EmProtArgs a)
 {
-    constexpr int RT = 2 * KS;
-    __shared__ __align__(16) ProtTables<KS> T;
+    constexpr int RH = (2 * KS + NH - 1) / NH;
+    // the tables share LDS with the staging of the log-odds (each lane reads
+    // back only what it wrote, before the first table build of the iteration)
+    __shared__ __align__(16) union {
+        ProtTables<KS, RH> T;
+        uint4 w[kPW][KS][64];
+    } U;
+    ProtTables<KS, RH> &T = U.T;
     __shared__ uint8_t sym[kPSymMax + 64];
-    __shared__ double coltot[kPW][16][24];    // M-step: column totals of each model
+    __shared__ uint32_t mm[16 * RH];    // M-step table build: window masks per kappa row
+    __shared__ float lzs[kPW][16][kPTMax];  // per-sequence log2-sum-exp2 of every model
+    __shared__ double lbg[20];              // ln of the background frequencies
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     int64_t nvalid = a.n_dev ? *a.n_dev : a.B;
@@ -128,17 +147,40 @@ __global__ void __launch_bounds__(64 * kPW, 2) k_em_prot(const EmProtArgs a)
     const int64_t b = b0 + 16 * wv + r;
     const bool vb = b < nvalid;
     const double beta = a.beta;
+    if (threadIdx.x < 20) lbg[threadIdx.x] = log(a.bg[threadIdx.x]);
+    __syncthreads();
+
+    auto unpack = [&](int i, int &L) {
+        const int64_t s0 = a.offsets[i];
+        const int n = (int)(a.offsets[i + 1] - s0);
+        L = n - l + 1;
+        __syncthreads();  // the previous users of sym and T are done
+        for (int q = threadIdx.x; q < n + 64; q += 64 * kPW)
+            sym[q] = q < n ? (uint8_t)prot_sym(a.packed, s0 + q) : (uint8_t)0;
+    };
+    auto estep = [&](const half8p(&Wb)[KS], float4p &S0, float4p &S1) {
+        S0 = float4p{0.f, 0.f, 0.f, 0.f};
+        S1 = S0;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const half8p A0 = __builtin_bit_cast(half8p, T.e[0][ks][lane]);
+            const half8p A1 = __builtin_bit_cast(half8p, T.e[1][ks][lane]);
+            S0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, Wb[ks], S0, 0, 0, 0);
+            S1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, Wb[ks], S1, 0, 0, 0);
+        }
+    };
 
     half8p Wb[KS];
-    float4p C[RT];
     for (int it = 0; it <= a.iters; ++it) {
         const bool last = it == a.iters;
         const double *src = it == 0 ? a.theta0 : a.theta_out;
-        // ---- log-odds of the lane's B-operand entries (log2 units) and the prior
+        // ---- log-odds of the lane's B-operand entries (log2 units) and the
+        // prior, one contraction step at a time through LDS (an unrolled build
+        // would keep the loads of all 8 KS entries in flight in registers)
         double prior = 0;
-#pragma unroll
+#pragma unroll 1
         for (int ks = 0; ks < KS; ++ks) {
-            half8p h;
+            half8p hv;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int kap = 32 * ks + 8 * g + j;
@@ -148,41 +190,32 @@ __global__ void __launch_bounds__(64 * kPW, 2) k_em_prot(const EmProtArgs a)
                     const double th = src[b * AL + sg * l + p];
                     if (it == 0) a.theta_out[b * AL + sg * l + p] = th;
                     const double lt = log(th);
-                    w = (float)((lt - log(a.bg[sg])) * (double)kPLog2e);
+                    w = (float)((lt - lbg[sg]) * (double)kPLog2e);
                     prior += a.bg[sg] * lt;
                 }
-                h[j] = (_Float16)w;
+                hv[j] = (_Float16)w;
             }
-            Wb[ks] = h;
+            U.w[wv][ks][lane] = __builtin_bit_cast(uint4, hv);
         }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) Wb[ks] = __builtin_bit_cast(half8p, U.w[wv][ks][lane]);
         prior += __shfl_xor(prior, 16);
         prior += __shfl_xor(prior, 32);
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) C[rt] = float4p{0.f, 0.f, 0.f, 0.f};
 
+        // ---- first sweep: log-sum-exp of every sequence (the best start too in
+        // the final E-step)
         double llr = 0;
         for (int i = 0; i < t; ++i) {
-            const int64_t s0 = a.offsets[i];
-            const int n = (int)(a.offsets[i + 1] - s0);
-            const int L = n - l + 1;
-            __syncthreads();  // the previous users of sym and T are done
-            for (int q = threadIdx.x; q < n + 64; q += 64 * kPW)
-                sym[q] = q < n ? (uint8_t)prot_sym(a.packed, s0 + q) : (uint8_t)0;
-            // ---- pass 1: log-sum-exp (and the best start in the final E-step)
+            int L;
+            unpack(i, L);
             float mx = -INFINITY, sm = 0.f, bestv = -INFINITY;
             int besti = 0;
             for (int a0 = 0; a0 < L; a0 += 32) {
                 __syncthreads();
-                build_prot_tables<KS>(sym, a0, l, false, T);
+                build_prot_tables<KS, RH>(sym, a0, l, -1, T, mm);
                 __syncthreads();
-                float4p S0 = {0.f, 0.f, 0.f, 0.f}, S1 = S0;
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    const half8p A0 = __builtin_bit_cast(half8p, T.e[0][ks][lane]);
-                    const half8p A1 = __builtin_bit_cast(half8p, T.e[1][ks][lane]);
-                    S0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, Wb[ks], S0, 0, 0, 0);
-                    S1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, Wb[ks], S1, 0, 0, 0);
-                }
+                float4p S0, S1;
+                estep(Wb, S0, S1);
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const int w = a0 + 16 * (q >> 2) + 4 * g + (q & 3);
@@ -209,48 +242,19 @@ __global__ void __launch_bounds__(64 * kPW, 2) k_em_prot(const EmProtArgs a)
             part += __shfl_xor(part, 16);
             part += __shfl_xor(part, 32);
             const float lz = M + __builtin_amdgcn_logf(part);  // log2 of the sum of 2^S
-            const double ln2 = 0.6931471805599453;
-            llr += (double)lz * ln2 - log((double)L);
-            if (last) {
-                if (a.sites) {
+            if (g == 0) lzs[wv][r][i] = lz;
+            llr += (double)lz * 0.6931471805599453 - log((double)L);
+            if (last && a.sites) {
 #pragma unroll
-                    for (int o = 16; o <= 32; o <<= 1) {
-                        const float ov = __shfl_xor(bestv, o);
-                        const int oi = __shfl_xor(besti, o);
-                        if (ov > bestv || (ov == bestv && oi < besti)) {
-                            bestv = ov;
-                            besti = oi;
-                        }
+                for (int o = 16; o <= 32; o <<= 1) {
+                    const float ov = __shfl_xor(bestv, o);
+                    const int oi = __shfl_xor(besti, o);
+                    if (ov > bestv || (ov == bestv && oi < besti)) {
+                        bestv = ov;
+                        besti = oi;
                     }
-                    if (g == 0 && vb) a.sites[b * t + i] = besti;
                 }
-                continue;
-            }
-            // ---- pass 2: normalised posteriors into the M-step accumulators
-            for (int a0 = 0; a0 < L; a0 += 32) {
-                __syncthreads();
-                build_prot_tables<KS>(sym, a0, l, true, T);
-                __syncthreads();
-                float4p S0 = {0.f, 0.f, 0.f, 0.f}, S1 = S0;
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    const half8p A0 = __builtin_bit_cast(half8p, T.e[0][ks][lane]);
-                    const half8p A1 = __builtin_bit_cast(half8p, T.e[1][ks][lane]);
-                    S0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(A0, Wb[ks], S0, 0, 0, 0);
-                    S1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, Wb[ks], S1, 0, 0, 0);
-                }
-                half8p Ph;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int w = a0 + 16 * (q >> 2) + 4 * g + (q & 3);
-                    const float v = q < 4 ? S0[q & 3] : S1[q & 3];
-                    Ph[q] = (_Float16)(w < L ? __builtin_amdgcn_exp2f(v - lz) : 0.f);
-                }
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt) {
-                    const half8p Am = __builtin_bit_cast(half8p, T.m[rt][lane]);
-                    C[rt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am, Ph, C[rt], 0, 0, 0);
-                }
+                if (g == 0 && vb) a.sites[b * t + i] = besti;
             }
         }
         if (g == 0 && vb) {
@@ -258,42 +262,68 @@ __global__ void __launch_bounds__(64 * kPW, 2) k_em_prot(const EmProtArgs a)
             if (a.llr) a.llr[b * (a.iters + 1) + it] = llr;
         }
         if (last) break;
-        // ---- M-step: counts of the lane's rows (kappa = 16 rt + 4 g + q) go to
-        // theta_out, then every column is normalised by its own total
-        __syncthreads();  // every lane has read its theta^it entries
-        if (vb) {
+
+        // ---- NH more sweeps: exactly normalised posteriors into the M-step
+        // counts of RH row tiles each, kept in registers across the sequences
+        __syncthreads();  // every lane has read its theta^it entries; lzs visible
+        for (int h = 0; h < NH; ++h) {
+            float4p C[RH];
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
+            for (int rt = 0; rt < RH; ++rt) C[rt] = float4p{0.f, 0.f, 0.f, 0.f};
+            for (int i = 0; i < t; ++i) {
+                int L;
+                unpack(i, L);
+                const float lz = lzs[wv][r][i];
+                for (int a0 = 0; a0 < L; a0 += 32) {
+                    __syncthreads();
+                    build_prot_tables<KS, RH>(sym, a0, l, h, T, mm);
+                    __syncthreads();
+                    float4p S0, S1;
+                    estep(Wb, S0, S1);
+                    half8p Ph;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int kap = 16 * rt + 4 * g + q;
-                    if (kap < nk) {
-                        const int p = kap / 20, sg = kap - 20 * p;
-                        a.theta_out[b * AL + sg * l + p] = (double)C[rt][q];
+                    for (int q = 0; q < 8; ++q) {
+                        const int w = a0 + 16 * (q >> 2) + 4 * g + (q & 3);
+                        const float v = q < 4 ? S0[q & 3] : S1[q & 3];
+                        Ph[q] = (_Float16)(w < L ? __builtin_amdgcn_exp2f(v - lz) : 0.f);
+                    }
+#pragma unroll
+                    for (int rt = 0; rt < RH; ++rt) {
+                        const half8p Am = __builtin_bit_cast(half8p, T.m[rt][lane]);
+                        C[rt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am, Ph, C[rt], 0, 0, 0);
                     }
                 }
+            }
+            // counts of the lane's rows, kappa = 16 (h RH + rt) + 4 g + q; the
+            // base goes through an empty asm statement so that the addresses of
+            // these stores are formed here, not hoisted to the kernel's entry
+            // and held (spilled) across the sweeps
+            int g4 = 16 * h * RH + 4 * g;
+            asm volatile("" : "+v"(g4));
+            if (vb) {
+#pragma unroll
+                for (int rt = 0; rt < RH; ++rt)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int kap = g4 + 16 * rt + q;
+                        if (kap < nk) {
+                            const int p = kap / 20, sg = kap - 20 * p;
+                            a.theta_out[b * AL + sg * l + p] = (double)C[rt][q];
+                        }
+                    }
+            }
         }
+        // ---- every column of the model divided by its own total; lane g takes
+        // the columns p = g, g + 4, ...
         __syncthreads();
-        // lane g sums the columns p = g, g + 4, ... of its model
         if (vb)
             for (int p = g; p < l; p += 4) {
                 double s = 0;
                 for (int c = 0; c < 20; ++c) s += a.theta_out[b * AL + c * l + p];
-                coltot[wv][r][p] = s + beta;
+                const double tot = s + beta;
+                for (int c = 0; c < 20; ++c)
+                    a.theta_out[b * AL + c * l + p] = (a.theta_out[b * AL + c * l + p] + beta * a.bg[c]) / tot;
             }
-        __syncthreads();
-        if (vb) {
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int kap = 16 * rt + 4 * g + q;
-                    if (kap < nk) {
-                        const int p = kap / 20, sg = kap - 20 * p;
-                        a.theta_out[b * AL + sg * l + p] = ((double)C[rt][q] + beta * a.bg[sg]) / coltot[wv][r][p];
-                    }
-                }
-        }
         __syncthreads();  // theta^(it+1) visible to every lane before it is read
     }
 }
@@ -301,8 +331,11 @@ __global__ void __launch_bounds__(64 * kPW, 2) k_em_prot(const EmProtArgs a)
 template <int KS>
 static int launch_prot(const EmProtArgs &a, hipStream_t st)
 {
+    // one M-step sweep while the counts of all 2 KS row tiles fit in registers
+    // beside the log-odds, two beyond
+    constexpr int NH = KS <= kPOneSweepKS ? 1 : 2;
     const int64_t groups = (a.B + 16 * kPW - 1) / (16 * kPW);
-    hipLaunchKernelGGL((k_em_prot<KS>), dim3((unsigned)groups), dim3(64 * kPW), 0, st, a);
+    hipLaunchKernelGGL((k_em_prot<KS, NH>), dim3((unsigned)groups), dim3(64 * kPW), 0, st, a);
     PM_LAUNCHED();
     return PM_OK;
 }
