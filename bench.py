@@ -106,8 +106,10 @@ def main():
     # pick the EM tile shape for this workload (timed on its own buckets)
     b = P.b
     tune_th, tune_J = torch.zeros_like(b.theta), torch.zeros_like(b.J)
-    nb_tune = min(nbk, 16384)
-    tile_shape = pm.em_autotune(P.S, l, b.theta0, P.bg, nb_tune, iters, beta, PREC, tune_th, tune_J)
+    # on all the pass's buckets: the shapes differ in workgroup size, so how
+    # well the bucket count fills the device is part of what is timed
+    tile_shape = pm.em_autotune(P.S, l, b.theta0, P.bg, nbk, iters, beta, PREC, tune_th, tune_J)
+    shape_g, shape_ppb = tile_shape // 10, tile_shape % 10
     del tune_th, tune_J
     P.run()
     torch.cuda.synchronize()
@@ -166,7 +168,7 @@ def main():
         roof = {"kernel": "k_hash<4,8,true>", "bound": "hbm", "achieved": round(hash_gbs, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4), "traffic": traffic("hash.hip")}
     else:
-        roof = {"kernel": f"k_em_mfma<5,true,true,{tile_shape}>", "bound": "mfma", "achieved": round(em_tfs, 3),
+        roof = {"kernel": f"k_em_mfma<5,true,true,{shape_ppb},{shape_g}>", "bound": "mfma", "achieved": round(em_tfs, 3),
                 "peak": FP16_MFMA_PEAK, "unit": "TFLOP/s", "frac": round(em_tfs / FP16_MFMA_PEAK, 5),
                 "traffic": traffic("em_mfma.hip"), "flops_per_launch": em_flops}
     out = {
@@ -185,7 +187,8 @@ def main():
         "data": "synthetic planted (18,6) motif, seeded",
         "config": {"workload": "(18,6) DNA: t=20, n=1000, k=8, s=4, m=5000 trials, 10 EM iterations",
                    "x_lmers_per_trial": x, "enriched_buckets": nbk, "members": nmem,
-                   "em_tile_shape": f"{tile_shape} window pairs per table build (autotuned)",
+                   "em_tile_shape": f"{16 * shape_g} models per wave, {shape_ppb} window pairs per table build "
+                                    "(autotuned)",
                    "parallelism": "single GPU"},
         "stage_ms": stage,
         "roofline": roof,
@@ -414,12 +417,7 @@ def instances_leg(torch, pm, count):
     plain = {"instances_per_s": round(count / (plain_ms / 1e3), 2), "ms": round(plain_ms, 3),
              "solved": int(solved), "solved_per_s": round(solved / (plain_ms / 1e3), 2),
              "mean_pc": round(pcs / count, 4), "em": "fp64, all enriched buckets"}
-    # the batched legs use the matrix-core EM: pick its tile shape for this
-    # length class on the first instance's buckets
-    P0 = pipes[0]
-    tune_th, tune_J = torch.zeros_like(P0.b.theta), torch.zeros_like(P0.b.J)
-    tile_shape = pm.em_autotune(P0.S, l, P0.b.theta0, P0.bg, P0.b.cap_b, iters, beta, pm.PM_F16X2, tune_th, tune_J)
-    del pipes, P0, tune_th, tune_J
+    del pipes
     torch.cuda.empty_cache()
 
     progress(f"plain leg: {plain_ms:.1f} ms")
@@ -427,6 +425,7 @@ def instances_leg(torch, pm, count):
     B = pm.Batch(4, l, k, [i.seqs for i, _ in insts], [mk for _, mk in insts])
     nbk, nmem = pm.size_batch(B, s)
     BP = pm.BatchPipeline(B, s, iters, beta, pm.PM_F16X2, bg, cap_b=nbk, cap_m=nmem)
+    tile_shape = pick_shape(torch, pm, l, BP.run)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -469,6 +468,7 @@ def instances_leg(torch, pm, count):
         return out
     tri = pm.Triage.load(path)
     TP = pm.TriagedBatchPipeline(B, s, iters, beta, pm.PM_F16X2, bg, nbk, nmem, tri, frac=0.05)
+    tri_shape = pick_shape(torch, pm, l, TP.run)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -496,10 +496,34 @@ def instances_leg(torch, pm, count):
                       "solved": int(solved), "solved_per_s": round(solved / (tri_ms / 1e3), 2),
                       "mean_pc": round(pcs / count, 4), "refined_buckets": int(TP.refined),
                       "fallbacks": int(sum(r["fell_back"] for r in res)), "frac": 0.05,
+                      "em_tile_shape": tri_shape,
                       "em": "split-f16 matrix cores on the triaged buckets, BF16 network, one HIP graph"}
     out["speedup_triaged"] = round(out["triaged"]["instances_per_s"] / plain["instances_per_s"], 3)
     out["pc_delta_triaged_vs_plain"] = round(out["triaged"]["mean_pc"] - plain["mean_pc"], 4)
     return out
+
+
+def pick_shape(torch, pm, l, run):
+    """Tile shape of the batched matrix-core EM, chosen on the whole batch: each
+    candidate pinned in turn, the pipeline run eagerly (once to warm up, once
+    timed), the fastest kept for the graph captured next."""
+    times = {}
+    for shape in (11, 12, 21, 22):
+        try:
+            pm.em_set_tuning(l, pm.PM_F16X2, shape)
+        except pm.PmError:
+            continue
+        run()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        times[shape] = e0.elapsed_time(e1)
+    best = min(times, key=times.get)
+    pm.em_set_tuning(l, pm.PM_F16X2, best)
+    progress("batch tile shapes (ms): " + ", ".join(f"{k}: {v:.2f}" for k, v in times.items()))
+    return best
 
 
 def cpu_baseline(inst, masks, cfg, bg, beta, nbk, budget):

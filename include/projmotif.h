@@ -184,18 +184,27 @@ int em_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *b
               double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *stream);
 
 /* Tile-shape autotuner of the matrix-core EM (PM_F16X2, PM_F16): runs
- * em_refine on the caller's B models once per candidate shape (window pairs
- * whose one-hot tables are built per workgroup barrier: 1 or 2), times each
+ * em_refine on the caller's B models once per candidate shape, times each
  * with HIP events on `stream` (the call synchronises), and records the
  * fastest for models of length class ceil(l/4) and this precision in a
  * process-wide table that later em_refine / em_refine_batch calls use.
+ * A shape is coded 10 G + PPB: G groups of 16 models per wave (1, or 2 for
+ * l <= 24), PPB window pairs whose one-hot tables are built per workgroup
+ * barrier (1 or 2).  Pass B of the size the later calls will have: the
+ * shapes differ in workgroup size, so their ranking depends on how well B
+ * fills the device.
  * theta_out, J_out: device scratch of em_refine's shapes (overwritten).
  * choice_out: host int32[1] or NULL.  em_tuning returns the shape in use
- * (untuned: 2), or a negative status. */
+ * (untuned: 12), or a negative status. */
 int em_autotune(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B, int32_t iters,
                 double beta, int32_t precision, double *theta_out, double *J_out, int32_t *choice_out,
                 void *stream);
 int em_tuning(int32_t l, int32_t precision);
+/* Records `shape` (coded as above) for l's length class and `precision`, in
+ * place of a tuned or default one: for callers that tuned in an earlier
+ * process or want a fixed shape.  PM_EINVAL for a shape the class cannot
+ * take. */
+int em_set_tuning(int32_t l, int32_t precision, int32_t shape);
 
 /* a10 -- Sec. 5.1: the model with the highest objective wins.  best_out
  * device int64[1]: the bucket with the largest J(theta^iters), lowest index

@@ -32,7 +32,7 @@ EXPORTS = [
     "pm_em_batch_workspace", "em_refine_batch", "em_best_batch",
     "triage_features", "pm_triage_packed_bytes", "triage_pack", "triage_forward", "pm_triage_workspace",
     "triage_train_step", "pm_triage_select_workspace", "triage_select", "triage_fallback_select",
-    "triage_merge_best", "em_autotune", "em_tuning",
+    "triage_merge_best", "em_autotune", "em_tuning", "em_set_tuning",
 ]
 
 PM_TRIAGE_PARAMS, PM_TRIAGE_INPUTS = 88577, 87
@@ -140,6 +140,7 @@ def lib():
         "triage_merge_best": (C.c_int, [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P]),
         "em_autotune": (C.c_int, [C.POINTER(pm_seqs), i32, P, P, i64, i32, dbl, i32, P, P, P, P]),
         "em_tuning": (C.c_int, [i32, i32]),
+        "em_set_tuning": (C.c_int, [i32, i32, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -245,6 +246,10 @@ def em_tuning(l: int, precision: int) -> int:
     if v < 0:
         _check(v)
     return v
+
+
+def em_set_tuning(l: int, precision: int, shape: int) -> None:
+    _check(lib().em_set_tuning(l, precision, shape))
 
 
 def em_best(J, B, n_dev, iters, theta, alphabet, l, best_out, consensus_out=None, stream=None):

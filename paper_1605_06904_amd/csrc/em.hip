@@ -379,6 +379,13 @@ extern "C" int em_tuning(int32_t l, int32_t precision)
     return em_tuned_shape(l, precision == PM_F16X2);
 }
 
+extern "C" int em_set_tuning(int32_t l, int32_t precision, int32_t shape)
+{
+    clear_error();
+    if (l < 1 || l > 32 || (precision != PM_F16X2 && precision != PM_F16)) return fail(PM_EINVAL, "bad l/precision");
+    return em_record_shape(l, precision == PM_F16X2, shape);
+}
+
 extern "C" int em_refine_batch(const pm_batch *Bt, const pm_bucket *buckets, const double *theta0, const double *bg,
                                int64_t B, const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
                                double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *ws,

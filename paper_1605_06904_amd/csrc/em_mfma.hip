@@ -33,12 +33,15 @@
 // neither a cross-lane maximum nor a rescale.  Posteriors enter the M-step as
 // 2^(S - ref + kPOff) <= 2^(kPOff + kSlack) = 2^15, inside the FP16 range.
 //
-// Work split: a workgroup of four waves takes 64 models (16 per wave) of one
-// instance; the four waves sweep the same windows in step and build the
-// one-hot tables of PPB window pairs together in LDS (double-buffered, one
-// barrier per PPB pairs) from the packed instance staged in LDS.  PPB is the
-// tunable tile shape: em_autotune times the variants on the caller's models
-// and records the fastest per (ceil(l/4), precision) class.
+// Work split: a workgroup of four waves takes 64 G models of one instance, G
+// groups of 16 per wave; the groups of a wave share every A operand (the
+// one-hot tables), so G = 2 halves the table reads and builds per model and
+// gives each wave two independent E-step/softmax/M-step chains to interleave.
+// The four waves sweep the same windows in step and build the one-hot tables
+// of PPB window pairs together in LDS (double-buffered, one barrier per PPB
+// pairs) from the packed instance staged in LDS.  (G, PPB) is the tunable tile
+// shape: em_autotune times the variants on the caller's models and records
+// the fastest per (ceil(l/4), precision) class.
 #include <math.h>
 #include <stdlib.h>
 
@@ -73,9 +76,18 @@ struct EmMfmaArgs {
     int P;
 };
 
+// workgroups of a launch that takes mw models per workgroup: whole groups of
+// the B models, or, for a batch, the plan's count bounded by one partly filled
+// group per instance
+static inline int64_t em_groups(const EmMfmaArgs &a, int mw)
+{
+    const int64_t full = (a.B + mw - 1) / mw;
+    return a.inst ? full + a.P : full;
+}
+
 // Workgroup plan of a batch: the instances in decreasing order of windows
-// (the longest sweeps start first), each cut into groups of 16 * kWaves
-// consecutive buckets.  Layout: wg_start[P + 1] (first workgroup of each rank),
+// (the longest sweeps start first), each cut into groups of 16 kWaves G
+// consecutive buckets (the models of one workgroup).  Layout: wg_start[P + 1] (first workgroup of each rank),
 // b0[P], b1[P] (bucket range of each instance), order[P] (instance of each rank).
 struct PlanView {
     const int64_t *wg_start, *b0, *b1, *order;
@@ -86,7 +98,10 @@ __host__ __device__ inline PlanView plan_view(const int64_t *plan, int P)
 }
 
 constexpr int kWaves = 4;  // waves (groups of 16 models) per workgroup
-constexpr int kPPBDefault = 2;  // window pairs built per workgroup barrier, untuned
+// tile shape 10 G + PPB: G groups of 16 models per wave, PPB window pairs
+// built per workgroup barrier
+constexpr int kShapeDefault = 12;  // untuned
+constexpr int kMaxMT2 = 6;         // G = 2 for ceil(l/4) <= 6 (registers)
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kPOff = 3.0f;
 constexpr float kSlack = 12.0f;
@@ -150,13 +165,15 @@ __device__ __forceinline__ uint32_t pack_hi(float p0, float p1)
 template <int MT>
 struct Tiles {
     static constexpr int LB = (MT + 1) / 2;
-    static constexpr int PX = 8 * LB;
+    static constexpr int CX = 4 * MT;       // count rows (positions) of a model
+    static constexpr int NE = 4 * MT + 12;  // M-step table entries a pair reads
 };
 
 // one-hot tables of one window pair: the symbols at s0 + a0 + e
-struct PairTables {
-    uint32_t oh2[64][4];     // letters 0..3 of symbol e, then of symbol e+1
-    uint32_t mt8[64][4][4];  // [e][c]: symbols e..e+3 and e+16..e+19 == c
+template <int MT>
+struct alignas(16) PairTables {
+    uint32_t oh2[64][4];          // letters 0..3 of symbol e, then of symbol e+1
+    uint4 mt8[Tiles<MT>::NE][4];  // [e][c]: symbols e..e+3 and e+16..e+19 == c
 };
 
 // lut[y]: four FP16 halves, half q = 1.0 where 2-bit field q of y (from the top)
@@ -171,18 +188,20 @@ __device__ __forceinline__ void build_lut(uint2 *lut)
 }
 
 // Workgroup-cooperative build: thread (e = tid / 4, c = tid % 4) writes
-// mt8[e][c] and word c of oh2[e].
-template <bool CLAMP>
+// mt8[e][c] (e < NE) and word c of oh2[e].
+template <int MT, bool CLAMP>
 __device__ __forceinline__ void build_tables(const uint32_t *W, int64_t nw, int64_t base, const uint2 *lut,
-                                             PairTables &T)
+                                             PairTables<MT> &T)
 {
     const int tid = threadIdx.x, e = tid >> 2;
     const uint32_t c = tid & 3u;
     uint32_t hi, lo;
     dna32<CLAMP>(W, base + e, nw, hi, lo);
-    const uint32_t cc = c * 0x55u;
-    const uint2 u0 = lut[(hi >> 24) ^ cc], u1 = lut[(lo >> 24) ^ cc];
-    *reinterpret_cast<uint4 *>(&T.mt8[e][c][0]) = make_uint4(u0.x, u0.y, u1.x, u1.y);
+    if (e < Tiles<MT>::NE) {
+        const uint32_t cc = c * 0x55u;
+        const uint2 u0 = lut[(hi >> 24) ^ cc], u1 = lut[(lo >> 24) ^ cc];
+        T.mt8[e][c] = make_uint4(u0.x, u0.y, u1.x, u1.y);
+    }
     // word c of oh2[e]: letters 2(c&1), 2(c&1)+1 of symbol e (c < 2) or e+1
     const uint32_t sym = c < 2 ? hi >> 30 : (hi >> 28) & 3u;
     T.oh2[e][c] = (sym >> 1) == (c & 1u) ? 0x3C00u << ((sym & 1u) << 4) : 0u;
@@ -196,10 +215,12 @@ struct SeqState {
 };
 
 // One pair of 16-window tiles (windows a0 .. a0+31 of one sequence) for this
-// wave's 16 models.
-template <int MT, bool LAST, bool TAIL, bool SPLIT>
-__device__ __forceinline__ void tile_pair(int a0, int L, const PairTables &T, const half8 (&Whi)[Tiles<MT>::LB],
-                                          const half8 (&Wlo)[Tiles<MT>::LB], float4v (&O)[MT], SeqState &st)
+// wave's G groups of 16 models; the groups share the A operands.
+template <int MT, bool LAST, bool TAIL, bool SPLIT, int G>
+__device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T,
+                                          const half8 (&Whi)[G][Tiles<MT>::LB],
+                                          const half8 (&Wlo)[G][Tiles<MT>::LB], float4v (&O)[G][MT],
+                                          SeqState (&st)[G])
 {
     constexpr int LB = Tiles<MT>::LB;
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
@@ -209,156 +230,194 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables &T, co
 #pragma unroll
         for (int kb = 0; kb < LB; ++kb)
             Ae[t2][kb] = *reinterpret_cast<const half8 *>(&T.oh2[16 * t2 + r + 8 * kb + 2 * g][0]);
-    // E-step, already shifted: S' = S - (mref - kPOff); one chain per tile
-    const float sh = st.mref - kPOff;
-    float4v S0 = {-sh, -sh, -sh, -sh}, S1 = S0;
+    // E-step, already shifted: S' = S - (mref - kPOff); one chain per tile and group
+    float sh[G];
+    float4v S0[G], S1[G];
 #pragma unroll
-    for (int kb = 0; kb < LB; ++kb) {
-        S0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[0][kb], Whi[kb], S0, 0, 0, 0);
-        S1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[1][kb], Whi[kb], S1, 0, 0, 0);
-        if (SPLIT) {
-            S0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[0][kb], Wlo[kb], S0, 0, 0, 0);
-            S1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[1][kb], Wlo[kb], S1, 0, 0, 0);
-        }
+    for (int q = 0; q < G; ++q) {
+        sh[q] = st[q].mref - kPOff;
+        S0[q] = float4v{-sh[q], -sh[q], -sh[q], -sh[q]};
+        S1[q] = S0[q];
     }
+#pragma unroll
+    for (int kb = 0; kb < LB; ++kb)
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            S0[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[0][kb], Whi[q][kb], S0[q], 0, 0, 0);
+            S1[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[1][kb], Whi[q][kb], S1[q], 0, 0, 0);
+            if (SPLIT) {
+                S0[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[0][kb], Wlo[q][kb], S0[q], 0, 0, 0);
+                S1[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[1][kb], Wlo[q][kb], S1[q], 0, 0, 0);
+            }
+        }
     half8 Am[MT];
     if (!LAST) {
         // M-step A operand: row (position pm, letter cm); windows 4g..4g+3 of both tiles
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-            Am[mt] = *reinterpret_cast<const half8 *>(&T.mt8[4 * g + 4 * mt + (r >> 2)][r & 3][0]);
+            Am[mt] = __builtin_bit_cast(half8, T.mt8[4 * g + 4 * mt + (r >> 2)][r & 3]);
     }
-    float S[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        S[j] = S0[j];
-        S[4 + j] = S1[j];
-    }
-    if (TAIL) {
+    for (int q = 0; q < G; ++q) {
+        float S[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (a0 + 16 * (q >> 2) + 4 * g + (q & 3) >= L) S[q] = -INFINITY;
-    }
-    float tm = fmaxf(fmaxf(fmaxf(S[0], S[1]), fmaxf(S[2], S[3])), fmaxf(fmaxf(S[4], S[5]), fmaxf(S[6], S[7])));
-    if (LAST) {
+        for (int j = 0; j < 4; ++j) {
+            S[j] = S0[q][j];
+            S[4 + j] = S1[q][j];
+        }
+        if (TAIL) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (S[q] + sh > st.bestv) {
-                st.bestv = S[q] + sh;
-                st.besti = a0 + 16 * (q >> 2) + 4 * g + (q & 3);
+            for (int u = 0; u < 8; ++u)
+                if (a0 + 16 * (u >> 2) + 4 * g + (u & 3) >= L) S[u] = -INFINITY;
+        }
+        // the common path needs only whether a score passed the slack, not the
+        // maximum (which fmaxf would form after quieting each operand)
+        bool big = false;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) big |= S[u] > kPOff + kSlack;
+        if (LAST) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (S[u] + sh[q] > st[q].bestv) {
+                    st[q].bestv = S[u] + sh[q];
+                    st[q].besti = a0 + 16 * (u >> 2) + 4 * g + (u & 3);
+                }
+        }
+        if (__builtin_expect(__ballot(big) != 0, 0)) {
+            // rare: move the reference up to the model's new maximum
+            float tm = fmaxf(fmaxf(fmaxf(S[0], S[1]), fmaxf(S[2], S[3])), fmaxf(fmaxf(S[4], S[5]), fmaxf(S[6], S[7])));
+            tm = fmaxf(tm, __shfl_xor(tm, 16));
+            tm = fmaxf(tm, __shfl_xor(tm, 32));
+            const float d = tm > kPOff + kSlack ? tm - kPOff : 0.f;
+            const float al = __builtin_amdgcn_exp2f(-d);
+            st[q].srun *= al;
+            if (!LAST)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) O[q][mt] *= al;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) S[u] -= d;
+            st[q].mref += d;
+        }
+        float P[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) P[u] = __builtin_amdgcn_exp2f(S[u]);
+        st[q].srun += ((P[0] + P[1]) + (P[2] + P[3])) + ((P[4] + P[5]) + (P[6] + P[7]));
+        if (!LAST) {
+            uint4 h;
+            h.x = pack_hi(P[0], P[1]);
+            h.y = pack_hi(P[2], P[3]);
+            h.z = pack_hi(P[4], P[5]);
+            h.w = pack_hi(P[6], P[7]);
+            const half8 Ph = __builtin_bit_cast(half8, h);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                O[q][mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[mt], Ph, O[q][mt], 0, 0, 0);
+            if (SPLIT) {
+                uint4 lw;
+                lw.x = split_lo(h.x, P[0], P[1]);
+                lw.y = split_lo(h.y, P[2], P[3]);
+                lw.z = split_lo(h.z, P[4], P[5]);
+                lw.w = split_lo(h.w, P[6], P[7]);
+                const half8 Pl = __builtin_bit_cast(half8, lw);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    O[q][mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[mt], Pl, O[q][mt], 0, 0, 0);
             }
-    }
-    if (__builtin_expect(__ballot(tm > kPOff + kSlack) != 0, 0)) {
-        // rare: move the reference up to the model's new maximum
-        tm = fmaxf(tm, __shfl_xor(tm, 16));
-        tm = fmaxf(tm, __shfl_xor(tm, 32));
-        const float d = tm > kPOff + kSlack ? tm - kPOff : 0.f;
-        const float al = __builtin_amdgcn_exp2f(-d);
-        st.srun *= al;
-        if (!LAST)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) O[mt] *= al;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) S[q] -= d;
-        st.mref += d;
-    }
-    float P[8], ps = 0.f;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        P[q] = __builtin_amdgcn_exp2f(S[q]);
-        ps += P[q];
-    }
-    st.srun += ps;
-    if (!LAST) {
-        uint4 h;
-        h.x = pack_hi(P[0], P[1]);
-        h.y = pack_hi(P[2], P[3]);
-        h.z = pack_hi(P[4], P[5]);
-        h.w = pack_hi(P[6], P[7]);
-        const half8 Ph = __builtin_bit_cast(half8, h);
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) O[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[mt], Ph, O[mt], 0, 0, 0);
-        if (SPLIT) {
-            uint4 lw;
-            lw.x = split_lo(h.x, P[0], P[1]);
-            lw.y = split_lo(h.y, P[2], P[3]);
-            lw.z = split_lo(h.z, P[4], P[5]);
-            lw.w = split_lo(h.w, P[6], P[7]);
-            const half8 Pl = __builtin_bit_cast(half8, lw);
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) O[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[mt], Pl, O[mt], 0, 0, 0);
         }
     }
 }
 
 // One sequence: every window pair (tables built by the whole workgroup), then
 // the per-sequence log-sum-exp and counts, or, in the final E-step, the best
-// start of every model.
-template <int MT, bool STAGED, bool LAST, bool SPLIT, int PPB>
+// start of every model.  acc[q]: the count accumulators of group q.
+template <int MT, bool STAGED, bool LAST, bool SPLIT, int PPB, int G>
 __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, const uint2 *lut, int i, int64_t bw,
-                                      int64_t nvalid, PairTables *tabs, int &parity, float (*acc)[Tiles<MT>::PX][4],
-                                      const half8 (&Whi)[Tiles<MT>::LB], const half8 (&Wlo)[Tiles<MT>::LB],
-                                      float mlow, double &llr)
+                                      int64_t nvalid, PairTables<MT> *tabs, int &parity,
+                                      float (*acc)[16][Tiles<MT>::CX][4], const half8 (&Whi)[G][Tiles<MT>::LB],
+                                      const half8 (&Wlo)[G][Tiles<MT>::LB], const float (&mlow)[G],
+                                      double (&llr)[G])
 {
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     const int64_t s0 = a.offsets[i];
     const int L = (int)(a.offsets[i + 1] - s0) - a.l + 1;
-    float4v O[MT];
+    float4v O[G][MT];
+    SeqState st[G];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) O[mt] = float4v{0.f, 0.f, 0.f, 0.f};
-    // the reference starts at the lowest score the model can give
-    SeqState st{mlow, 0.f, -INFINITY, 0};
+    for (int q = 0; q < G; ++q) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) O[q][mt] = float4v{0.f, 0.f, 0.f, 0.f};
+        // the reference starts at the lowest score the model can give
+        st[q] = SeqState{mlow[q], 0.f, -INFINITY, 0};
+    }
     for (int a0 = 0; a0 < L; a0 += 32 * PPB) {
-        PairTables *T = tabs + PPB * parity;
+        PairTables<MT> *T = tabs + PPB * parity;
         parity ^= 1;
 #pragma unroll
         for (int u = 0; u < PPB; ++u)
-            if (a0 + 32 * u < L) build_tables<!STAGED>(W, a.nwords, s0 + a0 + 32 * u, lut, T[u]);
+            if (a0 + 32 * u < L) build_tables<MT, !STAGED>(W, a.nwords, s0 + a0 + 32 * u, lut, T[u]);
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < PPB; ++u) {
             const int b0 = a0 + 32 * u;
-            if (b0 + 32 <= L) tile_pair<MT, LAST, false, SPLIT>(b0, L, T[u], Whi, Wlo, O, st);
-            else if (b0 < L) tile_pair<MT, LAST, true, SPLIT>(b0, L, T[u], Whi, Wlo, O, st);
+            if (b0 + 32 <= L) tile_pair<MT, LAST, false, SPLIT, G>(b0, L, T[u], Whi, Wlo, O, st);
+            else if (b0 < L) tile_pair<MT, LAST, true, SPLIT, G>(b0, L, T[u], Whi, Wlo, O, st);
         }
     }
-    float sr = st.srun;
-    sr += __shfl_xor(sr, 16);
-    sr += __shfl_xor(sr, 32);
-    const double ln2 = 0.6931471805599453;
-    const double lse = ((double)st.mref - (double)kPOff) * ln2 + log((double)sr);
-    llr += lse - log((double)L);
-    if (!LAST) {
-        const float inv = 1.0f / sr;
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            float4v *dst = reinterpret_cast<float4v *>(&acc[r][4 * mt + g][0]);
-            *dst += O[mt] * inv;
-        }
-    } else if (a.sites) {
-        float bv = st.bestv;
-        int bi = st.besti;
+    for (int q = 0; q < G; ++q) {
+        float sr = st[q].srun;
+        sr += __shfl_xor(sr, 16);
+        sr += __shfl_xor(sr, 32);
+        const double ln2 = 0.6931471805599453;
+        const double lse = ((double)st[q].mref - (double)kPOff) * ln2 + log((double)sr);
+        llr[q] += lse - log((double)L);
+        if (!LAST) {
+            const float inv = 1.0f / sr;
 #pragma unroll
-        for (int o = 16; o <= 32; o <<= 1) {
-            const float ov = __shfl_xor(bv, o);
-            const int oi = __shfl_xor(bi, o);
-            if (ov > bv || (ov == bv && oi < bi)) {
-                bv = ov;
-                bi = oi;
+            for (int mt = 0; mt < MT; ++mt) {
+                float4v *dst = reinterpret_cast<float4v *>(&acc[q][r][4 * mt + g][0]);
+                *dst += O[q][mt] * inv;
             }
+        } else if (a.sites) {
+            float bv = st[q].bestv;
+            int bi = st[q].besti;
+#pragma unroll
+            for (int o = 16; o <= 32; o <<= 1) {
+                const float ov = __shfl_xor(bv, o);
+                const int oi = __shfl_xor(bi, o);
+                if (ov > bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                }
+            }
+            const int64_t b = bw + 16 * q + r;
+            if (g == 0 && b < nvalid) a.sites[b * a.site_stride + i] = bi;
         }
-        const int64_t b = bw + r;
-        if (g == 0 && b < nvalid) a.sites[b * a.site_stride + i] = bi;
     }
 }
 
-template <int MT, bool STAGED, bool SPLIT, int PPB>
-__global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(const EmMfmaArgs a0)
+// static LDS of a workgroup and the waves per SIMD to compile for: three when
+// the registers of ceil(l/4) <= 5 allow it and three workgroups' LDS (with a
+// staged instance of up to 6 KB) fit the 160 KB of a CU, else two
+template <int MT, int PPB, int G>
+constexpr int em_static_lds()
 {
-    constexpr int LB = Tiles<MT>::LB, PX = Tiles<MT>::PX;
-    __shared__ __align__(16) PairTables tabs[2 * PPB];
+    return 2 * PPB * (int)sizeof(PairTables<MT>) + 256 * (int)sizeof(uint2) + kWaves * G * 16 * Tiles<MT>::CX * 16;
+}
+template <int MT, int PPB, int G>
+constexpr int em_waves_per_simd()
+{
+    return MT <= 5 && 3 * (em_static_lds<MT, PPB, G>() + 6 * 1024) <= 160 * 1024 ? 3 : 2;
+}
+
+// G groups of 16 models per wave, kWaves waves per workgroup
+template <int MT, bool STAGED, bool SPLIT, int PPB, int G>
+__global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())) k_em_mfma(const EmMfmaArgs a0)
+{
+    constexpr int LB = Tiles<MT>::LB, CX = Tiles<MT>::CX, MW = 16 * kWaves * G;
+    __shared__ __align__(16) PairTables<MT> tabs[2 * PPB];
     __shared__ __align__(16) uint2 lut[256];
-    __shared__ __align__(16) float accs[kWaves][16][PX][4];
+    __shared__ __align__(16) float accs[kWaves][G][16][CX][4];
     extern __shared__ __align__(16) uint32_t staged[];
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
@@ -382,12 +441,12 @@ __global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(cons
         a.t = I.t;
         a.nwords = (I.n_total + 15) / 16 + 4;
         a.stage_words = STAGED ? (int)a.nwords : 0;
-        b0 = pv.b0[p] + (wg - pv.wg_start[lo]) * 16 * kWaves;
-        nvalid = pv.b1[p] < b0 + 16 * kWaves ? pv.b1[p] : b0 + 16 * kWaves;
+        b0 = pv.b0[p] + (wg - pv.wg_start[lo]) * MW;
+        nvalid = pv.b1[p] < b0 + MW ? pv.b1[p] : b0 + MW;
     } else {
         nvalid = a.n_dev ? *a.n_dev : a.B;
         if (nvalid > a.B) nvalid = a.B;
-        b0 = (int64_t)blockIdx.x * 16 * kWaves;
+        b0 = (int64_t)blockIdx.x * MW;
         if (b0 >= nvalid) return;  // uniform over the workgroup
     }
     if (STAGED)
@@ -395,141 +454,178 @@ __global__ void __launch_bounds__(64 * kWaves, (MT <= 5 ? 3 : 2)) k_em_mfma(cons
             staged[k] = k < a.stage_words ? a.packed[k] : 0u;
     const uint32_t *W = STAGED ? staged : a.packed;
     build_lut(lut);
-    const int64_t bw = b0 + 16 * wv;
-    float (*acc)[PX][4] = accs[wv];
+    const int64_t bw = b0 + 16 * G * wv;
+    float (*acc)[16][CX][4] = accs[wv];
     const int l = a.l, t = a.t, AL = 4 * l;
     const double beta = a.beta;
-    const int64_t b = bw + r;
-    const bool vb = b < nvalid;
     int parity = 0;
 
-    half8 Whi[LB], Wlo[LB];
+    half8 Whi[G][LB], Wlo[G][LB];
     for (int it = 0; it <= a.iters; ++it) {
         const bool last = it == a.iters;
         const double *src = it == 0 ? a.theta0 : a.theta_out;
-        // ---- log-odds (log2 units) of the wave's models, own entries p = 4mt + g
-        double prior = 0;
-        float wmin = 0.f;
-        #pragma unroll 1
-        for (int mt = 0; mt < 2 * LB; ++mt) {
-            const int p = 4 * mt + g;
-            float mn = 0.f;
-            #pragma unroll 1
-            for (int c = 0; c < 4; ++c) {
-                float w = 0.f;
-                if (p < l && vb) {
-                    const double th = src[b * AL + c * l + p];
-                    if (it == 0) a.theta_out[b * AL + c * l + p] = th;
-                    const double lt = log(th);
-                    w = (float)((lt - log(a.bg[c])) * (double)kLog2e);
-                    prior += a.bg[c] * lt;
+        // ---- log-odds (log2 units) of the lane's E-step B operands: model r of
+        // group q, positions 8kb+2g and 8kb+2g+1, letters 0..3, split in two
+        // FP16 halves; the lane's entries cover every position once across the
+        // four lane groups, so the prior and the lowest score are lane sums
+        double prior[G];
+        float mlow[G];
+        // the lane's position base goes through an empty asm statement so that
+        // the index arithmetic below is formed here each iteration rather than
+        // hoisted out of the loop into registers the sweeps need
+        int g2 = 2 * g;
+        asm volatile("" : "+v"(g2));
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const int64_t b = bw + 16 * q + r;
+            const bool vb = b < nvalid;
+            double pr = 0;
+            float wmin = 0.f;
+#pragma unroll
+            for (int kb = 0; kb < LB; ++kb) {
+                half8 hi, lo;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int p = 8 * kb + g2 + h;
+                    float mn = 0.f;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        float w = 0.f;
+                        if (p < l && vb) {
+                            const double th = src[b * AL + c * l + p];
+                            if (it == 0) a.theta_out[b * AL + c * l + p] = th;
+                            const double lt = log(th);
+                            w = (float)((lt - log(a.bg[c])) * (double)kLog2e);
+                            pr += a.bg[c] * lt;
+                        }
+                        mn = c == 0 ? w : fminf(mn, w);
+                        hi[4 * h + c] = (_Float16)w;
+                        lo[4 * h + c] = (_Float16)(w - (float)hi[4 * h + c]);
+                    }
+                    wmin += mn;
                 }
-                acc[r][p][c] = w;
-                mn = c == 0 ? w : fminf(mn, w);
+                Whi[q][kb] = hi;
+                Wlo[q][kb] = lo;
             }
-            wmin += mn;
+            pr += __shfl_xor(pr, 16);
+            pr += __shfl_xor(pr, 32);
+            wmin += __shfl_xor(wmin, 16);
+            wmin += __shfl_xor(wmin, 32);
+            prior[q] = pr;
+            // lowest possible score, a little below to absorb rounding
+            mlow[q] = wmin - 1.0f;
         }
-        prior += __shfl_xor(prior, 16);
-        prior += __shfl_xor(prior, 32);
-        wmin += __shfl_xor(wmin, 16);
-        wmin += __shfl_xor(wmin, 32);
-        // lowest possible score, a little below to absorb rounding
-        const float mlow = wmin - 1.0f;
-        wave_sync();
-        // ---- E-step B operands: positions 8kb+2g and 8kb+2g+1, letters 0..3
-#pragma unroll
-        for (int kb = 0; kb < LB; ++kb) {
-            const int p0 = 8 * kb + 2 * g;
-            const float4v u = *reinterpret_cast<const float4v *>(&acc[r][p0][0]);
-            const float4v v = *reinterpret_cast<const float4v *>(&acc[r][p0 + 1][0]);
-            half8 hi, lo;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                hi[q] = (_Float16)u[q];
-                lo[q] = (_Float16)(u[q] - (float)hi[q]);
-                hi[q + 4] = (_Float16)v[q];
-                lo[q + 4] = (_Float16)(v[q] - (float)hi[q + 4]);
-            }
-            Whi[kb] = hi;
-            Wlo[kb] = lo;
-        }
-        wave_sync();
         // ---- clear the count accumulators (own entries)
 #pragma unroll
-        for (int mt = 0; mt < 2 * LB; ++mt)
-            *reinterpret_cast<float4v *>(&acc[r][4 * mt + g][0]) = float4v{0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                *reinterpret_cast<float4v *>(&acc[q][r][4 * mt + g][0]) = float4v{0.f, 0.f, 0.f, 0.f};
         __syncthreads();  // staged sequence visible (first pass), tables free
 
-        double llr = 0;
+        double llr[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) llr[q] = 0;
         for (int i = 0; i < t; ++i) {
-            if (last) sweep<MT, STAGED, true, SPLIT, PPB>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
-            else sweep<MT, STAGED, false, SPLIT, PPB>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
+            if (last)
+                sweep<MT, STAGED, true, SPLIT, PPB, G>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
+            else
+                sweep<MT, STAGED, false, SPLIT, PPB, G>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow,
+                                                        llr);
         }
         // ---- objective of theta^it, then the M-step (own entries)
-        if (g == 0 && vb) {
-            a.J[b * (a.iters + 1) + it] = llr + beta * prior;
-            if (a.llr) a.llr[b * (a.iters + 1) + it] = llr;
-        }
-        if (!last && vb) {
-            #pragma unroll 1
-            for (int mt = 0; mt < MT; ++mt) {
-                const int p = 4 * mt + g;
-                if (p < l) {
-                    const float4v cn = *reinterpret_cast<const float4v *>(&acc[r][p][0]);
-                    // every column's counts sum to t: normalising by the column's
-                    // own total is the same update and stays on the simplex
-                    const double tot = (double)cn[0] + (double)cn[1] + (double)cn[2] + (double)cn[3] + beta;
-                    #pragma unroll 1
-                    for (int c = 0; c < 4; ++c)
-                        a.theta_out[b * AL + c * l + p] = ((double)cn[c] + beta * a.bg[c]) / tot;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const int64_t b = bw + 16 * q + r;
+            const bool vb = b < nvalid;
+            if (g == 0 && vb) {
+                a.J[b * (a.iters + 1) + it] = llr[q] + beta * prior[q];
+                if (a.llr) a.llr[b * (a.iters + 1) + it] = llr[q];
+            }
+            if (!last && vb) {
+                #pragma unroll 1
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int p = 4 * mt + g;
+                    if (p < l) {
+                        const float4v cn = *reinterpret_cast<const float4v *>(&acc[q][r][p][0]);
+                        // every column's counts sum to t: normalising by the column's
+                        // own total is the same update and stays on the simplex
+                        const double tot = (double)cn[0] + (double)cn[1] + (double)cn[2] + (double)cn[3] + beta;
+                        #pragma unroll 1
+                        for (int c = 0; c < 4; ++c)
+                            a.theta_out[b * AL + c * l + p] = ((double)cn[c] + beta * a.bg[c]) / tot;
+                    }
                 }
             }
         }
-        wave_sync();
+        // theta^(it+1) visible to the lanes that read it: a lane's log-odds
+        // entries were normalised by other lanes of its wave
+        __syncthreads();
     }
 }
 
-template <int MT, bool SPLIT, int PPB>
-static int launch_em_mfma(const EmMfmaArgs &a, int64_t groups, hipStream_t st)
+template <int MT, bool SPLIT, int PPB, int G>
+static int launch_em_mfma(const EmMfmaArgs &a, hipStream_t st)
 {
+    const int64_t groups = em_groups(a, 16 * kWaves * G);
     if (a.stage_words)
-        hipLaunchKernelGGL((k_em_mfma<MT, true, SPLIT, PPB>), dim3((unsigned)groups), dim3(64 * kWaves),
+        hipLaunchKernelGGL((k_em_mfma<MT, true, SPLIT, PPB, G>), dim3((unsigned)groups), dim3(64 * kWaves),
                            (size_t)(a.stage_words + kStagePad) * 4, st, a);
     else
-        hipLaunchKernelGGL((k_em_mfma<MT, false, SPLIT, PPB>), dim3((unsigned)groups), dim3(64 * kWaves), 0, st, a);
+        hipLaunchKernelGGL((k_em_mfma<MT, false, SPLIT, PPB, G>), dim3((unsigned)groups), dim3(64 * kWaves), 0, st,
+                           a);
     PM_LAUNCHED();
     return PM_OK;
 }
 
-// tile shape in use per (ceil(l/4) - 1, split): 0 = untuned (kPPBDefault)
-static int g_ppb[8][2];
+// tile shape in use per (ceil(l/4) - 1, split), coded 10 G + PPB; 0 = untuned
+static int g_shape[8][2];
 
-static int tuned_ppb(int l, bool split)
+static bool shape_ok(int shape, int l)
 {
-    const int v = g_ppb[(l + 3) / 4 - 1][split ? 1 : 0];
-    return v ? v : kPPBDefault;
+    const int G = shape / 10, ppb = shape % 10;
+    return (ppb == 1 || ppb == 2) && (G == 1 || (G == 2 && (l + 3) / 4 <= kMaxMT2));
 }
 
-template <bool SPLIT, int PPB>
-static int dispatch_mt(const EmMfmaArgs &a, int64_t groups, hipStream_t st)
+static int tuned_shape(int l, bool split)
+{
+    const int v = g_shape[(l + 3) / 4 - 1][split ? 1 : 0];
+    return v ? v : kShapeDefault;
+}
+
+template <bool SPLIT, int PPB, int G>
+static int dispatch_mt(const EmMfmaArgs &a, hipStream_t st)
 {
     switch ((a.l + 3) / 4) {
-    case 1: return launch_em_mfma<1, SPLIT, PPB>(a, groups, st);
-    case 2: return launch_em_mfma<2, SPLIT, PPB>(a, groups, st);
-    case 3: return launch_em_mfma<3, SPLIT, PPB>(a, groups, st);
-    case 4: return launch_em_mfma<4, SPLIT, PPB>(a, groups, st);
-    case 5: return launch_em_mfma<5, SPLIT, PPB>(a, groups, st);
-    case 6: return launch_em_mfma<6, SPLIT, PPB>(a, groups, st);
-    case 7: return launch_em_mfma<7, SPLIT, PPB>(a, groups, st);
-    default: return launch_em_mfma<8, SPLIT, PPB>(a, groups, st);
+    case 1: return launch_em_mfma<1, SPLIT, PPB, G>(a, st);
+    case 2: return launch_em_mfma<2, SPLIT, PPB, G>(a, st);
+    case 3: return launch_em_mfma<3, SPLIT, PPB, G>(a, st);
+    case 4: return launch_em_mfma<4, SPLIT, PPB, G>(a, st);
+    case 5: return launch_em_mfma<5, SPLIT, PPB, G>(a, st);
+    case 6: return launch_em_mfma<6, SPLIT, PPB, G>(a, st);
+    case 7: if (G == 1) return launch_em_mfma<7, SPLIT, PPB, 1>(a, st); break;
+    default: if (G == 1) return launch_em_mfma<8, SPLIT, PPB, 1>(a, st); break;
+    }
+    return fail(PM_EINVAL, "tile shape with %d model groups per wave needs l <= %d", G, 4 * kMaxMT2);
+}
+
+template <bool SPLIT>
+static int dispatch_shape(const EmMfmaArgs &a, hipStream_t st, int shape)
+{
+    switch (shape) {
+    case 11: return dispatch_mt<SPLIT, 1, 1>(a, st);
+    case 12: return dispatch_mt<SPLIT, 2, 1>(a, st);
+    case 21: return dispatch_mt<SPLIT, 1, 2>(a, st);
+    default: return dispatch_mt<SPLIT, 2, 2>(a, st);
     }
 }
 
-static int dispatch_em_mfma(const EmMfmaArgs &a, int64_t groups, hipStream_t st, int ppb = 0)
+// shape 0: the one recorded for this length class and precision
+static int dispatch_em_mfma(const EmMfmaArgs &a, hipStream_t st, int shape = 0)
 {
-    if (!ppb) ppb = tuned_ppb(a.l, a.split != 0);
-    if (a.split) return ppb == 1 ? dispatch_mt<true, 1>(a, groups, st) : dispatch_mt<true, 2>(a, groups, st);
-    return ppb == 1 ? dispatch_mt<false, 1>(a, groups, st) : dispatch_mt<false, 2>(a, groups, st);
+    if (!shape) shape = tuned_shape(a.l, a.split != 0);
+    if (!shape_ok(shape, a.l)) shape = 10 + shape % 10;
+    return a.split ? dispatch_shape<true>(a, st, shape) : dispatch_shape<false>(a, st, shape);
 }
 
 int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
@@ -555,14 +651,14 @@ int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const doub
     a.l = l;
     a.iters = iters;
     a.beta = beta;
-    return dispatch_em_mfma(a, (B + 16 * kWaves - 1) / (16 * kWaves), st);
+    return dispatch_em_mfma(a, st);
 }
 
 // One workgroup: each instance's bucket range (buckets ascend by item), its
 // workgroup count, the largest-first order of the instances and the scan of
 // the counts in that order.
 __global__ void __launch_bounds__(1024) k_em_plan(const pm_inst *inst, int P, const pm_bucket *buckets,
-                                                 const int64_t *n_dev, int64_t Bcap, int64_t *plan)
+                                                 const int64_t *n_dev, int64_t Bcap, int mw, int64_t *plan)
 {
     const PlanView pv = plan_view(plan, P);
     int64_t *wg_start = const_cast<int64_t *>(pv.wg_start), *b0 = const_cast<int64_t *>(pv.b0);
@@ -599,7 +695,7 @@ __global__ void __launch_bounds__(1024) k_em_plan(const pm_inst *inst, int P, co
         for (int r = 0; r < P; ++r) {
             wg_start[r] = run;
             const int p = (int)order[r];
-            run += (b1[p] - b0[p] + 16 * kWaves - 1) / (16 * kWaves);
+            run += (b1[p] - b0[p] + mw - 1) / mw;
         }
         wg_start[P] = run;
     }
@@ -611,7 +707,10 @@ int em_refine_mfma_batch(const pm_batch *Bt, int64_t nw_max, int t_max, const pm
                          void *ws, bool split, hipStream_t st)
 {
     int64_t *plan = static_cast<int64_t *>(ws);
-    hipLaunchKernelGGL(k_em_plan, dim3(1), dim3(1024), 0, st, Bt->inst, Bt->P, buckets, n_dev, B, plan);
+    int shape = tuned_shape(Bt->l, split);
+    if (!shape_ok(shape, Bt->l)) shape = 10 + shape % 10;
+    hipLaunchKernelGGL(k_em_plan, dim3(1), dim3(1024), 0, st, Bt->inst, Bt->P, buckets, n_dev, B,
+                       16 * kWaves * (shape / 10), plan);
     PM_LAUNCHED();
     EmMfmaArgs a{};
     a.split = split;
@@ -632,8 +731,7 @@ int em_refine_mfma_batch(const pm_batch *Bt, int64_t nw_max, int t_max, const pm
     a.iters = iters;
     a.beta = beta;
     // every instance wastes at most one partly filled group
-    const int64_t groups = (B + 16 * kWaves - 1) / (16 * kWaves) + Bt->P;
-    return dispatch_em_mfma(a, groups, st);
+    return dispatch_em_mfma(a, st, shape);
 }
 
 int em_autotune_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B, int32_t iters,
@@ -655,34 +753,43 @@ int em_autotune_mfma(const pm_seqs *S, int32_t l, const double *theta0, const do
     a.l = l;
     a.iters = iters;
     a.beta = beta;
-    const int64_t groups = (B + 16 * kWaves - 1) / (16 * kWaves);
     hipEvent_t e0, e1;
     PM_TRY(hipEventCreate(&e0));
     PM_TRY(hipEventCreate(&e1));
     float best_ms = 0.f;
     int best = 0, rc = PM_OK;
-    for (int ppb = 1; ppb <= 2 && rc == PM_OK; ++ppb) {
+    for (const int shape : {11, 12, 21, 22}) {
+        if (!shape_ok(shape, l)) continue;
         float ms = 0.f;
-        rc = dispatch_em_mfma(a, groups, st, ppb);  // warm-up
+        rc = dispatch_em_mfma(a, st, shape);  // warm-up
         if (rc == PM_OK && hipEventRecord(e0, st) != hipSuccess) rc = fail(PM_EDEVICE, "hipEventRecord failed");
-        if (rc == PM_OK) rc = dispatch_em_mfma(a, groups, st, ppb);
+        if (rc == PM_OK) rc = dispatch_em_mfma(a, st, shape);
         if (rc == PM_OK && hipEventRecord(e1, st) != hipSuccess) rc = fail(PM_EDEVICE, "hipEventRecord failed");
         if (rc == PM_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(PM_EDEVICE, "hipEventSynchronize failed");
         if (rc == PM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(PM_EDEVICE, "hipEventElapsedTime failed");
-        if (rc == PM_OK && (best == 0 || ms < best_ms)) {
-            best = ppb;
+        if (rc != PM_OK) break;
+        if (best == 0 || ms < best_ms) {
+            best = shape;
             best_ms = ms;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != PM_OK) return rc;
-    g_ppb[(l + 3) / 4 - 1][split ? 1 : 0] = best;
+    g_shape[(l + 3) / 4 - 1][split ? 1 : 0] = best;
     if (choice) *choice = best;
     return PM_OK;
 }
 
-int em_tuned_shape(int32_t l, bool split) { return tuned_ppb(l, split); }
+int em_tuned_shape(int32_t l, bool split) { return tuned_shape(l, split); }
+
+int em_record_shape(int32_t l, bool split, int32_t shape)
+{
+    if (!shape_ok(shape, l))
+        return fail(PM_EINVAL, "tile shape %d is not one of 11, 12, 21, 22 (G = 2 needs l <= %d)", shape, 4 * kMaxMT2);
+    g_shape[(l + 3) / 4 - 1][split ? 1 : 0] = shape;
+    return PM_OK;
+}
 
 size_t em_batch_workspace(int32_t P) { return P < 1 ? 0 : (size_t)(4 * (int64_t)P + 1) * sizeof(int64_t) + 256; }
 

@@ -66,6 +66,7 @@ size_t em_batch_workspace(int32_t P);
 int em_autotune_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B, int32_t iters,
                      double beta, bool split, double *theta_out, double *J_out, int32_t *choice, hipStream_t st);
 int em_tuned_shape(int32_t l, bool split);
+int em_record_shape(int32_t l, bool split, int32_t shape);
 int em_refine_prot(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
                    const int64_t *n_dev, int32_t iters, double beta, double *theta_out, double *J_out,
                    double *llr_out, int32_t *sites_out, hipStream_t st);

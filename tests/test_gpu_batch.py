@@ -177,6 +177,36 @@ def test_batch_em_and_best_match_oracle(case, prec):
         assert multi >= 1  # some instance spans several matrix-core workgroups
 
 
+def test_batch_em_every_tile_shape_bit_identical():
+    """The batch plan cuts every instance into workgroups of the tile shape's
+    size (64 or 128 models); each shape gives the same bits, with instances
+    that span several workgroups and ones that fill part of one."""
+    name, A, P, l, k, d, s = next(c for c in BATCH_CASES if c[1] == 4 and c[0].startswith("dna l=11"))
+    insts = _instances(name, P, l, k, d)
+    bg = np.full(4, 0.25)
+    say("batch em tile shapes", name)
+    B = _batch(insts, A, l, k)
+    out = {}
+    try:
+        for shape in (11, 12, 21, 22):
+            pm.em_set_tuning(l, pm.PM_F16X2, shape)
+            Pp, nb_, nm_ = _pipeline(B, s, 3, 1.0, pm.PM_F16X2, bg)
+            Pp.run()
+            torch.cuda.synchronize()
+            b = Pp.b
+            out[shape] = (b.J.cpu().numpy()[:nb_], b.theta.cpu().numpy()[:nb_], b.sites.cpu().numpy()[:nb_],
+                          [r["best"] for r in Pp.results()])
+    finally:
+        pm.em_set_tuning(l, pm.PM_F16X2, 12)
+    trial = u32(b.buckets)[:nb_, 0]
+    per_inst = [int(((trial >= f) & (trial < f + m)).sum()) for f, m in zip(B.first_item, B.m)]
+    assert max(per_inst) > 64 and min(per_inst) < 64, per_inst
+    for shape in (12, 21, 22):
+        for x, y in zip(out[11][:3], out[shape][:3]):
+            assert np.array_equal(x, y), shape
+        assert out[11][3] == out[shape][3], shape
+
+
 def test_batch_graph_replays_match_eager():
     name, A, P, l, k, d, s = BATCH_CASES[0]
     insts = _instances(name, P, l, k, d)

@@ -557,20 +557,30 @@ def test_c5_full_size_sampled_against_oracle():
 
 
 def test_em_autotune_records_a_shape_and_keeps_results():
-    """The tile-shape autotuner times the candidates on the caller's models,
-    records the fastest, and the recorded shape gives bit-identical results
-    (the shapes change only how many window pairs share a barrier)."""
+    """The tile-shape autotuner times the candidates on the caller's models and
+    records the fastest; every shape gives bit-identical results (the shapes
+    change how many models share a wave's one-hot operands and how many window
+    pairs share a barrier, never the order of any model's arithmetic)."""
     inst, ref, bg, th0 = _em_case(21, 4, 12, 300, 18, 6, 200)
     say("em autotune")
     S = pm.Seqs(4, inst.seqs)
     for prec in (pm.PM_F16X2, pm.PM_F16):
-        before = _em_gpu(S, 18, th0, bg, 3, 1.0, prec)
+        pm.em_set_tuning(18, prec, 11)
+        base = _em_gpu(S, 18, th0, bg, 3, 1.0, prec)
+        for shape in (12, 21, 22):
+            pm.em_set_tuning(18, prec, shape)
+            assert pm.em_tuning(18, prec) == shape
+            got = _em_gpu(S, 18, th0, bg, 3, 1.0, prec)
+            assert all(np.array_equal(x, y) for x, y in zip(base[:4], got[:4])), shape
         d_th0 = torch.from_numpy(th0).cuda()
         th = torch.zeros_like(d_th0)
         J = torch.zeros((th0.shape[0], 4), dtype=torch.float64, device="cuda")
         choice = pm.em_autotune(S, 18, d_th0, torch.from_numpy(bg).cuda(), th0.shape[0], 3, 1.0, prec, th, J)
-        assert choice in (1, 2) and pm.em_tuning(18, prec) == choice
+        assert choice in (11, 12, 21, 22) and pm.em_tuning(18, prec) == choice
         after = _em_gpu(S, 18, th0, bg, 3, 1.0, prec)
-        assert np.array_equal(before[1], after[1]) and np.array_equal(before[0], after[0])
+        assert np.array_equal(base[1], after[1]) and np.array_equal(base[0], after[0])
+    # G = 2 is limited to l <= 24; the default shape stays valid everywhere
+    with pytest.raises(pm.PmError):
+        pm.em_set_tuning(28, pm.PM_F16X2, 21)
     with pytest.raises(pm.PmError):
         pm.em_tuning(18, pm.PM_FP64)
