@@ -28,18 +28,25 @@ FP16_MFMA_PEAK = 2500.0      # TFLOP/s, MI355X dense FP16 matrix cores
 # profiles/hbm_traffic_dna_18-6_m5000.md (copy-calibrated), valid only while
 # the kernel source is the one they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "hash.hip": ("9ec1b4adfe82aa62", 1.749e9),
-    "em_mfma.hip": ("5d988aa6702a5027", 0.352e9 + 0.611e9),
+    "hash.hip": ("9ec1b4adfe82aa62", {"k_hash<4,8,true>": 1.750e9}),
+    "em_mfma.hip": ("5939bc0aa31878a2", {
+        "k_em_mfma<5,true,true,1,1>": 0.328e9 + 0.590e9,
+        "k_em_mfma<5,true,true,2,1>": 0.322e9 + 0.626e9,
+        "k_em_mfma<5,true,true,1,2>": 0.454e9 + 0.622e9,
+        "k_em_mfma<5,true,true,2,2>": 0.426e9 + 0.632e9,
+    }),
 }
 
 
-def traffic(src):
+def traffic(src, kernel):
+    """HBM bytes per launch of `kernel` measured with the counters, or None when
+    the kernel's source has changed since they were taken."""
     import hashlib
-    sha, nbytes = MEASURED_TRAFFIC[src]
+    sha, per_kernel = MEASURED_TRAFFIC[src]
     path = os.path.join(ROOT, "paper_1605_06904_amd", "csrc", src)
     with open(path, "rb") as f:
         cur = hashlib.sha256(f.read()).hexdigest()[:16]
-    return nbytes if cur == sha else None
+    return per_kernel.get(kernel) if cur == sha else None
 
 
 def parse():
@@ -166,11 +173,12 @@ def main():
     dominant = max(stage, key=stage.get)
     if dominant == "hash":
         roof = {"kernel": "k_hash<4,8,true>", "bound": "hbm", "achieved": round(hash_gbs, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4), "traffic": traffic("hash.hip")}
+                "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4), "traffic": traffic("hash.hip", "k_hash<4,8,true>")}
     else:
         roof = {"kernel": f"k_em_mfma<5,true,true,{shape_ppb},{shape_g}>", "bound": "mfma", "achieved": round(em_tfs, 3),
                 "peak": FP16_MFMA_PEAK, "unit": "TFLOP/s", "frac": round(em_tfs / FP16_MFMA_PEAK, 5),
-                "traffic": traffic("em_mfma.hip"), "flops_per_launch": em_flops}
+                "traffic": traffic("em_mfma.hip", f"k_em_mfma<5,true,true,{shape_ppb},{shape_g}>"),
+                "flops_per_launch": em_flops}
     out = {
         "metric": "projected l-mers/s (whole PROJECTION+EM pass, (18,6) DNA workload)",
         "value": round(value, 1),
@@ -194,7 +202,7 @@ def main():
         "roofline": roof,
         "roofline_hash": {"kernel": "k_hash<4,8,true>", "bound": "hbm", "achieved": round(hash_gbs, 2),
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4),
-                          "traffic": traffic("hash.hip"), "bytes_per_launch": hash_bytes},
+                          "traffic": traffic("hash.hip", "k_hash<4,8,true>"), "bytes_per_launch": hash_bytes},
         "hash_lmers_per_s": round(lmers / (stage["hash"] / 1e3), 1),
         "em_column_updates_per_s": round(em_updates / (stage["em"] / 1e3), 1),
         "consensus": res.get("consensus"),
