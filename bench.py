@@ -115,7 +115,7 @@ def main():
     tune_th, tune_J = torch.zeros_like(b.theta), torch.zeros_like(b.J)
     # on all the pass's buckets: the shapes differ in workgroup size, so how
     # well the bucket count fills the device is part of what is timed
-    tile_shape = pm.em_autotune(P.S, l, b.theta0, P.bg, nbk, iters, beta, PREC, tune_th, tune_J)
+    tile_shape = pm.em_autotune(P.S, l, b.theta0, P.bg, nbk, iters, beta, PREC, tune_th, tune_J, ws=P.em_ws)
     shape_g, shape_ppb = tile_shape // 10, tile_shape % 10
     del tune_th, tune_J
     P.run()
@@ -142,7 +142,7 @@ def main():
         pm.theta_init(A, l, b.profile, b.cap_b, b.n_out, P.bg, beta, b.theta0)
         e[3].record()
         pm.em_refine(Sx, l, b.theta0, P.bg, b.cap_b, b.n_out, iters, beta, P.precision, b.theta,
-                     b.J, b.llr, b.sites)
+                     b.J, b.llr, b.sites, ws=P.em_ws)
         e[4].record()
         pm.em_best(b.J, b.cap_b, b.n_out, iters, b.theta, A, l, b.best, b.consensus)
         e[5].record()
@@ -239,13 +239,14 @@ def precision_leg(torch, pm, P, l, iters, beta, nbk, ms_em, sample=512):
     A = S.alphabet
     th16 = torch.zeros_like(b.theta)
     J16 = torch.zeros_like(b.J)
-    pm.em_refine(S, l, b.theta0, P.bg, b.cap_b, b.n_out, iters, beta, pm.PM_F16, th16, J16, None, None)
+    pm.em_refine(S, l, b.theta0, P.bg, b.cap_b, b.n_out, iters, beta, pm.PM_F16, th16, J16, None, None, ws=P.em_ws)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 3
     e0.record()
     for _ in range(reps):
-        pm.em_refine(S, l, b.theta0, P.bg, b.cap_b, b.n_out, iters, beta, pm.PM_F16, th16, J16, None, None)
+        pm.em_refine(S, l, b.theta0, P.bg, b.cap_b, b.n_out, iters, beta, pm.PM_F16, th16, J16, None, None,
+                     ws=P.em_ws)
     e1.record()
     torch.cuda.synchronize()
     ms16 = e0.elapsed_time(e1) / reps

@@ -178,10 +178,21 @@ int theta_init(int32_t alphabet, int32_t l, const uint32_t *profile, int64_t B,
  *   llr_out    device [B][iters+1] or NULL
  *   sites_out  device [B][t] int32 or NULL: argmax_a s_ia under theta^iters,
  *              first on ties
- *   precision  PM_FP64, PM_FP32, PM_F16X2 or PM_F16 (the last two DNA only) */
+ *   precision  PM_FP64, PM_FP32, PM_F16X2 or PM_F16
+ *   ws, ws_bytes  device workspace of at least pm_em_workspace(S, l, precision)
+ *              bytes, 16-byte aligned, or NULL.  The DNA matrix-core forms keep
+ *              the one-hot tables of every 32-window pair there (built once per
+ *              call, read by every model); with NULL they rebuild them inside
+ *              the EM kernel (same results, slower).  Other forms ignore it.
+ *              A non-NULL workspace below the size is PM_EINVAL. */
 int em_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
               const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
-              double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *stream);
+              double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *ws,
+              size_t ws_bytes, void *stream);
+/* Workspace bytes of em_refine: the one-hot tables of the DNA matrix-core
+ * forms (t + ceil(x/32) window pairs of 1 KB + (4 ceil(l/4) + 12) x 64 B each);
+ * 0 for the other forms or invalid arguments. */
+size_t pm_em_workspace(const pm_seqs *S, int32_t l, int32_t precision);
 
 /* Tile-shape autotuner of the matrix-core EM (PM_F16X2, PM_F16): runs
  * em_refine on the caller's B models once per candidate shape, times each
@@ -193,12 +204,13 @@ int em_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *b
  * barrier (1 or 2).  Pass B of the size the later calls will have: the
  * shapes differ in workgroup size, so their ranking depends on how well B
  * fills the device.
- * theta_out, J_out: device scratch of em_refine's shapes (overwritten).
- * choice_out: host int32[1] or NULL.  em_tuning returns the shape in use
- * (untuned: 12), or a negative status. */
+ * theta_out, J_out: device scratch of em_refine's shapes (overwritten);
+ * ws, ws_bytes: as for em_refine (pass the workspace the timed calls will
+ * have).  DNA only.  choice_out: host int32[1] or NULL.  em_tuning returns
+ * the shape in use (untuned: 12), or a negative status. */
 int em_autotune(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B, int32_t iters,
-                double beta, int32_t precision, double *theta_out, double *J_out, int32_t *choice_out,
-                void *stream);
+                double beta, int32_t precision, double *theta_out, double *J_out, void *ws, size_t ws_bytes,
+                int32_t *choice_out, void *stream);
 int em_tuning(int32_t l, int32_t precision);
 /* Records `shape` (coded as above) for l's length class and `precision`, in
  * place of a tuned or default one: for callers that tuned in an earlier
@@ -264,14 +276,19 @@ int bucket_profile_batch(const pm_batch *B, const pm_bucket *buckets, const uint
                          int64_t cap_members, int64_t Bcap, const int64_t *n_dev, uint32_t *profile,
                          void *stream);
 
-/* Workspace bytes em_refine_batch needs for P instances. */
-size_t pm_em_batch_workspace(int32_t P);
+/* Workspace bytes em_refine_batch needs for batch B in `precision`: for the
+ * DNA matrix-core forms the workgroup plan, every instance's first table slot
+ * and the one-hot tables of all its window pairs (as for em_refine); 0 for the
+ * vector forms (no workspace) or an invalid batch. */
+size_t pm_em_batch_workspace(const pm_batch *B, int32_t precision);
 
 /* a7 - a10 for every bucket of a batch, each against its own instance
  * (buckets as written by bucket_select_batch, ascending by item).  sites_out
  * is [Bcap][t_max] with t_max the largest t of the batch (entries past the
  * instance's t untouched).  The matrix-core form groups the buckets of one
- * instance into workgroups and issues the instances largest first. */
+ * instance into workgroups and issues the instances largest first; it needs
+ * ws of pm_em_batch_workspace(B, precision) bytes, 256-byte aligned
+ * (PM_EINVAL otherwise). */
 int em_refine_batch(const pm_batch *B, const pm_bucket *buckets, const double *theta0, const double *bg,
                     int64_t Bcap, const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
                     double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *ws,

@@ -29,7 +29,7 @@ EXPORTS = [
     "pm_auto_params", "projection_hash", "pm_select_workspace", "bucket_select",
     "bucket_profile", "theta_init", "em_refine", "em_best", "projection_run",
     "pm_batch_check", "projection_hash_batch", "bucket_select_batch", "bucket_profile_batch",
-    "pm_em_batch_workspace", "em_refine_batch", "em_best_batch",
+    "pm_em_batch_workspace", "pm_em_workspace", "em_refine_batch", "em_best_batch",
     "triage_features", "pm_triage_packed_bytes", "triage_pack", "triage_forward", "pm_triage_workspace",
     "triage_train_step", "pm_triage_select_workspace", "triage_select", "triage_fallback_select",
     "triage_merge_best", "em_autotune", "em_tuning", "em_set_tuning",
@@ -114,7 +114,8 @@ def lib():
         "bucket_profile": (C.c_int, [C.POINTER(pm_seqs), i32, P, P, i64, i64, P, P, P]),
         "theta_init": (C.c_int, [i32, i32, P, i64, P, P, dbl, P, P]),
         "em_refine": (C.c_int, [C.POINTER(pm_seqs), i32, P, P, i64, P, i32, dbl, i32, P, P, P,
-                                P, P]),
+                                P, P, sz, P]),
+        "pm_em_workspace": (sz, [C.POINTER(pm_seqs), i32, i32]),
         "em_best": (C.c_int, [P, i64, P, i32, P, i32, i32, P, P, P]),
         "projection_run": (C.c_int, [C.POINTER(pm_problem), C.POINTER(pm_options),
                                      C.POINTER(pm_result)]),
@@ -123,7 +124,7 @@ def lib():
         "bucket_select_batch": (C.c_int, [C.POINTER(pm_batch), P, P, u32, P, i64, P, i64, P, P, sz,
                                           P, P]),
         "bucket_profile_batch": (C.c_int, [C.POINTER(pm_batch), P, P, i64, i64, P, P, P]),
-        "pm_em_batch_workspace": (sz, [i32]),
+        "pm_em_batch_workspace": (sz, [C.POINTER(pm_batch), i32]),
         "em_refine_batch": (C.c_int, [C.POINTER(pm_batch), P, P, P, i64, P, i32, dbl, i32, P, P, P,
                                       P, P, sz, P]),
         "em_best_batch": (C.c_int, [C.POINTER(pm_batch), P, P, i64, P, i32, P, P, P, P]),
@@ -138,7 +139,7 @@ def lib():
         "triage_fallback_select": (C.c_int, [C.c_void_p, P, i64, P, P, P, P, P, i32, dbl, P, i32, i32, P, P,
                                              P, P, P, P, P, P, sz, P]),
         "triage_merge_best": (C.c_int, [i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P]),
-        "em_autotune": (C.c_int, [C.POINTER(pm_seqs), i32, P, P, i64, i32, dbl, i32, P, P, P, P]),
+        "em_autotune": (C.c_int, [C.POINTER(pm_seqs), i32, P, P, i64, i32, dbl, i32, P, P, P, sz, P, P]),
         "em_tuning": (C.c_int, [i32, i32]),
         "em_set_tuning": (C.c_int, [i32, i32, i32]),
     }
@@ -227,17 +228,38 @@ def theta_init(alphabet, l, profile, B, n_dev, bg, beta, theta0, stream=None):
                             _ptr(theta0), _stream(stream)))
 
 
+def pm_em_workspace(S, l: int, precision: int) -> int:
+    return int(lib().pm_em_workspace(C.byref(S.c), l, precision))
+
+
+def _em_ws(S, l, precision, ws, like):
+    """The workspace argument of em_refine / em_autotune: the caller's tensor,
+    False for none (tables built inside the EM kernel), or None for a fresh
+    one of pm_em_workspace bytes on `like`'s device."""
+    if ws is False:
+        return None, 0
+    if ws is None:
+        nbytes = pm_em_workspace(S, l, precision)
+        if nbytes == 0:
+            return None, 0
+        import torch
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=like.device)
+    return ws, ws.numel() * ws.element_size()
+
+
 def em_refine(S, l, theta0, bg, B, n_dev, iters, beta, precision, theta_out, J_out, llr_out=None,
-              sites_out=None, stream=None):
+              sites_out=None, stream=None, ws=None):
+    ws, ws_bytes = _em_ws(S, l, precision, ws, theta0)
     _check(lib().em_refine(C.byref(S.c), l, _ptr(theta0), _ptr(bg), B, _ptr(n_dev), iters, beta,
                            precision, _ptr(theta_out), _ptr(J_out), _ptr(llr_out), _ptr(sites_out),
-                           _stream(stream)))
+                           _ptr(ws), ws_bytes, _stream(stream)))
 
 
-def em_autotune(S, l, theta0, bg, B, iters, beta, precision, theta_out, J_out, stream=None) -> int:
+def em_autotune(S, l, theta0, bg, B, iters, beta, precision, theta_out, J_out, stream=None, ws=None) -> int:
+    ws, ws_bytes = _em_ws(S, l, precision, ws, theta0)
     choice = C.c_int32(0)
     _check(lib().em_autotune(C.byref(S.c), l, _ptr(theta0), _ptr(bg), B, iters, beta, precision, _ptr(theta_out),
-                             _ptr(J_out), C.byref(choice), _stream(stream)))
+                             _ptr(J_out), _ptr(ws), ws_bytes, C.byref(choice), _stream(stream)))
     return choice.value
 
 
@@ -278,8 +300,8 @@ def bucket_profile_batch(B, buckets, members, cap_members, Bcap, n_dev, profile,
                                       _ptr(n_dev), _ptr(profile), _stream(stream)))
 
 
-def pm_em_batch_workspace(P: int) -> int:
-    return int(lib().pm_em_batch_workspace(P))
+def pm_em_batch_workspace(B, precision: int) -> int:
+    return int(lib().pm_em_batch_workspace(C.byref(B.c), precision))
 
 
 def em_refine_batch(B, buckets, theta0, bg, Bcap, n_dev, iters, beta, precision, theta_out, J_out,
@@ -477,6 +499,8 @@ class Pipeline:
             best=z(1, dt=torch.int64), consensus=torch.zeros(l + 1, dtype=torch.uint8, device=dev),
             cap_b=cap_b, cap_m=cap_m)
         self.ws_bytes = ws_bytes
+        # one-hot tables of the matrix-core EM (empty for the other forms)
+        self.em_ws = torch.empty(max(pm_em_workspace(S, l, precision), 1), dtype=torch.uint8, device=dev)
 
     def hash(self, stream=None):
         b = self.b
@@ -492,7 +516,7 @@ class Pipeline:
         bucket_profile(self.S, self.l, b.buckets, b.members, b.cap_m, b.cap_b, b.n_out, b.profile, stream)
         theta_init(A, self.l, b.profile, b.cap_b, b.n_out, self.bg, self.beta, b.theta0, stream)
         em_refine(self.S, self.l, b.theta0, self.bg, b.cap_b, b.n_out, self.iters, self.beta,
-                  self.precision, b.theta, b.J, b.llr, b.sites, stream)
+                  self.precision, b.theta, b.J, b.llr, b.sites, stream, ws=self.em_ws)
         em_best(b.J, b.cap_b, b.n_out, self.iters, b.theta, A, self.l, b.best, b.consensus, stream)
 
     def run(self, stream=None):
@@ -605,7 +629,7 @@ class BatchPipeline:
         dev = device
         self.bg = torch.as_tensor(np.asarray(bg, dtype=np.float64), device=dev)
         self.ws_bytes = pm_select_workspace(B.items, cap_b)
-        self.em_ws_bytes = pm_em_batch_workspace(B.P)
+        self.em_ws_bytes = pm_em_batch_workspace(B, precision)
         cb = max(cap_b, 1)
         z = lambda *shape, dt=torch.int32: torch.zeros(*shape, dtype=dt, device=dev)
         self.b = PassBuffers(

@@ -308,7 +308,7 @@ extern "C" int projection_run(const pm_problem *P, const pm_options *O, pm_resul
         if (R->consensus) R->consensus[0] = 0;
         return PM_OK;
     }
-    DevBuf d_bk, d_mem, d_prof, d_bg, d_th0, d_th, d_J, d_llr, d_sites, d_best, d_cons;
+    DevBuf d_bk, d_mem, d_prof, d_bg, d_th0, d_th, d_J, d_llr, d_sites, d_best, d_cons, d_emws;
     PM_CALL(d_bk.alloc(sizeof(pm_bucket) * nbk));
     PM_CALL(d_mem.alloc(sizeof(uint32_t) * nmem));
     PM_CALL(d_ws.alloc(pm_select_workspace(m, nbk)));
@@ -349,13 +349,15 @@ extern "C" int projection_run(const pm_problem *P, const pm_options *O, pm_resul
     PM_CALL(d_sites.alloc(sizeof(int32_t) * nbk * P->t));
     PM_CALL(d_best.alloc(sizeof(int64_t)));
     PM_CALL(d_cons.alloc(l + 1));
+    const size_t em_ws = pm_em_workspace(&S, l, O->precision);
+    if (em_ws) PM_CALL(d_emws.alloc(em_ws));
     PM_TRY(hipMemcpyAsync(d_bg.p, bg.data(), sizeof(double) * A, hipMemcpyHostToDevice, st));
     PM_CALL(bucket_profile(&S, l, d_bk.as<pm_bucket>(), d_mem.as<uint32_t>(), nmem, nbk, nullptr,
                            d_prof.as<uint32_t>(), st));
     PM_CALL(theta_init(A, l, d_prof.as<uint32_t>(), nbk, nullptr, d_bg.as<double>(), O->beta, d_th0.as<double>(), st));
     PM_CALL(em_refine(&S, l, d_th0.as<double>(), d_bg.as<double>(), nbk, nullptr, O->em_iters, O->beta,
                       O->precision, d_th.as<double>(), d_J.as<double>(), d_llr.as<double>(),
-                      d_sites.as<int32_t>(), st));
+                      d_sites.as<int32_t>(), d_emws.p, em_ws, st));
     PM_CALL(em_best(d_J.as<double>(), nbk, nullptr, O->em_iters, d_th.as<double>(), A, l, d_best.as<int64_t>(),
                     d_cons.as<char>(), st));
     int64_t best = -1;

@@ -323,10 +323,18 @@ static int vec_launch(EmArgs &a, int A, int32_t precision, int64_t nw_max, int t
     return precision == PM_FP64 ? launch_em<double, 20>(a, lds, st) : launch_em<float, 20>(a, lds, st);
 }
 
+extern "C" size_t pm_em_workspace(const pm_seqs *S, int32_t l, int32_t precision)
+{
+    clear_error();
+    if (check_seqs(S, l) != PM_OK) return 0;
+    if (S->alphabet != 4 || (precision != PM_F16X2 && precision != PM_F16)) return 0;
+    return em_tables_workspace(S, l);
+}
+
 extern "C" int em_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
                          const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
                          double *theta_out, double *J_out, double *llr_out, int32_t *sites_out,
-                         void *stream)
+                         void *ws, size_t ws_bytes, void *stream)
 {
     clear_error();
     int rc = check_seqs(S, l);
@@ -337,8 +345,8 @@ extern "C" int em_refine(const pm_seqs *S, int32_t l, const double *theta0, cons
     if (precision == PM_F16 && S->alphabet == 20)
         return em_refine_prot(S, l, theta0, bg, B, n_dev, iters, beta, theta_out, J_out, llr_out, sites_out, st);
     if (precision == PM_F16X2 || precision == PM_F16)
-        return em_refine_mfma(S, l, theta0, bg, B, n_dev, iters, beta, theta_out, J_out, llr_out, sites_out,
-                              precision == PM_F16X2, st);
+        return em_refine_mfma(S, l, theta0, bg, B, n_dev, iters, beta, theta_out, J_out, llr_out, sites_out, ws,
+                              ws_bytes, precision == PM_F16X2, st);
     EmArgs a{};
     a.one = inst_of(S, l);
     a.theta0 = theta0;
@@ -356,11 +364,18 @@ extern "C" int em_refine(const pm_seqs *S, int32_t l, const double *theta0, cons
     return vec_launch(a, S->alphabet, precision, pm_packed_words(S->alphabet, S->n_total), S->t, st);
 }
 
-extern "C" size_t pm_em_batch_workspace(int32_t P) { return em_batch_workspace(P); }
+extern "C" size_t pm_em_batch_workspace(const pm_batch *B, int32_t precision)
+{
+    clear_error();
+    BatchInfo info;
+    if (check_batch(B, &info) != PM_OK) return 0;
+    const bool mfma = B->alphabet == 4 && (precision == PM_F16X2 || precision == PM_F16);
+    return mfma ? em_batch_workspace(B, true) : 0;
+}
 
 extern "C" int em_autotune(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
                            int32_t iters, double beta, int32_t precision, double *theta_out, double *J_out,
-                           int32_t *choice_out, void *stream)
+                           void *ws, size_t ws_bytes, int32_t *choice_out, void *stream)
 {
     clear_error();
     int rc = check_seqs(S, l);
@@ -368,8 +383,9 @@ extern "C" int em_autotune(const pm_seqs *S, int32_t l, const double *theta0, co
     if (precision != PM_F16X2 && precision != PM_F16) return fail(PM_EINVAL, "only the matrix-core forms are tuned");
     if ((rc = check_em_args(S->alphabet, B, iters, beta, precision, theta0, bg, theta_out, J_out))) return rc;
     if (B < 1) return fail(PM_EINVAL, "need B >= 1 models to time");
-    return em_autotune_mfma(S, l, theta0, bg, B, iters, beta, precision == PM_F16X2, theta_out, J_out, choice_out,
-                            as_stream(stream));
+    if (S->alphabet != 4) return fail(PM_EINVAL, "the tuned tile shapes are those of the DNA matrix-core form");
+    return em_autotune_mfma(S, l, theta0, bg, B, iters, beta, precision == PM_F16X2, theta_out, J_out, ws, ws_bytes,
+                            choice_out, as_stream(stream));
 }
 
 extern "C" int em_tuning(int32_t l, int32_t precision)
@@ -402,7 +418,9 @@ extern "C" int em_refine_batch(const pm_batch *Bt, const pm_bucket *buckets, con
     if (precision == PM_F16 && Bt->alphabet == 20)
         return fail(PM_EINVAL, "the protein matrix-core form runs on single instances (em_refine)");
     if (precision == PM_F16X2 || precision == PM_F16) {
-        if (!ws || ws_bytes < em_batch_workspace(Bt->P)) return fail(PM_EINVAL, "workspace too small");
+        const size_t need = em_batch_workspace(Bt, true);
+        if (!ws || ws_bytes < need) return fail(PM_EINVAL, "workspace of %zu bytes, need %zu", ws ? ws_bytes : 0, need);
+        if (((uintptr_t)ws & 255) != 0) return fail(PM_EINVAL, "workspace must be 256-byte aligned");
         return em_refine_mfma_batch(Bt, info.nw_max, info.t_max, buckets, theta0, bg, B, n_dev, iters, beta,
                                     theta_out, J_out, llr_out, sites_out, ws, precision == PM_F16X2, st);
     }

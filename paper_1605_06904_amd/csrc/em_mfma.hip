@@ -52,6 +52,7 @@ namespace pm {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef float float4v __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // one 16-byte table quad
 
 struct EmMfmaArgs {
     const uint32_t *packed;
@@ -74,6 +75,10 @@ struct EmMfmaArgs {
     const pm_inst *inst;
     const int64_t *plan;
     int P;
+    // precomputed one-hot tables (k_em_tables), or NULL to build them in the
+    // kernel; tbase: first slot of every instance of a batch (NULL: one instance)
+    const uint8_t *tables;
+    const int64_t *tbase;
 };
 
 // workgroups of a launch that takes mw models per workgroup: whole groups of
@@ -138,6 +143,24 @@ __device__ __forceinline__ void dna32(const uint32_t *w, int64_t P, int64_t nw, 
 // builds read up to 95 symbols past the last window start
 constexpr int kStagePad = 8;
 
+// where a workgroup's one-hot tables come from
+constexpr int kSrcGlobal = 0;  // built in the kernel from the packed instance in global memory
+constexpr int kSrcStaged = 1;  // built in the kernel from the packed instance staged in LDS
+constexpr int kSrcPre = 2;     // copied from tables precomputed once per call (k_em_tables)
+
+// Precomputed tables: pair j (windows 32j .. 32j+31) of sequence i of an
+// instance sits in slot i + floor(W_i / 32) + j, W_i = offsets[i] - i (l - 1)
+// being the sequence's first window in the instance's window numbering.  A
+// sequence of L_i windows ends at slot i + floor((W_i + L_i) / 32) at most, so
+// the slots of different sequences never overlap and an instance needs at
+// most t + ceil(x / 32) of them (a few stay unused).
+__host__ __device__ inline int64_t em_inst_slots(int64_t t, int64_t x) { return t + (x + 31) / 32; }
+
+__device__ __forceinline__ int64_t seq_slot0(const int64_t *offsets, int i, int l)
+{
+    return i + (offsets[i] - (int64_t)i * (l - 1)) / 32;
+}
+
 // two FP16 halves: 1.0 where letter a == c (low half), where b == c (high half)
 __device__ __forceinline__ uint32_t onehot_pair(uint32_t a, uint32_t b, uint32_t c)
 {
@@ -175,6 +198,10 @@ struct alignas(16) PairTables {
     uint32_t oh2[64][4];          // letters 0..3 of symbol e, then of symbol e+1
     uint4 mt8[Tiles<MT>::NE][4];  // [e][c]: symbols e..e+3 and e+16..e+19 == c
 };
+// 16-byte quads of one pair's tables: at most 256, one per thread of a workgroup
+template <int MT>
+constexpr int kTabQuads = (int)(sizeof(PairTables<MT>) / 16);
+static_assert(kTabQuads<8> <= 256, "one quad per thread");
 
 // lut[y]: four FP16 halves, half q = 1.0 where 2-bit field q of y (from the top)
 // is zero.  With y = (4 symbols) ^ (c * 0x55) that is the one-hot of letter c.
@@ -327,15 +354,35 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T
     }
 }
 
-// One sequence: every window pair (tables built by the whole workgroup), then
-// the per-sequence log-sum-exp and counts, or, in the final E-step, the best
-// start of every model.  acc[q]: the count accumulators of group q.
-template <int MT, bool STAGED, bool LAST, bool SPLIT, int PPB, int G>
+// This thread's quads of the tables of the PPB window pairs starting at
+// window a0 of sequence i (kSrcPre): loaded into registers one step ahead of
+// their use, written to LDS at the step that uses them.
+template <int MT, int PPB>
+__device__ __forceinline__ void fetch_tables(const EmMfmaArgs &a, int64_t tb, int i, int a0, u32x4 (&pf)[PPB])
+{
+    // every load is unconditional and in bounds (a pair past the sequence's
+    // end re-reads the step's first pair, threads past the quads re-read the
+    // last one), which keeps pf in registers; only the LDS writes are guarded
+    constexpr int NQ = kTabQuads<MT>;
+    const int L = (int)(a.offsets[i + 1] - a.offsets[i]) - a.l + 1;
+    const int q = (int)threadIdx.x < NQ ? (int)threadIdx.x : NQ - 1;
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(a.tables) + (tb + seq_slot0(a.offsets, i, a.l) + a0 / 32) * NQ + q;
+#pragma unroll
+    for (int u = 0; u < PPB; ++u) pf[u] = src[(a0 + 32 * u < L ? u : 0) * NQ];
+}
+
+// One sequence: every window pair (tables built by the whole workgroup, or
+// copied from the precomputed ones), then the per-sequence log-sum-exp and
+// counts, or, in the final E-step, the best start of every model.  acc[q]:
+// the count accumulators of group q.  kSrcPre: pf holds this thread's quads of
+// the sequence's first step on entry and of the step after the sequence (the
+// next sequence's first, or sequence 0's for the next iteration) on return.
+template <int MT, int SRC, bool LAST, bool SPLIT, int PPB, int G>
 __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, const uint2 *lut, int i, int64_t bw,
-                                      int64_t nvalid, PairTables<MT> *tabs, int &parity,
-                                      float (*acc)[16][Tiles<MT>::CX][4], const half8 (&Whi)[G][Tiles<MT>::LB],
-                                      const half8 (&Wlo)[G][Tiles<MT>::LB], const float (&mlow)[G],
-                                      double (&llr)[G])
+                                      int64_t nvalid, PairTables<MT> *tabs, int &parity, int64_t tb,
+                                      u32x4 (&pf)[PPB], float (*acc)[16][Tiles<MT>::CX][4],
+                                      const half8 (&Whi)[G][Tiles<MT>::LB], const half8 (&Wlo)[G][Tiles<MT>::LB],
+                                      const float (&mlow)[G], double (&llr)[G])
 {
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     const int64_t s0 = a.offsets[i];
@@ -352,10 +399,26 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
     for (int a0 = 0; a0 < L; a0 += 32 * PPB) {
         PairTables<MT> *T = tabs + PPB * parity;
         parity ^= 1;
+        if constexpr (SRC == kSrcPre) {
 #pragma unroll
-        for (int u = 0; u < PPB; ++u)
-            if (a0 + 32 * u < L) build_tables<MT, !STAGED>(W, a.nwords, s0 + a0 + 32 * u, lut, T[u]);
+            for (int u = 0; u < PPB; ++u)
+                if (a0 + 32 * u < L && threadIdx.x < kTabQuads<MT>)
+                    reinterpret_cast<u32x4 *>(&T[u])[threadIdx.x] = pf[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < PPB; ++u)
+                if (a0 + 32 * u < L) build_tables<MT, SRC == kSrcGlobal>(W, a.nwords, s0 + a0 + 32 * u, lut, T[u]);
+        }
         __syncthreads();
+        if constexpr (SRC == kSrcPre) {
+            // the next step's quads load while this step computes
+            int ni = i, na = a0 + 32 * PPB;
+            if (na >= L) {
+                na = 0;
+                ni = i + 1 < a.t ? i + 1 : 0;
+            }
+            fetch_tables<MT, PPB>(a, tb, ni, na, pf);
+        }
 #pragma unroll
         for (int u = 0; u < PPB; ++u) {
             const int b0 = a0 + 32 * u;
@@ -411,7 +474,7 @@ constexpr int em_waves_per_simd()
 }
 
 // G groups of 16 models per wave, kWaves waves per workgroup
-template <int MT, bool STAGED, bool SPLIT, int PPB, int G>
+template <int MT, int SRC, bool SPLIT, int PPB, int G>
 __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())) k_em_mfma(const EmMfmaArgs a0)
 {
     constexpr int LB = Tiles<MT>::LB, CX = Tiles<MT>::CX, MW = 16 * kWaves * G;
@@ -422,7 +485,7 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     EmMfmaArgs a = a0;
-    int64_t b0, nvalid;
+    int64_t b0, nvalid, tb = 0;
     if (a0.inst) {
         // batch: find this workgroup's instance rank, largest r with wg_start[r] <= wg
         const PlanView pv = plan_view(a0.plan, a0.P);
@@ -440,7 +503,8 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
         a.offsets = I.offsets;
         a.t = I.t;
         a.nwords = (I.n_total + 15) / 16 + 4;
-        a.stage_words = STAGED ? (int)a.nwords : 0;
+        a.stage_words = SRC == kSrcStaged ? (int)a.nwords : 0;
+        tb = a0.tbase ? a0.tbase[p] : 0;
         b0 = pv.b0[p] + (wg - pv.wg_start[lo]) * MW;
         nvalid = pv.b1[p] < b0 + MW ? pv.b1[p] : b0 + MW;
     } else {
@@ -449,11 +513,20 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
         b0 = (int64_t)blockIdx.x * MW;
         if (b0 >= nvalid) return;  // uniform over the workgroup
     }
-    if (STAGED)
+    const uint32_t *W = a.packed;
+    const uint2 *lutp = nullptr;
+    u32x4 pf[PPB];
+    if constexpr (SRC == kSrcStaged) {
         for (int k = threadIdx.x; k < a.stage_words + kStagePad; k += 64 * kWaves)
             staged[k] = k < a.stage_words ? a.packed[k] : 0u;
-    const uint32_t *W = STAGED ? staged : a.packed;
-    build_lut(lut);
+        W = staged;
+    }
+    if constexpr (SRC == kSrcPre) {
+        fetch_tables<MT, PPB>(a, tb, 0, 0, pf);  // the first step of the first sweep
+    } else {
+        build_lut(lut);
+        lutp = lut;
+    }
     const int64_t bw = b0 + 16 * G * wv;
     float (*acc)[16][CX][4] = accs[wv];
     const int l = a.l, t = a.t, AL = 4 * l;
@@ -528,10 +601,11 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
         for (int q = 0; q < G; ++q) llr[q] = 0;
         for (int i = 0; i < t; ++i) {
             if (last)
-                sweep<MT, STAGED, true, SPLIT, PPB, G>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow, llr);
+                sweep<MT, SRC, true, SPLIT, PPB, G>(a, W, lutp, i, bw, nvalid, tabs, parity, tb, pf, acc, Whi, Wlo,
+                                                    mlow, llr);
             else
-                sweep<MT, STAGED, false, SPLIT, PPB, G>(a, W, lut, i, bw, nvalid, tabs, parity, acc, Whi, Wlo, mlow,
-                                                        llr);
+                sweep<MT, SRC, false, SPLIT, PPB, G>(a, W, lutp, i, bw, nvalid, tabs, parity, tb, pf, acc, Whi, Wlo,
+                                                     mlow, llr);
         }
         // ---- objective of theta^it, then the M-step (own entries)
 #pragma unroll
@@ -564,16 +638,119 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
     }
 }
 
+// One workgroup per table slot: the one-hot tables of one window pair in the
+// layout the EM kernel copies into LDS.  Batch: the slot's instance from
+// tbase (first slot of every instance, ascending).  Slots past a sequence's
+// last pair are left untouched; nothing reads them.
+struct EmTabArgs {
+    pm_inst one;           // the instance when inst is NULL
+    const pm_inst *inst;   // batch instance table, or NULL
+    const int64_t *tbase;  // batch: [P + 1]
+    int P, l;
+    int64_t nslots;        // slots of the launch
+    int64_t nwords_one;    // packed words of `one` (reads are clamped below)
+    uint8_t *tables;
+};
+
+template <int MT>
+__global__ void __launch_bounds__(256) k_em_tables(const EmTabArgs a)
+{
+    __shared__ __align__(16) uint2 lut[256];
+    const int64_t slot = blockIdx.x;
+    if (slot >= a.nslots) return;
+    pm_inst I = a.one;
+    int64_t rel = slot, nw = a.nwords_one;
+    if (a.inst) {
+        if (slot >= a.tbase[a.P]) return;
+        int lo = 0, hi = a.P;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.tbase[mid] <= slot) lo = mid;
+            else hi = mid;
+        }
+        I = a.inst[lo];
+        rel = slot - a.tbase[lo];
+        nw = (I.n_total + 15) / 16 + 4;
+    }
+    // the sequence: largest i with seq_slot0(i) <= rel (seq_slot0 increases with i)
+    int lo = 0, hi = I.t;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seq_slot0(I.offsets, mid, a.l) <= rel) lo = mid;
+        else hi = mid;
+    }
+    const int64_t j = rel - seq_slot0(I.offsets, lo, a.l);
+    const int64_t s0 = I.offsets[lo];
+    const int L = (int)(I.offsets[lo + 1] - s0) - a.l + 1;
+    if (32 * j >= L) return;  // uniform over the workgroup
+    build_lut(lut);
+    __syncthreads();
+    build_tables<MT, true>(I.packed, nw, s0 + 32 * j, lut, reinterpret_cast<PairTables<MT> *>(a.tables)[slot]);
+}
+
+static size_t pair_table_bytes(int mt) { return 1024 + (size_t)(4 * mt + 12) * 64; }
+static_assert(sizeof(PairTables<1>) == 1024 + 16 * 64 && sizeof(PairTables<8>) == 1024 + 44 * 64, "table size");
+
+static int launch_em_tables(const EmTabArgs &t, hipStream_t st)
+{
+    if (t.nslots < 1) return PM_OK;
+    switch ((t.l + 3) / 4) {
+    case 1: hipLaunchKernelGGL(k_em_tables<1>, dim3((unsigned)t.nslots), dim3(256), 0, st, t); break;
+    case 2: hipLaunchKernelGGL(k_em_tables<2>, dim3((unsigned)t.nslots), dim3(256), 0, st, t); break;
+    case 3: hipLaunchKernelGGL(k_em_tables<3>, dim3((unsigned)t.nslots), dim3(256), 0, st, t); break;
+    case 4: hipLaunchKernelGGL(k_em_tables<4>, dim3((unsigned)t.nslots), dim3(256), 0, st, t); break;
+    case 5: hipLaunchKernelGGL(k_em_tables<5>, dim3((unsigned)t.nslots), dim3(256), 0, st, t); break;
+    case 6: hipLaunchKernelGGL(k_em_tables<6>, dim3((unsigned)t.nslots), dim3(256), 0, st, t); break;
+    case 7: hipLaunchKernelGGL(k_em_tables<7>, dim3((unsigned)t.nslots), dim3(256), 0, st, t); break;
+    default: hipLaunchKernelGGL(k_em_tables<8>, dim3((unsigned)t.nslots), dim3(256), 0, st, t); break;
+    }
+    PM_LAUNCHED();
+    return PM_OK;
+}
+
+static int64_t seqs_slots(const pm_seqs *S, int l) { return em_inst_slots(S->t, S->n_total - (int64_t)S->t * (l - 1)); }
+
+size_t em_tables_workspace(const pm_seqs *S, int32_t l)
+{
+    return (size_t)seqs_slots(S, l) * pair_table_bytes((l + 3) / 4);
+}
+
+// precomputed tables of one instance into ws (checked size), a.tables set
+static int prepare_tables(EmMfmaArgs &a, const pm_seqs *S, int l, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    a.tables = nullptr;
+    if (!ws) return PM_OK;
+    const size_t need = em_tables_workspace(S, l);
+    if (ws_bytes < need) return fail(PM_EINVAL, "workspace of %zu bytes, the one-hot tables need %zu", ws_bytes, need);
+    if (((uintptr_t)ws & 15) != 0) return fail(PM_EINVAL, "workspace must be 16-byte aligned");
+    EmTabArgs t{};
+    t.one.offsets = S->offsets;
+    t.one.packed = S->packed;
+    t.one.n_total = S->n_total;
+    t.one.t = S->t;
+    t.l = l;
+    t.nslots = seqs_slots(S, l);
+    t.nwords_one = pm_packed_words(S->alphabet, S->n_total);
+    t.tables = static_cast<uint8_t *>(ws);
+    const int rc = launch_em_tables(t, st);
+    if (rc != PM_OK) return rc;
+    a.tables = t.tables;
+    return PM_OK;
+}
+
 template <int MT, bool SPLIT, int PPB, int G>
 static int launch_em_mfma(const EmMfmaArgs &a, hipStream_t st)
 {
     const int64_t groups = em_groups(a, 16 * kWaves * G);
-    if (a.stage_words)
-        hipLaunchKernelGGL((k_em_mfma<MT, true, SPLIT, PPB, G>), dim3((unsigned)groups), dim3(64 * kWaves),
+    if (a.tables)
+        hipLaunchKernelGGL((k_em_mfma<MT, kSrcPre, SPLIT, PPB, G>), dim3((unsigned)groups), dim3(64 * kWaves), 0, st,
+                           a);
+    else if (a.stage_words)
+        hipLaunchKernelGGL((k_em_mfma<MT, kSrcStaged, SPLIT, PPB, G>), dim3((unsigned)groups), dim3(64 * kWaves),
                            (size_t)(a.stage_words + kStagePad) * 4, st, a);
     else
-        hipLaunchKernelGGL((k_em_mfma<MT, false, SPLIT, PPB, G>), dim3((unsigned)groups), dim3(64 * kWaves), 0, st,
-                           a);
+        hipLaunchKernelGGL((k_em_mfma<MT, kSrcGlobal, SPLIT, PPB, G>), dim3((unsigned)groups), dim3(64 * kWaves), 0,
+                           st, a);
     PM_LAUNCHED();
     return PM_OK;
 }
@@ -630,7 +807,7 @@ static int dispatch_em_mfma(const EmMfmaArgs &a, hipStream_t st, int shape = 0)
 
 int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
                    const int64_t *n_dev, int32_t iters, double beta, double *theta_out, double *J_out,
-                   double *llr_out, int32_t *sites_out, bool split, hipStream_t st)
+                   double *llr_out, int32_t *sites_out, void *ws, size_t ws_bytes, bool split, hipStream_t st)
 {
     EmMfmaArgs a{};
     a.split = split;
@@ -651,6 +828,8 @@ int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const doub
     a.l = l;
     a.iters = iters;
     a.beta = beta;
+    const int rc = prepare_tables(a, S, l, ws, ws_bytes, st);
+    if (rc != PM_OK) return rc;
     return dispatch_em_mfma(a, st);
 }
 
@@ -658,7 +837,8 @@ int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const doub
 // workgroup count, the largest-first order of the instances and the scan of
 // the counts in that order.
 __global__ void __launch_bounds__(1024) k_em_plan(const pm_inst *inst, int P, const pm_bucket *buckets,
-                                                 const int64_t *n_dev, int64_t Bcap, int mw, int64_t *plan)
+                                                 const int64_t *n_dev, int64_t Bcap, int mw, int64_t *plan,
+                                                 int64_t *tbase)
 {
     const PlanView pv = plan_view(plan, P);
     int64_t *wg_start = const_cast<int64_t *>(pv.wg_start), *b0 = const_cast<int64_t *>(pv.b0);
@@ -698,7 +878,34 @@ __global__ void __launch_bounds__(1024) k_em_plan(const pm_inst *inst, int P, co
             run += (b1[p] - b0[p] + mw - 1) / mw;
         }
         wg_start[P] = run;
+        // first precomputed-table slot of every instance, in instance order
+        if (tbase) {
+            int64_t sl = 0;
+            for (int p = 0; p < P; ++p) {
+                tbase[p] = sl;
+                sl += em_inst_slots(inst[p].t, inst[p].x);
+            }
+            tbase[P] = sl;
+        }
     }
+}
+
+// batch workspace: the plan, the instances' first table slots, the tables
+static size_t plan_bytes(int32_t P) { return ((size_t)(4 * (int64_t)P + 1) * sizeof(int64_t) + 255) / 256 * 256; }
+static size_t tbase_bytes(int32_t P) { return ((size_t)(P + 1) * sizeof(int64_t) + 255) / 256 * 256; }
+static int64_t batch_slots(const pm_batch *Bt)
+{
+    int64_t sl = 0;
+    for (int p = 0; p < Bt->P; ++p) sl += em_inst_slots(Bt->inst_host[p].t, Bt->inst_host[p].x);
+    return sl;
+}
+
+size_t em_batch_workspace(const pm_batch *Bt, bool tables)
+{
+    if (Bt->P < 1) return 0;
+    size_t n = plan_bytes(Bt->P) + tbase_bytes(Bt->P);
+    if (tables) n += (size_t)batch_slots(Bt) * pair_table_bytes((Bt->l + 3) / 4);
+    return n;
 }
 
 int em_refine_mfma_batch(const pm_batch *Bt, int64_t nw_max, int t_max, const pm_bucket *buckets,
@@ -706,17 +913,31 @@ int em_refine_mfma_batch(const pm_batch *Bt, int64_t nw_max, int t_max, const pm
                          double beta, double *theta_out, double *J_out, double *llr_out, int32_t *sites_out,
                          void *ws, bool split, hipStream_t st)
 {
-    int64_t *plan = static_cast<int64_t *>(ws);
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    int64_t *plan = reinterpret_cast<int64_t *>(w);
+    int64_t *tbase = reinterpret_cast<int64_t *>(w + plan_bytes(Bt->P));
+    uint8_t *tables = w + plan_bytes(Bt->P) + tbase_bytes(Bt->P);
     int shape = tuned_shape(Bt->l, split);
     if (!shape_ok(shape, Bt->l)) shape = 10 + shape % 10;
     hipLaunchKernelGGL(k_em_plan, dim3(1), dim3(1024), 0, st, Bt->inst, Bt->P, buckets, n_dev, B,
-                       16 * kWaves * (shape / 10), plan);
+                       16 * kWaves * (shape / 10), plan, tbase);
     PM_LAUNCHED();
+    EmTabArgs tt{};
+    tt.inst = Bt->inst;
+    tt.tbase = tbase;
+    tt.P = Bt->P;
+    tt.l = Bt->l;
+    tt.nslots = batch_slots(Bt);
+    tt.tables = tables;
+    const int rc = launch_em_tables(tt, st);
+    if (rc != PM_OK) return rc;
     EmMfmaArgs a{};
     a.split = split;
     a.inst = Bt->inst;
     a.plan = plan;
     a.P = Bt->P;
+    a.tables = tables;
+    a.tbase = tbase;
     a.theta0 = theta0;
     a.bg = bg;
     a.n_dev = n_dev;
@@ -725,17 +946,19 @@ int em_refine_mfma_batch(const pm_batch *Bt, int64_t nw_max, int t_max, const pm
     a.llr = llr_out;
     a.sites = sites_out;
     a.B = B;
-    a.stage_words = nw_max * 4 <= 32 * 1024 ? (int)nw_max : 0;  // LDS reserved; each group stages its own
+    a.stage_words = 0;
     a.site_stride = t_max;
     a.l = Bt->l;
     a.iters = iters;
     a.beta = beta;
+    (void)nw_max;
     // every instance wastes at most one partly filled group
     return dispatch_em_mfma(a, st, shape);
 }
 
 int em_autotune_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B, int32_t iters,
-                     double beta, bool split, double *theta_out, double *J_out, int32_t *choice, hipStream_t st)
+                     double beta, bool split, double *theta_out, double *J_out, void *ws, size_t ws_bytes,
+                     int32_t *choice, hipStream_t st)
 {
     EmMfmaArgs a{};
     a.split = split;
@@ -753,6 +976,8 @@ int em_autotune_mfma(const pm_seqs *S, int32_t l, const double *theta0, const do
     a.l = l;
     a.iters = iters;
     a.beta = beta;
+    const int prc = prepare_tables(a, S, l, ws, ws_bytes, st);
+    if (prc != PM_OK) return prc;
     hipEvent_t e0, e1;
     PM_TRY(hipEventCreate(&e0));
     PM_TRY(hipEventCreate(&e1));
@@ -791,6 +1016,5 @@ int em_record_shape(int32_t l, bool split, int32_t shape)
     return PM_OK;
 }
 
-size_t em_batch_workspace(int32_t P) { return P < 1 ? 0 : (size_t)(4 * (int64_t)P + 1) * sizeof(int64_t) + 256; }
 
 }  // namespace pm

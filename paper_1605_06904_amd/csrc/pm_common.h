@@ -57,14 +57,16 @@ int check_batch(const pm_batch *B, BatchInfo *info);
 
 int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
                    const int64_t *n_dev, int32_t iters, double beta, double *theta_out, double *J_out,
-                   double *llr_out, int32_t *sites_out, bool split, hipStream_t st);
+                   double *llr_out, int32_t *sites_out, void *ws, size_t ws_bytes, bool split, hipStream_t st);
+size_t em_tables_workspace(const pm_seqs *S, int32_t l);
 int em_refine_mfma_batch(const pm_batch *Bt, int64_t nw_max, int t_max, const pm_bucket *buckets,
                          const double *theta0, const double *bg, int64_t B, const int64_t *n_dev, int32_t iters,
                          double beta, double *theta_out, double *J_out, double *llr_out, int32_t *sites_out,
                          void *ws, bool split, hipStream_t st);
-size_t em_batch_workspace(int32_t P);
+size_t em_batch_workspace(const pm_batch *Bt, bool tables);
 int em_autotune_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B, int32_t iters,
-                     double beta, bool split, double *theta_out, double *J_out, int32_t *choice, hipStream_t st);
+                     double beta, bool split, double *theta_out, double *J_out, void *ws, size_t ws_bytes,
+                     int32_t *choice, hipStream_t st);
 int em_tuned_shape(int32_t l, bool split);
 int em_record_shape(int32_t l, bool split, int32_t shape);
 int em_refine_prot(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,

@@ -111,13 +111,19 @@ def test_other_entry_points_validate():
     assert L.theta_init(5, 4, 0x1, 1, None, 0x1, 1.0, 0x1, None) == pm.PM_EINVAL
     assert L.theta_init(4, 4, 0x1, 1, None, 0x1, -1.0, 0x1, None) == pm.PM_EINVAL
     assert L.em_refine(C.byref(S.c), 4, 0x1, 0x1, 1, None, 3, 1.0, 7, 0x1, 0x1, None, None,
-                       None) == pm.PM_EINVAL
+                       None, 0, None) == pm.PM_EINVAL
     assert L.em_refine(C.byref(S.c), 4, 0x1, 0x1, 1, None, -1, 1.0, 0, 0x1, 0x1, None, None,
-                       None) == pm.PM_EINVAL
+                       None, 0, None) == pm.PM_EINVAL
+    # matrix-core workspace: one-hot tables of t + ceil(x/32) window pairs of
+    # 1 KB + (4 ceil(l/4) + 12) x 64 B (t=2, n=10+10, l=4: x=14, 3 pairs of 2 KB)
+    assert L.pm_em_workspace(C.byref(S.c), 4, pm.PM_F16X2) == 3 * 2048
+    assert L.pm_em_workspace(C.byref(S.c), 4, pm.PM_FP64) == 0
+    assert L.em_refine(C.byref(S.c), 4, 0x1, 0x1, 1, None, 3, 1.0, pm.PM_F16X2, 0x1, 0x1, None, None,
+                       0x1000, 3 * 2048 - 1, None) == pm.PM_EINVAL
     assert L.em_best(0x1, 1, None, 0, 0x1, 4, 40, 0x1, None, None) == pm.PM_EINVAL
     # nothing to do is fine and launches nothing
     assert L.em_refine(C.byref(S.c), 4, None, None, 0, None, 3, 1.0, 0, None, None, None, None,
-                       None) == pm.PM_OK
+                       None, 0, None) == pm.PM_OK
 
 
 def test_projection_run_rejects_bad_problem():
@@ -175,14 +181,18 @@ def test_batch_and_triage_entry_points_validate():
     # EM: the matrix-core forms are DNA only; a too-small plan workspace
     S = _S(_fake_seqs(alphabet=20))
     assert L.em_refine(C.byref(S.c), 4, 0x1, 0x1, 1, None, 3, 1.0, pm.PM_F16X2, 0x1, 0x1, None, None,
-                       None) == pm.PM_EINVAL
+                       None, 0, None) == pm.PM_EINVAL
     # the protein matrix-core form takes l <= 24
     S25 = _S(_fake_seqs(alphabet=20, n_total=60, n_min=30, n_max=30))
     assert L.em_refine(C.byref(S25.c), 25, 0x1, 0x1, 1, None, 3, 1.0, pm.PM_F16, 0x1, 0x1, None, None,
-                       None) == pm.PM_ERANGE
+                       None, 0, None) == pm.PM_ERANGE
     assert L.em_refine_batch(C.byref(b), 0x1, 0x1, 0x1, 10, None, 2, 1.0, pm.PM_F16X2, 0x1, 0x1, None,
                              None, 0x1, 8, None) == pm.PM_EINVAL
-    assert pm.pm_em_batch_workspace(3) >= 8 * 13
+    # batch workspace: plan (4P+1 int64) and first slots (P+1 int64), each
+    # rounded to 256 B, then the tables: instances t = 2, 3, 4 with x = 20, 30,
+    # 40 at l = 11 take 3 + 4 + 6 window pairs of 1 KB + 24 x 64 B
+    assert L.pm_em_batch_workspace(C.byref(b), pm.PM_F16X2) == 256 + 256 + 13 * 2560
+    assert L.pm_em_batch_workspace(C.byref(b), pm.PM_FP32) == 0
     # triage: l above 21, frac outside (0, 1], workspace sizes
     assert L.triage_features(22, 0x1, 1, None, 0x1, None, None, 0x1, None) == pm.PM_EINVAL
     assert L.triage_features(15, 0x1, 1, None, 0x1, 0x1, None, 0x1, None) == pm.PM_EINVAL  # mu without sd

@@ -269,7 +269,7 @@ def _em_case(seed, A, t, n, l, d, nb):
     return inst, ref, bg, np.ascontiguousarray(th0)
 
 
-def _em_gpu(S, l, th0, bg, iters, beta, precision):
+def _em_gpu(S, l, th0, bg, iters, beta, precision, ws=None):
     B = th0.shape[0]
     A = S.alphabet
     d_th0 = torch.from_numpy(th0).cuda()
@@ -278,7 +278,7 @@ def _em_gpu(S, l, th0, bg, iters, beta, precision):
     J = torch.zeros((B, iters + 1), dtype=torch.float64, device="cuda")
     LL = torch.zeros_like(J)
     sites = torch.zeros((B, S.t), dtype=torch.int32, device="cuda")
-    pm.em_refine(S, l, d_th0, d_bg, B, None, iters, beta, precision, th, J, LL, sites)
+    pm.em_refine(S, l, d_th0, d_bg, B, None, iters, beta, precision, th, J, LL, sites, ws=ws)
     best = torch.zeros(1, dtype=torch.int64, device="cuda")
     cons = torch.zeros(l + 1, dtype=torch.uint8, device="cuda")
     pm.em_best(J, B, None, iters, th, A, l, best, cons)
@@ -554,6 +554,34 @@ def test_c5_full_size_sampled_against_oracle():
     """(21,7) DNA, t=50, n=2000 (x = 99 000: u32 histogram in key-range slices),
     k=9, m=10000; EM sample on the split-FP16 matrix cores."""
     _full_size_sampled("c5", pm.PM_F16X2, n_trials=4, n_buckets=16, seed=5)
+
+
+@pytest.mark.parametrize("case", [c for c in EM_CASES if c[2] == 4], ids=[c[0] for c in EM_CASES if c[2] == 4])
+def test_em_precomputed_tables_match_the_in_kernel_build(case):
+    """The DNA matrix-core forms read the one-hot tables of every window pair
+    from the workspace (built once per call) or, without one, build them inside
+    the EM kernel: the same tables, so the same bits, for ragged lengths,
+    sequence tails and a workspace padded with garbage past its size."""
+    name, seed, A, t, n, l, d, B, iters, beta = case
+    if n is None:
+        rng = np.random.default_rng(seed)
+        inst = planted_instance(rng, t, list(rng.integers(l + 3, 400, size=t)), l, d)
+        th0 = np.ascontiguousarray(np.stack([0.7 * rng.dirichlet(np.ones(4), size=l).T + 0.075
+                                              for _ in range(B)]))
+        bg = np.full(4, 0.25)
+    else:
+        inst, ref, bg, th0 = _em_case(seed, A, t, n, l, d, B)
+    say("em tables", name)
+    S = pm.Seqs(A, inst.seqs)
+    for prec in (pm.PM_F16X2, pm.PM_F16):
+        nbytes = pm.pm_em_workspace(S, l, prec)
+        assert nbytes > 0
+        ws = torch.full((nbytes + 4096,), 0x7F, dtype=torch.uint8, device="cuda")
+        pre = _em_gpu(S, l, th0, bg, iters, beta, prec, ws=ws)
+        built = _em_gpu(S, l, th0, bg, iters, beta, prec, ws=False)
+        for x, y in zip(pre[:4], built[:4]):
+            assert np.array_equal(x, y), (name, prec)
+        assert pre[4:] == built[4:]
 
 
 def test_em_autotune_records_a_shape_and_keeps_results():
