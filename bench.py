@@ -195,7 +195,7 @@ def main():
         "data": "synthetic planted (18,6) motif, seeded",
         "config": {"workload": "(18,6) DNA: t=20, n=1000, k=8, s=4, m=5000 trials, 10 EM iterations",
                    "x_lmers_per_trial": x, "enriched_buckets": nbk, "members": nmem,
-                   "em_tile_shape": f"{16 * shape_g} models per wave, {shape_ppb} window pairs per table build "
+                   "em_tile_shape": f"{16 * shape_g} models per wave, {shape_ppb} window pairs per barrier "
                                     "(autotuned)",
                    "parallelism": "single GPU"},
         "stage_ms": stage,
@@ -517,7 +517,7 @@ def pick_shape(torch, pm, l, run):
     candidate pinned in turn, the pipeline run eagerly (once to warm up, once
     timed), the fastest kept for the graph captured next."""
     times = {}
-    for shape in (11, 12, 21, 22):
+    for shape in (11, 12, 14, 21, 22, 24):
         try:
             pm.em_set_tuning(l, pm.PM_F16X2, shape)
         except pm.PmError:

@@ -200,14 +200,14 @@ size_t pm_em_workspace(const pm_seqs *S, int32_t l, int32_t precision);
  * fastest for models of length class ceil(l/4) and this precision in a
  * process-wide table that later em_refine / em_refine_batch calls use.
  * A shape is coded 10 G + PPB: G groups of 16 models per wave (1, or 2 for
- * l <= 24), PPB window pairs whose one-hot tables are built per workgroup
- * barrier (1 or 2).  Pass B of the size the later calls will have: the
+ * l <= 24), PPB window pairs whose one-hot tables are staged per workgroup
+ * barrier (1, 2 or 4).  Pass B of the size the later calls will have: the
  * shapes differ in workgroup size, so their ranking depends on how well B
  * fills the device.
  * theta_out, J_out: device scratch of em_refine's shapes (overwritten);
  * ws, ws_bytes: as for em_refine (pass the workspace the timed calls will
  * have).  DNA only.  choice_out: host int32[1] or NULL.  em_tuning returns
- * the shape in use (untuned: 12), or a negative status. */
+ * the shape in use (untuned: 14), or a negative status. */
 int em_autotune(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B, int32_t iters,
                 double beta, int32_t precision, double *theta_out, double *J_out, void *ws, size_t ws_bytes,
                 int32_t *choice_out, void *stream);

@@ -1,12 +1,16 @@
 """Build libprojmotif.so for gfx950 with hipcc, in-tree.
 
-Run ``python -m paper_1605_06904_amd.build`` (or call ``build()``).
+Run ``python -m paper_1605_06904_amd.build`` (or call ``build()``).  Every
+source is compiled to its own object in parallel (no device code crosses
+files), then the objects are linked into the shared library.
 """
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -20,7 +24,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     "-Wno-unused-function",
     # never let the compiler form packed FP32 instructions
@@ -28,22 +31,32 @@ FLAGS = [
     # matrix-core accumulators in ordinary VGPRs (no AGPR round trips)
     "-mllvm", "-amdgpu-mfma-vgpr-form=1",
 ]
+# the host pass does not know the packed-fp32 feature; that note is harmless
+_NOISE = "is not a recognized feature for this target"
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
-    # the host pass does not know the packed-fp32 feature; that note is harmless
-    noise = "is not a recognized feature for this target"
-    err = "\n".join(ln for ln in r.stderr.splitlines() if noise not in ln)
+    err = "\n".join(ln for ln in r.stderr.splitlines() if _NOISE not in ln)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed ({r.returncode}):\n{err}")
     if err.strip() and verbose:
         print(err, file=sys.stderr)
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    jobs = jobs or min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1)))
+    with tempfile.TemporaryDirectory(prefix="pm_build_") as tmpd:
+        objs = [os.path.join(tmpd, s.replace(".hip", ".o")) for s in SOURCES]
+        cmds = [[HIPCC, *FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+        with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        tmp = LIB + ".tmp"
+        _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

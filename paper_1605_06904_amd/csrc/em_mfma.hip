@@ -105,7 +105,7 @@ __host__ __device__ inline PlanView plan_view(const int64_t *plan, int P)
 constexpr int kWaves = 4;  // waves (groups of 16 models) per workgroup
 // tile shape 10 G + PPB: G groups of 16 models per wave, PPB window pairs
 // built per workgroup barrier
-constexpr int kShapeDefault = 12;  // untuned
+constexpr int kShapeDefault = 14;  // untuned
 constexpr int kMaxMT2 = 6;         // G = 2 for ceil(l/4) <= 6 (registers)
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kPOff = 3.0f;
@@ -761,7 +761,7 @@ static int g_shape[8][2];
 static bool shape_ok(int shape, int l)
 {
     const int G = shape / 10, ppb = shape % 10;
-    return (ppb == 1 || ppb == 2) && (G == 1 || (G == 2 && (l + 3) / 4 <= kMaxMT2));
+    return (ppb == 1 || ppb == 2 || ppb == 4) && (G == 1 || (G == 2 && (l + 3) / 4 <= kMaxMT2));
 }
 
 static int tuned_shape(int l, bool split)
@@ -792,8 +792,10 @@ static int dispatch_shape(const EmMfmaArgs &a, hipStream_t st, int shape)
     switch (shape) {
     case 11: return dispatch_mt<SPLIT, 1, 1>(a, st);
     case 12: return dispatch_mt<SPLIT, 2, 1>(a, st);
+    case 14: return dispatch_mt<SPLIT, 4, 1>(a, st);
     case 21: return dispatch_mt<SPLIT, 1, 2>(a, st);
-    default: return dispatch_mt<SPLIT, 2, 2>(a, st);
+    case 22: return dispatch_mt<SPLIT, 2, 2>(a, st);
+    default: return dispatch_mt<SPLIT, 4, 2>(a, st);
     }
 }
 
@@ -983,7 +985,7 @@ int em_autotune_mfma(const pm_seqs *S, int32_t l, const double *theta0, const do
     PM_TRY(hipEventCreate(&e1));
     float best_ms = 0.f;
     int best = 0, rc = PM_OK;
-    for (const int shape : {11, 12, 21, 22}) {
+    for (const int shape : {11, 12, 14, 21, 22, 24}) {
         if (!shape_ok(shape, l)) continue;
         float ms = 0.f;
         rc = dispatch_em_mfma(a, st, shape);  // warm-up
@@ -1011,7 +1013,8 @@ int em_tuned_shape(int32_t l, bool split) { return tuned_shape(l, split); }
 int em_record_shape(int32_t l, bool split, int32_t shape)
 {
     if (!shape_ok(shape, l))
-        return fail(PM_EINVAL, "tile shape %d is not one of 11, 12, 21, 22 (G = 2 needs l <= %d)", shape, 4 * kMaxMT2);
+        return fail(PM_EINVAL, "tile shape %d is not one of 11, 12, 14, 21, 22, 24 (G = 2 needs l <= %d)", shape,
+                    4 * kMaxMT2);
     g_shape[(l + 3) / 4 - 1][split ? 1 : 0] = shape;
     return PM_OK;
 }

@@ -188,7 +188,7 @@ def test_batch_em_every_tile_shape_bit_identical():
     B = _batch(insts, A, l, k)
     out = {}
     try:
-        for shape in (11, 12, 21, 22):
+        for shape in (11, 12, 14, 21, 22, 24):
             pm.em_set_tuning(l, pm.PM_F16X2, shape)
             Pp, nb_, nm_ = _pipeline(B, s, 3, 1.0, pm.PM_F16X2, bg)
             Pp.run()
@@ -197,11 +197,11 @@ def test_batch_em_every_tile_shape_bit_identical():
             out[shape] = (b.J.cpu().numpy()[:nb_], b.theta.cpu().numpy()[:nb_], b.sites.cpu().numpy()[:nb_],
                           [r["best"] for r in Pp.results()])
     finally:
-        pm.em_set_tuning(l, pm.PM_F16X2, 12)
+        pm.em_set_tuning(l, pm.PM_F16X2, 14)
     trial = u32(b.buckets)[:nb_, 0]
     per_inst = [int(((trial >= f) & (trial < f + m)).sum()) for f, m in zip(B.first_item, B.m)]
     assert max(per_inst) > 64 and min(per_inst) < 64, per_inst
-    for shape in (12, 21, 22):
+    for shape in (12, 14, 21, 22, 24):
         for x, y in zip(out[11][:3], out[shape][:3]):
             assert np.array_equal(x, y), shape
         assert out[11][3] == out[shape][3], shape

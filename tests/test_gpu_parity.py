@@ -595,7 +595,7 @@ def test_em_autotune_records_a_shape_and_keeps_results():
     for prec in (pm.PM_F16X2, pm.PM_F16):
         pm.em_set_tuning(18, prec, 11)
         base = _em_gpu(S, 18, th0, bg, 3, 1.0, prec)
-        for shape in (12, 21, 22):
+        for shape in (12, 14, 21, 22, 24):
             pm.em_set_tuning(18, prec, shape)
             assert pm.em_tuning(18, prec) == shape
             got = _em_gpu(S, 18, th0, bg, 3, 1.0, prec)
@@ -604,7 +604,7 @@ def test_em_autotune_records_a_shape_and_keeps_results():
         th = torch.zeros_like(d_th0)
         J = torch.zeros((th0.shape[0], 4), dtype=torch.float64, device="cuda")
         choice = pm.em_autotune(S, 18, d_th0, torch.from_numpy(bg).cuda(), th0.shape[0], 3, 1.0, prec, th, J)
-        assert choice in (11, 12, 21, 22) and pm.em_tuning(18, prec) == choice
+        assert choice in (11, 12, 14, 21, 22, 24) and pm.em_tuning(18, prec) == choice
         after = _em_gpu(S, 18, th0, bg, 3, 1.0, prec)
         assert np.array_equal(base[1], after[1]) and np.array_equal(base[0], after[0])
     # G = 2 is limited to l <= 24; the default shape stays valid everywhere
