@@ -37,9 +37,12 @@
 // groups of 16 per wave; the groups of a wave share every A operand (the
 // one-hot tables), so G = 2 halves the table reads and builds per model and
 // gives each wave two independent E-step/softmax/M-step chains to interleave.
-// The four waves sweep the same windows in step and build the one-hot tables
-// of PPB window pairs together in LDS (double-buffered, one barrier per PPB
-// pairs) from the packed instance staged in LDS.  (G, PPB) is the tunable tile
+// The four waves sweep the same windows in step; the one-hot tables of PPB
+// window pairs sit in LDS per step (double-buffered, one barrier per PPB
+// pairs).  With a workspace, k_em_tables builds every pair's tables once per
+// call and the EM kernel copies each step's into LDS, loading the next step's
+// while it computes; without one, the workgroup builds them itself from the
+// packed instance (staged in LDS when it fits).  (G, PPB) is the tunable tile
 // shape: em_autotune times the variants on the caller's models and records
 // the fastest per (ceil(l/4), precision) class.
 #include <math.h>
@@ -111,13 +114,6 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kPOff = 3.0f;
 constexpr float kSlack = 12.0f;
 
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // 32 DNA symbols starting at P (MSB-first) as hi (P..P+15) and lo (P+16..P+31).
 // CLAMP: reads clamped below nw (global memory); otherwise the buffer is padded.
 template <bool CLAMP>
@@ -159,12 +155,6 @@ __host__ __device__ inline int64_t em_inst_slots(int64_t t, int64_t x) { return 
 __device__ __forceinline__ int64_t seq_slot0(const int64_t *offsets, int i, int l)
 {
     return i + (offsets[i] - (int64_t)i * (l - 1)) / 32;
-}
-
-// two FP16 halves: 1.0 where letter a == c (low half), where b == c (high half)
-__device__ __forceinline__ uint32_t onehot_pair(uint32_t a, uint32_t b, uint32_t c)
-{
-    return (a == c ? 0x3C00u : 0u) | (b == c ? 0x3C000000u : 0u);
 }
 
 // fp16(p - hi) for two values whose fp16 roundings are packed in hi2
