@@ -566,9 +566,15 @@ def cpu_baseline(inst, masks, cfg, bg, beta, nbk, budget):
         oracle.em(ref, l, th0[:nb2], bg, iters, beta)
         per = (time.perf_counter() - t3) / nb2
     est = (t2 - t0) * m / mt + per * nbk
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), cpu_model)
+    except OSError:
+        pass
     return {"value": round(m * x / est, 1), "unit": "l-mers/s", "cores": cores, "kind": "oracle",
             "sample": f"hash+select of {mt}/{m} trials, EM of {max(nb, nb2)}/{nbk} buckets, linear extrapolation",
-            "est_s_per_step": round(est, 2)}
+            "est_s_per_step": round(est, 2), "cpu_model": cpu_model, "nproc": os.cpu_count()}
 
 
 if __name__ == "__main__":
