@@ -225,8 +225,10 @@ __device__ __forceinline__ void build_tables(const uint32_t *W, int64_t nw, int6
 }
 
 struct SeqState {
+    float4v neg;  // kPOff - mref in every component: the E-step accumulators' start
     float mref;   // reference (log2 units) of the scores
-    float srun;   // this lane's share of sum 2^(S - mref + kPOff)
+    float srun;   // final E-step: this lane's share of sum 2^(S - mref + kPOff)
+                  // (the other sweeps take the sum from the M-step counts)
     float bestv;  // final E-step: best score and window of this lane
     int besti;
 };
@@ -248,13 +250,11 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T
         for (int kb = 0; kb < LB; ++kb)
             Ae[t2][kb] = *reinterpret_cast<const half8 *>(&T.oh2[16 * t2 + r + 8 * kb + 2 * g][0]);
     // E-step, already shifted: S' = S - (mref - kPOff); one chain per tile and group
-    float sh[G];
     float4v S0[G], S1[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
-        sh[q] = st[q].mref - kPOff;
-        S0[q] = float4v{-sh[q], -sh[q], -sh[q], -sh[q]};
-        S1[q] = S0[q];
+        S0[q] = st[q].neg;
+        S1[q] = st[q].neg;
     }
 #pragma unroll
     for (int kb = 0; kb < LB; ++kb)
@@ -295,8 +295,8 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T
         if (LAST) {
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (S[u] + sh[q] > st[q].bestv) {
-                    st[q].bestv = S[u] + sh[q];
+                if (S[u] - st[q].neg[0] > st[q].bestv) {
+                    st[q].bestv = S[u] - st[q].neg[0];
                     st[q].besti = a0 + 16 * (u >> 2) + 4 * g + (u & 3);
                 }
         }
@@ -307,18 +307,20 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T
             tm = fmaxf(tm, __shfl_xor(tm, 32));
             const float d = tm > kPOff + kSlack ? tm - kPOff : 0.f;
             const float al = __builtin_amdgcn_exp2f(-d);
-            st[q].srun *= al;
+            if (LAST) st[q].srun *= al;
             if (!LAST)
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) O[q][mt] *= al;
 #pragma unroll
             for (int u = 0; u < 8; ++u) S[u] -= d;
             st[q].mref += d;
+            const float n = kPOff - st[q].mref;  // exactly what the scores are shifted by
+            st[q].neg = float4v{n, n, n, n};
         }
         float P[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) P[u] = __builtin_amdgcn_exp2f(S[u]);
-        st[q].srun += ((P[0] + P[1]) + (P[2] + P[3])) + ((P[4] + P[5]) + (P[6] + P[7]));
+        if (LAST) st[q].srun += ((P[0] + P[1]) + (P[2] + P[3])) + ((P[4] + P[5]) + (P[6] + P[7]));
         if (!LAST) {
             uint4 h;
             h.x = pack_hi(P[0], P[1]);
@@ -384,7 +386,8 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) O[q][mt] = float4v{0.f, 0.f, 0.f, 0.f};
         // the reference starts at the lowest score the model can give
-        st[q] = SeqState{mlow[q], 0.f, -INFINITY, 0};
+        const float n0 = kPOff - mlow[q];
+        st[q] = SeqState{float4v{n0, n0, n0, n0}, mlow[q], 0.f, -INFINITY, 0};
     }
     for (int a0 = 0; a0 < L; a0 += 32 * PPB) {
         PairTables<MT> *T = tabs + PPB * parity;
@@ -418,9 +421,17 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
     }
 #pragma unroll
     for (int q = 0; q < G; ++q) {
-        float sr = st[q].srun;
-        sr += __shfl_xor(sr, 16);
-        sr += __shfl_xor(sr, 32);
+        float sr;
+        if (LAST) {
+            sr = st[q].srun;
+            sr += __shfl_xor(sr, 16);
+            sr += __shfl_xor(sr, 32);
+        } else {
+            // every window has one letter at position 0, so the counts of
+            // position 0 (lane group 0's first row tile) sum to sum_w 2^(S_w - ref)
+            const float4v c0 = O[q][0];
+            sr = __shfl((c0[0] + c0[1]) + (c0[2] + c0[3]), r);
+        }
         const double ln2 = 0.6931471805599453;
         const double lse = ((double)st[q].mref - (double)kPOff) * ln2 + log((double)sr);
         llr[q] += lse - log((double)L);
