@@ -584,6 +584,26 @@ def test_em_precomputed_tables_match_the_in_kernel_build(case):
         assert pre[4:] == built[4:]
 
 
+def test_em_instance_too_large_to_stage_builds_from_global_memory():
+    """An instance of 150 000 symbols (more than the 32 KB of packed words the
+    kernel stages in LDS): without a workspace the matrix-core EM builds the
+    one-hot tables from the packed words in global memory (reads clamped to the
+    buffer), with one it copies the precomputed tables; both give the same
+    bits, within 1e-5 of the oracle."""
+    inst, ref, bg, th0 = _em_case(31, 4, 5, 30000, 12, 3, 6)
+    say("em large instance")
+    S = pm.Seqs(4, inst.seqs)
+    assert pm.pm_packed_words(4, S.n_total) * 4 > 32 * 1024
+    iters = 2
+    rth, rJ, rLL, rsites = oracle.em(ref, 12, th0, bg, iters, 1.0)
+    pre = _em_gpu(S, 12, th0, bg, iters, 1.0, pm.PM_F16X2)
+    built = _em_gpu(S, 12, th0, bg, iters, 1.0, pm.PM_F16X2, ws=False)
+    for x, y in zip(pre[:4], built[:4]):
+        assert np.array_equal(x, y)
+    np.testing.assert_allclose(pre[1], rJ, rtol=1e-5, atol=1e-5 * np.abs(rJ).max())
+    np.testing.assert_allclose(pre[0], rth, rtol=0, atol=2e-5)
+
+
 def test_em_autotune_records_a_shape_and_keeps_results():
     """The tile-shape autotuner times the candidates on the caller's models and
     records the fastest; every shape gives bit-identical results (the shapes
