@@ -350,17 +350,24 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T
 // window a0 of sequence i (kSrcPre): loaded into registers one step ahead of
 // their use, written to LDS at the step that uses them.
 template <int MT, int PPB>
-__device__ __forceinline__ void fetch_tables(const EmMfmaArgs &a, int64_t tb, int i, int a0, u32x4 (&pf)[PPB])
+__device__ __forceinline__ void fetch_tables(const EmMfmaArgs &a, int64_t slot0, int L, int a0, u32x4 (&pf)[PPB])
 {
     // every load is unconditional and in bounds (a pair past the sequence's
     // end re-reads the step's first pair, threads past the quads re-read the
     // last one), which keeps pf in registers; only the LDS writes are guarded
     constexpr int NQ = kTabQuads<MT>;
-    const int L = (int)(a.offsets[i + 1] - a.offsets[i]) - a.l + 1;
     const int q = (int)threadIdx.x < NQ ? (int)threadIdx.x : NQ - 1;
-    const u32x4 *src = reinterpret_cast<const u32x4 *>(a.tables) + (tb + seq_slot0(a.offsets, i, a.l) + a0 / 32) * NQ + q;
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(a.tables) + (slot0 + a0 / 32) * NQ + q;
 #pragma unroll
     for (int u = 0; u < PPB; ++u) pf[u] = src[(a0 + 32 * u < L ? u : 0) * NQ];
+}
+
+// windows and first table slot of sequence i of the instance whose first slot
+// is tb (kSrcPre)
+__device__ __forceinline__ void seq_slots(const EmMfmaArgs &a, int64_t tb, int i, int &L, int64_t &slot0)
+{
+    L = (int)(a.offsets[i + 1] - a.offsets[i]) - a.l + 1;
+    slot0 = tb + seq_slot0(a.offsets, i, a.l);
 }
 
 // One sequence: every window pair (tables built by the whole workgroup, or
@@ -379,6 +386,15 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     const int64_t s0 = a.offsets[i];
     const int L = (int)(a.offsets[i + 1] - s0) - a.l + 1;
+    // kSrcPre: this sequence's first slot and the next sequence's size and
+    // first slot, formed once here rather than at every step
+    int64_t sl = 0, sln = 0;
+    int Ln = 0;
+    if constexpr (SRC == kSrcPre) {
+        int Li;
+        seq_slots(a, tb, i, Li, sl);
+        seq_slots(a, tb, i + 1 < a.t ? i + 1 : 0, Ln, sln);
+    }
     float4v O[G][MT];
     SeqState st[G];
 #pragma unroll
@@ -404,13 +420,11 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
         }
         __syncthreads();
         if constexpr (SRC == kSrcPre) {
-            // the next step's quads load while this step computes
-            int ni = i, na = a0 + 32 * PPB;
-            if (na >= L) {
-                na = 0;
-                ni = i + 1 < a.t ? i + 1 : 0;
-            }
-            fetch_tables<MT, PPB>(a, tb, ni, na, pf);
+            // the next step's quads (this sequence's, or the next sequence's
+            // first) load while this step computes
+            const int na = a0 + 32 * PPB;
+            if (na < L) fetch_tables<MT, PPB>(a, sl, L, na, pf);
+            else fetch_tables<MT, PPB>(a, sln, Ln, 0, pf);
         }
 #pragma unroll
         for (int u = 0; u < PPB; ++u) {
@@ -523,7 +537,10 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
         W = staged;
     }
     if constexpr (SRC == kSrcPre) {
-        fetch_tables<MT, PPB>(a, tb, 0, 0, pf);  // the first step of the first sweep
+        int L0;
+        int64_t sl0;
+        seq_slots(a, tb, 0, L0, sl0);
+        fetch_tables<MT, PPB>(a, sl0, L0, 0, pf);  // the first step of the first sweep
     } else {
         build_lut(lut);
         lutp = lut;
