@@ -67,6 +67,9 @@ def parse():
                     help="also run the 512-instance uneven batch with this many trials per instance")
     ap.add_argument("--c5", action="store_true",
                     help="also run one (21,7) instance (t=50, n=2000, k=9, s=3, m=10000) with and without triage")
+    ap.add_argument("--c4", action="store_true",
+                    help="also time the protein (20,6) EM (t=30, n=1000, k=4, s=3, m=2000): the matrix-core "
+                         "precision form against the FP64 vector path, with its error")
     return ap.parse_args()
 
 
@@ -218,6 +221,8 @@ def main():
         out["uneven_batch"] = uneven_leg(torch, pm, args.uneven)
     if args.c5:
         out["triage_21_7"] = c5_leg(torch, pm)
+    if args.c4:
+        out["protein_20_6"] = c4_leg(torch, pm)
     if args.copy_probe:
         # a plain copy of known size, read once and written once, for scaling
         # the HBM byte counters of the kernels above
@@ -322,6 +327,57 @@ def uneven_leg(torch, pm, m, count=512, seed=1):
             "ms": round(ms, 2), "instances_per_s": round(count / (ms / 1e3), 1),
             "projected_lmers_per_s": round(lmers / (ms / 1e3), 1), "enriched_buckets": nbk_tot,
             "shape_classes": len(pipes), "solved": int(solved)}
+
+
+def c4_leg(torch, pm, seed=4, n_f16=131072, n_f64=16384):
+    """The protein (20,6) workload's EM: its enriched buckets (hash and
+    selection on the GPU), then the first n_f16 of them refined in the
+    matrix-core precision form (20-letter one-hot, FP16 operands, FP32
+    accumulation, FP64 log-sum-exp) and the first n_f64 in the FP64 vector
+    path; time per model of each, the full EM extrapolated, and the precision
+    form's error against FP64 on the common models (every iteration's J)."""
+    import oracle
+    from synth import make_config
+    inst, masks = make_config("c4", seed=seed)
+    cfg = inst.meta
+    l, k, s, iters = cfg["l"], cfg["k"], cfg["s"], cfg["iters"]
+    bg = oracle.bg_vector(20, inst.bg)
+    S = pm.Seqs(20, inst.seqs)
+    P0 = pm.Pipeline(S, l, k, s, masks, iters, 1.0, pm.PM_FP32, bg, 0, 0)
+    P0.hash()
+    P0.select()
+    torch.cuda.synchronize()
+    nbk, nmem = [int(v) for v in P0.b.n_out.cpu()]
+    del P0
+    P = pm.Pipeline(S, l, k, s, masks, iters, 1.0, pm.PM_FP32, bg, nbk, nmem)
+    P.hash()
+    P.select()
+    b = P.b
+    pm.bucket_profile(S, l, b.buckets, b.members, b.cap_m, b.cap_b, b.n_out, b.profile)
+    pm.theta_init(20, l, b.profile, b.cap_b, b.n_out, P.bg, 1.0, b.theta0)
+    progress(f"c4: {nbk} enriched buckets")
+    out = {"workload": f"(20,6) protein: t=30, n=1000, k={k}, s={s}, m={len(masks)}, {iters} EM iterations",
+           "enriched_buckets": nbk}
+    Js = {}
+    for prec, name, nb in ((pm.PM_F16, "f16_mfma", min(n_f16, nbk)), (pm.PM_FP64, "fp64_vector", min(n_f64, nbk))):
+        th = torch.zeros((nb, 20, l), dtype=torch.float64, device="cuda")
+        J = torch.zeros((nb, iters + 1), dtype=torch.float64, device="cuda")
+        pm.em_refine(S, l, b.theta0, P.bg, nb, None, iters, 1.0, prec, th, J)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pm.em_refine(S, l, b.theta0, P.bg, nb, None, iters, 1.0, prec, th, J)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out[name] = {"models": nb, "ms": round(ms, 3), "us_per_model": round(ms * 1e3 / nb, 4),
+                     "full_em_s": round(ms / nb * nbk / 1e3, 3)}
+        Js[name] = J[:min(n_f16, n_f64, nbk)].cpu().numpy()
+        progress(f"c4: {name} {ms / nb * 1e3:.3f} us/model")
+    d = np.abs(Js["f16_mfma"] - Js["fp64_vector"]) / np.abs(Js["fp64_vector"])
+    out["f16_vs_fp64"] = {"models": int(d.shape[0]), "max_rel_dJ": float(d.max()), "mean_rel_dJ": float(d.mean())}
+    out["speedup"] = round(out["fp64_vector"]["us_per_model"] / out["f16_mfma"]["us_per_model"], 2)
+    return out
 
 
 def c5_leg(torch, pm, seed=1):
