@@ -42,7 +42,7 @@
 // pairs).  With a workspace, k_em_tables builds every pair's tables once per
 // call and the EM kernel copies each step's into LDS, loading the next step's
 // while it computes; without one, the workgroup builds them itself from the
-// packed instance (staged in LDS when it fits).  (G, PPB) is the tunable tile
+// packed instance in global memory.  (G, PPB) is the tunable tile
 // shape: em_autotune times the variants on the caller's models and records
 // the fastest per (ceil(l/4), precision) class.
 #include <math.h>
@@ -70,7 +70,6 @@ struct EmMfmaArgs {
     int64_t B;
     int64_t nwords;  // packed words (reads are clamped below this)
     int t, l, iters;
-    int stage_words; // packed words staged in LDS, 0 = read from global memory
     int site_stride; // sites row length (t, or the largest t of a batch)
     int split;       // 1: two FP16 halves per operand; 0: one FP16 value
     double beta;
@@ -135,13 +134,8 @@ __device__ __forceinline__ void dna32(const uint32_t *w, int64_t P, int64_t nw, 
     lo = (uint32_t)((((uint64_t)w1 << 32) | w2) >> (32 - r));
 }
 
-// words of zero padding after a staged copy of the packed instance: table
-// builds read up to 95 symbols past the last window start
-constexpr int kStagePad = 8;
-
 // where a workgroup's one-hot tables come from
-constexpr int kSrcGlobal = 0;  // built in the kernel from the packed instance in global memory
-constexpr int kSrcStaged = 1;  // built in the kernel from the packed instance staged in LDS
+constexpr int kSrcGlobal = 0;  // built in the kernel from the packed instance (no workspace)
 constexpr int kSrcPre = 2;     // copied from tables precomputed once per call (k_em_tables)
 
 // Precomputed tables: pair j (windows 32j .. 32j+31) of sequence i of an
@@ -475,8 +469,8 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
 }
 
 // static LDS of a workgroup and the waves per SIMD to compile for: three when
-// the registers of ceil(l/4) <= 5 allow it and three workgroups' LDS (with a
-// staged instance of up to 6 KB) fit the 160 KB of a CU, else two
+// the registers of ceil(l/4) <= 5 allow it and three workgroups' LDS (with 6 KB
+// of headroom each) fit the 160 KB of a CU, else two
 template <int MT, int PPB, int G>
 constexpr int em_static_lds()
 {
@@ -496,7 +490,6 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
     __shared__ __align__(16) PairTables<MT> tabs[2 * PPB];
     __shared__ __align__(16) uint2 lut[256];
     __shared__ __align__(16) float accs[kWaves][G][16][CX][4];
-    extern __shared__ __align__(16) uint32_t staged[];
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     EmMfmaArgs a = a0;
@@ -518,7 +511,6 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
         a.offsets = I.offsets;
         a.t = I.t;
         a.nwords = (I.n_total + 15) / 16 + 4;
-        a.stage_words = SRC == kSrcStaged ? (int)a.nwords : 0;
         tb = a0.tbase ? a0.tbase[p] : 0;
         b0 = pv.b0[p] + (wg - pv.wg_start[lo]) * MW;
         nvalid = pv.b1[p] < b0 + MW ? pv.b1[p] : b0 + MW;
@@ -531,11 +523,6 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
     const uint32_t *W = a.packed;
     const uint2 *lutp = nullptr;
     u32x4 pf[PPB];
-    if constexpr (SRC == kSrcStaged) {
-        for (int k = threadIdx.x; k < a.stage_words + kStagePad; k += 64 * kWaves)
-            staged[k] = k < a.stage_words ? a.packed[k] : 0u;
-        W = staged;
-    }
     if constexpr (SRC == kSrcPre) {
         int L0;
         int64_t sl0;
@@ -612,7 +599,7 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 *reinterpret_cast<float4v *>(&acc[q][r][4 * mt + g][0]) = float4v{0.f, 0.f, 0.f, 0.f};
-        __syncthreads();  // staged sequence visible (first pass), tables free
+        __syncthreads();  // tables free
 
         double llr[G];
 #pragma unroll
@@ -763,9 +750,6 @@ static int launch_em_mfma(const EmMfmaArgs &a, hipStream_t st)
     if (a.tables)
         hipLaunchKernelGGL((k_em_mfma<MT, kSrcPre, SPLIT, PPB, G>), dim3((unsigned)groups), dim3(64 * kWaves), 0, st,
                            a);
-    else if (a.stage_words)
-        hipLaunchKernelGGL((k_em_mfma<MT, kSrcStaged, SPLIT, PPB, G>), dim3((unsigned)groups), dim3(64 * kWaves),
-                           (size_t)(a.stage_words + kStagePad) * 4, st, a);
     else
         hipLaunchKernelGGL((k_em_mfma<MT, kSrcGlobal, SPLIT, PPB, G>), dim3((unsigned)groups), dim3(64 * kWaves), 0,
                            st, a);
@@ -842,7 +826,6 @@ int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const doub
     a.sites = sites_out;
     a.B = B;
     a.nwords = pm_packed_words(S->alphabet, S->n_total);
-    a.stage_words = a.nwords * 4 <= 32 * 1024 ? (int)a.nwords : 0;
     a.t = S->t;
     a.site_stride = S->t;
     a.l = l;
@@ -966,7 +949,6 @@ int em_refine_mfma_batch(const pm_batch *Bt, int64_t nw_max, int t_max, const pm
     a.llr = llr_out;
     a.sites = sites_out;
     a.B = B;
-    a.stage_words = 0;
     a.site_stride = t_max;
     a.l = Bt->l;
     a.iters = iters;
@@ -990,7 +972,6 @@ int em_autotune_mfma(const pm_seqs *S, int32_t l, const double *theta0, const do
     a.J = J_out;
     a.B = B;
     a.nwords = pm_packed_words(S->alphabet, S->n_total);
-    a.stage_words = a.nwords * 4 <= 32 * 1024 ? (int)a.nwords : 0;
     a.t = S->t;
     a.site_stride = S->t;
     a.l = l;
