@@ -102,6 +102,7 @@ HASH_CASES = [
     ("dna l=32 k=16 keys", 4, 3, [64, 40, 33], 32, 11, 3),
     ("dna u32 histogram x>=65536", 4, 40, [1700] * 40, 12, 6, 3),
     ("dna sliced k=9", 4, 10, [900] * 10, 21, 9, 4),
+    ("dna k=8 two slices of a whole-trial histogram", 4, 8, [500] * 8, 12, 8, 3),
     ("protein k=3", 20, 7, [120, 31, 77, 64, 200, 23, 50], 10, 3, 5),
     ("protein sliced k=4", 20, 12, [400] * 12, 20, 4, 3),
     ("dna k=1", 4, 3, [10, 12, 9], 1, 1, 2),
