@@ -28,7 +28,7 @@ FP16_MFMA_PEAK = 2500.0      # TFLOP/s, MI355X dense FP16 matrix cores
 # profiles/hbm_traffic_dna_18-6_m5000.md (copy-calibrated), valid only while
 # the kernel source is the one they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "hash.hip": ("9ec1b4adfe82aa62", {"k_hash<4,8,true>": 1.749e9}),
+    "hash.hip": ("936ac3666631d158", {"k_hash<4,8,true>": 1.760e9}),
     "em_mfma.hip": ("c9812ec47bed7d94", {
         "k_em_mfma<5,2,true,1,1>": 0.758e9 + 0.705e9,
         "k_em_mfma<5,2,true,2,1>": 0.721e9 + 0.719e9,
