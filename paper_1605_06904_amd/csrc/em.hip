@@ -216,12 +216,15 @@ static int launch_em(const EmArgs &a, size_t lds, hipStream_t st)
 // ---------------------------------------------------------------- a10
 // one workgroup per instance (inst != NULL: a batch, whose buckets ascend by
 // item) or a single workgroup over all buckets
-__global__ void __launch_bounds__(256) k_best(const double *J, int64_t B, const int64_t *n_dev, int iters,
-                                              const double *theta, int A, int l, int64_t *best_out,
-                                              char *cons, const pm_inst *inst, const pm_bucket *buckets)
+constexpr int kBestThreads = 1024;
+constexpr int kBestUnroll = 8;  // final objectives in flight per thread
+
+__global__ void __launch_bounds__(kBestThreads) k_best(const double *J, int64_t B, const int64_t *n_dev, int iters,
+                                                       const double *theta, int A, int l, int64_t *best_out,
+                                                       char *cons, const pm_inst *inst, const pm_bucket *buckets)
 {
-    __shared__ double rv[4];
-    __shared__ int64_t ri[4];
+    __shared__ double rv[kBestThreads / kWave];
+    __shared__ int64_t ri[kBestThreads / kWave];
     __shared__ int64_t best_s;
     int64_t nvalid = n_dev ? *n_dev : B;
     if (nvalid > B) nvalid = B;
@@ -246,11 +249,21 @@ __global__ void __launch_bounds__(256) k_best(const double *J, int64_t B, const 
     }
     double bv = -INFINITY;
     int64_t bi = INT64_MAX;
-    for (int64_t b = lo_b + threadIdx.x; b < hi_b; b += 256) {
-        const double v = J[b * (iters + 1) + iters];
-        if (v == v && (bi == INT64_MAX || v > bv)) {
-            bv = v;
-            bi = b;
+    // each thread takes its buckets in ascending order, several loads at a time
+    const int64_t stride = (int64_t)iters + 1;
+    for (int64_t b0 = lo_b + threadIdx.x; b0 < hi_b; b0 += (int64_t)kBestUnroll * kBestThreads) {
+        double v[kBestUnroll];
+#pragma unroll
+        for (int u = 0; u < kBestUnroll; ++u) {
+            const int64_t b = b0 + (int64_t)u * kBestThreads;
+            v[u] = b < hi_b ? J[b * stride + iters] : NAN;
+        }
+#pragma unroll
+        for (int u = 0; u < kBestUnroll; ++u) {
+            if (v[u] == v[u] && (bi == INT64_MAX || v[u] > bv)) {
+                bv = v[u];
+                bi = b0 + (int64_t)u * kBestThreads;
+            }
         }
     }
     // (value, index): larger value wins, then smaller index
@@ -271,7 +284,7 @@ __global__ void __launch_bounds__(256) k_best(const double *J, int64_t B, const 
     if (threadIdx.x == 0) {
         double v = rv[0];
         int64_t i = ri[0];
-        for (int w = 1; w < 4; ++w)
+        for (int w = 1; w < kBestThreads / kWave; ++w)
             if (ri[w] != INT64_MAX && (i == INT64_MAX || rv[w] > v || (rv[w] == v && ri[w] < i))) {
                 v = rv[w];
                 i = ri[w];
@@ -450,7 +463,7 @@ extern "C" int em_best(const double *J, int64_t B, const int64_t *n_dev, int32_t
     if (alphabet != 4 && alphabet != 20) return fail(PM_EINVAL, "alphabet must be 4 or 20");
     if (l < 1 || l > 32 || B < 0 || iters < 0) return fail(PM_EINVAL, "bad sizes");
     if (!best_out || (B > 0 && (!J || !theta))) return fail(PM_EINVAL, "NULL buffer");
-    hipLaunchKernelGGL(k_best, dim3(1), dim3(256), 0, as_stream(stream), J, B, n_dev, iters, theta,
+    hipLaunchKernelGGL(k_best, dim3(1), dim3(kBestThreads), 0, as_stream(stream), J, B, n_dev, iters, theta,
                        alphabet, l, best_out, consensus_out, nullptr, nullptr);
     PM_LAUNCHED();
     return PM_OK;
@@ -465,7 +478,7 @@ extern "C" int em_best_batch(const pm_batch *Bt, const pm_bucket *buckets, const
     if (rc) return rc;
     if (B < 0 || iters < 0) return fail(PM_EINVAL, "bad sizes");
     if (!best_out || (B > 0 && (!J || !theta || !buckets))) return fail(PM_EINVAL, "NULL buffer");
-    hipLaunchKernelGGL(k_best, dim3(Bt->P), dim3(256), 0, as_stream(stream), J, B, n_dev, iters, theta,
+    hipLaunchKernelGGL(k_best, dim3(Bt->P), dim3(kBestThreads), 0, as_stream(stream), J, B, n_dev, iters, theta,
                        Bt->alphabet, Bt->l, best_out, consensus_out, Bt->inst, buckets);
     PM_LAUNCHED();
     return PM_OK;

@@ -416,6 +416,60 @@ def test_em_theta_equal_background_gives_zero():
         assert np.all(np.abs(LL[:, 0]) <= (0.0 if prec != pm.PM_F16X2 else 1e-9))
 
 
+
+def _first_largest(Jf):
+    """The winning index by definition: the largest final objective, the
+    smallest index among equals, NaN skipped, -1 when nothing is left."""
+    ok = ~np.isnan(Jf)
+    if not ok.any():
+        return -1
+    return int(np.flatnonzero(ok & (Jf == Jf[ok].max()))[0])
+
+
+BEST_CASES = [
+    # name, buckets, valid buckets (None: all), final-J pattern
+    ("empty", 0, None, "rand"),
+    ("one", 1, None, "rand"),
+    ("ragged tail", 8 * 1024 + 37, None, "rand"),
+    ("ties over the whole range", 100_003, None, "ties"),
+    ("nan and -inf", 5_000, None, "nan"),
+    ("all nan", 300, None, "allnan"),
+    ("all -inf", 300, None, "allninf"),
+    ("n_dev below capacity", 20_000, 12_345, "ties"),
+    ("(18,6) bucket count", 89_296, None, "ties"),
+]
+
+
+@pytest.mark.parametrize("case", BEST_CASES, ids=[c[0] for c in BEST_CASES])
+def test_em_best_is_the_first_largest_final_objective(case):
+    name, B, nvalid, pattern = case
+    A, l, iters = 4, 12, 3
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    Jf = {"rand": lambda: rng.standard_normal(B),
+          "ties": lambda: rng.integers(0, 40, B).astype(np.float64),
+          "nan": lambda: np.where(rng.random(B) < 0.3, np.nan,
+                                  np.where(rng.random(B) < 0.3, -np.inf, rng.integers(0, 9, B).astype(np.float64))),
+          "allnan": lambda: np.full(B, np.nan),
+          "allninf": lambda: np.full(B, -np.inf)}[pattern]()
+    # earlier iterations hold larger values: only the final column may count
+    J = np.concatenate([np.full((B, iters), 1e300), Jf[:, None]], axis=1)
+    theta = rng.random((B, A, l))
+    n = B if nvalid is None else nvalid
+    ref = _first_largest(Jf[:n])
+    say("em_best", name, B, n, ref)
+    d_J = torch.from_numpy(np.ascontiguousarray(J)).cuda()
+    d_th = torch.from_numpy(theta).cuda()
+    d_n = None if nvalid is None else torch.tensor([nvalid], dtype=torch.int64, device="cuda")
+    best = torch.full((1,), -7, dtype=torch.int64, device="cuda")
+    cons = torch.full((l + 1,), 0xFF, dtype=torch.uint8, device="cuda")
+    pm.em_best(d_J, B, d_n, iters, d_th, A, l, best, cons)
+    torch.cuda.synchronize()
+    assert int(best.item()) == ref
+    got = bytes(cons.cpu().numpy())
+    want = ("".join("ACTG"[c] for c in theta[ref].argmax(axis=0)).encode() if ref >= 0 else bytes(l)) + b"\0"
+    assert got == want
+
+
 # ------------------------------------------------------------------ end to end
 def test_projection_run_fig1_toy():
     """Example 1: PROJECTION + EM on Fig. 1 returns ATGCAACT at Fig. 2's sites."""
