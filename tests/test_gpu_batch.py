@@ -177,6 +177,60 @@ def test_batch_em_and_best_match_oracle(case, prec):
         assert multi >= 1  # some instance spans several matrix-core workgroups
 
 
+
+def _first_largest(Jf):
+    """The winning index by definition: the largest final objective, the
+    smallest index among equals, NaN skipped, -1 when nothing is left."""
+    ok = ~np.isnan(Jf)
+    if not ok.any():
+        return -1
+    return int(np.flatnonzero(ok & (Jf == Jf[ok].max()))[0])
+
+
+def test_batch_best_is_each_instance_first_largest_final_objective():
+    """Per instance: the winner among that instance's buckets only, by the
+    pick rule, with crafted objectives (ties, NaN, -inf, an instance whose
+    objectives are all NaN, one with no bucket) and a valid count that cuts
+    an instance short."""
+    name, A, P, l, k, d, s = next(c for c in BATCH_CASES if c[1] == 4 and c[0].startswith("dna l=11"))
+    insts = _instances(name, P, l, k, d)
+    say("batch best", name)
+    B = _batch(insts, A, l, k)
+    Pp, nb_, nm_ = _pipeline(B, s, 1, 1.0, pm.PM_FP64, np.full(A, 0.25))
+    Pp.hash()
+    Pp.select()
+    torch.cuda.synchronize()
+    trial = u32(Pp.b.buckets)[:nb_, 0].astype(np.int64)
+    iters = 2
+    rng = np.random.default_rng(5)
+    Jf = rng.integers(0, 6, nb_).astype(np.float64)
+    Jf[rng.random(nb_) < 0.2] = np.nan
+    Jf[rng.random(nb_) < 0.1] = -np.inf
+    ranges = [np.nonzero((trial >= f) & (trial < f + m))[0] for f, m in zip(B.first_item, B.m)]
+    filled = [p for p in range(P) if len(ranges[p])]
+    Jf[ranges[filled[0]]] = np.nan
+    Jf[ranges[filled[1]]] = -np.inf
+    J = np.concatenate([np.full((nb_, iters), 1e300), Jf[:, None]], axis=1)
+    theta = rng.random((nb_, A, l))
+    d_J = torch.from_numpy(np.ascontiguousarray(J)).cuda()
+    d_th = torch.from_numpy(theta).cuda()
+    for nvalid in (nb_, nb_ - 5):
+        d_n = torch.tensor([nvalid], dtype=torch.int64, device="cuda")
+        best = torch.full((P,), -7, dtype=torch.int64, device="cuda")
+        cons = torch.full((P, l + 1), 0xFF, dtype=torch.uint8, device="cuda")
+        pm.em_best_batch(B, Pp.b.buckets, d_J, nb_, d_n, iters, d_th, best, cons)
+        torch.cuda.synchronize()
+        got, gcons = best.cpu().numpy(), cons.cpu().numpy()
+        for p in range(P):
+            r = ranges[p][ranges[p] < nvalid]
+            w = _first_largest(Jf[r]) if len(r) else -1
+            ref = int(r[w]) if w >= 0 else -1
+            assert int(got[p]) == ref, (nvalid, p)
+            want = ("".join("ACTG"[c] for c in theta[ref].argmax(axis=0)).encode() if ref >= 0 else bytes(l)) + b"\0"
+            assert bytes(gcons[p]) == want, (nvalid, p)
+    assert len(filled) < P  # the last instance has no bucket
+
+
 def test_batch_em_every_tile_shape_bit_identical():
     """The batch plan cuts every instance into workgroups of the tile shape's
     size (64 or 128 models); each shape gives the same bits, with instances
