@@ -303,18 +303,27 @@ __global__ void __launch_bounds__(256) k_profile(const ProfArgs a)
     const pm_inst I = a.inst ? a.inst[a.item_inst[bk.trial]] : a.one;
     const int64_t lm1 = a.l - 1;
     const uint32_t size = (int64_t)bk.first + bk.size <= a.cap_m ? bk.size : 0u;
-    for (uint32_t r = 0; r < size; ++r) {
-        const int64_t w = a.members[(int64_t)bk.first + r];
-        int lo = 0, hi = I.t;  // last sequence whose first window <= w
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (I.offsets[mid] - (int64_t)mid * lm1 <= w) lo = mid;
-            else hi = mid;
+    // up to 64 members at a time: lane r finds where member r starts, then
+    // every column lane reads the members' symbols one after another
+    for (uint32_t r0 = 0; r0 < size; r0 += 64) {
+        const uint32_t nr = size - r0 < 64u ? size - r0 : 64u;
+        int64_t Pm = 0;
+        if ((uint32_t)lane < nr) {
+            const int64_t w = a.members[(int64_t)bk.first + r0 + lane];
+            int lo = 0, hi = I.t;  // last sequence whose first window <= w
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (I.offsets[mid] - (int64_t)mid * lm1 <= w) lo = mid;
+                else hi = mid;
+            }
+            Pm = w + (int64_t)lo * lm1;
         }
-        const int64_t P = w + (int64_t)lo * lm1;
-        if (lane < a.l) {
-            const uint32_t code = a.A == 4 ? dna_sym(I.packed, P + lane) : prot_sym(I.packed, P + lane);
-            C[code * 32 + lane] += 1;
+        for (uint32_t r = 0; r < nr; ++r) {
+            const int64_t P = __shfl(Pm, (int)r);
+            if (lane < a.l) {
+                const uint32_t code = a.A == 4 ? dna_sym(I.packed, P + lane) : prot_sym(I.packed, P + lane);
+                C[code * 32 + lane] += 1;
+            }
         }
     }
     uint32_t *out = a.profile + b * a.A * a.l;

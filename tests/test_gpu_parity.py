@@ -193,6 +193,7 @@ SELECT_CASES = [
     ("dna ragged s=2", 4, 12, 6, 2),
     ("dna s=1 every key", 4, 9, 4, 1),
     ("protein s=2", 20, 9, 2, 2),
+    ("dna k=1 buckets of more than 128 members", 4, 8, 1, 3),
 ]
 
 
@@ -212,6 +213,8 @@ def test_select_profile_theta0_bit_exact(case):
     ref = oracle.Seqs(A, seqs)
     RK, RN = oracle.hash_trials(ref, l, k, masks)
     rbk, rmem, (rnb, rnm), _ = oracle.select(ref, l, k, RK, RN, s)
+    if "more than 128" in name:
+        assert rbk[:, 2].min() > 128  # profiles read members 64 at a time
     say("select", name)
     S = pm.Seqs(A, seqs)
     bk, mem, nout, (nb_, nm_), st, cap_b, cap_m = _select_gpu(S, l, k, s, RK, RN)
