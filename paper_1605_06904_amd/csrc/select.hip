@@ -330,22 +330,23 @@ __global__ void __launch_bounds__(256) k_profile(const ProfArgs a)
     for (int i = lane; i < a.A * a.l; i += 64) out[i] = C[(i / a.l) * 32 + (i % a.l)];
 }
 
+// one thread per (bucket, column): the bucket's size from column 0, then the
+// column's A letters
 __global__ void k_theta_init(const uint32_t *__restrict__ prof, const int64_t *n_dev, int64_t B, int A,
                              int l, const double *__restrict__ bg, double beta, double *__restrict__ th)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per = (int64_t)A * l;
-    const int64_t b = g / per;
+    const int64_t b = g <= 0xffffffffll ? (int64_t)((uint32_t)g / (uint32_t)l) : g / l;
     int64_t nvalid = n_dev ? *n_dev : B;
     if (nvalid > B) nvalid = B;
     if (b >= nvalid) return;
-    const int rem = (int)(g - b * per);
-    const int c = rem / l, p = rem % l;
+    const int p = (int)(g - b * l);
+    const int64_t per = (int64_t)A * l;
     const uint32_t *P = prof + b * per;
+    double *T = th + b * per;
     double size = 0;
     for (int cc = 0; cc < A; ++cc) size += P[cc * l];
-    th[g] = (P[rem] + beta * bg[c]) / (size + beta);
-    (void)p;
+    for (int c = 0; c < A; ++c) T[c * l + p] = (P[c * l + p] + beta * bg[c]) / (size + beta);
 }
 
 }  // namespace pm
@@ -514,7 +515,7 @@ extern "C" int theta_init(int32_t alphabet, int32_t l, const uint32_t *profile, 
     if (B < 0 || beta < 0) return fail(PM_EINVAL, "need B >= 0 and beta >= 0");
     if (B == 0) return PM_OK;
     if (!profile || !bg || !theta0) return fail(PM_EINVAL, "NULL buffer");
-    const int64_t total = B * alphabet * l;
+    const int64_t total = B * l;
     const int threads = 256;
     hipLaunchKernelGGL(k_theta_init, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0,
                        as_stream(stream), profile, n_dev, B, alphabet, l, bg, beta, theta0);
