@@ -122,3 +122,26 @@ def expected_complete_loglik(seqs: Sequence[str], l: int, post: Sequence[Sequenc
                 continue
             q += w * sum(math.log(theta[S[a + p]][p]) for p in range(l))
     return q
+
+
+def oops_mstep(seqs: Sequence[str], l: int, post: Sequence[Sequence[float]], bg: Dict[str, float],
+               beta: float) -> Dict[str, List[float]]:
+    """One M-step on letters: the expected count of each letter in each column
+    (every start weighted by its posterior), smoothed by beta * bg and divided
+    by the column's total mass t + beta (Sec. 5.1 names EM; the update is the
+    textbook one for a multinomial column under a Dirichlet prior)."""
+    out = {c: [beta * bg[c]] * l for c in bg}
+    for S, ps in zip(seqs, post):
+        for a, w in enumerate(ps):
+            for p in range(l):
+                out[S[a + p]][p] += w
+    tot = len(seqs) + beta
+    return {c: [v / tot for v in col] for c, col in out.items()}
+
+
+def oops_objective(seqs: Sequence[str], l: int, theta: Dict[str, List[float]], bg: Dict[str, float],
+                   beta: float) -> float:
+    """The objective EM climbs: the OOPS log-likelihood ratio (explicit
+    products) plus the log prior beta * sum_c bg_c sum_p ln theta_c[p]."""
+    pri = sum(bg[c] * math.log(theta[c][p]) for c in bg for p in range(l))
+    return oops_loglik_ratio(seqs, l, theta, bg) + beta * pri

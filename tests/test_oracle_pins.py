@@ -418,3 +418,89 @@ def test_seeded_masks_are_uniform_k_subsets():
     np.testing.assert_allclose(freq, k / l, atol=0.035)
     assert np.array_equal(ms, oracle.masks_from_seed(12345, l, k, m))
     assert not np.array_equal(ms, oracle.masks_from_seed(12346, l, k, m))
+
+
+# ------------------------------------------------ theta^0 with pseudocounts
+def test_theta0_pseudocounts_by_hand(fig1):
+    """Sec. 5.1 / Fig. 4 with the pseudocount reading theta0 = (f + beta bg) /
+    (size + beta), values worked out by hand from Fig. 2's profile (f = 7, 6,
+    1 or 0 of size 7).  Uniform bg 0.25, beta = 1: 7.25/8, 6.25/8, 1.25/8,
+    0.25/8.  A non-uniform bg (A .1, C .2, T .3, G .4) with beta = 2 makes each
+    letter's own bg visible: column 1 (all A) gives A 7.2/9, C 0.4/9, T 0.6/9,
+    G 0.8/9."""
+    l = 8
+    starts = [7, 18, 2, 4, 30, 26, 14]
+    S = oracle.Seqs(DNA, fig1)
+    cum = np.concatenate([[0], np.cumsum([len(x) - l + 1 for x in fig1])])
+    members = np.array([cum[i] + a for i, a in enumerate(starts)], dtype=np.uint32)
+    prof = oracle.profile(S, l, np.array([[0, 0, 7, 0]], dtype=np.uint32), members)
+    L = oracle.letters(DNA)
+    th = oracle.theta0(prof, np.full(4, 0.25), 1.0)[0]
+    by_hand = {  # Fig. 2 rows: A 7 0 0 0 6 7 0 0 / T 0 7 0 0 0 0 0 6 / C 0 0 0 6 1 0 7 0 / G 0 0 7 1 0 0 0 1
+        "A": [7.25, .25, .25, .25, 6.25, 7.25, .25, .25],
+        "T": [.25, 7.25, .25, .25, .25, .25, .25, 6.25],
+        "C": [.25, .25, .25, 6.25, 1.25, .25, 7.25, .25],
+        "G": [.25, .25, 7.25, 1.25, .25, .25, .25, 1.25],
+    }
+    for ch, row in by_hand.items():
+        np.testing.assert_allclose(th[L.index(ch)], np.array(row) / 8.0, rtol=1e-15, atol=0)
+    bg = np.array([0.1, 0.2, 0.3, 0.4])  # code order A C T G
+    th2 = oracle.theta0(prof, bg, 2.0)[0]
+    np.testing.assert_allclose(th2[:, 0], [7.2 / 9, 0.4 / 9, 0.6 / 9, 0.8 / 9], rtol=1e-15)
+    # column 4 (1-based 5): A 6, C 1 -> A 6.2/9, C 1.4/9, T 0.6/9, G 0.8/9
+    np.testing.assert_allclose(th2[:, 4], [6.2 / 9, 1.4 / 9, 0.6 / 9, 0.8 / 9], rtol=1e-15)
+
+
+def test_example1_objective_at_beta_one(fig1):
+    """Example 1 at beta = 1, bg = 0.25, EM from the ATGAC bucket.  The
+    oracle's J of theta^0 .. theta^5 equals a letter-level EM written with
+    explicit products (no log-odds, no log-sum-exp, dictionaries of letters),
+    and the values 19.806893 (theta^0) and 19.806909 (theta^5) obtained by an
+    independent computation on the Fig. 1 data.  The plain LLR dips
+    (39.702425 -> 39.695728) while J rises: the monotone quantity is J."""
+    l, k, s, beta = 8, 5, 4, 1.0
+    bg = np.full(4, 0.25)
+    r = oracle.run(fig1, DNA, l, k, s, np.array([TOY_MASK_READ]), iters=5, beta=beta, bg=bg)
+    names = [_key_to_string(int(b[1]), k, DNA) for b in r["buckets"]]
+    b = names.index("ATGAC")
+    J, LL = r["J"][b], r["llr"][b]
+    assert round(J[0], 6) == 19.806893 and round(J[5], 6) == 19.806909
+    assert round(LL[0], 6) == 39.702425 and round(LL[5], 6) == 39.695728
+    L = oracle.letters(DNA)
+    bgd = {c: 0.25 for c in "ACGT"}
+    th = _as_dict(r["theta0"][b], DNA)
+    for it in range(6):
+        np.testing.assert_allclose(J[it], brute.oops_objective(fig1, l, th, bgd, beta), rtol=1e-12)
+        post = [brute.oops_posterior(x, l, th, bgd) for x in fig1]
+        th = brute.oops_mstep(fig1, l, post, bgd, beta)
+    # theta^5 itself
+    got = r["theta"][b]
+    th5 = _as_dict(r["theta0"][b], DNA)
+    for _ in range(5):
+        th5 = brute.oops_mstep(fig1, l, [brute.oops_posterior(x, l, th5, bgd) for x in fig1], bgd, beta)
+    for c in "ACGT":
+        np.testing.assert_allclose(got[L.index(c)], th5[c], rtol=1e-12)
+
+
+def test_best_and_consensus_tie_rules():
+    """Sec. 5.1 (highest objective wins) and Sec. 2 (consensus ties may go
+    either way): the reading taken is the lowest bucket index among equal J
+    and the lowest code (A C T G order) among equal probabilities."""
+    L = oracle.letters(DNA)
+    th = np.zeros((3, 4, 3))
+    # model 1 (the winner): column 0 ties A/G, column 1 ties C/T, column 2 ties T/G
+    for b in range(3):
+        th[b, L.index("A"), 0] = th[b, L.index("G"), 0] = 0.4
+        th[b, L.index("C"), 0] = th[b, L.index("T"), 0] = 0.1
+        th[b, L.index("C"), 1] = th[b, L.index("T"), 1] = 0.45
+        th[b, L.index("A"), 1] = th[b, L.index("G"), 1] = 0.05
+        th[b, L.index("T"), 2] = th[b, L.index("G"), 2] = 0.35
+        th[b, L.index("A"), 2] = th[b, L.index("C"), 2] = 0.15
+    th[2, L.index("G"), 0] = 0.41  # model 2 would read G in column 0
+    th[2, L.index("A"), 0] = 0.39
+    J = np.array([[0.0, 1.0], [0.0, 3.0], [0.0, 3.0]])
+    b, cons = oracle.best(J, th)
+    assert b == 1 and cons == "ACT"
+    J[1, 1] = np.nan
+    b, cons = oracle.best(J, th)
+    assert b == 2 and cons == "GCT"
