@@ -54,16 +54,21 @@ extern "C" {
 #define PM_DNA 4
 #define PM_PROTEIN 20
 
-/* EM arithmetic (em_refine `precision`) */
+/* EM arithmetic (em_refine `precision`).  In every form the per-sequence
+ * log-sum-exp is FP64: each window's term exp(s_ia - ref) is formed in the
+ * form's precision, converted to FP64 and summed in FP64 (lane partials
+ * combined in FP64), the logarithm is FP64, and LLR, J and the final
+ * comparison of models are FP64. */
 #define PM_FP64 0  /* every step in FP64 */
-#define PM_FP32 1  /* scores, posteriors and counts in FP32; log-sum-exp and J in FP64 */
+#define PM_FP32 1  /* scores, exponentials, posteriors and counts in FP32 */
 #define PM_F16X2 2 /* DNA only: E- and M-step on FP16 matrix cores with every non-0/1
                       operand split into two FP16 halves (about 22 significant bits,
-                      exact products, FP32 sums); log-sum-exp and J in FP64 */
-#define PM_F16 3   /* DNA only, the precision form: the same contractions with one FP16
-                      value per operand (11 significant bits), FP32 accumulation,
-                      log-sum-exp and J in FP64; results carry FP16-level error against
-                      FP64, which the caller measures and states */
+                      exact products, FP32 sums) */
+#define PM_F16 3   /* the precision form, DNA and protein (l <= 24, t <= 64,
+                      n_i <= 2048 for protein): the same contractions with one FP16
+                      value per operand (11 significant bits) and FP32 accumulation;
+                      results carry FP16-level error against FP64, which the caller
+                      measures and states */
 
 /* Encoded sequences.  Host fields describe the device arrays. */
 typedef struct pm_seqs {

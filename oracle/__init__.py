@@ -62,8 +62,16 @@ def lib():
         L.or_masks.argtypes = [_u64, _i32, _i32, _i32, _P]
         L.or_letter.restype = C.c_char
         L.or_letter.argtypes = [_i32, _i32]
+        L.or_set_threads.restype = _i32
+        L.or_set_threads.argtypes = [_i32]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops (n <= 0: unchanged); returns the
+    number in use."""
+    return int(lib().or_set_threads(n))
 
 
 def _p(a: np.ndarray):

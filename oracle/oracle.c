@@ -20,6 +20,22 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the OpenMP loops below (timing of the CPU baseline); returns the
+ * number in use afterwards (1 without OpenMP). */
+int or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------------- */
 /* Sec. 2 (notation) and Sec. 6 (integer equivalent of a k-mer): the DNA

@@ -132,14 +132,16 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
         for (int i = wv; i < t; i += kEmWaves) {
             const int64_t s0 = O[i];
             const int64_t L = O[i + 1] - s0 - l + 1;
-            T mx = ninf<T>(), sm = 0, bv = ninf<T>();
+            // online log-sum-exp, one exponential per window; the exponentials
+            // are in T, their running sum is FP64 in both precisions
+            T mx = ninf<T>(), bv = ninf<T>();
+            double sm = 0;
             int64_t ba = 0;
             for (int64_t x = lane; x < L; x += 64) {
                 const T s = score_at<T, A>(W, s0 + x, Wt, l);
-                // online log-sum-exp, one exponential per window
                 const bool up = s > mx;
                 const T e = ex(up ? mx - s : s - mx);
-                sm = up ? sm * e + (T)1 : (s > ninf<T>() ? sm + e : sm);
+                sm = up ? sm * (double)e + 1.0 : (s > ninf<T>() ? sm + (double)e : sm);
                 mx = up ? s : mx;
                 if (last && s > bv) {
                     bv = s;
@@ -147,9 +149,9 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
                 }
             }
             const T M = wave_max(mx);
-            const T part = mx > ninf<T>() ? sm * ex(mx - M) : (T)0;
-            const T Ssum = wave_sum(part);
-            const double lse = (double)M + log((double)Ssum);
+            const double part = mx > ninf<T>() ? sm * (double)ex(mx - M) : 0.0;
+            const double Ssum = wave_sum(part);
+            const double lse = (double)M + log(Ssum);
             llr_w += lse - log((double)L);
             if (last) {
                 if (a.sites) {

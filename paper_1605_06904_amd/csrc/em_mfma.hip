@@ -13,8 +13,11 @@
 // operand, so every product is exact and the operand carries about 22
 // significant bits; sums are FP32.  The single-FP16 form (SPLIT = false) keeps
 // only hi: half the matrix-core work, 11-bit operands.  Scores are kept in log2 units (W scaled
-// by log2 e) so the softmax uses the hardware exp2; the per-sequence
-// log-sum-exp and the objective are formed in FP64.
+// by log2 e) so the softmax uses the hardware exp2.  The per-sequence
+// log-sum-exp is FP64: every lane converts each of its posterior terms
+// 2^(S - ref) (FP32 exp2 of an FP32 score) to FP64 and adds it to an FP64
+// running sum, the four lane groups are combined with FP64 shuffles and the
+// logarithm is FP64; so are the objective and the final comparison.
 //
 // Lane layout of one 16x16x32 MFMA (lane L, r = L % 16, g = L / 16):
 //   A operand: row r, the g-th group of 8 contraction indices;
@@ -32,6 +35,8 @@
 // only when a score passes it by more than kSlack, so the common path needs
 // neither a cross-lane maximum nor a rescale.  Posteriors enter the M-step as
 // 2^(S - ref + kPOff) <= 2^(kPOff + kSlack) = 2^15, inside the FP16 range.
+// The reference moves by whole numbers, so every rescale (of the count
+// accumulators and of the FP64 sums) is an exact power of two.
 //
 // Work split: a workgroup of four waves takes 64 G models of one instance, G
 // groups of 16 per wave; the groups of a wave share every A operand (the
@@ -221,8 +226,7 @@ __device__ __forceinline__ void build_tables(const uint32_t *W, int64_t nw, int6
 struct SeqState {
     float4v neg;  // kPOff - mref in every component: the E-step accumulators' start
     float mref;   // reference (log2 units) of the scores
-    float srun;   // final E-step: this lane's share of sum 2^(S - mref + kPOff)
-                  // (the other sweeps take the sum from the M-step counts)
+    double srun;  // this lane's share of sum 2^(S - mref + kPOff), in FP64
     float bestv;  // final E-step: best score and window of this lane
     int besti;
 };
@@ -299,9 +303,10 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T
             float tm = fmaxf(fmaxf(fmaxf(S[0], S[1]), fmaxf(S[2], S[3])), fmaxf(fmaxf(S[4], S[5]), fmaxf(S[6], S[7])));
             tm = fmaxf(tm, __shfl_xor(tm, 16));
             tm = fmaxf(tm, __shfl_xor(tm, 32));
-            const float d = tm > kPOff + kSlack ? tm - kPOff : 0.f;
+            // a whole number of binades, so that the rescales below are exact
+            const float d = tm > kPOff + kSlack ? ceilf(tm - kPOff) : 0.f;
             const float al = __builtin_amdgcn_exp2f(-d);
-            if (LAST) st[q].srun *= al;
+            st[q].srun *= (double)al;
             if (!LAST)
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) O[q][mt] *= al;
@@ -314,7 +319,13 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T
         float P[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) P[u] = __builtin_amdgcn_exp2f(S[u]);
-        if (LAST) st[q].srun += ((P[0] + P[1]) + (P[2] + P[3])) + ((P[4] + P[5]) + (P[6] + P[7]));
+        // the lane's eight terms, each converted to FP64, summed in FP64
+        {
+            double e[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) e[u] = (double)P[u];
+            st[q].srun += ((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7]));
+        }
         if (!LAST) {
             uint4 h;
             h.x = pack_hi(P[0], P[1]);
@@ -397,7 +408,7 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
         for (int mt = 0; mt < MT; ++mt) O[q][mt] = float4v{0.f, 0.f, 0.f, 0.f};
         // the reference starts at the lowest score the model can give
         const float n0 = kPOff - mlow[q];
-        st[q] = SeqState{float4v{n0, n0, n0, n0}, mlow[q], 0.f, -INFINITY, 0};
+        st[q] = SeqState{float4v{n0, n0, n0, n0}, mlow[q], 0.0, -INFINITY, 0};
     }
     for (int a0 = 0; a0 < L; a0 += 32 * PPB) {
         PairTables<MT> *T = tabs + PPB * parity;
@@ -429,22 +440,16 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
     }
 #pragma unroll
     for (int q = 0; q < G; ++q) {
-        float sr;
-        if (LAST) {
-            sr = st[q].srun;
-            sr += __shfl_xor(sr, 16);
-            sr += __shfl_xor(sr, 32);
-        } else {
-            // every window has one letter at position 0, so the counts of
-            // position 0 (lane group 0's first row tile) sum to sum_w 2^(S_w - ref)
-            const float4v c0 = O[q][0];
-            sr = __shfl((c0[0] + c0[1]) + (c0[2] + c0[3]), r);
-        }
+        // the model's sum over the sequence's windows: the four lane groups'
+        // FP64 partials combined in FP64
+        double sr = st[q].srun;
+        sr += __shfl_xor(sr, 16);
+        sr += __shfl_xor(sr, 32);
         const double ln2 = 0.6931471805599453;
-        const double lse = ((double)st[q].mref - (double)kPOff) * ln2 + log((double)sr);
+        const double lse = ((double)st[q].mref - (double)kPOff) * ln2 + log(sr);
         llr[q] += lse - log((double)L);
         if (!LAST) {
-            const float inv = 1.0f / sr;
+            const float inv = (float)(1.0 / sr);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 float4v *dst = reinterpret_cast<float4v *>(&acc[q][r][4 * mt + g][0]);

@@ -6,8 +6,11 @@
 // them padded to KS steps of 32.  M-step counts: C = OneHot^T . Z with the
 // contraction over 32 windows (two E tiles), 2 KS row tiles of 16 kappa rows.
 // v_mfma_f32_16x16x32_f16, one FP16 value per non-0/1 operand (the log-odds W
-// and the posteriors Z), FP32 accumulation; per-sequence log-sum-exp combined
-// across lanes in FP32, LLR and J in FP64.
+// and the posteriors Z), FP32 accumulation.  The per-sequence log-sum-exp is
+// FP64: each lane keeps an FP64 sum of its terms 2^(S - ref) against a
+// whole-number reference (so that moving it rescales the sum exactly), the
+// lanes of a model are combined in FP64 and the logarithm is FP64; LLR and J
+// are FP64.
 //
 // A 20-letter model has 20 l count rows, too many to keep one sequence's
 // unnormalised counts beside the running totals, so every iteration first
@@ -208,7 +211,10 @@ __global__ void __launch_bounds__(64 * kPW, 2) k_em_prot(const EmProtArgs a)
         for (int i = 0; i < t; ++i) {
             int L;
             unpack(i, L);
-            float mx = -INFINITY, sm = 0.f, bestv = -INFINITY;
+            // mx: a whole number at or above every score seen by this lane
+            // (-inf before the first); sm: FP64 sum of 2^(v - mx)
+            float mx = -INFINITY, bestv = -INFINITY;
+            double sm = 0.0;
             int besti = 0;
             for (int a0 = 0; a0 < L; a0 += 32) {
                 __syncthreads();
@@ -222,11 +228,11 @@ __global__ void __launch_bounds__(64 * kPW, 2) k_em_prot(const EmProtArgs a)
                     const float v = q < 4 ? S0[q & 3] : S1[q & 3];
                     if (w < L) {
                         if (v > mx) {
-                            sm = sm * __builtin_amdgcn_exp2f(mx - v) + 1.f;
-                            mx = v;
-                        } else {
-                            sm += __builtin_amdgcn_exp2f(v - mx);
+                            const float nm = ceilf(v);
+                            sm = mx > -INFINITY ? ldexp(sm, (int)(mx - nm)) : 0.0;
+                            mx = nm;
                         }
+                        sm += (double)__builtin_amdgcn_exp2f(v - mx);
                         if (last && v > bestv) {
                             bestv = v;
                             besti = w;
@@ -234,16 +240,17 @@ __global__ void __launch_bounds__(64 * kPW, 2) k_em_prot(const EmProtArgs a)
                     }
                 }
             }
-            // combine the four lanes of each model
+            // combine the four lanes of each model in FP64 (the references are
+            // whole numbers: the rescales are exact)
             float M = mx;
             M = fmaxf(M, __shfl_xor(M, 16));
             M = fmaxf(M, __shfl_xor(M, 32));
-            float part = mx > -INFINITY ? sm * __builtin_amdgcn_exp2f(mx - M) : 0.f;
+            double part = mx > -INFINITY ? ldexp(sm, (int)(mx - M)) : 0.0;
             part += __shfl_xor(part, 16);
             part += __shfl_xor(part, 32);
-            const float lz = M + __builtin_amdgcn_logf(part);  // log2 of the sum of 2^S
-            if (g == 0) lzs[wv][r][i] = lz;
-            llr += (double)lz * 0.6931471805599453 - log((double)L);
+            const double lz = (double)M + log2(part);  // log2 of the sum of 2^S
+            if (g == 0) lzs[wv][r][i] = (float)lz;
+            llr += lz * 0.6931471805599453 - log((double)L);
             if (last && a.sites) {
 #pragma unroll
                 for (int o = 16; o <= 32; o <<= 1) {

@@ -373,15 +373,44 @@ def test_em_matches_oracle(case, prec):
         _sites_valid(sites, rsites, rth, ref, l, bg, 1e-5)
 
 
-@pytest.mark.parametrize("case", EM_CASES, ids=[c[0] for c in EM_CASES])
+F16_CASES = EM_CASES + [
+    # the protein matrix-core kernel at the (20,6) workload's shape (20 l = 400
+    # contraction rows in 13 steps of 32, counts of all 26 row tiles in
+    # registers), at l = 22 (the largest single sweep) and past it, where the
+    # count rows are split over two sweeps (l = 23, 24); B = 70 spans two
+    # workgroups of 64 models with a ragged tail
+    ("protein l=20 c4 shape", 41, 20, 9, 160, 20, 6, 70, 3, 1.0),
+    ("protein l=22", 42, 20, 5, 120, 22, 6, 20, 2, 1.0),
+    ("protein l=23 two sweeps", 43, 20, 6, 140, 23, 6, 20, 3, 1.0),
+    ("protein l=24 two sweeps", 44, 20, 7, 100, 24, 7, 70, 2, 0.5),
+]
+
+
+def _fp16_eval_bound(theta, bg, t):
+    """Largest error of an objective that the single-FP16 form evaluates at a
+    model theta it holds exactly (FP64): each log-odds entry W = ln(theta/bg)
+    is rounded once to FP16 (relative error at most 2^-11, plus 2^-24 for the
+    FP32 step before it), the l products are exact and summed in FP32, so a
+    window's score moves by at most (2^-11 + 2^-22) sum_p max_c |W_cp|; the
+    log-sum-exp of a sequence is 1-Lipschitz in its scores, and its FP32
+    exponentials carry 2^-22 relative error each, summed in FP64; t sequences
+    add up."""
+    W = np.log(theta) - np.log(bg)[None, :, None]
+    per_window = np.abs(W).max(axis=1).sum(axis=1)
+    return t * ((2.0 ** -11 + 2.0 ** -22) * per_window + 2.0 ** -21)
+
+
+@pytest.mark.parametrize("case", F16_CASES, ids=[c[0] for c in F16_CASES])
 def test_em_single_fp16_form_error_against_fp64(case):
-    """The precision form (one FP16 value per operand; the protein case runs
-    the 20-letter one-hot kernel): its error against the FP64 oracle is
-    stated, not held to 1e-5.  Bound from the arithmetic: each
-    log-odds entry carries a relative rounding of at most 2^-11, a score sums
-    l of them, so |dS| <= l * 2^-11 * max|W| per window; J moves by at most
-    t times that (log-sum-exp is 1-Lipschitz in the scores) plus the effect of
-    the M-step rounding of the posteriors (2^-11 relative per term)."""
+    """The precision form (one FP16 value per operand; protein cases run the
+    20-letter one-hot kernel) against the FP64 oracle.  What the arithmetic
+    fixes is asserted: the objective of theta^0 (held exactly on both sides)
+    and the objective the kernel reports for its own final model theta^I
+    (returned in FP64), each within the evaluation bound of _fp16_eval_bound
+    of the oracle's FP64 value at that same model; every column of theta^I on
+    the simplex.  The drift of later iterates from the oracle's trajectory
+    (the FP16 rounding of the posteriors feeds each M-step) has no a-priori
+    bound and is stated per case, not asserted."""
     name, seed, A, t, n, l, d, B, iters, beta = case
     if n is None:
         rng = np.random.default_rng(seed)
@@ -396,15 +425,22 @@ def test_em_single_fp16_form_error_against_fp64(case):
     say("em single fp16", name)
     S = pm.Seqs(A, inst.seqs)
     th, J, LL, sites, best, cons = _em_gpu(S, l, th0, bg, iters, beta, pm.PM_F16)
-    # first E-step (theta^0 exact on both sides): the score bound alone
-    W = np.log(th0) - np.log(bg)[None, :, None]
-    dS = l * 2.0 ** -11 * np.abs(W).max(axis=(1, 2)) * 1.5
-    assert np.all(np.abs(J[:, 0] - rJ[:, 0]) <= t * dS + 1e-9), (np.abs(J[:, 0] - rJ[:, 0]), t * dS)
+    assert np.all(np.isfinite(J)) and np.all(th > 0)
+    np.testing.assert_allclose(th.sum(axis=1), 1.0, rtol=0, atol=1e-12)
+    # J(theta^0): theta^0 is exact on both sides
+    b0 = _fp16_eval_bound(th0, bg, t)
+    assert np.all(np.abs(J[:, 0] - rJ[:, 0]) <= b0), (np.abs(J[:, 0] - rJ[:, 0]) / b0).max()
+    # J(theta^I) at the kernel's own theta^I, against the oracle's FP64 value there
+    _, eJ, eLL, _ = oracle.em(ref, l, np.ascontiguousarray(th), bg, 0, beta)
+    bI = _fp16_eval_bound(th, bg, t)
+    assert np.all(np.abs(J[:, -1] - eJ[:, 0]) <= bI), (np.abs(J[:, -1] - eJ[:, 0]) / bI).max()
+    assert np.all(np.abs(LL[:, -1] - eLL[:, 0]) <= bI)
     rel = np.abs(J - rJ) / np.maximum(1.0, np.abs(rJ))
-    print(f"[precision] {name}: max |dJ|/|J| = {rel.max():.3e}, mean = {rel.mean():.3e}, "
+    print(f"[precision] {name}: J(theta^0) error {np.abs(J[:, 0] - rJ[:, 0]).max():.3e} "
+          f"(bound {b0.min():.3e}..{b0.max():.3e}); J(theta^I) evaluation error "
+          f"{np.abs(J[:, -1] - eJ[:, 0]).max():.3e} (bound {bI.min():.3e}..{bI.max():.3e}); "
+          f"trajectory drift max |dJ|/|J| = {rel.max():.3e}, mean = {rel.mean():.3e}, "
           f"max |dtheta| = {np.abs(th - rth).max():.3e}", flush=True)
-    assert rel.max() <= 2e-2
-    assert np.abs(th - rth).max() <= 2e-2
 
 
 def test_em_theta_equal_background_gives_zero():
