@@ -397,39 +397,61 @@ int triage_merge_best(int32_t P, int32_t alphabet, int32_t l, int32_t iters, con
                       const int64_t *index2, const double *J2, const double *theta2, int64_t *best_out,
                       char *consensus_out, void *stream);
 
-/* The whole path on one instance, host in, host out, synchronous.  This
- * convenience entry point allocates and frees its own device buffers. */
+/* ---- The whole path, host in, host out (Alg. 2 and Alg. 3 INPUT/OUTPUT) ---- */
 typedef struct pm_problem {
     int32_t alphabet;          /* PM_DNA or PM_PROTEIN */
-    int32_t t;                 /* number of sequences */
-    const char *const *seqs;   /* host [t] strings */
-    const int32_t *n;          /* host [t] lengths */
-    int32_t l, d;              /* motif length, mutations (d only feeds auto parameters) */
-    int32_t k, s, m;           /* <= 0: chosen by pm_auto_params */
-    const uint32_t *masks;     /* host [m] or NULL: drawn by pm_masks_from_seed(seed) */
+    int32_t t;                 /* number of sequences S_1..S_t */
+    const char *const *seqs;   /* host [t] strings (need not be NUL-ended) */
+    const int32_t *n;          /* host [t] lengths, each >= l */
+    int32_t l, d;              /* motif length, mutations (d only feeds the automatic parameters) */
+    int32_t k, s, m;           /* projection size, threshold, trials; <= 0: chosen by
+                                  pm_auto_params (Sec. 5) */
+    const uint32_t *masks;     /* host [m] or NULL: drawn by pm_masks_from_seed(seed);
+                                  when given, m must be their number */
     uint64_t seed;
-    const double *bg;          /* host [|Sigma|] in code order, or NULL: input composition */
+    const double *bg;          /* host [|Sigma|] in code order (normalised here), or NULL:
+                                  the composition of the input (every letter must occur) */
 } pm_problem;
 
 typedef struct pm_options {
-    int32_t em_iters;   /* M-steps per model */
-    double beta;        /* pseudocount mass for theta^0 and the M-step */
-    int32_t precision;  /* PM_FP64 / PM_FP32 */
-    void *stream;
+    int32_t em_iters;          /* M-steps per model (then a final E-step) */
+    double beta;               /* pseudocount mass for theta^0 and the M-step */
+    int32_t precision;         /* PM_FP64, PM_FP32, PM_F16X2 or PM_F16 (protein PM_F16 only with
+                                  batched = 0 and triage = 0) */
+    int32_t batched;           /* 0: problems one after another through the single-instance
+                                  calls; 1: problems sharing alphabet, l, k, s and background run
+                                  as one batch each (projection_hash_batch ... em_best_batch) */
+    int32_t triage;            /* 1: learned bucket triage (DNA, l <= 21): EM of the
+                                  triage_frac best-scored buckets of each problem, fallback to all
+                                  its other buckets when the winner is weak, better winner kept */
+    double triage_frac;        /* fraction refined first; <= 0 means 0.05 */
+    const char *triage_weights;/* path of a weights file (format below); required with triage */
+    void *stream;              /* hipStream_t or NULL */
 } pm_options;
 
+/* Triage weights file, little-endian: the 8 bytes "PMTRIAG1"; int32
+ * PM_TRIAGE_PARAMS; int32 PM_TRIAGE_INPUTS; float params[PM_TRIAGE_PARAMS]
+ * (layout as for triage_train_step); float mu[PM_TRIAGE_INPUTS]; float
+ * sd[PM_TRIAGE_INPUTS]; double pooled fallback threshold; int32 n; then n
+ * records {int32 l; double threshold} of per-motif-length thresholds. */
+
 typedef struct pm_result {
-    char *consensus;      /* host [l+1], caller-owned */
-    int32_t *sites;       /* host [t], caller-owned, 0-based */
-    double *theta;        /* host [|Sigma|][l], caller-owned, or NULL */
-    double J, llr;        /* objective and log-likelihood ratio of the answer */
-    int32_t best_trial;
+    char *consensus;           /* host [l+1], caller-owned, or NULL; "" when nothing was enriched */
+    int32_t *sites;            /* host [t], caller-owned, or NULL: 0-based starts */
+    double *theta;             /* host [|Sigma|][l], caller-owned, or NULL */
+    double J, llr;             /* objective and log-likelihood ratio of the answer (-inf: none) */
+    int32_t best_trial;        /* trial of the winning bucket within its problem, -1: none */
     uint32_t best_key;
-    int64_t n_enriched;   /* buckets refined */
-    int32_t k, s, m;      /* parameters used */
+    int64_t n_enriched;        /* enriched buckets of the problem */
+    int64_t n_refined;         /* buckets refined by EM (all of them without triage) */
+    int32_t fallback_used;     /* 1 when triage fell back to refining the problem's other buckets */
+    int32_t k, s, m;           /* parameters used */
 } pm_result;
 
-int projection_run(const pm_problem *P, const pm_options *O, pm_result *R);
+/* Runs n_problems problems (R[p] answers P[p]); synchronous at return.  This
+ * convenience entry point allocates and frees its own device buffers.
+ * PM_EINVAL names the problem at fault in pm_last_error(). */
+int projection_run(const pm_problem *P, int32_t n_problems, const pm_options *O, pm_result *R);
 
 #ifdef __cplusplus
 }

@@ -77,13 +77,15 @@ class pm_problem(C.Structure):
 
 class pm_options(C.Structure):
     _fields_ = [("em_iters", C.c_int32), ("beta", C.c_double), ("precision", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("batched", C.c_int32), ("triage", C.c_int32), ("triage_frac", C.c_double),
+                ("triage_weights", C.c_char_p), ("stream", C.c_void_p)]
 
 
 class pm_result(C.Structure):
     _fields_ = [("consensus", C.c_char_p), ("sites", C.POINTER(C.c_int32)),
                 ("theta", C.POINTER(C.c_double)), ("J", C.c_double), ("llr", C.c_double),
                 ("best_trial", C.c_int32), ("best_key", C.c_uint32), ("n_enriched", C.c_int64),
+                ("n_refined", C.c_int64), ("fallback_used", C.c_int32),
                 ("k", C.c_int32), ("s", C.c_int32), ("m", C.c_int32)]
 
 
@@ -117,7 +119,7 @@ def lib():
                                 P, P, sz, P]),
         "pm_em_workspace": (sz, [C.POINTER(pm_seqs), i32, i32]),
         "em_best": (C.c_int, [P, i64, P, i32, P, i32, i32, P, P, P]),
-        "projection_run": (C.c_int, [C.POINTER(pm_problem), C.POINTER(pm_options),
+        "projection_run": (C.c_int, [C.POINTER(pm_problem), i32, C.POINTER(pm_options),
                                      C.POINTER(pm_result)]),
         "pm_batch_check": (C.c_int, [C.POINTER(pm_batch)]),
         "projection_hash_batch": (C.c_int, [C.POINTER(pm_batch), P, P, P, P, P]),
@@ -374,41 +376,75 @@ def triage_merge_best(P, alphabet, l, iters, best1, index1, J1, theta1, best2, i
                                    _ptr(consensus_out), _stream(stream)))
 
 
-def projection_run(seqs: Sequence[str], alphabet: int, l: int, d: int = 0, k: int = 0, s: int = 0,
-                   m: int = 0, masks=None, seed: int = 0, bg=None, em_iters: int = 5,
-                   beta: float = 1.0, precision: int = PM_FP64, stream=None) -> dict:
-    """Host in, host out: the whole path on one instance (synchronous)."""
+@dataclass
+class Problem:
+    """One motif-finding problem (Alg. 2 INPUT): sequences, alphabet, l, d;
+    k, s, m <= 0 are chosen by pm_auto_params; masks None are drawn from seed;
+    bg None is the input composition."""
+    seqs: Sequence[str]
+    alphabet: int
+    l: int
+    d: int = 0
+    k: int = 0
+    s: int = 0
+    m: int = 0
+    masks: object = None
+    seed: int = 0
+    bg: object = None
+
+
+def projection_run(problems, em_iters: int = 5, beta: float = 1.0, precision: int = PM_FP64,
+                   batched: bool = False, triage: bool = False, triage_frac: float = 0.05,
+                   triage_weights: Optional[str] = None, stream=None) -> list:
+    """Host in, host out: the whole path on every problem (synchronous).
+    `problems` is a Problem or a list of them; returns one dict per problem.
+    triage_weights defaults to the shipped weights file when triage is on."""
     import numpy as np
-    t = len(seqs)
-    raw = [x.encode("ascii") for x in seqs]
-    arr = (C.c_char_p * t)(*raw)
-    ns = (C.c_int32 * t)(*[len(x) for x in raw])
-    P = pm_problem()
-    P.alphabet, P.t, P.seqs, P.n = alphabet, t, C.cast(arr, C.POINTER(C.c_char_p)), ns
-    P.l, P.d, P.k, P.s, P.m, P.seed = l, d, k, s, m, seed
-    mk = None
-    if masks is not None:
-        mk = np.ascontiguousarray(masks, dtype=np.uint32)
-        P.masks = mk.ctypes.data_as(C.POINTER(C.c_uint32))
-        P.m = len(mk)
-    bgv = None
-    if bg is not None:
-        bgv = np.ascontiguousarray(bg, dtype=np.float64)
-        P.bg = bgv.ctypes.data_as(C.POINTER(C.c_double))
+    if isinstance(problems, Problem):
+        problems = [problems]
+    n = len(problems)
+    keep = []  # buffers the C structures point into
+    Ps = (pm_problem * n)()
+    Rs = (pm_result * n)()
+    outs = []
+    for q, (pr, P, R) in enumerate(zip(problems, Ps, Rs)):
+        t = len(pr.seqs)
+        raw = [x.encode("ascii") for x in pr.seqs]
+        arr = (C.c_char_p * t)(*raw)
+        ns = (C.c_int32 * t)(*[len(x) for x in raw])
+        keep += [raw, arr, ns]
+        P.alphabet, P.t, P.seqs, P.n = pr.alphabet, t, C.cast(arr, C.POINTER(C.c_char_p)), ns
+        P.l, P.d, P.k, P.s, P.m, P.seed = pr.l, pr.d, pr.k, pr.s, pr.m, pr.seed
+        if pr.masks is not None:
+            mk = np.ascontiguousarray(pr.masks, dtype=np.uint32)
+            keep.append(mk)
+            P.masks = mk.ctypes.data_as(C.POINTER(C.c_uint32))
+            P.m = len(mk)
+        if pr.bg is not None:
+            bgv = np.ascontiguousarray(pr.bg, dtype=np.float64)
+            keep.append(bgv)
+            P.bg = bgv.ctypes.data_as(C.POINTER(C.c_double))
+        cons = C.create_string_buffer(pr.l + 1)
+        sites = np.zeros(t, dtype=np.int32)
+        theta = np.zeros((pr.alphabet, pr.l), dtype=np.float64)
+        R.consensus = C.cast(cons, C.c_char_p)
+        R.sites = sites.ctypes.data_as(C.POINTER(C.c_int32))
+        R.theta = theta.ctypes.data_as(C.POINTER(C.c_double))
+        outs.append((cons, sites, theta))
     O = pm_options()
     O.em_iters, O.beta, O.precision = em_iters, beta, precision
+    O.batched, O.triage, O.triage_frac = int(bool(batched)), int(bool(triage)), triage_frac
+    if triage:
+        path = triage_weights or default_triage_bin_path()
+        O.triage_weights = path.encode()
     O.stream = _stream(stream) if stream is not None else None
-    cons = C.create_string_buffer(l + 1)
-    sites = np.zeros(t, dtype=np.int32)
-    theta = np.zeros((alphabet, l), dtype=np.float64)
-    R = pm_result()
-    R.consensus = C.cast(cons, C.c_char_p)
-    R.sites = sites.ctypes.data_as(C.POINTER(C.c_int32))
-    R.theta = theta.ctypes.data_as(C.POINTER(C.c_double))
-    _check(lib().projection_run(C.byref(P), C.byref(O), C.byref(R)))
-    return dict(consensus=cons.value.decode(), sites=sites, theta=theta, J=R.J, llr=R.llr,
-                best_trial=R.best_trial, best_key=R.best_key, n_enriched=R.n_enriched,
-                k=R.k, s=R.s, m=R.m)
+    _check(lib().projection_run(Ps, n, C.byref(O), Rs))
+    res = []
+    for R, (cons, sites, theta) in zip(Rs, outs):
+        res.append(dict(consensus=cons.value.decode(), sites=sites, theta=theta, J=R.J, llr=R.llr,
+                        best_trial=R.best_trial, best_key=R.best_key, n_enriched=R.n_enriched,
+                        n_refined=R.n_refined, fallback_used=bool(R.fallback_used), k=R.k, s=R.s, m=R.m))
+    return res
 
 
 # ----------------------------------------------------------------- device data
@@ -730,6 +766,11 @@ class Triage:
             meta = json.loads(str(z["meta"]))
             return cls(z["params"], z["mu"], z["sd"], float(z["threshold"]), device, meta)
 
+    def save_bin(self, path: str):
+        """The weights in the file format projection_run reads."""
+        write_triage_bin(path, self.params.cpu().numpy(), self.mu.cpu().numpy(), self.sd.cpu().numpy(),
+                         self.threshold, self.meta.get("thresholds_by_l", {}))
+
     def save(self, path: str):
         import json
         import numpy as np
@@ -750,6 +791,40 @@ class Triage:
 
 def default_triage_path() -> str:
     return os.path.join(PKG, "triage_weights.npz")
+
+
+def write_triage_bin(path: str, params, mu, sd, threshold: float, thresholds_by_l: dict):
+    """Triage weights in the format projection_run reads (include/projmotif.h):
+    "PMTRIAG1", the sizes, FP32 parameters, mu and sd, the pooled fallback
+    threshold and the per-motif-length thresholds."""
+    import struct
+    import numpy as np
+    per = {int(k): float(v) for k, v in thresholds_by_l.items()}
+    with open(path, "wb") as f:
+        f.write(b"PMTRIAG1")
+        f.write(struct.pack("<ii", PM_TRIAGE_PARAMS, PM_TRIAGE_INPUTS))
+        for a, n in ((params, PM_TRIAGE_PARAMS), (mu, PM_TRIAGE_INPUTS), (sd, PM_TRIAGE_INPUTS)):
+            v = np.ascontiguousarray(a, dtype="<f4").reshape(-1)
+            assert v.size == n
+            f.write(v.tobytes())
+        f.write(struct.pack("<di", float(threshold), len(per)))
+        for l in sorted(per):
+            f.write(struct.pack("<id", l, per[l]))
+
+
+def convert_triage_npz(npz_path: str, bin_path: str):
+    """The binary weights file of a training output (.npz)."""
+    import json
+    import numpy as np
+    with np.load(npz_path, allow_pickle=False) as z:
+        meta = json.loads(str(z["meta"]))
+        write_triage_bin(bin_path, z["params"], z["mu"], z["sd"], float(z["threshold"]),
+                         meta.get("thresholds_by_l", {}))
+
+
+def default_triage_bin_path() -> str:
+    """The shipped weights in the file format projection_run reads."""
+    return os.path.join(PKG, "triage_weights.bin")
 
 
 class TriagedBatchPipeline(BatchPipeline):

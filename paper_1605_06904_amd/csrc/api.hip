@@ -1,6 +1,5 @@
-// Host side of libprojmotif: error reporting, argument checks, host-side
-// parameter helpers (Sec. 5 and Sec. 6 of the paper) and projection_run, the
-// host-in/host-out driver of the whole path.
+// Host side of libprojmotif: error reporting, argument checks and the
+// host-side parameter helpers (Sec. 5 and Sec. 6 of the paper).
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -187,198 +186,5 @@ extern "C" int pm_auto_params(int32_t alphabet, int32_t t, int64_t x, int32_t l,
     if (k) *k = kk;
     if (s) *s = ss;
     if (m) *m = mm;
-    return PM_OK;
-}
-
-namespace {
-
-struct DevBuf {
-    void *p = nullptr;
-    ~DevBuf()
-    {
-        if (p) (void)hipFree(p);
-    }
-    int alloc(size_t n)
-    {
-        if (p) {
-            (void)hipFree(p);
-            p = nullptr;
-        }
-        if (n == 0) n = 16;
-        hipError_t e = hipMalloc(&p, n);
-        if (e != hipSuccess) return fail(PM_EDEVICE, "hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
-        return PM_OK;
-    }
-    template <typename T>
-    T *as() const { return static_cast<T *>(p); }
-};
-
-}  // namespace
-
-#define PM_CALL(expr)       \
-    do {                    \
-        int rc_ = (expr);   \
-        if (rc_) return rc_; \
-    } while (0)
-
-extern "C" int projection_run(const pm_problem *P, const pm_options *O, pm_result *R)
-{
-    clear_error();
-    if (!P || !O || !R) return fail(PM_EINVAL, "NULL argument");
-    const int A = P->alphabet;
-    if (A != 4 && A != 20) return fail(PM_EINVAL, "alphabet must be 4 or 20");
-    if (P->t < 1 || !P->seqs || !P->n) return fail(PM_EINVAL, "need t >= 1 sequences");
-    const int l = P->l;
-    int64_t n_total = 0;
-    int n_min = 0x7fffffff, n_max = 0;
-    for (int i = 0; i < P->t; ++i) {
-        if (!P->seqs[i] || P->n[i] < 0) return fail(PM_EINVAL, "sequence %d is NULL or has negative length", i);
-        n_total += P->n[i];
-        n_min = P->n[i] < n_min ? P->n[i] : n_min;
-        n_max = P->n[i] > n_max ? P->n[i] : n_max;
-    }
-    if (l < 1 || l > 32 || n_min < l) return fail(PM_EINVAL, "need 1 <= l <= 32 and l <= every n_i");
-    const int64_t x = n_total - (int64_t)P->t * (l - 1);
-    int k = P->k, s = P->s, m = P->m;
-    if (k <= 0 || s <= 0 || m <= 0) {
-        int ak, as, am;
-        PM_CALL(pm_auto_params(A, P->t, x, l, P->d, 0.95, &ak, &as, &am));
-        if (k <= 0) k = ak;
-        if (s <= 0) s = as;
-        if (m <= 0) m = am;
-    }
-    if (k < 1 || k > l) return fail(PM_EINVAL, "need 1 <= k <= l");
-    if (O->em_iters < 0 || O->beta < 0) return fail(PM_EINVAL, "need em_iters >= 0 and beta >= 0");
-    hipStream_t st = as_stream(O->stream);
-
-    // host staging: concatenated ASCII, offsets, masks, background
-    std::vector<uint8_t> ascii((size_t)n_total);
-    std::vector<int64_t> off(P->t + 1, 0);
-    for (int i = 0; i < P->t; ++i) {
-        memcpy(ascii.data() + off[i], P->seqs[i], (size_t)P->n[i]);
-        off[i + 1] = off[i] + P->n[i];
-    }
-    std::vector<uint32_t> masks((size_t)m);
-    if (P->masks) memcpy(masks.data(), P->masks, sizeof(uint32_t) * m);
-    else PM_CALL(pm_masks_from_seed(P->seed, l, k, m, masks.data()));
-    for (int j = 0; j < m; ++j)
-        if (__builtin_popcount(masks[j]) != k || (l < 32 && (masks[j] >> l)))
-            return fail(PM_EINVAL, "mask %d does not keep exactly k=%d of l=%d positions", j, k, l);
-
-    const int64_t nw = pm_packed_words(A, n_total);
-    const int64_t nb = ipow(A, k);
-    DevBuf d_ascii, d_off, d_packed, d_masks, d_keys, d_counts, d_status, d_nout, d_ws;
-    PM_CALL(d_ascii.alloc(n_total));
-    PM_CALL(d_off.alloc(sizeof(int64_t) * (P->t + 1)));
-    PM_CALL(d_packed.alloc(sizeof(uint32_t) * nw));
-    PM_CALL(d_masks.alloc(sizeof(uint32_t) * m));
-    PM_CALL(d_keys.alloc(sizeof(uint32_t) * (size_t)m * x));
-    PM_CALL(d_counts.alloc(sizeof(uint32_t) * (size_t)m * nb));
-    PM_CALL(d_status.alloc(sizeof(uint32_t)));
-    PM_CALL(d_nout.alloc(sizeof(int64_t) * 2));
-    PM_TRY(hipMemcpyAsync(d_ascii.p, ascii.data(), n_total, hipMemcpyHostToDevice, st));
-    PM_TRY(hipMemcpyAsync(d_off.p, off.data(), sizeof(int64_t) * (P->t + 1), hipMemcpyHostToDevice, st));
-    PM_TRY(hipMemcpyAsync(d_masks.p, masks.data(), sizeof(uint32_t) * m, hipMemcpyHostToDevice, st));
-    PM_TRY(hipMemsetAsync(d_status.p, 0, sizeof(uint32_t), st));
-
-    pm_seqs S{A, P->t, n_total, n_min, n_max, d_off.as<int64_t>(), d_packed.as<uint32_t>()};
-    PM_CALL(pm_pack(A, d_ascii.as<uint8_t>(), n_total, d_packed.as<uint32_t>(), d_status.as<uint32_t>(), st));
-    PM_CALL(projection_hash(&S, l, k, d_masks.as<uint32_t>(), m, d_keys.as<uint32_t>(),
-                            d_counts.as<uint32_t>(), d_status.as<uint32_t>(), st));
-    // size the bucket lists: one selection pass with empty capacities
-    PM_CALL(d_ws.alloc(pm_select_workspace(m, 0)));
-    PM_CALL(bucket_select(&S, l, k, d_keys.as<uint32_t>(), d_counts.as<uint32_t>(), m, (uint32_t)s, nullptr, 0,
-                          nullptr, 0, d_nout.as<int64_t>(), d_ws.p, pm_select_workspace(m, 0), nullptr, st));
-    int64_t nout[2];
-    uint32_t status = 0;
-    PM_TRY(hipMemcpyAsync(nout, d_nout.p, sizeof(nout), hipMemcpyDeviceToHost, st));
-    PM_TRY(hipMemcpyAsync(&status, d_status.p, sizeof(status), hipMemcpyDeviceToHost, st));
-    PM_TRY(hipStreamSynchronize(st));
-    if (status & PM_STATUS_BAD_SYMBOL) return fail(PM_EINVAL, "a sequence holds a symbol outside the alphabet");
-    if (status & PM_STATUS_BAD_MASK) return fail(PM_EINVAL, "bad projection mask");
-    const int64_t nbk = nout[0], nmem = nout[1];
-    R->k = k;
-    R->s = s;
-    R->m = m;
-    R->n_enriched = nbk;
-    R->best_trial = -1;
-    R->best_key = 0;
-    R->J = R->llr = -INFINITY;
-    if (nbk == 0) {
-        if (R->consensus) R->consensus[0] = 0;
-        return PM_OK;
-    }
-    DevBuf d_bk, d_mem, d_prof, d_bg, d_th0, d_th, d_J, d_llr, d_sites, d_best, d_cons, d_emws;
-    PM_CALL(d_bk.alloc(sizeof(pm_bucket) * nbk));
-    PM_CALL(d_mem.alloc(sizeof(uint32_t) * nmem));
-    PM_CALL(d_ws.alloc(pm_select_workspace(m, nbk)));
-    PM_CALL(bucket_select(&S, l, k, d_keys.as<uint32_t>(), d_counts.as<uint32_t>(), m, (uint32_t)s,
-                          d_bk.as<pm_bucket>(), nbk, d_mem.as<uint32_t>(), nmem, d_nout.as<int64_t>(), d_ws.p,
-                          pm_select_workspace(m, nbk), d_status.as<uint32_t>(), st));
-    // keys and counts are no longer needed
-    (void)hipFree(d_keys.p);
-    d_keys.p = nullptr;
-    (void)hipFree(d_counts.p);
-    d_counts.p = nullptr;
-
-    std::vector<double> bg(A, 0.0);
-    if (P->bg) {
-        double tot = 0;
-        for (int c = 0; c < A; ++c) tot += P->bg[c];
-        for (int c = 0; c < A; ++c) bg[c] = P->bg[c] / tot;
-    } else {
-        // composition of the input (the background is fixed, never re-estimated)
-        std::vector<double> cnt(A, 0.0);
-        for (int64_t g = 0; g < n_total; ++g) {
-            const char ch = (char)ascii[g];
-            const char u = (ch >= 'a' && ch <= 'z') ? (char)(ch - 'a' + 'A') : ch;
-            const char *L = A == 4 ? "ACTG" : "ARNDCQEGHILKMFPSTWYV";
-            const char *f = strchr(L, u);
-            if (f && u) cnt[f - L] += 1;
-        }
-        for (int c = 0; c < A; ++c) bg[c] = cnt[c] / (double)n_total;
-    }
-    const int AL = A * l;
-    const int it1 = O->em_iters + 1;
-    PM_CALL(d_prof.alloc(sizeof(uint32_t) * nbk * AL));
-    PM_CALL(d_bg.alloc(sizeof(double) * A));
-    PM_CALL(d_th0.alloc(sizeof(double) * nbk * AL));
-    PM_CALL(d_th.alloc(sizeof(double) * nbk * AL));
-    PM_CALL(d_J.alloc(sizeof(double) * nbk * it1));
-    PM_CALL(d_llr.alloc(sizeof(double) * nbk * it1));
-    PM_CALL(d_sites.alloc(sizeof(int32_t) * nbk * P->t));
-    PM_CALL(d_best.alloc(sizeof(int64_t)));
-    PM_CALL(d_cons.alloc(l + 1));
-    const size_t em_ws = pm_em_workspace(&S, l, O->precision);
-    if (em_ws) PM_CALL(d_emws.alloc(em_ws));
-    PM_TRY(hipMemcpyAsync(d_bg.p, bg.data(), sizeof(double) * A, hipMemcpyHostToDevice, st));
-    PM_CALL(bucket_profile(&S, l, d_bk.as<pm_bucket>(), d_mem.as<uint32_t>(), nmem, nbk, nullptr,
-                           d_prof.as<uint32_t>(), st));
-    PM_CALL(theta_init(A, l, d_prof.as<uint32_t>(), nbk, nullptr, d_bg.as<double>(), O->beta, d_th0.as<double>(), st));
-    PM_CALL(em_refine(&S, l, d_th0.as<double>(), d_bg.as<double>(), nbk, nullptr, O->em_iters, O->beta,
-                      O->precision, d_th.as<double>(), d_J.as<double>(), d_llr.as<double>(),
-                      d_sites.as<int32_t>(), d_emws.p, em_ws, st));
-    PM_CALL(em_best(d_J.as<double>(), nbk, nullptr, O->em_iters, d_th.as<double>(), A, l, d_best.as<int64_t>(),
-                    d_cons.as<char>(), st));
-    int64_t best = -1;
-    PM_TRY(hipMemcpyAsync(&best, d_best.p, sizeof(best), hipMemcpyDeviceToHost, st));
-    PM_TRY(hipStreamSynchronize(st));
-    if (best < 0) {
-        if (R->consensus) R->consensus[0] = 0;
-        return PM_OK;
-    }
-    pm_bucket bk;
-    PM_TRY(hipMemcpyAsync(&bk, d_bk.as<pm_bucket>() + best, sizeof(bk), hipMemcpyDeviceToHost, st));
-    PM_TRY(hipMemcpyAsync(&R->J, d_J.as<double>() + best * it1 + O->em_iters, sizeof(double), hipMemcpyDeviceToHost, st));
-    PM_TRY(hipMemcpyAsync(&R->llr, d_llr.as<double>() + best * it1 + O->em_iters, sizeof(double), hipMemcpyDeviceToHost, st));
-    if (R->consensus) PM_TRY(hipMemcpyAsync(R->consensus, d_cons.p, l + 1, hipMemcpyDeviceToHost, st));
-    if (R->sites)
-        PM_TRY(hipMemcpyAsync(R->sites, d_sites.as<int32_t>() + best * P->t, sizeof(int32_t) * P->t,
-                              hipMemcpyDeviceToHost, st));
-    if (R->theta)
-        PM_TRY(hipMemcpyAsync(R->theta, d_th.as<double>() + best * AL, sizeof(double) * AL, hipMemcpyDeviceToHost, st));
-    PM_TRY(hipStreamSynchronize(st));
-    R->best_trial = (int32_t)bk.trial;
-    R->best_key = bk.key;
     return PM_OK;
 }

@@ -247,6 +247,7 @@ def main(argv=None):
                 seconds=round(time.time() - t0, 1))
     tri = pm.Triage(params, mu, sd, pooled, meta=meta)
     tri.save(args.out)
+    tri.save_bin(os.path.splitext(args.out)[0] + ".bin")
     log(f"saved {args.out}: {json.dumps(meta)}")
 
 

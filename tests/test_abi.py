@@ -127,10 +127,47 @@ def test_other_entry_points_validate():
 
 
 def test_projection_run_rejects_bad_problem():
-    with pytest.raises(pm.PmError):
-        pm.projection_run(["ACGT", "ACG"], 4, 4)          # a sequence shorter than l
-    with pytest.raises(pm.PmError):
-        pm.projection_run(["ACGTACGT"], 4, 4, k=2, s=2, masks=np.array([0b111]))  # wrong popcount
+    """Host-side checks of projection_run fail before any device call."""
+    with pytest.raises(pm.PmError, match="problem 0"):
+        pm.projection_run(pm.Problem(["ACGT", "ACG"], 4, 4))          # a sequence shorter than l
+    with pytest.raises(pm.PmError, match="problem 1"):
+        pm.projection_run([pm.Problem(["ACGTACGT"], 4, 4, k=2, s=2, masks=np.array([0b11])),
+                           pm.Problem(["ACGTACGT"], 4, 4, k=2, s=2, masks=np.array([0b111]))])  # wrong popcount
+    with pytest.raises(pm.PmError, match="never occurs"):
+        pm.projection_run(pm.Problem(["AAAAAAAA"], 4, 4, k=2, s=2, masks=np.array([0b11])))  # bg from composition
+    with pytest.raises(pm.PmError, match="triage"):
+        pm.projection_run(pm.Problem(["ACGTACGT"], 4, 4, k=2, s=2, masks=np.array([0b11])), triage=True,
+                          triage_weights="/nonexistent/triage.bin")
+    L = pm.lib()
+    assert L.projection_run(None, 0, None, None) == pm.PM_EINVAL
+
+
+def test_triage_weights_file_round_trip(tmp_path):
+    """The shipped binary weights equal the training output they came from,
+    in the layout the header documents."""
+    import json
+    import struct
+    with np.load(pm.default_triage_path(), allow_pickle=False) as z:
+        params, mu, sd, thr = z["params"], z["mu"], z["sd"], float(z["threshold"])
+        per = json.loads(str(z["meta"])).get("thresholds_by_l", {})
+    raw = open(pm.default_triage_bin_path(), "rb").read()
+    assert raw[:8] == b"PMTRIAG1"
+    assert struct.unpack_from("<ii", raw, 8) == (pm.PM_TRIAGE_PARAMS, pm.PM_TRIAGE_INPUTS)
+    o = 16
+    for a, n in ((params, pm.PM_TRIAGE_PARAMS), (mu, 87), (sd, 87)):
+        assert np.array_equal(np.frombuffer(raw, dtype="<f4", count=n, offset=o), a.astype(np.float32))
+        o += 4 * n
+    t0, nl = struct.unpack_from("<di", raw, o)
+    assert t0 == thr and nl == len(per)
+    o += 12
+    got = {}
+    for _ in range(nl):
+        l, v = struct.unpack_from("<id", raw, o)
+        got[l] = v
+        o += 12
+    assert o == len(raw) and got == {int(k): float(v) for k, v in per.items()}
+    pm.convert_triage_npz(pm.default_triage_path(), str(tmp_path / "w.bin"))
+    assert open(tmp_path / "w.bin", "rb").read() == raw
 
 
 def _fake_batch(P=3, l=11, k=5, m=(2, 3, 1), x_fix=None, first_fix=None):

@@ -510,17 +510,6 @@ def test_em_best_is_the_first_largest_final_objective(case):
 
 
 # ------------------------------------------------------------------ end to end
-def test_projection_run_fig1_toy():
-    """Example 1: PROJECTION + EM on Fig. 1 returns ATGCAACT at Fig. 2's sites."""
-    seqs = [r[0] for r in read_golden("fig1_sequences.txt")]
-    say("projection_run toy")
-    r = pm.projection_run(seqs, 4, 8, k=5, s=4, masks=np.array([0b1100111]), em_iters=5,
-                          beta=1.0, bg=np.full(4, 0.25))
-    assert r["consensus"] == "ATGCAACT"
-    assert list(r["sites"]) == [7, 18, 2, 4, 30, 26, 14]
-    assert r["n_enriched"] == 2
-
-
 def _pipeline(inst, masks, cfg, precision, cap_factor=1):
     A = 4 if cfg["alphabet"] == "dna" else 20
     ref = oracle.Seqs(A, inst.seqs)
