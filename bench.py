@@ -518,6 +518,7 @@ def instances_leg(torch, pm, count):
     # the same per-instance pipeline with the batched leg's EM form, so that the
     # gain of batching is measured apart from the gain of the matrix cores
     plain_mc = plain_leg(pm.PM_F16X2, "split-f16 matrix cores")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     # ---- batched: all instances in one pass of launches, captured in a graph
     B = pm.Batch(4, l, k, [i.seqs for i, _ in insts], [mk for _, mk in insts])
     nbk, nmem = pm.size_batch(B, s)

@@ -56,8 +56,10 @@ extern "C" {
 
 /* EM arithmetic (em_refine `precision`).  In every form the per-sequence
  * log-sum-exp is FP64: each window's term exp(s_ia - ref) is formed in the
- * form's precision, converted to FP64 and summed in FP64 (lane partials
- * combined in FP64), the logarithm is FP64, and LLR, J and the final
+ * form's precision and accumulated over the sequence in FP64 (the DNA
+ * matrix-core forms first add the eight terms a lane holds for one 32-window
+ * pair in FP32, at most 3 * 2^-24 relative error), lane partials are
+ * combined in FP64, the logarithm is FP64, and LLR, J and the final
  * comparison of models are FP64. */
 #define PM_FP64 0  /* every step in FP64 */
 #define PM_FP32 1  /* scores, exponentials, posteriors and counts in FP32 */
@@ -151,6 +153,27 @@ int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *keys,
                   const uint32_t *counts, int32_t m, uint32_t s, pm_bucket *buckets,
                   int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out,
                   void *ws, size_t ws_bytes, uint32_t *status, void *stream);
+
+/* a3 + a4 + a5 fused -- Alg. 2 steps 2(b), 2(c) and 3 without keys or counts
+ * in device memory: each trial's histogram lives only in LDS, where its
+ * passing bins (at least s l-mers, Sec. 6) are turned into bucket records and
+ * member slots.  The outputs and their order are those of bucket_select
+ * (buckets ascending by (trial, key), `first` and `size` identical) except
+ * that the members of one bucket come in no particular order; n_out and
+ * truncation as for bucket_select.  One call runs a counting pass, a scan and
+ * the writing pass (with cap_buckets = cap_members = 0 only the first two,
+ * to size the lists).
+ *   masks   device [m] (bad masks: PM_STATUS_BAD_MASK, that trial contributes
+ *           nothing)
+ *   ws      device, pm_hash_select_workspace(S, l, k, m) bytes, 8-byte aligned;
+ *           it starts with the number of enriched buckets of every (trial,
+ *           key-range slice), trial-major (int64)
+ * Limits: DNA k <= 12, protein k <= 5 (the histogram is sliced over
+ * workgroups when it does not fit one workgroup's LDS). */
+size_t pm_hash_select_workspace(const pm_seqs *S, int32_t l, int32_t k, int32_t m);
+int bucket_hash_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m, uint32_t s,
+                       pm_bucket *buckets, int64_t cap_buckets, uint32_t *members, int64_t cap_members,
+                       int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status, void *stream);
 
 /* a6 (first half) -- Sec. 2 profile matrix P(s) of each bucket's alignment.
  *   members      device [cap_members] as written by bucket_select; a bucket
@@ -275,6 +298,13 @@ int projection_hash_batch(const pm_batch *B, const uint32_t *masks, uint32_t *ke
 int bucket_select_batch(const pm_batch *B, const uint32_t *keys, const uint32_t *counts, uint32_t s,
                         pm_bucket *buckets, int64_t cap_buckets, uint32_t *members, int64_t cap_members,
                         int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status, void *stream);
+
+/* The fused a3 - a5 over every item of a batch (bucket `trial` = item);
+ * ws: pm_hash_select_batch_workspace(B) bytes. */
+size_t pm_hash_select_batch_workspace(const pm_batch *B);
+int bucket_hash_select_batch(const pm_batch *B, const uint32_t *masks, uint32_t s, pm_bucket *buckets,
+                             int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out, void *ws,
+                             size_t ws_bytes, uint32_t *status, void *stream);
 
 /* a6 (profiles) for the buckets of a batch. */
 int bucket_profile_batch(const pm_batch *B, const pm_bucket *buckets, const uint32_t *members,

@@ -33,6 +33,7 @@ EXPORTS = [
     "triage_features", "pm_triage_packed_bytes", "triage_pack", "triage_forward", "pm_triage_workspace",
     "triage_train_step", "pm_triage_select_workspace", "triage_select", "triage_fallback_select",
     "triage_merge_best", "em_autotune", "em_tuning", "em_set_tuning",
+    "pm_hash_select_workspace", "bucket_hash_select", "pm_hash_select_batch_workspace", "bucket_hash_select_batch",
 ]
 
 PM_TRIAGE_PARAMS, PM_TRIAGE_INPUTS = 88577, 87
@@ -144,6 +145,11 @@ def lib():
         "em_autotune": (C.c_int, [C.POINTER(pm_seqs), i32, P, P, i64, i32, dbl, i32, P, P, P, sz, P, P]),
         "em_tuning": (C.c_int, [i32, i32]),
         "em_set_tuning": (C.c_int, [i32, i32, i32]),
+        "pm_hash_select_workspace": (sz, [C.POINTER(pm_seqs), i32, i32, i32]),
+        "bucket_hash_select": (C.c_int, [C.POINTER(pm_seqs), i32, i32, P, i32, u32, P, i64, P, i64, P, P, sz, P,
+                                         P]),
+        "pm_hash_select_batch_workspace": (sz, [C.POINTER(pm_batch)]),
+        "bucket_hash_select_batch": (C.c_int, [C.POINTER(pm_batch), P, u32, P, i64, P, i64, P, P, sz, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -218,6 +224,28 @@ def bucket_select(S, l, k, keys, counts, m, s, buckets, cap_buckets, members, ca
     _check(lib().bucket_select(C.byref(S.c), l, k, _ptr(keys), _ptr(counts), m, s, _ptr(buckets),
                                cap_buckets, _ptr(members), cap_members, _ptr(n_out), _ptr(ws),
                                ws_bytes, _ptr(status), _stream(stream)))
+
+
+def pm_hash_select_workspace(S, l: int, k: int, m: int) -> int:
+    return int(lib().pm_hash_select_workspace(C.byref(S.c), l, k, m))
+
+
+def bucket_hash_select(S, l, k, masks, m, s, buckets, cap_buckets, members, cap_members, n_out, ws, ws_bytes,
+                       status=None, stream=None):
+    _check(lib().bucket_hash_select(C.byref(S.c), l, k, _ptr(masks), m, s, _ptr(buckets), cap_buckets,
+                                    _ptr(members), cap_members, _ptr(n_out), _ptr(ws), ws_bytes, _ptr(status),
+                                    _stream(stream)))
+
+
+def pm_hash_select_batch_workspace(B) -> int:
+    return int(lib().pm_hash_select_batch_workspace(C.byref(B.c)))
+
+
+def bucket_hash_select_batch(B, masks, s, buckets, cap_buckets, members, cap_members, n_out, ws, ws_bytes,
+                             status=None, stream=None):
+    _check(lib().bucket_hash_select_batch(C.byref(B.c), _ptr(masks), s, _ptr(buckets), cap_buckets, _ptr(members),
+                                          cap_members, _ptr(n_out), _ptr(ws), ws_bytes, _ptr(status),
+                                          _stream(stream)))
 
 
 def bucket_profile(S, l, buckets, members, cap_members, B, n_dev, profile, stream=None):

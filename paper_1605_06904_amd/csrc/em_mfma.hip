@@ -14,10 +14,12 @@
 // significant bits; sums are FP32.  The single-FP16 form (SPLIT = false) keeps
 // only hi: half the matrix-core work, 11-bit operands.  Scores are kept in log2 units (W scaled
 // by log2 e) so the softmax uses the hardware exp2.  The per-sequence
-// log-sum-exp is FP64: every lane converts each of its posterior terms
-// 2^(S - ref) (FP32 exp2 of an FP32 score) to FP64 and adds it to an FP64
-// running sum, the four lane groups are combined with FP64 shuffles and the
-// logarithm is FP64; so are the objective and the final comparison.
+// log-sum-exp is FP64: the posterior terms 2^(S - ref) are FP32 exp2 of FP32
+// scores; the eight a lane holds for one window pair are added in FP32 (three
+// levels), and these pair partials are accumulated over the whole sequence in
+// FP64, so the error does not grow with the sequence length; the four lane
+// groups are combined with FP64 shuffles and the logarithm is FP64, as are
+// the objective and the final comparison.
 //
 // Lane layout of one 16x16x32 MFMA (lane L, r = L % 16, g = L / 16):
 //   A operand: row r, the g-th group of 8 contraction indices;
@@ -319,13 +321,9 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T
         float P[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) P[u] = __builtin_amdgcn_exp2f(S[u]);
-        // the lane's eight terms, each converted to FP64, summed in FP64
-        {
-            double e[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) e[u] = (double)P[u];
-            st[q].srun += ((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7]));
-        }
+        // the lane's eight terms of this pair (a three-level FP32 tree, relative
+        // error at most 3 * 2^-24), accumulated over the sequence in FP64
+        st[q].srun += (double)(((P[0] + P[1]) + (P[2] + P[3])) + ((P[4] + P[5]) + (P[6] + P[7])));
         if (!LAST) {
             uint4 h;
             h.x = pack_hi(P[0], P[1]);

@@ -81,68 +81,51 @@ struct HashArgs {
 constexpr int kHashThreads = 1024;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-template <int A, int K, bool U16>
-__global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
+// The instance of trial item j, with its packed input (and the window number
+// of every sequence start) staged in LDS when the launch reserved room.
+struct Staged {
+    pm_inst I;
+    const uint32_t *seq;  // LDS copy (seq_cap) or global words
+    const int32_t *wst;   // LDS window starts, when off_cap
+};
+
+template <int A>
+__device__ __forceinline__ Staged stage_input(const HashArgs &a, int j, uint32_t *seq, int32_t *wst)
 {
-    extern __shared__ __align__(16) uint32_t smem[];
-    const int slice = blockIdx.x % a.nslices;
-    const int j = blockIdx.x / a.nslices;
-    const int tid = threadIdx.x;
     const pm_inst I = a.inst ? a.inst[a.item_inst[j]] : a.one;
-    const int64_t x = I.x;
     const int seq_words = a.seq_cap ? (int)(A == 4 ? (I.n_total + 15) / 16 + 4 : (I.n_total + 5) / 6 + 4) : 0;
-
-    const uint32_t mask = a.masks[j];
-    const uint32_t lmask = a.l == 32 ? 0xffffffffu : ((1u << a.l) - 1u);
-    if (__popc(mask) != a.k || (mask & ~lmask)) {
-        if (tid == 0 && slice == 0 && a.status) atomicOr(a.status, PM_STATUS_BAD_MASK);
-        return;
-    }
-
-    uint32_t *hist = smem;
-    uint32_t *seq = smem + a.hist_words;
-    int32_t *wst = reinterpret_cast<int32_t *>(seq + a.seq_cap);  // window number of each sequence start
-
-    for (int i = tid; i < seq_words; i += kHashThreads) seq[i] = I.packed[i];
+    for (int i = threadIdx.x; i < seq_words; i += kHashThreads) seq[i] = I.packed[i];
     if (a.off_cap)
-        for (int i = tid; i <= I.t; i += kHashThreads) wst[i] = (int32_t)(I.offsets[i] - (int64_t)i * (a.l - 1));
-    if (a.counts)
-        for (int i = tid * 4; i < a.hist_words; i += kHashThreads * 4)
-            *reinterpret_cast<uint4 *>(hist + i) = make_uint4(0, 0, 0, 0);
-    __syncthreads();
+        for (int i = threadIdx.x; i <= I.t; i += kHashThreads) wst[i] = (int32_t)(I.offsets[i] - (int64_t)i * (a.l - 1));
+    return Staged{I, a.seq_cap ? seq : I.packed, wst};
+}
 
-    // kept positions, ascending (uniform across the workgroup): the shift of
-    // each kept position's 2-bit field in the 64-bit window (DNA), or the
-    // position itself (protein)
-    int pos[K];
-    {
-        uint32_t mm = mask;
+// kept positions, ascending: the shift of each kept position's 2-bit field in
+// the 64-bit window (DNA), or the position itself (protein)
+template <int A, int K>
+__device__ __forceinline__ void kept_positions(uint32_t mask, int (&pos)[K])
+{
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
-            const int p = __builtin_ctz(mm);
-            pos[q] = A == 4 ? 62 - 2 * p : p;
-            mm &= mm - 1;
-        }
+    for (int q = 0; q < K; ++q) {
+        const int p = __builtin_ctz(mask);
+        pos[q] = A == 4 ? 62 - 2 * p : p;
+        mask &= mask - 1;
     }
+}
 
-    const uint32_t slice_base = (uint32_t)slice * a.slice_bins;  // |Sigma|^k <= 2^24
-    const int64_t kw0 = x * slice / a.nslices, kw1 = x * (slice + 1) / a.nslices;
-    uint32_t *keys_j = a.keys ? a.keys + I.key_base + (int64_t)(j - I.first_item) * x : nullptr;
-    auto count = [&](uint32_t key) {
-        const uint32_t bin = key - slice_base;
-        if (bin < a.slice_bins) {
-            if (U16) atomicAdd(hist + (bin >> 1), 1u << ((bin & 1) << 4));
-            else atomicAdd(hist + bin, 1u);
-        }
-    };
-
+// fn(w, key) for every window w = tid, tid + kHashThreads, ... of the instance
+template <int A, int K, typename F>
+__device__ __forceinline__ void for_each_key(const HashArgs &a, const Staged &st, const int (&pos)[K], F &&fn)
+{
+    const int64_t x = st.I.x;
     if (a.seq_cap && a.off_cap) {
         // staged input: every read below is an LDS read, all indices 32-bit
         // (n_total < 2^31)
+        const uint32_t *seq = st.seq;
+        const int32_t *wst = st.wst;
         const uint32_t x32 = (uint32_t)x, lm1 = (uint32_t)(a.l - 1);
-        const uint32_t k0 = (uint32_t)kw0, k1 = (uint32_t)kw1;
         int i = 0;
-        for (uint32_t w = tid; w < x32; w += kHashThreads) {
+        for (uint32_t w = threadIdx.x; w < x32; w += kHashThreads) {
             while ((int32_t)w >= wst[i + 1]) ++i;
             const uint32_t P = w + (uint32_t)i * lm1;
             uint32_t key = 0;
@@ -162,16 +145,15 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
                     key = key * 20u + ((seq[qq] >> (27 - 5 * (g - 6u * qq))) & 31u);
                 }
             }
-            if (keys_j && w >= k0 && w < k1) __builtin_nontemporal_store(key, keys_j + w);
-            if (a.counts) count(key);
+            fn((int64_t)w, key);
         }
     } else {
         // large instances: packed input and offsets read from global memory
-        const uint32_t *W = a.seq_cap ? seq : I.packed;
-        const int64_t *O = I.offsets;
+        const uint32_t *W = st.seq;
+        const int64_t *O = st.I.offsets;
         const int64_t lm1 = a.l - 1;
         int i = 0;
-        for (int64_t w = tid; w < x; w += kHashThreads) {
+        for (int64_t w = threadIdx.x; w < x; w += kHashThreads) {
             while (w >= O[i + 1] - (int64_t)(i + 1) * lm1) ++i;
             const int64_t P = w + (int64_t)i * lm1;
             uint32_t key = 0;
@@ -185,10 +167,61 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
 #pragma unroll
                 for (int q = 0; q < K; ++q) key = key * 20u + prot_sym(W, P + pos[q]);
             }
-            if (keys_j && w >= kw0 && w < kw1) __builtin_nontemporal_store(key, keys_j + w);
-            if (a.counts) count(key);
+            fn(w, key);
         }
     }
+}
+
+__device__ __forceinline__ bool mask_ok(const HashArgs &a, uint32_t mask)
+{
+    const uint32_t lmask = a.l == 32 ? 0xffffffffu : ((1u << a.l) - 1u);
+    return __popc(mask) == a.k && !(mask & ~lmask);
+}
+
+template <bool U16>
+__device__ __forceinline__ void hist_add(uint32_t *hist, uint32_t bin)
+{
+    if (U16) atomicAdd(hist + (bin >> 1), 1u << ((bin & 1) << 4));
+    else atomicAdd(hist + bin, 1u);
+}
+
+template <int A, int K, bool U16>
+__global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
+{
+    extern __shared__ __align__(16) uint32_t smem[];
+    const int slice = blockIdx.x % a.nslices;
+    const int j = blockIdx.x / a.nslices;
+    const int tid = threadIdx.x;
+
+    const uint32_t mask = a.masks[j];
+    if (!mask_ok(a, mask)) {
+        if (tid == 0 && slice == 0 && a.status) atomicOr(a.status, PM_STATUS_BAD_MASK);
+        return;
+    }
+
+    uint32_t *hist = smem;
+    uint32_t *seq = smem + a.hist_words;
+    int32_t *wst = reinterpret_cast<int32_t *>(seq + a.seq_cap);  // window number of each sequence start
+    const Staged st = stage_input<A>(a, j, seq, wst);
+    const pm_inst &I = st.I;
+    const int64_t x = I.x;
+    if (a.counts)
+        for (int i = tid * 4; i < a.hist_words; i += kHashThreads * 4)
+            *reinterpret_cast<uint4 *>(hist + i) = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+
+    int pos[K];
+    kept_positions<A, K>(mask, pos);
+    const uint32_t slice_base = (uint32_t)slice * a.slice_bins;  // |Sigma|^k <= 2^24
+    const int64_t kw0 = x * slice / a.nslices, kw1 = x * (slice + 1) / a.nslices;
+    uint32_t *keys_j = a.keys ? a.keys + I.key_base + (int64_t)(j - I.first_item) * x : nullptr;
+    for_each_key<A, K>(a, st, pos, [&](int64_t w, uint32_t key) {
+        if (keys_j && w >= kw0 && w < kw1) __builtin_nontemporal_store(key, keys_j + w);
+        if (a.counts) {
+            const uint32_t bin = key - slice_base;
+            if (bin < a.slice_bins) hist_add<U16>(hist, bin);
+        }
+    });
     if (!a.counts) return;
     __syncthreads();
 
@@ -207,6 +240,154 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
     }
 }
 
+// ---------------------------------------------------------------- a3 - a5 fused
+// Projection, histogram and enriched-bucket list without keys or counts in
+// HBM.  Pass COUNT: the histogram of the (item, slice) in LDS, then its
+// number of passing bins and their total size.  Pass EMIT (after a scan of
+// those totals): the same histogram again; a block scan over the slice's bins
+// gives every passing bin its bucket number and first member slot, the bucket
+// records are written in key order, each passing bin's count is replaced in
+// place by its first slot (non-passing bins by an all-ones sentinel), and a
+// second sweep over the windows places every member with an LDS atomic add on
+// its bin, whose returned value is the member's slot.  Members of a bucket are
+// therefore complete but in no particular order.
+struct HselArgs {
+    HashArgs h;
+    uint32_t s;
+    int64_t *tot_b, *tot_m;          // [items * nslices]: passing bins and their members
+    const int64_t *base_b, *base_m;  // [items * nslices]: their first bucket and member slot (EMIT)
+    pm_bucket *buckets;
+    uint32_t *members;
+    int64_t cap_b, cap_m;
+};
+
+constexpr int kHselScanWords = 2 * kHashThreads;  // LDS words of the bin scan (per-thread totals)
+
+template <bool U16>
+__device__ __forceinline__ uint32_t hist_get(const uint32_t *hist, uint32_t bin)
+{
+    return U16 ? (hist[bin >> 1] >> ((bin & 1) << 4)) & 0xffffu : hist[bin];
+}
+
+template <bool U16>
+__device__ __forceinline__ void hist_set(uint32_t *hist, uint32_t bin, uint32_t v)
+{
+    if (U16) {
+        const uint32_t sh = (bin & 1) << 4;
+        hist[bin >> 1] = (hist[bin >> 1] & ~(0xffffu << sh)) | ((v & 0xffffu) << sh);
+    } else {
+        hist[bin] = v;
+    }
+}
+
+template <int A, int K, bool U16, bool EMIT>
+__global__ void __launch_bounds__(kHashThreads) k_hsel(const HselArgs g)
+{
+    const HashArgs &a = g.h;
+    extern __shared__ __align__(16) uint32_t smem[];
+    const int slice = blockIdx.x % a.nslices;
+    const int j = blockIdx.x / a.nslices;
+    const int tid = threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x;  // (item, slice) entry
+
+    const uint32_t mask = a.masks[j];
+    if (!mask_ok(a, mask)) {
+        if (tid == 0) {
+            if (slice == 0 && a.status) atomicOr(a.status, PM_STATUS_BAD_MASK);
+            if (!EMIT) g.tot_b[e] = g.tot_m[e] = 0;
+        }
+        return;
+    }
+    uint32_t *hist = smem;
+    uint32_t *seq = smem + a.hist_words;
+    int32_t *wst = reinterpret_cast<int32_t *>(seq + a.seq_cap);
+    uint32_t *scan = reinterpret_cast<uint32_t *>(wst + a.off_cap);  // [kHselScanWords]
+    const Staged st = stage_input<A>(a, j, seq, wst);
+    for (int i = tid * 4; i < a.hist_words; i += kHashThreads * 4)
+        *reinterpret_cast<uint4 *>(hist + i) = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+    int pos[K];
+    kept_positions<A, K>(mask, pos);
+    const uint32_t slice_base = (uint32_t)slice * a.slice_bins;
+    for_each_key<A, K>(a, st, pos, [&](int64_t, uint32_t key) {
+        const uint32_t bin = key - slice_base;
+        if (bin < a.slice_bins) hist_add<U16>(hist, bin);
+    });
+    __syncthreads();
+
+    // the slice's valid bins, an even number per thread (whole u16 pairs)
+    const uint64_t left = (uint64_t)a.nb - slice_base;
+    const uint32_t nvalid = left < a.slice_bins ? (uint32_t)left : a.slice_bins;
+    const uint32_t per = ((nvalid + kHashThreads - 1) / kHashThreads + 1) & ~1u;
+    const uint32_t lo = min(tid * per, nvalid), hi = min(lo + per, nvalid);
+    uint32_t nbk = 0, nmem = 0;
+    for (uint32_t b = lo; b < hi; ++b) {
+        const uint32_t c = hist_get<U16>(hist, b);
+        if (c >= g.s && c > 0) {
+            nbk += 1;
+            nmem += c;
+        }
+    }
+    if (!EMIT) {
+        // totals of the (item, slice)
+        const uint32_t tb = wave_sum(nbk), tm = wave_sum(nmem);
+        if (lane_id() == 0) {
+            scan[2 * (tid >> 6)] = tb;
+            scan[2 * (tid >> 6) + 1] = tm;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int64_t sb = 0, sm = 0;
+            for (int w = 0; w < kHashThreads / 64; ++w) {
+                sb += scan[2 * w];
+                sm += scan[2 * w + 1];
+            }
+            g.tot_b[e] = sb;
+            g.tot_m[e] = sm;
+        }
+        return;
+    }
+    // exclusive scan of the per-thread (buckets, members) over the workgroup
+    scan[tid] = nbk;
+    scan[kHashThreads + tid] = nmem;
+    __syncthreads();
+    for (int o = 1; o < kHashThreads; o <<= 1) {
+        const uint32_t ub = tid >= o ? scan[tid - o] : 0u, um = tid >= o ? scan[kHashThreads + tid - o] : 0u;
+        __syncthreads();
+        scan[tid] += ub;
+        scan[kHashThreads + tid] += um;
+        __syncthreads();
+    }
+    uint32_t bi = scan[tid] - nbk, mi = scan[kHashThreads + tid] - nmem;
+    const int64_t bb = g.base_b[e], mb = g.base_m[e];
+    constexpr uint32_t kNone = U16 ? 0xffffu : 0xffffffffu;
+    for (uint32_t b = lo; b < hi; ++b) {
+        const uint32_t c = hist_get<U16>(hist, b);
+        if (c >= g.s && c > 0) {
+            const int64_t idx = bb + bi;
+            if (idx < g.cap_b)
+                g.buckets[idx] = pm_bucket{(uint32_t)j, slice_base + b, c, (uint32_t)(mb + mi)};
+            hist_set<U16>(hist, b, mi);
+            bi += 1;
+            mi += c;
+        } else {
+            hist_set<U16>(hist, b, kNone);
+        }
+    }
+    __syncthreads();
+    // members: each window of a passing bin takes the bin's next slot
+    for_each_key<A, K>(a, st, pos, [&](int64_t w, uint32_t key) {
+        const uint32_t bin = key - slice_base;
+        if (bin < a.slice_bins && hist_get<U16>(hist, bin) != kNone) {
+            uint32_t slot;
+            if (U16) slot = (atomicAdd(hist + (bin >> 1), 1u << ((bin & 1) << 4)) >> ((bin & 1) << 4)) & 0xffffu;
+            else slot = atomicAdd(hist + bin, 1u);
+            const int64_t ms = mb + slot;
+            if (ms < g.cap_m) g.members[ms] = (uint32_t)w;
+        }
+    });
+}
+
 template <int A, int K, bool U16>
 static int launch_hash(const HashArgs &a, size_t lds, int blocks, hipStream_t st)
 {
@@ -220,6 +401,46 @@ static int launch_hash(const HashArgs &a, size_t lds, int blocks, hipStream_t st
     hipLaunchKernelGGL((k_hash<A, K, U16>), dim3(blocks), dim3(kHashThreads), lds, st, a);
     PM_LAUNCHED();
     return PM_OK;
+}
+
+template <int A, int K, bool U16, bool EMIT>
+static int launch_hsel(const HselArgs &g, size_t lds, int blocks, hipStream_t st)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_hsel<A, K, U16, EMIT>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, device_lds_bytes());
+        (void)hipGetLastError();
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_hsel<A, K, U16, EMIT>), dim3(blocks), dim3(kHashThreads), lds, st, g);
+    PM_LAUNCHED();
+    return PM_OK;
+}
+
+template <int K>
+static int dispatch_hsel(int alphabet, int k, bool u16, bool emit, const HselArgs &g, size_t lds, int blocks,
+                         hipStream_t st)
+{
+    constexpr int KMAX = 12;  // |Sigma|^k within the LDS histogram's slices
+    if constexpr (K > KMAX) {
+        return fail(PM_ERANGE, "k=%d not supported by the fused selection", k);
+    } else {
+        if (k != K) return dispatch_hsel<K + 1>(alphabet, k, u16, emit, g, lds, blocks, st);
+        if (alphabet == 4) {
+            if (u16) return emit ? launch_hsel<4, K, true, true>(g, lds, blocks, st)
+                                 : launch_hsel<4, K, true, false>(g, lds, blocks, st);
+            return emit ? launch_hsel<4, K, false, true>(g, lds, blocks, st)
+                        : launch_hsel<4, K, false, false>(g, lds, blocks, st);
+        }
+        if constexpr (K <= 5) {
+            if (u16) return emit ? launch_hsel<20, K, true, true>(g, lds, blocks, st)
+                                 : launch_hsel<20, K, true, false>(g, lds, blocks, st);
+            return emit ? launch_hsel<20, K, false, true>(g, lds, blocks, st)
+                        : launch_hsel<20, K, false, false>(g, lds, blocks, st);
+        }
+        return fail(PM_ERANGE, "k=%d not supported by the fused selection for protein", k);
+    }
 }
 
 // run-time (alphabet, k, histogram width) -> compile-time kernel
@@ -267,21 +488,25 @@ extern "C" int pm_pack(int32_t alphabet, const uint8_t *ascii, int64_t n_total, 
     return PM_OK;
 }
 
-// sizes the LDS (staged input, histogram slices) for the largest instance
-// and launches one workgroup per (item, slice)
-static int hash_launch(HashArgs &a, int A, int32_t items, int64_t x_max, int64_t nw_max, int t_max,
-                       hipStream_t st)
+// LDS layout for the largest instance (staged input, histogram slices):
+// returns the dynamic LDS bytes, or 0 after fail().  extra: further fixed LDS
+// words; balance: split a whole-trial histogram that would leave its
+// workgroup alone on a CU into two slices.
+static size_t hash_layout(HashArgs &a, bool hist, int64_t x_max, int64_t nw_max, int t_max, int extra, bool balance)
 {
     const bool u16 = x_max < 65536;
     const int lds_max = device_lds_bytes();
     a.seq_cap = nw_max * 4 <= 48 * 1024 ? (int)nw_max : 0;
     a.off_cap = (t_max + 1) * 4 <= 8 * 1024 ? t_max + 1 : 0;
-    const int fixed = (a.seq_cap + a.off_cap) * 4;
-    if (a.counts) {
+    const int fixed = (a.seq_cap + a.off_cap + extra) * 4;
+    if (hist) {
         const int64_t need_words = u16 ? (a.nb + 1) / 2 : a.nb;
         int64_t budget = (lds_max - fixed) / 4;
         budget &= ~int64_t(3);
-        if (budget < 1024) return fail(PM_ERANGE, "input too large for the LDS budget");
+        if (budget < 1024) {
+            fail(PM_ERANGE, "input too large for the LDS budget");
+            return 0;
+        }
         int64_t hw = std::min<int64_t>(need_words, budget);
         // a whole-trial histogram that fits one workgroup but leaves it alone on
         // its CU goes into two balanced slices instead, so that two workgroups
@@ -289,7 +514,7 @@ static int hash_launch(HashArgs &a, int A, int32_t items, int64_t x_max, int64_t
         // (each slice recomputes the trial's keys; measured 11% faster on the
         // (18,6) workload's 128 KB histograms)
         const int64_t half = ((int64_t)lds_max / 2 - fixed) / 4;
-        if (need_words <= budget && need_words > half && half >= 1024) hw = (need_words + 1) / 2;
+        if (balance && need_words <= budget && need_words > half && half >= 1024) hw = (need_words + 1) / 2;
         hw = (hw + 3) & ~int64_t(3);
         if (hw > budget) hw = budget;
         a.hist_words = (int)hw;
@@ -300,10 +525,71 @@ static int hash_launch(HashArgs &a, int A, int32_t items, int64_t x_max, int64_t
         a.slice_bins = 0;
         a.nslices = 1;
     }
-    const size_t lds = (size_t)a.hist_words * 4 + fixed;
+    return (size_t)a.hist_words * 4 + fixed;
+}
+
+// sizes the LDS for the largest instance and launches one workgroup per
+// (item, slice)
+static int hash_launch(HashArgs &a, int A, int32_t items, int64_t x_max, int64_t nw_max, int t_max,
+                       hipStream_t st)
+{
+    const size_t lds = hash_layout(a, a.counts != nullptr, x_max, nw_max, t_max, 0, true);
+    if (!lds) return PM_ERANGE;
     const int64_t blocks = (int64_t)items * a.nslices;
     if (blocks > 0x7fffffff) return fail(PM_ERANGE, "too many trials x slices");
-    return dispatch_hash<1>(A, a.k, u16, a, lds, (int)blocks, st);
+    return dispatch_hash<1>(A, a.k, x_max < 65536, a, lds, (int)blocks, st);
+}
+
+// ---- fused selection: workspace of per-(item, slice) totals and bases
+static int64_t hsel_entries(HashArgs a, int32_t items, int64_t x_max, int64_t nw_max, int t_max)
+{
+    if (!hash_layout(a, true, x_max, nw_max, t_max, kHselScanWords, false)) return -1;
+    return (int64_t)items * a.nslices;
+}
+
+static size_t hsel_ws_bytes(int64_t entries) { return entries < 0 ? 0 : (size_t)entries * 4 * sizeof(int64_t) + 256; }
+
+static int check_hsel_args(int A, int l, int k, const uint32_t *masks, int64_t items, const int64_t *n_out,
+                           pm_bucket *buckets, int64_t cap_b, uint32_t *members, int64_t cap_m, void *ws)
+{
+    if (k < 1 || k > l) return fail(PM_EINVAL, "need 1 <= k <= l (k=%d, l=%d)", k, l);
+    if (items < 1) return fail(PM_EINVAL, "need at least one trial");
+    if (!masks || !n_out || !ws) return fail(PM_EINVAL, "masks, n_out and ws are required");
+    if (cap_b < 0 || cap_m < 0) return fail(PM_EINVAL, "negative capacity");
+    if ((cap_b > 0 && !buckets) || (cap_m > 0 && !members)) return fail(PM_EINVAL, "NULL output with a non-zero capacity");
+    if (cap_m > 0xffffffffll) return fail(PM_ERANGE, "cap_members must be below 2^32");
+    if ((A == 4 && k > 12) || (A == 20 && k > 5)) return fail(PM_ERANGE, "|Sigma|^k too large for the fused selection (k=%d)", k);
+    return PM_OK;
+}
+
+static int hsel_run(HashArgs &a, int A, int32_t items, int64_t x_max, int64_t nw_max, int t_max, uint32_t s,
+                    pm_bucket *buckets, int64_t cap_b, uint32_t *members, int64_t cap_m, int64_t *n_out, void *ws,
+                    size_t ws_bytes, hipStream_t st)
+{
+    const size_t lds = hash_layout(a, true, x_max, nw_max, t_max, kHselScanWords, false);
+    if (!lds) return PM_ERANGE;
+    const int64_t entries = (int64_t)items * a.nslices;
+    if (entries > 0x7fffffff) return fail(PM_ERANGE, "too many trials x slices");
+    if (ws_bytes < hsel_ws_bytes(entries)) return fail(PM_EINVAL, "workspace of %zu bytes, need %zu", ws_bytes,
+                                                      hsel_ws_bytes(entries));
+    int64_t *w = static_cast<int64_t *>(ws);
+    HselArgs g{};
+    g.h = a;
+    g.s = s;
+    g.tot_b = w;
+    g.tot_m = w + entries;
+    g.base_b = w + 2 * entries;
+    g.base_m = w + 3 * entries;
+    g.buckets = buckets;
+    g.members = members;
+    g.cap_b = cap_b;
+    g.cap_m = cap_m;
+    const bool u16 = x_max < 65536;
+    if (int rc = dispatch_hsel<1>(A, a.k, u16, false, g, lds, (int)entries, st)) return rc;
+    const TotScan ts{g.tot_b, g.tot_m, w + 2 * entries, w + 3 * entries, entries, cap_b, cap_m, n_out, a.status};
+    if (int rc = launch_tot_scan(ts, st)) return rc;
+    if (cap_b == 0 && cap_m == 0) return PM_OK;  // sizing only
+    return dispatch_hsel<1>(A, a.k, u16, true, g, lds, (int)entries, st);
 }
 
 static int check_hash_args(int A, int l, int k, const uint32_t *masks, int64_t items, const uint32_t *keys,
@@ -362,4 +648,67 @@ extern "C" int projection_hash_batch(const pm_batch *B, const uint32_t *masks, u
     a.l = B->l;
     a.k = B->k;
     return hash_launch(a, A, B->items, info.x_max, info.nw_max, info.t_max, as_stream(stream));
+}
+
+extern "C" size_t pm_hash_select_workspace(const pm_seqs *S, int32_t l, int32_t k, int32_t m)
+{
+    clear_error();
+    if (check_seqs(S, l) != PM_OK || k < 1 || k > l || m < 1) return 0;
+    HashArgs a{};
+    a.nb = ipow(S->alphabet, k);
+    return hsel_ws_bytes(hsel_entries(a, m, num_windows(S, l), pm_packed_words(S->alphabet, S->n_total), S->t));
+}
+
+extern "C" size_t pm_hash_select_batch_workspace(const pm_batch *B)
+{
+    clear_error();
+    BatchInfo info;
+    if (check_batch(B, &info) != PM_OK) return 0;
+    HashArgs a{};
+    a.nb = ipow(B->alphabet, B->k);
+    return hsel_ws_bytes(hsel_entries(a, B->items, info.x_max, info.nw_max, info.t_max));
+}
+
+extern "C" int bucket_hash_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m,
+                                  uint32_t s, pm_bucket *buckets, int64_t cap_buckets, uint32_t *members,
+                                  int64_t cap_members, int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status,
+                                  void *stream)
+{
+    clear_error();
+    int rc = check_seqs(S, l);
+    if (rc) return rc;
+    const int A = S->alphabet;
+    if ((rc = check_hsel_args(A, l, k, masks, m, n_out, buckets, cap_buckets, members, cap_members, ws))) return rc;
+    HashArgs a{};
+    a.one = inst_of(S, l);
+    a.masks = masks;
+    a.status = status;
+    a.nb = ipow(A, k);
+    a.l = l;
+    a.k = k;
+    return hsel_run(a, A, m, a.one.x, pm_packed_words(A, S->n_total), S->t, s, buckets, cap_buckets, members,
+                    cap_members, n_out, ws, ws_bytes, as_stream(stream));
+}
+
+extern "C" int bucket_hash_select_batch(const pm_batch *B, const uint32_t *masks, uint32_t s, pm_bucket *buckets,
+                                        int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out,
+                                        void *ws, size_t ws_bytes, uint32_t *status, void *stream)
+{
+    clear_error();
+    BatchInfo info;
+    int rc = check_batch(B, &info);
+    if (rc) return rc;
+    const int A = B->alphabet;
+    if ((rc = check_hsel_args(A, B->l, B->k, masks, B->items, n_out, buckets, cap_buckets, members, cap_members, ws)))
+        return rc;
+    HashArgs a{};
+    a.inst = B->inst;
+    a.item_inst = B->item_inst;
+    a.masks = masks;
+    a.status = status;
+    a.nb = ipow(A, B->k);
+    a.l = B->l;
+    a.k = B->k;
+    return hsel_run(a, A, B->items, info.x_max, info.nw_max, info.t_max, s, buckets, cap_buckets, members,
+                    cap_members, n_out, ws, ws_bytes, as_stream(stream));
 }

@@ -55,6 +55,17 @@ struct BatchInfo {
 };
 int check_batch(const pm_batch *B, BatchInfo *info);
 
+// exclusive scan of n per-entry (bucket, member) totals into bases; writes the
+// grand totals to n_out and PM_STATUS_CAPACITY when they exceed the capacities
+struct TotScan {
+    const int64_t *ne, *ms;
+    int64_t *bb, *mb;
+    int64_t n, cap_b, cap_m;
+    int64_t *n_out;
+    uint32_t *status;
+};
+int launch_tot_scan(const TotScan &a, hipStream_t st);
+
 int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
                    const int64_t *n_dev, int32_t iters, double beta, double *theta_out, double *J_out,
                    double *llr_out, int32_t *sites_out, void *ws, size_t ws_bytes, bool split, hipStream_t st);

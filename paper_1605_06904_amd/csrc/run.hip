@@ -349,121 +349,77 @@ __global__ void k_count_by_instance(const pm_bucket *bk, const int64_t *n_dev, i
 }
 
 // ---------------------------------------------------------------- a batch of problems
-int run_group(const std::vector<const Prepared *> &G, const std::vector<pm_result *> &Rs, const pm_options &O,
-              const TriageModel *tri, hipStream_t st)
-{
-    const Prepared &q0 = *G[0];
-    const int A = q0.A, l = q0.l, k = q0.k, s = q0.s, P = (int)G.size();
-    const int per = A == 4 ? 16 : 6;
-    const int iters = O.em_iters, it1 = iters + 1, AL = A * l;
-    for (int p = 0; p < P; ++p) empty_result(*Rs[p], *G[p]);
+// Device inputs of one group of problems, packed once: every instance's words,
+// offsets and masks, and the instance table over the whole group.
+struct GroupDev {
+    int A, l, k, s, t_max;
+    DevBuf packed, off, masks, bg, status;
+    std::vector<pm_inst> inst;     // host table over the group (device pointers set)
+    std::vector<int64_t> nb, nm;   // enriched buckets and members of every instance
+};
 
-    // host layout: instance p's ASCII padded with code-0 letters to whole
-    // packed words (including pm_pack's four padding words), its local offsets
-    std::vector<int64_t> word_base(P), off_base(P);
-    int64_t words = 0, offs = 0, items = 0, keys_total = 0;
-    int t_max = 0;
-    for (int p = 0; p < P; ++p) {
-        word_base[p] = words;
-        off_base[p] = offs;
-        words += pm_packed_words(A, G[p]->n_total);
-        offs += G[p]->t + 1;
-        items += G[p]->m;
-        keys_total += (int64_t)G[p]->m * G[p]->x;
-        t_max = std::max(t_max, G[p]->t);
+// Bytes one enriched bucket costs through the rest of the path (lists,
+// profiles, models, objectives, sites; the two triage lists when on).
+size_t bytes_per_bucket(int AL, int it1, int t_max, bool triage)
+{
+    size_t b = sizeof(pm_bucket) + (size_t)AL * (4 + 8 + 8) + (size_t)it1 * 16 + (size_t)t_max * 4;
+    if (triage)
+        b += (size_t)PM_TRIAGE_INPUTS * 4 + 4 + 1 +
+             2 * (sizeof(pm_bucket) + (size_t)AL * 16 + 8 + (size_t)it1 * 16 + (size_t)t_max * 4);
+    return b;
+}
+
+// The sub-batch of instances [p0, p1): its own instance table (items and key
+// bases restarting at 0), the fused selection, profiles, theta^0, EM (all
+// buckets, or triaged), the best model of every instance, copied into Rs.
+int run_sub(GroupDev &D, int p0, int p1, const std::vector<const Prepared *> &G, const std::vector<pm_result *> &Rs,
+            const pm_options &O, const TriageModel *tri, hipStream_t st)
+{
+    const int A = D.A, l = D.l, k = D.k, s = D.s, P = p1 - p0, t_max = D.t_max;
+    const int iters = O.em_iters, it1 = iters + 1, AL = A * l;
+    std::vector<pm_inst> inst(D.inst.begin() + p0, D.inst.begin() + p1);
+    const int64_t item0 = inst[0].first_item;
+    int64_t items = 0, key = 0;
+    for (pm_inst &I : inst) {
+        I.first_item = (int32_t)items;
+        I.key_base = key;
+        items += I.m;
+        key += (int64_t)I.m * I.x;
     }
-    if (items > 0x7fffffff) return fail(PM_ERANGE, "more than 2^31 - 1 trials in one batch");
-    std::vector<uint8_t> ascii((size_t)(words * per), (uint8_t)'A');
-    std::vector<int64_t> off((size_t)offs);
-    std::vector<uint32_t> masks((size_t)items);
     std::vector<int32_t> item_inst((size_t)items);
-    std::vector<pm_inst> inst(P);
-    {
-        int64_t it = 0, key = 0;
-        for (int p = 0; p < P; ++p) {
-            const Prepared &Q = *G[p];
-            memcpy(ascii.data() + word_base[p] * per, Q.ascii.data(), (size_t)Q.n_total);
-            memcpy(off.data() + off_base[p], Q.off.data(), sizeof(int64_t) * (Q.t + 1));
-            memcpy(masks.data() + it, Q.masks.data(), sizeof(uint32_t) * Q.m);
-            for (int j = 0; j < Q.m; ++j) item_inst[it + j] = p;
-            pm_inst &I = inst[p];
-            I.n_total = Q.n_total;
-            I.x = Q.x;
-            I.key_base = key;
-            I.t = Q.t;
-            I.n_min = Q.n_min;
-            I.m = Q.m;
-            I.first_item = (int32_t)it;
-            it += Q.m;
-            key += (int64_t)Q.m * Q.x;
-        }
-    }
-    const int64_t nb = ipow(A, k);
-    DevBuf d_ascii, d_off, d_packed, d_masks, d_inst, d_item, d_keys, d_counts, d_status, d_nout, d_ws, d_bg;
-    PM_CALL(d_ascii.alloc(ascii.size()));
-    PM_CALL(d_off.alloc(sizeof(int64_t) * off.size()));
-    PM_CALL(d_packed.alloc(sizeof(uint32_t) * pm_packed_words(A, (int64_t)ascii.size())));
-    PM_CALL(d_masks.alloc(sizeof(uint32_t) * items));
+    for (int p = 0; p < P; ++p)
+        for (int j = 0; j < inst[p].m; ++j) item_inst[inst[p].first_item + j] = p;
+    DevBuf d_inst, d_item, d_nout, d_ws;
     PM_CALL(d_inst.alloc(sizeof(pm_inst) * P));
     PM_CALL(d_item.alloc(sizeof(int32_t) * items));
-    PM_CALL(d_keys.alloc(sizeof(uint32_t) * (size_t)keys_total));
-    PM_CALL(d_counts.alloc(sizeof(uint32_t) * (size_t)items * nb));
-    PM_CALL(d_status.alloc(sizeof(uint32_t)));
     PM_CALL(d_nout.alloc(sizeof(int64_t) * 2));
-    PM_CALL(d_bg.alloc(sizeof(double) * A));
-    for (int p = 0; p < P; ++p) {
-        inst[p].offsets = d_off.as<int64_t>() + off_base[p];
-        inst[p].packed = d_packed.as<uint32_t>() + word_base[p];
-    }
-    PM_TRY(hipMemcpyAsync(d_ascii.p, ascii.data(), ascii.size(), hipMemcpyHostToDevice, st));
-    PM_TRY(hipMemcpyAsync(d_off.p, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice, st));
-    PM_TRY(hipMemcpyAsync(d_masks.p, masks.data(), sizeof(uint32_t) * items, hipMemcpyHostToDevice, st));
     PM_TRY(hipMemcpyAsync(d_inst.p, inst.data(), sizeof(pm_inst) * P, hipMemcpyHostToDevice, st));
     PM_TRY(hipMemcpyAsync(d_item.p, item_inst.data(), sizeof(int32_t) * items, hipMemcpyHostToDevice, st));
-    PM_TRY(hipMemcpyAsync(d_bg.p, q0.bg.data(), sizeof(double) * A, hipMemcpyHostToDevice, st));
-    PM_TRY(hipMemsetAsync(d_status.p, 0, sizeof(uint32_t), st));
-    PM_CALL(pm_pack(A, d_ascii.as<uint8_t>(), (int64_t)ascii.size(), d_packed.as<uint32_t>(), d_status.as<uint32_t>(),
-                    st));
     const pm_batch Bt{A, l, k, P, (int32_t)items, d_inst.as<pm_inst>(), inst.data(), d_item.as<int32_t>()};
-    PM_CALL(projection_hash_batch(&Bt, d_masks.as<uint32_t>(), d_keys.as<uint32_t>(), d_counts.as<uint32_t>(),
-                                  d_status.as<uint32_t>(), st));
-    PM_CALL(d_ws.alloc(pm_select_workspace((int32_t)items, 0)));
-    PM_CALL(bucket_select_batch(&Bt, d_keys.as<uint32_t>(), d_counts.as<uint32_t>(), (uint32_t)s, nullptr, 0, nullptr,
-                                0, d_nout.as<int64_t>(), d_ws.p, pm_select_workspace((int32_t)items, 0), nullptr, st));
-    int64_t nout[2];
-    uint32_t status = 0;
-    std::vector<int64_t> per_trial((size_t)items);
-    PM_TRY(hipMemcpyAsync(nout, d_nout.p, sizeof(nout), hipMemcpyDeviceToHost, st));
-    PM_TRY(hipMemcpyAsync(&status, d_status.p, sizeof(status), hipMemcpyDeviceToHost, st));
-    // the selection workspace starts with the number of enriched buckets of every trial item
-    PM_TRY(hipMemcpyAsync(per_trial.data(), d_ws.p, sizeof(int64_t) * items, hipMemcpyDeviceToHost, st));
-    PM_TRY(hipStreamSynchronize(st));
-    if (status & PM_STATUS_BAD_SYMBOL) return fail(PM_EINVAL, "a sequence holds a symbol outside the alphabet");
-    if (status & PM_STATUS_BAD_MASK) return fail(PM_EINVAL, "bad projection mask");
-    for (int p = 0; p < P; ++p) {
-        int64_t n = 0;
-        for (int j = 0; j < G[p]->m; ++j) n += per_trial[inst[p].first_item + j];
-        Rs[p]->n_enriched = n;
+    const uint32_t *masks = D.masks.as<uint32_t>() + item0;
+    int64_t nbk = 0, nmem = 0;
+    for (int p = p0; p < p1; ++p) {
+        nbk += D.nb[p];
+        nmem += D.nm[p];
     }
-    const int64_t nbk = nout[0], nmem = nout[1];
     if (nbk == 0) return PM_OK;
-
+    const size_t hws = pm_hash_select_batch_workspace(&Bt);
+    if (!hws) return PM_ERANGE;
     DevBuf d_bk, d_mem, d_prof, d_th0, d_th, d_J, d_llr, d_sites, d_best, d_cons, d_emws;
+    PM_CALL(d_ws.alloc(hws));
     PM_CALL(d_bk.alloc(sizeof(pm_bucket) * nbk));
     PM_CALL(d_mem.alloc(sizeof(uint32_t) * nmem));
-    PM_CALL(d_ws.alloc(pm_select_workspace((int32_t)items, nbk)));
-    PM_CALL(bucket_select_batch(&Bt, d_keys.as<uint32_t>(), d_counts.as<uint32_t>(), (uint32_t)s, d_bk.as<pm_bucket>(),
-                                nbk, d_mem.as<uint32_t>(), nmem, d_nout.as<int64_t>(), d_ws.p,
-                                pm_select_workspace((int32_t)items, nbk), d_status.as<uint32_t>(), st));
-    d_keys.release();
-    d_counts.release();
+    PM_CALL(bucket_hash_select_batch(&Bt, masks, (uint32_t)s, d_bk.as<pm_bucket>(), nbk, d_mem.as<uint32_t>(), nmem,
+                                     d_nout.as<int64_t>(), d_ws.p, hws, D.status.as<uint32_t>(), st));
+    d_ws.release();
     PM_CALL(d_prof.alloc(sizeof(uint32_t) * nbk * AL));
     PM_CALL(d_th0.alloc(sizeof(double) * nbk * AL));
     PM_CALL(d_best.alloc(sizeof(int64_t) * P));
     PM_CALL(d_cons.alloc((size_t)P * (l + 1)));
     PM_CALL(bucket_profile_batch(&Bt, d_bk.as<pm_bucket>(), d_mem.as<uint32_t>(), nmem, nbk, nullptr,
                                  d_prof.as<uint32_t>(), st));
-    PM_CALL(theta_init(A, l, d_prof.as<uint32_t>(), nbk, nullptr, d_bg.as<double>(), O.beta, d_th0.as<double>(), st));
+    d_mem.release();
+    PM_CALL(theta_init(A, l, d_prof.as<uint32_t>(), nbk, nullptr, D.bg.as<double>(), O.beta, d_th0.as<double>(), st));
     const size_t em_ws = pm_em_batch_workspace(&Bt, O.precision);
     if (em_ws) PM_CALL(d_emws.alloc(em_ws));
 
@@ -479,11 +435,12 @@ int run_group(const std::vector<const Prepared *> &G, const std::vector<pm_resul
     std::vector<unsigned long long> refined(P, 0);
 
     if (!tri) {
+        d_prof.release();
         PM_CALL(d_th.alloc(sizeof(double) * nbk * AL));
         PM_CALL(d_J.alloc(sizeof(double) * nbk * it1));
         PM_CALL(d_llr.alloc(sizeof(double) * nbk * it1));
         PM_CALL(d_sites.alloc(sizeof(int32_t) * nbk * t_max));
-        PM_CALL(em_refine_batch(&Bt, d_bk.as<pm_bucket>(), d_th0.as<double>(), d_bg.as<double>(), nbk, nullptr, iters,
+        PM_CALL(em_refine_batch(&Bt, d_bk.as<pm_bucket>(), d_th0.as<double>(), D.bg.as<double>(), nbk, nullptr, iters,
                                 O.beta, O.precision, d_th.as<double>(), d_J.as<double>(), d_llr.as<double>(),
                                 d_sites.as<int32_t>(), d_emws.p, em_ws, st));
         PM_CALL(em_best_batch(&Bt, d_bk.as<pm_bucket>(), d_J.as<double>(), nbk, nullptr, iters, d_th.as<double>(),
@@ -495,7 +452,7 @@ int run_group(const std::vector<const Prepared *> &G, const std::vector<pm_resul
                            g_which.as<int32_t>(), g_J.as<double>(), g_llr.as<double>(), g_theta.as<double>(),
                            g_sites.as<int32_t>(), g_bk.as<pm_bucket>());
         PM_LAUNCHED();
-        for (int p = 0; p < P; ++p) refined[p] = (unsigned long long)Rs[p]->n_enriched;
+        for (int p = 0; p < P; ++p) refined[p] = (unsigned long long)D.nb[p0 + p];
     } else {
         // scores of every bucket, then the two refinement lists
         DevBuf t_params, t_mu, t_sd, t_packed, t_feat, t_score, t_taken, t_sws, t_fell, t_z;
@@ -515,9 +472,11 @@ int run_group(const std::vector<const Prepared *> &G, const std::vector<pm_resul
         PM_TRY(hipMemcpyAsync(t_mu.p, tri->mu.data(), sizeof(float) * PM_TRIAGE_INPUTS, hipMemcpyHostToDevice, st));
         PM_TRY(hipMemcpyAsync(t_sd.p, tri->sd.data(), sizeof(float) * PM_TRIAGE_INPUTS, hipMemcpyHostToDevice, st));
         PM_CALL(triage_pack(t_params.as<float>(), t_packed.p, st));
-        PM_CALL(triage_features(l, d_prof.as<uint32_t>(), nbk, nullptr, d_bg.as<double>(), t_mu.as<float>(),
+        PM_CALL(triage_features(l, d_prof.as<uint32_t>(), nbk, nullptr, D.bg.as<double>(), t_mu.as<float>(),
                                 t_sd.as<float>(), t_feat.as<float>(), st));
         PM_CALL(triage_forward(t_packed.p, t_feat.as<float>(), nbk, nullptr, t_score.as<float>(), st));
+        d_prof.release();
+        t_feat.release();
         struct List {
             DevBuf bk, th0, index, n, th, J, llr, sites, best;
         } L[2];
@@ -533,7 +492,7 @@ int run_group(const std::vector<const Prepared *> &G, const std::vector<pm_resul
             PM_CALL(X.best.alloc(sizeof(int64_t) * P));
         }
         auto refine = [&](List &X) -> int {
-            PM_CALL(em_refine_batch(&Bt, X.bk.as<pm_bucket>(), X.th0.as<double>(), d_bg.as<double>(), nbk,
+            PM_CALL(em_refine_batch(&Bt, X.bk.as<pm_bucket>(), X.th0.as<double>(), D.bg.as<double>(), nbk,
                                     X.n.as<int64_t>(), iters, O.beta, O.precision, X.th.as<double>(), X.J.as<double>(),
                                     X.llr.as<double>(), X.sites.as<int32_t>(), d_emws.p, em_ws, st));
             return em_best_batch(&Bt, X.bk.as<pm_bucket>(), X.J.as<double>(), nbk, X.n.as<int64_t>(), iters,
@@ -580,6 +539,7 @@ int run_group(const std::vector<const Prepared *> &G, const std::vector<pm_resul
     std::vector<int32_t> sites((size_t)P * t_max);
     std::vector<pm_bucket> bk(P);
     std::vector<char> cons((size_t)P * (l + 1));
+    uint32_t status = 0;
     PM_TRY(hipMemcpyAsync(which.data(), g_which.p, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st));
     PM_TRY(hipMemcpyAsync(J.data(), g_J.p, sizeof(double) * P, hipMemcpyDeviceToHost, st));
     PM_TRY(hipMemcpyAsync(llr.data(), g_llr.p, sizeof(double) * P, hipMemcpyDeviceToHost, st));
@@ -587,9 +547,11 @@ int run_group(const std::vector<const Prepared *> &G, const std::vector<pm_resul
     PM_TRY(hipMemcpyAsync(sites.data(), g_sites.p, sizeof(int32_t) * P * t_max, hipMemcpyDeviceToHost, st));
     PM_TRY(hipMemcpyAsync(bk.data(), g_bk.p, sizeof(pm_bucket) * P, hipMemcpyDeviceToHost, st));
     PM_TRY(hipMemcpyAsync(cons.data(), d_cons.p, (size_t)P * (l + 1), hipMemcpyDeviceToHost, st));
+    PM_TRY(hipMemcpyAsync(&status, D.status.p, sizeof(status), hipMemcpyDeviceToHost, st));
     PM_TRY(hipStreamSynchronize(st));
+    if (status & PM_STATUS_CAPACITY) return fail(PM_EDEVICE, "bucket lists overflowed their counted sizes");
     for (int p = 0; p < P; ++p) {
-        pm_result &R = *Rs[p];
+        pm_result &R = *Rs[p0 + p];
         R.n_refined = (int64_t)refined[p];
         R.fallback_used = fell[p];
         if (which[p] == 0) continue;
@@ -598,8 +560,137 @@ int run_group(const std::vector<const Prepared *> &G, const std::vector<pm_resul
         R.best_trial = (int32_t)bk[p].trial - inst[p].first_item;
         R.best_key = bk[p].key;
         if (R.consensus) memcpy(R.consensus, cons.data() + (size_t)p * (l + 1), l + 1);
-        if (R.sites) memcpy(R.sites, sites.data() + (size_t)p * t_max, sizeof(int32_t) * G[p]->t);
+        if (R.sites) memcpy(R.sites, sites.data() + (size_t)p * t_max, sizeof(int32_t) * G[p0 + p]->t);
         if (R.theta) memcpy(R.theta, theta.data() + (size_t)p * AL, sizeof(double) * AL);
+    }
+    return PM_OK;
+}
+
+// A group of problems sharing alphabet, l, k, s and background: packed once,
+// counted once over all its trials (fused selection, counting pass only),
+// then streamed through the rest of the path in sub-batches of whole
+// instances whose buckets fit the memory budget.
+int run_group(const std::vector<const Prepared *> &G, const std::vector<pm_result *> &Rs, const pm_options &O,
+              const TriageModel *tri, hipStream_t st)
+{
+    const Prepared &q0 = *G[0];
+    const int A = q0.A, l = q0.l, k = q0.k, s = q0.s, P = (int)G.size();
+    const int per = A == 4 ? 16 : 6;
+    const int AL = A * l;
+    for (int p = 0; p < P; ++p) empty_result(*Rs[p], *G[p]);
+
+    // host layout: instance p's ASCII padded with code-0 letters to whole
+    // packed words (including pm_pack's four padding words), its local offsets
+    std::vector<int64_t> word_base(P), off_base(P);
+    int64_t words = 0, offs = 0, items = 0;
+    int t_max = 0;
+    for (int p = 0; p < P; ++p) {
+        word_base[p] = words;
+        off_base[p] = offs;
+        words += pm_packed_words(A, G[p]->n_total);
+        offs += G[p]->t + 1;
+        items += G[p]->m;
+        t_max = std::max(t_max, G[p]->t);
+    }
+    if (items > 0x7fffffff) return fail(PM_ERANGE, "more than 2^31 - 1 trials in one batch");
+    std::vector<uint8_t> ascii((size_t)(words * per), (uint8_t)'A');
+    std::vector<int64_t> off((size_t)offs);
+    std::vector<uint32_t> masks((size_t)items);
+    std::vector<int32_t> item_inst((size_t)items);
+    GroupDev D;
+    D.A = A;
+    D.l = l;
+    D.k = k;
+    D.s = s;
+    D.t_max = t_max;
+    D.inst.resize(P);
+    {
+        int64_t it = 0, key = 0;
+        for (int p = 0; p < P; ++p) {
+            const Prepared &Q = *G[p];
+            memcpy(ascii.data() + word_base[p] * per, Q.ascii.data(), (size_t)Q.n_total);
+            memcpy(off.data() + off_base[p], Q.off.data(), sizeof(int64_t) * (Q.t + 1));
+            memcpy(masks.data() + it, Q.masks.data(), sizeof(uint32_t) * Q.m);
+            for (int j = 0; j < Q.m; ++j) item_inst[it + j] = p;
+            pm_inst &I = D.inst[p];
+            I.n_total = Q.n_total;
+            I.x = Q.x;
+            I.key_base = key;
+            I.t = Q.t;
+            I.n_min = Q.n_min;
+            I.m = Q.m;
+            I.first_item = (int32_t)it;
+            it += Q.m;
+            key += (int64_t)Q.m * Q.x;
+        }
+    }
+    DevBuf d_ascii, d_inst, d_item, d_nout, d_ws;
+    PM_CALL(d_ascii.alloc(ascii.size()));
+    PM_CALL(D.off.alloc(sizeof(int64_t) * off.size()));
+    PM_CALL(D.packed.alloc(sizeof(uint32_t) * pm_packed_words(A, (int64_t)ascii.size())));
+    PM_CALL(D.masks.alloc(sizeof(uint32_t) * items));
+    PM_CALL(D.bg.alloc(sizeof(double) * A));
+    PM_CALL(D.status.alloc(sizeof(uint32_t)));
+    PM_CALL(d_inst.alloc(sizeof(pm_inst) * P));
+    PM_CALL(d_item.alloc(sizeof(int32_t) * items));
+    PM_CALL(d_nout.alloc(sizeof(int64_t) * 2));
+    for (int p = 0; p < P; ++p) {
+        D.inst[p].offsets = D.off.as<int64_t>() + off_base[p];
+        D.inst[p].packed = D.packed.as<uint32_t>() + word_base[p];
+    }
+    PM_TRY(hipMemcpyAsync(d_ascii.p, ascii.data(), ascii.size(), hipMemcpyHostToDevice, st));
+    PM_TRY(hipMemcpyAsync(D.off.p, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice, st));
+    PM_TRY(hipMemcpyAsync(D.masks.p, masks.data(), sizeof(uint32_t) * items, hipMemcpyHostToDevice, st));
+    PM_TRY(hipMemcpyAsync(d_inst.p, D.inst.data(), sizeof(pm_inst) * P, hipMemcpyHostToDevice, st));
+    PM_TRY(hipMemcpyAsync(d_item.p, item_inst.data(), sizeof(int32_t) * items, hipMemcpyHostToDevice, st));
+    PM_TRY(hipMemcpyAsync(D.bg.p, q0.bg.data(), sizeof(double) * A, hipMemcpyHostToDevice, st));
+    PM_TRY(hipMemsetAsync(D.status.p, 0, sizeof(uint32_t), st));
+    PM_CALL(pm_pack(A, d_ascii.as<uint8_t>(), (int64_t)ascii.size(), D.packed.as<uint32_t>(), D.status.as<uint32_t>(),
+                    st));
+    const pm_batch Bt{A, l, k, P, (int32_t)items, d_inst.as<pm_inst>(), D.inst.data(), d_item.as<int32_t>()};
+    // counting pass over every trial: totals per (item, key-range slice)
+    const size_t hws = pm_hash_select_batch_workspace(&Bt);
+    if (!hws) return PM_ERANGE;
+    PM_CALL(d_ws.alloc(hws));
+    PM_CALL(bucket_hash_select_batch(&Bt, D.masks.as<uint32_t>(), (uint32_t)s, nullptr, 0, nullptr, 0,
+                                     d_nout.as<int64_t>(), d_ws.p, hws, nullptr, st));
+    const int64_t entries = (int64_t)((hws - 256) / (4 * sizeof(int64_t)));
+    const int64_t nslices = entries / items;
+    std::vector<int64_t> tot((size_t)(2 * entries));
+    uint32_t status = 0;
+    PM_TRY(hipMemcpyAsync(tot.data(), d_ws.p, sizeof(int64_t) * 2 * entries, hipMemcpyDeviceToHost, st));
+    PM_TRY(hipMemcpyAsync(&status, D.status.p, sizeof(status), hipMemcpyDeviceToHost, st));
+    PM_TRY(hipStreamSynchronize(st));
+    d_ws.release();
+    if (status & PM_STATUS_BAD_SYMBOL) return fail(PM_EINVAL, "a sequence holds a symbol outside the alphabet");
+    D.nb.assign(P, 0);
+    D.nm.assign(P, 0);
+    for (int p = 0; p < P; ++p) {
+        const int64_t e0 = (int64_t)D.inst[p].first_item * nslices, e1 = e0 + (int64_t)D.inst[p].m * nslices;
+        for (int64_t e = e0; e < e1; ++e) {
+            D.nb[p] += tot[e];
+            D.nm[p] += tot[entries + e];
+        }
+        Rs[p]->n_enriched = D.nb[p];
+    }
+    // sub-batches of whole instances within the memory budget: about 45% of
+    // the free device memory for the per-bucket data of one sub-batch
+    size_t mfree = 0, mtotal = 0;
+    PM_TRY(hipMemGetInfo(&mfree, &mtotal));
+    const size_t budget = (size_t)(0.45 * (double)mfree);
+    const size_t per_b = bytes_per_bucket(AL, O.em_iters + 1, t_max, tri != nullptr);
+    int p0 = 0;
+    while (p0 < P) {
+        int p1 = p0;
+        size_t used = 0;
+        while (p1 < P) {
+            const size_t need = (size_t)D.nb[p1] * per_b + (size_t)D.nm[p1] * 4;
+            if (p1 > p0 && used + need > budget) break;
+            used += need;
+            ++p1;
+        }
+        PM_CALL(run_sub(D, p0, p1, G, Rs, O, tri, st));
+        p0 = p1;
     }
     return PM_OK;
 }

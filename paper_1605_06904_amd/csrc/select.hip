@@ -84,16 +84,17 @@ __global__ void __launch_bounds__(256) k_sel_count(const SelArgs a)
     }
 }
 
-// exclusive scan of the per-trial totals (one workgroup)
-__global__ void __launch_bounds__(1024) k_sel_scan(const SelArgs a)
+// exclusive scan of per-trial (or per trial-slice) totals, one workgroup:
+// bases of every entry, the required totals in n_out, capacity status
+__global__ void __launch_bounds__(1024) k_tot_scan(const TotScan a)
 {
     __shared__ int64_t sa[1024], sb[1024];
     __shared__ int64_t carry[2];
     if (threadIdx.x == 0) carry[0] = carry[1] = 0;
     __syncthreads();
-    for (int64_t base = 0; base < a.m; base += 1024) {
+    for (int64_t base = 0; base < a.n; base += 1024) {
         const int64_t j = base + threadIdx.x;
-        const int64_t ve = j < a.m ? a.ws.ne[j] : 0, vm = j < a.m ? a.ws.ms[j] : 0;
+        const int64_t ve = j < a.n ? a.ne[j] : 0, vm = j < a.n ? a.ms[j] : 0;
         sa[threadIdx.x] = ve;
         sb[threadIdx.x] = vm;
         __syncthreads();
@@ -108,9 +109,9 @@ __global__ void __launch_bounds__(1024) k_sel_scan(const SelArgs a)
             sb[threadIdx.x] += ub;
             __syncthreads();
         }
-        if (j < a.m) {
-            a.ws.bb[j] = carry[0] + sa[threadIdx.x] - ve;
-            a.ws.mb[j] = carry[1] + sb[threadIdx.x] - vm;
+        if (j < a.n) {
+            a.bb[j] = carry[0] + sa[threadIdx.x] - ve;
+            a.mb[j] = carry[1] + sb[threadIdx.x] - vm;
         }
         __syncthreads();
         if (threadIdx.x == 1023) {
@@ -124,6 +125,13 @@ __global__ void __launch_bounds__(1024) k_sel_scan(const SelArgs a)
         a.n_out[1] = carry[1];
         if ((carry[0] > a.cap_b || carry[1] > a.cap_m) && a.status) atomicOr(a.status, PM_STATUS_CAPACITY);
     }
+}
+
+int launch_tot_scan(const TotScan &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tot_scan, dim3(1), dim3(1024), 0, st, a);
+    PM_LAUNCHED();
+    return PM_OK;
 }
 
 // exclusive prefix sums of n u32 values in place (256 threads, n <= 256 * 64)
@@ -365,8 +373,8 @@ static int select_launch(SelArgs &a, int A, int k, hipStream_t st)
     a.nb = ipow(A, k);
     hipLaunchKernelGGL(k_sel_count, dim3(a.m), dim3(256), 0, st, a);
     PM_LAUNCHED();
-    hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(1024), 0, st, a);
-    PM_LAUNCHED();
+    const TotScan ts{a.ws.ne, a.ws.ms, a.ws.bb, a.ws.mb, a.m, a.cap_b, a.cap_m, a.n_out, a.status};
+    if (int rc = launch_tot_scan(ts, st)) return rc;
     a.nwb = (int)((a.nb + 63) / 64);
     const size_t lds = (size_t)a.nwb * 16;
     static bool attr = false;
