@@ -42,6 +42,8 @@ def lib():
         L.or_hash.restype = _i32
         L.or_hash.argtypes = [_i32, _i32, _P, _P, _i32, _i32, _P, _i32, _P, _P]
         L.or_select.restype = _i32
+        L.or_select_sorted.restype = _i32
+        L.or_select_sorted.argtypes = [_i32, _P, _i32, _P, _i32, _u32, _P, _i64, _P, _i64, _P]
         L.or_select.argtypes = [_i32, _P, _i32, _i32, _i32, _P, _P, _i32, _u32,
                                 _P, _i64, _P, _i64, _P]
         L.or_profile.restype = None
@@ -146,6 +148,23 @@ def select(S: Seqs, l: int, k: int, keys: np.ndarray, counts: np.ndarray, s: int
                          _p(bk), cap_b, _p(mem), cap_m, _p(n))
     nb_, nm_ = int(n[0]), int(n[1])
     return bk[:min(nb_, cap_b)], mem[:min(nm_, cap_m)], (nb_, nm_), rc
+
+
+def select_sorted(S: Seqs, l: int, keys: np.ndarray, s: int):
+    """Enriched buckets of every trial from its keys alone (no count table):
+    (key, window) pairs sorted per trial, runs of at least s equal keys.
+    Same output as select()."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint32)
+    m = keys.shape[0]
+    n = np.zeros(2, dtype=np.int64)
+    rc = lib().or_select_sorted(S.t, _p(S.off), l, _p(keys), m, s, None, 0, None, 0, _p(n))
+    if rc == -2:
+        raise MemoryError("or_select_sorted")
+    cap_b, cap_m = int(n[0]), int(n[1])
+    bk = np.zeros((max(cap_b, 1), 4), dtype=np.uint32)
+    mem = np.zeros(max(cap_m, 1), dtype=np.uint32)
+    rc = lib().or_select_sorted(S.t, _p(S.off), l, _p(keys), m, s, _p(bk), cap_b, _p(mem), cap_m, _p(n))
+    return bk[:cap_b], mem[:cap_m], (int(n[0]), int(n[1])), rc
 
 
 def profile(S: Seqs, l: int, bk: np.ndarray, members: np.ndarray) -> np.ndarray:

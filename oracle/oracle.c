@@ -185,6 +185,63 @@ int or_select(int t, const int64_t *off, int l, int A, int k,
     return (nbk > cap_b || nmem > cap_m) ? -3 : 0;
 }
 
+/* The same enriched-bucket list without the |Sigma|^k count table (Alg. 2
+ * step 3 for alphabets and k whose table does not fit; the paper's own answer
+ * to that space problem is its K2 of Sec. 6).  Definition used here: sort
+ * every trial's (key, window) pairs by key, then window; a run of equal keys
+ * is one bucket, enriched when its length is at least s.  Same output order
+ * and contents as or_select (buckets by (trial, key), members ascending).
+ * Needs keys only.  Returns 0, -3 on a too small capacity, -2 on no memory. */
+typedef struct { uint32_t key, w; } or_kw;
+
+static int cmp_kw(const void *pa, const void *pb)
+{
+    const or_kw *a = (const or_kw *)pa, *b = (const or_kw *)pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    if (a->w != b->w) return a->w < b->w ? -1 : 1;
+    return 0;
+}
+
+int or_select_sorted(int t, const int64_t *off, int l, const uint32_t *keys, int m, uint32_t s,
+                     uint32_t *bk, int64_t cap_b, uint32_t *members, int64_t cap_m, int64_t *n_out)
+{
+    int64_t x = windows_total(t, off, l);
+    int64_t nbk = 0, nmem = 0;
+    or_kw *v = (or_kw *)malloc((size_t)(x > 0 ? x : 1) * sizeof(or_kw));
+    if (!v) return -2;
+    for (int j = 0; j < m; ++j) {
+        const uint32_t *kj = keys + (int64_t)j * x;
+        for (int64_t w = 0; w < x; ++w) {
+            v[w].key = kj[w];
+            v[w].w = (uint32_t)w;
+        }
+        qsort(v, (size_t)x, sizeof(or_kw), cmp_kw);
+        int64_t r0 = 0;
+        while (r0 < x) {
+            int64_t r1 = r0 + 1;
+            while (r1 < x && v[r1].key == v[r0].key) ++r1;
+            int64_t size = r1 - r0;
+            if (size >= (int64_t)s) {
+                if (nbk < cap_b) {
+                    bk[4 * nbk + 0] = (uint32_t)j;
+                    bk[4 * nbk + 1] = v[r0].key;
+                    bk[4 * nbk + 2] = (uint32_t)size;
+                    bk[4 * nbk + 3] = (uint32_t)nmem;
+                }
+                for (int64_t q = r0; q < r1; ++q)
+                    if (nmem + (q - r0) < cap_m) members[nmem + (q - r0)] = v[q].w;
+                nbk += 1;
+                nmem += size;
+            }
+            r0 = r1;
+        }
+    }
+    free(v);
+    n_out[0] = nbk;
+    n_out[1] = nmem;
+    return (nbk > cap_b || nmem > cap_m) ? -3 : 0;
+}
+
 /* window number -> (sequence, start) */
 static void window_site(int t, const int64_t *off, int l, int64_t w, int *i_out, int64_t *a_out)
 {

@@ -221,6 +221,72 @@ def test_select_matches_brute():
             assert nb == sum(len(np.unique(keys[j])) for j in range(len(masks)))
 
 
+def _brute_enriched(seqs, l, masks, s, A):
+    """Enriched buckets by grouping the projected strings themselves (letters),
+    ordered by trial, then by the base-|Sigma| value of the string (digit of a
+    letter = its place in the code order), members in window order."""
+    L = oracle.letters(A)
+    win = brute.windows(seqs, l)
+    exp = []
+    for j, mk in enumerate(masks):
+        groups = {}
+        for w, (i, a) in enumerate(win):
+            groups.setdefault(brute.projected_string(seqs[i][a:a + l], int(mk)), []).append(w)
+        def val(z):
+            v = 0
+            for c in z:
+                v = v * A + L.index(c)
+            return v
+        for name in sorted(groups, key=val):
+            if len(groups[name]) >= s:
+                exp.append((j, name, groups[name]))
+    return exp
+
+
+@pytest.mark.parametrize("A,alpha,l,k", [(DNA, "dna", 16, 14), (DNA, "dna", 18, 16), (PROT, "protein", 9, 6),
+                                         (PROT, "protein", 10, 7)])
+def test_select_sorted_matches_brute_large_k(A, alpha, l, k):
+    """Alg. 2 step 3 without a count table (|Sigma|^k of 2^28 - 2^32 bins):
+    the sorted-runs oracle against brute-force grouping of projected strings.
+    Low-complexity sequences make buckets of every size at these k."""
+    rng = np.random.default_rng(11 + k)
+    L = oracle.letters(A)
+    seqs = random_sequences(rng, 4, [40, 33, 51, 28], alpha)
+    # a repeat-rich sequence over three letters, so that large k still gives
+    # buckets of several l-mers
+    seqs.append("".join(rng.choice(list(L[:3]), size=60)))
+    seqs.append(L[1] * 45)
+    masks = projection_masks(rng, l, k, 3)
+    S = oracle.Seqs(A, seqs)
+    keys, _ = oracle.hash_trials(S, l, k, masks, counts=False)
+    for s in (1, 2, 3, 7):
+        bk, mem, (nb, nm), rc = oracle.select_sorted(S, l, keys, s)
+        assert rc == 0
+        exp = _brute_enriched(seqs, l, masks, s, A)
+        assert nb == len(exp) and nm == sum(len(e[2]) for e in exp)
+        for b, (j, name, ws) in zip(bk, exp):
+            assert int(b[0]) == j and _key_to_string(int(b[1]), k, A) == name
+            assert int(b[2]) == len(ws)
+            assert list(mem[b[3]:b[3] + b[2]]) == ws
+        if s == 1:
+            assert nb == sum(len(np.unique(keys[j])) for j in range(len(masks)))
+
+
+def test_select_sorted_equals_count_table_select():
+    """Where the count table fits, both definitions of the enriched list
+    (table of counts, sorted runs) give the same bytes."""
+    rng = np.random.default_rng(12)
+    for A, alpha, l, k in ((DNA, "dna", 12, 7), (DNA, "dna", 9, 4), (PROT, "protein", 11, 3)):
+        inst_seqs = random_sequences(rng, 6, [300, 120, 77, 410, 260, 90], alpha)
+        masks = projection_masks(rng, l, k, 5)
+        S = oracle.Seqs(A, inst_seqs)
+        keys, counts = oracle.hash_trials(S, l, k, masks)
+        for s in (1, 2, 4):
+            b1, m1, n1, _ = oracle.select(S, l, k, keys, counts, s)
+            b2, m2, n2, _ = oracle.select_sorted(S, l, keys, s)
+            assert n1 == n2 and np.array_equal(b1, b2) and np.array_equal(m1, m2)
+
+
 def test_select_capacity_truncates_and_reports():
     rng = np.random.default_rng(4)
     seqs = random_sequences(rng, 3, 30, "dna")
