@@ -56,6 +56,13 @@ def lib():
         L.or_mstep.argtypes = [_i32, _P, _P, _i32, _i32, _P, _P, _dbl, _P]
         L.or_em.restype = None
         L.or_em.argtypes = [_i32, _P, _P, _i32, _i32, _P, _P, _i64, _i32, _dbl, _P, _P, _P, _P]
+        L.or_estep_model.restype = _dbl
+        L.or_estep_model.argtypes = [_i32, _dbl, _i32, _P, _P, _i32, _i32, _P, _P, _P, _P, _P]
+        L.or_mstep_model.restype = None
+        L.or_mstep_model.argtypes = [_i32, _i32, _P, _P, _i32, _i32, _P, _P, _dbl, _dbl, _P, _P]
+        L.or_em_model.restype = None
+        L.or_em_model.argtypes = [_i32, _dbl, _i32, _P, _P, _i32, _i32, _P, _P, _i64, _i32, _dbl, _P, _P, _P,
+                                  _P, _P]
         L.or_best.restype = _i64
         L.or_best.argtypes = [_P, _i64, _i32, _P, _i32, _i32, C.c_char_p]
         L.or_parkmiller.restype = _u32
@@ -215,6 +222,46 @@ def em(S: Seqs, l: int, theta0_: np.ndarray, bg: np.ndarray, iters: int, beta: f
                 _p(np.ascontiguousarray(bg, dtype=np.float64)), B, iters, float(beta),
                 _p(th), _p(J), _p(LL), _p(sites))
     return th, J, LL, sites
+
+
+OOPS, ZOOPS, TCM = 0, 1, 2
+
+
+def estep_model(S: Seqs, l: int, model: int, mix: float, theta: np.ndarray, bg: np.ndarray):
+    """One E-step of the OOPS, ZOOPS or TCM model: (LLR, s[x], Z[x], q[t])."""
+    x = S.nwin(l)
+    s = np.zeros(max(x, 1))
+    Z = np.zeros(max(x, 1))
+    q = np.zeros(max(S.t, 1))
+    v = lib().or_estep_model(model, float(mix), S.t, _p(S.off), _p(S.codes), l, S.A,
+                             _p(np.ascontiguousarray(theta, dtype=np.float64)),
+                             _p(np.ascontiguousarray(bg, dtype=np.float64)), _p(s), _p(Z), _p(q))
+    return float(v), s[:x], Z[:x], q[:S.t]
+
+
+def mstep_model(S: Seqs, l: int, model: int, Z: np.ndarray, bg: np.ndarray, beta: float, mix: float):
+    """The M-step of the model given posteriors Z: (theta', mix')."""
+    th = np.zeros((S.A, l))
+    mx = np.zeros(1)
+    lib().or_mstep_model(model, S.t, _p(S.off), _p(S.codes), l, S.A, _p(np.ascontiguousarray(Z, dtype=np.float64)),
+                         _p(np.ascontiguousarray(bg, dtype=np.float64)), float(beta), float(mix), _p(th), _p(mx))
+    return th, float(mx[0])
+
+
+def em_model(S: Seqs, l: int, model: int, mix0: float, theta0_: np.ndarray, bg: np.ndarray, iters: int,
+             beta: float):
+    """EM of the OOPS, ZOOPS or TCM model: (theta, mix, J, LLR, sites)."""
+    th0 = np.ascontiguousarray(theta0_, dtype=np.float64)
+    B = th0.shape[0]
+    th = np.zeros_like(th0)
+    mix = np.zeros(B)
+    J = np.zeros((B, iters + 1))
+    LL = np.zeros((B, iters + 1))
+    sites = np.zeros((B, S.t), dtype=np.int32)
+    lib().or_em_model(model, float(mix0), S.t, _p(S.off), _p(S.codes), l, S.A, _p(th0),
+                      _p(np.ascontiguousarray(bg, dtype=np.float64)), B, iters, float(beta), _p(th), _p(mix),
+                      _p(J), _p(LL), _p(sites))
+    return th, mix, J, LL, sites
 
 
 def best(J: np.ndarray, theta: np.ndarray):

@@ -145,3 +145,77 @@ def oops_objective(seqs: Sequence[str], l: int, theta: Dict[str, List[float]], b
     products) plus the log prior beta * sum_c bg_c sum_p ln theta_c[p]."""
     pri = sum(bg[c] * math.log(theta[c][p]) for c in bg for p in range(l))
     return oops_loglik_ratio(seqs, l, theta, bg) + beta * pri
+
+
+def _site_product(S: str, l: int, a: int, theta: Dict[str, List[float]], bg: Dict[str, float]) -> float:
+    """P(S | the motif starts at a) by an explicit product over every letter."""
+    pr = 1.0
+    for j, ch in enumerate(S):
+        pr *= theta[ch][j - a] if a <= j < a + l else bg[ch]
+    return pr
+
+
+def zoops_loglik_ratio(seqs: Sequence[str], l: int, theta: Dict[str, List[float]], bg: Dict[str, float],
+                       gamma: float) -> float:
+    """ln P(S | ZOOPS) / P(S | background) by explicit products: each sequence
+    holds no site with probability 1 - gamma, else one site at a uniform start
+    (Sec. 2: at most one occurrence per sequence)."""
+    total = 0.0
+    for S in seqs:
+        L = len(S) - l + 1
+        back = math.prod(bg[ch] for ch in S)
+        acc = (1.0 - gamma) * back + sum(gamma / L * _site_product(S, l, a, theta, bg) for a in range(L))
+        total += math.log(acc / back)
+    return total
+
+
+def zoops_posterior(S: str, l: int, theta: Dict[str, List[float]], bg: Dict[str, float],
+                    gamma: float) -> List[float]:
+    """P(site at a | S) under ZOOPS by Bayes' rule over explicit products (the
+    remaining mass is the no-site case)."""
+    L = len(S) - l + 1
+    back = math.prod(bg[ch] for ch in S)
+    w = [gamma / L * _site_product(S, l, a, theta, bg) for a in range(L)]
+    z = (1.0 - gamma) * back + sum(w)
+    return [v / z for v in w]
+
+
+def tcm_loglik_ratio(seqs: Sequence[str], l: int, theta: Dict[str, List[float]], bg: Dict[str, float],
+                     lam: float) -> float:
+    """ln of the TCM likelihood ratio: every window independently an
+    occurrence with probability lam (Sec. 2: zero or more occurrences),
+    explicit products per window."""
+    total = 0.0
+    for S in seqs:
+        for a in range(len(S) - l + 1):
+            w = S[a:a + l]
+            motif = math.prod(theta[ch][p] for p, ch in enumerate(w))
+            back = math.prod(bg[ch] for ch in w)
+            total += math.log(((1.0 - lam) * back + lam * motif) / back)
+    return total
+
+
+def tcm_posterior(S: str, l: int, theta: Dict[str, List[float]], bg: Dict[str, float], lam: float) -> List[float]:
+    out = []
+    for a in range(len(S) - l + 1):
+        w = S[a:a + l]
+        motif = lam * math.prod(theta[ch][p] for p, ch in enumerate(w))
+        back = (1.0 - lam) * math.prod(bg[ch] for ch in w)
+        out.append(motif / (motif + back))
+    return out
+
+
+def mixture_expected_loglik(seqs: Sequence[str], l: int, post: Sequence[Sequence[float]],
+                            theta: Dict[str, List[float]], mix: float, model: str) -> float:
+    """The part of the expected complete-data log-likelihood that depends on
+    (theta, mix): sum Z ln theta over the site columns, plus the mixing terms
+    (ZOOPS: per sequence q ln gamma + (1 - q) ln(1 - gamma), q = sum_a Z;
+    TCM: per window Z ln lam + (1 - Z) ln(1 - lam))."""
+    v = expected_complete_loglik(seqs, l, post, theta)
+    for ps in post:
+        if model == "zoops":
+            q = sum(ps)
+            v += q * math.log(mix) + (1.0 - q) * math.log(1.0 - mix)
+        else:
+            v += sum(z * math.log(mix) + (1.0 - z) * math.log(1.0 - mix) for z in ps)
+    return v

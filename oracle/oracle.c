@@ -401,6 +401,171 @@ void or_em(int t, const int64_t *off, const uint8_t *codes, int l, int A,
     }
 }
 
+/* ---------------------------------------------------------------------- */
+/* ZOOPS and TCM sequence models.  Sec. 2 names them beside OOPS: ZOOPS lets a
+ * sequence hold at most one occurrence (possibly none), TCM any number.  The
+ * paper gives no formulas; these are the two-component mixtures of the MEME
+ * papers it cites, with the motif model theta, the fixed background bg, a
+ * uniform start prior within a sequence and one mixing parameter `mix`:
+ *
+ * ZOOPS (mix = gamma, the prior probability that a sequence holds a site):
+ *   P(S_i) / P_bg(S_i) = (1 - gamma) + (gamma / L_i) sum_a e^{s_ia}
+ *   LLR_i = ln of that;  Z_ia = (gamma / L_i) e^{s_ia} / that ratio;
+ *   q_i = sum_a Z_ia, the posterior probability that S_i holds a site.
+ * TCM (mix = lambda, the probability that a window is an occurrence; windows
+ * are treated as independent draws, overlaps included):
+ *   per window  (1 - lambda) + lambda e^{s_ia};  LLR = sum over windows of its
+ *   ln;  Z_ia = lambda e^{s_ia} / ((1 - lambda) + lambda e^{s_ia}).
+ * M-step (both): counts c[c][p] = sum_{i,a} Z_ia [S_i[a+p] = c],
+ *   theta' = (c + beta*bg) / (sum_{i,a} Z_ia + beta),
+ *   ZOOPS gamma' = sum_{i,a} Z_ia / t;  TCM lambda' = sum_{i,a} Z_ia / x.
+ * J = LLR + beta * sum bg ln theta, as for OOPS; the mixing parameter has no
+ * prior (its update maximises the expected complete log-likelihood), so EM
+ * still never decreases J.  ZOOPS with gamma = 1 is OOPS.
+ * Sites: ZOOPS reports the best start of a sequence when q_i >= 1/2, else -1;
+ * TCM the best start when that window's Z_ia >= 1/2, else -1 (one site per
+ * sequence is reported even though TCM allows several).                     */
+#define OR_OOPS 0
+#define OR_ZOOPS 1
+#define OR_TCM 2
+
+/* ln(e^u + e^v), with e^{-inf} = 0 */
+static double log_add(double u, double v)
+{
+    if (u == -INFINITY) return v;
+    if (v == -INFINITY) return u;
+    double m = u > v ? u : v;
+    return m + log(exp(u - m) + exp(v - m));
+}
+
+/* One E-step of `model` for one model; s, Z: [x]; q: [t] (or NULL).
+ * Returns LLR. */
+double or_estep_model(int model, double mix, int t, const int64_t *off, const uint8_t *codes, int l, int A,
+                      const double *theta, const double *bg, double *s, double *Z, double *q)
+{
+    if (model == OR_OOPS) {
+        double llr = or_estep(t, off, codes, l, A, theta, bg, s, Z, NULL);
+        if (q)
+            for (int i = 0; i < t; ++i) q[i] = 1.0;
+        return llr;
+    }
+    double W[20 * 32];
+    for (int c = 0; c < A; ++c)
+        for (int p = 0; p < l; ++p) W[c * l + p] = log(theta[c * l + p]) - log(bg[c]);
+    const double lmix = log(mix), lnone = log(1.0 - mix);
+    double llr = 0;
+    int64_t w0 = 0;
+    for (int i = 0; i < t; ++i) {
+        int64_t L = (off[i + 1] - off[i]) - l + 1;
+        for (int64_t a = 0; a < L; ++a) {
+            double v = 0;
+            for (int p = 0; p < l; ++p) v += W[codes[off[i] + a + p] * l + p];
+            s[w0 + a] = v;
+        }
+        if (model == OR_ZOOPS) {
+            double mx = -INFINITY;
+            for (int64_t a = 0; a < L; ++a)
+                if (s[w0 + a] > mx) mx = s[w0 + a];
+            double sum = 0;
+            for (int64_t a = 0; a < L; ++a) sum += exp(s[w0 + a] - mx);
+            const double lsite = lmix - log((double)L) + mx + log(sum);
+            const double li = log_add(lnone, lsite);
+            for (int64_t a = 0; a < L; ++a) Z[w0 + a] = exp(lmix - log((double)L) + s[w0 + a] - li);
+            if (q) q[i] = exp(lsite - li);
+            llr += li;
+        } else {
+            for (int64_t a = 0; a < L; ++a) {
+                const double li = log_add(lnone, lmix + s[w0 + a]);
+                Z[w0 + a] = exp(lmix + s[w0 + a] - li);
+                llr += li;
+            }
+            if (q) {
+                double m = 0;
+                for (int64_t a = 0; a < L; ++a) m += Z[w0 + a];
+                q[i] = m;
+            }
+        }
+        w0 += L;
+    }
+    return llr;
+}
+
+/* The M-step of `model` given the posteriors Z: theta_new, and *mix_new. */
+void or_mstep_model(int model, int t, const int64_t *off, const uint8_t *codes, int l, int A, const double *Z,
+                    const double *bg, double beta, double mix, double *theta_new, double *mix_new)
+{
+    double cnt[20 * 32];
+    memset(cnt, 0, sizeof(cnt));
+    double total = 0;
+    int64_t w0 = 0;
+    for (int i = 0; i < t; ++i) {
+        int64_t L = (off[i + 1] - off[i]) - l + 1;
+        for (int64_t a = 0; a < L; ++a) {
+            for (int p = 0; p < l; ++p) cnt[codes[off[i] + a + p] * l + p] += Z[w0 + a];
+            total += Z[w0 + a];
+        }
+        w0 += L;
+    }
+    if (model == OR_OOPS) total = (double)t;
+    for (int c = 0; c < A; ++c)
+        for (int p = 0; p < l; ++p) theta_new[c * l + p] = (cnt[c * l + p] + beta * bg[c]) / (total + beta);
+    /* sum Z is at most t (ZOOPS) or x (TCM); rounding can pass that bound by
+     * an ulp, which would make ln(1 - mix) undefined, so the update is capped
+     * at 1 */
+    if (model == OR_ZOOPS) *mix_new = fmin(1.0, total / (double)t);
+    else if (model == OR_TCM) *mix_new = fmin(1.0, total / (double)w0);
+    else *mix_new = mix;
+}
+
+/* EM of `model` for B independent models from theta0 and mix0; outputs as
+ * or_em, plus mix_out[B] (the mixing parameter of the final E-step). */
+void or_em_model(int model, double mix0, int t, const int64_t *off, const uint8_t *codes, int l, int A,
+                 const double *theta0, const double *bg, int64_t B, int iters, double beta, double *theta_out,
+                 double *mix_out, double *J, double *llr, int32_t *sites)
+{
+    int64_t x = windows_total(t, off, l);
+#pragma omp parallel
+    {
+        double *s = (double *)malloc(sizeof(double) * (x > 0 ? x : 1));
+        double *Z = (double *)malloc(sizeof(double) * (x > 0 ? x : 1));
+        double *q = (double *)malloc(sizeof(double) * (t > 0 ? t : 1));
+        double th[20 * 32], th2[20 * 32];
+#pragma omp for schedule(dynamic)
+        for (int64_t b = 0; b < B; ++b) {
+            memcpy(th, theta0 + b * A * l, sizeof(double) * A * l);
+            double mix = mix0;
+            for (int it = 0; it <= iters; ++it) {
+                double v = or_estep_model(model, mix, t, off, codes, l, A, th, bg, s, Z, q);
+                llr[b * (iters + 1) + it] = v;
+                J[b * (iters + 1) + it] = v + prior_term(A, l, th, bg, beta);
+                if (it < iters) {
+                    double mix2 = mix;
+                    or_mstep_model(model, t, off, codes, l, A, Z, bg, beta, mix, th2, &mix2);
+                    memcpy(th, th2, sizeof(double) * A * l);
+                    mix = mix2;
+                }
+            }
+            memcpy(theta_out + b * A * l, th, sizeof(double) * A * l);
+            if (mix_out) mix_out[b] = mix;
+            int64_t w0 = 0;
+            for (int i = 0; i < t; ++i) {
+                int64_t L = (off[i + 1] - off[i]) - l + 1;
+                int64_t best = 0;
+                for (int64_t a = 1; a < L; ++a)
+                    if (s[w0 + a] > s[w0 + best]) best = a;
+                int keep = 1;
+                if (model == OR_ZOOPS) keep = q[i] >= 0.5;
+                else if (model == OR_TCM) keep = Z[w0 + best] >= 0.5;
+                sites[b * t + i] = keep ? (int32_t)best : -1;
+                w0 += L;
+            }
+        }
+        free(s);
+        free(Z);
+        free(q);
+    }
+}
+
 /* Sec. 5.1: the model with the highest objective is the answer.  Readings:
  * the objective is J(theta^iters); ties go to the lowest bucket index (the
  * lowest (trial, key)); the consensus takes in each column the letter of
