@@ -168,10 +168,27 @@ int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *keys,
  *   ws      device, pm_hash_select_workspace(S, l, k, m) bytes, 8-byte aligned;
  *           it starts with the number of enriched buckets of every (trial,
  *           key-range slice), trial-major (int64)
- * Limits: DNA k <= 12, protein k <= 5 (the histogram is sliced over
- * workgroups when it does not fit one workgroup's LDS). */
+ * Limits: DNA k <= 16, protein k <= 7.  DNA k <= 12 and protein k <= 5 use
+ * the LDS count table (sliced over workgroups when it does not fit one
+ * workgroup's LDS); larger k use the sorted selection below, whose members
+ * come in ascending window order. */
 size_t pm_hash_select_workspace(const pm_seqs *S, int32_t l, int32_t k, int32_t m);
 int bucket_hash_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m, uint32_t s,
+                       pm_bucket *buckets, int64_t cap_buckets, uint32_t *members, int64_t cap_members,
+                       int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status, void *stream);
+
+/* a3 + a4 + a5 for key spaces too large for a count table (the space
+ * problem Sec. 6 answers with its K2 kernel and Fig. 8): the same bucket
+ * list as bucket_select, formed by sorting each trial's (key, window) pairs
+ * by key within key-range slices in LDS instead of counting into |Sigma|^k
+ * bins.  Buckets ascending by (trial, key), members of each bucket in
+ * ascending window order, `first` and `size` identical to bucket_select's;
+ * n_out, truncation and bad masks as for bucket_hash_select (which calls this
+ * path itself for DNA k > 12 and protein k > 5).
+ *   ws   device, pm_sort_select_workspace(S, l, k, m) bytes, 8-byte aligned
+ * Limits: DNA 8 <= k <= 16, protein 4 <= k <= 7 (PM_ERANGE otherwise). */
+size_t pm_sort_select_workspace(const pm_seqs *S, int32_t l, int32_t k, int32_t m);
+int bucket_sort_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m, uint32_t s,
                        pm_bucket *buckets, int64_t cap_buckets, uint32_t *members, int64_t cap_members,
                        int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status, void *stream);
 
@@ -217,6 +234,37 @@ int em_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *b
               const int64_t *n_dev, int32_t iters, double beta, int32_t precision,
               double *theta_out, double *J_out, double *llr_out, int32_t *sites_out, void *ws,
               size_t ws_bytes, void *stream);
+
+/* Sequence models of Sec. 2: OOPS (exactly one occurrence per sequence, the
+ * model of em_refine), ZOOPS (zero or one) and TCM (zero or more). */
+#define PM_OOPS 0
+#define PM_ZOOPS 1
+#define PM_TCM 2
+
+/* a7 - a10 under ZOOPS or TCM (Sec. 2 defines both only in words; the
+ * readings are the two-component mixtures of the MEME papers the paper
+ * cites, with one mixing parameter `mix`):
+ *   ZOOPS (mix = gamma, the probability that a sequence holds a site):
+ *     LLR_i = ln((1 - gamma) + (gamma / L_i) sum_a e^{s_ia}),
+ *     Z_ia = (gamma / L_i) e^{s_ia - LLR_i},  gamma' = sum Z / t;
+ *   TCM (mix = lambda, the probability that a window is an occurrence,
+ *     windows independent):
+ *     LLR = sum_{i,a} ln((1 - lambda) + lambda e^{s_ia}),
+ *     Z_ia = lambda e^{s_ia} / ((1 - lambda) + lambda e^{s_ia}),
+ *     lambda' = sum Z / x;
+ *   both: theta' = (sum Z_ia [S_i[a+p] = c] + beta * bg) / (sum Z + beta),
+ *     J = LLR + beta * sum bg ln theta (never decreases), mix' capped at 1.
+ * model PM_OOPS calls em_refine (mix0 ignored, mix_out not written).
+ *   mix0      in (0, 1]; ZOOPS with gamma = 1 is OOPS
+ *   mix_out   device [B] mixing parameter of the final E-step, or NULL
+ *   sites_out device [B][t]: ZOOPS the best start of sequence i when its site
+ *             mass sum_a Z_ia >= 1/2, TCM when that start's Z >= 1/2, else -1
+ * Other arguments as em_refine; precision PM_FP64 or PM_FP32 (the vector
+ * path), PM_EINVAL otherwise. */
+int em_refine_model(const pm_seqs *S, int32_t l, int32_t model, double mix0, const double *theta0,
+                    const double *bg, int64_t B, const int64_t *n_dev, int32_t iters, double beta,
+                    int32_t precision, double *theta_out, double *mix_out, double *J_out, double *llr_out,
+                    int32_t *sites_out, void *stream);
 /* Workspace bytes of em_refine: the one-hot tables of the DNA matrix-core
  * forms (t + ceil(x/32) window pairs of 1 KB + (4 ceil(l/4) + 12) x 64 B each);
  * 0 for the other forms or invalid arguments. */
@@ -305,6 +353,12 @@ size_t pm_hash_select_batch_workspace(const pm_batch *B);
 int bucket_hash_select_batch(const pm_batch *B, const uint32_t *masks, uint32_t s, pm_bucket *buckets,
                              int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out, void *ws,
                              size_t ws_bytes, uint32_t *status, void *stream);
+/* bucket_sort_select over a batch (trial = item number, as above).
+ *   ws  device, pm_sort_select_batch_workspace(B) bytes, 8-byte aligned */
+size_t pm_sort_select_batch_workspace(const pm_batch *B);
+int bucket_sort_select_batch(const pm_batch *B, const uint32_t *masks, uint32_t s, pm_bucket *buckets,
+                             int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out,
+                             void *ws, size_t ws_bytes, uint32_t *status, void *stream);
 
 /* a6 (profiles) for the buckets of a batch. */
 int bucket_profile_batch(const pm_batch *B, const pm_bucket *buckets, const uint32_t *members,

@@ -34,6 +34,8 @@ EXPORTS = [
     "triage_train_step", "pm_triage_select_workspace", "triage_select", "triage_fallback_select",
     "triage_merge_best", "em_autotune", "em_tuning", "em_set_tuning",
     "pm_hash_select_workspace", "bucket_hash_select", "pm_hash_select_batch_workspace", "bucket_hash_select_batch",
+    "pm_sort_select_workspace", "bucket_sort_select", "pm_sort_select_batch_workspace", "bucket_sort_select_batch",
+    "em_refine_model",
 ]
 
 PM_TRIAGE_PARAMS, PM_TRIAGE_INPUTS = 88577, 87
@@ -150,6 +152,13 @@ def lib():
                                          P]),
         "pm_hash_select_batch_workspace": (sz, [C.POINTER(pm_batch)]),
         "bucket_hash_select_batch": (C.c_int, [C.POINTER(pm_batch), P, u32, P, i64, P, i64, P, P, sz, P, P]),
+        "em_refine_model": (C.c_int, [C.POINTER(pm_seqs), i32, i32, dbl, P, P, i64, P, i32, dbl, i32, P, P, P, P,
+                                      P, P]),
+        "pm_sort_select_workspace": (sz, [C.POINTER(pm_seqs), i32, i32, i32]),
+        "bucket_sort_select": (C.c_int, [C.POINTER(pm_seqs), i32, i32, P, i32, u32, P, i64, P, i64, P, P, sz, P,
+                                         P]),
+        "pm_sort_select_batch_workspace": (sz, [C.POINTER(pm_batch)]),
+        "bucket_sort_select_batch": (C.c_int, [C.POINTER(pm_batch), P, u32, P, i64, P, i64, P, P, sz, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -237,6 +246,28 @@ def bucket_hash_select(S, l, k, masks, m, s, buckets, cap_buckets, members, cap_
                                     _stream(stream)))
 
 
+def pm_sort_select_workspace(S, l: int, k: int, m: int) -> int:
+    return int(lib().pm_sort_select_workspace(C.byref(S.c), l, k, m))
+
+
+def bucket_sort_select(S, l, k, masks, m, s, buckets, cap_buckets, members, cap_members, n_out, ws, ws_bytes,
+                       status=None, stream=None):
+    _check(lib().bucket_sort_select(C.byref(S.c), l, k, _ptr(masks), m, s, _ptr(buckets), cap_buckets,
+                                    _ptr(members), cap_members, _ptr(n_out), _ptr(ws), ws_bytes, _ptr(status),
+                                    _stream(stream)))
+
+
+def pm_sort_select_batch_workspace(B) -> int:
+    return int(lib().pm_sort_select_batch_workspace(C.byref(B.c)))
+
+
+def bucket_sort_select_batch(B, masks, s, buckets, cap_buckets, members, cap_members, n_out, ws, ws_bytes,
+                             status=None, stream=None):
+    _check(lib().bucket_sort_select_batch(C.byref(B.c), _ptr(masks), s, _ptr(buckets), cap_buckets, _ptr(members),
+                                          cap_members, _ptr(n_out), _ptr(ws), ws_bytes, _ptr(status),
+                                          _stream(stream)))
+
+
 def pm_hash_select_batch_workspace(B) -> int:
     return int(lib().pm_hash_select_batch_workspace(C.byref(B.c)))
 
@@ -283,6 +314,16 @@ def em_refine(S, l, theta0, bg, B, n_dev, iters, beta, precision, theta_out, J_o
     _check(lib().em_refine(C.byref(S.c), l, _ptr(theta0), _ptr(bg), B, _ptr(n_dev), iters, beta,
                            precision, _ptr(theta_out), _ptr(J_out), _ptr(llr_out), _ptr(sites_out),
                            _ptr(ws), ws_bytes, _stream(stream)))
+
+
+PM_OOPS, PM_ZOOPS, PM_TCM = 0, 1, 2
+
+
+def em_refine_model(S, l, model, mix0, theta0, bg, B, n_dev, iters, beta, precision, theta_out, mix_out, J_out,
+                    llr_out=None, sites_out=None, stream=None):
+    _check(lib().em_refine_model(C.byref(S.c), l, model, mix0, _ptr(theta0), _ptr(bg), B, _ptr(n_dev), iters, beta,
+                                 precision, _ptr(theta_out), _ptr(mix_out), _ptr(J_out), _ptr(llr_out),
+                                 _ptr(sites_out), _stream(stream)))
 
 
 def em_autotune(S, l, theta0, bg, B, iters, beta, precision, theta_out, J_out, stream=None, ws=None) -> int:

@@ -31,6 +31,9 @@ struct EmArgs {
     int l, iters;
     int site_stride;  // sites row length (t, or the largest t of a batch)
     double beta;
+    int model;        // PM_OOPS, PM_ZOOPS or PM_TCM
+    double mix0;      // ZOOPS gamma or TCM lambda of theta0
+    double *mix_out;  // [B] mixing parameter of the final E-step, or NULL
     int seq_cap;      // LDS words reserved for the packed input (0: read from global)
     int off_cap;      // LDS offsets reserved (0: read from global)
 };
@@ -47,6 +50,18 @@ __device__ __forceinline__ double ninf<double>() { return -INFINITY; }
 
 __device__ __forceinline__ float ex(float v) { return expf(v); }
 __device__ __forceinline__ double ex(double v) { return exp(v); }
+__device__ __forceinline__ float lg1p(float v) { return log1pf(v); }
+__device__ __forceinline__ double lg1p(double v) { return log1p(v); }
+
+// ln(e^u + e^v), e^{-inf} = 0
+template <typename T>
+__device__ __forceinline__ T log_add(T u, T v)
+{
+    if (u == ninf<T>()) return v;
+    if (v == ninf<T>()) return u;
+    const T d = u - v;
+    return (d > 0 ? u : v) + lg1p(ex(d > 0 ? -d : d));
+}
 
 template <typename V>
 __device__ __forceinline__ V block_sum(V v, V *red)
@@ -98,6 +113,7 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
     __shared__ T acc[kEmWaves][A * 32];
     __shared__ double red[kEmWaves];
     __shared__ double colsum[32];
+    __shared__ double ztot;
     extern __shared__ __align__(16) uint32_t dyn[];
     uint32_t *seq = dyn;
     int64_t *offs = reinterpret_cast<int64_t *>(dyn + ((a.seq_cap + 1) & ~1));
@@ -116,8 +132,11 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
     const uint32_t *W = a.seq_cap ? seq : I.packed;
     const int64_t *O = a.off_cap ? offs : I.offsets;
 
+    // mixing parameter of ZOOPS (gamma) or TCM (lambda); OOPS has none
+    double mix = a.mix0;
     for (int it = 0; it <= a.iters; ++it) {
         const bool last = it == a.iters;
+        const double lmix = log(mix), lnone = log1p(-mix);
         double pr = 0;
         for (int i = tid; i < AL; i += kEmThreads) {
             const int c = i / l;
@@ -132,6 +151,46 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
         for (int i = wv; i < t; i += kEmWaves) {
             const int64_t s0 = O[i];
             const int64_t L = O[i + 1] - s0 - l + 1;
+            if (a.model == PM_TCM) {
+                // every window its own two-component mixture: one sweep gives
+                // its log-likelihood term, its posterior and its counts
+                const T lm = (T)lmix, ln0 = (T)lnone;
+                double lsum = 0;
+                T bv = ninf<T>();
+                int64_t ba = 0;
+                T *ac = acc[wv];
+                for (int64_t x = lane; x < L; x += 64) {
+                    const T s = score_at<T, A>(W, s0 + x, Wt, l);
+                    const T v = lm + s;
+                    const T li = log_add(ln0, v);
+                    lsum += (double)li;
+                    if (last) {
+                        if (s > bv) {
+                            bv = s;
+                            ba = x;
+                        }
+                        continue;
+                    }
+                    const T z = v == ninf<T>() ? (T)0 : ex(v - li);
+                    const int64_t P = s0 + x;
+                    if (A == 4) {
+                        uint32_t hi, lo;
+                        dna_window(W, P, hi, lo);
+                        for (int p = 0; p < l; ++p) atomicAdd(&ac[dna_at(hi, lo, p) * l + p], z);
+                    } else {
+                        for (int p = 0; p < l; ++p) atomicAdd(&ac[prot_sym(W, P + p) * l + p], z);
+                    }
+                }
+                llr_w += wave_sum(lsum);
+                if (last && a.sites) {
+                    const T bm = wave_max(bv);
+                    const int64_t cand = wave_min_i64(bv == bm ? ba : INT64_MAX);
+                    // reported when that window's posterior is at least 1/2
+                    const bool keep = (double)bm + lmix >= lnone;
+                    if (lane == 0) a.sites[b * a.site_stride + i] = keep ? (int32_t)cand : -1;
+                }
+                continue;
+            }
             // online log-sum-exp, one exponential per window; the exponentials
             // are in T, their running sum is FP64 in both precisions
             T mx = ninf<T>(), bv = ninf<T>();
@@ -152,19 +211,33 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
             const double part = mx > ninf<T>() ? sm * (double)ex(mx - M) : 0.0;
             const double Ssum = wave_sum(part);
             const double lse = (double)M + log(Ssum);
-            llr_w += lse - log((double)L);
+            // OOPS: LLR_i = LSE_i - ln L_i, Z = e^{s - LSE_i}.  ZOOPS: the
+            // sequence holds no site with probability 1 - gamma, so
+            // LLR_i = ln((1 - gamma) + gamma e^{LSE_i} / L_i) and
+            // Z = gamma e^s / (L_i e^{LLR_i}); q_i = sum_a Z is its site mass
+            double li, zoff, qi = 1.0;
+            if (a.model == PM_ZOOPS) {
+                const double lsite = lmix - log((double)L) + lse;
+                li = log_add(lnone, lsite);
+                zoff = lmix - log((double)L) - li;
+                qi = exp(lsite - li);
+            } else {
+                li = lse - log((double)L);
+                zoff = -lse;
+            }
+            llr_w += li;
             if (last) {
                 if (a.sites) {
                     const T bm = wave_max(bv);
                     const int64_t cand = wave_min_i64(bv == bm ? ba : INT64_MAX);
-                    if (lane == 0) a.sites[b * a.site_stride + i] = (int32_t)cand;
+                    if (lane == 0) a.sites[b * a.site_stride + i] = qi >= 0.5 ? (int32_t)cand : -1;
                 }
             } else {
                 T *ac = acc[wv];
-                const T lse_t = (T)lse;
+                const T zo = (T)zoff;
                 for (int64_t x = lane; x < L; x += 64) {
                     const T s = score_at<T, A>(W, s0 + x, Wt, l);
-                    const T z = ex(s - lse_t);
+                    const T z = ex(s + zo);
                     const int64_t P = s0 + x;
                     if (A == 4) {
                         uint32_t hi, lo;
@@ -198,13 +271,20 @@ __global__ void __launch_bounds__(kEmThreads) k_em_vec(const EmArgs a)
                 double tot = 0;
                 for (int c = 0; c < A; ++c) tot += th[c * l + p];
                 colsum[p] = tot + beta;
+                if (p == 0) ztot = tot;
             }
             __syncthreads();
             for (int i = tid; i < AL; i += kEmThreads) th[i] = (th[i] + beta * a.bg[i / l]) / colsum[i % l];
+            // the mixing parameter's update: the posterior mass (every
+            // column's counts total it) over t sequences (ZOOPS) or x windows
+            // (TCM), capped at 1 against rounding
+            if (a.model == PM_ZOOPS) mix = fmin(1.0, ztot / (double)t);
+            else if (a.model == PM_TCM) mix = fmin(1.0, ztot / (double)I.x);
             __syncthreads();
         }
     }
     for (int i = tid; i < AL; i += kEmThreads) a.theta_out[b * AL + i] = th[i];
+    if (tid == 0 && a.mix_out) a.mix_out[b] = mix;
 }
 
 template <typename T, int A>
@@ -377,6 +457,43 @@ extern "C" int em_refine(const pm_seqs *S, int32_t l, const double *theta0, cons
     a.site_stride = S->t;
     a.beta = beta;
     return vec_launch(a, S->alphabet, precision, pm_packed_words(S->alphabet, S->n_total), S->t, st);
+}
+
+extern "C" int em_refine_model(const pm_seqs *S, int32_t l, int32_t model, double mix0, const double *theta0,
+                               const double *bg, int64_t B, const int64_t *n_dev, int32_t iters, double beta,
+                               int32_t precision, double *theta_out, double *mix_out, double *J_out,
+                               double *llr_out, int32_t *sites_out, void *stream)
+{
+    clear_error();
+    if (model == PM_OOPS)
+        return em_refine(S, l, theta0, bg, B, n_dev, iters, beta, precision, theta_out, J_out, llr_out, sites_out,
+                         nullptr, 0, stream);
+    int rc = check_seqs(S, l);
+    if (rc) return rc;
+    if (model != PM_ZOOPS && model != PM_TCM) return fail(PM_EINVAL, "unknown sequence model %d", model);
+    if (!(mix0 > 0.0 && mix0 <= 1.0)) return fail(PM_EINVAL, "the mixing parameter must lie in (0, 1] (%g)", mix0);
+    if (precision != PM_FP64 && precision != PM_FP32)
+        return fail(PM_EINVAL, "ZOOPS and TCM run in PM_FP64 or PM_FP32 (precision %d)", precision);
+    if ((rc = check_em_args(S->alphabet, B, iters, beta, precision, theta0, bg, theta_out, J_out))) return rc;
+    if (B == 0) return PM_OK;
+    EmArgs a{};
+    a.one = inst_of(S, l);
+    a.theta0 = theta0;
+    a.bg = bg;
+    a.n_dev = n_dev;
+    a.theta_out = theta_out;
+    a.J = J_out;
+    a.llr = llr_out;
+    a.sites = sites_out;
+    a.B = B;
+    a.l = l;
+    a.iters = iters;
+    a.site_stride = S->t;
+    a.beta = beta;
+    a.model = model;
+    a.mix0 = mix0;
+    a.mix_out = mix_out;
+    return vec_launch(a, S->alphabet, precision, pm_packed_words(S->alphabet, S->n_total), S->t, as_stream(stream));
 }
 
 extern "C" size_t pm_em_batch_workspace(const pm_batch *B, int32_t precision)

@@ -8,7 +8,7 @@
 // wave-aggregated atomics, then streams the histogram out as dense u32 counts.
 #include <algorithm>
 
-#include "pm_common.h"
+#include "hash_dev.h"
 
 namespace pm {
 
@@ -61,122 +61,6 @@ __global__ void k_pack(int A, const uint8_t *__restrict__ ascii, int64_t n, uint
 }
 
 // ---------------------------------------------------------------- a3 + a4
-struct HashArgs {
-    pm_inst one;               // the instance, when inst is NULL
-    const pm_inst *inst;       // batch: instance table, or NULL
-    const int32_t *item_inst;  // batch: instance of every trial item
-    const uint32_t *masks;
-    uint32_t *keys;
-    uint32_t *counts;
-    uint32_t *status;
-    int64_t nb;          // |Sigma|^k
-    int l, k;
-    int nslices;         // key-range slices per trial
-    uint32_t slice_bins; // bins per slice (multiple of 4)
-    int hist_words;      // LDS words of histogram
-    int seq_cap;         // LDS words reserved for the packed input (0: read from global)
-    int off_cap;         // LDS window starts reserved, t + 1 (0: read offsets from global)
-};
-
-constexpr int kHashThreads = 1024;
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// The instance of trial item j, with its packed input (and the window number
-// of every sequence start) staged in LDS when the launch reserved room.
-struct Staged {
-    pm_inst I;
-    const uint32_t *seq;  // LDS copy (seq_cap) or global words
-    const int32_t *wst;   // LDS window starts, when off_cap
-};
-
-template <int A>
-__device__ __forceinline__ Staged stage_input(const HashArgs &a, int j, uint32_t *seq, int32_t *wst)
-{
-    const pm_inst I = a.inst ? a.inst[a.item_inst[j]] : a.one;
-    const int seq_words = a.seq_cap ? (int)(A == 4 ? (I.n_total + 15) / 16 + 4 : (I.n_total + 5) / 6 + 4) : 0;
-    for (int i = threadIdx.x; i < seq_words; i += kHashThreads) seq[i] = I.packed[i];
-    if (a.off_cap)
-        for (int i = threadIdx.x; i <= I.t; i += kHashThreads) wst[i] = (int32_t)(I.offsets[i] - (int64_t)i * (a.l - 1));
-    return Staged{I, a.seq_cap ? seq : I.packed, wst};
-}
-
-// kept positions, ascending: the shift of each kept position's 2-bit field in
-// the 64-bit window (DNA), or the position itself (protein)
-template <int A, int K>
-__device__ __forceinline__ void kept_positions(uint32_t mask, int (&pos)[K])
-{
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        const int p = __builtin_ctz(mask);
-        pos[q] = A == 4 ? 62 - 2 * p : p;
-        mask &= mask - 1;
-    }
-}
-
-// fn(w, key) for every window w = tid, tid + kHashThreads, ... of the instance
-template <int A, int K, typename F>
-__device__ __forceinline__ void for_each_key(const HashArgs &a, const Staged &st, const int (&pos)[K], F &&fn)
-{
-    const int64_t x = st.I.x;
-    if (a.seq_cap && a.off_cap) {
-        // staged input: every read below is an LDS read, all indices 32-bit
-        // (n_total < 2^31)
-        const uint32_t *seq = st.seq;
-        const int32_t *wst = st.wst;
-        const uint32_t x32 = (uint32_t)x, lm1 = (uint32_t)(a.l - 1);
-        int i = 0;
-        for (uint32_t w = threadIdx.x; w < x32; w += kHashThreads) {
-            while ((int32_t)w >= wst[i + 1]) ++i;
-            const uint32_t P = w + (uint32_t)i * lm1;
-            uint32_t key = 0;
-            if (A == 4) {
-                const uint32_t wi = P >> 4, r = (P & 15u) << 1;
-                const uint32_t w0 = seq[wi], w1 = seq[wi + 1], w2 = seq[wi + 2];
-                const uint32_t hi = (uint32_t)((((uint64_t)w0 << 32) | w1) >> (32 - r));
-                const uint32_t lo = (uint32_t)((((uint64_t)w1 << 32) | w2) >> (32 - r));
-                const uint64_t win = ((uint64_t)hi << 32) | lo;
-#pragma unroll
-                for (int q = 0; q < K; ++q) key = (key << 2) | ((uint32_t)(win >> pos[q]) & 3u);
-            } else {
-#pragma unroll
-                for (int q = 0; q < K; ++q) {
-                    const uint32_t g = P + (uint32_t)pos[q];
-                    const uint32_t qq = div6(g);
-                    key = key * 20u + ((seq[qq] >> (27 - 5 * (g - 6u * qq))) & 31u);
-                }
-            }
-            fn((int64_t)w, key);
-        }
-    } else {
-        // large instances: packed input and offsets read from global memory
-        const uint32_t *W = st.seq;
-        const int64_t *O = st.I.offsets;
-        const int64_t lm1 = a.l - 1;
-        int i = 0;
-        for (int64_t w = threadIdx.x; w < x; w += kHashThreads) {
-            while (w >= O[i + 1] - (int64_t)(i + 1) * lm1) ++i;
-            const int64_t P = w + (int64_t)i * lm1;
-            uint32_t key = 0;
-            if (A == 4) {
-                uint32_t hi, lo;
-                dna_window(W, P, hi, lo);
-                const uint64_t win = ((uint64_t)hi << 32) | lo;
-#pragma unroll
-                for (int q = 0; q < K; ++q) key = (key << 2) | ((uint32_t)(win >> pos[q]) & 3u);
-            } else {
-#pragma unroll
-                for (int q = 0; q < K; ++q) key = key * 20u + prot_sym(W, P + pos[q]);
-            }
-            fn(w, key);
-        }
-    }
-}
-
-__device__ __forceinline__ bool mask_ok(const HashArgs &a, uint32_t mask)
-{
-    const uint32_t lmask = a.l == 32 ? 0xffffffffu : ((1u << a.l) - 1u);
-    return __popc(mask) == a.k && !(mask & ~lmask);
-}
 
 template <bool U16>
 __device__ __forceinline__ void hist_add(uint32_t *hist, uint32_t bin)
@@ -558,9 +442,12 @@ static int check_hsel_args(int A, int l, int k, const uint32_t *masks, int64_t i
     if (cap_b < 0 || cap_m < 0) return fail(PM_EINVAL, "negative capacity");
     if ((cap_b > 0 && !buckets) || (cap_m > 0 && !members)) return fail(PM_EINVAL, "NULL output with a non-zero capacity");
     if (cap_m > 0xffffffffll) return fail(PM_ERANGE, "cap_members must be below 2^32");
-    if ((A == 4 && k > 12) || (A == 20 && k > 5)) return fail(PM_ERANGE, "|Sigma|^k too large for the fused selection (k=%d)", k);
     return PM_OK;
 }
+
+// count-table (LDS histogram) selection for DNA k <= 12 and protein k <= 5;
+// larger key spaces go to the sorted selection
+static bool dense_sel(int A, int k) { return (A == 4 && k <= 12) || (A == 20 && k <= 5); }
 
 static int hsel_run(HashArgs &a, int A, int32_t items, int64_t x_max, int64_t nw_max, int t_max, uint32_t s,
                     pm_bucket *buckets, int64_t cap_b, uint32_t *members, int64_t cap_m, int64_t *n_out, void *ws,
@@ -654,9 +541,19 @@ extern "C" size_t pm_hash_select_workspace(const pm_seqs *S, int32_t l, int32_t 
 {
     clear_error();
     if (check_seqs(S, l) != PM_OK || k < 1 || k > l || m < 1) return 0;
+    const int A = S->alphabet;
+    const int64_t x = num_windows(S, l), nw = pm_packed_words(A, S->n_total);
+    if (!dense_sel(A, k)) return hsort_check_k(A, k) ? 0 : hsort_workspace(A, l, k, m, x, nw, S->t);
     HashArgs a{};
-    a.nb = ipow(S->alphabet, k);
-    return hsel_ws_bytes(hsel_entries(a, m, num_windows(S, l), pm_packed_words(S->alphabet, S->n_total), S->t));
+    a.nb = ipow(A, k);
+    return hsel_ws_bytes(hsel_entries(a, m, x, nw, S->t));
+}
+
+extern "C" size_t pm_sort_select_workspace(const pm_seqs *S, int32_t l, int32_t k, int32_t m)
+{
+    clear_error();
+    if (check_seqs(S, l) != PM_OK || k < 1 || k > l || m < 1 || hsort_check_k(S->alphabet, k)) return 0;
+    return hsort_workspace(S->alphabet, l, k, m, num_windows(S, l), pm_packed_words(S->alphabet, S->n_total), S->t);
 }
 
 extern "C" size_t pm_hash_select_batch_workspace(const pm_batch *B)
@@ -664,15 +561,25 @@ extern "C" size_t pm_hash_select_batch_workspace(const pm_batch *B)
     clear_error();
     BatchInfo info;
     if (check_batch(B, &info) != PM_OK) return 0;
+    const int A = B->alphabet;
+    if (!dense_sel(A, B->k))
+        return hsort_check_k(A, B->k) ? 0 : hsort_workspace(A, B->l, B->k, B->items, info.x_max, info.nw_max, info.t_max);
     HashArgs a{};
-    a.nb = ipow(B->alphabet, B->k);
+    a.nb = ipow(A, B->k);
     return hsel_ws_bytes(hsel_entries(a, B->items, info.x_max, info.nw_max, info.t_max));
 }
 
-extern "C" int bucket_hash_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m,
-                                  uint32_t s, pm_bucket *buckets, int64_t cap_buckets, uint32_t *members,
-                                  int64_t cap_members, int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status,
-                                  void *stream)
+extern "C" size_t pm_sort_select_batch_workspace(const pm_batch *B)
+{
+    clear_error();
+    BatchInfo info;
+    if (check_batch(B, &info) != PM_OK || hsort_check_k(B->alphabet, B->k)) return 0;
+    return hsort_workspace(B->alphabet, B->l, B->k, B->items, info.x_max, info.nw_max, info.t_max);
+}
+
+static int hash_select_one(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m, uint32_t s,
+                           pm_bucket *buckets, int64_t cap_buckets, uint32_t *members, int64_t cap_members,
+                           int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status, void *stream, bool sorted)
 {
     clear_error();
     int rc = check_seqs(S, l);
@@ -686,13 +593,17 @@ extern "C" int bucket_hash_select(const pm_seqs *S, int32_t l, int32_t k, const 
     a.nb = ipow(A, k);
     a.l = l;
     a.k = k;
-    return hsel_run(a, A, m, a.one.x, pm_packed_words(A, S->n_total), S->t, s, buckets, cap_buckets, members,
-                    cap_members, n_out, ws, ws_bytes, as_stream(stream));
+    const int64_t nw = pm_packed_words(A, S->n_total);
+    if (!sorted && dense_sel(A, k))
+        return hsel_run(a, A, m, a.one.x, nw, S->t, s, buckets, cap_buckets, members, cap_members, n_out, ws,
+                        ws_bytes, as_stream(stream));
+    return hsort_run(a, A, m, a.one.x, nw, S->t, s, buckets, cap_buckets, members, cap_members, n_out, ws, ws_bytes,
+                     as_stream(stream));
 }
 
-extern "C" int bucket_hash_select_batch(const pm_batch *B, const uint32_t *masks, uint32_t s, pm_bucket *buckets,
-                                        int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out,
-                                        void *ws, size_t ws_bytes, uint32_t *status, void *stream)
+static int hash_select_batch(const pm_batch *B, const uint32_t *masks, uint32_t s, pm_bucket *buckets,
+                             int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out, void *ws,
+                             size_t ws_bytes, uint32_t *status, void *stream, bool sorted)
 {
     clear_error();
     BatchInfo info;
@@ -709,6 +620,44 @@ extern "C" int bucket_hash_select_batch(const pm_batch *B, const uint32_t *masks
     a.nb = ipow(A, B->k);
     a.l = B->l;
     a.k = B->k;
-    return hsel_run(a, A, B->items, info.x_max, info.nw_max, info.t_max, s, buckets, cap_buckets, members,
-                    cap_members, n_out, ws, ws_bytes, as_stream(stream));
+    if (!sorted && dense_sel(A, B->k))
+        return hsel_run(a, A, B->items, info.x_max, info.nw_max, info.t_max, s, buckets, cap_buckets, members,
+                        cap_members, n_out, ws, ws_bytes, as_stream(stream));
+    return hsort_run(a, A, B->items, info.x_max, info.nw_max, info.t_max, s, buckets, cap_buckets, members,
+                     cap_members, n_out, ws, ws_bytes, as_stream(stream));
 }
+
+extern "C" int bucket_hash_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m,
+                                  uint32_t s, pm_bucket *buckets, int64_t cap_buckets, uint32_t *members,
+                                  int64_t cap_members, int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status,
+                                  void *stream)
+{
+    return hash_select_one(S, l, k, masks, m, s, buckets, cap_buckets, members, cap_members, n_out, ws, ws_bytes,
+                           status, stream, false);
+}
+
+extern "C" int bucket_sort_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m,
+                                  uint32_t s, pm_bucket *buckets, int64_t cap_buckets, uint32_t *members,
+                                  int64_t cap_members, int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status,
+                                  void *stream)
+{
+    return hash_select_one(S, l, k, masks, m, s, buckets, cap_buckets, members, cap_members, n_out, ws, ws_bytes,
+                           status, stream, true);
+}
+
+extern "C" int bucket_hash_select_batch(const pm_batch *B, const uint32_t *masks, uint32_t s, pm_bucket *buckets,
+                                        int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out,
+                                        void *ws, size_t ws_bytes, uint32_t *status, void *stream)
+{
+    return hash_select_batch(B, masks, s, buckets, cap_buckets, members, cap_members, n_out, ws, ws_bytes, status,
+                             stream, false);
+}
+
+extern "C" int bucket_sort_select_batch(const pm_batch *B, const uint32_t *masks, uint32_t s, pm_bucket *buckets,
+                                        int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out,
+                                        void *ws, size_t ws_bytes, uint32_t *status, void *stream)
+{
+    return hash_select_batch(B, masks, s, buckets, cap_buckets, members, cap_members, n_out, ws, ws_bytes, status,
+                             stream, true);
+}
+
