@@ -192,6 +192,24 @@ int bucket_sort_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *m
                        pm_bucket *buckets, int64_t cap_buckets, uint32_t *members, int64_t cap_members,
                        int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status, void *stream);
 
+/* bucket_hash_select without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, outputs and order as
+ * bucket_hash_select, minus ws/ws_bytes: the per-(trial, key-range slice)
+ * totals and bases live in a fixed device array of
+ * pm_hash_select_scratch_bytes() bytes (8 MiB) that each GPU holds from the
+ * first call on it until the process ends.  A call whose trials x slices need
+ * more (pm_hash_select_workspace() above that size, i.e. more than 262 136
+ * trial-slices) returns PM_ERANGE before anything is enqueued.  Nothing
+ * needs to start at zero: every call rewrites the entries it uses.  All calls
+ * on one GPU share the array, so calls that overlap on that GPU (different
+ * streams, or threads) race and must be serialised by the caller.  Allocates
+ * nothing (no hipMalloc, hipFree or allocating library call). */
+size_t pm_hash_select_scratch_bytes(void);
+int bucket_hash_select_noalloc(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m,
+                               uint32_t s, pm_bucket *buckets, int64_t cap_buckets, uint32_t *members,
+                               int64_t cap_members, int64_t *n_out, uint32_t *status, void *stream);
+
 /* a6 (first half) -- Sec. 2 profile matrix P(s) of each bucket's alignment.
  *   members      device [cap_members] as written by bucket_select; a bucket
  *                whose members run past cap_members gets an all-zero profile

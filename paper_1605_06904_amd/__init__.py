@@ -34,6 +34,7 @@ EXPORTS = [
     "triage_train_step", "pm_triage_select_workspace", "triage_select", "triage_fallback_select",
     "triage_merge_best", "em_autotune", "em_tuning", "em_set_tuning",
     "pm_hash_select_workspace", "bucket_hash_select", "pm_hash_select_batch_workspace", "bucket_hash_select_batch",
+    "pm_hash_select_scratch_bytes", "bucket_hash_select_noalloc",
     "pm_sort_select_workspace", "bucket_sort_select", "pm_sort_select_batch_workspace", "bucket_sort_select_batch",
     "em_refine_model",
 ]
@@ -159,6 +160,9 @@ def lib():
                                          P]),
         "pm_sort_select_batch_workspace": (sz, [C.POINTER(pm_batch)]),
         "bucket_sort_select_batch": (C.c_int, [C.POINTER(pm_batch), P, u32, P, i64, P, i64, P, P, sz, P, P]),
+        "pm_hash_select_scratch_bytes": (sz, []),
+        "bucket_hash_select_noalloc": (C.c_int, [C.POINTER(pm_seqs), i32, i32, P, i32, u32, P, i64, P, i64, P, P,
+                                                 P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -266,6 +270,16 @@ def bucket_sort_select_batch(B, masks, s, buckets, cap_buckets, members, cap_mem
     _check(lib().bucket_sort_select_batch(C.byref(B.c), _ptr(masks), s, _ptr(buckets), cap_buckets, _ptr(members),
                                           cap_members, _ptr(n_out), _ptr(ws), ws_bytes, _ptr(status),
                                           _stream(stream)))
+
+
+def pm_hash_select_scratch_bytes() -> int:
+    return int(lib().pm_hash_select_scratch_bytes())
+
+
+def bucket_hash_select_noalloc(S, l, k, masks, m, s, buckets, cap_buckets, members, cap_members, n_out, status=None,
+                               stream=None):
+    _check(lib().bucket_hash_select_noalloc(C.byref(S.c), l, k, _ptr(masks), m, s, _ptr(buckets), cap_buckets,
+                                            _ptr(members), cap_members, _ptr(n_out), _ptr(status), _stream(stream)))
 
 
 def pm_hash_select_batch_workspace(B) -> int:

@@ -7,6 +7,7 @@
 // with coalesced stores and counts them in an LDS histogram with
 // wave-aggregated atomics, then streams the histogram out as dense u32 counts.
 #include <algorithm>
+#include <mutex>
 
 #include "hash_dev.h"
 
@@ -661,3 +662,73 @@ extern "C" int bucket_sort_select_batch(const pm_batch *B, const uint32_t *masks
                              stream, true);
 }
 
+// ---- allocation-free form of the fused selection
+// The per-(trial, slice) totals and bases live in a fixed device array instead
+// of a caller workspace.  Its host-side name is not a device address: every
+// use goes through the address hipGetSymbolAddress returns on each device.
+constexpr size_t kHselScratchBytes = size_t(8) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kHselScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(PM_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PM_EDEVICE, "device %d beyond the %d this library tracks", dev,
+                                                  kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PM_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PM_OK;
+}
+
+extern "C" size_t pm_hash_select_scratch_bytes(void) { return kHselScratchBytes; }
+
+extern "C" int bucket_hash_select_noalloc(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m,
+                                          uint32_t s, pm_bucket *buckets, int64_t cap_buckets, uint32_t *members,
+                                          int64_t cap_members, int64_t *n_out, uint32_t *status, void *stream)
+{
+    clear_error();
+    int rc = check_seqs(S, l);
+    if (rc) return rc;
+    const int A = S->alphabet;
+    // the scratch stands in for the workspace: pass its address as non-NULL
+    // only after the size check below, so the argument check sees a workspace
+    if ((rc = check_hsel_args(A, l, k, masks, m, n_out, buckets, cap_buckets, members, cap_members,
+                              reinterpret_cast<void *>(uintptr_t(1)))))
+        return rc;
+    HashArgs a{};
+    a.one = inst_of(S, l);
+    a.masks = masks;
+    a.status = status;
+    a.nb = ipow(A, k);
+    a.l = l;
+    a.k = k;
+    const int64_t nw = pm_packed_words(A, S->n_total);
+    const bool dense = dense_sel(A, k);
+    if (!dense && (rc = hsort_check_k(A, k))) return rc;
+    const size_t need = dense ? hsel_ws_bytes(hsel_entries(a, m, a.one.x, nw, S->t))
+                              : hsort_workspace(A, l, k, m, a.one.x, nw, S->t);
+    if (need == 0) return fail(PM_ERANGE, "this instance does not fit the fused selection's LDS layout");
+    if (need > kHselScratchBytes)
+        return fail(PM_ERANGE, "%d trials need %zu bytes of scratch; the fixed scratch holds %zu (at most %zu "
+                               "trial-slices)",
+                    m, need, kHselScratchBytes, (kHselScratchBytes - 256) / (4 * sizeof(int64_t)));
+    void *ws = nullptr;
+    if ((rc = scratch_address(&ws))) return rc;
+    if (dense)
+        return hsel_run(a, A, m, a.one.x, nw, S->t, s, buckets, cap_buckets, members, cap_members, n_out, ws,
+                        kHselScratchBytes, as_stream(stream));
+    return hsort_run(a, A, m, a.one.x, nw, S->t, s, buckets, cap_buckets, members, cap_members, n_out, ws,
+                     kHselScratchBytes, as_stream(stream));
+}
