@@ -60,6 +60,16 @@ def lib():
         L.or_estep_model.argtypes = [_i32, _dbl, _i32, _P, _P, _i32, _i32, _P, _P, _P, _P, _P]
         L.or_mstep_model.restype = None
         L.or_mstep_model.argtypes = [_i32, _i32, _P, _P, _i32, _i32, _P, _P, _dbl, _dbl, _P, _P]
+        L.or_philox4x64.restype = None
+        L.or_philox4x64.argtypes = [_P, _P, _P]
+        L.or_gibbs_uniform.restype = _dbl
+        L.or_gibbs_uniform.argtypes = [_u64, _i32, _i32, _i64]
+        L.or_gibbs_weights.restype = None
+        L.or_gibbs_weights.argtypes = [_i32, _P, _P, _i32, _i32, _P, _dbl, _P, _i32, _P]
+        L.or_alignment_score.restype = _dbl
+        L.or_alignment_score.argtypes = [_i32, _P, _P, _i32, _i32, _P, _dbl, _P, _P]
+        L.or_gibbs.restype = _i32
+        L.or_gibbs.argtypes = [_i32, _P, _P, _i32, _i32, _P, _P, _i64, _i32, _dbl, _u64, _P, _P, _P]
         L.or_em_model.restype = None
         L.or_em_model.argtypes = [_i32, _dbl, _i32, _P, _P, _i32, _i32, _P, _P, _i64, _i32, _dbl, _P, _P, _P,
                                   _P, _P]
@@ -338,3 +348,86 @@ def run(seqs: Sequence[str], A: int, l: int, k: int, s: int, masks: np.ndarray, 
     return dict(S=S, keys=keys, counts=counts, buckets=bk, members=mem, profile=prof,
                 theta0=th0, theta=th, J=J, llr=LL, sites=sites, best=b, consensus=cons,
                 bg=bgv)
+
+
+def run_range(seqs: Sequence[str], A: int, l_minus: int, l_plus: int, d: int, seed: int, iters: int,
+              beta: float = 1.0, bg: np.ndarray | None = None, k: int = 0, s: int = 0, m: int = 0):
+    """A motif-length range (l-, l+) (Sec. 2): the whole path at every length,
+    k, s, m from auto_params (Sec. 5) unless given, masks from the seeded
+    Park-Miller tables (Sec. 6); the chosen length has the largest
+    log-likelihood ratio per motif column, the longer on ties (the paper does
+    not say how lengths compete).  Returns (per-length dicts, chosen l or -1)."""
+    out = []
+    S = Seqs(A, seqs)
+    bgv = bg if bg is not None else bg_vector(A, None, S)
+    for l in range(l_minus, l_plus + 1):
+        x = S.nwin(l)
+        ak, as_, am = auto_params(l, d, S.t, x, A) if (k <= 0 or s <= 0 or m <= 0) else (k, s, m)
+        kk, ss, mm = (k if k > 0 else ak), (s if s > 0 else as_), (m if m > 0 else am)
+        masks = masks_from_seed(seed, l, kk, mm)
+        keys, counts = hash_trials(S, l, kk, masks, counts=float(A) ** kk <= 2 ** 22)
+        if counts is not None:
+            bk, mem, _, _ = select(S, l, kk, keys, counts, ss)
+        else:
+            bk, mem, _, _ = select_sorted(S, l, keys, ss)
+        r = dict(l=l, k=kk, s=ss, m=mm, n_enriched=len(bk), consensus="", llr=-math.inf, J=-math.inf, best=-1)
+        if len(bk):
+            prof = profile(S, l, bk, mem)
+            th0 = theta0(prof, bgv, beta)
+            th, J, LL, sites = em(S, l, th0, bgv, iters, beta)
+            b, cons = best(J, th)
+            r.update(best=b, consensus=cons, llr=float(LL[b, -1]), J=float(J[b, -1]), theta=th[b],
+                     sites=sites[b], bucket=bk[b])
+        out.append(r)
+    chosen, bv = -1, -math.inf
+    for r in out:
+        if r["best"] < 0:
+            continue
+        v = r["llr"] / r["l"]
+        if chosen < 0 or v >= bv:
+            chosen, bv = r["l"], v
+    return out, chosen
+
+
+# ------------------------------------------------------------ Gibbs sampling
+def philox4x64(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().or_philox4x64(_p(c), _p(k), _p(out))
+    return out
+
+
+def gibbs_uniform(seed: int, sweep: int, i: int, model: int) -> float:
+    return float(lib().or_gibbs_uniform(seed, sweep, i, model))
+
+
+def gibbs_weights(S: Seqs, l: int, bg: np.ndarray, beta: float, sites: np.ndarray, i: int) -> np.ndarray:
+    """The sampler's conditional distribution of the start of sequence i."""
+    L = int(S.off[i + 1] - S.off[i]) - l + 1
+    w = np.zeros(L)
+    lib().or_gibbs_weights(S.t, _p(S.off), _p(S.codes), l, S.A, _p(np.ascontiguousarray(bg, dtype=np.float64)),
+                           float(beta), _p(np.ascontiguousarray(sites, dtype=np.int32)), i, _p(w))
+    return w
+
+
+def alignment_score(S: Seqs, l: int, bg: np.ndarray, beta: float, sites: np.ndarray):
+    th = np.zeros((S.A, l))
+    F = lib().or_alignment_score(S.t, _p(S.off), _p(S.codes), l, S.A,
+                                 _p(np.ascontiguousarray(bg, dtype=np.float64)), float(beta),
+                                 _p(np.ascontiguousarray(sites, dtype=np.int32)), _p(th))
+    return float(F), th
+
+
+def gibbs(S: Seqs, l: int, theta0_: np.ndarray, bg: np.ndarray, sweeps: int, beta: float, seed: int):
+    """Gibbs refinement of every model: (theta, F [B][sweeps+1], sites)."""
+    th0 = np.ascontiguousarray(theta0_, dtype=np.float64)
+    B = th0.shape[0]
+    th = np.zeros_like(th0)
+    F = np.zeros((B, sweeps + 1))
+    sites = np.zeros((B, S.t), dtype=np.int32)
+    rc = lib().or_gibbs(S.t, _p(S.off), _p(S.codes), l, S.A, _p(th0), _p(np.ascontiguousarray(bg, dtype=np.float64)),
+                        B, sweeps, float(beta), seed, _p(th), _p(F), _p(sites))
+    if rc != 0:
+        raise ValueError("Gibbs sampling needs beta > 0")
+    return th, F, sites

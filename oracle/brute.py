@@ -219,3 +219,32 @@ def mixture_expected_loglik(seqs: Sequence[str], l: int, post: Sequence[Sequence
         else:
             v += sum(z * math.log(mix) + (1.0 - z) * math.log(1.0 - mix) for z in ps)
     return v
+
+
+def gibbs_conditional(seqs: Sequence[str], l: int, sites: Sequence[int], i: int, bg: Dict[str, float],
+                      beta: float) -> List[float]:
+    """P(a_i = a | the other sites) for the site sampler: the model is the
+    profile of the other t-1 aligned l-mers with pseudocounts beta * bg, and
+    the start is drawn by Bayes' rule over explicit products (uniform prior)."""
+    others = [seqs[j][sites[j]:sites[j] + l] for j in range(len(seqs)) if j != i]
+    theta = {c: [(sum(1 for w in others if w[p] == c) + beta * bg[c]) / (len(others) + beta) for p in range(l)]
+             for c in bg}
+    S = seqs[i]
+    w = [_site_product(S, l, a, theta, bg) for a in range(len(S) - l + 1)]
+    z = sum(w)
+    return [v / z for v in w]
+
+
+def alignment_log_odds(seqs: Sequence[str], l: int, sites: Sequence[int], bg: Dict[str, float],
+                       beta: float) -> float:
+    """F = sum over columns and letters of count * ln(theta / bg), theta the
+    smoothed profile of the aligned l-mers."""
+    words = [S[a:a + l] for S, a in zip(seqs, sites)]
+    t = len(words)
+    F = 0.0
+    for c in bg:
+        for p in range(l):
+            n = sum(1 for w in words if w[p] == c)
+            if n:
+                F += n * math.log((n + beta * bg[c]) / (t + beta) / bg[c])
+    return F

@@ -566,6 +566,188 @@ void or_em_model(int model, double mix0, int t, const int64_t *off, const uint8_
     }
 }
 
+/* ---------------------------------------------------------------------- */
+/* Gibbs sampling as the local optimiser that refines a bucket instead of EM
+ * (Sec. 1 and Sec. 3 name Gibbs sampling beside EM; the sampler is the site
+ * sampler of Lawrence et al., cited by the paper).  The paper gives no
+ * details; the reading used here:
+ *   start  a_i = the best start of S_i under the bucket's theta0 (first on ties);
+ *   sweep  for i = 0..t-1 in order: counts c of the other t-1 current sites,
+ *          theta = (c + beta*bg) / (t - 1 + beta), weight of start a of S_i
+ *          w_a = prod_p theta[S_i[a+p]][p] / bg[S_i[a+p]]; draw a_i with
+ *          probability w_a / sum w, by the first a whose running sum of
+ *          weights exceeds u * sum w (u uniform in [0,1));
+ *   score  of an alignment, F = sum_{c,p} n_cp ln(theta_cp / bg_c) with n the
+ *          counts of all t sites and theta = (n + beta*bg) / (t + beta);
+ *   answer the alignment of largest F among the start and the end of every
+ *          sweep (the earliest on ties), its theta and sites.
+ * Random numbers: Philox4x64-10 (Salmon et al., SC'11), key {seed, 0},
+ * counter {sweep, i, model, 0}; u = (first output word >> 11) * 2^-53.      */
+static void philox_round(uint64_t c[4], const uint64_t k[2])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const unsigned __int128 p0 = (unsigned __int128)M0 * c[0];
+    const unsigned __int128 p1 = (unsigned __int128)M1 * c[2];
+    const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    const uint64_t n0 = hi1 ^ c[1] ^ k[0], n2 = hi0 ^ c[3] ^ k[1];
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+}
+
+void or_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint64_t k[2] = {key[0], key[1]};
+    for (int r = 0; r < 10; ++r) {
+        philox_round(c, k);
+        k[0] += 0x9E3779B97F4A7C15ull;
+        k[1] += 0xBB67AE8584CAA73Bull;
+    }
+    for (int q = 0; q < 4; ++q) out[q] = c[q];
+}
+
+double or_gibbs_uniform(uint64_t seed, int sweep, int i, int64_t model)
+{
+    const uint64_t ctr[4] = {(uint64_t)sweep, (uint64_t)i, (uint64_t)model, 0};
+    const uint64_t key[2] = {seed, 0};
+    uint64_t out[4];
+    or_philox4x64(ctr, key, out);
+    return (double)(out[0] >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* counts n[c][p] of the sites of every sequence except `skip` (-1: none) */
+static void site_counts(int t, const int64_t *off, const uint8_t *codes, int l, const int32_t *site, int skip,
+                        double *n)
+{
+    memset(n, 0, sizeof(double) * 20 * 32);
+    for (int i = 0; i < t; ++i) {
+        if (i == skip) continue;
+        for (int p = 0; p < l; ++p) n[codes[off[i] + site[i] + p] * l + p] += 1.0;
+    }
+}
+
+/* The weights of the starts of S_i given the other sites, scaled by the
+ * largest (w[a] = e^{s_a - max_a s}); returns their sum. */
+static double gibbs_raw_weights(int t, const int64_t *off, const uint8_t *codes, int l, int A, const double *bg,
+                                double beta, const int32_t *site, int i, double *w)
+{
+    double n[20 * 32], W[20 * 32];
+    site_counts(t, off, codes, l, site, i, n);
+    for (int c = 0; c < A; ++c)
+        for (int p = 0; p < l; ++p)
+            W[c * l + p] = log((n[c * l + p] + beta * bg[c]) / ((double)(t - 1) + beta)) - log(bg[c]);
+    const int64_t L = (off[i + 1] - off[i]) - l + 1;
+    double mx = -INFINITY;
+    for (int64_t a = 0; a < L; ++a) {
+        double v = 0;
+        for (int p = 0; p < l; ++p) v += W[codes[off[i] + a + p] * l + p];
+        w[a] = v;
+        if (v > mx) mx = v;
+    }
+    double sum = 0;
+    for (int64_t a = 0; a < L; ++a) {
+        w[a] = exp(w[a] - mx);
+        sum += w[a];
+    }
+    return sum;
+}
+
+/* The sampler's conditional distribution for sequence i: w[a] / sum w. */
+void or_gibbs_weights(int t, const int64_t *off, const uint8_t *codes, int l, int A, const double *bg, double beta,
+                      const int32_t *site, int i, double *w)
+{
+    const double sum = gibbs_raw_weights(t, off, codes, l, A, bg, beta, site, i, w);
+    const int64_t L = (off[i + 1] - off[i]) - l + 1;
+    for (int64_t a = 0; a < L; ++a) w[a] /= sum;
+}
+
+/* F of the alignment `site` and its theta */
+double or_alignment_score(int t, const int64_t *off, const uint8_t *codes, int l, int A, const double *bg,
+                          double beta, const int32_t *site, double *theta)
+{
+    double n[20 * 32];
+    site_counts(t, off, codes, l, site, -1, n);
+    double F = 0;
+    for (int c = 0; c < A; ++c)
+        for (int p = 0; p < l; ++p) {
+            const double th = (n[c * l + p] + beta * bg[c]) / ((double)t + beta);
+            if (theta) theta[c * l + p] = th;
+            if (n[c * l + p] > 0) F += n[c * l + p] * log(th / bg[c]);
+        }
+    return F;
+}
+
+/* Gibbs refinement of B models: theta_out [B][A][l], F [B][sweeps+1] (F of
+ * the start and after each sweep), sites [B][t] of the best alignment.
+ * Returns 0, or -1 when beta <= 0. */
+int or_gibbs(int t, const int64_t *off, const uint8_t *codes, int l, int A, const double *theta0, const double *bg,
+             int64_t B, int sweeps, double beta, uint64_t seed, double *theta_out, double *F, int32_t *sites)
+{
+    if (!(beta > 0)) return -1;
+    int64_t x = windows_total(t, off, l);
+    int64_t Lmax = 1;
+    for (int i = 0; i < t; ++i)
+        if ((off[i + 1] - off[i]) - l + 1 > Lmax) Lmax = (off[i + 1] - off[i]) - l + 1;
+#pragma omp parallel
+    {
+        double *s = (double *)malloc(sizeof(double) * (x > 0 ? x : 1));
+        double *Z = (double *)malloc(sizeof(double) * (x > 0 ? x : 1));
+        double *w = (double *)malloc(sizeof(double) * Lmax);
+        int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * t);
+        int32_t *bst = (int32_t *)malloc(sizeof(int32_t) * t);
+#pragma omp for schedule(dynamic)
+        for (int64_t b = 0; b < B; ++b) {
+            /* start: the best start of every sequence under theta0 */
+            or_estep(t, off, codes, l, A, theta0 + b * A * l, bg, s, Z, NULL);
+            int64_t w0 = 0;
+            for (int i = 0; i < t; ++i) {
+                int64_t L = (off[i + 1] - off[i]) - l + 1, best = 0;
+                for (int64_t a = 1; a < L; ++a)
+                    if (s[w0 + a] > s[w0 + best]) best = a;
+                cur[i] = (int32_t)best;
+                w0 += L;
+            }
+            double Fb = or_alignment_score(t, off, codes, l, A, bg, beta, cur, NULL);
+            F[b * (sweeps + 1)] = Fb;
+            memcpy(bst, cur, sizeof(int32_t) * t);
+            for (int r = 0; r < sweeps; ++r) {
+                for (int i = 0; i < t; ++i) {
+                    const int64_t L = (off[i + 1] - off[i]) - l + 1;
+                    const double tot = gibbs_raw_weights(t, off, codes, l, A, bg, beta, cur, i, w);
+                    const double target = or_gibbs_uniform(seed, r, i, b) * tot;
+                    int64_t pick = L - 1;
+                    double run = 0;
+                    for (int64_t a = 0; a < L; ++a) {
+                        run += w[a];
+                        if (run > target) {
+                            pick = a;
+                            break;
+                        }
+                    }
+                    cur[i] = (int32_t)pick;
+                }
+                const double Fr = or_alignment_score(t, off, codes, l, A, bg, beta, cur, NULL);
+                F[b * (sweeps + 1) + r + 1] = Fr;
+                if (Fr > Fb) {
+                    Fb = Fr;
+                    memcpy(bst, cur, sizeof(int32_t) * t);
+                }
+            }
+            or_alignment_score(t, off, codes, l, A, bg, beta, bst, theta_out + b * A * l);
+            memcpy(sites + b * t, bst, sizeof(int32_t) * t);
+        }
+        free(s);
+        free(Z);
+        free(w);
+        free(cur);
+        free(bst);
+    }
+    return 0;
+}
+
 /* Sec. 5.1: the model with the highest objective is the answer.  Readings:
  * the objective is J(theta^iters); ties go to the lowest bucket index (the
  * lowest (trial, key)); the consensus takes in each column the letter of
