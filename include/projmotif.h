@@ -283,6 +283,29 @@ int em_refine_model(const pm_seqs *S, int32_t l, int32_t model, double mix0, con
                     const double *bg, int64_t B, const int64_t *n_dev, int32_t iters, double beta,
                     int32_t precision, double *theta_out, double *mix_out, double *J_out, double *llr_out,
                     int32_t *sites_out, void *stream);
+/* Gibbs site sampling as the local optimiser of each model, in place of EM
+ * (Sec. 1 and Sec. 3 name Gibbs sampling beside EM; the site sampler of
+ * Lawrence et al., cited by the paper).  Per model: start from the best start
+ * of every sequence under theta0 (first on ties); each of `sweeps` sweeps
+ * visits S_1..S_t in order and redraws S_i's start a with probability
+ * proportional to prod_p theta[S_i[a+p]][p] / bg[S_i[a+p]], theta the
+ * profile of the other t-1 sites with pseudocounts,
+ * theta = (counts + beta * bg) / (t - 1 + beta) -- the draw is the first
+ * start whose running weight sum exceeds u times the total;
+ * u = (x >> 11) * 2^-53 with x the first word of Philox4x64-10 (Salmon et
+ * al., SC'11) at key {seed, 0}, counter {sweep, i, model, 0}.  The answer is
+ * the alignment of largest F = sum_{c,p} n_cp ln(theta_cp / bg_c) (n its
+ * letter counts, theta = (n + beta * bg) / (t + beta)) among the start and
+ * the end of every sweep, the earliest on ties.
+ *   theta0     device [B][|Sigma|][l]
+ *   theta_out  device [B][|Sigma|][l]: theta of the best alignment
+ *   F_out      device [B][sweeps+1] (F of the start, then after each sweep), or NULL
+ *   sites_out  device [B][t] best alignment's starts, or NULL
+ * beta > 0 (PM_EINVAL otherwise); t <= 512 (PM_ERANGE).  FP64 throughout. */
+int gibbs_refine(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
+                 const int64_t *n_dev, int32_t sweeps, double beta, uint64_t seed, double *theta_out,
+                 double *F_out, int32_t *sites_out, void *stream);
+
 /* Workspace bytes of em_refine: the one-hot tables of the DNA matrix-core
  * forms (t + ceil(x/32) window pairs of 1 KB + (4 ceil(l/4) + 12) x 64 B each);
  * 0 for the other forms or invalid arguments. */
@@ -554,6 +577,17 @@ typedef struct pm_result {
  * convenience entry point allocates and frees its own device buffers.
  * PM_EINVAL names the problem at fault in pm_last_error(). */
 int projection_run(const pm_problem *P, int32_t n_problems, const pm_options *O, pm_result *R);
+
+/* A motif-length range (l-, l+) (Sec. 2): the problem P run at every length
+ * l- .. l+ in one projection_run call (P->l ignored; k, s, m <= 0 chosen per
+ * length by pm_auto_params from P->d, a given k must not exceed l-; masks
+ * must be NULL, drawn per length from P->seed).  R[q] (host [l+ - l- + 1],
+ * consensus buffers of l- + q + 1 bytes) answers length l- + q.  *chosen (or
+ * NULL) receives the length whose answer has the largest LLR per motif column
+ * (the longer on ties; the paper does not say how lengths compete), -1 when
+ * no length has an enriched bucket. */
+int projection_run_range(const pm_problem *P, int32_t l_minus, int32_t l_plus, const pm_options *O, pm_result *R,
+                         int32_t *chosen);
 
 #ifdef __cplusplus
 }

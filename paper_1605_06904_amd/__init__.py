@@ -36,7 +36,7 @@ EXPORTS = [
     "pm_hash_select_workspace", "bucket_hash_select", "pm_hash_select_batch_workspace", "bucket_hash_select_batch",
     "pm_hash_select_scratch_bytes", "bucket_hash_select_noalloc",
     "pm_sort_select_workspace", "bucket_sort_select", "pm_sort_select_batch_workspace", "bucket_sort_select_batch",
-    "em_refine_model",
+    "em_refine_model", "projection_run_range", "gibbs_refine",
 ]
 
 PM_TRIAGE_PARAMS, PM_TRIAGE_INPUTS = 88577, 87
@@ -125,6 +125,8 @@ def lib():
         "em_best": (C.c_int, [P, i64, P, i32, P, i32, i32, P, P, P]),
         "projection_run": (C.c_int, [C.POINTER(pm_problem), i32, C.POINTER(pm_options),
                                      C.POINTER(pm_result)]),
+        "projection_run_range": (C.c_int, [C.POINTER(pm_problem), i32, i32, C.POINTER(pm_options),
+                                           C.POINTER(pm_result), P]),
         "pm_batch_check": (C.c_int, [C.POINTER(pm_batch)]),
         "projection_hash_batch": (C.c_int, [C.POINTER(pm_batch), P, P, P, P, P]),
         "bucket_select_batch": (C.c_int, [C.POINTER(pm_batch), P, P, u32, P, i64, P, i64, P, P, sz,
@@ -155,6 +157,7 @@ def lib():
         "bucket_hash_select_batch": (C.c_int, [C.POINTER(pm_batch), P, u32, P, i64, P, i64, P, P, sz, P, P]),
         "em_refine_model": (C.c_int, [C.POINTER(pm_seqs), i32, i32, dbl, P, P, i64, P, i32, dbl, i32, P, P, P, P,
                                       P, P]),
+        "gibbs_refine": (C.c_int, [C.POINTER(pm_seqs), i32, P, P, i64, P, i32, dbl, u64, P, P, P, P]),
         "pm_sort_select_workspace": (sz, [C.POINTER(pm_seqs), i32, i32, i32]),
         "bucket_sort_select": (C.c_int, [C.POINTER(pm_seqs), i32, i32, P, i32, u32, P, i64, P, i64, P, P, sz, P,
                                          P]),
@@ -330,6 +333,12 @@ def em_refine(S, l, theta0, bg, B, n_dev, iters, beta, precision, theta_out, J_o
                            _ptr(ws), ws_bytes, _stream(stream)))
 
 
+def gibbs_refine(S, l, theta0, bg, B, n_dev, sweeps, beta, seed, theta_out, F_out=None, sites_out=None,
+                 stream=None):
+    _check(lib().gibbs_refine(C.byref(S.c), l, _ptr(theta0), _ptr(bg), B, _ptr(n_dev), sweeps, beta, seed,
+                              _ptr(theta_out), _ptr(F_out), _ptr(sites_out), _stream(stream)))
+
+
 PM_OOPS, PM_ZOOPS, PM_TCM = 0, 1, 2
 
 
@@ -476,44 +485,38 @@ class Problem:
     bg: object = None
 
 
-def projection_run(problems, em_iters: int = 5, beta: float = 1.0, precision: int = PM_FP64,
-                   batched: bool = False, triage: bool = False, triage_frac: float = 0.05,
-                   triage_weights: Optional[str] = None, stream=None) -> list:
-    """Host in, host out: the whole path on every problem (synchronous).
-    `problems` is a Problem or a list of them; returns one dict per problem.
-    triage_weights defaults to the shipped weights file when triage is on."""
+def _fill_problem(pr, P, keep):
     import numpy as np
-    if isinstance(problems, Problem):
-        problems = [problems]
-    n = len(problems)
-    keep = []  # buffers the C structures point into
-    Ps = (pm_problem * n)()
-    Rs = (pm_result * n)()
-    outs = []
-    for q, (pr, P, R) in enumerate(zip(problems, Ps, Rs)):
-        t = len(pr.seqs)
-        raw = [x.encode("ascii") for x in pr.seqs]
-        arr = (C.c_char_p * t)(*raw)
-        ns = (C.c_int32 * t)(*[len(x) for x in raw])
-        keep += [raw, arr, ns]
-        P.alphabet, P.t, P.seqs, P.n = pr.alphabet, t, C.cast(arr, C.POINTER(C.c_char_p)), ns
-        P.l, P.d, P.k, P.s, P.m, P.seed = pr.l, pr.d, pr.k, pr.s, pr.m, pr.seed
-        if pr.masks is not None:
-            mk = np.ascontiguousarray(pr.masks, dtype=np.uint32)
-            keep.append(mk)
-            P.masks = mk.ctypes.data_as(C.POINTER(C.c_uint32))
-            P.m = len(mk)
-        if pr.bg is not None:
-            bgv = np.ascontiguousarray(pr.bg, dtype=np.float64)
-            keep.append(bgv)
-            P.bg = bgv.ctypes.data_as(C.POINTER(C.c_double))
-        cons = C.create_string_buffer(pr.l + 1)
-        sites = np.zeros(t, dtype=np.int32)
-        theta = np.zeros((pr.alphabet, pr.l), dtype=np.float64)
-        R.consensus = C.cast(cons, C.c_char_p)
-        R.sites = sites.ctypes.data_as(C.POINTER(C.c_int32))
-        R.theta = theta.ctypes.data_as(C.POINTER(C.c_double))
-        outs.append((cons, sites, theta))
+    t = len(pr.seqs)
+    raw = [x.encode("ascii") for x in pr.seqs]
+    arr = (C.c_char_p * t)(*raw)
+    ns = (C.c_int32 * t)(*[len(x) for x in raw])
+    keep += [raw, arr, ns]
+    P.alphabet, P.t, P.seqs, P.n = pr.alphabet, t, C.cast(arr, C.POINTER(C.c_char_p)), ns
+    P.l, P.d, P.k, P.s, P.m, P.seed = pr.l, pr.d, pr.k, pr.s, pr.m, pr.seed
+    if pr.masks is not None:
+        mk = np.ascontiguousarray(pr.masks, dtype=np.uint32)
+        keep.append(mk)
+        P.masks = mk.ctypes.data_as(C.POINTER(C.c_uint32))
+        P.m = len(mk)
+    if pr.bg is not None:
+        bgv = np.ascontiguousarray(pr.bg, dtype=np.float64)
+        keep.append(bgv)
+        P.bg = bgv.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _result_buffers(R, A, t, l):
+    import numpy as np
+    cons = C.create_string_buffer(l + 1)
+    sites = np.zeros(t, dtype=np.int32)
+    theta = np.zeros((A, l), dtype=np.float64)
+    R.consensus = C.cast(cons, C.c_char_p)
+    R.sites = sites.ctypes.data_as(C.POINTER(C.c_int32))
+    R.theta = theta.ctypes.data_as(C.POINTER(C.c_double))
+    return cons, sites, theta
+
+
+def _options(em_iters, beta, precision, batched, triage, triage_frac, triage_weights, stream):
     O = pm_options()
     O.em_iters, O.beta, O.precision = em_iters, beta, precision
     O.batched, O.triage, O.triage_frac = int(bool(batched)), int(bool(triage)), triage_frac
@@ -521,13 +524,54 @@ def projection_run(problems, em_iters: int = 5, beta: float = 1.0, precision: in
         path = triage_weights or default_triage_bin_path()
         O.triage_weights = path.encode()
     O.stream = _stream(stream) if stream is not None else None
-    _check(lib().projection_run(Ps, n, C.byref(O), Rs))
+    return O
+
+
+def _results(Rs, outs):
     res = []
     for R, (cons, sites, theta) in zip(Rs, outs):
         res.append(dict(consensus=cons.value.decode(), sites=sites, theta=theta, J=R.J, llr=R.llr,
                         best_trial=R.best_trial, best_key=R.best_key, n_enriched=R.n_enriched,
                         n_refined=R.n_refined, fallback_used=bool(R.fallback_used), k=R.k, s=R.s, m=R.m))
     return res
+
+
+def projection_run(problems, em_iters: int = 5, beta: float = 1.0, precision: int = PM_FP64,
+                   batched: bool = False, triage: bool = False, triage_frac: float = 0.05,
+                   triage_weights: Optional[str] = None, stream=None) -> list:
+    """Host in, host out: the whole path on every problem (synchronous).
+    `problems` is a Problem or a list of them; returns one dict per problem.
+    triage_weights defaults to the shipped weights file when triage is on."""
+    if isinstance(problems, Problem):
+        problems = [problems]
+    n = len(problems)
+    keep = []  # buffers the C structures point into
+    Ps = (pm_problem * n)()
+    Rs = (pm_result * n)()
+    outs = []
+    for pr, P, R in zip(problems, Ps, Rs):
+        _fill_problem(pr, P, keep)
+        outs.append(_result_buffers(R, pr.alphabet, len(pr.seqs), pr.l))
+    O = _options(em_iters, beta, precision, batched, triage, triage_frac, triage_weights, stream)
+    _check(lib().projection_run(Ps, n, C.byref(O), Rs))
+    return _results(Rs, outs)
+
+
+def projection_run_range(problem, l_minus: int, l_plus: int, em_iters: int = 5, beta: float = 1.0,
+                         precision: int = PM_FP64, batched: bool = False, triage: bool = False,
+                         triage_frac: float = 0.05, triage_weights: Optional[str] = None, stream=None):
+    """One problem at every motif length l_minus..l_plus (problem.l is
+    ignored): (one dict per length, the chosen length or -1)."""
+    keep = []
+    P = pm_problem()
+    _fill_problem(problem, P, keep)
+    n = l_plus - l_minus + 1
+    Rs = (pm_result * max(n, 1))()
+    outs = [_result_buffers(R, problem.alphabet, len(problem.seqs), l_minus + q) for q, R in enumerate(Rs)]
+    O = _options(em_iters, beta, precision, batched, triage, triage_frac, triage_weights, stream)
+    chosen = C.c_int32(-1)
+    _check(lib().projection_run_range(C.byref(P), l_minus, l_plus, C.byref(O), Rs, C.byref(chosen)))
+    return _results(Rs, outs), chosen.value
 
 
 # ----------------------------------------------------------------- device data

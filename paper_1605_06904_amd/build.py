@@ -16,7 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libprojmotif.so")
-SOURCES = ["api.hip", "hash.hip", "sortsel.hip", "select.hip", "em.hip", "em_mfma.hip", "em_prot.hip", "triage.hip", "run.hip"]
+SOURCES = ["api.hip", "hash.hip", "sortsel.hip", "select.hip", "em.hip", "em_mfma.hip", "em_prot.hip", "triage.hip", "gibbs.hip", "run.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -167,14 +167,11 @@ int run_single(const Prepared &Q, const pm_options &O, pm_result &R, hipStream_t
     const int64_t n_total = Q.n_total, x = Q.x;
     empty_result(R, Q);
     const int64_t nw = pm_packed_words(A, n_total);
-    const int64_t nb = ipow(A, k);
-    DevBuf d_ascii, d_off, d_packed, d_masks, d_keys, d_counts, d_status, d_nout, d_ws;
+    DevBuf d_ascii, d_off, d_packed, d_masks, d_status, d_nout, d_ws;
     PM_CALL(d_ascii.alloc(n_total));
     PM_CALL(d_off.alloc(sizeof(int64_t) * (t + 1)));
     PM_CALL(d_packed.alloc(sizeof(uint32_t) * nw));
     PM_CALL(d_masks.alloc(sizeof(uint32_t) * m));
-    PM_CALL(d_keys.alloc(sizeof(uint32_t) * (size_t)m * x));
-    PM_CALL(d_counts.alloc(sizeof(uint32_t) * (size_t)m * nb));
     PM_CALL(d_status.alloc(sizeof(uint32_t)));
     PM_CALL(d_nout.alloc(sizeof(int64_t) * 2));
     PM_TRY(hipMemcpyAsync(d_ascii.p, Q.ascii.data(), n_total, hipMemcpyHostToDevice, st));
@@ -184,32 +181,30 @@ int run_single(const Prepared &Q, const pm_options &O, pm_result &R, hipStream_t
 
     pm_seqs S{A, t, n_total, Q.n_min, Q.n_max, d_off.as<int64_t>(), d_packed.as<uint32_t>()};
     PM_CALL(pm_pack(A, d_ascii.as<uint8_t>(), n_total, d_packed.as<uint32_t>(), d_status.as<uint32_t>(), st));
-    PM_CALL(projection_hash(&S, l, k, d_masks.as<uint32_t>(), m, d_keys.as<uint32_t>(), d_counts.as<uint32_t>(),
-                            d_status.as<uint32_t>(), st));
-    // size the bucket lists: one selection pass with empty capacities
-    PM_CALL(d_ws.alloc(pm_select_workspace(m, 0)));
-    PM_CALL(bucket_select(&S, l, k, d_keys.as<uint32_t>(), d_counts.as<uint32_t>(), m, (uint32_t)s, nullptr, 0,
-                          nullptr, 0, d_nout.as<int64_t>(), d_ws.p, pm_select_workspace(m, 0), nullptr, st));
+    // the fused selection (keys and counts stay on chip; large key spaces are
+    // sorted instead of counted): a sizing pass with empty capacities, then
+    // the lists
+    const size_t hws = pm_hash_select_workspace(&S, l, k, m);
+    if (!hws) return fail(PM_ERANGE, "k=%d is beyond the selection's range for this alphabet", k);
+    PM_CALL(d_ws.alloc(hws));
+    PM_CALL(bucket_hash_select(&S, l, k, d_masks.as<uint32_t>(), m, (uint32_t)s, nullptr, 0, nullptr, 0,
+                               d_nout.as<int64_t>(), d_ws.p, hws, nullptr, st));
     int64_t nout[2];
     uint32_t status = 0;
     PM_TRY(hipMemcpyAsync(nout, d_nout.p, sizeof(nout), hipMemcpyDeviceToHost, st));
     PM_TRY(hipMemcpyAsync(&status, d_status.p, sizeof(status), hipMemcpyDeviceToHost, st));
     PM_TRY(hipStreamSynchronize(st));
     if (status & PM_STATUS_BAD_SYMBOL) return fail(PM_EINVAL, "a sequence holds a symbol outside the alphabet");
-    if (status & PM_STATUS_BAD_MASK) return fail(PM_EINVAL, "bad projection mask");
     const int64_t nbk = nout[0], nmem = nout[1];
     R.n_enriched = nbk;
     if (nbk == 0) return PM_OK;
     DevBuf d_bk, d_mem, d_prof, d_bg, d_th0, d_th, d_J, d_llr, d_sites, d_best, d_cons, d_emws;
     PM_CALL(d_bk.alloc(sizeof(pm_bucket) * nbk));
     PM_CALL(d_mem.alloc(sizeof(uint32_t) * nmem));
-    PM_CALL(d_ws.alloc(pm_select_workspace(m, nbk)));
-    PM_CALL(bucket_select(&S, l, k, d_keys.as<uint32_t>(), d_counts.as<uint32_t>(), m, (uint32_t)s,
-                          d_bk.as<pm_bucket>(), nbk, d_mem.as<uint32_t>(), nmem, d_nout.as<int64_t>(), d_ws.p,
-                          pm_select_workspace(m, nbk), d_status.as<uint32_t>(), st));
-    // keys and counts are no longer needed (hipFree waits for the stream's work)
-    d_keys.release();
-    d_counts.release();
+    PM_CALL(bucket_hash_select(&S, l, k, d_masks.as<uint32_t>(), m, (uint32_t)s, d_bk.as<pm_bucket>(), nbk,
+                               d_mem.as<uint32_t>(), nmem, d_nout.as<int64_t>(), d_ws.p, hws,
+                               d_status.as<uint32_t>(), st));
+    d_ws.release();
 
     const int AL = A * l;
     const int it1 = O.em_iters + 1;
@@ -755,5 +750,40 @@ extern "C" int projection_run(const pm_problem *P, int32_t n_problems, const pm_
         }
         PM_CALL(run_group(G, Rs, opt, O->triage ? &tri : nullptr, st));
     }
+    return PM_OK;
+}
+
+// Sec. 2: the motif length may be a range (l-, l+).  Every length of the range
+// is one problem of a single projection_run call (the batched path gives each
+// length its own shape class); the paper does not say how lengths compete,
+// so the reported choice is the length whose answer has the largest
+// log-likelihood ratio per motif column, the longer length on ties (a
+// motif's columns each add to the ratio, so the ratio itself favours long
+// models fitted to noise; per column it favours the planted motif or a
+// piece of it).
+extern "C" int projection_run_range(const pm_problem *P, int32_t l_minus, int32_t l_plus, const pm_options *O,
+                                    pm_result *R, int32_t *chosen)
+{
+    clear_error();
+    if (!P || !O || !R) return fail(PM_EINVAL, "NULL argument");
+    if (l_minus < 1 || l_plus < l_minus || l_plus > 32)
+        return fail(PM_EINVAL, "need 1 <= l- <= l+ <= 32 (l- = %d, l+ = %d)", l_minus, l_plus);
+    if (P->masks) return fail(PM_EINVAL, "a length range draws its own masks per length (masks must be NULL)");
+    if (P->k > l_minus) return fail(PM_EINVAL, "a given k (%d) must not exceed l- (%d)", P->k, l_minus);
+    const int n = l_plus - l_minus + 1;
+    std::vector<pm_problem> Ps(n, *P);
+    for (int q = 0; q < n; ++q) Ps[q].l = l_minus + q;
+    PM_CALL(projection_run(Ps.data(), n, O, R));
+    int best = -1;
+    double bv = -INFINITY;
+    for (int q = 0; q < n; ++q) {
+        if (R[q].best_trial < 0 || !(R[q].llr == R[q].llr)) continue;
+        const double v = R[q].llr / (double)(l_minus + q);
+        if (best < 0 || v >= bv) {
+            best = q;
+            bv = v;
+        }
+    }
+    if (chosen) *chosen = best < 0 ? -1 : l_minus + best;
     return PM_OK;
 }

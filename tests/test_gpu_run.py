@@ -144,3 +144,25 @@ def test_projection_run_rejects_bad_options():
         pm.projection_run(prot, triage=True)  # triage is for DNA
     with pytest.raises(pm.PmError):
         pm.projection_run(prot, precision=pm.PM_F16, batched=True)
+
+
+def test_projection_run_range_matches_oracle():
+    """A motif-length range (Sec. 2) over one planted (11,2) problem at
+    l = 10..12 (k and s from the Sec. 5 rules, 40 Park-Miller trials per
+    length): every length's answer and the chosen length equal the oracle's,
+    unbatched and batched."""
+    rng = np.random.default_rng(71)
+    inst = planted_instance(rng, 14, 300, 11, 2)
+    pr = pm.Problem(inst.seqs, 4, 11, d=2, m=40, seed=7)
+    ref, rchosen = oracle.run_range(inst.seqs, 4, 10, 12, 2, 7, 3, 1.0, m=40)
+    assert rchosen > 0
+    for batched in (False, True):
+        say("projection_run_range batched" if batched else "projection_run_range")
+        res, chosen = pm.projection_run_range(pr, 10, 12, em_iters=3, beta=1.0, precision=pm.PM_FP64,
+                                              batched=batched)
+        assert chosen == rchosen
+        for r, q in zip(res, ref):
+            assert (r["k"], r["s"], r["m"], r["n_enriched"]) == (q["k"], q["s"], q["m"], q["n_enriched"])
+            assert r["consensus"] == q["consensus"]
+            assert abs(r["llr"] - q["llr"]) <= 1e-12 * abs(q["llr"])
+            assert np.array_equal(r["sites"], q["sites"])

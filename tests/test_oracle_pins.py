@@ -570,3 +570,24 @@ def test_best_and_consensus_tie_rules():
     J[1, 1] = np.nan
     b, cons = oracle.best(J, th)
     assert b == 2 and cons == "GCT"
+
+
+# ------------------------------------------- Sec. 2 motif-length range (l-, l+)
+def test_length_range_is_the_per_length_runs_and_the_per_column_choice():
+    """run_range at every length equals a plain run at that length (auto
+    parameters of Sec. 5, Park-Miller masks of Sec. 6), and the chosen length
+    is the argmax of LLR / l over lengths that found a bucket, the longer on
+    ties."""
+    rng = np.random.default_rng(31)
+    inst = planted_instance(rng, 14, 300, 11, 2)
+    out, chosen = oracle.run_range(inst.seqs, DNA, 10, 12, 2, 7, 3, 1.0, m=40)
+    S = oracle.Seqs(DNA, inst.seqs)
+    for r in out:
+        k, s, _ = oracle.auto_params(r["l"], 2, 14, S.nwin(r["l"]), DNA)
+        assert (r["k"], r["s"], r["m"]) == (k, s, 40)
+        ref = oracle.run(inst.seqs, DNA, r["l"], k, s, oracle.masks_from_seed(7, r["l"], k, 40), 3, 1.0)
+        assert r["consensus"] == ref["consensus"]
+        assert r["llr"] == ref["llr"][ref["best"], -1]
+    per_col = {r["l"]: r["llr"] / r["l"] for r in out if r["best"] >= 0}
+    top = max(per_col.values())
+    assert chosen == max(l for l, v in per_col.items() if v == top)
