@@ -77,6 +77,10 @@ def parse():
                     help="also run one plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--instances", type=int, default=256,
                     help="(15,4) instances for the instances/s leg (0: skip it)")
+    ap.add_argument("--no-extra-hash", action="store_true",
+                    help="skip the hash rooflines of the (21,7) DNA and (20,6) protein workloads")
+    ap.add_argument("--c3-chunk", type=int, default=250,
+                    help="trials per instance per chunk of the 512-instance uneven workload at m=1000 (0: skip)")
     ap.add_argument("--uneven", type=int, default=0,
                     help="also run the 512-instance uneven batch with this many trials per instance")
     ap.add_argument("--c5", action="store_true",
@@ -240,6 +244,11 @@ def main():
     out["precision"] = precision_leg(torch, pm, P, l, iters, beta, nbk, ms_em=stage["em"])
     if args.instances > 0:
         out["instances"] = instances_leg(torch, pm, args.instances)
+    if not args.no_extra_hash:
+        out["roofline_hash_c5"] = hash_roofline(torch, pm, "c5")
+        out["roofline_hash_c4"] = hash_roofline(torch, pm, "c4")
+    if args.c3_chunk > 0:
+        out["uneven_full_m"] = c3_full_leg(torch, pm, chunk=args.c3_chunk)
     if args.uneven > 0:
         out["uneven_batch"] = uneven_leg(torch, pm, args.uneven)
     if args.c5:
@@ -450,6 +459,135 @@ def c5_leg(torch, pm, seed=1):
         out["speedup"] = round(out["full"]["ms"] / out["triaged"]["ms"], 3)
         progress(f"c5: triaged pass {out['triaged']['ms']} ms")
     return out
+
+
+def hash_roofline(torch, pm, name, seed=1, reps=3):
+    """projection_hash (keys and dense counts of every trial) on one
+    configuration's full trial set, timed on its launch stream: algorithmic
+    bytes per launch = 4 B per projected l-mer key + 4 B per count bin."""
+    from synth import make_config
+    inst, masks = make_config(name, seed=seed)
+    cfg = inst.meta
+    A = 20 if cfg.get("alphabet") == "protein" else 4
+    l, k, m = cfg["l"], cfg["k"], len(masks)
+    S = pm.Seqs(A, inst.seqs)
+    x = S.nwin(l)
+    dm = torch.from_numpy(np.ascontiguousarray(masks, dtype=np.uint32).view(np.int32)).cuda()
+    keys = torch.empty((m, x), dtype=torch.int32, device="cuda")
+    counts = torch.empty((m, A ** k), dtype=torch.int32, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pm.projection_hash(S, l, k, dm, m, keys, counts, st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pm.projection_hash(S, l, k, dm, m, keys, counts, st)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 4.0 * m * x + 4.0 * m * A ** k
+    gbs = nbytes / (ms / 1e3) / 1e9
+    del keys, counts
+    torch.cuda.empty_cache()
+    kern = f"k_hash<{A},{k},{'true' if x < 65536 else 'false'}>"
+    progress(f"{name} hash: {ms:.3f} ms, {gbs:.0f} GB/s")
+    return {"kernel": kern, "bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes, "ms": round(ms, 4),
+            "workload": f"{'protein' if A == 20 else 'DNA'} ({l},{cfg['d']}): t={len(inst.seqs)}, "
+                        f"n={cfg['n']}, k={k}, m={m} trials, keys and counts of every trial",
+            "lmers_per_s": round(m * x / (ms / 1e3), 1)}
+
+
+def c3_full_leg(torch, pm, m=1000, chunk=250, count=512, seed=1):
+    """The 512-instance uneven workload with all m = 1000 trials of every
+    instance: per shape class (motif length), the trials in chunks of
+    `chunk` per instance through key and count buffers reused from chunk to
+    chunk; every chunk hashed (keys + dense counts), its enriched buckets
+    selected from them, and the same trials through the fused selection
+    (keys and counts kept on chip).  Times on the launch stream; hash bytes
+    algorithmic (4 B per key, 4 B per count bin)."""
+    from synth import batch_config
+    insts = batch_config(seed, count=count, m=m)
+    classes = {}
+    for inst, masks in insts:
+        classes.setdefault(inst.meta["l"], []).append((inst, masks))
+    progress(f"c3: {count} instances, {len(classes)} shape classes generated")
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    # one set of buffers for the largest chunk of any class
+    plans, keys_max, counts_max, items_max = [], 0, 0, 0
+    for l in sorted(classes):
+        group = classes[l]
+        meta = group[0][0].meta
+        xs = [i.meta["t"] * (i.meta["n"] - l + 1) for i, _ in group]
+        nb = 4 ** meta["k"]
+        items = len(group) * chunk
+        keys_max = max(keys_max, sum(xs) * chunk)
+        counts_max = max(counts_max, items * nb)
+        items_max = max(items_max, items)
+        plans.append((l, meta, group))
+    keys = torch.empty(keys_max, dtype=torch.int32, device="cuda")
+    counts = torch.empty(counts_max, dtype=torch.int32, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    n_out = torch.zeros(2, dtype=torch.int64, device="cuda")
+    bk = torch.empty((1, 4), dtype=torch.int32, device="cuda")
+    mem = torch.empty(1, dtype=torch.int32, device="cuda")
+    t_hash = t_sel = t_fused = 0.0
+    nbytes = lmers = 0.0
+    nbk_tot = nmem_tot = 0
+    for l, meta, group in plans:
+        k, s = meta["k"], meta["s"]
+        for c0 in range(0, m, chunk):
+            B = pm.Batch(4, l, k, [i.seqs for i, _ in group], [mk[c0:c0 + chunk] for _, mk in group])
+            nb = 4 ** k
+            # sizes of the chunk's lists (untimed), then its buffers
+            sws0 = pm.pm_select_workspace(B.items, 0)
+            ws = torch.empty(max(sws0, 16), dtype=torch.uint8, device="cuda")
+            pm.projection_hash_batch(B, B.masks, keys, counts, status)
+            pm.bucket_select_batch(B, keys, counts, s, None, 0, None, 0, n_out, ws, sws0, None)
+            torch.cuda.synchronize()
+            nbk, nmem = [int(v) for v in n_out.cpu()]
+            if bk.shape[0] < nbk:
+                bk = torch.empty((int(nbk * 1.1) + 1, 4), dtype=torch.int32, device="cuda")
+            if mem.numel() < nmem:
+                mem = torch.empty(int(nmem * 1.1) + 1, dtype=torch.int32, device="cuda")
+            sws = pm.pm_select_workspace(B.items, nbk)
+            ws = torch.empty(max(sws, 16), dtype=torch.uint8, device="cuda")
+            hws = pm.pm_hash_select_batch_workspace(B)
+            hw = torch.empty(max(hws, 16), dtype=torch.uint8, device="cuda")
+            e = [ev() for _ in range(6)]
+            e[0].record()
+            pm.projection_hash_batch(B, B.masks, keys, counts, status)
+            e[1].record()
+            pm.bucket_select_batch(B, keys, counts, s, bk, nbk, mem, nmem, n_out, ws, sws, status)
+            e[2].record()
+            e[3].record()
+            pm.bucket_hash_select_batch(B, B.masks, s, bk, nbk, mem, nmem, n_out, hw, hws, status)
+            e[4].record()
+            torch.cuda.synchronize()
+            t_hash += e[0].elapsed_time(e[1])
+            t_sel += e[1].elapsed_time(e[2])
+            t_fused += e[3].elapsed_time(e[4])
+            nbytes += 4.0 * B.keys_total + 4.0 * B.items * nb
+            lmers += float(sum(B.x[p] * B.m[p] for p in range(B.P)))
+            nbk_tot += nbk
+            nmem_tot += nmem
+        progress(f"c3: class l={l} done ({len(group)} instances)")
+    if int(status.item()) != 0:
+        raise SystemExit(f"c3 device status {int(status.item())}")
+    gbs = nbytes / (t_hash / 1e3) / 1e9
+    del keys, counts, bk, mem
+    torch.cuda.empty_cache()
+    return {"workload": f"{count} uneven DNA instances (t~U[10,40], n~U[300,2000], l~U[11,21], d=floor(l/4)+1, "
+                        f"k=clamp(l-d-4,6,9), s=3), all m={m} trials of every instance, {len(plans)} shape classes, "
+                        f"trials in chunks of {chunk} per instance through reused key/count buffers",
+            "projected_lmers": lmers, "enriched_buckets": nbk_tot, "members": nmem_tot,
+            "hash_ms": round(t_hash, 2), "select_ms": round(t_sel, 2), "fused_select_ms": round(t_fused, 2),
+            "roofline_hash": {"kernel": "k_hash<4,k,*> (11 classes)", "bound": "hbm", "achieved": round(gbs, 2),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "traffic": None, "bytes": nbytes},
+            "lmers_per_s_hash": round(lmers / (t_hash / 1e3), 1),
+            "lmers_per_s_hash_and_select": round(lmers / ((t_hash + t_sel) / 1e3), 1),
+            "lmers_per_s_fused_select": round(lmers / (t_fused / 1e3), 1)}
 
 
 def perf_coefficient(starts, sites, l):

@@ -310,3 +310,75 @@ def test_batch_rejects_bad_tables():
         pm.pm_batch_check(B)
     B.tab_host[1].x -= 1
     pm.pm_batch_check(B)
+
+
+def test_uneven_shape_classes_in_one_graph_match_oracle():
+    """The uneven batching workload's rules at test size: motif lengths 11, 14,
+    17 and 20 with d = floor(l/4) + 1 and k = clamp(l - d - 4, 6, 9), ragged t
+    and n, two or three trials per instance (s = 2, so that every class fills
+    buckets at this size); one batch per length, all four captured in one HIP
+    graph and replayed twice with eager work between.  Per instance of every
+    class: keys and counts bit-exact, J of every model (split FP16) within
+    1e-5 of the oracle, the winner the oracle's (or tied with it in J) with
+    its consensus."""
+    rng = np.random.default_rng(2024)
+    bg = np.full(4, 0.25)
+    iters, s = 4, 2
+    classes = []
+    for l in (11, 14, 17, 20):
+        d = l // 4 + 1
+        k = min(max(l - d - 4, 6), 9)
+        insts = []
+        for _ in range(3):
+            t = int(rng.integers(5, 13))
+            lens = [int(v) for v in rng.integers(120, 420, size=t)]
+            insts.append((planted_instance(rng, t, lens, l, d), projection_masks(rng, l, k, int(rng.integers(2, 4)))))
+        B = _batch(insts, 4, l, k)
+        Pp, nb_, nm_ = _pipeline(B, s, iters, 1.0, pm.PM_F16X2, bg)
+        assert nb_ > 0, l
+        classes.append((l, k, insts, B, Pp, nb_))
+    say("uneven classes in one graph", [(c[0], c[5]) for c in classes])
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for c in classes:
+            c[4].run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for c in classes:
+            c[4].run()
+    for rep in range(2):
+        for c in classes:
+            c[4].b.J.fill_(-1.0)
+            c[4].b.best.fill_(-7)
+            c[4].b.keys.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (torch.arange(1000, device="cuda") * 3).sum().item()
+        for l, k, insts, B, Pp, nb_ in classes:
+            b = Pp.b
+            assert int(b.status.item()) == 0
+            keys, counts = u32(b.keys), u32(b.counts)
+            bk = u32(b.buckets)[:nb_]
+            J = b.J.cpu().numpy()[:nb_]
+            res = Pp.results()
+            for p, (inst, masks) in enumerate(insts):
+                ref, RK, RN, rbk, rmem, rprof = _oracle_instance(inst, masks, 4, l, k, s)
+                f, x, m = B.first_item[p], B.x[p], B.m[p]
+                assert np.array_equal(keys[B.key_base[p]:B.key_base[p] + m * x].reshape(m, x), RK), (rep, l, p)
+                assert np.array_equal(counts[f:f + m], RN), (rep, l, p)
+                sel = np.nonzero((bk[:, 0] >= f) & (bk[:, 0] < f + m))[0]
+                assert len(sel) == len(rbk), (rep, l, p)
+                if len(rbk) == 0:
+                    assert res[p]["best"] == -1
+                    continue
+                rth, rJ, _, _ = oracle.em(ref, l, oracle.theta0(rprof, bg, 1.0), bg, iters, 1.0)
+                np.testing.assert_allclose(J[sel], rJ, rtol=1e-5, atol=1e-5 * np.abs(rJ).max())
+                rbest, rcons = oracle.best(rJ, rth)
+                got = res[p]["best"] - sel[0]
+                _same_best(got, rbest, rJ, 1e-5)
+                if got == rbest:
+                    assert res[p]["consensus"] == rcons, (rep, l, p)
