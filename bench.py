@@ -241,6 +241,7 @@ def main():
         "planted": inst.motif,
     }
     progress(f"pass timed: {ms_step:.3f} ms/step")
+    out["fused_selection"] = fused_select_leg(torch, pm, P, l, k, s, m, nbk, nmem)
     out["precision"] = precision_leg(torch, pm, P, l, iters, beta, nbk, ms_em=stage["em"])
     if args.instances > 0:
         out["instances"] = instances_leg(torch, pm, args.instances)
@@ -268,6 +269,36 @@ def main():
         progress("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(inst, masks, cfg, bg, beta, nbk, args.cpu_budget)
     print(json.dumps(out), flush=True)
+
+
+def fused_select_leg(torch, pm, P, l, k, s, m, nbk, nmem, reps=5):
+    """The same trials through the fused selection (projection, histogram and
+    enriched-bucket lists with keys and counts kept on chip): its time beside
+    the pass's hash + selection stages, and its lists against the pass's
+    (records equal, members equal as sets per bucket)."""
+    b = P.b
+    nbytes = pm.pm_hash_select_workspace(P.S, l, k, m)
+    ws = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    n_out = torch.zeros(2, dtype=torch.int64, device="cuda")
+    bk = torch.zeros((nbk, 4), dtype=torch.int32, device="cuda")
+    mem = torch.zeros(nmem, dtype=torch.int32, device="cuda")
+    pm.bucket_hash_select(P.S, l, k, P.masks, m, s, bk, nbk, mem, nmem, n_out, ws, nbytes)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pm.bucket_hash_select(P.S, l, k, P.masks, m, s, bk, nbk, mem, nmem, n_out, ws, nbytes)
+    e1.record()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(bk, b.buckets[:nbk]))
+    if same:
+        # members of every bucket as a set: sort within each bucket's slice
+        seg = torch.repeat_interleave(torch.arange(nbk, device="cuda"), b.buckets[:nbk, 2].long())
+        key = seg * (1 << 32) + mem.long().view(-1) % (1 << 32)
+        ref = seg * (1 << 32) + b.members[:nmem].long() % (1 << 32)
+        same = bool(torch.equal(torch.sort(key).values, torch.sort(ref).values))
+    return {"ms": round(e0.elapsed_time(e1) / reps, 4), "lists_equal_to_pass": same,
+            "note": "bucket_hash_select over the pass's trials: keys and counts never leave LDS"}
 
 
 def precision_leg(torch, pm, P, l, iters, beta, nbk, ms_em, sample=512):

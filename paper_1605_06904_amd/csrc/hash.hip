@@ -4,8 +4,11 @@
 // per GPU thread.  Here one workgroup owns one trial (and one slice of the
 // key range when the |Sigma|^k histogram does not fit in LDS): it stages the
 // packed input (a few KB) in LDS, builds keys from LDS windows, writes them
-// with coalesced stores and counts them in an LDS histogram with
-// wave-aggregated atomics, then streams the histogram out as dense u32 counts.
+// with coalesced stores and counts them in an LDS histogram of u8, u16 or u32
+// counters (the width that needs the fewest key-range slices, the widest on a
+// tie), then streams the histogram out as dense u32 counts.  A narrow counter
+// that wraps is seen from the value its atomic returned (u8) or from the
+// slice's window total (u16), and such a slice is counted again in u32.
 #include <algorithm>
 #include <mutex>
 
@@ -70,9 +73,28 @@ __device__ __forceinline__ void hist_add(uint32_t *hist, uint32_t bin)
     else atomicAdd(hist + bin, 1u);
 }
 
-template <int A, int K, bool U16>
+constexpr int kHashFlagWords = 1;  // LDS words after the staged input: the slice's window total
+
+// Count-table widths of k_hash.
+constexpr int kHist16 = 0;       // u16 pairs: instances below 65 536 windows
+constexpr int kHist16Check = 1;  // u16 pairs, slices of 65 536 windows or more counted again in u32
+constexpr int kHist32 = 2;       // u32
+constexpr int kHist8 = 3;        // u8 quads, a slice where a count wrapped counted again in u32
+constexpr int kHistModes = 4;
+
+// Narrow counts hold more bins per slice, so fewer slices (each of which
+// recomputes every key of its trial).  A u16 count can pass 65 535 only when
+// at least 65 536 windows fall in its slice, so with kHist16Check every thread
+// counts the windows of its slice (one add per window, the atomics stay
+// non-returning) and a slice that received 65 536 or more is counted again in
+// u32, hist_words bins per pass.  u8 counts wrap at 256: kHist8 increments
+// with returning atomics and a slice where a count wrapped is counted again
+// in u32 the same way (only a key with 256 windows or more in one trial can).
+template <int A, int K, int HIST>
 __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
 {
+    // all LDS is dynamic (the count table may take every byte the device
+    // allows, so a static variable would not fit beside it)
     extern __shared__ __align__(16) uint32_t smem[];
     const int slice = blockIdx.x % a.nslices;
     const int j = blockIdx.x / a.nslices;
@@ -87,12 +109,14 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
     uint32_t *hist = smem;
     uint32_t *seq = smem + a.hist_words;
     int32_t *wst = reinterpret_cast<int32_t *>(seq + a.seq_cap);  // window number of each sequence start
+    uint32_t &in_slice = *reinterpret_cast<uint32_t *>(wst + a.off_cap);  // kHashFlagWords
     const Staged st = stage_input<A>(a, j, seq, wst);
     const pm_inst &I = st.I;
     const int64_t x = I.x;
     if (a.counts)
         for (int i = tid * 4; i < a.hist_words; i += kHashThreads * 4)
             *reinterpret_cast<uint4 *>(hist + i) = make_uint4(0, 0, 0, 0);
+    if (tid == 0) in_slice = 0;
     __syncthreads();
 
     int pos[K];
@@ -100,28 +124,78 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
     const uint32_t slice_base = (uint32_t)slice * a.slice_bins;  // |Sigma|^k <= 2^24
     const int64_t kw0 = x * slice / a.nslices, kw1 = x * (slice + 1) / a.nslices;
     uint32_t *keys_j = a.keys ? a.keys + I.key_base + (int64_t)(j - I.first_item) * x : nullptr;
+    uint32_t mine = 0;
     for_each_key<A, K>(a, st, pos, [&](int64_t w, uint32_t key) {
         if (keys_j && w >= kw0 && w < kw1) __builtin_nontemporal_store(key, keys_j + w);
         if (a.counts) {
             const uint32_t bin = key - slice_base;
-            if (bin < a.slice_bins) hist_add<U16>(hist, bin);
+            if (bin < a.slice_bins) {
+                if (HIST == kHist32) {
+                    atomicAdd(hist + bin, 1u);
+                } else if (HIST == kHist8) {
+                    const uint32_t sh = (bin & 3) << 3;
+                    const uint32_t old = atomicAdd(hist + (bin >> 2), 1u << sh);
+                    mine |= ((old >> sh) & 0xffu) == 0xffu;
+                } else {
+                    atomicAdd(hist + (bin >> 1), 1u << ((bin & 1) << 4));
+                    if (HIST == kHist16Check) ++mine;
+                }
+            }
         }
     });
     if (!a.counts) return;
+    if (HIST == kHist16Check) {
+        mine = wave_sum(mine);
+        if (lane_id() == 0) atomicAdd(&in_slice, mine);
+    } else if (HIST == kHist8) {
+        if (mine) in_slice = 1u << 16;  // a count wrapped: recount below
+    }
     __syncthreads();
 
     const uint64_t left = (uint64_t)a.nb - slice_base;
     const uint32_t nvalid = left < a.slice_bins ? (uint32_t)left : a.slice_bins;  // multiple of 4
     uint32_t *out = a.counts + (int64_t)j * a.nb + slice_base;
-    for (uint32_t b4 = tid * 4; b4 < nvalid; b4 += kHashThreads * 4) {
-        uint4 v;
-        if (U16) {
-            const uint32_t w0 = hist[b4 >> 1], w1 = hist[(b4 >> 1) + 1];
-            v = make_uint4(w0 & 0xffffu, w0 >> 16, w1 & 0xffffu, w1 >> 16);
-        } else {
-            v = *reinterpret_cast<const uint4 *>(hist + b4);
+    if (HIST == kHist32) {
+        for (uint32_t b4 = tid * 4; b4 < nvalid; b4 += kHashThreads * 4) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(hist + b4);
+            __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<u32x4 *>(out + b4));
         }
-        __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<u32x4 *>(out + b4));
+        return;
+    }
+    if (HIST == kHist8 && in_slice < 65536u) {
+        for (uint32_t b4 = tid * 4; b4 < nvalid; b4 += kHashThreads * 4) {
+            const uint32_t w = hist[b4 >> 2];
+            __builtin_nontemporal_store(u32x4{w & 0xffu, (w >> 8) & 0xffu, (w >> 16) & 0xffu, w >> 24},
+                                        reinterpret_cast<u32x4 *>(out + b4));
+        }
+        return;
+    }
+    if (HIST == kHist16 || (HIST == kHist16Check && in_slice < 65536u)) {
+        for (uint32_t b4 = tid * 4; b4 < nvalid; b4 += kHashThreads * 4) {
+            const uint32_t w0 = hist[b4 >> 1], w1 = hist[(b4 >> 1) + 1];
+            __builtin_nontemporal_store(u32x4{w0 & 0xffffu, w0 >> 16, w1 & 0xffffu, w1 >> 16},
+                                        reinterpret_cast<u32x4 *>(out + b4));
+        }
+        return;
+    }
+    // a count may have wrapped: the slice counted again in u32, hist_words
+    // bins per pass
+    const uint32_t hw = (uint32_t)a.hist_words;  // multiple of 4
+    for (uint32_t h0 = 0; h0 < nvalid; h0 += hw) {
+        __syncthreads();
+        for (int i = tid * 4; i < a.hist_words; i += kHashThreads * 4)
+            *reinterpret_cast<uint4 *>(hist + i) = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        for_each_key<A, K>(a, st, pos, [&](int64_t, uint32_t key) {
+            const uint32_t bin = key - slice_base - h0;
+            if (bin < hw) atomicAdd(hist + bin, 1u);
+        });
+        __syncthreads();
+        const uint32_t n = nvalid - h0 < hw ? nvalid - h0 : hw;
+        for (uint32_t b4 = tid * 4; b4 < n; b4 += kHashThreads * 4) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(hist + b4);
+            __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<u32x4 *>(out + h0 + b4));
+        }
     }
 }
 
@@ -273,17 +347,17 @@ __global__ void __launch_bounds__(kHashThreads) k_hsel(const HselArgs g)
     });
 }
 
-template <int A, int K, bool U16>
+template <int A, int K, int HIST>
 static int launch_hash(const HashArgs &a, size_t lds, int blocks, hipStream_t st)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_hash<A, K, U16>,
+        (void)hipFuncSetAttribute((const void *)k_hash<A, K, HIST>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, device_lds_bytes());
         (void)hipGetLastError();  // an unsupported attribute must not poison the launch check
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_hash<A, K, U16>), dim3(blocks), dim3(kHashThreads), lds, st, a);
+    hipLaunchKernelGGL((k_hash<A, K, HIST>), dim3(blocks), dim3(kHashThreads), lds, st, a);
     PM_LAUNCHED();
     return PM_OK;
 }
@@ -328,21 +402,28 @@ static int dispatch_hsel(int alphabet, int k, bool u16, bool emit, const HselArg
     }
 }
 
-// run-time (alphabet, k, histogram width) -> compile-time kernel
+// run-time (alphabet, k, count-table width) -> compile-time kernel
+template <int H, int A, int K>
+static int launch_hist(int hist, const HashArgs &a, size_t lds, int blocks, hipStream_t st)
+{
+    if constexpr (H >= kHistModes) {
+        return fail(PM_EINVAL, "unknown count-table width %d", hist);
+    } else {
+        if (hist != H) return launch_hist<H + 1, A, K>(hist, a, lds, blocks, st);
+        return launch_hash<A, K, H>(a, lds, blocks, st);
+    }
+}
+
 template <int K>
-static int dispatch_hash(int alphabet, int k, bool u16, const HashArgs &a, size_t lds, int blocks, hipStream_t st)
+static int dispatch_hash(int alphabet, int k, int hist, const HashArgs &a, size_t lds, int blocks, hipStream_t st)
 {
     constexpr int KMAX = 16;
     if constexpr (K > KMAX) {
         return fail(PM_ERANGE, "k=%d not supported", k);
     } else {
-        if (k != K) {
-            return dispatch_hash<K + 1>(alphabet, k, u16, a, lds, blocks, st);
-        }
-        if (alphabet == 4)
-            return u16 ? launch_hash<4, K, true>(a, lds, blocks, st) : launch_hash<4, K, false>(a, lds, blocks, st);
-        if constexpr (K <= 7)
-            return u16 ? launch_hash<20, K, true>(a, lds, blocks, st) : launch_hash<20, K, false>(a, lds, blocks, st);
+        if (k != K) return dispatch_hash<K + 1>(alphabet, k, hist, a, lds, blocks, st);
+        if (alphabet == 4) return launch_hist<kHist16, 4, K>(hist, a, lds, blocks, st);
+        if constexpr (K <= 7) return launch_hist<kHist16, 20, K>(hist, a, lds, blocks, st);
         return fail(PM_ERANGE, "k=%d not supported for protein", k);
     }
 }
@@ -374,18 +455,21 @@ extern "C" int pm_pack(int32_t alphabet, const uint8_t *ascii, int64_t n_total, 
 }
 
 // LDS layout for the largest instance (staged input, histogram slices):
-// returns the dynamic LDS bytes, or 0 after fail().  extra: further fixed LDS
-// words; balance: split a whole-trial histogram that would leave its
-// workgroup alone on a CU into two slices.
-static size_t hash_layout(HashArgs &a, bool hist, int64_t x_max, int64_t nw_max, int t_max, int extra, bool balance)
+// returns the dynamic LDS bytes, or 0 after fail().  per_word: counts per
+// 32-bit LDS word (1, 2 or 4); extra: further fixed LDS words; balance: split
+// a whole-trial histogram that would leave its workgroup alone on a CU into
+// two slices.
+static size_t hash_layout(HashArgs &a, bool hist, int per_word, int64_t nw_max, int t_max, int extra, bool balance)
 {
-    const bool u16 = x_max < 65536;
     const int lds_max = device_lds_bytes();
-    a.seq_cap = nw_max * 4 <= 48 * 1024 ? (int)nw_max : 0;
+    const int64_t sw = staged_words(a.A, nw_max);
     a.off_cap = (t_max + 1) * 4 <= 8 * 1024 ? t_max + 1 : 0;
+    // protein bytes are read only by the staged path, which needs the
+    // window starts staged too
+    a.seq_cap = sw * 4 <= 48 * 1024 && (a.A == 4 || a.off_cap) ? (int)sw : 0;
     const int fixed = (a.seq_cap + a.off_cap + extra) * 4;
     if (hist) {
-        const int64_t need_words = u16 ? (a.nb + 1) / 2 : a.nb;
+        const int64_t need_words = (a.nb + per_word - 1) / per_word;
         int64_t budget = (lds_max - fixed) / 4;
         budget &= ~int64_t(3);
         if (budget < 1024) {
@@ -403,7 +487,7 @@ static size_t hash_layout(HashArgs &a, bool hist, int64_t x_max, int64_t nw_max,
         hw = (hw + 3) & ~int64_t(3);
         if (hw > budget) hw = budget;
         a.hist_words = (int)hw;
-        a.slice_bins = (uint32_t)(u16 ? 2 * hw : hw);
+        a.slice_bins = (uint32_t)(per_word * hw);
         a.nslices = (int)((a.nb + a.slice_bins - 1) / a.slice_bins);
     } else {
         a.hist_words = 0;
@@ -418,17 +502,33 @@ static size_t hash_layout(HashArgs &a, bool hist, int64_t x_max, int64_t nw_max,
 static int hash_launch(HashArgs &a, int A, int32_t items, int64_t x_max, int64_t nw_max, int t_max,
                        hipStream_t st)
 {
-    const size_t lds = hash_layout(a, a.counts != nullptr, x_max, nw_max, t_max, 0, true);
+    // the count width giving the fewest slices (each slice recomputes its
+    // trial's keys), the widest among equals: no check for u32, nor for u16
+    // below 65 536 windows
+    int hist = kHist16, per_word = 2;
+    if (a.counts) {
+        int best_slices = 0x7fffffff;
+        for (const int pw : {1, 2, 4}) {
+            HashArgs probe = a;
+            if (!hash_layout(probe, true, pw, nw_max, t_max, kHashFlagWords, true)) continue;
+            if (probe.nslices < best_slices) {
+                best_slices = probe.nslices;
+                per_word = pw;
+            }
+        }
+        hist = per_word == 1 ? kHist32 : per_word == 4 ? kHist8 : x_max < 65536 ? kHist16 : kHist16Check;
+    }
+    const size_t lds = hash_layout(a, a.counts != nullptr, per_word, nw_max, t_max, kHashFlagWords, true);
     if (!lds) return PM_ERANGE;
     const int64_t blocks = (int64_t)items * a.nslices;
     if (blocks > 0x7fffffff) return fail(PM_ERANGE, "too many trials x slices");
-    return dispatch_hash<1>(A, a.k, x_max < 65536, a, lds, (int)blocks, st);
+    return dispatch_hash<1>(A, a.k, hist, a, lds, (int)blocks, st);
 }
 
 // ---- fused selection: workspace of per-(item, slice) totals and bases
 static int64_t hsel_entries(HashArgs a, int32_t items, int64_t x_max, int64_t nw_max, int t_max)
 {
-    if (!hash_layout(a, true, x_max, nw_max, t_max, kHselScanWords, false)) return -1;
+    if (!hash_layout(a, true, x_max < 65536 ? 2 : 1, nw_max, t_max, kHselScanWords, false)) return -1;
     return (int64_t)items * a.nslices;
 }
 
@@ -454,7 +554,7 @@ static int hsel_run(HashArgs &a, int A, int32_t items, int64_t x_max, int64_t nw
                     pm_bucket *buckets, int64_t cap_b, uint32_t *members, int64_t cap_m, int64_t *n_out, void *ws,
                     size_t ws_bytes, hipStream_t st)
 {
-    const size_t lds = hash_layout(a, true, x_max, nw_max, t_max, kHselScanWords, false);
+    const size_t lds = hash_layout(a, true, x_max < 65536 ? 2 : 1, nw_max, t_max, kHselScanWords, false);
     if (!lds) return PM_ERANGE;
     const int64_t entries = (int64_t)items * a.nslices;
     if (entries > 0x7fffffff) return fail(PM_ERANGE, "too many trials x slices");
@@ -505,6 +605,7 @@ extern "C" int projection_hash(const pm_seqs *S, int32_t l, int32_t k, const uin
     if ((rc = check_hash_args(A, l, k, masks, m, keys, counts))) return rc;
     if (m == 0) return PM_OK;
     HashArgs a{};
+    a.A = A;
     a.one = inst_of(S, l);
     a.masks = masks;
     a.keys = keys;
@@ -526,6 +627,7 @@ extern "C" int projection_hash_batch(const pm_batch *B, const uint32_t *masks, u
     const int A = B->alphabet;
     if ((rc = check_hash_args(A, B->l, B->k, masks, B->items, keys, counts))) return rc;
     HashArgs a{};
+    a.A = A;
     a.inst = B->inst;
     a.item_inst = B->item_inst;
     a.masks = masks;
@@ -546,6 +648,7 @@ extern "C" size_t pm_hash_select_workspace(const pm_seqs *S, int32_t l, int32_t 
     const int64_t x = num_windows(S, l), nw = pm_packed_words(A, S->n_total);
     if (!dense_sel(A, k)) return hsort_check_k(A, k) ? 0 : hsort_workspace(A, l, k, m, x, nw, S->t);
     HashArgs a{};
+    a.A = A;
     a.nb = ipow(A, k);
     return hsel_ws_bytes(hsel_entries(a, m, x, nw, S->t));
 }
@@ -566,6 +669,7 @@ extern "C" size_t pm_hash_select_batch_workspace(const pm_batch *B)
     if (!dense_sel(A, B->k))
         return hsort_check_k(A, B->k) ? 0 : hsort_workspace(A, B->l, B->k, B->items, info.x_max, info.nw_max, info.t_max);
     HashArgs a{};
+    a.A = A;
     a.nb = ipow(A, B->k);
     return hsel_ws_bytes(hsel_entries(a, B->items, info.x_max, info.nw_max, info.t_max));
 }
@@ -588,6 +692,7 @@ static int hash_select_one(const pm_seqs *S, int32_t l, int32_t k, const uint32_
     const int A = S->alphabet;
     if ((rc = check_hsel_args(A, l, k, masks, m, n_out, buckets, cap_buckets, members, cap_members, ws))) return rc;
     HashArgs a{};
+    a.A = A;
     a.one = inst_of(S, l);
     a.masks = masks;
     a.status = status;
@@ -614,6 +719,7 @@ static int hash_select_batch(const pm_batch *B, const uint32_t *masks, uint32_t 
     if ((rc = check_hsel_args(A, B->l, B->k, masks, B->items, n_out, buckets, cap_buckets, members, cap_members, ws)))
         return rc;
     HashArgs a{};
+    a.A = A;
     a.inst = B->inst;
     a.item_inst = B->item_inst;
     a.masks = masks;
@@ -708,6 +814,7 @@ extern "C" int bucket_hash_select_noalloc(const pm_seqs *S, int32_t l, int32_t k
                               reinterpret_cast<void *>(uintptr_t(1)))))
         return rc;
     HashArgs a{};
+    a.A = A;
     a.one = inst_of(S, l);
     a.masks = masks;
     a.status = status;

@@ -17,11 +17,12 @@ struct HashArgs {
     uint32_t *counts;
     uint32_t *status;
     int64_t nb;          // |Sigma|^k
-    int l, k;
+    int A, l, k;         // alphabet size, motif length, projection size
     int nslices;         // key-range slices per trial
     uint32_t slice_bins; // bins per slice (multiple of 4)
     int hist_words;      // LDS words of histogram
-    int seq_cap;         // LDS words reserved for the packed input (0: read from global)
+    int seq_cap;         // LDS words reserved for the input (0: read from global): DNA the packed
+                         // words, protein one byte per symbol (unpacked on staging)
     int off_cap;         // LDS window starts reserved, t + 1 (0: read offsets from global)
 };
 
@@ -32,7 +33,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // of every sequence start) staged in LDS when the launch reserved room.
 struct Staged {
     pm_inst I;
-    const uint32_t *seq;  // LDS copy (seq_cap) or global words
+    const uint32_t *seq;  // LDS copy (seq_cap; protein: bytes) or the global packed words
     const int32_t *wst;   // LDS window starts, when off_cap
 };
 
@@ -41,7 +42,18 @@ __device__ __forceinline__ Staged stage_input(const HashArgs &a, int j, uint32_t
 {
     const pm_inst I = a.inst ? a.inst[a.item_inst[j]] : a.one;
     const int seq_words = a.seq_cap ? (int)(A == 4 ? (I.n_total + 15) / 16 + 4 : (I.n_total + 5) / 6 + 4) : 0;
-    for (int i = threadIdx.x; i < seq_words; i += kHashThreads) seq[i] = I.packed[i];
+    if (A == 4) {
+        for (int i = threadIdx.x; i < seq_words; i += kHashThreads) seq[i] = I.packed[i];
+    } else {
+        // protein: one byte per symbol, so that a key reads each projected
+        // symbol with one LDS byte load instead of a division by six
+        uint8_t *sb = reinterpret_cast<uint8_t *>(seq);
+        for (int i = threadIdx.x; i < seq_words; i += kHashThreads) {
+            const uint32_t v = I.packed[i];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) sb[6 * i + q] = (uint8_t)((v >> (27 - 5 * q)) & 31u);
+        }
+    }
     if (a.off_cap)
         for (int i = threadIdx.x; i <= I.t; i += kHashThreads) wst[i] = (int32_t)(I.offsets[i] - (int64_t)i * (a.l - 1));
     return Staged{I, a.seq_cap ? seq : I.packed, wst};
@@ -85,12 +97,9 @@ __device__ __forceinline__ void for_each_key(const HashArgs &a, const Staged &st
 #pragma unroll
                 for (int q = 0; q < K; ++q) key = (key << 2) | ((uint32_t)(win >> pos[q]) & 3u);
             } else {
+                const uint8_t *sb = reinterpret_cast<const uint8_t *>(seq);
 #pragma unroll
-                for (int q = 0; q < K; ++q) {
-                    const uint32_t g = P + (uint32_t)pos[q];
-                    const uint32_t qq = div6(g);
-                    key = key * 20u + ((seq[qq] >> (27 - 5 * (g - 6u * qq))) & 31u);
-                }
+                for (int q = 0; q < K; ++q) key = key * 20u + sb[P + (uint32_t)pos[q]];
             }
             fn((int64_t)w, key);
         }
@@ -125,6 +134,10 @@ __device__ __forceinline__ bool mask_ok(const HashArgs &a, uint32_t mask)
     return __popc(mask) == a.k && !(mask & ~lmask);
 }
 
+// LDS words that stage an instance of nw packed words: the words themselves
+// (DNA) or one byte per symbol (protein, six per word)
+__host__ __device__ inline int64_t staged_words(int A, int64_t nw) { return A == 4 ? nw : (6 * nw + 3) / 4; }
+
 // The key of window w (w < x), with i the sequence index of an earlier
 // window of the caller (0 at the start; advanced here).  Same arithmetic as
 // for_each_key, for loops whose trip count must be the same in every thread.
@@ -147,12 +160,9 @@ __device__ __forceinline__ uint32_t window_key(const HashArgs &a, const Staged &
 #pragma unroll
             for (int q = 0; q < K; ++q) key = (key << 2) | ((uint32_t)(win >> pos[q]) & 3u);
         } else {
+            const uint8_t *sb = reinterpret_cast<const uint8_t *>(seq);
 #pragma unroll
-            for (int q = 0; q < K; ++q) {
-                const uint32_t g = P + (uint32_t)pos[q];
-                const uint32_t qq = div6(g);
-                key = key * 20u + ((seq[qq] >> (27 - 5 * (g - 6u * qq))) & 31u);
-            }
+            for (int q = 0; q < K; ++q) key = key * 20u + sb[P + (uint32_t)pos[q]];
         }
     } else {
         const int64_t *O = st.I.offsets;

@@ -315,8 +315,9 @@ static int dispatch_hsort(int alphabet, int k, bool emit, const HsortArgs &g, si
 static size_t hsort_layout(HashArgs &a, int64_t x_max, int64_t nw_max, int t_max)
 {
     const int lds_max = device_lds_bytes();
-    a.seq_cap = nw_max * 4 <= 48 * 1024 ? (int)nw_max : 0;
+    const int64_t sw = staged_words(a.A, nw_max);
     a.off_cap = (t_max + 1) * 4 <= 8 * 1024 ? t_max + 1 : 0;
+    a.seq_cap = sw * 4 <= 48 * 1024 && (a.A == 4 || a.off_cap) ? (int)sw : 0;
     a.hist_words = 0;
     a.slice_bins = 0;
     // slices of the key range sized for about half a sort buffer of windows
@@ -353,6 +354,7 @@ int hsort_check_k(int A, int k)
 size_t hsort_workspace(int A, int l, int k, int32_t items, int64_t x_max, int64_t nw_max, int t_max)
 {
     HashArgs a{};
+    a.A = A;
     a.nb = ipow(A, k);
     a.l = l;
     a.k = k;

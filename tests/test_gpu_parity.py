@@ -166,6 +166,25 @@ def test_hash_degenerate_single_bucket():
     assert np.all(K == 0) and np.all(N[:, 0] == x) and np.all(N[:, 1:] == 0)
 
 
+@pytest.mark.parametrize("k,l,extra", [(3, 7, 0), (9, 12, 6), (8, 11, 3)],
+                         ids=["one slice", "k=9 several slices", "k=8 two slices"])
+def test_hash_count_past_u16_is_recounted(k, l, extra):
+    """More than 65 535 windows share one key (poly-A, x >= 65 536): the LDS
+    count of that bin wraps its 16 bits, so the slice holding it is counted
+    again in u32; every count bit-exact against the oracle, beside random
+    sequences whose keys fill the other bins and slices."""
+    rng = np.random.default_rng(100 + k)
+    seqs = ["A" * 40000, "A" * 36000] + random_sequences(rng, extra, [3000] * extra, "dna")
+    masks = projection_masks(rng, l, k, 2)
+    say(f"hash u16 wrap k={k}")
+    S = pm.Seqs(4, seqs)
+    K, N, st = _hash_gpu(S, l, k, masks)
+    assert st == 0
+    RK, RN = oracle.hash_trials(oracle.Seqs(4, seqs), l, k, masks)
+    assert np.array_equal(K, RK) and np.array_equal(N, RN)
+    assert N[:, 0].min() > 65535
+
+
 # ------------------------------------------------------------------ a5, a6
 def _select_gpu(S, l, k, s, K, N, cap_b=None, cap_m=None):
     m = K.shape[0]
