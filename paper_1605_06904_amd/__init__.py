@@ -990,9 +990,15 @@ class TriagedBatchPipeline(BatchPipeline):
         em_best_batch(self.B, L["buckets"], L["J"], self.b.cap_b, L["n"], self.iters, L["theta"], L["best"], None,
                       stream)
 
-    def triage(self, stream=None):
+    def score_buckets(self, stream=None):
+        """Scores of every bucket into score_buf: the network's (a subclass
+        may rank the buckets another way)."""
         b, B = self.b, self.B
         self.tri.score(B.l, b.profile, b.cap_b, b.n_out, self.bg, self.feat, self.score_buf, stream)
+
+    def triage(self, stream=None):
+        b, B = self.b, self.B
+        self.score_buckets(stream)
         L1, L2 = self.lists
         triage_select(B, b.buckets, self.score_buf, b.cap_b, b.n_out, self.frac, b.theta0, B.alphabet, B.l,
                       self.taken, L1["buckets"], L1["theta0"], L1["index"], L1["n"], self.sel_ws, self.sel_ws_bytes,

@@ -10,8 +10,9 @@
    triage_features) and its post-EM outcome: 1 when its refinement ends at the
    motif of its instance's winner (same consensus), else 0 -- what triage must
    rank.  Winning buckets are rare and are kept up to a third of the pairs.
-   (--label llr: the post-EM LLR(theta^iters) / t standardised within the
-   instance instead.)
+   (--label planted: 1 when the refinement ends at the motif planted in the
+   instance, which the generator knows; --label llr: the post-EM
+   LLR(theta^iters) / t standardised within the instance.)
 3. Standardise features and scores with the training statistics, train the
    network with the library's FP32 forward/backward and Adam kernels on
    mini-batches, then fold the score standardisation into the last layer.
@@ -64,6 +65,14 @@ def _run_full(pm, torch, insts, l, k, s, iters, bg, label="winner"):
         win_cons = cons[best[inst_d]]
         has = torch.tensor([r["best"] >= 0 for r in res], device="cuda")[inst_d]
         score = ((cons == win_cons).all(dim=1) & has).float().cpu().numpy()
+    elif label == "planted":
+        # 1 where the bucket's refinement ends at the motif planted in its
+        # instance (the generator knows it; serving never needs it), else 0
+        order = pm.code_order(4)
+        planted = torch.tensor([[order.index(ch) for ch in inst.motif] for inst, _ in insts], device="cuda")
+        cons = P.b.theta[:nb_].argmax(dim=1)
+        inst_d = torch.from_numpy(inst_of.astype(np.int64)).cuda()
+        score = (cons == planted[inst_d]).all(dim=1).float().cpu().numpy()
     else:
         t = np.array(B.t)[inst_of]
         score = P.b.llr[:nb_, -1].cpu().numpy() / t
@@ -199,7 +208,7 @@ def main(argv=None):
     ap.add_argument("--mb", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--frac", type=float, default=0.05)
-    ap.add_argument("--label", choices=["winner", "llr"], default="winner")
+    ap.add_argument("--label", choices=["winner", "planted", "llr"], default="winner")
     ap.add_argument("--extra-c1", type=int, default=0, help="(15,4) instances added to the training runs")
     args = ap.parse_args(argv)
     import torch
@@ -211,8 +220,8 @@ def main(argv=None):
                                   log)
     X, y = np.concatenate(Xs), np.concatenate(ys)
     rng = np.random.default_rng(args.seed)
-    if args.label == "winner":
-        # winning buckets are rare: keep them up to a third of the pairs
+    if args.label in ("winner", "planted"):
+        # positive buckets are rare: keep them up to a third of the pairs
         pos, neg = np.nonzero(y > 0.5)[0], np.nonzero(y <= 0.5)[0]
         npos = min(len(pos), args.pairs // 3)
         keep = np.concatenate([rng.choice(pos, size=npos, replace=False),
@@ -241,8 +250,10 @@ def main(argv=None):
     meta = dict(pairs=int(len(y)), seed=args.seed, extra_c1=args.extra_c1, epochs=args.epochs, minibatch=args.mb, lr=args.lr,
                 fallback="z-score of the triaged winner's J among the instance's refined buckets",
                 frac=args.frac, triaged_solved=int(sum(ok for _, _, ok in zrows)),
-                label=("1 if the bucket's refinement ends at the instance winner's consensus" if args.label == "winner"
-                       else "LLR(theta^iters)/t, standardised within the instance"), thresholds_by_l=per_l, threshold_pooled=pooled,
+                label={"winner": "1 if the bucket's refinement ends at the instance winner's consensus",
+                       "planted": "1 if the bucket's refinement ends at the planted motif's consensus",
+                       "llr": "LLR(theta^iters)/t, standardised within the instance"}[args.label],
+                thresholds_by_l=per_l, threshold_pooled=pooled,
                 winners=len(win), solved_winners=int(sum(ok for _, _, ok in win)),
                 seconds=round(time.time() - t0, 1))
     tri = pm.Triage(params, mu, sd, pooled, meta=meta)

@@ -1,10 +1,15 @@
-"""What the trained triage network gains over the method without it.
+"""What the trained triage network gains over the method without it, and how
+its ranking compares with simpler ones.
 
-On held-out (15,4) instances (seeds the training never saw): the network's
-ranking against an untrained one at the same 5% of refined buckets, and the
-triaged pipeline with its fallback against full refinement (the method
-without the network).  Training outcome: parity unpinned (stochastic); this
-test states the gain.
+On 64 held-out (15,4) instances (seeds the training never saw) the enriched
+buckets of every instance are ranked four ways and the top 5% of each
+instance refined, without fallback: by the trained network, by an untrained
+network of the same shape, by bucket size (random order among equal sizes),
+and at random.  Recovery is measured by the performance coefficient of the
+winner's sites against the planted ones and by the instances whose consensus
+is the planted motif.  The triaged pipeline with its fallback is held to full
+refinement (the method without the network) at equal recovery, mean PC within
+0.01.  Training outcome: parity unpinned (stochastic); measured here.
 """
 import os
 import sys
@@ -35,37 +40,55 @@ def trained():
     return pm.Triage.load(path)
 
 
-def _solved(results, insts):
-    return sum(r.get("consensus") == inst.motif for r, (inst, _) in zip(results, insts))
+def perf_coefficient(starts, sites, l):
+    inter = union = 0
+    for a, b in zip(starts, sites):
+        ov = max(0, min(a, b) + l - max(a, b))
+        inter += ov
+        union += 2 * l - ov
+    return inter / union
 
 
-def _run(B, s, iters, bg, nb_, nm_, tri, threshold):
-    TP = pm.TriagedBatchPipeline(B, s, iters, 1.0, pm.PM_F16X2, bg, nb_, nm_, tri, frac=0.05)
-    if threshold is not None:
-        TP.threshold = threshold
-    TP.run()
-    res = TP.results()
-    return res, TP.refined
+class RankedPipeline(pm.TriagedBatchPipeline):
+    """The triaged pipeline with the buckets ranked by size (random order
+    among equal sizes) or at random instead of by the network."""
+
+    def __init__(self, *args, ranking="network", seed=1, **kw):
+        super().__init__(*args, **kw)
+        self.ranking = ranking
+        self.rng = np.random.default_rng(seed)
+
+    def score_buckets(self, stream=None):
+        if self.ranking == "network":
+            return super().score_buckets(stream)
+        u = torch.from_numpy(self.rng.random(self.b.cap_b).astype(np.float32)).cuda()
+        if self.ranking == "size":
+            self.score_buf.copy_(self.b.buckets[:, 2].float() + 0.5 * u)
+        else:
+            self.score_buf.copy_(u)
 
 
-def test_trained_triage_gain_on_held_out_instances(trained):
-    """On 64 held-out (15,4) instances the triaged pipeline with its fallback
-    recovers the planted motif within one instance of full refinement (the
-    method without the network) while refining fewer buckets.  The ranking
-    alone (no fallback, 5% refined) is reported against an untrained network
-    and not asserted: on this shape the profile of a bucket says little about
-    where its refinement ends (parity unpinned; measured)."""
+def _recovery(results, insts, l):
+    solved = sum(r.get("consensus") == inst.motif for r, (inst, _) in zip(results, insts))
+    pc = float(np.mean([perf_coefficient(inst.starts, r.get("sites", [0] * len(inst.starts)), l)
+                        for r, (inst, _) in zip(results, insts)]))
+    return solved, pc
+
+
+def test_trained_triage_against_other_rankings_on_held_out_instances(trained):
     n = 64
     insts = [make_config("c1", seed=20000 + i) for i in range(n)]
     cfg = insts[0][0].meta
     l, k, s, iters = cfg["l"], cfg["k"], cfg["s"], cfg["iters"]
     bg = np.full(4, 0.25)
-    say(f"triage gain on {n} held-out (15,4) instances")
+    say(f"triage rankings on {n} held-out (15,4) instances")
     B = pm.Batch(4, l, k, [i.seqs for i, _ in insts], [mk for _, mk in insts])
     nb_, nm_ = pm.size_batch(B, s)
     full = pm.BatchPipeline(B, s, iters, 1.0, pm.PM_F16X2, bg, nb_, nm_)
     full.run()
-    solved_full = _solved(full.results(), insts)
+    s_full, pc_full = _recovery(full.results(), insts, l)
+    del full
+    torch.cuda.empty_cache()
 
     rng = np.random.default_rng(0)
     sizes = (pm.PM_TRIAGE_INPUTS, 256, 256, 1)
@@ -74,13 +97,23 @@ def test_trained_triage_gain_on_held_out_instances(trained):
         parts += [rng.normal(0, np.sqrt(2.0 / a), size=a * b), np.zeros(b)]
     untrained = pm.Triage(np.concatenate(parts).astype(np.float32), trained.mu.cpu().numpy(),
                           trained.sd.cpu().numpy(), -np.inf)
-    res_u, ref_u = _run(B, s, iters, bg, nb_, nm_, untrained, -np.inf)
-    res_t, ref_t = _run(B, s, iters, bg, nb_, nm_, trained, -np.inf)
-    res_f, ref_f = _run(B, s, iters, bg, nb_, nm_, trained, None)
-    su, st, sf = _solved(res_u, insts), _solved(res_t, insts), _solved(res_f, insts)
-    fell = sum(r["fell_back"] for r in res_f)
-    print(f"[gain] {n} instances, {nb_} buckets: full EM solved {solved_full}; 5% by untrained network "
-          f"{su} ({ref_u} refined); 5% by trained network {st} ({ref_t} refined); trained + fallback {sf} "
-          f"({ref_f} refined = {ref_f / nb_:.3f}, {fell} fallbacks)", flush=True)
-    assert sf >= solved_full - 1
-    assert ref_f < nb_
+    out = {}
+    for name, tri, ranking, fallback in (("trained", trained, "network", False),
+                                         ("untrained", untrained, "network", False),
+                                         ("size", trained, "size", False), ("random", trained, "random", False),
+                                         ("trained+fallback", trained, "network", True)):
+        TP = RankedPipeline(B, s, iters, 1.0, pm.PM_F16X2, bg, nb_, nm_, tri, frac=0.05, ranking=ranking)
+        if not fallback:
+            TP.threshold = -np.inf
+        TP.run()
+        res = TP.results()
+        out[name] = _recovery(res, insts, l) + (TP.refined,)
+        del TP
+        torch.cuda.empty_cache()
+    print(f"[gain] {n} instances, {nb_} buckets; full EM: {s_full} solved, PC {pc_full:.4f}; "
+          + "; ".join(f"{k}: {v[0]} solved, PC {v[1]:.4f}, {v[2]} refined" for k, v in out.items()), flush=True)
+    # equal recovery with the fallback, on a fraction of the EM work
+    assert out["trained+fallback"][1] >= pc_full - 0.01
+    assert out["trained+fallback"][2] < nb_
+    # the network's 5% recovers more than 5% drawn at random
+    assert out["trained"][1] > out["random"][1] and out["trained"][0] >= out["random"][0]
