@@ -571,7 +571,7 @@ def c3_full_leg(torch, pm, m=1000, chunk=250, count=512, seed=1):
             B = pm.Batch(4, l, k, [i.seqs for i, _ in group], [mk[c0:c0 + chunk] for _, mk in group])
             nb = 4 ** k
             # sizes of the chunk's lists (untimed), then its buffers
-            sws0 = pm.pm_select_workspace(B.items, 0)
+            sws0 = pm.pm_select_workspace(4, k, B.items, 0)
             ws = torch.empty(max(sws0, 16), dtype=torch.uint8, device="cuda")
             pm.projection_hash_batch(B, B.masks, keys, counts, status)
             pm.bucket_select_batch(B, keys, counts, s, None, 0, None, 0, n_out, ws, sws0, None)
@@ -581,7 +581,7 @@ def c3_full_leg(torch, pm, m=1000, chunk=250, count=512, seed=1):
                 bk = torch.empty((int(nbk * 1.1) + 1, 4), dtype=torch.int32, device="cuda")
             if mem.numel() < nmem:
                 mem = torch.empty(int(nmem * 1.1) + 1, dtype=torch.int32, device="cuda")
-            sws = pm.pm_select_workspace(B.items, nbk)
+            sws = pm.pm_select_workspace(4, k, B.items, nbk)
             ws = torch.empty(max(sws, 16), dtype=torch.uint8, device="cuda")
             hws = pm.pm_hash_select_batch_workspace(B)
             hw = torch.empty(max(hws, 16), dtype=torch.uint8, device="cuda")

@@ -135,8 +135,11 @@ int pm_auto_params(int32_t alphabet, int32_t t, int64_t x, int32_t l, int32_t d,
 int projection_hash(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m,
                     uint32_t *keys, uint32_t *counts, uint32_t *status, void *stream);
 
-/* Workspace bytes bucket_select needs for m trials and cap_buckets buckets. */
-size_t pm_select_workspace(int32_t m, int64_t cap_buckets);
+/* Workspace bytes bucket_select needs for m trials of |Sigma|^k bins and
+ * cap_buckets buckets (a per-trial bitmap of passing keys, per-trial totals
+ * and per-bucket member cursors); 0 when the alphabet is not 4 or 20 or
+ * |Sigma|^k exceeds 2^19. */
+size_t pm_select_workspace(int32_t alphabet, int32_t k, int32_t m, int64_t cap_buckets);
 
 /* a5 -- Alg. 2 step 3 and Sec. 6 (a bucket passes when it holds at least s
  * l-mers): list every (trial, key) with counts >= s, ascending by (trial,
@@ -147,8 +150,9 @@ size_t pm_select_workspace(int32_t m, int64_t cap_buckets);
  *   n_out         device int64[2]: required number of buckets and members
  *                 (may exceed the capacities: then the lists are truncated to
  *                 their first entries and PM_STATUS_CAPACITY is set)
- *   ws            device, pm_select_workspace(m, cap_buckets) bytes
- * Limit: |Sigma|^k <= 2^24. */
+ *   ws            device, pm_select_workspace(alphabet, k, m, cap_buckets)
+ *                 bytes, 8-byte aligned
+ * The counts are read once.  Limit: |Sigma|^k <= 2^19 (PM_ERANGE above). */
 int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *keys,
                   const uint32_t *counts, int32_t m, uint32_t s, pm_bucket *buckets,
                   int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out,
@@ -383,7 +387,8 @@ int projection_hash_batch(const pm_batch *B, const uint32_t *masks, uint32_t *ke
                           uint32_t *status, void *stream);
 
 /* a5 over every item of a batch; same outputs as bucket_select with `trial`
- * holding the item.  ws: pm_select_workspace(items, cap_buckets) bytes. */
+ * holding the item.  ws: pm_select_workspace(alphabet, k, items, cap_buckets)
+ * bytes, 8-byte aligned. */
 int bucket_select_batch(const pm_batch *B, const uint32_t *keys, const uint32_t *counts, uint32_t s,
                         pm_bucket *buckets, int64_t cap_buckets, uint32_t *members, int64_t cap_members,
                         int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status, void *stream);

@@ -114,7 +114,7 @@ def lib():
         "pm_masks_from_seed": (C.c_int, [u64, i32, i32, i32, P]),
         "pm_auto_params": (C.c_int, [i32, i32, i64, i32, i32, dbl, P, P, P]),
         "projection_hash": (C.c_int, [C.POINTER(pm_seqs), i32, i32, P, i32, P, P, P, P]),
-        "pm_select_workspace": (sz, [i32, i64]),
+        "pm_select_workspace": (sz, [i32, i32, i32, i64]),
         "bucket_select": (C.c_int, [C.POINTER(pm_seqs), i32, i32, P, P, i32, u32, P, i64, P, i64,
                                     P, P, sz, P, P]),
         "bucket_profile": (C.c_int, [C.POINTER(pm_seqs), i32, P, P, i64, i64, P, P, P]),
@@ -231,8 +231,8 @@ def projection_hash(S: "Seqs", l, k, masks, m, keys=None, counts=None, status=No
                                  _ptr(status), _stream(stream)))
 
 
-def pm_select_workspace(m: int, cap_buckets: int) -> int:
-    return int(lib().pm_select_workspace(m, cap_buckets))
+def pm_select_workspace(alphabet: int, k: int, m: int, cap_buckets: int) -> int:
+    return int(lib().pm_select_workspace(alphabet, k, m, cap_buckets))
 
 
 def bucket_select(S, l, k, keys, counts, m, s, buckets, cap_buckets, members, cap_members, n_out,
@@ -650,7 +650,7 @@ class Pipeline:
         dev = device
         self.masks = torch.from_numpy(np.ascontiguousarray(masks, dtype=np.uint32).view(np.int32)).to(dev)
         self.bg = torch.as_tensor(np.asarray(bg, dtype=np.float64), device=dev)
-        ws_bytes = pm_select_workspace(self.m, cap_b)
+        ws_bytes = pm_select_workspace(A, k, self.m, cap_b)
         AL = A * l
         z = lambda *shape, dt=torch.int32: torch.zeros(*shape, dtype=dt, device=dev)
         self.b = PassBuffers(
@@ -791,7 +791,7 @@ class BatchPipeline:
         self.nb = A ** B.k
         dev = device
         self.bg = torch.as_tensor(np.asarray(bg, dtype=np.float64), device=dev)
-        self.ws_bytes = pm_select_workspace(B.items, cap_b)
+        self.ws_bytes = pm_select_workspace(A, B.k, B.items, cap_b)
         self.em_ws_bytes = pm_em_batch_workspace(B, precision)
         cb = max(cap_b, 1)
         z = lambda *shape, dt=torch.int32: torch.zeros(*shape, dtype=dt, device=dev)

@@ -56,13 +56,18 @@ struct BatchInfo {
 int check_batch(const pm_batch *B, BatchInfo *info);
 
 // exclusive scan of n per-entry (bucket, member) totals into bases; writes the
-// grand totals to n_out and PM_STATUS_CAPACITY when they exceed the capacities
+// grand totals to n_out and PM_STATUS_CAPACITY when they exceed the capacities.
+// With `heavy` set, also lists in order the entries with more than heavy_above
+// buckets, and their number in n_heavy.
 struct TotScan {
     const int64_t *ne, *ms;
     int64_t *bb, *mb;
     int64_t n, cap_b, cap_m;
     int64_t *n_out;
     uint32_t *status;
+    int32_t *heavy;
+    int64_t *n_heavy;
+    int64_t heavy_above;
 };
 int launch_tot_scan(const TotScan &a, hipStream_t st);
 

@@ -164,7 +164,7 @@ void empty_result(pm_result &R, const Prepared &Q)
 int run_single(const Prepared &Q, const pm_options &O, pm_result &R, hipStream_t st)
 {
     const int A = Q.A, l = Q.l, k = Q.k, s = Q.s, m = Q.m, t = Q.t;
-    const int64_t n_total = Q.n_total, x = Q.x;
+    const int64_t n_total = Q.n_total;
     empty_result(R, Q);
     const int64_t nw = pm_packed_words(A, n_total);
     DevBuf d_ascii, d_off, d_packed, d_masks, d_status, d_nout, d_ws;

@@ -2,12 +2,17 @@
 //
 // The paper finds enriched buckets by comparing every k-mer with every other
 // one (Sec. 6, quadratic work) to avoid a |Sigma|^k table.  On MI355X the dense
-// counts already sit in HBM (the histogram of projection_hash), so selection is
-// a streaming pass: count the passing bins per trial, scan the per-trial
-// totals, then one workgroup per trial turns its counts into an LDS bitmap of
-// passing keys (one ballot per 64 keys), scans it to give every bucket its
-// index and first member slot, and places the member windows with a stable,
-// deterministic two-pass counting sort over four window quarters.
+// counts already sit in HBM (the histogram of projection_hash), so selection
+// reads them once: a counting pass per trial writes the number of passing
+// bins, their total size and a bitmap of the passing keys (one bit per key).
+// After a scan of the per-trial totals, one workgroup per trial loads its
+// bitmap into LDS, gathers the counts of the passing keys only, scans them
+// into bucket numbers and first member slots, and places the member windows
+// with a stable counting sort: the windows go by in order in chunks, each wave
+// groups its passing windows by key (by a sort across the wave when many
+// pass), and every bucket keeps its next free slot per wave in LDS.
+#include <algorithm>
+
 #include "pm_common.h"
 
 namespace pm {
@@ -17,11 +22,19 @@ struct SelWs {
     int64_t *ms;      // [m] members per trial
     int64_t *bb;      // [m] first bucket of the trial
     int64_t *mb;      // [m] first member slot of the trial
-    uint32_t *qcnt;   // [cap_b][4] members of the bucket in each window quarter
-    uint32_t *placed; // [cap_b][4] members placed so far by each quarter's wave
+    int64_t *n_heavy; // [1] trials with more buckets than the first emit launch takes
+    int32_t *heavy;   // [m] those trials, in order
+    uint64_t *bits;   // [m][nwb] passing keys: bit key % 64 of word key / 64
+    uint32_t *rows;   // [cap_b][4] member cursors of trials with more buckets than the LDS holds
 };
 
-static SelWs carve(void *ws, int32_t m, int64_t cap_b)
+static size_t sel_ws_bytes(int32_t m, int64_t nwb, int64_t cap_b)
+{
+    const size_t head = (size_t)m * 4 * sizeof(int64_t) + sizeof(int64_t) + (((size_t)m * 4 + 7) & ~(size_t)7);
+    return head + (size_t)m * nwb * 8 + (size_t)cap_b * 4 * sizeof(uint32_t) + 256;
+}
+
+static SelWs carve(void *ws, int32_t m, int64_t nwb)
 {
     char *p = static_cast<char *>(ws);
     SelWs w;
@@ -29,8 +42,11 @@ static SelWs carve(void *ws, int32_t m, int64_t cap_b)
     w.ms = w.ne + m;
     w.bb = w.ms + m;
     w.mb = w.bb + m;
-    w.qcnt = reinterpret_cast<uint32_t *>(w.mb + m);
-    w.placed = w.qcnt + 4 * cap_b;
+    w.n_heavy = w.mb + m;
+    w.heavy = reinterpret_cast<int32_t *>(w.n_heavy + 1);
+    w.bits = reinterpret_cast<uint64_t *>(p + (size_t)m * 4 * sizeof(int64_t) + sizeof(int64_t) +
+                                          (((size_t)m * 4 + 7) & ~(size_t)7));
+    w.rows = reinterpret_cast<uint32_t *>(w.bits + (int64_t)m * nwb);
     return w;
 }
 
@@ -46,34 +62,71 @@ struct SelArgs {
     uint32_t *status;
     SelWs ws;
     int64_t nb, cap_b, cap_m;
-    int32_t m;  // trials (items)
+    int64_t take_hi;  // k_sel_emit: trials with 0 < buckets <= take_hi
+    int32_t m;                 // trials (items)
     uint32_t s;
     int nwb;  // bitmap words, ceil(nb / 64)
+    int cb;   // buckets whose cursors the LDS holds
 };
 
 __device__ __forceinline__ bool passes(uint32_t c, uint32_t s) { return c >= s && c > 0; }
 
-// per trial: number of passing bins and their total size
+// bit i of a 16-bit value moved to bit 4i
+__device__ __forceinline__ uint64_t spread4(uint32_t x)
+{
+    uint64_t v = x & 0xffffu;
+    v = (v | (v << 24)) & 0x000000ff000000ffull;
+    v = (v | (v << 12)) & 0x000f000f000f000full;
+    v = (v | (v << 6)) & 0x0303030303030303ull;
+    v = (v | (v << 3)) & 0x1111111111111111ull;
+    return v;
+}
+
+// per trial: number of passing bins, their total size and the bitmap of the
+// passing keys; a wave reads 4 x 256 bins at a time as uint4 per lane
 __global__ void __launch_bounds__(256) k_sel_count(const SelArgs a)
 {
     const int j = blockIdx.x;
+    const int wv = threadIdx.x >> 6, lane = lane_id();
     const uint4 *cnt = reinterpret_cast<const uint4 *>(a.counts + (int64_t)j * a.nb);  // nb % 4 == 0
+    uint64_t *bits = a.ws.bits + (int64_t)j * a.nwb;
+    const int64_t n4 = a.nb / 4;
     uint64_t ne = 0, ms = 0;
-    for (int64_t b = threadIdx.x; b < a.nb / 4; b += 256) {
-        const uint4 v = cnt[b];
-        const uint32_t c[4] = {v.x, v.y, v.z, v.w};
+    constexpr int U = 4;
+    for (int64_t c0 = (int64_t)wv * 64 * U; c0 < n4; c0 += 256 * U) {
+        uint4 v[U];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (passes(c[q], a.s)) {
-                ne += 1;
-                ms += c[q];
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = c0 + 64 * u + lane;
+            v[u] = i < n4 ? cnt[i] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t c[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+            uint64_t bal[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool p = passes(c[q], a.s);
+                ne += p ? 1u : 0u;
+                ms += p ? c[q] : 0u;
+                bal[q] = __ballot(p);
             }
+            // lanes 16g .. 16g+15 hold bins 64g .. 64g+63 of these 256:
+            // bit 4i+q of word g is bin q of lane 16g+i
+            if (lane < 4) {
+                const int64_t wi = (c0 + 64 * u) / 16 + lane;
+                const int sh = 16 * lane;
+                uint64_t w = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) w |= spread4((uint32_t)(bal[q] >> sh)) << q;
+                if (wi < a.nwb) bits[wi] = w;
+            }
+        }
     }
     ne = wave_sum(ne);
     ms = wave_sum(ms);
     __shared__ uint64_t red[2][4];
-    const int wv = threadIdx.x >> 6;
-    if (lane_id() == 0) {
+    if (lane == 0) {
         red[0][wv] = ne;
         red[1][wv] = ms;
     }
@@ -85,18 +138,24 @@ __global__ void __launch_bounds__(256) k_sel_count(const SelArgs a)
 }
 
 // exclusive scan of per-trial (or per trial-slice) totals, one workgroup:
-// bases of every entry, the required totals in n_out, capacity status
+// bases of every entry, the required totals in n_out, capacity status, and
+// on request the list of heavy entries
 __global__ void __launch_bounds__(1024) k_tot_scan(const TotScan a)
 {
     __shared__ int64_t sa[1024], sb[1024];
-    __shared__ int64_t carry[2];
-    if (threadIdx.x == 0) carry[0] = carry[1] = 0;
+    __shared__ int64_t carry[3];
+    __shared__ uint32_t hw[16];
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    if (threadIdx.x == 0) carry[0] = carry[1] = carry[2] = 0;
     __syncthreads();
     for (int64_t base = 0; base < a.n; base += 1024) {
         const int64_t j = base + threadIdx.x;
         const int64_t ve = j < a.n ? a.ne[j] : 0, vm = j < a.n ? a.ms[j] : 0;
         sa[threadIdx.x] = ve;
         sb[threadIdx.x] = vm;
+        const bool h = a.heavy && j < a.n && ve > a.heavy_above;
+        const uint64_t hb = __ballot(h);
+        if (lane == 0) hw[wave] = (uint32_t)__popcll(hb);
         __syncthreads();
         for (int o = 1; o < 1024; o <<= 1) {
             int64_t ua = 0, ub = 0;
@@ -113,10 +172,18 @@ __global__ void __launch_bounds__(1024) k_tot_scan(const TotScan a)
             a.bb[j] = carry[0] + sa[threadIdx.x] - ve;
             a.mb[j] = carry[1] + sb[threadIdx.x] - vm;
         }
+        if (h) {
+            int64_t at = carry[2] + __popcll(hb & lanemask_lt());
+            for (int w = 0; w < wave; ++w) at += hw[w];
+            a.heavy[at] = (int32_t)j;
+        }
         __syncthreads();
         if (threadIdx.x == 1023) {
             carry[0] += sa[1023];
             carry[1] += sb[1023];
+            int64_t nh = 0;
+            for (int w = 0; w < 16; ++w) nh += hw[w];
+            carry[2] += nh;
         }
         __syncthreads();
     }
@@ -124,6 +191,7 @@ __global__ void __launch_bounds__(1024) k_tot_scan(const TotScan a)
         a.n_out[0] = carry[0];
         a.n_out[1] = carry[1];
         if ((carry[0] > a.cap_b || carry[1] > a.cap_m) && a.status) atomicOr(a.status, PM_STATUS_CAPACITY);
+        if (a.heavy) a.n_heavy[0] = carry[2];
     }
 }
 
@@ -158,127 +226,331 @@ __device__ void block_excl_scan(uint32_t *v, int n, uint32_t *tmp)
     __syncthreads();
 }
 
-// one workgroup (four waves) per trial
-__global__ void __launch_bounds__(256) k_sel_emit(const SelArgs a)
+// ---------------------------------------------------------------- members
+constexpr int kSelU = 8;                   // window loads in flight per lane
+constexpr int kSelChunk = 4 * 64 * kSelU;  // windows per workgroup step
+constexpr int kSelSortMin = 6;             // flagged lanes from which a wave groups by sorting
+constexpr uint32_t kNoSlot = 0xffffffffu;
+
+struct Group {
+    int head;       // lowest lane holding the same key
+    uint32_t rank;  // lanes below this one holding the same key
+    uint32_t n;     // lanes holding the key (set at the head)
+};
+
+// Groups the flagged lanes of a wave by key (keys below 2^26 - 1).  With few
+// flagged lanes, one ballot per distinct key; with many, a bitonic sort of
+// (key, lane) across the wave, run heads and run ends by scans, and the
+// results pushed back to the lanes they belong to.  Both give the same answer.
+__device__ __forceinline__ Group group_by_key(bool flag, uint32_t key)
 {
-    extern __shared__ __align__(16) uint64_t bm[];  // [nwb] passing keys
+    const int lane = lane_id();
+    const uint64_t bal = __ballot(flag);
+    Group g{lane, 0u, 0u};
+    if (__popcll(bal) < kSelSortMin) {
+        uint64_t left = bal;
+        while (left) {
+            const int leader = __ffsll((unsigned long long)left) - 1;
+            const uint32_t lk = __shfl(key, leader);
+            const uint64_t peers = __ballot(flag && key == lk);
+            if ((peers >> lane) & 1ull) {
+                g.head = leader;
+                g.rank = (uint32_t)__popcll(peers & lanemask_lt());
+                g.n = (uint32_t)__popcll(peers);
+            }
+            left &= ~peers;
+        }
+        return g;
+    }
+    constexpr uint32_t kNoKey = 0x3ffffffu;  // sorts after every key
+    uint32_t v = ((flag ? key : kNoKey) << 6) | (uint32_t)lane;
+#pragma unroll
+    for (int kk = 2; kk <= 64; kk <<= 1)
+#pragma unroll
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            const uint32_t o = __shfl_xor(v, jj);
+            const bool keep_min = ((lane & jj) == 0) == ((lane & kk) == 0);
+            v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+        }
+    // position `lane` of the sorted order holds (key, original lane); equal
+    // keys are in lane order, flagged lanes first
+    const uint32_t sk = v >> 6;
+    const uint32_t prev = __shfl_up(v, 1);
+    const bool head = sk != kNoKey && (lane == 0 || (prev >> 6) != sk);
+    int hp = head ? lane : 0;  // the run's head: last head at or before this position
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(hp, o);
+        if (lane >= o) hp = t > hp ? t : hp;
+    }
+    int nx = head ? lane : 64;  // first head at or after this position
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_down(nx, o);
+        if (lane + o < 64) nx = t < nx ? t : nx;
+    }
+    int after = __shfl_down(nx, 1);
+    if (lane == 63) after = 64;
+    const int nflag = __popcll(bal);
+    const int end = after < nflag ? after : nflag;
+    const uint32_t orig = v & 63u;
+    const uint32_t head_orig = (uint32_t)__shfl((int)orig, hp);
+    const uint32_t pack = (uint32_t)(lane - hp) | (head_orig << 8) | ((uint32_t)(head ? end - lane : 0) << 16);
+    // the sorted order is a permutation of the lanes: every lane receives one value
+    const uint32_t got = (uint32_t)__builtin_amdgcn_ds_permute((int)(orig << 2), (int)pack);
+    if (flag) {
+        g.rank = got & 0xffu;
+        g.head = (int)((got >> 8) & 0xffu);
+        g.n = got >> 16;
+    }
+    return g;
+}
+
+// bucket number of a passing key within its trial
+__device__ __forceinline__ uint32_t local_bucket(const uint64_t *bm, const uint32_t *wcnt, uint32_t key)
+{
+    const uint32_t wd = key >> 6;
+    return wcnt[wd] + (uint32_t)__popcll(bm[wd] & ((1ull << (key & 63u)) - 1ull));
+}
+
+// Bucket records and member lists of trial j, which has ne > 0 passing keys,
+// by one workgroup of four waves.  Member cursors: rows[q][bucket] in LDS
+// when ne <= cb, else ws.rows[bucket][q] in device memory.
+__device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, uint32_t *tmp)
+{
     uint32_t *wcnt = reinterpret_cast<uint32_t *>(bm + a.nwb);  // [nwb] -> buckets before the word
     uint32_t *wsz = wcnt + a.nwb;                               // [nwb] -> members before the word
-    __shared__ uint32_t tmp[256];
-    const int j = blockIdx.x;
+    uint32_t *rows = wsz + a.nwb;                               // [4][cb]
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
+    const int cb = a.cb;
+    const bool in_lds = ne <= cb;
     const uint32_t *cnt = a.counts + (int64_t)j * a.nb;
+    const uint64_t *bits = a.ws.bits + (int64_t)j * a.nwb;
     const int64_t bbase = a.ws.bb[j], mbase = a.ws.mb[j];
     const pm_inst I = a.inst ? a.inst[a.item_inst[j]] : a.one;
 
-    // ---- bitmap of passing keys, one ballot per word of 64 keys; eight loads
-    // in flight per wave
-    constexpr int U = 8;
-    for (int w0 = wv; w0 < a.nwb; w0 += 4 * U) {
-        uint32_t c[U];
+    // ---- the bitmap, and per word the total size of its passing buckets: a
+    // wave takes 64 words and gathers the counts of eight non-empty ones at a time
+    for (int w0 = wv * 64; w0 < a.nwb; w0 += 256) {
+        const int wi = w0 + lane;
+        const uint64_t b = wi < a.nwb ? bits[wi] : 0ull;
+        uint32_t sz = 0;
+        uint64_t nz = __ballot(b != 0ull);
+        while (nz) {
+            constexpr int G = 8;
+            int idx[G];
+            uint32_t c[G];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t key = (int64_t)(w0 + 4 * u) * 64 + lane;
-            c[u] = (w0 + 4 * u < a.nwb && key < a.nb) ? cnt[key] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int wi = w0 + 4 * u;
-            const bool flag = passes(c[u], a.s);
-            const uint64_t bal = __ballot(flag);
-            uint32_t sz = 0;
-            if (bal) sz = wave_sum(flag ? c[u] : 0u);
-            if (lane == 0 && wi < a.nwb) {
-                bm[wi] = bal;
-                wcnt[wi] = __popcll(bal);
-                wsz[wi] = sz;
+            for (int u = 0; u < G; ++u) {
+                idx[u] = nz ? __ffsll((unsigned long long)nz) - 1 : -1;
+                nz &= nz - 1ull;
             }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                c[u] = 0u;
+                if (idx[u] >= 0) {
+                    const uint32_t lo = __shfl((uint32_t)b, idx[u]), hi = __shfl((uint32_t)(b >> 32), idx[u]);
+                    if (((((uint64_t)hi << 32) | lo) >> lane) & 1ull) c[u] = cnt[(int64_t)(w0 + idx[u]) * 64 + lane];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+                if (idx[u] >= 0) {
+                    const uint32_t t = wave_sum(c[u]);
+                    if (lane == idx[u]) sz = t;
+                }
+        }
+        if (wi < a.nwb) {
+            bm[wi] = b;
+            wcnt[wi] = (uint32_t)__popcll(b);
+            wsz[wi] = sz;
         }
     }
     __syncthreads();
     block_excl_scan(wcnt, a.nwb, tmp);
     block_excl_scan(wsz, a.nwb, tmp);
 
-    // ---- bucket records, in key order
-    for (int wi = tid; wi < a.nwb; wi += 256) {
-        uint64_t bits = bm[wi];
-        int64_t b = bbase + wcnt[wi];
-        int64_t first = mbase + wsz[wi];
-        while (bits) {
-            const int bit = __ffsll((unsigned long long)bits) - 1;
-            bits &= bits - 1;
-            const int64_t key = (int64_t)wi * 64 + bit;
-            const uint32_t c = cnt[key];
-            if (b < a.cap_b) {
-                pm_bucket *B = a.buckets + b;
-                st_agent(&B->trial, (uint32_t)j);
-                st_agent(&B->key, (uint32_t)key);
-                st_agent(&B->size, c);
-                st_agent(&B->first, (uint32_t)first);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    st_agent(a.ws.qcnt + 4 * b + q, 0u);
-                    st_agent(a.ws.placed + 4 * b + q, 0u);
+    // ---- bucket records in key order (a word's buckets are its set lanes),
+    // and every bucket's cursor row: its first slot, then zeros
+    for (int w0 = wv * 64; w0 < a.nwb; w0 += 256) {
+        const int wi = w0 + lane;
+        uint64_t nz = __ballot(wi < a.nwb && bm[wi] != 0ull);
+        while (nz) {
+            const int w = w0 + __ffsll((unsigned long long)nz) - 1;
+            nz &= nz - 1ull;
+            const uint64_t wb = bm[w];
+            const bool set = (wb >> lane) & 1ull;
+            const uint32_t key = (uint32_t)w * 64u + (uint32_t)lane;
+            const uint32_t c = set ? cnt[key] : 0u;
+            const uint32_t frel = wsz[w] + wave_incl_scan(c) - c;  // first slot within the trial
+            const uint32_t bi = wcnt[w] + (uint32_t)__popcll(wb & lanemask_lt());
+            const int64_t b = bbase + bi;
+            if (set) {
+                if (b < a.cap_b) a.buckets[b] = pm_bucket{(uint32_t)j, key, c, (uint32_t)(mbase + frel)};
+                if (in_lds) {
+                    rows[bi] = frel;
+                    rows[cb + bi] = rows[2 * cb + bi] = rows[3 * cb + bi] = 0u;
+                } else if (b < a.cap_b) {
+                    uint32_t *r = a.ws.rows + 4 * b;
+                    st_agent(r, frel);
+                    st_agent(r + 1, 0u);
+                    st_agent(r + 2, 0u);
+                    st_agent(r + 3, 0u);
                 }
             }
-            ++b;
-            first += c;
         }
     }
-    // the records, counters and first slots above are agent-scope atomics read
-    // back only by this workgroup: a workgroup barrier orders them (an
-    // agent-scope fence would write back and invalidate the whole L2)
+    // device-memory cursors: the stores above are done before any wave's atomics
+    if (!in_lds) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    // ---- members: wave wv owns windows [lo, hi); pass 0 counts per bucket,
-    // pass 1 places them after the members of earlier quarters
     const uint32_t *kj = a.keys + I.key_base + (int64_t)(j - I.first_item) * I.x;
-    const int64_t lo = I.x * wv / 4, hi = I.x * (wv + 1) / 4;
+    const int64_t x = I.x;
+    const int64_t nb = a.nb;
+    auto passing = [&](uint32_t key) { return key < nb && ((bm[key >> 6] >> (key & 63u)) & 1ull); };
+
+    if (in_lds) {
+        // chunks of 2048 windows, wave q owning the q-th quarter of each: rows
+        // 1-3 count the members of waves 0-2 per bucket, a sweep turns rows
+        // 0-3 into each wave's first slot, the waves place their members, and
+        // wave 3's row, now the first free slot, becomes row 0 again
+        for (int64_t c0 = 0; c0 < x; c0 += kSelChunk) {
+            const int64_t wb = c0 + (int64_t)wv * 64 * kSelU;
+            uint32_t kk[kSelU];
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u) {
+                const int64_t w = wb + 64 * u + lane;
+                kk[u] = w < x ? kj[w] : 0u;
+            }
+            uint32_t fl = 0;  // bit u: this lane's window of step u passes
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u)
+                if (wb + 64 * u + lane < x && passing(kk[u])) fl |= 1u << u;
+            if (!__syncthreads_or(fl != 0u)) continue;
+            if (wv < 3) {
+#pragma unroll
+                for (int u = 0; u < kSelU; ++u) {
+                    const bool f = (fl >> u) & 1u;
+                    if (__ballot(f) == 0ull) continue;
+                    const Group g = group_by_key(f, kk[u]);
+                    if (f && g.head == lane) rows[(wv + 1) * cb + local_bucket(bm, wcnt, kk[u])] += g.n;
+                }
+            }
+            __syncthreads();
+            for (int64_t bi = tid; bi < ne; bi += 256) {
+                const uint32_t r1 = rows[bi] + rows[cb + bi];
+                const uint32_t r2 = r1 + rows[2 * cb + bi];
+                rows[cb + bi] = r1;
+                rows[2 * cb + bi] = r2;
+                rows[3 * cb + bi] += r2;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u) {
+                const bool f = (fl >> u) & 1u;
+                if (__ballot(f) == 0ull) continue;
+                const Group g = group_by_key(f, kk[u]);
+                uint32_t old = kNoSlot;
+                if (f && g.head == lane) {
+                    const uint32_t bi = local_bucket(bm, wcnt, kk[u]);
+                    if (bbase + bi < a.cap_b) {
+                        uint32_t *r = rows + wv * cb + bi;
+                        old = *r;
+                        *r = old + g.n;
+                    }
+                }
+                old = __shfl(old, g.head);
+                if (f && old != kNoSlot) {
+                    const int64_t slot = mbase + old + g.rank;
+                    if (slot < a.cap_m) a.members[slot] = (uint32_t)(wb + 64 * u + lane);
+                }
+            }
+            __syncthreads();
+            for (int64_t bi = tid; bi < ne; bi += 256) {
+                rows[bi] = rows[3 * cb + bi];
+                rows[cb + bi] = rows[2 * cb + bi] = rows[3 * cb + bi] = 0u;
+            }
+            __syncthreads();
+        }
+        return;
+    }
+
+    // device-memory cursors (more buckets than the LDS rows hold): wave q owns
+    // the q-th quarter of the windows; pass 0 counts, a sweep forms the first
+    // slots, pass 1 places with one returning atomic per key group
+    const int64_t lo = x * wv / 4, hi = x * (wv + 1) / 4;
     for (int pass = 0; pass < 2; ++pass) {
-        for (int64_t wb = lo; wb < hi; wb += 64 * U) {
-          uint32_t kk[U];
+        if (pass == 1 || wv < 3) {
+            for (int64_t wb = lo; wb < hi; wb += 64 * kSelU) {
+                uint32_t kk[kSelU];
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-              const int64_t w = wb + 64 * u + lane;
-              kk[u] = w < hi ? kj[w] : 0u;
-          }
+                for (int u = 0; u < kSelU; ++u) {
+                    const int64_t w = wb + 64 * u + lane;
+                    kk[u] = w < hi ? kj[w] : 0u;
+                }
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int64_t w = wb + 64 * u + lane;
-            const bool valid = w < hi;
-            const uint32_t key = kk[u];
-            const bool flag = valid && key < a.nb && ((bm[key >> 6] >> (key & 63)) & 1ull);
-            uint64_t bal = __ballot(flag);
-            while (bal) {
-                const int leader = __ffsll((unsigned long long)bal) - 1;
-                const uint32_t lk = __shfl(key, leader);
-                const bool peer = flag && key == lk;
-                const uint64_t peers = __ballot(peer);
-                int64_t slot0 = -1;
-                if (lane == leader) {
-                    const uint64_t word = bm[lk >> 6];
-                    const int64_t b = bbase + wcnt[lk >> 6] + __popcll(word & ((1ull << (lk & 63)) - 1ull));
-                    if (b < a.cap_b) {
-                        if (pass == 0) {
-                            atomicAdd(a.ws.qcnt + 4 * b + wv, (uint32_t)__popcll(peers));
-                        } else {
-                            int64_t base = ld_agent(&a.buckets[b].first);
-                            for (int q = 0; q < wv; ++q) base += ld_agent(a.ws.qcnt + 4 * b + q);
-                            slot0 = base + atomicAdd(a.ws.placed + 4 * b + wv, (uint32_t)__popcll(peers));
+                for (int u = 0; u < kSelU; ++u) {
+                    const int64_t w = wb + 64 * u + lane;
+                    const bool f = w < hi && passing(kk[u]);
+                    if (__ballot(f) == 0ull) continue;
+                    const Group g = group_by_key(f, kk[u]);
+                    uint32_t old = kNoSlot;
+                    if (f && g.head == lane) {
+                        const int64_t b = bbase + local_bucket(bm, wcnt, kk[u]);
+                        if (b < a.cap_b) {
+                            if (pass == 0) atomicAdd(a.ws.rows + 4 * b + wv + 1, g.n);
+                            else old = atomicAdd(a.ws.rows + 4 * b + wv, g.n);
+                        }
+                    }
+                    if (pass == 1) {
+                        old = __shfl(old, g.head);
+                        if (f && old != kNoSlot) {
+                            const int64_t slot = mbase + old + g.rank;
+                            if (slot < a.cap_m) a.members[slot] = (uint32_t)w;
                         }
                     }
                 }
-                if (pass == 1) {
-                    slot0 = __shfl(slot0, leader);
-                    if (peer && slot0 >= 0) {
-                        const int64_t slot = slot0 + __popcll(peers & lanemask_lt());
-                        if (slot < a.cap_m) a.members[slot] = (uint32_t)w;
-                    }
-                }
-                bal &= ~peers;
             }
-          }
         }
+        if (pass == 0) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            for (int64_t bi = tid; bi < ne && bbase + bi < a.cap_b; bi += 256) {
+                uint32_t *r = a.ws.rows + 4 * (bbase + bi);
+                const uint32_t r1 = ld_agent(r) + ld_agent(r + 1);
+                const uint32_t r2 = r1 + ld_agent(r + 2);
+                const uint32_t r3 = r2 + ld_agent(r + 3);
+                st_agent(r + 1, r1);
+                st_agent(r + 2, r2);
+                st_agent(r + 3, r3);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+    }
+}
+
+// one workgroup per trial whose buckets fit the LDS rows
+__global__ void __launch_bounds__(256) k_sel_emit(const SelArgs a)
+{
+    extern __shared__ __align__(16) uint64_t bm[];
+    __shared__ uint32_t tmp[256];
+    const int j = blockIdx.x;
+    const int64_t ne = a.ws.ne[j];
+    if (ne == 0 || ne > a.take_hi) return;
+    emit_trial(a, j, ne, bm, tmp);
+}
+
+// the trials with more buckets than that, listed by the scan; a fixed grid
+// of workgroups takes them in turn
+__global__ void __launch_bounds__(256) k_sel_emit_heavy(const SelArgs a)
+{
+    extern __shared__ __align__(16) uint64_t bm[];
+    __shared__ uint32_t tmp[256];
+    const int64_t nh = *a.ws.n_heavy;
+    for (int64_t i = blockIdx.x; i < nh; i += gridDim.x) {
+        const int j = a.ws.heavy[i];
+        emit_trial(a, j, a.ws.ne[j], bm, tmp);
         __syncthreads();
     }
 }
@@ -361,46 +633,82 @@ __global__ void k_theta_init(const uint32_t *__restrict__ prof, const int64_t *n
 
 using namespace pm;
 
-extern "C" size_t pm_select_workspace(int32_t m, int64_t cap_buckets)
+// |Sigma|^k for the count-table selection, or -1 above 2^19 bins
+static int64_t sel_bins(int A, int k)
 {
-    if (m < 0 || cap_buckets < 0) return 0;
-    return (size_t)m * 4 * sizeof(int64_t) + (size_t)cap_buckets * 8 * sizeof(uint32_t) + 256;
+    if ((A != 4 && A != 20) || k < 1) return -1;
+    int64_t nb = 1;
+    for (int i = 0; i < k; ++i) {
+        nb *= A;
+        if (nb > (1ll << 19)) return -1;
+    }
+    return nb;
 }
 
-static int select_launch(SelArgs &a, int A, int k, hipStream_t st)
+extern "C" size_t pm_select_workspace(int32_t alphabet, int32_t k, int32_t m, int64_t cap_buckets)
 {
-    if (ipow(A, k) > (1ll << 19)) return fail(PM_ERANGE, "|Sigma|^k above 2^19");
-    a.nb = ipow(A, k);
+    const int64_t nb = sel_bins(alphabet, k);
+    if (nb < 0 || m < 0 || cap_buckets < 0) return 0;
+    return sel_ws_bytes(m, (nb + 63) / 64, cap_buckets);
+}
+
+static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st)
+{
+    const int64_t nwb = (a.nb + 63) / 64;
+    a.nwb = (int)nwb;
     hipLaunchKernelGGL(k_sel_count, dim3(a.m), dim3(256), 0, st, a);
     PM_LAUNCHED();
-    const TotScan ts{a.ws.ne, a.ws.ms, a.ws.bb, a.ws.mb, a.m, a.cap_b, a.cap_m, a.n_out, a.status};
+    // a trial has at most min(|Sigma|^k, x / s) passing bins; the first emit
+    // launch keeps its LDS near 20 KB (eight workgroups per CU) and takes the
+    // trials whose buckets fit there, a second one with all the LDS the device
+    // gives takes the rest from a list the scan writes
+    const int64_t ne_bound = std::min<int64_t>(a.nb, x_max / std::max<uint32_t>(a.s, 1u));
+    const int64_t lds_max = device_lds_bytes() - 2048;  // the emit kernels hold 1 KB of static LDS
+    const int64_t fit = (lds_max - 16 * nwb) / 16;
+    const int64_t cb_a = std::max<int64_t>(1, std::min<int64_t>(ne_bound, std::max<int64_t>(256, (20480 - 16 * nwb) / 16)));
+    const bool heavy = a.nb > cb_a;  // counts not written by projection_hash may pass anywhere
+    TotScan ts{a.ws.ne, a.ws.ms, a.ws.bb, a.ws.mb, a.m, a.cap_b, a.cap_m, a.n_out, a.status};
+    if (heavy) {
+        ts.heavy = a.ws.heavy;
+        ts.n_heavy = a.ws.n_heavy;
+        ts.heavy_above = cb_a;
+    }
     if (int rc = launch_tot_scan(ts, st)) return rc;
-    a.nwb = (int)((a.nb + 63) / 64);
-    const size_t lds = (size_t)a.nwb * 16;
     static bool attr = false;
     if (!attr) {
-        // the kernel also holds 1 KB of static LDS
-        (void)hipFuncSetAttribute((const void *)k_sel_emit, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  device_lds_bytes() - 2048);
+        (void)hipFuncSetAttribute((const void *)k_sel_emit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+        (void)hipFuncSetAttribute((const void *)k_sel_emit_heavy, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds_max);
         (void)hipGetLastError();  // an unsupported attribute must not poison the launch check
         attr = true;
     }
-    hipLaunchKernelGGL(k_sel_emit, dim3(a.m), dim3(256), lds, st, a);
+    a.take_hi = cb_a;
+    a.cb = (int)cb_a;
+    hipLaunchKernelGGL(k_sel_emit, dim3(a.m), dim3(256), (size_t)(16 * nwb + 16 * cb_a), st, a);
     PM_LAUNCHED();
+    if (heavy) {
+        const int64_t cb_b = std::max<int64_t>(cb_a, std::min<int64_t>(ne_bound, fit));
+        a.cb = (int)cb_b;
+        const int grid = std::min<int32_t>(a.m, 1024);
+        hipLaunchKernelGGL(k_sel_emit_heavy, dim3(grid), dim3(256), (size_t)(16 * nwb + 16 * cb_b), st, a);
+        PM_LAUNCHED();
+    }
     return PM_OK;
 }
 
-static int check_select_args(int32_t items, const uint32_t *keys, const uint32_t *counts, const int64_t *n_out,
-                             void *ws, size_t ws_bytes, pm_bucket *buckets, int64_t cap_buckets,
-                             uint32_t *members, int64_t cap_members)
+static int check_select_args(int A, int k, int32_t items, const uint32_t *keys, const uint32_t *counts,
+                             const int64_t *n_out, void *ws, size_t ws_bytes, pm_bucket *buckets,
+                             int64_t cap_buckets, uint32_t *members, int64_t cap_members)
 {
     if (items < 1) return fail(PM_EINVAL, "m must be >= 1");
+    if (sel_bins(A, k) < 0) return fail(PM_ERANGE, "|Sigma|^k above 2^19");
     if (!keys || !counts || !n_out || !ws) return fail(PM_EINVAL, "keys, counts, n_out and ws are required");
     if (cap_buckets < 0 || cap_members < 0) return fail(PM_EINVAL, "negative capacity");
     if ((cap_buckets > 0 && !buckets) || (cap_members > 0 && !members))
         return fail(PM_EINVAL, "NULL output with a non-zero capacity");
     if (cap_members > 0xffffffffll) return fail(PM_ERANGE, "cap_members must be below 2^32");
-    if (ws_bytes < pm_select_workspace(items, cap_buckets)) return fail(PM_EINVAL, "workspace too small");
+    if (ws_bytes < pm_select_workspace(A, k, items, cap_buckets)) return fail(PM_EINVAL, "workspace too small");
+    if (reinterpret_cast<uintptr_t>(ws) & 7) return fail(PM_EINVAL, "workspace must be 8-byte aligned");
     return PM_OK;
 }
 
@@ -413,7 +721,8 @@ extern "C" int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint3
     int rc = check_seqs(S, l);
     if (rc) return rc;
     if (k < 1 || k > l) return fail(PM_EINVAL, "need 1 <= k <= l");
-    if ((rc = check_select_args(m, keys, counts, n_out, ws, ws_bytes, buckets, cap_buckets, members, cap_members)))
+    if ((rc = check_select_args(S->alphabet, k, m, keys, counts, n_out, ws, ws_bytes, buckets, cap_buckets, members,
+                                cap_members)))
         return rc;
     SelArgs a{};
     a.one = inst_of(S, l);
@@ -423,12 +732,13 @@ extern "C" int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint3
     a.members = members;
     a.n_out = n_out;
     a.status = status;
-    a.ws = carve(ws, m, cap_buckets);
+    a.nb = sel_bins(S->alphabet, k);
+    a.ws = carve(ws, m, (a.nb + 63) / 64);
     a.cap_b = cap_buckets;
     a.cap_m = cap_members;
     a.m = m;
     a.s = s;
-    return select_launch(a, S->alphabet, k, as_stream(stream));
+    return select_launch(a, a.one.x, as_stream(stream));
 }
 
 extern "C" int bucket_select_batch(const pm_batch *B, const uint32_t *keys, const uint32_t *counts, uint32_t s,
@@ -437,10 +747,11 @@ extern "C" int bucket_select_batch(const pm_batch *B, const uint32_t *keys, cons
                                    uint32_t *status, void *stream)
 {
     clear_error();
-    int rc = check_batch(B, nullptr);
+    BatchInfo info;
+    int rc = check_batch(B, &info);
     if (rc) return rc;
-    if ((rc = check_select_args(B->items, keys, counts, n_out, ws, ws_bytes, buckets, cap_buckets, members,
-                                cap_members)))
+    if ((rc = check_select_args(B->alphabet, B->k, B->items, keys, counts, n_out, ws, ws_bytes, buckets, cap_buckets,
+                                members, cap_members)))
         return rc;
     SelArgs a{};
     a.inst = B->inst;
@@ -451,12 +762,13 @@ extern "C" int bucket_select_batch(const pm_batch *B, const uint32_t *keys, cons
     a.members = members;
     a.n_out = n_out;
     a.status = status;
-    a.ws = carve(ws, B->items, cap_buckets);
+    a.nb = sel_bins(B->alphabet, B->k);
+    a.ws = carve(ws, B->items, (a.nb + 63) / 64);
     a.cap_b = cap_buckets;
     a.cap_m = cap_members;
     a.m = B->items;
     a.s = s;
-    return select_launch(a, B->alphabet, B->k, as_stream(stream));
+    return select_launch(a, info.x_max, as_stream(stream));
 }
 
 static int profile_launch(const ProfArgs &a, hipStream_t st)

@@ -193,13 +193,13 @@ def _select_gpu(S, l, k, s, K, N, cap_b=None, cap_m=None):
     nout = torch.zeros(2, dtype=torch.int64, device="cuda")
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     if cap_b is None:
-        ws = torch.zeros(pm.pm_select_workspace(m, 0) // 4 + 1, dtype=torch.int32, device="cuda")
+        ws = torch.zeros(pm.pm_select_workspace(S.alphabet, k, m, 0) // 4 + 1, dtype=torch.int32, device="cuda")
         pm.bucket_select(S, l, k, dK, dN, m, s, None, 0, None, 0, nout, ws, ws.numel() * 4, st)
         torch.cuda.synchronize()
         cap_b, cap_m = [int(v) for v in nout.cpu()]
     bk = torch.full((max(cap_b, 1), 4), -1, dtype=torch.int32, device="cuda")
     mem = torch.full((max(cap_m, 1),), -1, dtype=torch.int32, device="cuda")
-    ws = torch.zeros(pm.pm_select_workspace(m, cap_b) // 4 + 1, dtype=torch.int32, device="cuda")
+    ws = torch.zeros(pm.pm_select_workspace(S.alphabet, k, m, cap_b) // 4 + 1, dtype=torch.int32, device="cuda")
     st.zero_()
     pm.bucket_select(S, l, k, dK, dN, m, s, bk, cap_b, mem, cap_m, nout, ws, ws.numel() * 4, st)
     torch.cuda.synchronize()

@@ -1,0 +1,149 @@
+"""bucket_select on trials large enough to use every form of its member
+placement, against the CPU oracle (Alg. 2 step 3; Sec. 6's threshold s).
+
+The selection keeps each trial's member cursors in LDS when its buckets fit
+there (a first launch with a small LDS footprint), in a second launch with
+all the LDS the device gives for trials with more buckets, and in device
+memory beyond that; windows go by in chunks of 2048, and a wave groups its
+passing windows by key with ballots when few pass and with a sort across
+the wave when many do.  Bucket lists and members must match the oracle bit
+for bit in every form, also truncated to a capacity and in a batch whose
+instances take different forms.
+"""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1605_06904_amd as pm
+from synth import random_sequences, projection_masks
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    yield
+    torch.cuda.synchronize()
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _case(name, A, t, n, l, k, m):
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    lens = [int(v) for v in rng.integers(n - n // 5, n + n // 5, size=t)]
+    seqs = random_sequences(rng, t, lens, "dna" if A == 4 else "protein")
+    return seqs, projection_masks(rng, l, k, m)
+
+
+def _select(S, A, l, k, s, K, N, cap_b=None, cap_m=None):
+    m = K.shape[0]
+    dK = torch.from_numpy(K.view(np.int32)).cuda()
+    dN = torch.from_numpy(N.view(np.int32)).cuda()
+    nout = torch.zeros(2, dtype=torch.int64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    if cap_b is None:
+        ws = torch.zeros(pm.pm_select_workspace(A, k, m, 0) // 4 + 1, dtype=torch.int32, device="cuda")
+        pm.bucket_select(S, l, k, dK, dN, m, s, None, 0, None, 0, nout, ws, ws.numel() * 4, st)
+        torch.cuda.synchronize()
+        cap_b, cap_m = [int(v) for v in nout.cpu()]
+        st.zero_()
+    bk = torch.full((max(cap_b, 1), 4), -1, dtype=torch.int32, device="cuda")
+    mem = torch.full((max(cap_m, 1),), -1, dtype=torch.int32, device="cuda")
+    ws = torch.zeros(pm.pm_select_workspace(A, k, m, cap_b) // 4 + 1, dtype=torch.int32, device="cuda")
+    pm.bucket_select(S, l, k, dK, dN, m, s, bk, cap_b, mem, cap_m, nout, ws, ws.numel() * 4, st)
+    torch.cuda.synchronize()
+    return u32(bk), u32(mem), [int(v) for v in nout.cpu()], int(st.item())
+
+
+CASES = [
+    # name, alphabet, t, n, l, k, s, m; the form each trial takes on a device
+    # with 160 KB of LDS per workgroup is in the name
+    ("chunks, few passing, LDS rows", 4, 10, 1300, 15, 7, 3, 3),
+    ("many passing, second launch, LDS rows", 4, 10, 2000, 12, 6, 1, 2),
+    ("many passing, device-memory rows", 4, 10, 3500, 12, 7, 1, 2),
+    ("protein, second launch, LDS rows", 20, 10, 2000, 8, 3, 1, 2),
+    ("protein k=4, few passing", 20, 12, 1500, 10, 4, 3, 3),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_select_large_trials_match_oracle(case):
+    name, A, t, n, l, k, s, m = case
+    seqs, masks = _case(name, A, t, n, l, k, m)
+    ref = oracle.Seqs(A, seqs)
+    RK, RN = oracle.hash_trials(ref, l, k, masks)
+    rbk, rmem, (rnb, rnm), _ = oracle.select(ref, l, k, RK, RN, s)
+    per_trial = np.bincount(rbk[:, 0], minlength=m)
+    say("select forms", name, "x", RK.shape[1], "buckets per trial", per_trial.tolist())
+    S = pm.Seqs(A, seqs)
+    bk, mem, (nb_, nm_), st = _select(S, A, l, k, s, RK, RN)
+    assert st == 0 and (nb_, nm_) == (rnb, rnm)
+    assert np.array_equal(bk[:nb_], rbk)
+    assert np.array_equal(mem[:nm_], rmem)
+
+
+def test_select_device_rows_truncated_to_capacity():
+    name, A, t, n, l, k, s, m = CASES[2]
+    seqs, masks = _case(name, A, t, n, l, k, m)
+    ref = oracle.Seqs(A, seqs)
+    RK, RN = oracle.hash_trials(ref, l, k, masks)
+    rbk, rmem, (rnb, rnm), _ = oracle.select(ref, l, k, RK, RN, s)
+    cap_b, cap_m = rnb // 2 + 3, rnm // 3
+    say("select forms truncated", cap_b, cap_m)
+    S = pm.Seqs(A, seqs)
+    bk, mem, (nb_, nm_), st = _select(S, A, l, k, s, RK, RN, cap_b=cap_b, cap_m=cap_m)
+    assert st & pm.PM_STATUS_CAPACITY and (nb_, nm_) == (rnb, rnm)
+    assert np.array_equal(bk[:cap_b], rbk[:cap_b])
+    # every member slot below the capacity that belongs to a kept bucket
+    slots = np.zeros(cap_m, dtype=bool)
+    for b in rbk[:cap_b]:
+        slots[b[3]:min(b[3] + b[2], cap_m)] = True
+    assert slots.any()
+    assert np.array_equal(mem[:cap_m][slots], rmem[:cap_m][slots])
+
+
+def test_select_batch_mixes_light_and_heavy_trials():
+    """One batch, s = 1, k = 6: a small instance whose trials fit the first
+    launch and a large one whose trials go to the second."""
+    A, l, k, s = 4, 12, 6, 1
+    insts = [_case("light", A, 3, 200, l, k, 3), _case("heavy", A, 10, 2000, l, k, 2),
+             _case("light 2", A, 4, 150, l, k, 2)]
+    say("select forms batch")
+    B = pm.Batch(A, l, k, [sq for sq, _ in insts], [mk for _, mk in insts])
+    nb_, nm_ = pm.size_batch(B, s)
+    P = pm.BatchPipeline(B, s, 0, 1.0, pm.PM_FP64, np.full(A, 0.25), cap_b=nb_, cap_m=nm_)
+    P.hash()
+    P.select()
+    torch.cuda.synchronize()
+    b = P.b
+    assert int(b.status.item()) == 0
+    bk, mem = u32(b.buckets)[:nb_], u32(b.members)[:nm_]
+    tot = 0
+    for p, (seqs, masks) in enumerate(insts):
+        ref = oracle.Seqs(A, seqs)
+        RK, RN = oracle.hash_trials(ref, l, k, masks)
+        rbk, rmem, (rnb, rnm), _ = oracle.select(ref, l, k, RK, RN, s)
+        f, mp = B.first_item[p], B.m[p]
+        sel = (bk[:, 0] >= f) & (bk[:, 0] < f + mp)
+        gb = bk[sel]
+        assert len(gb) == rnb, p
+        assert np.array_equal(gb[:, 0] - f, rbk[:, 0]) and np.array_equal(gb[:, 1:3], rbk[:, 1:3]), p
+        for g, r in zip(gb, rbk):
+            assert np.array_equal(mem[g[3]:g[3] + g[2]], rmem[r[3]:r[3] + r[2]]), p
+        tot += rnb
+    assert tot == nb_
