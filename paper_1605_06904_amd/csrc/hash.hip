@@ -80,16 +80,18 @@ constexpr int kHist16 = 0;       // u16 pairs: instances below 65 536 windows
 constexpr int kHist16Check = 1;  // u16 pairs, slices of 65 536 windows or more counted again in u32
 constexpr int kHist32 = 2;       // u32
 constexpr int kHist8 = 3;        // u8 quads, a slice where a count wrapped counted again in u32
-constexpr int kHistModes = 4;
+constexpr int kHist4 = 4;        // u4 octets, the same
+constexpr int kHistModes = 5;
 
 // Narrow counts hold more bins per slice, so fewer slices (each of which
 // recomputes every key of its trial).  A u16 count can pass 65 535 only when
 // at least 65 536 windows fall in its slice, so with kHist16Check every thread
 // counts the windows of its slice (one add per window, the atomics stay
 // non-returning) and a slice that received 65 536 or more is counted again in
-// u32, hist_words bins per pass.  u8 counts wrap at 256: kHist8 increments
-// with returning atomics and a slice where a count wrapped is counted again
-// in u32 the same way (only a key with 256 windows or more in one trial can).
+// u32, hist_words bins per pass.  u8 counts wrap at 256 and u4 counts at 16:
+// kHist8 and kHist4 increment with returning atomics and a slice where a count
+// wrapped is counted again in u32 the same way (only a key with 256, or 16,
+// windows or more in one trial can).
 template <int A, int K, int HIST>
 __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
 {
@@ -136,6 +138,10 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
                     const uint32_t sh = (bin & 3) << 3;
                     const uint32_t old = atomicAdd(hist + (bin >> 2), 1u << sh);
                     mine |= ((old >> sh) & 0xffu) == 0xffu;
+                } else if (HIST == kHist4) {
+                    const uint32_t sh = (bin & 7) << 2;
+                    const uint32_t old = atomicAdd(hist + (bin >> 3), 1u << sh);
+                    mine |= ((old >> sh) & 0xfu) == 0xfu;
                 } else {
                     atomicAdd(hist + (bin >> 1), 1u << ((bin & 1) << 4));
                     if (HIST == kHist16Check) ++mine;
@@ -147,7 +153,7 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
     if (HIST == kHist16Check) {
         mine = wave_sum(mine);
         if (lane_id() == 0) atomicAdd(&in_slice, mine);
-    } else if (HIST == kHist8) {
+    } else if (HIST == kHist8 || HIST == kHist4) {
         if (mine) in_slice = 1u << 16;  // a count wrapped: recount below
     }
     __syncthreads();
@@ -166,6 +172,14 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
         for (uint32_t b4 = tid * 4; b4 < nvalid; b4 += kHashThreads * 4) {
             const uint32_t w = hist[b4 >> 2];
             __builtin_nontemporal_store(u32x4{w & 0xffu, (w >> 8) & 0xffu, (w >> 16) & 0xffu, w >> 24},
+                                        reinterpret_cast<u32x4 *>(out + b4));
+        }
+        return;
+    }
+    if (HIST == kHist4 && in_slice < 65536u) {
+        for (uint32_t b4 = tid * 4; b4 < nvalid; b4 += kHashThreads * 4) {
+            const uint32_t w = hist[b4 >> 3] >> ((b4 & 4u) << 2);
+            __builtin_nontemporal_store(u32x4{w & 0xfu, (w >> 4) & 0xfu, (w >> 8) & 0xfu, (w >> 12) & 0xfu},
                                         reinterpret_cast<u32x4 *>(out + b4));
         }
         return;
@@ -483,7 +497,8 @@ static size_t hash_layout(HashArgs &a, bool hist, int per_word, int64_t nw_max, 
         // (each slice recomputes the trial's keys; measured 11% faster on the
         // (18,6) workload's 128 KB histograms)
         const int64_t half = ((int64_t)lds_max / 2 - fixed) / 4;
-        if (balance && need_words <= budget && need_words > half && half >= 1024) hw = (need_words + 1) / 2;
+        if (balance && need_words <= budget && need_words > half && (need_words + 1) / 2 <= half && half >= 1024)
+            hw = (need_words + 1) / 2;
         hw = (hw + 3) & ~int64_t(3);
         if (hw > budget) hw = budget;
         a.hist_words = (int)hw;
@@ -503,20 +518,28 @@ static int hash_launch(HashArgs &a, int A, int32_t items, int64_t x_max, int64_t
                        hipStream_t st)
 {
     // the count width giving the fewest slices (each slice recomputes its
-    // trial's keys), the widest among equals: no check for u32, nor for u16
-    // below 65 536 windows
+    // trial's keys), then the most workgroups per CU (one's key pass overlaps
+    // another's count write-out), then the widest: no check for u32, nor for
+    // u16 below 65 536 windows
     int hist = kHist16, per_word = 2;
     if (a.counts) {
-        int best_slices = 0x7fffffff;
-        for (const int pw : {1, 2, 4}) {
+        int best_slices = 0x7fffffff, best_wgs = 0;
+        for (const int pw : {1, 2, 4, 8}) {
             HashArgs probe = a;
-            if (!hash_layout(probe, true, pw, nw_max, t_max, kHashFlagWords, true)) continue;
-            if (probe.nslices < best_slices) {
+            const size_t bytes = hash_layout(probe, true, pw, nw_max, t_max, kHashFlagWords, true);
+            if (!bytes) continue;
+            const int wgs = std::min((int)(device_lds_bytes() / bytes), 2048 / kHashThreads);
+            if (probe.nslices < best_slices || (probe.nslices == best_slices && wgs > best_wgs)) {
                 best_slices = probe.nslices;
+                best_wgs = wgs;
                 per_word = pw;
             }
         }
-        hist = per_word == 1 ? kHist32 : per_word == 4 ? kHist8 : x_max < 65536 ? kHist16 : kHist16Check;
+        hist = per_word == 1   ? kHist32
+               : per_word == 8 ? kHist4
+               : per_word == 4 ? kHist8
+               : x_max < 65536 ? kHist16
+                               : kHist16Check;
     }
     const size_t lds = hash_layout(a, a.counts != nullptr, per_word, nw_max, t_max, kHashFlagWords, true);
     if (!lds) return PM_ERANGE;

@@ -185,6 +185,38 @@ def test_hash_count_past_u16_is_recounted(k, l, extra):
     assert N[:, 0].min() > 65535
 
 
+NARROW_CASES = [
+    # name, alphabet, l, k, runs: (letter, windows) of one-letter sequences
+    ("u4 highest count 15", 4, 12, 9, [("C", 15), ("T", 7)]),
+    ("u4 count 16 wraps", 4, 12, 9, [("C", 15), ("T", 16), ("G", 40)]),
+    ("u4 protein count 17 wraps", 20, 10, 4, [("A", 17), ("W", 15)]),
+    ("u8 counts 255 and 256", 4, 11, 8, [("C", 255), ("A", 256)]),
+]
+
+
+@pytest.mark.parametrize("case", NARROW_CASES, ids=[c[0] for c in NARROW_CASES])
+def test_hash_narrow_counters_wrap_and_recount(case):
+    """Count tables of 4- and 8-bit counters (chosen for |Sigma|^k too large
+    for wider ones: DNA k = 9 and protein k = 4 take 4 bits, DNA k = 8 takes 8
+    on a device with 160 KB of LDS per workgroup).  A one-letter sequence of
+    c windows puts c windows on one key under every mask, so counts sit just
+    below and at the counter's limit; a slice where one wrapped is counted
+    again in u32.  Every count bit-exact against the oracle, beside random
+    sequences that fill the other bins."""
+    name, A, l, k, runs = case
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    alpha = "dna" if A == 4 else "protein"
+    seqs = random_sequences(rng, 8, [2500] * 8, alpha) + [ch * (l + c - 1) for ch, c in runs]
+    masks = projection_masks(rng, l, k, 3)
+    say("hash narrow counters", name)
+    S = pm.Seqs(A, seqs)
+    K, N, st = _hash_gpu(S, l, k, masks)
+    assert st == 0
+    RK, RN = oracle.hash_trials(oracle.Seqs(A, seqs), l, k, masks)
+    assert np.array_equal(K, RK) and np.array_equal(N, RN)
+    assert RN.max() >= max(c for _, c in runs)
+
+
 # ------------------------------------------------------------------ a5, a6
 def _select_gpu(S, l, k, s, K, N, cap_b=None, cap_m=None):
     m = K.shape[0]
