@@ -58,7 +58,9 @@ int check_batch(const pm_batch *B, BatchInfo *info);
 // exclusive scan of n per-entry (bucket, member) totals into bases; writes the
 // grand totals to n_out and PM_STATUS_CAPACITY when they exceed the capacities.
 // With `heavy` set, also lists in order the entries with more than heavy_above
-// buckets, and their number in n_heavy.
+// buckets, and their number in n_heavy.  With parts > 1 the totals of entry j
+// are the sums of ne/ms[j * parts .. j * parts + parts - 1], also written to
+// ne_sum/ms_sum.
 struct TotScan {
     const int64_t *ne, *ms;
     int64_t *bb, *mb;
@@ -68,6 +70,8 @@ struct TotScan {
     int32_t *heavy;
     int64_t *n_heavy;
     int64_t heavy_above;
+    int parts;
+    int64_t *ne_sum, *ms_sum;
 };
 int launch_tot_scan(const TotScan &a, hipStream_t st);
 

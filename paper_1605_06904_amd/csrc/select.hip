@@ -24,14 +24,31 @@ struct SelWs {
     int64_t *mb;      // [m] first member slot of the trial
     int64_t *n_heavy; // [1] trials with more buckets than the first emit launch takes
     int32_t *heavy;   // [m] those trials, in order
+    int64_t *nep;     // [m][parts] buckets of each part of a trial's bins (parts > 1)
+    int64_t *msp;     // [m][parts] their members
     uint64_t *bits;   // [m][nwb] passing keys: bit key % 64 of word key / 64
     uint32_t *rows;   // [cap_b][4] member cursors of trials with more buckets than the LDS holds
 };
 
+// parts of a trial's bins counted by separate workgroups: enough workgroups
+// (about 16 384) that the launch does not end on a partly filled wave of
+// them, each part at least 32 bitmap words
+static int sel_parts(int32_t m, int64_t nwb)
+{
+    int64_t p = (16384 + (int64_t)m - 1) / std::max<int64_t>(m, 1);
+    p = std::min<int64_t>(p, std::max<int64_t>(1, nwb / 32));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(p, 64));
+}
+
+static size_t sel_head_bytes(int32_t m, int64_t nwb)
+{
+    return (size_t)m * 4 * sizeof(int64_t) + sizeof(int64_t) + (((size_t)m * 4 + 7) & ~(size_t)7) +
+           (size_t)m * sel_parts(m, nwb) * 2 * sizeof(int64_t);
+}
+
 static size_t sel_ws_bytes(int32_t m, int64_t nwb, int64_t cap_b)
 {
-    const size_t head = (size_t)m * 4 * sizeof(int64_t) + sizeof(int64_t) + (((size_t)m * 4 + 7) & ~(size_t)7);
-    return head + (size_t)m * nwb * 8 + (size_t)cap_b * 4 * sizeof(uint32_t) + 256;
+    return sel_head_bytes(m, nwb) + (size_t)m * nwb * 8 + (size_t)cap_b * 4 * sizeof(uint32_t) + 256;
 }
 
 static SelWs carve(void *ws, int32_t m, int64_t nwb)
@@ -44,8 +61,10 @@ static SelWs carve(void *ws, int32_t m, int64_t nwb)
     w.mb = w.bb + m;
     w.n_heavy = w.mb + m;
     w.heavy = reinterpret_cast<int32_t *>(w.n_heavy + 1);
-    w.bits = reinterpret_cast<uint64_t *>(p + (size_t)m * 4 * sizeof(int64_t) + sizeof(int64_t) +
-                                          (((size_t)m * 4 + 7) & ~(size_t)7));
+    w.nep = reinterpret_cast<int64_t *>(p + (size_t)m * 4 * sizeof(int64_t) + sizeof(int64_t) +
+                                        (((size_t)m * 4 + 7) & ~(size_t)7));
+    w.msp = w.nep + (int64_t)m * sel_parts(m, nwb);
+    w.bits = reinterpret_cast<uint64_t *>(p + sel_head_bytes(m, nwb));
     w.rows = reinterpret_cast<uint32_t *>(w.bits + (int64_t)m * nwb);
     return w;
 }
@@ -65,75 +84,61 @@ struct SelArgs {
     int64_t take_hi;  // k_sel_emit: trials with 0 < buckets <= take_hi
     int32_t m;                 // trials (items)
     uint32_t s;
-    int nwb;  // bitmap words, ceil(nb / 64)
-    int cb;   // buckets whose cursors the LDS holds
+    int nwb;    // bitmap words, ceil(nb / 64)
+    int cb;     // buckets whose cursors the LDS holds
+    int parts;  // k_sel_count: workgroups per trial
 };
 
-__device__ __forceinline__ bool passes(uint32_t c, uint32_t s) { return c >= s && c > 0; }
-
-// bit i of a 16-bit value moved to bit 4i
-__device__ __forceinline__ uint64_t spread4(uint32_t x)
-{
-    uint64_t v = x & 0xffffu;
-    v = (v | (v << 24)) & 0x000000ff000000ffull;
-    v = (v | (v << 12)) & 0x000f000f000f000full;
-    v = (v | (v << 6)) & 0x0303030303030303ull;
-    v = (v | (v << 3)) & 0x1111111111111111ull;
-    return v;
-}
-
-// per trial: number of passing bins, their total size and the bitmap of the
-// passing keys; a wave reads 4 x 256 bins at a time as uint4 per lane
+// per (trial, part of its bins): number of passing bins, their total size
+// and the bitmap words of the passing keys.  Lane i of a wave reads bin 64 w +
+// i, so the ballot of word w is word w of the bitmap; a wave takes eight
+// consecutive words at a time.
 __global__ void __launch_bounds__(256) k_sel_count(const SelArgs a)
 {
-    const int j = blockIdx.x;
+    const int j = blockIdx.x / a.parts, part = blockIdx.x % a.parts;
     const int wv = threadIdx.x >> 6, lane = lane_id();
-    const uint4 *cnt = reinterpret_cast<const uint4 *>(a.counts + (int64_t)j * a.nb);  // nb % 4 == 0
+    const uint32_t *cnt = a.counts + (int64_t)j * a.nb;
     uint64_t *bits = a.ws.bits + (int64_t)j * a.nwb;
-    const int64_t n4 = a.nb / 4;
-    uint64_t ne = 0, ms = 0;
-    constexpr int U = 4;
-    for (int64_t c0 = (int64_t)wv * 64 * U; c0 < n4; c0 += 256 * U) {
-        uint4 v[U];
+    const uint32_t smin = a.s > 1u ? a.s : 1u;  // a bin passes with at least max(s, 1) l-mers
+    constexpr int U = 8;
+    const int64_t per = ((a.nwb + a.parts - 1) / a.parts + U - 1) / U * U;
+    const int64_t w_lo = part * per, w_hi = std::min<int64_t>(a.nwb, w_lo + per);
+    uint32_t ne = 0, ms = 0;  // ne counts whole ballots (the same in every lane); a trial has fewer than 2^32 windows
+    for (int64_t wb = w_lo + (int64_t)wv * U; wb < w_hi; wb += 4 * U) {
+        uint32_t c[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t i = c0 + 64 * u + lane;
-            v[u] = i < n4 ? cnt[i] : make_uint4(0u, 0u, 0u, 0u);
+            const int64_t key = (wb + u) * 64 + lane;
+            c[u] = wb + u < w_hi && key < a.nb ? cnt[key] : 0u;
         }
+        uint64_t mine = 0;  // lane u < U: word wb + u
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t c[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-            uint64_t bal[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const bool p = passes(c[q], a.s);
-                ne += p ? 1u : 0u;
-                ms += p ? c[q] : 0u;
-                bal[q] = __ballot(p);
-            }
-            // lanes 16g .. 16g+15 hold bins 64g .. 64g+63 of these 256:
-            // bit 4i+q of word g is bin q of lane 16g+i
-            if (lane < 4) {
-                const int64_t wi = (c0 + 64 * u) / 16 + lane;
-                const int sh = 16 * lane;
-                uint64_t w = 0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) w |= spread4((uint32_t)(bal[q] >> sh)) << q;
-                if (wi < a.nwb) bits[wi] = w;
-            }
+            const bool p = c[u] >= smin;
+            const uint64_t bal = __ballot(p);
+            ne += (uint32_t)__popcll(bal);
+            ms += p ? c[u] : 0u;
+            if (lane == u) mine = bal;
         }
+        if (lane < U && wb + lane < w_hi) bits[wb + lane] = mine;
     }
-    ne = wave_sum(ne);
-    ms = wave_sum(ms);
+    const uint32_t mst = wave_sum(ms);
     __shared__ uint64_t red[2][4];
     if (lane == 0) {
         red[0][wv] = ne;
-        red[1][wv] = ms;
+        red[1][wv] = mst;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        a.ws.ne[j] = (int64_t)(red[0][0] + red[0][1] + red[0][2] + red[0][3]);
-        a.ws.ms[j] = (int64_t)(red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+        const int64_t tb = (int64_t)(red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+        const int64_t tm = (int64_t)(red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+        if (a.parts > 1) {
+            a.ws.nep[(int64_t)j * a.parts + part] = tb;
+            a.ws.msp[(int64_t)j * a.parts + part] = tm;
+        } else {
+            a.ws.ne[j] = tb;
+            a.ws.ms[j] = tm;
+        }
     }
 }
 
@@ -150,7 +155,20 @@ __global__ void __launch_bounds__(1024) k_tot_scan(const TotScan a)
     __syncthreads();
     for (int64_t base = 0; base < a.n; base += 1024) {
         const int64_t j = base + threadIdx.x;
-        const int64_t ve = j < a.n ? a.ne[j] : 0, vm = j < a.n ? a.ms[j] : 0;
+        int64_t ve = 0, vm = 0;
+        if (j < a.n) {
+            if (a.parts > 1) {
+                for (int q = 0; q < a.parts; ++q) {
+                    ve += a.ne[j * a.parts + q];
+                    vm += a.ms[j * a.parts + q];
+                }
+                a.ne_sum[j] = ve;
+                a.ms_sum[j] = vm;
+            } else {
+                ve = a.ne[j];
+                vm = a.ms[j];
+            }
+        }
         sa[threadIdx.x] = ve;
         sb[threadIdx.x] = vm;
         const bool h = a.heavy && j < a.n && ve > a.heavy_above;
@@ -330,40 +348,51 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
     const pm_inst I = a.inst ? a.inst[a.item_inst[j]] : a.one;
 
     // ---- the bitmap, and per word the total size of its passing buckets: a
-    // wave takes 64 words and gathers the counts of eight non-empty ones at a time
-    for (int w0 = wv * 64; w0 < a.nwb; w0 += 256) {
-        const int wi = w0 + lane;
-        const uint64_t b = wi < a.nwb ? bits[wi] : 0ull;
-        uint32_t sz = 0;
-        uint64_t nz = __ballot(b != 0ull);
-        while (nz) {
-            constexpr int G = 8;
-            int idx[G];
-            uint32_t c[G];
+    // wave takes four groups of 64 words at once (one load each) and gathers
+    // the counts of eight non-empty words at a time
+    for (int base = wv * 64; base < a.nwb; base += 4 * 256) {
+        uint64_t b[4];
 #pragma unroll
-            for (int u = 0; u < G; ++u) {
-                idx[u] = nz ? __ffsll((unsigned long long)nz) - 1 : -1;
-                nz &= nz - 1ull;
-            }
-#pragma unroll
-            for (int u = 0; u < G; ++u) {
-                c[u] = 0u;
-                if (idx[u] >= 0) {
-                    const uint32_t lo = __shfl((uint32_t)b, idx[u]), hi = __shfl((uint32_t)(b >> 32), idx[u]);
-                    if (((((uint64_t)hi << 32) | lo) >> lane) & 1ull) c[u] = cnt[(int64_t)(w0 + idx[u]) * 64 + lane];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < G; ++u)
-                if (idx[u] >= 0) {
-                    const uint32_t t = wave_sum(c[u]);
-                    if (lane == idx[u]) sz = t;
-                }
+        for (int it = 0; it < 4; ++it) {
+            const int wi = base + 256 * it + lane;
+            b[it] = wi < a.nwb ? bits[wi] : 0ull;
         }
-        if (wi < a.nwb) {
-            bm[wi] = b;
-            wcnt[wi] = (uint32_t)__popcll(b);
-            wsz[wi] = sz;
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int w0 = base + 256 * it, wi = w0 + lane;
+            uint32_t sz = 0;
+            uint64_t nz = __ballot(b[it] != 0ull);
+            while (nz) {
+                constexpr int G = 8;
+                int idx[G];
+                uint32_t c[G];
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    idx[u] = nz ? __ffsll((unsigned long long)nz) - 1 : -1;
+                    nz &= nz - 1ull;
+                }
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    c[u] = 0u;
+                    if (idx[u] >= 0) {
+                        const uint32_t lo = __shfl((uint32_t)b[it], idx[u]);
+                        const uint32_t hi = __shfl((uint32_t)(b[it] >> 32), idx[u]);
+                        if (((((uint64_t)hi << 32) | lo) >> lane) & 1ull)
+                            c[u] = cnt[(int64_t)(w0 + idx[u]) * 64 + lane];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < G; ++u)
+                    if (idx[u] >= 0) {
+                        const uint32_t t = wave_sum(c[u]);
+                        if (lane == idx[u]) sz = t;
+                    }
+            }
+            if (wi < a.nwb) {
+                bm[wi] = b[it];
+                wcnt[wi] = (uint32_t)__popcll(b[it]);
+                wsz[wi] = sz;
+            }
         }
     }
     __syncthreads();
@@ -371,31 +400,47 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
     block_excl_scan(wsz, a.nwb, tmp);
 
     // ---- bucket records in key order (a word's buckets are its set lanes),
-    // and every bucket's cursor row: its first slot, then zeros
+    // and every bucket's cursor row: its first slot, then zeros; the counts of
+    // eight non-empty words are read at a time
     for (int w0 = wv * 64; w0 < a.nwb; w0 += 256) {
         const int wi = w0 + lane;
         uint64_t nz = __ballot(wi < a.nwb && bm[wi] != 0ull);
         while (nz) {
-            const int w = w0 + __ffsll((unsigned long long)nz) - 1;
-            nz &= nz - 1ull;
-            const uint64_t wb = bm[w];
-            const bool set = (wb >> lane) & 1ull;
-            const uint32_t key = (uint32_t)w * 64u + (uint32_t)lane;
-            const uint32_t c = set ? cnt[key] : 0u;
-            const uint32_t frel = wsz[w] + wave_incl_scan(c) - c;  // first slot within the trial
-            const uint32_t bi = wcnt[w] + (uint32_t)__popcll(wb & lanemask_lt());
-            const int64_t b = bbase + bi;
-            if (set) {
-                if (b < a.cap_b) a.buckets[b] = pm_bucket{(uint32_t)j, key, c, (uint32_t)(mbase + frel)};
-                if (in_lds) {
-                    rows[bi] = frel;
-                    rows[cb + bi] = rows[2 * cb + bi] = rows[3 * cb + bi] = 0u;
-                } else if (b < a.cap_b) {
-                    uint32_t *r = a.ws.rows + 4 * b;
-                    st_agent(r, frel);
-                    st_agent(r + 1, 0u);
-                    st_agent(r + 2, 0u);
-                    st_agent(r + 3, 0u);
+            constexpr int G = 8;
+            int wd[G];
+            uint32_t c[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                wd[u] = nz ? w0 + __ffsll((unsigned long long)nz) - 1 : -1;
+                nz &= nz - 1ull;
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                c[u] = 0u;
+                if (wd[u] >= 0 && ((bm[wd[u]] >> lane) & 1ull)) c[u] = cnt[(uint32_t)wd[u] * 64u + (uint32_t)lane];
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                if (wd[u] < 0) continue;
+                const int w = wd[u];
+                const uint64_t wb = bm[w];
+                const bool set = (wb >> lane) & 1ull;
+                const uint32_t key = (uint32_t)w * 64u + (uint32_t)lane;
+                const uint32_t frel = wsz[w] + wave_incl_scan(c[u]) - c[u];  // first slot within the trial
+                const uint32_t bi = wcnt[w] + (uint32_t)__popcll(wb & lanemask_lt());
+                const int64_t b = bbase + bi;
+                if (set) {
+                    if (b < a.cap_b) a.buckets[b] = pm_bucket{(uint32_t)j, key, c[u], (uint32_t)(mbase + frel)};
+                    if (in_lds) {
+                        rows[bi] = frel;
+                        rows[cb + bi] = rows[2 * cb + bi] = rows[3 * cb + bi] = 0u;
+                    } else if (b < a.cap_b) {
+                        uint32_t *r = a.ws.rows + 4 * b;
+                        st_agent(r, frel);
+                        st_agent(r + 1, 0u);
+                        st_agent(r + 2, 0u);
+                        st_agent(r + 3, 0u);
+                    }
                 }
             }
         }
@@ -407,25 +452,44 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
     const uint32_t *kj = a.keys + I.key_base + (int64_t)(j - I.first_item) * I.x;
     const int64_t x = I.x;
     const int64_t nb = a.nb;
-    auto passing = [&](uint32_t key) { return key < nb && ((bm[key >> 6] >> (key & 63u)) & 1ull); };
+    // the bitmap as 32-bit words (little-endian halves of the 64-bit ones)
+    const uint32_t *bm32 = reinterpret_cast<const uint32_t *>(bm);
+    const uint32_t nb32 = (uint32_t)nb;
+    auto passing = [&](uint32_t key) { return key < nb32 && ((bm32[key >> 5] >> (key & 31u)) & 1u); };
 
     if (in_lds) {
         // chunks of 2048 windows, wave q owning the q-th quarter of each: rows
         // 1-3 count the members of waves 0-2 per bucket, a sweep turns rows
         // 0-3 into each wave's first slot, the waves place their members, and
         // wave 3's row, now the first free slot, becomes row 0 again
+        // the next chunk's keys are loaded while this one is placed
+        uint32_t nk[kSelU];
+#pragma unroll
+        for (int u = 0; u < kSelU; ++u) {
+            const int64_t w = (int64_t)wv * 64 * kSelU + 64 * u + lane;
+            nk[u] = w < x ? kj[w] : 0u;
+        }
         for (int64_t c0 = 0; c0 < x; c0 += kSelChunk) {
             const int64_t wb = c0 + (int64_t)wv * 64 * kSelU;
             uint32_t kk[kSelU];
 #pragma unroll
-            for (int u = 0; u < kSelU; ++u) {
-                const int64_t w = wb + 64 * u + lane;
-                kk[u] = w < x ? kj[w] : 0u;
+            for (int u = 0; u < kSelU; ++u) kk[u] = nk[u];
+            if (c0 + kSelChunk < x) {
+#pragma unroll
+                for (int u = 0; u < kSelU; ++u) {
+                    const int64_t w = wb + kSelChunk + 64 * u + lane;
+                    nk[u] = w < x ? kj[w] : 0u;
+                }
             }
             uint32_t fl = 0;  // bit u: this lane's window of step u passes
+            if (c0 + kSelChunk <= x) {
 #pragma unroll
-            for (int u = 0; u < kSelU; ++u)
-                if (wb + 64 * u + lane < x && passing(kk[u])) fl |= 1u << u;
+                for (int u = 0; u < kSelU; ++u) fl |= passing(kk[u]) ? 1u << u : 0u;
+            } else {
+                const int left = (int)(x - wb);  // windows of this wave in the last chunk
+#pragma unroll
+                for (int u = 0; u < kSelU; ++u) fl |= 64 * u + lane < left && passing(kk[u]) ? 1u << u : 0u;
+            }
             if (!__syncthreads_or(fl != 0u)) continue;
             if (wv < 3) {
 #pragma unroll
@@ -656,7 +720,8 @@ static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st)
 {
     const int64_t nwb = (a.nb + 63) / 64;
     a.nwb = (int)nwb;
-    hipLaunchKernelGGL(k_sel_count, dim3(a.m), dim3(256), 0, st, a);
+    a.parts = sel_parts(a.m, nwb);
+    hipLaunchKernelGGL(k_sel_count, dim3((unsigned)((int64_t)a.m * a.parts)), dim3(256), 0, st, a);
     PM_LAUNCHED();
     // a trial has at most min(|Sigma|^k, x / s) passing bins; the first emit
     // launch keeps its LDS near 20 KB (eight workgroups per CU) and takes the
@@ -668,6 +733,13 @@ static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st)
     const int64_t cb_a = std::max<int64_t>(1, std::min<int64_t>(ne_bound, std::max<int64_t>(256, (20480 - 16 * nwb) / 16)));
     const bool heavy = a.nb > cb_a;  // counts not written by projection_hash may pass anywhere
     TotScan ts{a.ws.ne, a.ws.ms, a.ws.bb, a.ws.mb, a.m, a.cap_b, a.cap_m, a.n_out, a.status};
+    if (a.parts > 1) {
+        ts.ne = a.ws.nep;
+        ts.ms = a.ws.msp;
+        ts.parts = a.parts;
+        ts.ne_sum = a.ws.ne;
+        ts.ms_sum = a.ws.ms;
+    }
     if (heavy) {
         ts.heavy = a.ws.heavy;
         ts.n_heavy = a.ws.n_heavy;
