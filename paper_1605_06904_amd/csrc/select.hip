@@ -8,9 +8,11 @@
 // After a scan of the per-trial totals, one workgroup per trial loads its
 // bitmap into LDS, gathers the counts of the passing keys only, scans them
 // into bucket numbers and first member slots, and places the member windows
-// with a stable counting sort: the windows go by in order in chunks, each wave
-// groups its passing windows by key (by a sort across the wave when many
-// pass), and every bucket keeps its next free slot per wave in LDS.
+// in window order.  A trial of few members lists its passing windows per wave
+// quarter in LDS and places them from the lists; otherwise a stable counting
+// sort goes over the windows in chunks, each wave grouping its passing
+// windows by key (by a sort across the wave when many pass), every bucket
+// keeping its next free slot per wave in LDS.
 #include <algorithm>
 
 #include "pm_common.h"
@@ -90,37 +92,47 @@ struct SelArgs {
 };
 
 // per (trial, part of its bins): number of passing bins, their total size
-// and the bitmap words of the passing keys.  Lane i of a wave reads bin 64 w +
-// i, so the ballot of word w is word w of the bitmap; a wave takes eight
-// consecutive words at a time.
+// and the bitmap words of the passing keys.  Lane i of a wave reads bins 4i ..
+// 4i+3 of 256 as one 16-byte load, and the four ballots (one per bin of the
+// load) become four words in lane-major order: bit 16q + i of word g is bin
+// 64g + 4i + q.  The emit pass puts the words in key order.
 __global__ void __launch_bounds__(256) k_sel_count(const SelArgs a)
 {
     const int j = blockIdx.x / a.parts, part = blockIdx.x % a.parts;
     const int wv = threadIdx.x >> 6, lane = lane_id();
-    const uint32_t *cnt = a.counts + (int64_t)j * a.nb;
+    const uint4 *cnt = reinterpret_cast<const uint4 *>(a.counts + (int64_t)j * a.nb);  // nb % 4 == 0
     uint64_t *bits = a.ws.bits + (int64_t)j * a.nwb;
     const uint32_t smin = a.s > 1u ? a.s : 1u;  // a bin passes with at least max(s, 1) l-mers
-    constexpr int U = 8;
-    const int64_t per = ((a.nwb + a.parts - 1) / a.parts + U - 1) / U * U;
+    constexpr int U = 4;                        // 256-bin groups per wave at a time
+    const int64_t n4 = a.nb / 4;
+    const int64_t per = ((a.nwb + a.parts - 1) / a.parts + 4 * U - 1) / (4 * U) * (4 * U);  // words per part
     const int64_t w_lo = part * per, w_hi = std::min<int64_t>(a.nwb, w_lo + per);
     uint32_t ne = 0, ms = 0;  // ne counts whole ballots (the same in every lane); a trial has fewer than 2^32 windows
-    for (int64_t wb = w_lo + (int64_t)wv * U; wb < w_hi; wb += 4 * U) {
-        uint32_t c[U];
+    for (int64_t g0 = w_lo / 4 + (int64_t)wv * U; 4 * g0 < w_hi; g0 += 4 * U) {
+        uint4 v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t key = (wb + u) * 64 + lane;
-            c[u] = wb + u < w_hi && key < a.nb ? cnt[key] : 0u;
+            const int64_t i = (g0 + u) * 64 + lane;  // 16-byte load index
+            v[u] = 4 * (g0 + u) < w_hi && i < n4 ? cnt[i] : make_uint4(0u, 0u, 0u, 0u);
         }
-        uint64_t mine = 0;  // lane u < U: word wb + u
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool p = c[u] >= smin;
-            const uint64_t bal = __ballot(p);
-            ne += (uint32_t)__popcll(bal);
-            ms += p ? c[u] : 0u;
-            if (lane == u) mine = bal;
+            const uint32_t c[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+            uint64_t bal[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool p = c[q] >= smin;
+                bal[q] = __ballot(p);
+                ne += (uint32_t)__popcll(bal[q]);
+                ms += p ? c[q] : 0u;
+            }
+            const int64_t wi = 4 * (g0 + u) + lane;
+            if (lane < 4 && wi < w_hi) {
+                const int sh = 16 * lane;
+                bits[wi] = ((bal[0] >> sh) & 0xffffull) | (((bal[1] >> sh) & 0xffffull) << 16) |
+                           (((bal[2] >> sh) & 0xffffull) << 32) | (((bal[3] >> sh) & 0xffffull) << 48);
+            }
         }
-        if (lane < U && wb + lane < w_hi) bits[wb + lane] = mine;
     }
     const uint32_t mst = wave_sum(ms);
     __shared__ uint64_t red[2][4];
@@ -140,6 +152,23 @@ __global__ void __launch_bounds__(256) k_sel_count(const SelArgs a)
             a.ws.ms[j] = tm;
         }
     }
+}
+
+// bit i of a 16-bit value moved to bit 4i
+__device__ __forceinline__ uint64_t spread4(uint64_t x)
+{
+    uint64_t v = x & 0xffffull;
+    v = (v | (v << 24)) & 0x000000ff000000ffull;
+    v = (v | (v << 12)) & 0x000f000f000f000full;
+    v = (v | (v << 6)) & 0x0303030303030303ull;
+    v = (v | (v << 3)) & 0x1111111111111111ull;
+    return v;
+}
+
+// a bitmap word from lane-major order (bit 16q + i: key 4i + q) to key order
+__device__ __forceinline__ uint64_t word_in_key_order(uint64_t b)
+{
+    return spread4(b) | (spread4(b >> 16) << 1) | (spread4(b >> 32) << 2) | (spread4(b >> 48) << 3);
 }
 
 // exclusive scan of per-trial (or per trial-slice) totals, one workgroup:
@@ -249,6 +278,7 @@ constexpr int kSelU = 8;                   // window loads in flight per lane
 constexpr int kSelChunk = 4 * 64 * kSelU;  // windows per workgroup step
 constexpr int kSelSortMin = 6;             // flagged lanes from which a wave groups by sorting
 constexpr uint32_t kNoSlot = 0xffffffffu;
+constexpr int kSelListCap = 256;           // passing windows each wave may list in a trial of few members
 
 struct Group {
     int head;       // lowest lane holding the same key
@@ -358,6 +388,9 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
             b[it] = wi < a.nwb ? bits[wi] : 0ull;
         }
 #pragma unroll
+        for (int it = 0; it < 4; ++it)
+            if (__ballot(b[it] != 0ull)) b[it] = word_in_key_order(b[it]);
+#pragma unroll
         for (int it = 0; it < 4; ++it) {
             const int w0 = base + 256 * it, wi = w0 + lane;
             uint32_t sz = 0;
@@ -457,6 +490,81 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
     const uint32_t nb32 = (uint32_t)nb;
     auto passing = [&](uint32_t key) { return key < nb32 && ((bm32[key >> 5] >> (key & 31u)) & 1u); };
 
+    if (in_lds && a.ws.ms[j] <= 4 * kSelListCap) {
+        // few members: each wave lists the passing windows of its quarter of
+        // the trial in order (no barrier), then one wave places the four lists,
+        // which together are in window order, with the buckets' cursors (row 0)
+        uint32_t *lw = rows + cb;                // [4][cap] windows
+        uint32_t *lk = lw + 4 * kSelListCap;     // [4][cap] their keys
+        const int64_t lo = x * wv / 4, hi = x * (wv + 1) / 4;
+        uint32_t n = 0;
+        uint32_t nk[kSelU];
+#pragma unroll
+        for (int u = 0; u < kSelU; ++u) {
+            const int64_t w = lo + 64 * u + lane;
+            nk[u] = w < hi ? kj[w] : 0u;
+        }
+        for (int64_t wb = lo; wb < hi; wb += 64 * kSelU) {
+            uint32_t kk[kSelU];
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u) kk[u] = nk[u];
+            if (wb + 64 * kSelU < hi) {
+#pragma unroll
+                for (int u = 0; u < kSelU; ++u) {
+                    const int64_t w = wb + 64 * kSelU + 64 * u + lane;
+                    nk[u] = w < hi ? kj[w] : 0u;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u) {
+                const int64_t w = wb + 64 * u + lane;
+                const bool f = w < hi && passing(kk[u]);
+                const uint64_t bal = __ballot(f);
+                if (bal == 0ull) continue;
+                const uint32_t pos = n + (uint32_t)__popcll(bal & lanemask_lt());
+                if (f && pos < (uint32_t)kSelListCap) {
+                    lw[wv * kSelListCap + pos] = (uint32_t)w;
+                    lk[wv * kSelListCap + pos] = kk[u];
+                }
+                n += (uint32_t)__popcll(bal);
+            }
+        }
+        if (lane == 0) tmp[wv] = n;
+        __syncthreads();
+        const uint32_t n0 = tmp[0], n1 = tmp[1], n2 = tmp[2], n3 = tmp[3];
+        const uint32_t cap = (uint32_t)kSelListCap;
+        if (n0 <= cap && n1 <= cap && n2 <= cap && n3 <= cap) {
+            if (wv == 0) {
+                const uint32_t e1 = n0, e2 = e1 + n1, e3 = e2 + n2, total = e3 + n3;
+                for (uint32_t e0 = 0; e0 < total; e0 += 64) {
+                    const uint32_t e = e0 + (uint32_t)lane;
+                    const bool valid = e < total;
+                    const uint32_t q = (e >= e1) + (e >= e2) + (e >= e3);
+                    const uint32_t at = q * cap + e - (q == 0 ? 0u : q == 1 ? e1 : q == 2 ? e2 : e3);
+                    const uint32_t w = valid ? lw[at] : 0u, key = valid ? lk[at] : 0u;
+                    const Group g = group_by_key(valid, key);
+                    uint32_t old = kNoSlot;
+                    if (valid && g.head == lane) {
+                        const uint32_t bi = local_bucket(bm, wcnt, key);
+                        if (bbase + bi < a.cap_b) {
+                            old = rows[bi];
+                            rows[bi] = old + g.n;
+                        }
+                    }
+                    old = __shfl(old, g.head);
+                    if (valid && old != kNoSlot) {
+                        const int64_t slot = mbase + old + g.rank;
+                        if (slot < a.cap_m) a.members[slot] = w;
+                    }
+                }
+            }
+            return;
+        }
+        // a quarter held more than its list: the chunked placement below, with
+        // rows 1-3 (which the lists overwrote) cleared again
+        for (int64_t bi = tid; bi < ne; bi += 256) rows[cb + bi] = rows[2 * cb + bi] = rows[3 * cb + bi] = 0u;
+        __syncthreads();
+    }
     if (in_lds) {
         // chunks of 2048 windows, wave q owning the q-th quarter of each: rows
         // 1-3 count the members of waves 0-2 per bucket, a sweep turns rows
@@ -716,6 +824,13 @@ extern "C" size_t pm_select_workspace(int32_t alphabet, int32_t k, int32_t m, in
     return sel_ws_bytes(m, (nb + 63) / 64, cap_buckets);
 }
 
+// dynamic LDS of the emit kernels: bitmap, word scans, cursor row 0, then
+// rows 1-3 or the member lists of a trial with few members
+static size_t sel_emit_lds(int64_t nwb, int64_t cb)
+{
+    return (size_t)(16 * nwb + 4 * cb + 4 * std::max<int64_t>(3 * cb, 8 * kSelListCap));
+}
+
 static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st)
 {
     const int64_t nwb = (a.nb + 63) / 64;
@@ -756,13 +871,13 @@ static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st)
     }
     a.take_hi = cb_a;
     a.cb = (int)cb_a;
-    hipLaunchKernelGGL(k_sel_emit, dim3(a.m), dim3(256), (size_t)(16 * nwb + 16 * cb_a), st, a);
+    hipLaunchKernelGGL(k_sel_emit, dim3(a.m), dim3(256), sel_emit_lds(nwb, cb_a), st, a);
     PM_LAUNCHED();
     if (heavy) {
         const int64_t cb_b = std::max<int64_t>(cb_a, std::min<int64_t>(ne_bound, fit));
         a.cb = (int)cb_b;
         const int grid = std::min<int32_t>(a.m, 1024);
-        hipLaunchKernelGGL(k_sel_emit_heavy, dim3(grid), dim3(256), (size_t)(16 * nwb + 16 * cb_b), st, a);
+        hipLaunchKernelGGL(k_sel_emit_heavy, dim3(grid), dim3(256), sel_emit_lds(nwb, cb_b), st, a);
         PM_LAUNCHED();
     }
     return PM_OK;

@@ -147,3 +147,25 @@ def test_select_batch_mixes_light_and_heavy_trials():
             assert np.array_equal(mem[g[3]:g[3] + g[2]], rmem[r[3]:r[3] + r[2]]), p
         tot += rnb
     assert tot == nb_
+
+
+def test_select_few_members_one_quarter_over_its_list():
+    """A trial of few members whose passing windows crowd into the first
+    quarter of its windows (a poly-A run of 400 windows first): that quarter
+    holds more than its wave may list, so the trial falls back to the chunked
+    placement; lists bit-exact against the oracle."""
+    A, l, k, s, m = 4, 12, 8, 3, 3
+    rng = np.random.default_rng(77)
+    seqs = ["A" * (l + 399)] + random_sequences(rng, 7, [500] * 7, "dna")
+    masks = projection_masks(rng, l, k, m)
+    ref = oracle.Seqs(A, seqs)
+    RK, RN = oracle.hash_trials(ref, l, k, masks)
+    rbk, rmem, (rnb, rnm), _ = oracle.select(ref, l, k, RK, RN, s)
+    per_trial = np.bincount(rbk[:, 0], minlength=m, weights=rbk[:, 2])
+    assert per_trial.max() <= 1024 and per_trial.min() >= 400
+    say("select few members, crowded quarter", per_trial.tolist())
+    S = pm.Seqs(A, seqs)
+    bk, mem, (nb_, nm_), st = _select(S, A, l, k, s, RK, RN)
+    assert st == 0 and (nb_, nm_) == (rnb, rnm)
+    assert np.array_equal(bk[:nb_], rbk)
+    assert np.array_equal(mem[:nm_], rmem)
