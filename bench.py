@@ -29,13 +29,13 @@ FP16_MFMA_PEAK = 2500.0      # TFLOP/s, MI355X dense FP16 matrix cores
 # the kernel source is the one they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
     "hash.hip": ("936ac3666631d158", {"k_hash<4,8,true>": 1.760e9}),
-    "em_mfma.hip": ("c9812ec47bed7d94", {
-        "k_em_mfma<5,2,true,1,1>": 0.758e9 + 0.705e9,
-        "k_em_mfma<5,2,true,2,1>": 0.721e9 + 0.719e9,
-        "k_em_mfma<5,2,true,4,1>": 0.753e9 + 0.716e9,
-        "k_em_mfma<5,2,true,1,2>": 0.789e9 + 0.737e9,
-        "k_em_mfma<5,2,true,2,2>": 0.788e9 + 0.750e9,
-        "k_em_mfma<5,2,true,4,2>": 0.786e9 + 0.734e9,
+    "em_mfma.hip": ("7b50002b89335e08", {
+        "k_em_mfma<5,2,true,1,1>": 0.726e9 + 0.695e9,
+        "k_em_mfma<5,2,true,2,1>": 0.695e9 + 0.715e9,
+        "k_em_mfma<5,2,true,4,1>": 0.762e9 + 0.725e9,
+        "k_em_mfma<5,2,true,1,2>": 0.780e9 + 0.750e9,
+        "k_em_mfma<5,2,true,2,2>": 0.772e9 + 0.724e9,
+        "k_em_mfma<5,2,true,4,2>": 0.785e9 + 0.754e9,
     }),
 }
 
