@@ -28,7 +28,7 @@ FP16_MFMA_PEAK = 2500.0      # TFLOP/s, MI355X dense FP16 matrix cores
 # profiles/hbm_traffic_dna_18-6_m5000.md (copy-calibrated), valid only while
 # the kernel source is the one they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "hash.hip": ("936ac3666631d158", {"k_hash<4,8,true>": 1.760e9}),
+    "hash.hip": ("f7095d0c251b8e84", {"k_hash<4,8>": 1.772e9, "k_hash<4,9>": 14.918e9, "k_hash<20,4>": 1.557e9}),
     "em_mfma.hip": ("7b50002b89335e08", {
         "k_em_mfma<5,2,true,1,1>": 0.726e9 + 0.695e9,
         "k_em_mfma<5,2,true,2,1>": 0.695e9 + 0.715e9,
@@ -81,6 +81,8 @@ def parse():
                     help="skip the hash rooflines of the (21,7) DNA and (20,6) protein workloads")
     ap.add_argument("--c3-chunk", type=int, default=250,
                     help="trials per instance per chunk of the 512-instance uneven workload at m=1000 (0: skip)")
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the timings of the sorted selection, ZOOPS/TCM, Gibbs and length-range rows")
     ap.add_argument("--uneven", type=int, default=0,
                     help="also run the 512-instance uneven batch with this many trials per instance")
     ap.add_argument("--c5", action="store_true",
@@ -200,8 +202,8 @@ def main():
     em_kernel = f"k_em_mfma<{(l + 3) // 4},2,true,{shape_ppb},{shape_g}>"
     dominant = max(stage, key=stage.get)
     if dominant == "hash":
-        roof = {"kernel": "k_hash<4,8,true>", "bound": "hbm", "achieved": round(hash_gbs, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4), "traffic": traffic("hash.hip", "k_hash<4,8,true>")}
+        roof = {"kernel": "k_hash<4,8>", "bound": "hbm", "achieved": round(hash_gbs, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4), "traffic": traffic("hash.hip", "k_hash<4,8>")}
     else:
         roof = {"kernel": em_kernel, "bound": "mfma", "achieved": round(em_alg_tfs, 3),
                 "peak": FP16_MFMA_PEAK, "unit": "TFLOP/s", "frac": round(em_alg_tfs / FP16_MFMA_PEAK, 5),
@@ -232,9 +234,9 @@ def main():
                    "parallelism": "single GPU"},
         "stage_ms": stage,
         "roofline": roof,
-        "roofline_hash": {"kernel": "k_hash<4,8,true>", "bound": "hbm", "achieved": round(hash_gbs, 2),
+        "roofline_hash": {"kernel": "k_hash<4,8>", "bound": "hbm", "achieved": round(hash_gbs, 2),
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hash_gbs / HBM_PEAK_GBS, 4),
-                          "traffic": traffic("hash.hip", "k_hash<4,8,true>"), "bytes_per_launch": hash_bytes},
+                          "traffic": traffic("hash.hip", "k_hash<4,8>"), "bytes_per_launch": hash_bytes},
         "hash_lmers_per_s": round(lmers / (stage["hash"] / 1e3), 1),
         "em_column_updates_per_s": round(em_updates / (stage["em"] / 1e3), 1),
         "consensus": res.get("consensus"),
@@ -242,6 +244,8 @@ def main():
     }
     progress(f"pass timed: {ms_step:.3f} ms/step")
     out["fused_selection"] = fused_select_leg(torch, pm, P, l, k, s, m, nbk, nmem)
+    if not args.no_next_rows:
+        out["next_rows"] = next_rows_leg(torch, pm, P, inst, l, cfg, iters, beta, nbk)
     out["precision"] = precision_leg(torch, pm, P, l, iters, beta, nbk, ms_em=stage["em"])
     if args.instances > 0:
         out["instances"] = instances_leg(torch, pm, args.instances)
@@ -299,6 +303,79 @@ def fused_select_leg(torch, pm, P, l, k, s, m, nbk, nmem, reps=5):
         same = bool(torch.equal(torch.sort(key).values, torch.sort(ref).values))
     return {"ms": round(e0.elapsed_time(e1) / reps, 4), "lists_equal_to_pass": same,
             "note": "bucket_hash_select over the pass's trials: keys and counts never leave LDS"}
+
+
+def next_rows_leg(torch, pm, P, inst, l, cfg, iters, beta, nbk, sample=4096, sort_m=1000, sort_k=14,
+                  range_m=500):
+    """The rows beyond the plain pass, on the (18,6) workload's sequences:
+    ZOOPS and TCM EM (FP32 vector kernel, 10 iterations) and Gibbs site
+    sampling (10 sweeps) of the first `sample` enriched buckets of the pass;
+    the sorted selection at k = 14 (|Sigma|^k = 2^28, no count table) over
+    `sort_m` trials; the motif-length range 16..20 (projection_run, host in
+    and host out, `range_m` trials per length)."""
+    S = P.S
+    nb = min(sample, nbk)
+    th0 = P.b.theta0[:nb].contiguous()
+    dbg = P.bg
+    out = {"buckets": nb}
+    progress(f"next rows: ZOOPS/TCM, Gibbs on {nb} buckets, sorted selection k={sort_k}, length range 16..20")
+
+    def timed(fn):
+        fn()  # warm
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    th = torch.empty_like(th0)
+    mix = torch.empty(nb, dtype=torch.float64, device="cuda")
+    J = torch.empty((nb, iters + 1), dtype=torch.float64, device="cuda")
+    for name, model in (("zoops", pm.PM_ZOOPS), ("tcm", pm.PM_TCM)):
+        ms = timed(lambda: pm.em_refine_model(S, l, model, 0.5, th0, dbg, nb, None, iters, beta, pm.PM_FP32, th,
+                                              mix, J))
+        out[name] = {"ms": round(ms, 3), "us_per_model": round(1e3 * ms / nb, 3), "precision": "fp32 vector"}
+    ms = timed(lambda: pm.em_refine(S, l, th0, dbg, nb, None, iters, beta, pm.PM_FP32, th, J))
+    out["oops_fp32_vector"] = {"ms": round(ms, 3), "us_per_model": round(1e3 * ms / nb, 3)}
+    F = torch.empty((nb, iters + 1), dtype=torch.float64, device="cuda")
+    sites = torch.empty((nb, S.t), dtype=torch.int32, device="cuda")
+    ms = timed(lambda: pm.gibbs_refine(S, l, th0, dbg, nb, None, iters, beta, 7, th, F, sites))
+    out["gibbs"] = {"ms": round(ms, 3), "us_per_chain": round(1e3 * ms / nb, 3), "sweeps": iters}
+    del th, mix, J, F, sites
+
+    # sorted selection (large key space)
+    rng = np.random.default_rng(5)
+    from synth import projection_masks
+    mk = projection_masks(rng, l, sort_k, sort_m)
+    dm = torch.from_numpy(np.ascontiguousarray(mk, dtype=np.uint32).view(np.int32)).cuda()
+    nbytes = pm.pm_sort_select_workspace(S, l, sort_k, sort_m)
+    ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device="cuda")
+    n_out = torch.zeros(2, dtype=torch.int64, device="cuda")
+    pm.bucket_sort_select(S, l, sort_k, dm, sort_m, 2, None, 0, None, 0, n_out, ws, nbytes)
+    torch.cuda.synchronize()
+    nb2, nm2 = [int(v) for v in n_out.cpu()]
+    bk = torch.empty((max(nb2, 1), 4), dtype=torch.int32, device="cuda")
+    mem = torch.empty(max(nm2, 1), dtype=torch.int32, device="cuda")
+    ms = timed(lambda: pm.bucket_sort_select(S, l, sort_k, dm, sort_m, 2, bk, nb2, mem, nm2, n_out, ws, nbytes))
+    x = S.nwin(l)
+    out["sorted_selection"] = {"k": sort_k, "s": 2, "trials": sort_m, "ms": round(ms, 3),
+                               "lmers_per_s": round(sort_m * x / (ms / 1e3), 1), "buckets": nb2, "members": nm2}
+    del ws, bk, mem
+    torch.cuda.empty_cache()
+
+    # motif-length range, host in and host out
+    prob = pm.Problem(seqs=inst.seqs, alphabet=4, l=cfg["l"], d=cfg["d"], k=0, s=0, m=range_m, seed=11)
+    pm.projection_run_range(prob, 16, 20, em_iters=iters, precision=pm.PM_F16X2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, chosen = pm.projection_run_range(prob, 16, 20, em_iters=iters, precision=pm.PM_F16X2)
+    sec = time.perf_counter() - t0
+    out["length_range"] = {"lengths": "16..20", "trials_per_length": range_m, "s": round(sec, 3),
+                           "chosen_l": chosen, "consensus": res[chosen - 16]["consensus"] if chosen >= 16 else "",
+                           "k_per_length": [r["k"] for r in res], "note": "projection_run_range, host in and out"}
+    return out
 
 
 def precision_leg(torch, pm, P, l, iters, beta, nbk, ms_em, sample=512):
@@ -520,10 +597,11 @@ def hash_roofline(torch, pm, name, seed=1, reps=3):
     gbs = nbytes / (ms / 1e3) / 1e9
     del keys, counts
     torch.cuda.empty_cache()
-    kern = f"k_hash<{A},{k},{'true' if x < 65536 else 'false'}>"
+    kern = f"k_hash<{A},{k}>"  # counter width chosen by the library per launch
     progress(f"{name} hash: {ms:.3f} ms, {gbs:.0f} GB/s")
     return {"kernel": kern, "bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": nbytes, "ms": round(ms, 4),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic("hash.hip", kern), "bytes_per_launch": nbytes,
+            "ms": round(ms, 4),
             "workload": f"{'protein' if A == 20 else 'DNA'} ({l},{cfg['d']}): t={len(inst.seqs)}, "
                         f"n={cfg['n']}, k={k}, m={m} trials, keys and counts of every trial",
             "lmers_per_s": round(m * x / (ms / 1e3), 1)}

@@ -243,6 +243,7 @@ SELECT_CASES = [
     ("toy", None, 8, 5, 4),
     ("dna ragged s=2", 4, 12, 6, 2),
     ("dna s=1 every key", 4, 9, 4, 1),
+    ("dna s=0 same as s=1", 4, 9, 4, 0),
     ("protein s=2", 20, 9, 2, 2),
     ("dna k=1 buckets of more than 128 members", 4, 8, 1, 3),
 ]
