@@ -740,28 +740,39 @@ struct ProfArgs {
     int l, A;
 };
 
-// one wave per bucket; lane p owns column p
+// SW lanes per bucket (16 for l <= 16, else 32; 64 / SW buckets per wave);
+// lane j of a bucket's group owns column j
+template <int SW>
 __global__ void __launch_bounds__(256) k_profile(const ProfArgs a)
 {
-    __shared__ uint32_t cnt[4][20 * 32];
-    const int wv = threadIdx.x >> 6, lane = lane_id();
-    const int64_t b = (int64_t)blockIdx.x * 4 + wv;
+    constexpr int NB = 64 / SW;  // buckets per wave
+    __shared__ uint32_t cnt[4][NB][20 * SW];
+    const int wv = threadIdx.x >> 6, lane = lane_id(), sub = lane / SW, j = lane % SW;
+    const int64_t b = ((int64_t)blockIdx.x * 4 + wv) * NB + sub;
     int64_t nvalid = a.n_dev ? *a.n_dev : a.B;
     if (nvalid > a.B) nvalid = a.B;
-    if (b >= nvalid) return;
-    uint32_t *C = cnt[wv];
-    for (int i = lane; i < a.A * 32; i += 64) C[i] = 0;
-    const pm_bucket bk = a.buckets[b];
-    const pm_inst I = a.inst ? a.inst[a.item_inst[bk.trial]] : a.one;
+    if (((int64_t)blockIdx.x * 4 + wv) * NB >= nvalid) return;  // the wave's first bucket (uniform)
+    const bool live = b < nvalid;
+    uint32_t *C = cnt[wv][sub];
+    for (int i = j; i < a.A * SW; i += SW) C[i] = 0;
+    pm_bucket bk{0u, 0u, 0u, 0u};
+    if (live) bk = a.buckets[b];
+    const pm_inst I = a.inst ? a.inst[a.item_inst[live ? bk.trial : 0]] : a.one;
     const int64_t lm1 = a.l - 1;
-    const uint32_t size = (int64_t)bk.first + bk.size <= a.cap_m ? bk.size : 0u;
-    // up to 64 members at a time: lane r finds where member r starts, then
-    // every column lane reads the members' symbols one after another
-    for (uint32_t r0 = 0; r0 < size; r0 += 64) {
-        const uint32_t nr = size - r0 < 64u ? size - r0 : 64u;
+    const uint32_t size = live && (int64_t)bk.first + bk.size <= a.cap_m ? bk.size : 0u;
+    // SW members at a time: lane j finds where member j starts, then every
+    // column lane reads the members' symbols one after another
+    uint32_t most = size;  // the wave's largest bucket
+#pragma unroll
+    for (int o = SW; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_xor(most, o);
+        most = t > most ? t : most;
+    }
+    for (uint32_t r0 = 0; r0 < most; r0 += SW) {
+        const uint32_t nr = size > r0 ? (size - r0 < (uint32_t)SW ? size - r0 : (uint32_t)SW) : 0u;
         int64_t Pm = 0;
-        if ((uint32_t)lane < nr) {
-            const int64_t w = a.members[(int64_t)bk.first + r0 + lane];
+        if ((uint32_t)j < nr) {
+            const int64_t w = a.members[(int64_t)bk.first + r0 + j];
             int lo = 0, hi = I.t;  // last sequence whose first window <= w
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
@@ -770,16 +781,19 @@ __global__ void __launch_bounds__(256) k_profile(const ProfArgs a)
             }
             Pm = w + (int64_t)lo * lm1;
         }
-        for (uint32_t r = 0; r < nr; ++r) {
-            const int64_t P = __shfl(Pm, (int)r);
-            if (lane < a.l) {
-                const uint32_t code = a.A == 4 ? dna_sym(I.packed, P + lane) : prot_sym(I.packed, P + lane);
-                C[code * 32 + lane] += 1;
+        const uint32_t nmost = most - r0 < (uint32_t)SW ? most - r0 : (uint32_t)SW;
+        for (uint32_t r = 0; r < nmost; ++r) {
+            const int64_t P = __shfl(Pm, sub * SW + (int)r);
+            if (r < nr && j < a.l) {
+                const uint32_t code = a.A == 4 ? dna_sym(I.packed, P + j) : prot_sym(I.packed, P + j);
+                C[code * SW + j] += 1;
             }
         }
     }
+    if (!live) return;
     uint32_t *out = a.profile + b * a.A * a.l;
-    for (int i = lane; i < a.A * a.l; i += 64) out[i] = C[(i / a.l) * 32 + (i % a.l)];
+    for (int c = 0; c < a.A; ++c)
+        if (j < a.l) out[c * a.l + j] = C[c * SW + j];
 }
 
 // one thread per (bucket, column): the bucket's size from column 0, then the
@@ -960,7 +974,11 @@ extern "C" int bucket_select_batch(const pm_batch *B, const uint32_t *keys, cons
 
 static int profile_launch(const ProfArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_profile, dim3((unsigned)((a.B + 3) / 4)), dim3(256), 0, st, a);
+    if (a.l <= 16) {
+        hipLaunchKernelGGL(k_profile<16>, dim3((unsigned)((a.B + 15) / 16)), dim3(256), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(k_profile<32>, dim3((unsigned)((a.B + 7) / 8)), dim3(256), 0, st, a);
+    }
     PM_LAUNCHED();
     return PM_OK;
 }
