@@ -128,7 +128,9 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
     uint32_t *keys_j = a.keys ? a.keys + I.key_base + (int64_t)(j - I.first_item) * x : nullptr;
     uint32_t mine = 0;
     for_each_key<A, K>(a, st, pos, [&](int64_t w, uint32_t key) {
-        if (keys_j && w >= kw0 && w < kw1) __builtin_nontemporal_store(key, keys_j + w);
+        // ordinary stores: a trial's key row is not aligned to cache lines, and
+        // non-temporal stores of partial lines cost a quarter of the kernel
+        if (keys_j && w >= kw0 && w < kw1) keys_j[w] = key;
         if (a.counts) {
             const uint32_t bin = key - slice_base;
             if (bin < a.slice_bins) {
