@@ -108,6 +108,14 @@ def test_other_entry_points_validate():
     # workspace too small
     assert L.bucket_select(C.byref(S.c), 4, 2, 0x1, 0x1, 1, 2, 0x1, 1, 0x1, 1, 0x1, 0x1, 8,
                            None, None) == pm.PM_EINVAL
+    # selection workspace: per-trial totals and bitmap of |Sigma|^k / 64 words,
+    # per-bucket cursors; 0 outside the count-table range (|Sigma|^k <= 2^19)
+    assert pm.pm_select_workspace(4, 9, 10, 100) > pm.pm_select_workspace(4, 8, 10, 100) > 0
+    assert pm.pm_select_workspace(4, 8, 10, 200) - pm.pm_select_workspace(4, 8, 10, 100) == 100 * 16
+    assert pm.pm_select_workspace(4, 10, 10, 100) == 0
+    assert pm.pm_select_workspace(20, 5, 10, 100) == 0
+    assert pm.pm_select_workspace(20, 4, 10, 100) > 0
+    assert pm.pm_select_workspace(3, 4, 10, 100) == 0
     assert L.theta_init(5, 4, 0x1, 1, None, 0x1, 1.0, 0x1, None) == pm.PM_EINVAL
     assert L.theta_init(4, 4, 0x1, 1, None, 0x1, -1.0, 0x1, None) == pm.PM_EINVAL
     assert L.em_refine(C.byref(S.c), 4, 0x1, 0x1, 1, None, 3, 1.0, 7, 0x1, 0x1, None, None,
