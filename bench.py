@@ -28,14 +28,14 @@ FP16_MFMA_PEAK = 2500.0      # TFLOP/s, MI355X dense FP16 matrix cores
 # profiles/hbm_traffic_dna_18-6_m5000.md (copy-calibrated), valid only while
 # the kernel source is the one they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "hash.hip": ("f7095d0c251b8e84", {"k_hash<4,8>": 1.772e9, "k_hash<4,9>": 14.918e9, "k_hash<20,4>": 1.557e9}),
+    "hash.hip": ("d7f5edcdb1da61ea", {"k_hash<4,8>": 1.705e9, "k_hash<4,9>": 14.486e9, "k_hash<20,4>": 1.516e9}),
     "em_mfma.hip": ("7b50002b89335e08", {
-        "k_em_mfma<5,2,true,1,1>": 0.726e9 + 0.695e9,
-        "k_em_mfma<5,2,true,2,1>": 0.695e9 + 0.715e9,
-        "k_em_mfma<5,2,true,4,1>": 0.762e9 + 0.725e9,
-        "k_em_mfma<5,2,true,1,2>": 0.780e9 + 0.750e9,
-        "k_em_mfma<5,2,true,2,2>": 0.772e9 + 0.724e9,
-        "k_em_mfma<5,2,true,4,2>": 0.785e9 + 0.754e9,
+        "k_em_mfma<5,2,true,1,1>": 0.727e9 + 0.692e9,
+        "k_em_mfma<5,2,true,2,1>": 0.697e9 + 0.712e9,
+        "k_em_mfma<5,2,true,4,1>": 0.763e9 + 0.725e9,
+        "k_em_mfma<5,2,true,1,2>": 0.783e9 + 0.752e9,
+        "k_em_mfma<5,2,true,2,2>": 0.777e9 + 0.726e9,
+        "k_em_mfma<5,2,true,4,2>": 0.784e9 + 0.755e9,
     }),
 }
 
