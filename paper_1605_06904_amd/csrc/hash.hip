@@ -4,11 +4,12 @@
 // per GPU thread.  Here one workgroup owns one trial (and one slice of the
 // key range when the |Sigma|^k histogram does not fit in LDS): it stages the
 // packed input (a few KB) in LDS, builds keys from LDS windows, writes them
-// with coalesced stores and counts them in an LDS histogram of u8, u16 or u32
-// counters (the width that needs the fewest key-range slices, the widest on a
-// tie), then streams the histogram out as dense u32 counts.  A narrow counter
-// that wraps is seen from the value its atomic returned (u8) or from the
-// slice's window total (u16), and such a slice is counted again in u32.
+// with coalesced stores and counts them in an LDS histogram of u4, u8, u16 or
+// u32 counters (the width that needs the fewest key-range slices, then the
+// most workgroups per CU, then the widest), then streams the histogram out as
+// dense u32 counts.  A narrow counter that wraps is seen from the value its
+// atomic returned (u4, u8) or from the slice's window total (u16), and such a
+// slice is counted again in u32.
 #include <algorithm>
 #include <mutex>
 

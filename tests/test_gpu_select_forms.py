@@ -97,14 +97,18 @@ def test_select_large_trials_match_oracle(case):
     assert np.array_equal(mem[:nm_], rmem)
 
 
-def test_select_device_rows_truncated_to_capacity():
-    name, A, t, n, l, k, s, m = CASES[2]
+@pytest.mark.parametrize("which", [0, 1, 2, 3], ids=[CASES[i][0] for i in range(4)])
+def test_select_truncated_to_capacity(which):
+    """Capacities that end inside a trial's buckets and inside a bucket's
+    members, in every placement form: the kept records and every member slot
+    of a kept bucket below the member capacity as the oracle's."""
+    name, A, t, n, l, k, s, m = CASES[which]
     seqs, masks = _case(name, A, t, n, l, k, m)
     ref = oracle.Seqs(A, seqs)
     RK, RN = oracle.hash_trials(ref, l, k, masks)
     rbk, rmem, (rnb, rnm), _ = oracle.select(ref, l, k, RK, RN, s)
     cap_b, cap_m = rnb // 2 + 3, rnm // 3
-    say("select forms truncated", cap_b, cap_m)
+    say("select forms truncated", name, cap_b, cap_m)
     S = pm.Seqs(A, seqs)
     bk, mem, (nb_, nm_), st = _select(S, A, l, k, s, RK, RN, cap_b=cap_b, cap_m=cap_m)
     assert st & pm.PM_STATUS_CAPACITY and (nb_, nm_) == (rnb, rnm)
