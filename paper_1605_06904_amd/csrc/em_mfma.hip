@@ -493,6 +493,7 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
     __shared__ __align__(16) PairTables<MT> tabs[2 * PPB];
     __shared__ __align__(16) uint2 lut[256];
     __shared__ __align__(16) float accs[kWaves][G][16][CX][4];
+    __shared__ double lbg[4];  // ln bg[c], formed once for every iteration's log-odds
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     EmMfmaArgs a = a0;
@@ -535,6 +536,8 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
         build_lut(lut);
         lutp = lut;
     }
+    if (threadIdx.x < 4) lbg[threadIdx.x] = log(a.bg[threadIdx.x]);
+    __syncthreads();
     const int64_t bw = b0 + 16 * G * wv;
     float (*acc)[16][CX][4] = accs[wv];
     const int l = a.l, t = a.t, AL = 4 * l;
@@ -576,7 +579,7 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
                             const double th = src[b * AL + c * l + p];
                             if (it == 0) a.theta_out[b * AL + c * l + p] = th;
                             const double lt = log(th);
-                            w = (float)((lt - log(a.bg[c])) * (double)kLog2e);
+                            w = (float)((lt - lbg[c]) * (double)kLog2e);
                             pr += a.bg[c] * lt;
                         }
                         mn = c == 0 ? w : fminf(mn, w);
