@@ -183,6 +183,13 @@ struct Tiles {
     static constexpr int NE = 4 * MT + 12;  // M-step table entries a pair reads
 };
 
+// Split form with an odd number of 4-position tiles: the last k-block holds
+// at most four real positions, so its hi and lo halves share one MFMA (lane
+// groups 0, 1 carry the hi halves of its positions, groups 2, 3 the lo halves
+// of the same positions) instead of two MFMAs each half zero.
+template <int MT, bool SPLIT>
+constexpr bool kMergeTail = SPLIT && (MT & 1) != 0;
+
 // one-hot tables of one window pair: the symbols at s0 + a0 + e
 template <int MT>
 struct alignas(16) PairTables {
@@ -242,13 +249,17 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T
                                           SeqState (&st)[G])
 {
     constexpr int LB = Tiles<MT>::LB;
+    constexpr bool MERGE = kMergeTail<MT, SPLIT>;
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     half8 Ae[2][LB];
 #pragma unroll
     for (int t2 = 0; t2 < 2; ++t2)
 #pragma unroll
-        for (int kb = 0; kb < LB; ++kb)
-            Ae[t2][kb] = *reinterpret_cast<const half8 *>(&T.oh2[16 * t2 + r + 8 * kb + 2 * g][0]);
+        for (int kb = 0; kb < LB; ++kb) {
+            // merged last block: groups 2, 3 repeat the positions of groups 0, 1
+            const int gp = MERGE && kb == LB - 1 ? g & 1 : g;
+            Ae[t2][kb] = *reinterpret_cast<const half8 *>(&T.oh2[16 * t2 + r + 8 * kb + 2 * gp][0]);
+        }
     // E-step, already shifted: S' = S - (mref - kPOff); one chain per tile and group
     float4v S0[G], S1[G];
 #pragma unroll
@@ -262,7 +273,7 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T
         for (int q = 0; q < G; ++q) {
             S0[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[0][kb], Whi[q][kb], S0[q], 0, 0, 0);
             S1[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[1][kb], Whi[q][kb], S1[q], 0, 0, 0);
-            if (SPLIT) {
+            if (SPLIT && !(MERGE && kb == LB - 1)) {
                 S0[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[0][kb], Wlo[q][kb], S0[q], 0, 0, 0);
                 S1[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ae[1][kb], Wlo[q][kb], S1[q], 0, 0, 0);
             }
@@ -550,8 +561,10 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
         const double *src = it == 0 ? a.theta0 : a.theta_out;
         // ---- log-odds (log2 units) of the lane's E-step B operands: model r of
         // group q, positions 8kb+2g and 8kb+2g+1, letters 0..3, split in two
-        // FP16 halves; the lane's entries cover every position once across the
-        // four lane groups, so the prior and the lowest score are lane sums
+        // FP16 halves (a merged last block: hi halves in groups 0, 1, lo halves
+        // of the same positions in groups 2, 3); the lane's hi entries cover
+        // every position once across the four lane groups, so the prior and the
+        // lowest score are lane sums over them
         double prior[G];
         float mlow[G];
         // the lane's position base goes through an empty asm statement so that
@@ -567,28 +580,29 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
             float wmin = 0.f;
 #pragma unroll
             for (int kb = 0; kb < LB; ++kb) {
+                const bool lo_half = kMergeTail<MT, SPLIT> && kb == LB - 1 && g2 >= 4;
                 half8 hi, lo;
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int p = 8 * kb + g2 + h;
+                    const int p = 8 * kb + (lo_half ? g2 - 4 : g2) + h;
                     float mn = 0.f;
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         float w = 0.f;
                         if (p < l && vb) {
                             const double th = src[b * AL + c * l + p];
-                            if (it == 0) a.theta_out[b * AL + c * l + p] = th;
+                            if (it == 0 && !lo_half) a.theta_out[b * AL + c * l + p] = th;
                             const double lt = log(th);
                             w = (float)((lt - lbg[c]) * (double)kLog2e);
-                            pr += a.bg[c] * lt;
+                            if (!lo_half) pr += a.bg[c] * lt;
                         }
                         mn = c == 0 ? w : fminf(mn, w);
                         hi[4 * h + c] = (_Float16)w;
                         lo[4 * h + c] = (_Float16)(w - (float)hi[4 * h + c]);
                     }
-                    wmin += mn;
+                    if (!lo_half) wmin += mn;
                 }
-                Whi[q][kb] = hi;
+                Whi[q][kb] = lo_half ? lo : hi;
                 Wlo[q][kb] = lo;
             }
             pr += __shfl_xor(pr, 16);

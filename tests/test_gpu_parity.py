@@ -368,6 +368,12 @@ EM_CASES = [
     ("dna ragged beta 0.3", 3, 4, 11, None, 13, 3, 5, 7, 0.3),
     ("protein", 4, 20, 8, 150, 12, 3, 4, 4, 1.0),
     ("dna l=32", 5, 4, 5, 120, 32, 6, 3, 3, 2.0),
+    # odd numbers of 4-position tiles: the split form's last k-block holds the
+    # hi and lo halves of its positions in one MFMA (two positions at l = 18,
+    # four at l = 20, one at l = 9); more models than one group of 16
+    ("dna l=18", 6, 4, 8, 200, 18, 6, 20, 4, 1.0),
+    ("dna l=20", 7, 4, 7, 160, 20, 5, 37, 3, 0.5),
+    ("dna l=9", 8, 4, 6, 110, 9, 2, 17, 4, 1.0),
 ]
 
 
