@@ -158,6 +158,25 @@ int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *keys,
                   int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out,
                   void *ws, size_t ws_bytes, uint32_t *status, void *stream);
 
+/* a3 + a4 + a5 in one call -- projection_hash followed by bucket_select, with
+ * the same keys, counts, buckets, members and n_out (bit for bit), but the
+ * selection's passing-key bitmap and per-trial totals are formed by the hash
+ * pass while each trial's histogram is still in LDS, so the counts are not
+ * read back for them (Alg. 2 steps 2(b), 2(c) and 3; Sec. 6's bucket test,
+ * a bucket passes with at least s l-mers, s = 0 as s = 1).
+ *   keys, counts  device [m][x], [m][|Sigma|^k] uint32, both required
+ *   masks         device [m]; a bad mask sets PM_STATUS_BAD_MASK and that
+ *                 trial's keys and counts are not written and it gives no
+ *                 buckets
+ *   buckets, members, n_out, ws, truncation: as for bucket_select (ws:
+ *                 pm_select_workspace(alphabet, k, m, cap_buckets) bytes,
+ *                 8-byte aligned)
+ * Limits: those of projection_hash and bucket_select (|Sigma|^k <= 2^19). */
+int projection_hash_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m,
+                           uint32_t *keys, uint32_t *counts, uint32_t s, pm_bucket *buckets,
+                           int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out,
+                           void *ws, size_t ws_bytes, uint32_t *status, void *stream);
+
 /* a3 + a4 + a5 fused -- Alg. 2 steps 2(b), 2(c) and 3 without keys or counts
  * in device memory: each trial's histogram lives only in LDS, where its
  * passing bins (at least s l-mers, Sec. 6) are turned into bucket records and
@@ -392,6 +411,14 @@ int projection_hash_batch(const pm_batch *B, const uint32_t *masks, uint32_t *ke
 int bucket_select_batch(const pm_batch *B, const uint32_t *keys, const uint32_t *counts, uint32_t s,
                         pm_bucket *buckets, int64_t cap_buckets, uint32_t *members, int64_t cap_members,
                         int64_t *n_out, void *ws, size_t ws_bytes, uint32_t *status, void *stream);
+
+/* projection_hash_select over every item of a batch: the outputs of
+ * projection_hash_batch followed by bucket_select_batch.  ws:
+ * pm_select_workspace(alphabet, k, items, cap_buckets) bytes, 8-byte aligned. */
+int projection_hash_select_batch(const pm_batch *B, const uint32_t *masks, uint32_t *keys, uint32_t *counts,
+                                 uint32_t s, pm_bucket *buckets, int64_t cap_buckets, uint32_t *members,
+                                 int64_t cap_members, int64_t *n_out, void *ws, size_t ws_bytes,
+                                 uint32_t *status, void *stream);
 
 /* The fused a3 - a5 over every item of a batch (bucket `trial` = item);
  * ws: pm_hash_select_batch_workspace(B) bytes. */

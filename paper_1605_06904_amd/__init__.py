@@ -37,6 +37,7 @@ EXPORTS = [
     "pm_hash_select_scratch_bytes", "bucket_hash_select_noalloc",
     "pm_sort_select_workspace", "bucket_sort_select", "pm_sort_select_batch_workspace", "bucket_sort_select_batch",
     "em_refine_model", "projection_run_range", "gibbs_refine",
+    "projection_hash_select", "projection_hash_select_batch",
 ]
 
 PM_TRIAGE_PARAMS, PM_TRIAGE_INPUTS = 88577, 87
@@ -163,6 +164,10 @@ def lib():
                                          P]),
         "pm_sort_select_batch_workspace": (sz, [C.POINTER(pm_batch)]),
         "bucket_sort_select_batch": (C.c_int, [C.POINTER(pm_batch), P, u32, P, i64, P, i64, P, P, sz, P, P]),
+        "projection_hash_select": (C.c_int, [C.POINTER(pm_seqs), i32, i32, P, i32, P, P, u32, P, i64, P, i64,
+                                             P, P, sz, P, P]),
+        "projection_hash_select_batch": (C.c_int, [C.POINTER(pm_batch), P, P, P, u32, P, i64, P, i64, P, P, sz,
+                                                   P, P]),
         "pm_hash_select_scratch_bytes": (sz, []),
         "bucket_hash_select_noalloc": (C.c_int, [C.POINTER(pm_seqs), i32, i32, P, i32, u32, P, i64, P, i64, P, P,
                                                  P]),
@@ -240,6 +245,13 @@ def bucket_select(S, l, k, keys, counts, m, s, buckets, cap_buckets, members, ca
     _check(lib().bucket_select(C.byref(S.c), l, k, _ptr(keys), _ptr(counts), m, s, _ptr(buckets),
                                cap_buckets, _ptr(members), cap_members, _ptr(n_out), _ptr(ws),
                                ws_bytes, _ptr(status), _stream(stream)))
+
+
+def projection_hash_select(S, l, k, masks, m, keys, counts, s, buckets, cap_buckets, members, cap_members,
+                           n_out, ws, ws_bytes, status=None, stream=None):
+    _check(lib().projection_hash_select(C.byref(S.c), l, k, _ptr(masks), m, _ptr(keys), _ptr(counts), s,
+                                        _ptr(buckets), cap_buckets, _ptr(members), cap_members, _ptr(n_out),
+                                        _ptr(ws), ws_bytes, _ptr(status), _stream(stream)))
 
 
 def pm_hash_select_workspace(S, l: int, k: int, m: int) -> int:
@@ -387,6 +399,13 @@ def bucket_select_batch(B, keys, counts, s, buckets, cap_buckets, members, cap_m
     _check(lib().bucket_select_batch(C.byref(B.c), _ptr(keys), _ptr(counts), s, _ptr(buckets), cap_buckets,
                                      _ptr(members), cap_members, _ptr(n_out), _ptr(ws), ws_bytes,
                                      _ptr(status), _stream(stream)))
+
+
+def projection_hash_select_batch(B, masks, keys, counts, s, buckets, cap_buckets, members, cap_members, n_out,
+                                 ws, ws_bytes, status=None, stream=None):
+    _check(lib().projection_hash_select_batch(C.byref(B.c), _ptr(masks), _ptr(keys), _ptr(counts), s,
+                                              _ptr(buckets), cap_buckets, _ptr(members), cap_members,
+                                              _ptr(n_out), _ptr(ws), ws_bytes, _ptr(status), _stream(stream)))
 
 
 def bucket_profile_batch(B, buckets, members, cap_members, Bcap, n_dev, profile, stream=None):
@@ -674,6 +693,13 @@ class Pipeline:
         bucket_select(self.S, self.l, self.k, b.keys, b.counts, self.m, self.s, b.buckets, b.cap_b,
                       b.members, b.cap_m, b.n_out, b.ws, self.ws_bytes, b.status, stream)
 
+    def hash_select(self, stream=None):
+        """hash() then select() in one call (the same outputs): the hash pass
+        also forms the selection's bitmap and totals."""
+        b = self.b
+        projection_hash_select(self.S, self.l, self.k, self.masks, self.m, b.keys, b.counts, self.s, b.buckets,
+                               b.cap_b, b.members, b.cap_m, b.n_out, b.ws, self.ws_bytes, b.status, stream)
+
     def refine(self, stream=None):
         b, A = self.b, self.S.alphabet
         bucket_profile(self.S, self.l, b.buckets, b.members, b.cap_m, b.cap_b, b.n_out, b.profile, stream)
@@ -683,8 +709,7 @@ class Pipeline:
         em_best(b.J, b.cap_b, b.n_out, self.iters, b.theta, A, self.l, b.best, b.consensus, stream)
 
     def run(self, stream=None):
-        self.hash(stream)
-        self.select(stream)
+        self.hash_select(stream)
         self.refine(stream)
 
     def result(self) -> dict:
@@ -813,6 +838,12 @@ class BatchPipeline:
         bucket_select_batch(self.B, b.keys, b.counts, self.s, b.buckets, b.cap_b, b.members, b.cap_m,
                             b.n_out, b.ws, self.ws_bytes, b.status, stream)
 
+    def hash_select(self, stream=None):
+        """hash() then select() in one call (the same outputs)."""
+        b = self.b
+        projection_hash_select_batch(self.B, self.B.masks, b.keys, b.counts, self.s, b.buckets, b.cap_b,
+                                     b.members, b.cap_m, b.n_out, b.ws, self.ws_bytes, b.status, stream)
+
     def profile(self, stream=None):
         b = self.b
         bucket_profile_batch(self.B, b.buckets, b.members, b.cap_m, b.cap_b, b.n_out, b.profile, stream)
@@ -830,8 +861,7 @@ class BatchPipeline:
                       stream)
 
     def run(self, stream=None):
-        self.hash(stream)
-        self.select(stream)
+        self.hash_select(stream)
         self.profile(stream)
         self.refine(stream)
         self.best(stream)
@@ -1013,8 +1043,7 @@ class TriagedBatchPipeline(BatchPipeline):
                           L2["best"], L2["index"], L2["J"], L2["theta"], b.best, b.consensus, stream)
 
     def run(self, stream=None):
-        self.hash(stream)
-        self.select(stream)
+        self.hash_select(stream)
         self.profile(stream)
         self.triage(stream)
 

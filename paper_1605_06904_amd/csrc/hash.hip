@@ -74,7 +74,8 @@ __device__ __forceinline__ void hist_add(uint32_t *hist, uint32_t bin)
     else atomicAdd(hist + bin, 1u);
 }
 
-constexpr int kHashFlagWords = 1;  // LDS words after the staged input: the slice's window total
+constexpr int kHashFlagWords = 3;  // LDS words after the staged input: the slice's window total, and
+                                   // its passing bins and members for projection_hash_select
 
 // Count-table widths of k_hash.
 constexpr int kHist16 = 0;       // u16 pairs: instances below 65 536 windows
@@ -113,13 +114,14 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
     uint32_t *seq = smem + a.hist_words;
     int32_t *wst = reinterpret_cast<int32_t *>(seq + a.seq_cap);  // window number of each sequence start
     uint32_t &in_slice = *reinterpret_cast<uint32_t *>(wst + a.off_cap);  // kHashFlagWords
+    uint32_t *sel_acc = &in_slice + 1;                                     // [2]
     const Staged st = stage_input<A>(a, j, seq, wst);
     const pm_inst &I = st.I;
     const int64_t x = I.x;
     if (a.counts)
         for (int i = tid * 4; i < a.hist_words; i += kHashThreads * 4)
             *reinterpret_cast<uint4 *>(hist + i) = make_uint4(0, 0, 0, 0);
-    if (tid == 0) in_slice = 0;
+    if (tid == 0) in_slice = sel_acc[0] = sel_acc[1] = 0;
     __syncthreads();
 
     int pos[K];
@@ -164,55 +166,91 @@ __global__ void __launch_bounds__(kHashThreads) k_hash(const HashArgs a)
     const uint64_t left = (uint64_t)a.nb - slice_base;
     const uint32_t nvalid = left < a.slice_bins ? (uint32_t)left : a.slice_bins;  // multiple of 4
     uint32_t *out = a.counts + (int64_t)j * a.nb + slice_base;
-    if (HIST == kHist32) {
-        for (uint32_t b4 = tid * 4; b4 < nvalid; b4 += kHashThreads * 4) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(hist + b4);
-            __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<u32x4 *>(out + b4));
+    const int wv = tid >> 6, lane = lane_id();
+    uint32_t sel_ne = 0, sel_ms = 0;  // sel_ne counts whole ballots (the same in every lane)
+    // projection_hash_select: the counts v of bins base + 4 lane .. +3 (a wave
+    // takes 256 bins, base a multiple of 256 from the slice's start): one
+    // ballot per bin of the quad gives four bitmap words
+    auto select_words = [&](uint32_t base, bool valid, const u32x4 &v) {
+        uint64_t bal[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool p = valid && v[q] >= a.sel_smin;
+            bal[q] = __ballot(p);
+            sel_ne += (uint32_t)__popcll(bal[q]);
+            sel_ms += p ? v[q] : 0u;
         }
-        return;
+        const int64_t wi = (int64_t)(slice_base + base) / 64 + lane;
+        if (lane < 4 && wi < a.sel_nwb) {
+            const int sh = 16 * lane;
+            a.sel_bits[(int64_t)j * a.sel_nwb + wi] =
+                ((bal[0] >> sh) & 0xffffull) | (((bal[1] >> sh) & 0xffffull) << 16) |
+                (((bal[2] >> sh) & 0xffffull) << 32) | (((bal[3] >> sh) & 0xffffull) << 48);
+        }
+    };
+    const bool wrapped = (HIST == kHist16Check || HIST == kHist8 || HIST == kHist4) && in_slice >= 65536u;
+    if (!wrapped) {
+        for (uint32_t base = 256u * wv; base < nvalid; base += kHashThreads * 4) {
+            const uint32_t b4 = base + 4u * lane;
+            const bool valid = b4 < nvalid;
+            u32x4 v = u32x4{0u, 0u, 0u, 0u};
+            if (valid) {
+                if (HIST == kHist32) {
+                    const uint4 w = *reinterpret_cast<const uint4 *>(hist + b4);
+                    v = u32x4{w.x, w.y, w.z, w.w};
+                } else if (HIST == kHist8) {
+                    const uint32_t w = hist[b4 >> 2];
+                    v = u32x4{w & 0xffu, (w >> 8) & 0xffu, (w >> 16) & 0xffu, w >> 24};
+                } else if (HIST == kHist4) {
+                    const uint32_t w = hist[b4 >> 3] >> ((b4 & 4u) << 2);
+                    v = u32x4{w & 0xfu, (w >> 4) & 0xfu, (w >> 8) & 0xfu, (w >> 12) & 0xfu};
+                } else {
+                    const uint32_t w0 = hist[b4 >> 1], w1 = hist[(b4 >> 1) + 1];
+                    v = u32x4{w0 & 0xffffu, w0 >> 16, w1 & 0xffffu, w1 >> 16};
+                }
+                __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(out + b4));
+            }
+            if (a.sel_bits) select_words(base, valid, v);
+        }
+    } else {
+        // a count may have wrapped: the slice counted again in u32,
+        // hist_words bins per pass (a multiple of 256 with the selection)
+        const uint32_t hw = (uint32_t)a.hist_words;
+        for (uint32_t h0 = 0; h0 < nvalid; h0 += hw) {
+            __syncthreads();
+            for (int i = tid * 4; i < a.hist_words; i += kHashThreads * 4)
+                *reinterpret_cast<uint4 *>(hist + i) = make_uint4(0, 0, 0, 0);
+            __syncthreads();
+            for_each_key<A, K>(a, st, pos, [&](int64_t, uint32_t key) {
+                const uint32_t bin = key - slice_base - h0;
+                if (bin < hw) atomicAdd(hist + bin, 1u);
+            });
+            __syncthreads();
+            const uint32_t n = nvalid - h0 < hw ? nvalid - h0 : hw;
+            for (uint32_t base = 256u * wv; base < n; base += kHashThreads * 4) {
+                const uint32_t b4 = base + 4u * lane;
+                const bool valid = b4 < n;
+                u32x4 v = u32x4{0u, 0u, 0u, 0u};
+                if (valid) {
+                    const uint4 w = *reinterpret_cast<const uint4 *>(hist + b4);
+                    v = u32x4{w.x, w.y, w.z, w.w};
+                    __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(out + h0 + b4));
+                }
+                if (a.sel_bits) select_words(h0 + base, valid, v);
+            }
+        }
     }
-    if (HIST == kHist8 && in_slice < 65536u) {
-        for (uint32_t b4 = tid * 4; b4 < nvalid; b4 += kHashThreads * 4) {
-            const uint32_t w = hist[b4 >> 2];
-            __builtin_nontemporal_store(u32x4{w & 0xffu, (w >> 8) & 0xffu, (w >> 16) & 0xffu, w >> 24},
-                                        reinterpret_cast<u32x4 *>(out + b4));
-        }
-        return;
+    if (!a.sel_bits) return;
+    // the item's passing bins and members, summed over its slices
+    sel_ms = wave_sum(sel_ms);
+    if (lane == 0) {
+        atomicAdd(sel_acc, sel_ne);
+        atomicAdd(sel_acc + 1, sel_ms);
     }
-    if (HIST == kHist4 && in_slice < 65536u) {
-        for (uint32_t b4 = tid * 4; b4 < nvalid; b4 += kHashThreads * 4) {
-            const uint32_t w = hist[b4 >> 3] >> ((b4 & 4u) << 2);
-            __builtin_nontemporal_store(u32x4{w & 0xfu, (w >> 4) & 0xfu, (w >> 8) & 0xfu, (w >> 12) & 0xfu},
-                                        reinterpret_cast<u32x4 *>(out + b4));
-        }
-        return;
-    }
-    if (HIST == kHist16 || (HIST == kHist16Check && in_slice < 65536u)) {
-        for (uint32_t b4 = tid * 4; b4 < nvalid; b4 += kHashThreads * 4) {
-            const uint32_t w0 = hist[b4 >> 1], w1 = hist[(b4 >> 1) + 1];
-            __builtin_nontemporal_store(u32x4{w0 & 0xffffu, w0 >> 16, w1 & 0xffffu, w1 >> 16},
-                                        reinterpret_cast<u32x4 *>(out + b4));
-        }
-        return;
-    }
-    // a count may have wrapped: the slice counted again in u32, hist_words
-    // bins per pass
-    const uint32_t hw = (uint32_t)a.hist_words;  // multiple of 4
-    for (uint32_t h0 = 0; h0 < nvalid; h0 += hw) {
-        __syncthreads();
-        for (int i = tid * 4; i < a.hist_words; i += kHashThreads * 4)
-            *reinterpret_cast<uint4 *>(hist + i) = make_uint4(0, 0, 0, 0);
-        __syncthreads();
-        for_each_key<A, K>(a, st, pos, [&](int64_t, uint32_t key) {
-            const uint32_t bin = key - slice_base - h0;
-            if (bin < hw) atomicAdd(hist + bin, 1u);
-        });
-        __syncthreads();
-        const uint32_t n = nvalid - h0 < hw ? nvalid - h0 : hw;
-        for (uint32_t b4 = tid * 4; b4 < n; b4 += kHashThreads * 4) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(hist + b4);
-            __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<u32x4 *>(out + h0 + b4));
-        }
+    __syncthreads();
+    if (tid == 0) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(a.sel_ne + j), (unsigned long long)sel_acc[0]);
+        atomicAdd(reinterpret_cast<unsigned long long *>(a.sel_ms + j), (unsigned long long)sel_acc[1]);
     }
 }
 
@@ -500,10 +538,19 @@ static size_t hash_layout(HashArgs &a, bool hist, int per_word, int64_t nw_max, 
         // (each slice recomputes the trial's keys; measured 11% faster on the
         // (18,6) workload's 128 KB histograms)
         const int64_t half = ((int64_t)lds_max / 2 - fixed) / 4;
-        if (balance && need_words <= budget && need_words > half && (need_words + 1) / 2 <= half && half >= 1024)
+        int64_t cap = budget;
+        if (balance && need_words <= budget && need_words > half && (need_words + 1) / 2 <= half && half >= 1024) {
             hw = (need_words + 1) / 2;
+            cap = half;
+        }
         hw = (hw + 3) & ~int64_t(3);
         if (hw > budget) hw = budget;
+        if (a.sel_bits) {
+            // the selection's bitmap: every slice and every u32 recount pass
+            // a whole number of 256-bin groups (budget >= 1024 words)
+            const int64_t up = (hw + 255) & ~int64_t(255);
+            hw = up <= cap ? up : hw & ~int64_t(255);
+        }
         a.hist_words = (int)hw;
         a.slice_bins = (uint32_t)(per_word * hw);
         a.nslices = (int)((a.nb + a.slice_bins - 1) / a.slice_bins);
@@ -664,6 +711,81 @@ extern "C" int projection_hash_batch(const pm_batch *B, const uint32_t *masks, u
     a.l = B->l;
     a.k = B->k;
     return hash_launch(a, A, B->items, info.x_max, info.nw_max, info.t_max, as_stream(stream));
+}
+
+// the hash launch of projection_hash_select: keys and counts as
+// projection_hash writes them, and the selection's bitmap and totals
+static int hash_counted(HashArgs &a, int A, int32_t items, int64_t x_max, int64_t nw_max, int t_max, uint32_t s,
+                        void *ws, hipStream_t st)
+{
+    SelCounted c;
+    if (int rc = select_counted_prepare(ws, items, A, a.k, &c, st)) return rc;
+    a.sel_bits = c.bits;
+    a.sel_ne = c.ne;
+    a.sel_ms = c.ms;
+    a.sel_nwb = c.nwb;
+    a.sel_smin = s > 1u ? s : 1u;  // s = 0 selects like s = 1
+    return hash_launch(a, A, items, x_max, nw_max, t_max, st);
+}
+
+extern "C" int projection_hash_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m,
+                                      uint32_t *keys, uint32_t *counts, uint32_t s, pm_bucket *buckets,
+                                      int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out,
+                                      void *ws, size_t ws_bytes, uint32_t *status, void *stream)
+{
+    clear_error();
+    int rc = check_seqs(S, l);
+    if (rc) return rc;
+    const int A = S->alphabet;
+    if ((rc = check_hash_args(A, l, k, masks, m, keys, counts))) return rc;
+    if ((rc = check_select_ws(A, k, m, keys, counts, n_out, ws, ws_bytes, buckets, cap_buckets, members,
+                              cap_members)))
+        return rc;
+    HashArgs a{};
+    a.A = A;
+    a.one = inst_of(S, l);
+    a.masks = masks;
+    a.keys = keys;
+    a.counts = counts;
+    a.status = status;
+    a.nb = ipow(A, k);
+    a.l = l;
+    a.k = k;
+    const hipStream_t st = as_stream(stream);
+    if ((rc = hash_counted(a, A, m, a.one.x, pm_packed_words(A, S->n_total), S->t, s, ws, st))) return rc;
+    return select_counted(a.one, nullptr, nullptr, A, k, keys, counts, m, s, buckets, cap_buckets, members,
+                          cap_members, n_out, ws, status, a.one.x, st);
+}
+
+extern "C" int projection_hash_select_batch(const pm_batch *B, const uint32_t *masks, uint32_t *keys,
+                                            uint32_t *counts, uint32_t s, pm_bucket *buckets, int64_t cap_buckets,
+                                            uint32_t *members, int64_t cap_members, int64_t *n_out, void *ws,
+                                            size_t ws_bytes, uint32_t *status, void *stream)
+{
+    clear_error();
+    BatchInfo info;
+    int rc = check_batch(B, &info);
+    if (rc) return rc;
+    const int A = B->alphabet;
+    if ((rc = check_hash_args(A, B->l, B->k, masks, B->items, keys, counts))) return rc;
+    if ((rc = check_select_ws(A, B->k, B->items, keys, counts, n_out, ws, ws_bytes, buckets, cap_buckets, members,
+                              cap_members)))
+        return rc;
+    HashArgs a{};
+    a.A = A;
+    a.inst = B->inst;
+    a.item_inst = B->item_inst;
+    a.masks = masks;
+    a.keys = keys;
+    a.counts = counts;
+    a.status = status;
+    a.nb = ipow(A, B->k);
+    a.l = B->l;
+    a.k = B->k;
+    const hipStream_t st = as_stream(stream);
+    if ((rc = hash_counted(a, A, B->items, info.x_max, info.nw_max, info.t_max, s, ws, st))) return rc;
+    return select_counted(a.one, B->inst, B->item_inst, A, B->k, keys, counts, B->items, s, buckets, cap_buckets,
+                          members, cap_members, n_out, ws, status, info.x_max, st);
 }
 
 extern "C" size_t pm_hash_select_workspace(const pm_seqs *S, int32_t l, int32_t k, int32_t m)

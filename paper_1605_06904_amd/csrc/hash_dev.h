@@ -24,6 +24,16 @@ struct HashArgs {
     int seq_cap;         // LDS words reserved for the input (0: read from global): DNA the packed
                          // words, protein one byte per symbol (unpacked on staging)
     int off_cap;         // LDS window starts reserved, t + 1 (0: read offsets from global)
+    // projection_hash_select: with the counts, the selection's passing-key
+    // bitmap (words of 64 bins in lane-major bit order: bit 16q + i of the
+    // word of bins 64w .. 64w+63 is bin 64w + 4i + q) and per item the number
+    // of passing bins and their members, added up over the item's slices
+    // (zeroed before the launch); slices are then whole 256-bin groups.  NULL
+    // in projection_hash.
+    uint64_t *sel_bits;        // [items][sel_nwb]
+    int64_t *sel_ne, *sel_ms;  // [items]
+    int64_t sel_nwb;
+    uint32_t sel_smin;         // a bin passes with at least this many l-mers
 };
 
 constexpr int kHashThreads = 1024;

@@ -75,6 +75,24 @@ struct TotScan {
 };
 int launch_tot_scan(const TotScan &a, hipStream_t st);
 
+// projection_hash_select: the pieces of bucket_select's workspace that its
+// hash pass writes (passing-key bitmap, per-trial passing bins and members),
+// with the totals zeroed on the stream; then the selection from them, the
+// counting pass skipped.  The workspace is bucket_select's.
+struct SelCounted {
+    uint64_t *bits;
+    int64_t *ne, *ms;
+    int64_t nwb;
+};
+int check_select_ws(int A, int k, int32_t items, const uint32_t *keys, const uint32_t *counts,
+                    const int64_t *n_out, void *ws, size_t ws_bytes, pm_bucket *buckets, int64_t cap_buckets,
+                    uint32_t *members, int64_t cap_members);
+int select_counted_prepare(void *ws, int32_t m, int A, int k, SelCounted *out, hipStream_t st);
+int select_counted(const pm_inst &one, const pm_inst *inst, const int32_t *item_inst, int A, int k,
+                   const uint32_t *keys, const uint32_t *counts, int32_t m, uint32_t s, pm_bucket *buckets,
+                   int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out, void *ws,
+                   uint32_t *status, int64_t x_max, hipStream_t st);
+
 int em_refine_mfma(const pm_seqs *S, int32_t l, const double *theta0, const double *bg, int64_t B,
                    const int64_t *n_dev, int32_t iters, double beta, double *theta_out, double *J_out,
                    double *llr_out, int32_t *sites_out, void *ws, size_t ws_bytes, bool split, hipStream_t st);

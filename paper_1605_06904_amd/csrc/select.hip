@@ -845,13 +845,17 @@ static size_t sel_emit_lds(int64_t nwb, int64_t cb)
     return (size_t)(16 * nwb + 4 * cb + 4 * std::max<int64_t>(3 * cb, 8 * kSelListCap));
 }
 
-static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st)
+// counted: the bitmap and the per-trial totals are already in the workspace
+// (projection_hash_select's hash pass wrote them), so no counting pass
+static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st, bool counted = false)
 {
     const int64_t nwb = (a.nb + 63) / 64;
     a.nwb = (int)nwb;
-    a.parts = sel_parts(a.m, nwb);
-    hipLaunchKernelGGL(k_sel_count, dim3((unsigned)((int64_t)a.m * a.parts)), dim3(256), 0, st, a);
-    PM_LAUNCHED();
+    a.parts = counted ? 1 : sel_parts(a.m, nwb);
+    if (!counted) {
+        hipLaunchKernelGGL(k_sel_count, dim3((unsigned)((int64_t)a.m * a.parts)), dim3(256), 0, st, a);
+        PM_LAUNCHED();
+    }
     // a trial has at most min(|Sigma|^k, x / s) passing bins; the first emit
     // launch keeps its LDS near 20 KB (eight workgroups per CU) and takes the
     // trials whose buckets fit there, a second one with all the LDS the device
@@ -912,6 +916,60 @@ static int check_select_args(int A, int k, int32_t items, const uint32_t *keys, 
     if (reinterpret_cast<uintptr_t>(ws) & 7) return fail(PM_EINVAL, "workspace must be 8-byte aligned");
     return PM_OK;
 }
+
+namespace pm {
+
+int check_select_ws(int A, int k, int32_t items, const uint32_t *keys, const uint32_t *counts,
+                    const int64_t *n_out, void *ws, size_t ws_bytes, pm_bucket *buckets, int64_t cap_buckets,
+                    uint32_t *members, int64_t cap_members)
+{
+    return check_select_args(A, k, items, keys, counts, n_out, ws, ws_bytes, buckets, cap_buckets, members,
+                             cap_members);
+}
+
+__global__ void k_sel_zero(int64_t *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+int select_counted_prepare(void *ws, int32_t m, int A, int k, SelCounted *out, hipStream_t st)
+{
+    const int64_t nb = sel_bins(A, k), nwb = (nb + 63) / 64;
+    const SelWs w = carve(ws, m, nwb);
+    // ne and ms are adjacent: [m] each
+    hipLaunchKernelGGL(k_sel_zero, dim3((unsigned)((2 * (int64_t)m + 255) / 256)), dim3(256), 0, st, w.ne,
+                       2 * (int64_t)m);
+    PM_LAUNCHED();
+    *out = SelCounted{w.bits, w.ne, w.ms, nwb};
+    return PM_OK;
+}
+
+int select_counted(const pm_inst &one, const pm_inst *inst, const int32_t *item_inst, int A, int k,
+                   const uint32_t *keys, const uint32_t *counts, int32_t m, uint32_t s, pm_bucket *buckets,
+                   int64_t cap_buckets, uint32_t *members, int64_t cap_members, int64_t *n_out, void *ws,
+                   uint32_t *status, int64_t x_max, hipStream_t st)
+{
+    SelArgs a{};
+    a.one = one;
+    a.inst = inst;
+    a.item_inst = item_inst;
+    a.keys = keys;
+    a.counts = counts;
+    a.buckets = buckets;
+    a.members = members;
+    a.n_out = n_out;
+    a.status = status;
+    a.nb = sel_bins(A, k);
+    a.ws = carve(ws, m, (a.nb + 63) / 64);
+    a.cap_b = cap_buckets;
+    a.cap_m = cap_members;
+    a.m = m;
+    a.s = s;
+    return select_launch(a, x_max, st, true);
+}
+
+}  // namespace pm
 
 extern "C" int bucket_select(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *keys,
                              const uint32_t *counts, int32_t m, uint32_t s, pm_bucket *buckets,
