@@ -28,14 +28,14 @@ FP16_MFMA_PEAK = 2500.0      # TFLOP/s, MI355X dense FP16 matrix cores
 # profiles/hbm_traffic_dna_18-6_m5000.md (copy-calibrated), valid only while
 # the kernel source is the one they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
-    "hash.hip": ("817d6bac13bf265a", {"k_hash<4,8>": 1.705e9, "k_hash<4,9>": 14.486e9, "k_hash<20,4>": 1.516e9}),
-    "em_mfma.hip": ("7b50002b89335e08", {
-        "k_em_mfma<5,2,true,1,1>": 0.727e9 + 0.692e9,
-        "k_em_mfma<5,2,true,2,1>": 0.697e9 + 0.712e9,
-        "k_em_mfma<5,2,true,4,1>": 0.763e9 + 0.725e9,
-        "k_em_mfma<5,2,true,1,2>": 0.783e9 + 0.752e9,
-        "k_em_mfma<5,2,true,2,2>": 0.777e9 + 0.726e9,
-        "k_em_mfma<5,2,true,4,2>": 0.784e9 + 0.755e9,
+    "hash.hip": ("8544af7b0b679691", {"k_hash<4,8>": 1.705e9, "k_hash<4,9>": 14.492e9, "k_hash<20,4>": 1.517e9}),
+    "em_mfma.hip": ("05301b28e7c01f29", {
+        "k_em_mfma<5,2,true,1,1>": 0.745e9 + 0.715e9,
+        "k_em_mfma<5,2,true,2,1>": 0.692e9 + 0.698e9,
+        "k_em_mfma<5,2,true,4,1>": 1.050e9 + 0.740e9,
+        "k_em_mfma<5,2,true,1,2>": 0.747e9 + 0.744e9,
+        "k_em_mfma<5,2,true,2,2>": 0.742e9 + 0.739e9,
+        "k_em_mfma<5,2,true,4,2>": 0.889e9 + 0.732e9,
     }),
 }
 
@@ -56,12 +56,15 @@ def em_issued_flops(S, l, iters, nbk, split):
     32-window pair of a sequence (partial pairs padded), 2 ceil(MT/2) E-step
     MFMAs in each of iters + 1 E-steps and MT M-step MFMAs in each of iters
     M-steps, MT = ceil(l/4), each 16x16x32 (16 384 FLOPs), doubled by the
-    split halves; models padded to groups of 16."""
+    split halves except the last E-step k-block when MT is odd (its hi and
+    lo halves share one MFMA); models padded to groups of 16."""
     mt = (l + 3) // 4
     lb = (mt + 1) // 2
     pairs = sum((n - l + 1 + 31) // 32 for n in S.lens)
     groups = (nbk + 15) // 16
-    per_pair = (2 * lb * (iters + 1) + mt * iters) * (2 if split else 1)
+    e_step = 2 * (2 * lb - (mt & 1)) if split else 2 * lb
+    m_step = mt * (2 if split else 1)
+    per_pair = e_step * (iters + 1) + m_step * iters
     return float(groups) * pairs * per_pair * 16384.0
 
 
@@ -279,20 +282,22 @@ def main():
 
 def split_stages_leg(torch, P, reps=5):
     """projection_hash and bucket_select as two calls on the pass's buffers
-    (the pass runs projection_hash_select): the hash kernel's own time, for
-    its HBM roofline, and the selection with its counting pass."""
-    out = {}
-    for name, fn in (("hash", P.hash), ("select", P.select)):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        out[name] = round(e0.elapsed_time(e1) / reps, 4)
-    return out
+    (the pass runs projection_hash_select), in turn as a pass would make them:
+    the hash kernel's own time, for its HBM roofline, and the selection with
+    its counting pass."""
+    P.hash()
+    P.select()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+    for e in ev:
+        e[0].record()
+        P.hash()
+        e[1].record()
+        P.select()
+        e[2].record()
+    torch.cuda.synchronize()
+    return {"hash": round(sum(e[0].elapsed_time(e[1]) for e in ev) / reps, 4),
+            "select": round(sum(e[1].elapsed_time(e[2]) for e in ev) / reps, 4)}
 
 
 def fused_select_leg(torch, pm, P, l, k, s, m, nbk, nmem, reps=5):
