@@ -4,15 +4,16 @@
 // one (Sec. 6, quadratic work) to avoid a |Sigma|^k table.  On MI355X the dense
 // counts already sit in HBM (the histogram of projection_hash), so selection
 // reads them once: a counting pass per trial writes the number of passing
-// bins, their total size and a bitmap of the passing keys (one bit per key).
-// After a scan of the per-trial totals, one workgroup per trial loads its
-// bitmap into LDS, gathers the counts of the passing keys only, scans them
-// into bucket numbers and first member slots, and places the member windows
-// in window order.  A trial of few members lists its passing windows per wave
-// quarter in LDS and places them from the lists; otherwise a stable counting
-// sort goes over the windows in chunks, each wave grouping its passing
-// windows by key (by a sort across the wave when many pass), every bucket
-// keeping its next free slot per wave in LDS.
+// bins, their total size and a bitmap of the passing keys (one bit per key);
+// projection_hash_select has its hash kernel write these instead.  After a
+// scan of the per-trial totals, one workgroup per trial loads its bitmap into
+// LDS, gathers the counts of the passing keys only, scans them into bucket
+// numbers and first member slots, and places the member windows in window
+// order.  A trial of few members lists its passing windows per wave quarter
+// in LDS and places them from the lists; otherwise a stable counting sort
+// goes over the windows in chunks: per-wave counts by LDS atomics, then each
+// wave groups its passing windows by key (by ballots over the key bits when
+// many pass), every bucket keeping its next free slot per wave in LDS.
 #include <algorithm>
 
 #include "pm_common.h"
@@ -276,7 +277,7 @@ __device__ void block_excl_scan(uint32_t *v, int n, uint32_t *tmp)
 // ---------------------------------------------------------------- members
 constexpr int kSelU = 8;                   // window loads in flight per lane
 constexpr int kSelChunk = 4 * 64 * kSelU;  // windows per workgroup step
-constexpr int kSelSortMin = 6;             // flagged lanes from which a wave groups by sorting
+constexpr int kSelBitsMin = 6;             // flagged lanes from which a wave groups by key bits
 constexpr uint32_t kNoSlot = 0xffffffffu;
 constexpr int kSelListCap = 256;           // passing windows each wave may list in a trial of few members
 
@@ -286,16 +287,18 @@ struct Group {
     uint32_t n;     // lanes holding the key (set at the head)
 };
 
-// Groups the flagged lanes of a wave by key (keys below 2^26 - 1).  With few
-// flagged lanes, one ballot per distinct key; with many, a bitonic sort of
-// (key, lane) across the wave, run heads and run ends by scans, and the
-// results pushed back to the lanes they belong to.  Both give the same answer.
-__device__ __forceinline__ Group group_by_key(bool flag, uint32_t key)
+// Groups the flagged lanes of a wave by key (keys below 2^nbits).  With few
+// flagged lanes, one ballot per distinct key; with many, each lane's peers
+// (the flagged lanes holding its key) as the AND, over the nbits bits of the
+// key, of the lanes that agree with it on that bit: VALU and scalar work only,
+// where a sort across the wave was a chain of dependent cross-lane moves.
+// Both give the same answer.
+__device__ __forceinline__ Group group_by_key(bool flag, uint32_t key, int nbits)
 {
     const int lane = lane_id();
     const uint64_t bal = __ballot(flag);
     Group g{lane, 0u, 0u};
-    if (__popcll(bal) < kSelSortMin) {
+    if (__popcll(bal) < kSelBitsMin) {
         uint64_t left = bal;
         while (left) {
             const int leader = __ffsll((unsigned long long)left) - 1;
@@ -310,46 +313,16 @@ __device__ __forceinline__ Group group_by_key(bool flag, uint32_t key)
         }
         return g;
     }
-    constexpr uint32_t kNoKey = 0x3ffffffu;  // sorts after every key
-    uint32_t v = ((flag ? key : kNoKey) << 6) | (uint32_t)lane;
-#pragma unroll
-    for (int kk = 2; kk <= 64; kk <<= 1)
-#pragma unroll
-        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            const uint32_t o = __shfl_xor(v, jj);
-            const bool keep_min = ((lane & jj) == 0) == ((lane & kk) == 0);
-            v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
-        }
-    // position `lane` of the sorted order holds (key, original lane); equal
-    // keys are in lane order, flagged lanes first
-    const uint32_t sk = v >> 6;
-    const uint32_t prev = __shfl_up(v, 1);
-    const bool head = sk != kNoKey && (lane == 0 || (prev >> 6) != sk);
-    int hp = head ? lane : 0;  // the run's head: last head at or before this position
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(hp, o);
-        if (lane >= o) hp = t > hp ? t : hp;
+    uint64_t peers = bal;
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (key >> b) & 1u;
+        const uint64_t on = __ballot(bit);
+        peers &= bit ? on : ~on;
     }
-    int nx = head ? lane : 64;  // first head at or after this position
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_down(nx, o);
-        if (lane + o < 64) nx = t < nx ? t : nx;
-    }
-    int after = __shfl_down(nx, 1);
-    if (lane == 63) after = 64;
-    const int nflag = __popcll(bal);
-    const int end = after < nflag ? after : nflag;
-    const uint32_t orig = v & 63u;
-    const uint32_t head_orig = (uint32_t)__shfl((int)orig, hp);
-    const uint32_t pack = (uint32_t)(lane - hp) | (head_orig << 8) | ((uint32_t)(head ? end - lane : 0) << 16);
-    // the sorted order is a permutation of the lanes: every lane receives one value
-    const uint32_t got = (uint32_t)__builtin_amdgcn_ds_permute((int)(orig << 2), (int)pack);
     if (flag) {
-        g.rank = got & 0xffu;
-        g.head = (int)((got >> 8) & 0xffu);
-        g.n = got >> 16;
+        g.head = __ffsll((unsigned long long)peers) - 1;
+        g.rank = (uint32_t)__popcll(peers & lanemask_lt());
+        g.n = (uint32_t)__popcll(peers);
     }
     return g;
 }
@@ -488,6 +461,7 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
     // the bitmap as 32-bit words (little-endian halves of the 64-bit ones)
     const uint32_t *bm32 = reinterpret_cast<const uint32_t *>(bm);
     const uint32_t nb32 = (uint32_t)nb;
+    const int nbits = 32 - __builtin_clz(nb32 - 1u);  // key bits (|Sigma|^k >= 4)
     auto passing = [&](uint32_t key) { return key < nb32 && ((bm32[key >> 5] >> (key & 31u)) & 1u); };
 
     if (in_lds && a.ws.ms[j] <= 4 * kSelListCap) {
@@ -542,7 +516,7 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
                     const uint32_t q = (e >= e1) + (e >= e2) + (e >= e3);
                     const uint32_t at = q * cap + e - (q == 0 ? 0u : q == 1 ? e1 : q == 2 ? e2 : e3);
                     const uint32_t w = valid ? lw[at] : 0u, key = valid ? lk[at] : 0u;
-                    const Group g = group_by_key(valid, key);
+                    const Group g = group_by_key(valid, key, nbits);
                     uint32_t old = kNoSlot;
                     if (valid && g.head == lane) {
                         const uint32_t bi = local_bucket(bm, wcnt, key);
@@ -600,13 +574,10 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
             }
             if (!__syncthreads_or(fl != 0u)) continue;
             if (wv < 3) {
+                // counts only: one LDS atomic per member, no grouping
 #pragma unroll
-                for (int u = 0; u < kSelU; ++u) {
-                    const bool f = (fl >> u) & 1u;
-                    if (__ballot(f) == 0ull) continue;
-                    const Group g = group_by_key(f, kk[u]);
-                    if (f && g.head == lane) rows[(wv + 1) * cb + local_bucket(bm, wcnt, kk[u])] += g.n;
-                }
+                for (int u = 0; u < kSelU; ++u)
+                    if ((fl >> u) & 1u) atomicAdd(rows + (wv + 1) * cb + local_bucket(bm, wcnt, kk[u]), 1u);
             }
             __syncthreads();
             for (int64_t bi = tid; bi < ne; bi += 256) {
@@ -621,7 +592,7 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
             for (int u = 0; u < kSelU; ++u) {
                 const bool f = (fl >> u) & 1u;
                 if (__ballot(f) == 0ull) continue;
-                const Group g = group_by_key(f, kk[u]);
+                const Group g = group_by_key(f, kk[u], nbits);
                 uint32_t old = kNoSlot;
                 if (f && g.head == lane) {
                     const uint32_t bi = local_bucket(bm, wcnt, kk[u]);
@@ -665,7 +636,7 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
                     const int64_t w = wb + 64 * u + lane;
                     const bool f = w < hi && passing(kk[u]);
                     if (__ballot(f) == 0ull) continue;
-                    const Group g = group_by_key(f, kk[u]);
+                    const Group g = group_by_key(f, kk[u], nbits);
                     uint32_t old = kNoSlot;
                     if (f && g.head == lane) {
                         const int64_t b = bbase + local_bucket(bm, wcnt, kk[u]);
