@@ -84,7 +84,7 @@ struct SelArgs {
     uint32_t *status;
     SelWs ws;
     int64_t nb, cap_b, cap_m;
-    int64_t take_hi;  // k_sel_emit: trials with 0 < buckets <= take_hi
+    int64_t take_lo, take_hi;  // the trials a launch takes: take_lo < buckets <= take_hi
     int32_t m;                 // trials (items)
     uint32_t s;
     int nwb;    // bitmap words, ceil(nb / 64)
@@ -539,6 +539,68 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
         for (int64_t bi = tid; bi < ne; bi += 256) rows[cb + bi] = rows[2 * cb + bi] = rows[3 * cb + bi] = 0u;
         __syncthreads();
     }
+    if (in_lds && ne > kSelChunk / 2) {
+        // more buckets than half a chunk's windows: two sweeps over them per
+        // chunk would cost more than the chunk, so the trial goes by quarters
+        // (wave q owns the q-th quarter of its windows): waves 0-2 count their
+        // members per bucket into rows 1-3 with LDS atomics, one sweep turns
+        // rows 0-3 into each wave's first slot, and every wave places its
+        // quarter (the keys are read twice)
+        const int64_t lo = x * wv / 4, hi = x * (wv + 1) / 4;
+        if (wv < 3) {
+            for (int64_t wb = lo; wb < hi; wb += 64 * kSelU) {
+                uint32_t kk[kSelU];
+#pragma unroll
+                for (int u = 0; u < kSelU; ++u) {
+                    const int64_t w = wb + 64 * u + lane;
+                    kk[u] = w < hi ? kj[w] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < kSelU; ++u)
+                    if (wb + 64 * u + lane < hi && passing(kk[u]))
+                        atomicAdd(rows + (wv + 1) * cb + local_bucket(bm, wcnt, kk[u]), 1u);
+            }
+        }
+        __syncthreads();
+        for (int64_t bi = tid; bi < ne; bi += 256) {
+            const uint32_t r1 = rows[bi] + rows[cb + bi];
+            const uint32_t r2 = r1 + rows[2 * cb + bi];
+            rows[cb + bi] = r1;
+            rows[2 * cb + bi] = r2;
+            rows[3 * cb + bi] += r2;
+        }
+        __syncthreads();
+        for (int64_t wb = lo; wb < hi; wb += 64 * kSelU) {
+            uint32_t kk[kSelU];
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u) {
+                const int64_t w = wb + 64 * u + lane;
+                kk[u] = w < hi ? kj[w] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u) {
+                const int64_t w = wb + 64 * u + lane;
+                const bool f = w < hi && passing(kk[u]);
+                if (__ballot(f) == 0ull) continue;
+                const Group g = group_by_key(f, kk[u], nbits);
+                uint32_t old = kNoSlot;
+                if (f && g.head == lane) {
+                    const uint32_t bi = local_bucket(bm, wcnt, kk[u]);
+                    if (bbase + bi < a.cap_b) {
+                        uint32_t *r = rows + wv * cb + bi;
+                        old = *r;
+                        *r = old + g.n;
+                    }
+                }
+                old = __shfl(old, g.head);
+                if (f && old != kNoSlot) {
+                    const int64_t slot = mbase + old + g.rank;
+                    if (slot < a.cap_m) a.members[slot] = (uint32_t)w;
+                }
+            }
+        }
+        return;
+    }
     if (in_lds) {
         // chunks of 2048 windows, wave q owning the q-th quarter of each: rows
         // 1-3 count the members of waves 0-2 per bucket, a sweep turns rows
@@ -680,12 +742,12 @@ __global__ void __launch_bounds__(256) k_sel_emit(const SelArgs a)
     __shared__ uint32_t tmp[256];
     const int j = blockIdx.x;
     const int64_t ne = a.ws.ne[j];
-    if (ne == 0 || ne > a.take_hi) return;
+    if (ne <= a.take_lo || ne > a.take_hi) return;
     emit_trial(a, j, ne, bm, tmp);
 }
 
 // the trials with more buckets than that, listed by the scan; a fixed grid
-// of workgroups takes them in turn
+// of workgroups takes those of the launch's range in turn
 __global__ void __launch_bounds__(256) k_sel_emit_heavy(const SelArgs a)
 {
     extern __shared__ __align__(16) uint64_t bm[];
@@ -693,7 +755,9 @@ __global__ void __launch_bounds__(256) k_sel_emit_heavy(const SelArgs a)
     const int64_t nh = *a.ws.n_heavy;
     for (int64_t i = blockIdx.x; i < nh; i += gridDim.x) {
         const int j = a.ws.heavy[i];
-        emit_trial(a, j, a.ws.ne[j], bm, tmp);
+        const int64_t ne = a.ws.ne[j];
+        if (ne <= a.take_lo || ne > a.take_hi) continue;  // uniform over the workgroup
+        emit_trial(a, j, ne, bm, tmp);
         __syncthreads();
     }
 }
@@ -858,16 +922,31 @@ static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st, bool counted
         (void)hipGetLastError();  // an unsupported attribute must not poison the launch check
         attr = true;
     }
+    a.take_lo = 0;
     a.take_hi = cb_a;
     a.cb = (int)cb_a;
     hipLaunchKernelGGL(k_sel_emit, dim3(a.m), dim3(256), sel_emit_lds(nwb, cb_a), st, a);
     PM_LAUNCHED();
     if (heavy) {
-        const int64_t cb_b = std::max<int64_t>(cb_a, std::min<int64_t>(ne_bound, fit));
-        a.cb = (int)cb_b;
-        const int grid = std::min<int32_t>(a.m, 1024);
-        hipLaunchKernelGGL(k_sel_emit_heavy, dim3(grid), dim3(256), sel_emit_lds(nwb, cb_b), st, a);
-        PM_LAUNCHED();
+        // the heavy trials in tiers of LDS rows sized for four, two and one
+        // workgroups per CU (the fewer rows, the more workgroups hide each
+        // other's latency); the last tier also takes the trials beyond every
+        // LDS row count, with device-memory cursors
+        int64_t lo = cb_a;
+        for (const int per_cu : {4, 2, 1}) {
+            int64_t cb = (lds_max / per_cu - 2048 - 16 * nwb) / 16;  // 1 KB static LDS, 1 KB headroom
+            if (per_cu == 1) cb = std::max<int64_t>(lo, std::min<int64_t>(ne_bound, fit));
+            else if (cb <= lo) continue;
+            cb = std::min<int64_t>(cb, std::max<int64_t>(lo, ne_bound));
+            a.cb = (int)cb;
+            a.take_lo = lo;
+            a.take_hi = per_cu == 1 ? INT64_MAX : cb;
+            const int grid = std::min<int32_t>(a.m, 1024);
+            hipLaunchKernelGGL(k_sel_emit_heavy, dim3(grid), dim3(256), sel_emit_lds(nwb, cb), st, a);
+            PM_LAUNCHED();
+            lo = cb;
+            if (lo >= ne_bound) break;  // no trial has more buckets
+        }
     }
     return PM_OK;
 }

@@ -2,13 +2,15 @@
 placement, against the CPU oracle (Alg. 2 step 3; Sec. 6's threshold s).
 
 The selection keeps each trial's member cursors in LDS when its buckets fit
-there (a first launch with a small LDS footprint), in a second launch with
-all the LDS the device gives for trials with more buckets, and in device
-memory beyond that; windows go by in chunks of 2048, and a wave groups its
-passing windows by key with ballots when few pass and with a sort across
-the wave when many do.  Bucket lists and members must match the oracle bit
-for bit in every form, also truncated to a capacity and in a batch whose
-instances take different forms.
+there (a first launch with a small LDS footprint), in further launches with
+LDS rows for four, two and one workgroups per CU for trials with more
+buckets, and in device memory beyond that; windows go by in chunks of 2048,
+or by wave quarters in two passes when a trial has more buckets than half a
+chunk's windows, and a wave groups its passing windows by key with one
+ballot per key when few pass and with ballots over the key bits when many
+do.  Bucket lists and members must match the oracle bit for bit in every
+form, also truncated to a capacity and in a batch whose instances take
+different forms.
 """
 import sys
 import zlib
@@ -78,6 +80,10 @@ CASES = [
     ("many passing, device-memory rows", 4, 10, 3500, 12, 7, 1, 2),
     ("protein, second launch, LDS rows", 20, 10, 2000, 8, 3, 1, 2),
     ("protein k=4, few passing", 20, 12, 1500, 10, 4, 3, 3),
+    # more buckets than the first launch takes, few enough for the heavy
+    # tier whose LDS rows let four workgroups share a CU
+    ("tier of four workgroups per CU", 4, 6, 1500, 12, 6, 3, 3),
+    ("tier of four workgroups per CU, protein", 20, 6, 1500, 8, 3, 2, 3),
 ]
 
 
