@@ -637,8 +637,9 @@ def c3_full_leg(torch, pm, m=1000, chunk=250, count=512, seed=1):
     instance: per shape class (motif length), the trials in chunks of
     `chunk` per instance through key and count buffers reused from chunk to
     chunk; every chunk hashed (keys + dense counts), its enriched buckets
-    selected from them, and the same trials through the fused selection
-    (keys and counts kept on chip).  Times on the launch stream; hash bytes
+    selected from them, the same trials through the fused selection (keys
+    and counts kept on chip), and through projection_hash_select (keys and
+    counts written, the selection's bitmap formed by the hash kernel).  Times on the launch stream; hash bytes
     algorithmic (4 B per key, 4 B per count bin)."""
     from synth import batch_config
     insts = batch_config(seed, count=count, m=m)
@@ -665,7 +666,7 @@ def c3_full_leg(torch, pm, m=1000, chunk=250, count=512, seed=1):
     n_out = torch.zeros(2, dtype=torch.int64, device="cuda")
     bk = torch.empty((1, 4), dtype=torch.int32, device="cuda")
     mem = torch.empty(1, dtype=torch.int32, device="cuda")
-    t_hash = t_sel = t_fused = 0.0
+    t_hash = t_sel = t_fused = t_one = 0.0
     nbytes = lmers = 0.0
     nbk_tot = nmem_tot = 0
     for l, meta, group in plans:
@@ -697,10 +698,13 @@ def c3_full_leg(torch, pm, m=1000, chunk=250, count=512, seed=1):
             e[3].record()
             pm.bucket_hash_select_batch(B, B.masks, s, bk, nbk, mem, nmem, n_out, hw, hws, status)
             e[4].record()
+            pm.projection_hash_select_batch(B, B.masks, keys, counts, s, bk, nbk, mem, nmem, n_out, ws, sws, status)
+            e[5].record()
             torch.cuda.synchronize()
             t_hash += e[0].elapsed_time(e[1])
             t_sel += e[1].elapsed_time(e[2])
             t_fused += e[3].elapsed_time(e[4])
+            t_one += e[4].elapsed_time(e[5])
             nbytes += 4.0 * B.keys_total + 4.0 * B.items * nb
             lmers += float(sum(B.x[p] * B.m[p] for p in range(B.P)))
             nbk_tot += nbk
@@ -716,12 +720,14 @@ def c3_full_leg(torch, pm, m=1000, chunk=250, count=512, seed=1):
                         f"trials in chunks of {chunk} per instance through reused key/count buffers",
             "projected_lmers": lmers, "enriched_buckets": nbk_tot, "members": nmem_tot,
             "hash_ms": round(t_hash, 2), "select_ms": round(t_sel, 2), "fused_select_ms": round(t_fused, 2),
+            "hash_then_select_one_call_ms": round(t_one, 2),
             "roofline_hash": {"kernel": "k_hash<4,k,*> (11 classes)", "bound": "hbm", "achieved": round(gbs, 2),
                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                               "traffic": None, "bytes": nbytes},
             "lmers_per_s_hash": round(lmers / (t_hash / 1e3), 1),
             "lmers_per_s_hash_and_select": round(lmers / ((t_hash + t_sel) / 1e3), 1),
-            "lmers_per_s_fused_select": round(lmers / (t_fused / 1e3), 1)}
+            "lmers_per_s_fused_select": round(lmers / (t_fused / 1e3), 1),
+            "lmers_per_s_hash_then_select_one_call": round(lmers / (t_one / 1e3), 1)}
 
 
 def perf_coefficient(starts, sites, l):

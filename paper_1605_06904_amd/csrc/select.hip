@@ -30,7 +30,8 @@ struct SelWs {
     int64_t *nep;     // [m][parts] buckets of each part of a trial's bins (parts > 1)
     int64_t *msp;     // [m][parts] their members
     uint64_t *bits;   // [m][nwb] passing keys: bit key % 64 of word key / 64
-    uint32_t *rows;   // [cap_b][4] member cursors of trials with more buckets than the LDS holds
+    uint32_t *rows;   // [cap_b][4]: word 0 the first member slot of each bucket of trials with
+                      // more buckets than the LDS rows hold
 };
 
 // parts of a trial's bins counted by separate workgroups: enough workgroups
@@ -335,8 +336,9 @@ __device__ __forceinline__ uint32_t local_bucket(const uint64_t *bm, const uint3
 }
 
 // Bucket records and member lists of trial j, which has ne > 0 passing keys,
-// by one workgroup of four waves.  Member cursors: rows[q][bucket] in LDS
-// when ne <= cb, else ws.rows[bucket][q] in device memory.
+// by one workgroup of four waves.  Member cursors: rows[q][bucket] in LDS,
+// for ranges of cb buckets at a time when ne > cb (their first slots kept in
+// ws.rows[bucket][0] meanwhile).
 __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, uint32_t *tmp)
 {
     uint32_t *wcnt = reinterpret_cast<uint32_t *>(bm + a.nwb);  // [nwb] -> buckets before the word
@@ -441,17 +443,13 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
                         rows[bi] = frel;
                         rows[cb + bi] = rows[2 * cb + bi] = rows[3 * cb + bi] = 0u;
                     } else if (b < a.cap_b) {
-                        uint32_t *r = a.ws.rows + 4 * b;
-                        st_agent(r, frel);
-                        st_agent(r + 1, 0u);
-                        st_agent(r + 2, 0u);
-                        st_agent(r + 3, 0u);
+                        st_agent(a.ws.rows + 4 * b, frel);  // read back range by range below
                     }
                 }
             }
         }
     }
-    // device-memory cursors: the stores above are done before any wave's atomics
+    // first slots in device memory: the stores above are done before any wave reads them
     if (!in_lds) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
@@ -539,15 +537,52 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
         for (int64_t bi = tid; bi < ne; bi += 256) rows[cb + bi] = rows[2 * cb + bi] = rows[3 * cb + bi] = 0u;
         __syncthreads();
     }
-    if (in_lds && ne > kSelChunk / 2) {
-        // more buckets than half a chunk's windows: two sweeps over them per
-        // chunk would cost more than the chunk, so the trial goes by quarters
-        // (wave q owns the q-th quarter of its windows): waves 0-2 count their
-        // members per bucket into rows 1-3 with LDS atomics, one sweep turns
-        // rows 0-3 into each wave's first slot, and every wave places its
-        // quarter (the keys are read twice)
+    if (!in_lds || ne > kSelChunk / 2) {
+        // more buckets than half a chunk's windows (two sweeps over them per
+        // chunk would cost more than the chunk), or more than the LDS rows
+        // hold: the trial goes by quarters (wave q owns the q-th quarter of
+        // its windows) and, past the LDS rows, by ranges of cb buckets, each
+        // range taking two passes over all the windows: waves 0-2 count the
+        // members of the range's buckets into rows 1-3 with LDS atomics, one
+        // sweep turns rows 0-3 into each wave's first slot, and every wave
+        // places its quarter's members of the range
         const int64_t lo = x * wv / 4, hi = x * (wv + 1) / 4;
-        if (wv < 3) {
+        for (int64_t r0 = 0; r0 < ne; r0 += cb) {
+            const uint32_t nr = (uint32_t)std::min<int64_t>(cb, ne - r0);
+            if (!in_lds) {
+                // the range's first slots (written with the records), cursors cleared
+                for (int64_t bi = tid; bi < nr; bi += 256) {
+                    const int64_t b = bbase + r0 + bi;
+                    rows[bi] = b < a.cap_b ? ld_agent(a.ws.rows + 4 * b) : 0u;
+                    rows[cb + bi] = rows[2 * cb + bi] = rows[3 * cb + bi] = 0u;
+                }
+                __syncthreads();
+            }
+            if (wv < 3) {
+                for (int64_t wb = lo; wb < hi; wb += 64 * kSelU) {
+                    uint32_t kk[kSelU];
+#pragma unroll
+                    for (int u = 0; u < kSelU; ++u) {
+                        const int64_t w = wb + 64 * u + lane;
+                        kk[u] = w < hi ? kj[w] : 0u;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kSelU; ++u)
+                        if (wb + 64 * u + lane < hi && passing(kk[u])) {
+                            const uint32_t bi = local_bucket(bm, wcnt, kk[u]) - (uint32_t)r0;
+                            if (bi < nr) atomicAdd(rows + (wv + 1) * cb + bi, 1u);
+                        }
+                }
+            }
+            __syncthreads();
+            for (int64_t bi = tid; bi < nr; bi += 256) {
+                const uint32_t r1 = rows[bi] + rows[cb + bi];
+                const uint32_t r2 = r1 + rows[2 * cb + bi];
+                rows[cb + bi] = r1;
+                rows[2 * cb + bi] = r2;
+                rows[3 * cb + bi] += r2;
+            }
+            __syncthreads();
             for (int64_t wb = lo; wb < hi; wb += 64 * kSelU) {
                 uint32_t kk[kSelU];
 #pragma unroll
@@ -556,48 +591,27 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
                     kk[u] = w < hi ? kj[w] : 0u;
                 }
 #pragma unroll
-                for (int u = 0; u < kSelU; ++u)
-                    if (wb + 64 * u + lane < hi && passing(kk[u]))
-                        atomicAdd(rows + (wv + 1) * cb + local_bucket(bm, wcnt, kk[u]), 1u);
-            }
-        }
-        __syncthreads();
-        for (int64_t bi = tid; bi < ne; bi += 256) {
-            const uint32_t r1 = rows[bi] + rows[cb + bi];
-            const uint32_t r2 = r1 + rows[2 * cb + bi];
-            rows[cb + bi] = r1;
-            rows[2 * cb + bi] = r2;
-            rows[3 * cb + bi] += r2;
-        }
-        __syncthreads();
-        for (int64_t wb = lo; wb < hi; wb += 64 * kSelU) {
-            uint32_t kk[kSelU];
-#pragma unroll
-            for (int u = 0; u < kSelU; ++u) {
-                const int64_t w = wb + 64 * u + lane;
-                kk[u] = w < hi ? kj[w] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < kSelU; ++u) {
-                const int64_t w = wb + 64 * u + lane;
-                const bool f = w < hi && passing(kk[u]);
-                if (__ballot(f) == 0ull) continue;
-                const Group g = group_by_key(f, kk[u], nbits);
-                uint32_t old = kNoSlot;
-                if (f && g.head == lane) {
-                    const uint32_t bi = local_bucket(bm, wcnt, kk[u]);
-                    if (bbase + bi < a.cap_b) {
+                for (int u = 0; u < kSelU; ++u) {
+                    const int64_t w = wb + 64 * u + lane;
+                    uint32_t bi = 0xffffffffu;
+                    if (w < hi && passing(kk[u])) bi = local_bucket(bm, wcnt, kk[u]) - (uint32_t)r0;
+                    const bool f = bi < nr;
+                    if (__ballot(f) == 0ull) continue;
+                    const Group g = group_by_key(f, kk[u], nbits);
+                    uint32_t old = kNoSlot;
+                    if (f && g.head == lane && bbase + r0 + bi < a.cap_b) {
                         uint32_t *r = rows + wv * cb + bi;
                         old = *r;
                         *r = old + g.n;
                     }
-                }
-                old = __shfl(old, g.head);
-                if (f && old != kNoSlot) {
-                    const int64_t slot = mbase + old + g.rank;
-                    if (slot < a.cap_m) a.members[slot] = (uint32_t)w;
+                    old = __shfl(old, g.head);
+                    if (f && old != kNoSlot) {
+                        const int64_t slot = mbase + old + g.rank;
+                        if (slot < a.cap_m) a.members[slot] = (uint32_t)w;
+                    }
                 }
             }
+            __syncthreads();  // the rows are reused by the next range
         }
         return;
     }
@@ -678,60 +692,6 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
             __syncthreads();
         }
         return;
-    }
-
-    // device-memory cursors (more buckets than the LDS rows hold): wave q owns
-    // the q-th quarter of the windows; pass 0 counts, a sweep forms the first
-    // slots, pass 1 places with one returning atomic per key group
-    const int64_t lo = x * wv / 4, hi = x * (wv + 1) / 4;
-    for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1 || wv < 3) {
-            for (int64_t wb = lo; wb < hi; wb += 64 * kSelU) {
-                uint32_t kk[kSelU];
-#pragma unroll
-                for (int u = 0; u < kSelU; ++u) {
-                    const int64_t w = wb + 64 * u + lane;
-                    kk[u] = w < hi ? kj[w] : 0u;
-                }
-#pragma unroll
-                for (int u = 0; u < kSelU; ++u) {
-                    const int64_t w = wb + 64 * u + lane;
-                    const bool f = w < hi && passing(kk[u]);
-                    if (__ballot(f) == 0ull) continue;
-                    const Group g = group_by_key(f, kk[u], nbits);
-                    uint32_t old = kNoSlot;
-                    if (f && g.head == lane) {
-                        const int64_t b = bbase + local_bucket(bm, wcnt, kk[u]);
-                        if (b < a.cap_b) {
-                            if (pass == 0) atomicAdd(a.ws.rows + 4 * b + wv + 1, g.n);
-                            else old = atomicAdd(a.ws.rows + 4 * b + wv, g.n);
-                        }
-                    }
-                    if (pass == 1) {
-                        old = __shfl(old, g.head);
-                        if (f && old != kNoSlot) {
-                            const int64_t slot = mbase + old + g.rank;
-                            if (slot < a.cap_m) a.members[slot] = (uint32_t)w;
-                        }
-                    }
-                }
-            }
-        }
-        if (pass == 0) {
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            for (int64_t bi = tid; bi < ne && bbase + bi < a.cap_b; bi += 256) {
-                uint32_t *r = a.ws.rows + 4 * (bbase + bi);
-                const uint32_t r1 = ld_agent(r) + ld_agent(r + 1);
-                const uint32_t r2 = r1 + ld_agent(r + 2);
-                const uint32_t r3 = r2 + ld_agent(r + 3);
-                st_agent(r + 1, r1);
-                st_agent(r + 2, r2);
-                st_agent(r + 3, r3);
-            }
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-        }
     }
 }
 
