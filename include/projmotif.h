@@ -135,10 +135,10 @@ int pm_auto_params(int32_t alphabet, int32_t t, int64_t x, int32_t l, int32_t d,
 int projection_hash(const pm_seqs *S, int32_t l, int32_t k, const uint32_t *masks, int32_t m,
                     uint32_t *keys, uint32_t *counts, uint32_t *status, void *stream);
 
-/* Workspace bytes bucket_select needs for m trials of |Sigma|^k bins and
- * cap_buckets buckets (a per-trial bitmap of passing keys, per-trial totals
- * and per-bucket member cursors); 0 when the alphabet is not 4 or 20 or
- * |Sigma|^k exceeds 2^19. */
+/* Workspace bytes bucket_select needs for m trials of |Sigma|^k bins (a
+ * per-trial bitmap of passing keys and per-trial totals; the member cursors
+ * live in LDS, so cap_buckets does not change the size); 0 when the alphabet
+ * is not 4 or 20 or |Sigma|^k exceeds 2^19. */
 size_t pm_select_workspace(int32_t alphabet, int32_t k, int32_t m, int64_t cap_buckets);
 
 /* a5 -- Alg. 2 step 3 and Sec. 6 (a bucket passes when it holds at least s

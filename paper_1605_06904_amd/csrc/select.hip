@@ -30,8 +30,6 @@ struct SelWs {
     int64_t *nep;     // [m][parts] buckets of each part of a trial's bins (parts > 1)
     int64_t *msp;     // [m][parts] their members
     uint64_t *bits;   // [m][nwb] passing keys: bit key % 64 of word key / 64
-    uint32_t *rows;   // [cap_b][4]: word 0 the first member slot of each bucket of trials with
-                      // more buckets than the LDS rows hold
 };
 
 // parts of a trial's bins counted by separate workgroups: enough workgroups
@@ -50,9 +48,9 @@ static size_t sel_head_bytes(int32_t m, int64_t nwb)
            (size_t)m * sel_parts(m, nwb) * 2 * sizeof(int64_t);
 }
 
-static size_t sel_ws_bytes(int32_t m, int64_t nwb, int64_t cap_b)
+static size_t sel_ws_bytes(int32_t m, int64_t nwb)
 {
-    return sel_head_bytes(m, nwb) + (size_t)m * nwb * 8 + (size_t)cap_b * 4 * sizeof(uint32_t) + 256;
+    return sel_head_bytes(m, nwb) + (size_t)m * nwb * 8 + 256;
 }
 
 static SelWs carve(void *ws, int32_t m, int64_t nwb)
@@ -69,7 +67,6 @@ static SelWs carve(void *ws, int32_t m, int64_t nwb)
                                         (((size_t)m * 4 + 7) & ~(size_t)7));
     w.msp = w.nep + (int64_t)m * sel_parts(m, nwb);
     w.bits = reinterpret_cast<uint64_t *>(p + sel_head_bytes(m, nwb));
-    w.rows = reinterpret_cast<uint32_t *>(w.bits + (int64_t)m * nwb);
     return w;
 }
 
@@ -91,6 +88,7 @@ struct SelArgs {
     int nwb;    // bitmap words, ceil(nb / 64)
     int cb;     // buckets whose cursors the LDS holds
     int parts;  // k_sel_count: workgroups per trial
+    int ranges; // k_sel_emit_heavy: bucket ranges of cb per trial at most
 };
 
 // per (trial, part of its bins): number of passing bins, their total size
@@ -336,17 +334,20 @@ __device__ __forceinline__ uint32_t local_bucket(const uint64_t *bm, const uint3
 }
 
 // Bucket records and member lists of trial j, which has ne > 0 passing keys,
-// by one workgroup of four waves.  Member cursors: rows[q][bucket] in LDS,
-// for ranges of cb buckets at a time when ne > cb (their first slots kept in
-// ws.rows[bucket][0] meanwhile).
-__device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, uint32_t *tmp)
+// for its buckets r0 .. r0 + cb - 1 (all of them when ne <= cb), by one
+// workgroup of four waves.  Member cursors: rows[q][bucket - r0] in LDS.  A
+// trial with more buckets than cb is taken by several workgroups, one range
+// of buckets each, every one of them reading all of the trial's windows.
+__device__ void emit_trial(const SelArgs &a, int j, int64_t ne, int64_t r0, uint64_t *bm, uint32_t *tmp)
 {
     uint32_t *wcnt = reinterpret_cast<uint32_t *>(bm + a.nwb);  // [nwb] -> buckets before the word
     uint32_t *wsz = wcnt + a.nwb;                               // [nwb] -> members before the word
     uint32_t *rows = wsz + a.nwb;                               // [4][cb]
     const int tid = threadIdx.x, wv = tid >> 6, lane = lane_id();
     const int cb = a.cb;
-    const bool in_lds = ne <= cb;
+    const bool whole = r0 == 0 && ne <= cb;                           // one range: every bucket
+    const uint32_t nr = (uint32_t)std::min<int64_t>(cb, ne - r0);     // the range's buckets
+    const uint32_t rlo = (uint32_t)r0, rhi = rlo + nr;
     const uint32_t *cnt = a.counts + (int64_t)j * a.nb;
     const uint64_t *bits = a.ws.bits + (int64_t)j * a.nwb;
     const int64_t bbase = a.ws.bb[j], mbase = a.ws.mb[j];
@@ -409,10 +410,11 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
 
     // ---- bucket records in key order (a word's buckets are its set lanes),
     // and every bucket's cursor row: its first slot, then zeros; the counts of
-    // eight non-empty words are read at a time
+    // eight non-empty words with buckets in the range are read at a time
     for (int w0 = wv * 64; w0 < a.nwb; w0 += 256) {
         const int wi = w0 + lane;
-        uint64_t nz = __ballot(wi < a.nwb && bm[wi] != 0ull);
+        uint64_t nz = __ballot(wi < a.nwb && bm[wi] != 0ull && wcnt[wi] < rhi &&
+                               wcnt[wi] + (uint32_t)__popcll(bm[wi]) > rlo);
         while (nz) {
             constexpr int G = 8;
             int wd[G];
@@ -437,20 +439,15 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
                 const uint32_t frel = wsz[w] + wave_incl_scan(c[u]) - c[u];  // first slot within the trial
                 const uint32_t bi = wcnt[w] + (uint32_t)__popcll(wb & lanemask_lt());
                 const int64_t b = bbase + bi;
-                if (set) {
+                if (set && bi >= rlo && bi < rhi) {
                     if (b < a.cap_b) a.buckets[b] = pm_bucket{(uint32_t)j, key, c[u], (uint32_t)(mbase + frel)};
-                    if (in_lds) {
-                        rows[bi] = frel;
-                        rows[cb + bi] = rows[2 * cb + bi] = rows[3 * cb + bi] = 0u;
-                    } else if (b < a.cap_b) {
-                        st_agent(a.ws.rows + 4 * b, frel);  // read back range by range below
-                    }
+                    const uint32_t ri = bi - rlo;
+                    rows[ri] = frel;
+                    rows[cb + ri] = rows[2 * cb + ri] = rows[3 * cb + ri] = 0u;
                 }
             }
         }
     }
-    // first slots in device memory: the stores above are done before any wave reads them
-    if (!in_lds) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
     const uint32_t *kj = a.keys + I.key_base + (int64_t)(j - I.first_item) * I.x;
@@ -462,7 +459,7 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
     const int nbits = 32 - __builtin_clz(nb32 - 1u);  // key bits (|Sigma|^k >= 4)
     auto passing = [&](uint32_t key) { return key < nb32 && ((bm32[key >> 5] >> (key & 31u)) & 1u); };
 
-    if (in_lds && a.ws.ms[j] <= 4 * kSelListCap) {
+    if (whole && a.ws.ms[j] <= 4 * kSelListCap) {
         // few members: each wave lists the passing windows of its quarter of
         // the trial in order (no barrier), then one wave places the four lists,
         // which together are in window order, with the buckets' cursors (row 0)
@@ -537,85 +534,71 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, uint64_t *bm, ui
         for (int64_t bi = tid; bi < ne; bi += 256) rows[cb + bi] = rows[2 * cb + bi] = rows[3 * cb + bi] = 0u;
         __syncthreads();
     }
-    if (!in_lds || ne > kSelChunk / 2) {
+    if (!whole || ne > kSelChunk / 2) {
         // more buckets than half a chunk's windows (two sweeps over them per
-        // chunk would cost more than the chunk), or more than the LDS rows
-        // hold: the trial goes by quarters (wave q owns the q-th quarter of
-        // its windows) and, past the LDS rows, by ranges of cb buckets, each
-        // range taking two passes over all the windows: waves 0-2 count the
+        // chunk would cost more than the chunk), or a range of a trial with
+        // more buckets than the LDS rows hold: the windows go by quarters
+        // (wave q owns the q-th quarter) in two passes: waves 0-2 count the
         // members of the range's buckets into rows 1-3 with LDS atomics, one
         // sweep turns rows 0-3 into each wave's first slot, and every wave
         // places its quarter's members of the range
-        const int64_t lo = x * wv / 4, hi = x * (wv + 1) / 4;
-        for (int64_t r0 = 0; r0 < ne; r0 += cb) {
-            const uint32_t nr = (uint32_t)std::min<int64_t>(cb, ne - r0);
-            if (!in_lds) {
-                // the range's first slots (written with the records), cursors cleared
-                for (int64_t bi = tid; bi < nr; bi += 256) {
-                    const int64_t b = bbase + r0 + bi;
-                    rows[bi] = b < a.cap_b ? ld_agent(a.ws.rows + 4 * b) : 0u;
-                    rows[cb + bi] = rows[2 * cb + bi] = rows[3 * cb + bi] = 0u;
-                }
-                __syncthreads();
-            }
-            if (wv < 3) {
-                for (int64_t wb = lo; wb < hi; wb += 64 * kSelU) {
-                    uint32_t kk[kSelU];
-#pragma unroll
-                    for (int u = 0; u < kSelU; ++u) {
-                        const int64_t w = wb + 64 * u + lane;
-                        kk[u] = w < hi ? kj[w] : 0u;
-                    }
-#pragma unroll
-                    for (int u = 0; u < kSelU; ++u)
-                        if (wb + 64 * u + lane < hi && passing(kk[u])) {
-                            const uint32_t bi = local_bucket(bm, wcnt, kk[u]) - (uint32_t)r0;
-                            if (bi < nr) atomicAdd(rows + (wv + 1) * cb + bi, 1u);
-                        }
-                }
-            }
-            __syncthreads();
-            for (int64_t bi = tid; bi < nr; bi += 256) {
-                const uint32_t r1 = rows[bi] + rows[cb + bi];
-                const uint32_t r2 = r1 + rows[2 * cb + bi];
-                rows[cb + bi] = r1;
-                rows[2 * cb + bi] = r2;
-                rows[3 * cb + bi] += r2;
-            }
-            __syncthreads();
-            for (int64_t wb = lo; wb < hi; wb += 64 * kSelU) {
+        const uint32_t lo = (uint32_t)(x * wv / 4), hi = (uint32_t)(x * (wv + 1) / 4);  // x < 2^32
+        if (wv < 3) {
+            for (uint32_t wb = lo; wb < hi; wb += 64 * kSelU) {
                 uint32_t kk[kSelU];
 #pragma unroll
                 for (int u = 0; u < kSelU; ++u) {
-                    const int64_t w = wb + 64 * u + lane;
+                    const uint32_t w = wb + 64 * u + lane;
                     kk[u] = w < hi ? kj[w] : 0u;
                 }
 #pragma unroll
-                for (int u = 0; u < kSelU; ++u) {
-                    const int64_t w = wb + 64 * u + lane;
-                    uint32_t bi = 0xffffffffu;
-                    if (w < hi && passing(kk[u])) bi = local_bucket(bm, wcnt, kk[u]) - (uint32_t)r0;
-                    const bool f = bi < nr;
-                    if (__ballot(f) == 0ull) continue;
-                    const Group g = group_by_key(f, kk[u], nbits);
-                    uint32_t old = kNoSlot;
-                    if (f && g.head == lane && bbase + r0 + bi < a.cap_b) {
-                        uint32_t *r = rows + wv * cb + bi;
-                        old = *r;
-                        *r = old + g.n;
+                for (int u = 0; u < kSelU; ++u)
+                    if (wb + 64 * u + lane < hi && passing(kk[u])) {
+                        const uint32_t ri = local_bucket(bm, wcnt, kk[u]) - rlo;
+                        if (ri < nr) atomicAdd(rows + (wv + 1) * cb + ri, 1u);
                     }
-                    old = __shfl(old, g.head);
-                    if (f && old != kNoSlot) {
-                        const int64_t slot = mbase + old + g.rank;
-                        if (slot < a.cap_m) a.members[slot] = (uint32_t)w;
-                    }
+            }
+        }
+        __syncthreads();
+        for (uint32_t ri = tid; ri < nr; ri += 256) {
+            const uint32_t r1 = rows[ri] + rows[cb + ri];
+            const uint32_t r2 = r1 + rows[2 * cb + ri];
+            rows[cb + ri] = r1;
+            rows[2 * cb + ri] = r2;
+            rows[3 * cb + ri] += r2;
+        }
+        __syncthreads();
+        for (uint32_t wb = lo; wb < hi; wb += 64 * kSelU) {
+            uint32_t kk[kSelU];
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u) {
+                const uint32_t w = wb + 64 * u + lane;
+                kk[u] = w < hi ? kj[w] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u) {
+                const uint32_t w = wb + 64 * u + lane;
+                uint32_t ri = 0xffffffffu;
+                if (w < hi && passing(kk[u])) ri = local_bucket(bm, wcnt, kk[u]) - rlo;
+                const bool f = ri < nr;
+                if (__ballot(f) == 0ull) continue;
+                const Group g = group_by_key(f, kk[u], nbits);
+                uint32_t old = kNoSlot;
+                if (f && g.head == lane && bbase + rlo + ri < a.cap_b) {
+                    uint32_t *r = rows + wv * cb + ri;
+                    old = *r;
+                    *r = old + g.n;
+                }
+                old = __shfl(old, g.head);
+                if (f && old != kNoSlot) {
+                    const int64_t slot = mbase + old + g.rank;
+                    if (slot < a.cap_m) a.members[slot] = w;
                 }
             }
-            __syncthreads();  // the rows are reused by the next range
         }
         return;
     }
-    if (in_lds) {
+    {
         // chunks of 2048 windows, wave q owning the q-th quarter of each: rows
         // 1-3 count the members of waves 0-2 per bucket, a sweep turns rows
         // 0-3 into each wave's first slot, the waves place their members, and
@@ -703,21 +686,23 @@ __global__ void __launch_bounds__(256) k_sel_emit(const SelArgs a)
     const int j = blockIdx.x;
     const int64_t ne = a.ws.ne[j];
     if (ne <= a.take_lo || ne > a.take_hi) return;
-    emit_trial(a, j, ne, bm, tmp);
+    emit_trial(a, j, ne, 0, bm, tmp);
 }
 
 // the trials with more buckets than that, listed by the scan; a fixed grid
-// of workgroups takes those of the launch's range in turn
+// of workgroups takes the (range of cb buckets, trial) units of the trials in
+// the launch's range of bucket counts in turn, range-major (so that the
+// trials' first ranges, which every trial has, spread over all workgroups)
 __global__ void __launch_bounds__(256) k_sel_emit_heavy(const SelArgs a)
 {
     extern __shared__ __align__(16) uint64_t bm[];
     __shared__ uint32_t tmp[256];
-    const int64_t nh = *a.ws.n_heavy;
-    for (int64_t i = blockIdx.x; i < nh; i += gridDim.x) {
-        const int j = a.ws.heavy[i];
-        const int64_t ne = a.ws.ne[j];
-        if (ne <= a.take_lo || ne > a.take_hi) continue;  // uniform over the workgroup
-        emit_trial(a, j, ne, bm, tmp);
+    const int64_t nh = *a.ws.n_heavy, nu = nh * a.ranges;
+    for (int64_t un = blockIdx.x; un < nu; un += gridDim.x) {
+        const int j = a.ws.heavy[un % nh];
+        const int64_t ne = a.ws.ne[j], r0 = (un / nh) * (int64_t)a.cb;
+        if (ne <= a.take_lo || ne > a.take_hi || r0 >= ne) continue;  // uniform over the workgroup
+        emit_trial(a, j, ne, r0, bm, tmp);
         __syncthreads();
     }
 }
@@ -830,7 +815,7 @@ extern "C" size_t pm_select_workspace(int32_t alphabet, int32_t k, int32_t m, in
 {
     const int64_t nb = sel_bins(alphabet, k);
     if (nb < 0 || m < 0 || cap_buckets < 0) return 0;
-    return sel_ws_bytes(m, (nb + 63) / 64, cap_buckets);
+    return sel_ws_bytes(m, (nb + 63) / 64);  // member cursors live in LDS: no per-bucket space
 }
 
 // dynamic LDS of the emit kernels: bitmap, word scans, cursor row 0, then
@@ -901,6 +886,8 @@ static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st, bool counted
             a.cb = (int)cb;
             a.take_lo = lo;
             a.take_hi = per_cu == 1 ? INT64_MAX : cb;
+            // only the last tier has trials with more buckets than its rows
+            a.ranges = per_cu == 1 ? (int)((std::max<int64_t>(ne_bound, cb) + cb - 1) / cb) : 1;
             const int grid = std::min<int32_t>(a.m, 1024);
             hipLaunchKernelGGL(k_sel_emit_heavy, dim3(grid), dim3(256), sel_emit_lds(nwb, cb), st, a);
             PM_LAUNCHED();

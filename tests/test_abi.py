@@ -111,7 +111,7 @@ def test_other_entry_points_validate():
     # selection workspace: per-trial totals and bitmap of |Sigma|^k / 64 words,
     # per-bucket cursors; 0 outside the count-table range (|Sigma|^k <= 2^19)
     assert pm.pm_select_workspace(4, 9, 10, 100) > pm.pm_select_workspace(4, 8, 10, 100) > 0
-    assert pm.pm_select_workspace(4, 8, 10, 200) - pm.pm_select_workspace(4, 8, 10, 100) == 100 * 16
+    assert pm.pm_select_workspace(4, 8, 10, 200) == pm.pm_select_workspace(4, 8, 10, 100)  # cursors in LDS
     assert pm.pm_select_workspace(4, 10, 10, 100) == 0
     assert pm.pm_select_workspace(20, 5, 10, 100) == 0
     assert pm.pm_select_workspace(20, 4, 10, 100) > 0

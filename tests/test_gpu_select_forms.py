@@ -4,9 +4,9 @@ placement, against the CPU oracle (Alg. 2 step 3; Sec. 6's threshold s).
 The selection keeps each trial's member cursors in LDS when its buckets fit
 there (a first launch with a small LDS footprint), in further launches with
 LDS rows for four, two and one workgroups per CU for trials with more
-buckets, and in device memory beyond that; windows go by in chunks of 2048,
-or by wave quarters in two passes when a trial has more buckets than half a
-chunk's windows, and a wave groups its passing windows by key with one
+buckets, in ranges of buckets taken by separate workgroups beyond that;
+windows go by in chunks of 2048, or by wave quarters in two passes when a
+trial has more buckets than half a chunk's windows, and a wave groups its passing windows by key with one
 ballot per key when few pass and with ballots over the key bits when many
 do.  Bucket lists and members must match the oracle bit for bit in every
 form, also truncated to a capacity and in a batch whose instances take
@@ -84,6 +84,9 @@ CASES = [
     # tier whose LDS rows let four workgroups share a CU
     ("tier of four workgroups per CU", 4, 6, 1500, 12, 6, 3, 3),
     ("tier of four workgroups per CU, protein", 20, 6, 1500, 8, 3, 2, 3),
+    # about 58 000 buckets per trial: eight ranges of LDS rows, each taken by
+    # its own workgroup over all of the trial's windows
+    ("protein k=4, s=1, several bucket ranges", 20, 12, 6000, 10, 4, 1, 2),
 ]
 
 
@@ -103,7 +106,7 @@ def test_select_large_trials_match_oracle(case):
     assert np.array_equal(mem[:nm_], rmem)
 
 
-@pytest.mark.parametrize("which", [0, 1, 2, 3], ids=[CASES[i][0] for i in range(4)])
+@pytest.mark.parametrize("which", [0, 1, 2, 3, 7], ids=[CASES[i][0] for i in (0, 1, 2, 3, 7)])
 def test_select_truncated_to_capacity(which):
     """Capacities that end inside a trial's buckets and inside a bucket's
     members, in every placement form: the kept records and every member slot
