@@ -26,6 +26,7 @@ struct SelWs {
     int64_t *bb;      // [m] first bucket of the trial
     int64_t *mb;      // [m] first member slot of the trial
     int64_t *n_heavy; // [1] trials with more buckets than the first emit launch takes
+    int64_t *qctr;    // [4] next unit of each heavy launch (work queue heads)
     int32_t *heavy;   // [m] those trials, in order
     int64_t *nep;     // [m][parts] buckets of each part of a trial's bins (parts > 1)
     int64_t *msp;     // [m][parts] their members
@@ -44,7 +45,7 @@ static int sel_parts(int32_t m, int64_t nwb)
 
 static size_t sel_head_bytes(int32_t m, int64_t nwb)
 {
-    return (size_t)m * 4 * sizeof(int64_t) + sizeof(int64_t) + (((size_t)m * 4 + 7) & ~(size_t)7) +
+    return (size_t)m * 4 * sizeof(int64_t) + 5 * sizeof(int64_t) + (((size_t)m * 4 + 7) & ~(size_t)7) +
            (size_t)m * sel_parts(m, nwb) * 2 * sizeof(int64_t);
 }
 
@@ -62,8 +63,9 @@ static SelWs carve(void *ws, int32_t m, int64_t nwb)
     w.bb = w.ms + m;
     w.mb = w.bb + m;
     w.n_heavy = w.mb + m;
-    w.heavy = reinterpret_cast<int32_t *>(w.n_heavy + 1);
-    w.nep = reinterpret_cast<int64_t *>(p + (size_t)m * 4 * sizeof(int64_t) + sizeof(int64_t) +
+    w.qctr = w.n_heavy + 1;
+    w.heavy = reinterpret_cast<int32_t *>(w.qctr + 4);
+    w.nep = reinterpret_cast<int64_t *>(p + (size_t)m * 4 * sizeof(int64_t) + 5 * sizeof(int64_t) +
                                         (((size_t)m * 4 + 7) & ~(size_t)7));
     w.msp = w.nep + (int64_t)m * sel_parts(m, nwb);
     w.bits = reinterpret_cast<uint64_t *>(p + sel_head_bytes(m, nwb));
@@ -89,6 +91,7 @@ struct SelArgs {
     int cb;     // buckets whose cursors the LDS holds
     int parts;  // k_sel_count: workgroups per trial
     int ranges; // k_sel_emit_heavy: bucket ranges of cb per trial at most
+    int tier;   // k_sel_emit_heavy: its work queue (ws.qctr[tier])
 };
 
 // per (trial, part of its bins): number of passing bins, their total size
@@ -684,6 +687,7 @@ __global__ void __launch_bounds__(256) k_sel_emit(const SelArgs a)
     extern __shared__ __align__(16) uint64_t bm[];
     __shared__ uint32_t tmp[256];
     const int j = blockIdx.x;
+    if (j == 0 && threadIdx.x < 4) a.ws.qctr[threadIdx.x] = 0;  // the heavy launches' queues, for after this one
     const int64_t ne = a.ws.ne[j];
     if (ne <= a.take_lo || ne > a.take_hi) return;
     emit_trial(a, j, ne, 0, bm, tmp);
@@ -691,19 +695,27 @@ __global__ void __launch_bounds__(256) k_sel_emit(const SelArgs a)
 
 // the trials with more buckets than that, listed by the scan; a fixed grid
 // of workgroups takes the (range of cb buckets, trial) units of the trials in
-// the launch's range of bucket counts in turn, range-major (so that the
-// trials' first ranges, which every trial has, spread over all workgroups)
+// the launch's range of bucket counts from a work queue (trials differ in
+// size by an order of magnitude), range-major (so that the trials' first
+// ranges, which every trial has, come first)
 __global__ void __launch_bounds__(256) k_sel_emit_heavy(const SelArgs a)
 {
     extern __shared__ __align__(16) uint64_t bm[];
     __shared__ uint32_t tmp[256];
+    __shared__ int64_t claim;
     const int64_t nh = *a.ws.n_heavy, nu = nh * a.ranges;
-    for (int64_t un = blockIdx.x; un < nu; un += gridDim.x) {
+    if (nu == 0) return;  // no heavy trial: no queue traffic
+    unsigned long long *q = reinterpret_cast<unsigned long long *>(a.ws.qctr + a.tier);
+    for (;;) {
+        if (threadIdx.x == 0) claim = (int64_t)atomicAdd(q, 1ull);
+        __syncthreads();
+        const int64_t un = claim;
+        __syncthreads();
+        if (un >= nu) break;  // every workgroup ends here once the queue is past its end
         const int j = a.ws.heavy[un % nh];
         const int64_t ne = a.ws.ne[j], r0 = (un / nh) * (int64_t)a.cb;
         if (ne <= a.take_lo || ne > a.take_hi || r0 >= ne) continue;  // uniform over the workgroup
         emit_trial(a, j, ne, r0, bm, tmp);
-        __syncthreads();
     }
 }
 
@@ -878,6 +890,7 @@ static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st, bool counted
         // other's latency); the last tier also takes the trials beyond every
         // LDS row count, with device-memory cursors
         int64_t lo = cb_a;
+        int tier = 0;
         for (const int per_cu : {4, 2, 1}) {
             int64_t cb = (lds_max / per_cu - 2048 - 16 * nwb) / 16;  // 1 KB static LDS, 1 KB headroom
             if (per_cu == 1) cb = std::max<int64_t>(lo, std::min<int64_t>(ne_bound, fit));
@@ -888,6 +901,7 @@ static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st, bool counted
             a.take_hi = per_cu == 1 ? INT64_MAX : cb;
             // only the last tier has trials with more buckets than its rows
             a.ranges = per_cu == 1 ? (int)((std::max<int64_t>(ne_bound, cb) + cb - 1) / cb) : 1;
+            a.tier = tier++;
             const int grid = std::min<int32_t>(a.m, 1024);
             hipLaunchKernelGGL(k_sel_emit_heavy, dim3(grid), dim3(256), sel_emit_lds(nwb, cb), st, a);
             PM_LAUNCHED();
