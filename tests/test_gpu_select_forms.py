@@ -162,6 +162,57 @@ def test_select_batch_mixes_light_and_heavy_trials():
     assert tot == nb_
 
 
+def _check_batch_against_oracle(B, insts, A, l, k, s, bk, mem, nb_):
+    tot = 0
+    for p, (seqs, masks) in enumerate(insts):
+        ref = oracle.Seqs(A, seqs)
+        RK, RN = oracle.hash_trials(ref, l, k, masks)
+        rbk, rmem, (rnb, rnm), _ = oracle.select(ref, l, k, RK, RN, s)
+        f, mp = B.first_item[p], B.m[p]
+        sel = (bk[:, 0] >= f) & (bk[:, 0] < f + mp)
+        gb = bk[sel]
+        assert len(gb) == rnb, p
+        assert np.array_equal(gb[:, 0] - f, rbk[:, 0]) and np.array_equal(gb[:, 1:3], rbk[:, 1:3]), p
+        for g, r in zip(gb, rbk):
+            assert np.array_equal(mem[g[3]:g[3] + g[2]], rmem[r[3]:r[3] + r[2]]), p
+        tot += rnb
+    assert tot == nb_
+
+
+def test_select_batch_spans_every_heavy_tier():
+    """One batch, DNA k = 7, s = 1, whose trials fall in the first launch and
+    in every heavy tier of one call (LDS rows for four, two and one
+    workgroups per CU, and several bucket ranges), all taken from the tiers'
+    work queues; every instance's list bit-exact against the oracle, through
+    bucket_select_batch and through projection_hash_select_batch."""
+    A, l, k, s = 4, 12, 7, 1
+    insts = [_case("tier first launch", A, 2, 400, l, k, 2), _case("tier four per CU", A, 2, 800, l, k, 2),
+             _case("tier two per CU", A, 4, 880, l, k, 2), _case("tier one per CU", A, 6, 1500, l, k, 2),
+             _case("tier ranges", A, 15, 2000, l, k, 2)]
+    buckets = []
+    for seqs, masks in insts:
+        ref = oracle.Seqs(A, seqs)
+        RK, RN = oracle.hash_trials(ref, l, k, masks)
+        buckets.append(int((RN >= s).sum(axis=1).max()))
+    say("select forms, every heavy tier", buckets)
+    # first launch <= 1024 buckets, then 2 144, 4 672 and 9 856 LDS rows on a
+    # device with 160 KB of LDS per workgroup
+    assert buckets[0] <= 1024 < buckets[1] <= 2144 < buckets[2] <= 4672 < buckets[3] <= 9856 < buckets[4]
+    B = pm.Batch(A, l, k, [sq for sq, _ in insts], [mk for _, mk in insts])
+    nb_, nm_ = pm.size_batch(B, s)
+    for fused in (False, True):
+        P = pm.BatchPipeline(B, s, 0, 1.0, pm.PM_FP64, np.full(A, 0.25), cap_b=nb_, cap_m=nm_)
+        if fused:
+            P.hash_select()
+        else:
+            P.hash()
+            P.select()
+        torch.cuda.synchronize()
+        b = P.b
+        assert int(b.status.item()) == 0
+        _check_batch_against_oracle(B, insts, A, l, k, s, u32(b.buckets)[:nb_], u32(b.members)[:nm_], nb_)
+
+
 def test_select_few_members_one_quarter_over_its_list():
     """A trial of few members whose passing windows crowd into the first
     quarter of its windows (a poly-A run of 400 windows first): that quarter
