@@ -53,6 +53,7 @@
 // shape: em_autotune times the variants on the caller's models and records
 // the fastest per (ceil(l/4), precision) class.
 #include <math.h>
+#include <stddef.h>
 #include <stdlib.h>
 
 #include "pm_common.h"
@@ -242,8 +243,15 @@ struct SeqState {
 
 // One pair of 16-window tiles (windows a0 .. a0+31 of one sequence) for this
 // wave's G groups of 16 models; the groups share the A operands.
+// LDS byte offsets of this lane's fragments within a pair's tables, formed
+// once per kernel: E-step A (positions 2g, 2g+1 of window r), the same for a
+// merged last k-block (positions 2(g & 1), 2(g & 1)+1), M-step A
+struct FragOff {
+    uint32_t a, a_merged, m;
+};
+
 template <int MT, bool LAST, bool TAIL, bool SPLIT, int G>
-__device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T,
+__device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T, const FragOff &fo,
                                           const half8 (&Whi)[G][Tiles<MT>::LB],
                                           const half8 (&Wlo)[G][Tiles<MT>::LB], float4v (&O)[G][MT],
                                           SeqState (&st)[G])
@@ -251,14 +259,16 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T
     constexpr int LB = Tiles<MT>::LB;
     constexpr bool MERGE = kMergeTail<MT, SPLIT>;
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    const char *tb = reinterpret_cast<const char *>(&T);
     half8 Ae[2][LB];
 #pragma unroll
     for (int t2 = 0; t2 < 2; ++t2)
 #pragma unroll
         for (int kb = 0; kb < LB; ++kb) {
-            // merged last block: groups 2, 3 repeat the positions of groups 0, 1
-            const int gp = MERGE && kb == LB - 1 ? g & 1 : g;
-            Ae[t2][kb] = *reinterpret_cast<const half8 *>(&T.oh2[16 * t2 + r + 8 * kb + 2 * gp][0]);
+            // entry 16 t2 + 8 kb + (r + 2g) of oh2 (16 B each); a merged last
+            // block's groups 2, 3 repeat the positions of groups 0, 1
+            const uint32_t off = MERGE && kb == LB - 1 ? fo.a_merged : fo.a;
+            Ae[t2][kb] = *reinterpret_cast<const half8 *>(tb + off + (16 * t2 + 8 * kb) * 16);
         }
     // E-step, already shifted: S' = S - (mref - kPOff); one chain per tile and group
     float4v S0[G], S1[G];
@@ -282,8 +292,8 @@ __device__ __forceinline__ void tile_pair(int a0, int L, const PairTables<MT> &T
     if (!LAST) {
         // M-step A operand: row (position pm, letter cm); windows 4g..4g+3 of both tiles
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-            Am[mt] = __builtin_bit_cast(half8, T.mt8[4 * g + 4 * mt + (r >> 2)][r & 3]);
+        for (int mt = 0; mt < MT; ++mt)  // mt8[4g + 4mt + r/4][r % 4]
+            Am[mt] = *reinterpret_cast<const half8 *>(tb + fo.m + mt * 256);
     }
 #pragma unroll
     for (int q = 0; q < G; ++q) {
@@ -400,6 +410,9 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     const int64_t s0 = a.offsets[i];
     const int L = (int)(a.offsets[i + 1] - s0) - a.l + 1;
+    static_assert(offsetof(PairTables<MT>, mt8) == 1024, "M-step fragments follow the 1 KB of E-step ones");
+    const FragOff fo{(uint32_t)(r + 2 * g) * 16u, (uint32_t)(r + 2 * (g & 1)) * 16u,
+                     1024u + (uint32_t)((4 * g + (r >> 2)) * 4 + (r & 3)) * 16u};
     // kSrcPre: this sequence's first slot and the next sequence's size and
     // first slot, formed once here rather than at every step
     int64_t sl = 0, sln = 0;
@@ -443,8 +456,8 @@ __device__ __forceinline__ void sweep(const EmMfmaArgs &a, const uint32_t *W, co
 #pragma unroll
         for (int u = 0; u < PPB; ++u) {
             const int b0 = a0 + 32 * u;
-            if (b0 + 32 <= L) tile_pair<MT, LAST, false, SPLIT, G>(b0, L, T[u], Whi, Wlo, O, st);
-            else if (b0 < L) tile_pair<MT, LAST, true, SPLIT, G>(b0, L, T[u], Whi, Wlo, O, st);
+            if (b0 + 32 <= L) tile_pair<MT, LAST, false, SPLIT, G>(b0, L, T[u], fo, Whi, Wlo, O, st);
+            else if (b0 < L) tile_pair<MT, LAST, true, SPLIT, G>(b0, L, T[u], fo, Whi, Wlo, O, st);
         }
     }
 #pragma unroll
