@@ -888,7 +888,7 @@ static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st, bool counted
         // the heavy trials in tiers of LDS rows sized for four, two and one
         // workgroups per CU (the fewer rows, the more workgroups hide each
         // other's latency); the last tier also takes the trials beyond every
-        // LDS row count, with device-memory cursors
+        // LDS row count, as several ranges of buckets
         int64_t lo = cb_a;
         int tier = 0;
         for (const int per_cu : {4, 2, 1}) {
