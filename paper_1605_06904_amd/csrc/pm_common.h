@@ -72,6 +72,7 @@ struct TotScan {
     int64_t heavy_above;
     int parts;
     int64_t *ne_sum, *ms_sum;
+    int64_t *max_heavy;  // with `heavy`: the most buckets of a heavy entry (or NULL)
 };
 int launch_tot_scan(const TotScan &a, hipStream_t st);
 

@@ -26,7 +26,8 @@ struct SelWs {
     int64_t *bb;      // [m] first bucket of the trial
     int64_t *mb;      // [m] first member slot of the trial
     int64_t *n_heavy; // [1] trials with more buckets than the first emit launch takes
-    int64_t *qctr;    // [4] next unit of each heavy launch (work queue heads)
+    int64_t *qctr;    // [4] next unit of each heavy launch (work queue heads, [0..2]), then
+                      // the most buckets of a heavy trial ([3], written by the scan)
     int32_t *heavy;   // [m] those trials, in order
     int64_t *nep;     // [m][parts] buckets of each part of a trial's bins (parts > 1)
     int64_t *msp;     // [m][parts] their members
@@ -181,9 +182,13 @@ __global__ void __launch_bounds__(1024) k_tot_scan(const TotScan a)
 {
     __shared__ int64_t sa[1024], sb[1024];
     __shared__ int64_t carry[3];
+    __shared__ unsigned long long hmax;
     __shared__ uint32_t hw[16];
     const int wave = threadIdx.x >> 6, lane = lane_id();
-    if (threadIdx.x == 0) carry[0] = carry[1] = carry[2] = 0;
+    if (threadIdx.x == 0) {
+        carry[0] = carry[1] = carry[2] = 0;
+        hmax = 0;
+    }
     __syncthreads();
     for (int64_t base = 0; base < a.n; base += 1024) {
         const int64_t j = base + threadIdx.x;
@@ -204,6 +209,7 @@ __global__ void __launch_bounds__(1024) k_tot_scan(const TotScan a)
         sa[threadIdx.x] = ve;
         sb[threadIdx.x] = vm;
         const bool h = a.heavy && j < a.n && ve > a.heavy_above;
+        if (h) atomicMax(&hmax, (unsigned long long)ve);
         const uint64_t hb = __ballot(h);
         if (lane == 0) hw[wave] = (uint32_t)__popcll(hb);
         __syncthreads();
@@ -242,6 +248,7 @@ __global__ void __launch_bounds__(1024) k_tot_scan(const TotScan a)
         a.n_out[1] = carry[1];
         if ((carry[0] > a.cap_b || carry[1] > a.cap_m) && a.status) atomicOr(a.status, PM_STATUS_CAPACITY);
         if (a.heavy) a.n_heavy[0] = carry[2];
+        if (a.max_heavy) a.max_heavy[0] = (int64_t)hmax;
     }
 }
 
@@ -687,7 +694,7 @@ __global__ void __launch_bounds__(256) k_sel_emit(const SelArgs a)
     extern __shared__ __align__(16) uint64_t bm[];
     __shared__ uint32_t tmp[256];
     const int j = blockIdx.x;
-    if (j == 0 && threadIdx.x < 4) a.ws.qctr[threadIdx.x] = 0;  // the heavy launches' queues, for after this one
+    if (j == 0 && threadIdx.x < 3) a.ws.qctr[threadIdx.x] = 0;  // the heavy launches' queues, for after this one
     const int64_t ne = a.ws.ne[j];
     if (ne <= a.take_lo || ne > a.take_hi) return;
     emit_trial(a, j, ne, 0, bm, tmp);
@@ -703,7 +710,9 @@ __global__ void __launch_bounds__(256) k_sel_emit_heavy(const SelArgs a)
     extern __shared__ __align__(16) uint64_t bm[];
     __shared__ uint32_t tmp[256];
     __shared__ int64_t claim;
-    const int64_t nh = *a.ws.n_heavy, nu = nh * a.ranges;
+    // bucket ranges of the largest heavy trial (at most a.ranges)
+    const int64_t rg = std::min<int64_t>(a.ranges, (a.ws.qctr[3] + a.cb - 1) / a.cb);
+    const int64_t nh = *a.ws.n_heavy, nu = nh * rg;
     if (nu == 0) return;  // no heavy trial: no queue traffic
     unsigned long long *q = reinterpret_cast<unsigned long long *>(a.ws.qctr + a.tier);
     for (;;) {
@@ -713,7 +722,7 @@ __global__ void __launch_bounds__(256) k_sel_emit_heavy(const SelArgs a)
         __syncthreads();
         if (un >= nu) break;  // every workgroup ends here once the queue is past its end
         const int j = a.ws.heavy[un % nh];
-        const int64_t ne = a.ws.ne[j], r0 = (un / nh) * (int64_t)a.cb;
+        const int64_t ne = a.ws.ne[j], r0 = (un / nh) * (int64_t)a.cb;  // range-major
         if (ne <= a.take_lo || ne > a.take_hi || r0 >= ne) continue;  // uniform over the workgroup
         emit_trial(a, j, ne, r0, bm, tmp);
     }
@@ -869,6 +878,7 @@ static int select_launch(SelArgs &a, int64_t x_max, hipStream_t st, bool counted
         ts.heavy = a.ws.heavy;
         ts.n_heavy = a.ws.n_heavy;
         ts.heavy_above = cb_a;
+        ts.max_heavy = a.ws.qctr + 3;
     }
     if (int rc = launch_tot_scan(ts, st)) return rc;
     static bool attr = false;
