@@ -108,8 +108,24 @@ def test_other_entry_points_validate():
     # workspace too small
     assert L.bucket_select(C.byref(S.c), 4, 2, 0x1, 0x1, 1, 2, 0x1, 1, 0x1, 1, 0x1, 0x1, 8,
                            None, None) == pm.PM_EINVAL
-    # selection workspace: per-trial totals and bitmap of |Sigma|^k / 64 words,
-    # per-bucket cursors; 0 outside the count-table range (|Sigma|^k <= 2^19)
+    # hash + selection in one call: keys and counts both required, the
+    # selection's workspace and |Sigma|^k limit
+    ws = pm.pm_select_workspace(4, 2, 1, 1)
+    assert L.projection_hash_select(C.byref(S.c), 4, 2, 0x3000, 1, None, 0x5000, 2, 0x1, 1, 0x1, 1, 0x1,
+                                    0x1000, ws, None, None) == pm.PM_EINVAL
+    assert L.projection_hash_select(C.byref(S.c), 4, 2, 0x3000, 1, 0x4000, None, 2, 0x1, 1, 0x1, 1, 0x1,
+                                    0x1000, ws, None, None) == pm.PM_EINVAL
+    assert L.projection_hash_select(C.byref(S.c), 4, 2, 0x3000, 1, 0x4000, 0x5000, 2, 0x1, 1, 0x1, 1, 0x1,
+                                    0x1000, ws - 8, None, None) == pm.PM_EINVAL
+    assert L.projection_hash_select(C.byref(S.c), 4, 2, 0x3000, 1, 0x4000, 0x5000, 2, 0x1, 1, 0x1, 1, 0x1,
+                                    0x1004, ws, None, None) == pm.PM_EINVAL  # workspace not 8-byte aligned
+    assert L.projection_hash_select(C.byref(S.c), 4, 2, 0x3000, 0, 0x4000, 0x5000, 2, 0x1, 1, 0x1, 1, 0x1,
+                                    0x1000, ws, None, None) == pm.PM_EINVAL  # no trials
+    S3 = _S(_fake_seqs(n_total=40, n_min=20, n_max=20))
+    assert L.projection_hash_select(C.byref(S3.c), 20, 10, 0x3000, 1, 0x4000, 0x5000, 2, 0x1, 1, 0x1, 1, 0x1,
+                                    0x1000, 1 << 30, None, None) == pm.PM_ERANGE  # 4^10 bins
+    # selection workspace: per-trial totals and bitmap of |Sigma|^k / 64 words;
+    # 0 outside the count-table range (|Sigma|^k <= 2^19)
     assert pm.pm_select_workspace(4, 9, 10, 100) > pm.pm_select_workspace(4, 8, 10, 100) > 0
     assert pm.pm_select_workspace(4, 8, 10, 200) == pm.pm_select_workspace(4, 8, 10, 100)  # cursors in LDS
     assert pm.pm_select_workspace(4, 10, 10, 100) == 0
