@@ -579,23 +579,63 @@ __device__ void emit_trial(const SelArgs &a, int j, int64_t ne, int64_t r0, uint
         }
         __syncthreads();
         for (uint32_t wb = lo; wb < hi; wb += 64 * kSelU) {
-            uint32_t kk[kSelU];
+            uint32_t kk[kSelU], ri[kSelU];
+            uint64_t peers[kSelU];
 #pragma unroll
             for (int u = 0; u < kSelU; ++u) {
                 const uint32_t w = wb + 64 * u + lane;
                 kk[u] = w < hi ? kj[w] : 0u;
             }
+            uint32_t nflag = 0;
 #pragma unroll
             for (int u = 0; u < kSelU; ++u) {
                 const uint32_t w = wb + 64 * u + lane;
-                uint32_t ri = 0xffffffffu;
-                if (w < hi && passing(kk[u])) ri = local_bucket(bm, wcnt, kk[u]) - rlo;
-                const bool f = ri < nr;
-                if (__ballot(f) == 0ull) continue;
+                ri[u] = 0xffffffffu;
+                if (w < hi && passing(kk[u])) ri[u] = local_bucket(bm, wcnt, kk[u]) - rlo;
+                peers[u] = __ballot(ri[u] < nr);
+                nflag += (uint32_t)__popcll(peers[u]);
+            }
+            if (nflag >= (uint32_t)(kSelBitsMin * kSelU)) {
+                // many members: the groups of all kSelU steps at once (their
+                // ballots over the key bits interleave), then one returning LDS
+                // atomic per group head, in step order (a wave's LDS operations
+                // complete in order, so a bucket's cursor advances step by step)
+                for (int b = 0; b < nbits; ++b)
+#pragma unroll
+                    for (int u = 0; u < kSelU; ++u) {
+                        const bool bit = (kk[u] >> b) & 1u;
+                        const uint64_t on = __ballot(bit);
+                        peers[u] &= bit ? on : ~on;
+                    }
+                uint32_t old[kSelU];
+                int head[kSelU];
+#pragma unroll
+                for (int u = 0; u < kSelU; ++u) {
+                    const bool f = ri[u] < nr;
+                    head[u] = f ? __ffsll((unsigned long long)peers[u]) - 1 : lane;
+                    old[u] = kNoSlot;
+                    if (f && head[u] == lane && bbase + rlo + ri[u] < a.cap_b)
+                        old[u] = atomicAdd(rows + wv * cb + ri[u], (uint32_t)__popcll(peers[u]));
+                }
+#pragma unroll
+                for (int u = 0; u < kSelU; ++u) {
+                    const uint32_t o = __shfl(old[u], head[u]);
+                    if (ri[u] < nr && o != kNoSlot) {
+                        const int64_t slot = mbase + o + (uint32_t)__popcll(peers[u] & lanemask_lt());
+                        if (slot < a.cap_m) a.members[slot] = wb + 64 * u + lane;
+                    }
+                }
+                continue;
+            }
+#pragma unroll
+            for (int u = 0; u < kSelU; ++u) {
+                const uint32_t w = wb + 64 * u + lane;
+                const bool f = ri[u] < nr;
+                if (peers[u] == 0ull) continue;
                 const Group g = group_by_key(f, kk[u], nbits);
                 uint32_t old = kNoSlot;
-                if (f && g.head == lane && bbase + rlo + ri < a.cap_b) {
-                    uint32_t *r = rows + wv * cb + ri;
+                if (f && g.head == lane && bbase + rlo + ri[u] < a.cap_b) {
+                    uint32_t *r = rows + wv * cb + ri[u];
                     old = *r;
                     *r = old + g.n;
                 }
