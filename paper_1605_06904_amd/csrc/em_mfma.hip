@@ -12,8 +12,10 @@
 // hi = fp16(x) and lo = fp16(x - hi), both multiplied by the same one-hot
 // operand, so every product is exact and the operand carries about 22
 // significant bits; sums are FP32.  The single-FP16 form (SPLIT = false) keeps
-// only hi: half the matrix-core work, 11-bit operands.  Scores are kept in log2 units (W scaled
-// by log2 e) so the softmax uses the hardware exp2.  The per-sequence
+// only hi: half the matrix-core work, 11-bit operands.  Scores are kept in
+// log2 units (W = log2 theta - log2 bg by the hardware FP32 logarithm, about
+// 2^-23 relative, inside the 22 bits the split halves carry; the prior term of
+// J adds those logarithms in FP64) so the softmax uses the hardware exp2.  The per-sequence
 // log-sum-exp is FP64: the posterior terms 2^(S - ref) are FP32 exp2 of FP32
 // scores; the eight a lane holds for one window pair are added in FP32 (three
 // levels), and these pair partials are accumulated over the whole sequence in
@@ -117,7 +119,6 @@ constexpr int kWaves = 4;  // waves (groups of 16 models) per workgroup
 // built per workgroup barrier
 constexpr int kShapeDefault = 14;  // untuned
 constexpr int kMaxMT2 = 6;         // G = 2 for ceil(l/4) <= 6 (registers)
-constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kPOff = 3.0f;
 constexpr float kSlack = 12.0f;
 
@@ -517,7 +518,7 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
     __shared__ __align__(16) PairTables<MT> tabs[2 * PPB];
     __shared__ __align__(16) uint2 lut[256];
     __shared__ __align__(16) float accs[kWaves][G][16][CX][4];
-    __shared__ double lbg[4];  // ln bg[c], formed once for every iteration's log-odds
+    __shared__ float lbg2[4];  // log2 bg[c], formed once for every iteration's log-odds
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
     EmMfmaArgs a = a0;
@@ -560,7 +561,9 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
         build_lut(lut);
         lutp = lut;
     }
-    if (threadIdx.x < 4) lbg[threadIdx.x] = log(a.bg[threadIdx.x]);
+    // by the same FP32 logarithm as the models' log2 theta, so that theta = bg
+    // gives log-odds of exactly zero
+    if (threadIdx.x < 4) lbg2[threadIdx.x] = __builtin_amdgcn_logf((float)a.bg[threadIdx.x]);
     __syncthreads();
     const int64_t bw = b0 + 16 * G * wv;
     float (*acc)[16][CX][4] = accs[wv];
@@ -605,9 +608,11 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
                         if (p < l && vb) {
                             const double th = src[b * AL + c * l + p];
                             if (it == 0 && !lo_half) a.theta_out[b * AL + c * l + p] = th;
-                            const double lt = log(th);
-                            w = (float)((lt - lbg[c]) * (double)kLog2e);
-                            if (!lo_half) pr += a.bg[c] * lt;
+                            // log2 theta by the hardware FP32 logarithm (about 2^-23
+                            // relative, within what the split FP16 halves carry)
+                            const float l2 = __builtin_amdgcn_logf((float)th);
+                            w = l2 - lbg2[c];
+                            if (!lo_half) pr += a.bg[c] * (double)l2;  // log2 units
                         }
                         mn = c == 0 ? w : fminf(mn, w);
                         hi[4 * h + c] = (_Float16)w;
@@ -622,7 +627,7 @@ __global__ void __launch_bounds__(64 * kWaves, (em_waves_per_simd<MT, PPB, G>())
             pr += __shfl_xor(pr, 32);
             wmin += __shfl_xor(wmin, 16);
             wmin += __shfl_xor(wmin, 32);
-            prior[q] = pr;
+            prior[q] = pr * 0.6931471805599453;  // natural log
             // lowest possible score, a little below to absorb rounding
             mlow[q] = wmin - 1.0f;
         }
