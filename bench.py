@@ -29,13 +29,13 @@ FP16_MFMA_PEAK = 2500.0      # TFLOP/s, MI355X dense FP16 matrix cores
 # the kernel source is the one they were taken on (sha256 prefix).
 MEASURED_TRAFFIC = {
     "hash.hip": ("8544af7b0b679691", {"k_hash<4,8>": 1.705e9, "k_hash<4,9>": 14.492e9, "k_hash<20,4>": 1.517e9}),
-    "em_mfma.hip": ("8890acb47162cfc1", {
-        "k_em_mfma<5,2,true,1,1>": 0.733e9 + 0.712e9,
-        "k_em_mfma<5,2,true,2,1>": 0.714e9 + 0.732e9,
-        "k_em_mfma<5,2,true,4,1>": 1.023e9 + 0.742e9,
-        "k_em_mfma<5,2,true,1,2>": 0.745e9 + 0.737e9,
-        "k_em_mfma<5,2,true,2,2>": 0.742e9 + 0.737e9,
-        "k_em_mfma<5,2,true,4,2>": 0.889e9 + 0.736e9,
+    "em_mfma.hip": ("ff6a29f1b25ea3d3", {
+        "k_em_mfma<5,2,true,1,1>": 0.740e9 + 0.694e9,
+        "k_em_mfma<5,2,true,2,1>": 0.699e9 + 0.705e9,
+        "k_em_mfma<5,2,true,4,1>": 0.732e9 + 0.693e9,
+        "k_em_mfma<5,2,true,1,2>": 0.745e9 + 0.723e9,
+        "k_em_mfma<5,2,true,2,2>": 0.733e9 + 0.731e9,
+        "k_em_mfma<5,2,true,4,2>": 0.763e9 + 0.742e9,
     }),
 }
 
