@@ -108,7 +108,7 @@ def stage_events(torch, n):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "the benchmark runs the path on exactly one GPU (the multi-GPU split is not implemented); --gpus must be 1"}), flush=True)
         sys.exit(2)
     import torch
 
